@@ -1,0 +1,182 @@
+/*
+ * ar.h -- C ABI of the MI355X (gfx950) abstract renderer for Gaussian-splat scenes.
+ *
+ * Abstract rendering (Li, Ji, Zhong, Zhang, Mitra, "Abstract Rendering: Computing All
+ * that is Seen in Gaussian Splat Scenes", arXiv 2503.00308): given a scene of 3-D
+ * Gaussians and a SET of camera poses, compute for every pixel a lower and an upper
+ * RGB bound that contain the colour the splat renderer produces at every pose of the
+ * set (Sec. 2.2, "Abstract rendering problem"; Theorem "all" of Sec. 3.3).
+ *
+ * The set of poses is a box in pose parameters (Sec. 4.2: position radius eps_t and
+ * orientation radius eps_R around a nominal camera), or a cell of an orbit about a
+ * vertical axis.  Every quantity of Alg. GaussianSplat is propagated as a pair of
+ * linear forms over the normalised box, the 2x2 covariance inverse by MatrixInv
+ * (Sec. 3.1) and the blend by BlendInd (Sec. 3.2), as in AbstractSplat (Sec. 3.3).
+ *
+ * Conventions
+ *   camera axes x right, y down, z forward; a world point uw maps to
+ *   uc = R (uw - t) with R world->camera and t the camera centre (Alg. GaussianSplat
+ *   line 2); pixel (col, row) has centre (col + 1/2, row + 1/2); fx, fy, cx, cy the
+ *   pinhole intrinsics (Sec. 2.2, matrix K).
+ *
+ * Memory
+ *   Unless stated otherwise, pointers are host pointers.  Output images are DEVICE
+ *   pointers (HBM) of H*W*3 floats in row-major [row][col][channel] order.  The caller
+ *   owns every buffer it passes; a scene handle owns its device copy of the scene.
+ *   Work is issued on the given HIP stream (NULL = the default stream).  The render
+ *   calls synchronise that stream once mid-way (to size the tile lists) and again at
+ *   the end, so outputs and statistics are complete when they return.
+ *
+ * Errors
+ *   Every function returns AR_OK (0) or a negative AR_E_* code; nothing aborts.
+ *   ar_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef AR_H
+#define AR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  AR_OK = 0,
+  AR_E_INVALID = -1,     /* an argument is out of range, non-finite or inconsistent */
+  AR_E_OOM = -2,         /* device memory could not be allocated */
+  AR_E_DEVICE = -3,      /* a HIP runtime call failed */
+  AR_E_UNSUPPORTED = -4, /* a valid request this build does not handle */
+  AR_E_BUDGET = -5       /* a server request does not fit the memory budget */
+};
+
+enum { AR_POSE_CAMERA6 = 0, AR_POSE_ORBIT = 1 };
+
+/* Opaque scene handle: a device-resident copy of the Gaussians. */
+typedef struct ar_scene ar_scene;
+
+/*
+ * Scene of n Gaussians <uw, Mw, o, c> (Sec. 2.2): mean uw, covariance factor Mw with
+ * Cov = Mw Mw^T (footnote of Sec. 2.2), opacity o in (0, 1], colour c in [0, 1]^3.
+ * Structure-of-arrays, float32, host or device memory (see on_device):
+ *   mean       [3][n]  (x of all Gaussians, then y, then z)
+ *   cov_factor [9][n]  entry (r, c) of Mw at plane 3 r + c
+ *   opacity    [n]
+ *   rgb        [3][n]
+ * Rejected (AR_E_INVALID): n < 1, a NULL array, a non-finite value, o outside (0, 1],
+ * a colour outside [0, 1].
+ */
+typedef struct {
+  int32_t n;
+  int32_t on_device; /* 0: the arrays are host memory, 1: device memory */
+  const float *mean;
+  const float *cov_factor;
+  const float *opacity;
+  const float *rgb;
+} ar_scene_desc;
+
+/* Pinhole intrinsics and image size (Sec. 2.2, K).  width, height in [1, 16384]. */
+typedef struct {
+  int32_t width, height;
+  double fx, fy, cx, cy;
+} ar_intrinsics;
+
+/*
+ * A set of camera poses.
+ *   AR_POSE_CAMERA6: p = (tx, ty, tz, yaw, pitch, roll) in the box lo <= p <= hi;
+ *     R(p) = Ry(yaw) Rx(pitch) Rz(roll) R0 and t(p) = t0 + (tx, ty, tz), angles in
+ *     radians, elementary rotations right-handed.  lo = hi on an axis fixes it.
+ *   AR_POSE_ORBIT: the camera rig (R0, t0) turned by phi in [lo[0], hi[0]] about the
+ *     vertical (y) axis through pivot: t(phi) = pivot + Ry(phi)(t0 - pivot),
+ *     R(phi) = R0 Ry(phi)^T.  Entries 1..5 of lo / hi are ignored.
+ * R0 is row-major world->camera.  Rejected: lo > hi, non-finite entries, angle
+ * half-widths above 0.5 rad.
+ */
+typedef struct {
+  int32_t model;
+  double R0[9];
+  double t0[3];
+  double pivot[3];
+  double lo[6];
+  double hi[6];
+} ar_pose_box;
+
+/*
+ * Options; a zero field takes the default.
+ *   tile        pixel tile side of the binning and of one workgroup, 8 (only value)
+ *   groups      Gaussian groups (waves) per tile, 1..8 (default: chosen from the size)
+ *   chunk       Gaussians per group and round, 4..256 (default 32)
+ *   taylor_k    MatrixInv order k (Sec. 3.1; default 8, the paper's default), 1..16
+ *   cull_budget bound E on the colour change from pruning faint Gaussians (default 1e-7);
+ *               Gaussian i is dropped from pixel u when its alpha is provably below
+ *               cull_budget / n at every pose; lower / upper bounds are widened by E
+ *   z_near      near plane (default 0.01): depth <= z_near gives alpha 0
+ *   t_min       stop a tile once every pixel's transmittance upper bound is below it,
+ *               widening the upper bound by that transmittance (default 1e-7;
+ *               negative disables)
+ */
+typedef struct {
+  int32_t tile;
+  int32_t groups;
+  int32_t chunk;
+  int32_t taylor_k;
+  double cull_budget;
+  double z_near;
+  double t_min;
+} ar_options;
+
+/* Statistics of one call (filled when the call returns). */
+typedef struct {
+  int64_t pairs;         /* (pixel, Gaussian) pairs whose alpha bounds were evaluated */
+  int64_t tile_pairs;    /* (tile, Gaussian) pairs produced by binning */
+  int32_t n_fallback;    /* Gaussians whose MatrixInv assertion failed (alpha in [0, bound]) */
+  int32_t n_wild;        /* Gaussians straddling the near plane (alpha in [0, o] everywhere) */
+  int32_t n_dropped;     /* Gaussians behind the near plane at every pose */
+  int32_t P;             /* number of pose variables of the box */
+  int32_t max_window;    /* largest Ind window of uncertain depth order (rotations) */
+  int32_t reserved;
+  double raster_ms;      /* device time of the per-pixel kernels (HIP events on the call's stream) */
+  double total_ms;       /* device time of the whole call from its first to its last kernel */
+} ar_stats;
+
+/* Copies the scene to the device on `stream` (synchronises it).  *out receives a
+ * handle to release with ar_scene_destroy. */
+int ar_scene_create(const ar_scene_desc *desc, void *hip_stream, ar_scene **out);
+
+/* Releases a scene handle and its device memory (NULL is ignored). */
+void ar_scene_destroy(ar_scene *scene);
+
+/* Number of Gaussians of a scene handle (0 for NULL). */
+int32_t ar_scene_size(const ar_scene *scene);
+
+/*
+ * Lower / upper images over the pose box (AbstractSplat, Sec. 3.3).
+ *   lo_rgb, hi_rgb: device pointers to height*width*3 floats, [row][col][channel];
+ *   for every pose p of the box and every pixel, lo <= GaussianSplat(scene, p) <= hi.
+ *   opts, stats may be NULL.  The scene handle's workspace is reused, so calls on the
+ *   same scene handle must not overlap in time (serialise them on one stream).
+ */
+int ar_render_bounds(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *box,
+                     const ar_options *opts, float *lo_rgb, float *hi_rgb, void *hip_stream,
+                     ar_stats *stats);
+
+/*
+ * Bounds for ncells pose boxes of one scene (the partition of a larger set of poses,
+ * Sec. 4.2 "#part"); lo_rgb / hi_rgb hold ncells images back to back.  Equivalent to
+ * ncells calls of ar_render_bounds; stats (may be NULL) accumulates over the cells.
+ */
+int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *cells,
+                    int32_t ncells, const ar_options *opts, float *lo_rgb, float *hi_rgb,
+                    void *hip_stream, ar_stats *stats);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *ar_last_error(void);
+
+/* Library version string. */
+const char *ar_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AR_H */

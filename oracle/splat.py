@@ -15,9 +15,10 @@ Readings where the paper is silent (each one is also listed in the design notes)
   formed once per Gaussian;
 * line 10: x = -q q^T / 2 lies in [-s_hi/2, -max(0, s_lo)/2]; a = o * Exp(x) and its
   interval is [o exp(x_lo), o exp(x_hi)];
-* Ind(d_i - d_j) (Alg. BlendInd) is decided on d_i - d_j = A_z (uw_i - uw_j), the
-  identity behind line 7 with tau and beta cancelled: 1 if its lower bound is > 0,
-  0 if its upper bound is <= 0, unknown otherwise;
+* Ind(d_i - d_j) (Alg. BlendInd) is decided on two bounds of d_i - d_j: the identity
+  d_i - d_j = A_z (uw_i - uw_j) behind line 7 (tau and beta cancel), and the literal
+  difference of the depth forms with a 1e-10 margin: 1 if a lower bound proves it
+  positive, 0 if an upper bound proves it non-positive, unknown otherwise;
 * transmittances are interval products (BlendInd line 2):
       T_hi[i] = prod_{Ind_ij = 1} (1 - a_lo[j]),  T_lo[i] = prod_{Ind_ij != 0} (1 - a_hi[j]);
 * colour (BlendInd line 3, then item (5) of Sec. 3.3):
@@ -218,17 +219,41 @@ def pixel_alpha(rec, idx, ux, uy):
     return a, o[:, None] * np.exp(xlo), o[:, None] * np.exp(xhi)
 
 
-def ind_matrix(rec, idx):
-    """Three-valued Ind(d_i - d_j) for Gaussians idx: 1, 0, or 2 (unknown); plus borderline mask."""
+IND_MARGIN = 1e-10
+
+
+def ind_matrix(rec, idx, block=256):
+    """Three-valued Ind(d_i - d_j) for Gaussians idx: 1, 0, or 2 (unknown); plus borderline mask.
+
+    d_i - d_j is bounded two ways, both sound: the identity d_i - d_j = A_z (uw_i - uw_j)
+    behind line 7 (tau and beta cancel), and the literal Add(d[i], -d[j]) of the two
+    depth forms (Alg. BlendInd line 1).  Ind is 1 if either lower bound proves
+    d_i > d_j, 0 if either upper bound proves d_i <= d_j, unknown otherwise.  The
+    literal bound is used with a margin IND_MARGIN: its depth forms carry rounding
+    noise, and at an exact tie (identity bound exactly 0) that noise must not decide.
+    Rows are evaluated in blocks to bound memory.
+    """
     A3 = rec["A"][2]                       # z-row of A, quantity shape (3,)
     uw = rec["uw"][idx]
-    duw = uw[:, None, :] - uw[None, :, :]  # (n, n, 3) constants
-    delta = lf.scale(lf.broadcast(A3, duw.shape), duw).sum(-1)
-    lo, hi = delta.bounds()
-    ind = np.where(lo > 0, 1, np.where(hi <= 0, 0, 2)).astype(np.int8)
-    scale = 1e-12 * (1.0 + np.abs(duw).sum(axis=-1))
-    exact_tie = (lo == hi) & (lo == 0)
-    border = (~exact_tie) & ((np.abs(lo) < scale) | (np.abs(hi) < scale))
+    d = rec["d"][idx]
+    n = len(idx)
+    ind = np.empty((n, n), np.int8)
+    border = np.empty((n, n), bool)
+    for b0 in range(0, n, block):
+        b1 = min(n, b0 + block)
+        duw = uw[b0:b1, None, :] - uw[None, :, :]  # (b, n, 3) constants
+        delta = lf.scale(lf.broadcast(A3, duw.shape), duw).sum(-1)
+        lo_r, hi_r = delta.bounds()
+        lit = lf.sub(d[b0:b1].expand(-1), d.expand(0))
+        lo_l, hi_l = lit.bounds()
+        one = (lo_r > 0) | (lo_l > IND_MARGIN)
+        zero = (hi_r <= 0) | (hi_l <= -IND_MARGIN)
+        ind[b0:b1] = np.where(one, 1, np.where(zero, 0, 2))
+        s = 1e-12 * (1.0 + np.abs(duw).sum(axis=-1))
+        exact_tie = (lo_r == hi_r) & (lo_r == 0)
+        border[b0:b1] = (~exact_tie) & ((np.abs(lo_r) < s) | (np.abs(hi_r) < s)
+                                        | (np.abs(lo_l - IND_MARGIN) < s) | (np.abs(hi_l + IND_MARGIN) < s))
+    np.fill_diagonal(ind, 0)
     np.fill_diagonal(border, False)
     return ind, border
 

@@ -1,0 +1,198 @@
+"""Python binding of the C ABI in include/ar.h (argument marshalling only).
+
+Every step of the abstract render runs in the HIP library (libabstract_render.so);
+this module converts NumPy / dict inputs to the C structures, uses PyTorch only to
+allocate device memory and to name the current HIP stream, and raises if the library
+is missing or a call fails.  There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libabstract_render.so")
+
+AR_OK, AR_E_INVALID, AR_E_OOM, AR_E_DEVICE, AR_E_UNSUPPORTED, AR_E_BUDGET = 0, -1, -2, -3, -4, -5
+AR_POSE_CAMERA6, AR_POSE_ORBIT = 0, 1
+
+
+class ARError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"abstract-render error {code}: {msg}")
+        self.code = code
+
+
+class SceneDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("on_device", ctypes.c_int32),
+                ("mean", ctypes.c_void_p), ("cov_factor", ctypes.c_void_p),
+                ("opacity", ctypes.c_void_p), ("rgb", ctypes.c_void_p)]
+
+
+class Intrinsics(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_double), ("fy", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double)]
+
+
+class PoseBox(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("R0", ctypes.c_double * 9), ("t0", ctypes.c_double * 3),
+                ("pivot", ctypes.c_double * 3), ("lo", ctypes.c_double * 6), ("hi", ctypes.c_double * 6)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("groups", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("taylor_k", ctypes.c_int32), ("cull_budget", ctypes.c_double),
+                ("z_near", ctypes.c_double), ("t_min", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_int64), ("tile_pairs", ctypes.c_int64),
+                ("n_fallback", ctypes.c_int32), ("n_wild", ctypes.c_int32), ("n_dropped", ctypes.c_int32),
+                ("P", ctypes.c_int32), ("max_window", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("raster_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+# the exported C symbols and their signatures (the same list as include/ar.h)
+SYMBOLS = {
+    "ar_scene_create": (ctypes.c_int, [ctypes.POINTER(SceneDesc), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "ar_scene_destroy": (None, [ctypes.c_void_p]),
+    "ar_scene_size": (ctypes.c_int32, [ctypes.c_void_p]),
+    "ar_render_bounds": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
+                                        ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.POINTER(Stats)]),
+    "ar_render_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
+                                       ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.POINTER(Stats)]),
+    "ar_last_error": (ctypes.c_char_p, []),
+    "ar_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ARError(AR_E_UNSUPPORTED, f"HIP library not built: {path} (run paper_2503_00308_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SYMBOLS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != AR_OK:
+        raise ARError(code, load().ar_last_error().decode())
+
+
+def intrinsics(d) -> Intrinsics:
+    return Intrinsics(int(d["width"]), int(d["height"]), float(d["fx"]), float(d["fy"]),
+                      float(d["cx"]), float(d["cy"]))
+
+
+def pose_box(d) -> PoseBox:
+    b = PoseBox()
+    b.model = int(d.get("model", AR_POSE_CAMERA6))
+    b.R0[:] = [float(v) for v in np.asarray(d.get("R0", np.eye(3)), np.float64).reshape(9)]
+    b.t0[:] = [float(v) for v in np.asarray(d.get("t0", np.zeros(3)), np.float64).reshape(3)]
+    b.pivot[:] = [float(v) for v in np.asarray(d.get("pivot", np.zeros(3)), np.float64).reshape(3)]
+    b.lo[:] = [float(v) for v in np.asarray(d["lo"], np.float64).reshape(6)]
+    b.hi[:] = [float(v) for v in np.asarray(d["hi"], np.float64).reshape(6)]
+    return b
+
+
+def options(d=None) -> Options:
+    d = d or {}
+    return Options(int(d.get("tile", 0)), int(d.get("groups", 0)), int(d.get("chunk", 0)),
+                   int(d.get("taylor_k", 0)), float(d.get("cull_budget", 0.0)),
+                   float(d.get("z_near", 0.0)), float(d.get("t_min", 0.0)))
+
+
+class Scene:
+    """A device-resident scene (ar_scene handle) built from a dict of arrays:
+    mean (N,3), cov_factor (N,3,3), opacity (N,), rgb (N,3)."""
+
+    def __init__(self, scene, stream=None):
+        lib = load()
+        n = len(scene["mean"])
+        # structure-of-arrays, float32, contiguous (the layout include/ar.h specifies)
+        self._mean = np.ascontiguousarray(np.asarray(scene["mean"], np.float32).T)
+        self._cov = np.ascontiguousarray(np.asarray(scene["cov_factor"], np.float32).reshape(n, 9).T)
+        self._op = np.ascontiguousarray(np.asarray(scene["opacity"], np.float32))
+        self._rgb = np.ascontiguousarray(np.asarray(scene["rgb"], np.float32).T)
+        desc = SceneDesc(n, 0, self._mean.ctypes.data, self._cov.ctypes.data,
+                         self._op.ctypes.data, self._rgb.ctypes.data)
+        h = ctypes.c_void_p()
+        _check(lib.ar_scene_create(ctypes.byref(desc), _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+        self.n = n
+
+    def close(self):
+        if self.handle:
+            load().ar_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        return ctypes.c_void_p(0)
+    return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+def render_bounds(scene: Scene, intr, box, opts=None, stream=None, out=None):
+    """Lower / upper images (torch float32 tensors (H, W, 3) on the GPU) and stats."""
+    import torch
+    lib = load()
+    ci = intrinsics(intr)
+    H, W = ci.height, ci.width
+    if out is None:
+        lo = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+        hi = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    else:
+        lo, hi = out
+    st = Stats()
+    cb = pose_box(box)
+    co = options(opts)
+    _check(lib.ar_render_bounds(scene.handle, ctypes.byref(ci), ctypes.byref(cb), ctypes.byref(co),
+                                ctypes.c_void_p(lo.data_ptr()), ctypes.c_void_p(hi.data_ptr()),
+                                _stream_ptr(stream), ctypes.byref(st)))
+    return lo, hi, st.as_dict()
+
+
+def render_batch(scene: Scene, intr, cells, opts=None, stream=None):
+    """Bounds for a list of pose boxes: tensors (ncells, H, W, 3) and accumulated stats."""
+    import torch
+    lib = load()
+    ci = intrinsics(intr)
+    H, W = ci.height, ci.width
+    m = len(cells)
+    arr = (PoseBox * m)(*[pose_box(c) for c in cells])
+    lo = torch.empty((m, H, W, 3), dtype=torch.float32, device="cuda")
+    hi = torch.empty((m, H, W, 3), dtype=torch.float32, device="cuda")
+    st = Stats()
+    co = options(opts)
+    _check(lib.ar_render_batch(scene.handle, ctypes.byref(ci), arr, m, ctypes.byref(co),
+                               ctypes.c_void_p(lo.data_ptr()), ctypes.c_void_p(hi.data_ptr()),
+                               _stream_ptr(stream), ctypes.byref(st)))
+    return lo, hi, st.as_dict()

@@ -1,0 +1,411 @@
+// Host side of the C ABI (include/ar.h): validation, device workspace and the launch
+// sequence of one abstract render.
+//
+// Sequence for one pose box (AbstractSplat over all pixels, Sec. 3.3):
+//   pose forms -> per-Gaussian records (FP64, stored as outward FP32) -> depth order
+//   (radix sort of the upper depth bound) -> tile lists (count, scan, emit, stable
+//   sort by tile) -> per-pixel BlendInd loop -> lower / upper images.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "ar_internal.h"
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                              \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ == hipErrorOutOfMemory) return fail(AR_E_OOM, "%s: out of device memory", #expr);      \
+    if (e_ != hipSuccess) return fail(AR_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+hipError_t grow(T *&p, size_t need) {
+  if (p) {
+    hipError_t e = hipFree(p);
+    if (e != hipSuccess) return e;
+    p = nullptr;
+  }
+  return hipMalloc((void **)&p, std::max(need, (size_t)64) * sizeof(T));
+}
+
+}  // namespace
+
+struct ar_scene {
+  ar::SceneDev dev{};
+  ar::Workspace ws{};
+  float *base = nullptr;  // one allocation holding the scene arrays
+};
+
+namespace ar {
+
+static bool finite_box(const ar_pose_box *b) {
+  for (int i = 0; i < 9; ++i)
+    if (!isfinite(b->R0[i])) return false;
+  for (int i = 0; i < 3; ++i)
+    if (!isfinite(b->t0[i]) || !isfinite(b->pivot[i])) return false;
+  for (int i = 0; i < 6; ++i)
+    if (!isfinite(b->lo[i]) || !isfinite(b->hi[i])) return false;
+  return true;
+}
+
+// number of pose variables; *rotates: the depth order may change inside the box
+static int pose_vars(const ar_pose_box *b, bool *rotates) {
+  if (b->model == AR_POSE_ORBIT) {
+    *rotates = b->hi[0] > b->lo[0];
+    return *rotates ? 1 : 0;
+  }
+  int P = 0;
+  for (int a = 0; a < 6; ++a) P += b->hi[a] > b->lo[a];
+  *rotates = (b->hi[3] > b->lo[3]) || (b->hi[4] > b->lo[4]) || (b->hi[5] > b->lo[5]);
+  return P;
+}
+
+static int validate_box(const ar_pose_box *b) {
+  if (!b) return fail(AR_E_INVALID, "pose box is NULL");
+  if (b->model != AR_POSE_CAMERA6 && b->model != AR_POSE_ORBIT)
+    return fail(AR_E_INVALID, "unknown pose model %d", b->model);
+  if (!finite_box(b)) return fail(AR_E_INVALID, "pose box has a non-finite entry");
+  const int na = b->model == AR_POSE_ORBIT ? 1 : 6;
+  for (int a = 0; a < na; ++a) {
+    if (b->lo[a] > b->hi[a]) return fail(AR_E_INVALID, "pose box axis %d has lo > hi", a);
+    const bool angle = b->model == AR_POSE_ORBIT || a >= 3;
+    if (angle && 0.5 * (b->hi[a] - b->lo[a]) > 0.5)
+      return fail(AR_E_INVALID, "angle half-width above 0.5 rad on axis %d", a);
+  }
+  return AR_OK;
+}
+
+static int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *op, Params &prm) {
+  if (!in) return fail(AR_E_INVALID, "intrinsics are NULL");
+  if (in->width < 1 || in->height < 1 || in->width > 16384 || in->height > 16384)
+    return fail(AR_E_INVALID, "image size %dx%d outside [1, 16384]", in->width, in->height);
+  if (!(isfinite(in->fx) && isfinite(in->fy) && isfinite(in->cx) && isfinite(in->cy)) || !(in->fx > 0) ||
+      !(in->fy > 0))
+    return fail(AR_E_INVALID, "intrinsics must be finite with fx, fy > 0");
+  ar_options o{};
+  if (op) o = *op;
+  if (o.tile != 0 && o.tile != kTile) return fail(AR_E_UNSUPPORTED, "tile %d: only %d is built", o.tile, kTile);
+  if (o.groups < 0 || o.groups > 8) return fail(AR_E_INVALID, "groups %d outside [0, 8]", o.groups);
+  if (o.chunk != 0 && (o.chunk < 4 || o.chunk > 256)) return fail(AR_E_INVALID, "chunk %d outside [4, 256]", o.chunk);
+  if (o.taylor_k < 0 || o.taylor_k > 16) return fail(AR_E_INVALID, "taylor_k %d outside [1, 16]", o.taylor_k);
+  if (!(o.cull_budget >= 0.0) || !isfinite(o.cull_budget) || o.cull_budget >= 1.0)
+    return fail(AR_E_INVALID, "cull_budget must be in [0, 1)");
+  if (!(o.z_near >= 0.0) || !isfinite(o.z_near)) return fail(AR_E_INVALID, "z_near must be finite and >= 0");
+  if (!isfinite(o.t_min) || o.t_min >= 1.0) return fail(AR_E_INVALID, "t_min must be finite and < 1");
+  prm.width = in->width;
+  prm.height = in->height;
+  prm.fx = in->fx;
+  prm.fy = in->fy;
+  prm.cx = in->cx;
+  prm.cy = in->cy;
+  prm.taylor_k = o.taylor_k ? o.taylor_k : 8;
+  prm.z_near = o.z_near > 0 ? o.z_near : 0.01;
+  const double budget = o.cull_budget > 0 ? o.cull_budget : 1e-7;
+  prm.eps_cull = budget / (double)sc->dev.n;
+  prm.E = budget * (1.0 + 0x1p-10);
+  prm.t_min = o.t_min == 0.0 ? 1e-7 : o.t_min;  // negative disables the early stop
+  prm.ntx = (in->width + kTile - 1) / kTile;
+  prm.nty = (in->height + kTile - 1) / kTile;
+  const int ntiles = prm.ntx * prm.nty;
+  int G = o.groups;
+  if (G == 0) {
+    G = 1;
+    while (G < 8 && ntiles * G < 2048) G *= 2;
+  }
+  prm.groups = G;
+  prm.chunk = o.chunk ? o.chunk : 32;
+  return AR_OK;
+}
+
+// Workspace buffers sized for n Gaussians and ntiles tiles.
+static int ensure_ws(Workspace &ws, int n, int ntiles) {
+  const size_t nn = (size_t)n;
+  if (nn > ws.cap_n || !ws.rec) {
+    const size_t c = nn + 64;
+    HIP_TRY(grow(ws.rec, c * rec_stride(kMaxP)));
+    HIP_TRY(grow(ws.key, c));
+    HIP_TRY(grow(ws.key_sort, c));
+    HIP_TRY(grow(ws.key_alt, c));
+    HIP_TRY(grow(ws.perm, c));
+    HIP_TRY(grow(ws.perm_alt, c));
+    HIP_TRY(grow(ws.rect, 4 * c));
+    HIP_TRY(grow(ws.dform, 2 * (kMaxP + 1) * c));
+    HIP_TRY(grow(ws.count, c + 1));
+    ws.cap_n = nn;
+  }
+  if ((size_t)ntiles > ws.cap_tiles || !ws.tile_range) {
+    HIP_TRY(grow(ws.tile_range, 2 * (size_t)ntiles + 2));
+    ws.cap_tiles = (size_t)ntiles;
+  }
+  if (!ws.pose) {
+    HIP_TRY(hipMalloc(&ws.pose, sizeof(PoseForms)));
+    ws.cap_cells = 1;
+  }
+  if (!ws.counters) {
+    HIP_TRY(hipMalloc((void **)&ws.counters, 8 * sizeof(unsigned long long)));
+    HIP_TRY(hipHostMalloc((void **)&ws.host_counters, 16 * sizeof(unsigned long long), hipHostMallocDefault));
+    for (int i = 0; i < 3; ++i) HIP_TRY(hipEventCreate(&ws.ev[i]));
+  }
+  return AR_OK;
+}
+
+static int ensure_pairs(Workspace &ws, size_t npairs) {
+  if (npairs <= ws.cap_pairs && ws.pair_key) return AR_OK;
+  const size_t need = std::max(npairs + npairs / 4, (size_t)4096);
+  HIP_TRY(grow(ws.pair_key, need));
+  HIP_TRY(grow(ws.pair_key_alt, need));
+  HIP_TRY(grow(ws.pair_val, need));
+  HIP_TRY(grow(ws.pair_val_alt, need));
+  ws.cap_pairs = need;
+  return AR_OK;
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int n) {
+  const int i = threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+__global__ void k_zero_u32(uint32_t *p, int n) {
+  const int i = threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+static int bits_for(uint32_t v) {
+  int b = 0;
+  while (b < 32 && (1ull << b) <= (unsigned long long)v) ++b;
+  return b;
+}
+
+// One abstract render of one pose box into device images lo / hi.
+static int render_one(ar_scene *sc, const Params &prm, const ar_pose_box &box, int P, bool rotates, float *lo,
+                      float *hi, hipStream_t s, ar_stats *st) {
+  Workspace &ws = sc->ws;
+  const int n = sc->dev.n;
+  const int ntiles = prm.ntx * prm.nty;
+  if (rotates) return fail(AR_E_UNSUPPORTED, "pose boxes with rotation are not supported by this build yet");
+  if (P > 3) return fail(AR_E_UNSUPPORTED, "more than 3 translation variables");
+  int rc = ensure_ws(ws, n, ntiles);
+  if (rc) return rc;
+  HIP_TRY(hipEventRecord(ws.ev[0], s));
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ws.counters, 8);
+  HIP_TRY(hipGetLastError());
+  PoseForms *pose = (PoseForms *)ws.pose;
+  HIP_TRY(launch_pose_value(box, P, pose, s));
+  HIP_TRY(launch_project(P, sc->dev, pose, prm, ws, s));
+  // depth order: the upper depth bound as an orderable 64-bit key; values = gid
+  bool alt = false;
+  HIP_TRY(radix_sort_u64(ws.key_sort, ws.key_alt, ws.perm, ws.perm_alt, n, 0, 64, ws, s, &alt));
+  if (alt) {
+    std::swap(ws.key_sort, ws.key_alt);
+    std::swap(ws.perm, ws.perm_alt);
+  }
+  // tile lists in depth order
+  HIP_TRY(launch_count_tiles(P, ws, n, prm, s));
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.count + n, 1);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(exclusive_scan_u32(ws.count, n + 1, ws, s));
+  HIP_TRY(hipMemcpyAsync(ws.host_counters, ws.count + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const uint32_t npairs = *(const uint32_t *)ws.host_counters;
+  rc = ensure_pairs(ws, npairs);
+  if (rc) return rc;
+  HIP_TRY(launch_emit_tiles(P, ws, n, prm, s));
+  const int tbits = bits_for((uint32_t)(ntiles - 1));
+  HIP_TRY(radix_sort_u32(ws.pair_key, ws.pair_key_alt, ws.pair_val, ws.pair_val_alt, (int)npairs, 0,
+                         ((tbits + 7) / 8) * 8, ws, s, &alt));
+  if (alt) {
+    std::swap(ws.pair_key, ws.pair_key_alt);
+    std::swap(ws.pair_val, ws.pair_val_alt);
+  }
+  HIP_TRY(launch_tile_ranges(ws.pair_key, (int)npairs, ws.tile_range, ntiles, s));
+  HIP_TRY(hipEventRecord(ws.ev[1], s));
+  HIP_TRY(launch_raster_translation(P, ws, ws.pair_val, sc->dev, prm, lo, hi, s));
+  HIP_TRY(hipEventRecord(ws.ev[2], s));
+  HIP_TRY(hipMemcpyAsync(ws.host_counters, ws.counters, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  float ms_raster = 0.0f, ms_total = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms_raster, ws.ev[1], ws.ev[2]));
+  HIP_TRY(hipEventElapsedTime(&ms_total, ws.ev[0], ws.ev[2]));
+  if (st) {
+    st->pairs += (int64_t)ws.host_counters[0];
+    st->tile_pairs += (int64_t)npairs;
+    st->n_fallback += (int32_t)ws.host_counters[2];
+    st->n_wild += (int32_t)ws.host_counters[3];
+    st->n_dropped += (int32_t)ws.host_counters[4];
+    st->P = P;
+    st->raster_ms += ms_raster;
+    st->total_ms += ms_total;
+  }
+  return AR_OK;
+}
+
+}  // namespace ar
+
+// ------------------------------------------------------------------------------------
+// C ABI
+// ------------------------------------------------------------------------------------
+extern "C" {
+
+const char *ar_last_error(void) { return g_error.c_str(); }
+
+const char *ar_version(void) { return "abstract-render-gfx950 0.1"; }
+
+int32_t ar_scene_size(const ar_scene *scene) { return scene ? scene->dev.n : 0; }
+
+static int validate_scene_host(const ar_scene_desc *d, const float *mean, const float *cov, const float *op,
+                               const float *rgb) {
+  const size_t n = (size_t)d->n;
+  for (size_t i = 0; i < 3 * n; ++i)
+    if (!isfinite(mean[i])) return fail(AR_E_INVALID, "non-finite mean at index %zu", i);
+  for (size_t i = 0; i < 9 * n; ++i)
+    if (!isfinite(cov[i])) return fail(AR_E_INVALID, "non-finite covariance factor at index %zu", i);
+  for (size_t i = 0; i < n; ++i)
+    if (!(op[i] > 0.0f && op[i] <= 1.0f)) return fail(AR_E_INVALID, "opacity %g at %zu outside (0, 1]", op[i], i);
+  for (size_t i = 0; i < 3 * n; ++i)
+    if (!(rgb[i] >= 0.0f && rgb[i] <= 1.0f)) return fail(AR_E_INVALID, "colour %g at %zu outside [0, 1]", rgb[i], i);
+  return AR_OK;
+}
+
+int ar_scene_create(const ar_scene_desc *desc, void *hip_stream, ar_scene **out) {
+  if (!out) return fail(AR_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!desc) return fail(AR_E_INVALID, "scene description is NULL");
+  if (desc->n < 1) return fail(AR_E_INVALID, "scene has n = %d Gaussians", desc->n);
+  if (!desc->mean || !desc->cov_factor || !desc->opacity || !desc->rgb) return fail(AR_E_INVALID, "scene array is NULL");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t n = (size_t)desc->n;
+  // validation reads host copies of the arrays
+  std::vector<float> hm, hc, ho, hr;
+  const float *mean = desc->mean, *cov = desc->cov_factor, *op = desc->opacity, *rgb = desc->rgb;
+  if (desc->on_device) {
+    hm.resize(3 * n); hc.resize(9 * n); ho.resize(n); hr.resize(3 * n);
+    HIP_TRY(hipMemcpyAsync(hm.data(), mean, 3 * n * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hc.data(), cov, 9 * n * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ho.data(), op, n * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hr.data(), rgb, 3 * n * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    mean = hm.data(); cov = hc.data(); op = ho.data(); rgb = hr.data();
+  }
+  int rc = validate_scene_host(desc, mean, cov, op, rgb);
+  if (rc) return rc;
+  ar_scene *sc = new ar_scene();
+  float *base = nullptr;
+  hipError_t e = hipMalloc((void **)&base, 16 * n * sizeof(float));
+  if (e != hipSuccess) {
+    delete sc;
+    return fail(e == hipErrorOutOfMemory ? AR_E_OOM : AR_E_DEVICE, "scene allocation failed: %s", hipGetErrorString(e));
+  }
+  sc->base = base;
+  sc->dev.n = desc->n;
+  sc->dev.mean = base;
+  sc->dev.cov = base + 3 * n;
+  sc->dev.opac = base + 12 * n;
+  sc->dev.rgb = base + 13 * n;
+  const hipMemcpyKind k = desc->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  const float *src[4] = {desc->mean, desc->cov_factor, desc->opacity, desc->rgb};
+  float *dst[4] = {sc->dev.mean, sc->dev.cov, sc->dev.opac, sc->dev.rgb};
+  const size_t cnt[4] = {3 * n, 9 * n, n, 3 * n};
+  for (int i = 0; i < 4; ++i) {
+    e = hipMemcpyAsync(dst[i], src[i], cnt[i] * sizeof(float), k, s);
+    if (e != hipSuccess) break;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    ar_scene_destroy(sc);
+    return fail(AR_E_DEVICE, "scene upload failed: %s", hipGetErrorString(e));
+  }
+  *out = sc;
+  return AR_OK;
+}
+
+void ar_scene_destroy(ar_scene *sc) {
+  if (!sc) return;
+  ar::Workspace &w = sc->ws;
+  void *bufs[] = {w.pose, w.rec, w.key, w.key_sort, w.key_alt, w.perm, w.perm_alt, w.rect, w.dform, w.count,
+                  w.pair_key, w.pair_key_alt, w.pair_val, w.pair_val_alt, w.tile_range, w.hist, w.scan_tmp,
+                  w.counters, w.win, w.mask_off, w.masks, w.ivl, sc->base};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  if (w.host_counters) (void)hipHostFree(w.host_counters);
+  for (int i = 0; i < 3; ++i)
+    if (w.ev[i]) (void)hipEventDestroy(w.ev[i]);
+  delete sc;
+}
+
+static int check_outputs(const float *lo, const float *hi) {
+  if (!lo || !hi) return fail(AR_E_INVALID, "output image is NULL");
+  hipPointerAttribute_t a{};
+  for (const float *p : {lo, hi}) {
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess || a.type != hipMemoryTypeDevice) {
+      (void)hipGetLastError();
+      return fail(AR_E_INVALID, "output images must be device memory");
+    }
+  }
+  return AR_OK;
+}
+
+int ar_render_bounds(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *box,
+                     const ar_options *opts, float *lo_rgb, float *hi_rgb, void *hip_stream, ar_stats *stats) {
+  if (!scene) return fail(AR_E_INVALID, "scene is NULL");
+  int rc = ar::validate_box(box);
+  if (rc) return rc;
+  ar::Params prm{};
+  rc = ar::make_params(scene, intr, opts, prm);
+  if (rc) return rc;
+  rc = check_outputs(lo_rgb, hi_rgb);
+  if (rc) return rc;
+  if (stats) memset(stats, 0, sizeof(*stats));
+  bool rot = false;
+  const int P = ar::pose_vars(box, &rot);
+  return ar::render_one(const_cast<ar_scene *>(scene), prm, *box, P, rot, lo_rgb, hi_rgb, (hipStream_t)hip_stream,
+                        stats);
+}
+
+int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *cells, int32_t ncells,
+                    const ar_options *opts, float *lo_rgb, float *hi_rgb, void *hip_stream, ar_stats *stats) {
+  if (!scene) return fail(AR_E_INVALID, "scene is NULL");
+  if (!cells || ncells < 1) return fail(AR_E_INVALID, "batch needs at least one cell");
+  for (int i = 0; i < ncells; ++i) {
+    int rc = ar::validate_box(&cells[i]);
+    if (rc) return rc;
+  }
+  ar::Params prm{};
+  int rc = ar::make_params(scene, intr, opts, prm);
+  if (rc) return rc;
+  rc = check_outputs(lo_rgb, hi_rgb);
+  if (rc) return rc;
+  if (stats) memset(stats, 0, sizeof(*stats));
+  const size_t img = (size_t)intr->width * intr->height * 3;
+  for (int i = 0; i < ncells; ++i) {
+    bool rot = false;
+    const int P = ar::pose_vars(&cells[i], &rot);
+    rc = ar::render_one(const_cast<ar_scene *>(scene), prm, cells[i], P, rot, lo_rgb + i * img, hi_rgb + i * img,
+                        (hipStream_t)hip_stream, stats);
+    if (rc) return rc;
+  }
+  return AR_OK;
+}
+
+}  // extern "C"

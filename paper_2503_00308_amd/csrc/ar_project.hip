@@ -1,0 +1,519 @@
+// Pose stage and per-Gaussian stage of abstract rendering (FP64), gfx950.
+//
+// Pose stage: the set of cameras as linear forms uc = A (uw - tau) + beta
+//   (Alg. GaussianSplat line 2 with R and t replaced by their forms over the box).
+// Per-Gaussian stage (one thread per Gaussian): lines 2-8 of Alg. GaussianSplat as
+//   linear-relational operations (Sec. 3.3), MatrixInv for line 8 (Sec. 3.1), and
+//   B = Conic * Mp hoisted out of the pixel loop (line 9 evaluated as v * (Conic Mp)).
+//   The result is stored as an FP32 record with every lower form rounded down and
+//   every upper form rounded up, plus the footprint bound used for pruning.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "ar_internal.h"
+#include "ar_lf64.h"
+
+namespace ar {
+
+// ---------------------------------------------------------------------------------
+// pose stage
+// ---------------------------------------------------------------------------------
+template <int P>
+__device__ void store_form(double (*dst)[kMaxP + 1], const L64<P> &x) {
+  for (int k = 0; k <= kMaxP; ++k) { dst[0][k] = 0.0; dst[1][k] = 0.0; }
+  for (int k = 0; k < P; ++k) { dst[0][k] = x.lo[k]; dst[1][k] = x.up[k]; }
+  dst[0][kMaxP] = x.lo[P];
+  dst[1][kMaxP] = x.up[P];
+}
+
+template <int P>
+__device__ __forceinline__ L64<P> load_form(const double (*src)[kMaxP + 1]) {
+  L64<P> x;
+#pragma unroll
+  for (int k = 0; k < P; ++k) { x.lo[k] = src[0][k]; x.up[k] = src[1][k]; }
+  x.lo[P] = src[0][kMaxP];
+  x.up[P] = src[1][kMaxP];
+  return x;
+}
+
+// elementary right-handed rotation (axis 0 = x, 1 = y, 2 = z) of an exact affine angle
+template <int P>
+__device__ void rot_forms(int axis, const L64<P> &ang, L64<P> R[9]) {
+  const L64<P> c = l_trig<P>(ang, false);
+  const L64<P> s = l_trig<P>(ang, true);
+  const L64<P> ns = l_neg<P>(s);
+  const L64<P> one = l_const<P>(1.0), zero = l_const<P>(0.0);
+  if (axis == 0) {
+    R[0] = one; R[1] = zero; R[2] = zero; R[3] = zero; R[4] = c; R[5] = ns; R[6] = zero; R[7] = s; R[8] = c;
+  } else if (axis == 1) {
+    R[0] = c; R[1] = zero; R[2] = s; R[3] = zero; R[4] = one; R[5] = zero; R[6] = ns; R[7] = zero; R[8] = c;
+  } else {
+    R[0] = c; R[1] = ns; R[2] = zero; R[3] = s; R[4] = c; R[5] = zero; R[6] = zero; R[7] = zero; R[8] = one;
+  }
+}
+
+// C = Mmul(A, B) for 3x3 matrices of forms: C_ij = sum_t Mul(A_it, B_tj)
+template <int P>
+__device__ void mmul3(const L64<P> A[9], const L64<P> B[9], L64<P> C[9]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      L64<P> acc = l_mul<P>(A[i * 3 + 0], B[0 * 3 + j]);
+      acc = l_add<P>(acc, l_mul<P>(A[i * 3 + 1], B[1 * 3 + j]));
+      acc = l_add<P>(acc, l_mul<P>(A[i * 3 + 2], B[2 * 3 + j]));
+      C[i * 3 + j] = acc;
+    }
+}
+
+template <int P>
+__device__ L64<P> pose_param(const double *lo, const double *hi, int axis, const int *index) {
+  const double c = 0.5 * (lo[axis] + hi[axis]);
+  const double r = 0.5 * (hi[axis] - lo[axis]);
+  L64<P> x = l_const<P>(c);
+  if (index[axis] >= 0) {
+    x.lo[index[axis]] = r;
+    x.up[index[axis]] = r;
+  }
+  return x;
+}
+
+template <int P>
+__device__ void pose_forms(const ar_pose_box &b, PoseForms &pf) {
+  pf.P = P;
+  L64<P> A[9], tau[3], beta[3];
+  if (b.model == AR_POSE_CAMERA6) {
+    int index[6];
+    int p = 0;
+    for (int a = 0; a < 6; ++a) index[a] = (b.hi[a] > b.lo[a]) ? p++ : -1;
+    for (int k = 0; k < 3; ++k) tau[k] = l_addc<P>(pose_param<P>(b.lo, b.hi, k, index), b.t0[k]);
+    L64<P> Ry[9], Rx[9], Rz[9], T1[9], T2[9], R0[9];
+    rot_forms<P>(1, pose_param<P>(b.lo, b.hi, 3, index), Ry);
+    rot_forms<P>(0, pose_param<P>(b.lo, b.hi, 4, index), Rx);
+    rot_forms<P>(2, pose_param<P>(b.lo, b.hi, 5, index), Rz);
+    for (int i = 0; i < 9; ++i) R0[i] = l_const<P>(b.R0[i]);
+    mmul3<P>(Ry, Rx, T1);
+    mmul3<P>(T1, Rz, T2);
+    mmul3<P>(T2, R0, A);
+    for (int k = 0; k < 3; ++k) beta[k] = l_const<P>(0.0);
+  } else {
+    int index[6] = {(b.hi[0] > b.lo[0]) ? 0 : -1, -1, -1, -1, -1, -1};
+    L64<P> phi = pose_param<P>(b.lo, b.hi, 0, index);
+    L64<P> Ry[9], R0[9];
+    rot_forms<P>(1, l_neg<P>(phi), Ry);
+    for (int i = 0; i < 9; ++i) R0[i] = l_const<P>(b.R0[i]);
+    mmul3<P>(R0, Ry, A);
+    for (int k = 0; k < 3; ++k) {
+      tau[k] = l_const<P>(b.pivot[k]);
+      double s = 0.0;
+      for (int l = 0; l < 3; ++l) s += b.R0[k * 3 + l] * (b.pivot[l] - b.t0[l]);
+      beta[k] = l_const<P>(s);
+    }
+  }
+  for (int i = 0; i < 9; ++i) store_form<P>(pf.A[i], A[i]);
+  for (int k = 0; k < 3; ++k) {
+    store_form<P>(pf.tau[k], tau[k]);
+    store_form<P>(pf.beta[k], beta[k]);
+  }
+}
+
+template <int P>
+__global__ void k_pose(const ar_pose_box *boxes, int ncells, PoseForms *out) {
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell < ncells) pose_forms<P>(boxes[cell], out[cell]);
+}
+
+template <int P>
+__global__ void k_pose_value(ar_pose_box box, PoseForms *out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) pose_forms<P>(box, out[0]);
+}
+
+// ---------------------------------------------------------------------------------
+// per-Gaussian stage
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t order_key(double d) {
+  uint64_t b = __double_as_longlong(d);
+  return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// Round a lower (is_lower) or upper form to FP32, moving the constant outward by the
+// coefficient rounding plus 2^-32 of the form's magnitude (covers the FP64 stage).
+template <int P>
+__device__ __forceinline__ void store_f32(float *dst, const double *f, bool is_lower) {
+  double err = 0.0;
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const float g = (float)f[k];
+    dst[k] = g;
+    err += fabs((double)g - f[k]);
+  }
+  const double widen = err + 0x1p-32 * l_mag<P>(f);
+  dst[P] = is_lower ? __double2float_rd(f[P] - widen) : __double2float_ru(f[P] + widen);
+}
+
+template <int P>
+__device__ __forceinline__ double mag_f32(const float *f) {
+  double s = fabs((double)f[P]);
+#pragma unroll
+  for (int k = 0; k < P; ++k) s += fabs((double)f[k]);
+  return s;
+}
+
+template <int P>
+__device__ __forceinline__ void bounds_f32(const float *flo, const float *fhi, double &lo, double &hi) {
+  double sl = 0.0, sh = 0.0;
+#pragma unroll
+  for (int k = 0; k < P; ++k) { sl += fabs((double)flo[k]); sh += fabs((double)fhi[k]); }
+  lo = (double)flo[P] - sl;
+  hi = (double)fhi[P] + sh;
+}
+
+template <int P>
+__device__ __forceinline__ void store_lf(float *dst, const L64<P> &x) {
+  store_f32<P>(dst, x.lo, true);
+  store_f32<P>(dst + P + 1, x.up, false);
+}
+
+// Round a form to a two-float sum hi + lo (hi = nearest float, lo = nearest float of the
+// rest); the constant's lo part is rounded outward and moved by the representation
+// error of the coefficients plus 2^-32 of the form's magnitude.
+template <int P>
+__device__ __forceinline__ void store_f32x2(float *hi, float *lo, const double *f, bool is_lower) {
+  double err = 0.0;
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const float h = (float)f[k];
+    const float l = (float)(f[k] - (double)h);
+    hi[k] = h;
+    lo[k] = l;
+    err += fabs(f[k] - (double)h - (double)l);
+  }
+  const double widen = err + 0x1p-32 * l_mag<P>(f);
+  const float h = (float)f[P];
+  hi[P] = h;
+  lo[P] = is_lower ? __double2float_rd((f[P] - (double)h) - widen) : __double2float_ru((f[P] - (double)h) + widen);
+}
+
+// layout: lower hi, lower lo, upper hi, upper lo (F floats each)
+template <int P>
+__device__ __forceinline__ void store_lf2(float *dst, const L64<P> &x) {
+  constexpr int F = P + 1;
+  store_f32x2<P>(dst, dst + F, x.lo, true);
+  store_f32x2<P>(dst + 2 * F, dst + 3 * F, x.up, false);
+}
+
+template <int P>
+__device__ __forceinline__ double mag_f32x2(const float *h, const float *l) {
+  double s = fabs((double)h[P] + (double)l[P]);
+#pragma unroll
+  for (int k = 0; k < P; ++k) s += fabs((double)h[k] + (double)l[k]);
+  return s;
+}
+
+// MatrixInv(X; X0, k) for the symmetric 2x2 set X = [[x00, x01], [x01, x11]] (Sec. 3.1):
+//   IXX0 = I - X X0 with X0 the inverse of the interval-hull centre,
+//   Xp = X0 sum_{i=0..k} IXX0^i,  Eps = ||X0|| n^(k+1) / (1 - n),  n >= ||IXX0||,
+//   conic = <Xp - Eps, Xp + Eps>.  Returns false when the assertion n < 1 fails.
+template <int P>
+__device__ bool matrix_inv(const L64<P> &x00, const L64<P> &x01, const L64<P> &x11, int k, L64<P> conic[4]) {
+  double b00l, b00h, b01l, b01h, b11l, b11h;
+  l_bounds<P>(x00, b00l, b00h);
+  l_bounds<P>(x01, b01l, b01h);
+  l_bounds<P>(x11, b11l, b11h);
+  const double m00 = 0.5 * (b00l + b00h), m01 = 0.5 * (b01l + b01h), m11 = 0.5 * (b11l + b11h);
+  const double det = m00 * m11 - m01 * m01;
+  if (!(det > 0.0) || !isfinite(det)) return false;
+  double X0[4] = {m11 / det, -m01 / det, -m01 / det, m00 / det};
+  const L64<P> *X[4] = {&x00, &x01, &x01, &x11};
+  L64<P> E[4];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      L64<P> s = l_add<P>(l_scale<P>(*X[i * 2 + 0], X0[0 * 2 + j]), l_scale<P>(*X[i * 2 + 1], X0[1 * 2 + j]));
+      L64<P> e = l_addc<P>(l_neg<P>(s), i == j ? 1.0 : 0.0);
+      // cover the FP64 rounding of the cancelling sum I - X X0
+      const double rho = 0x1p-50 * (l_mag<P>(X[i * 2 + 0]->lo) + l_mag<P>(X[i * 2 + 0]->up)) * fabs(X0[j]) +
+                         0x1p-50 * (l_mag<P>(X[i * 2 + 1]->lo) + l_mag<P>(X[i * 2 + 1]->up)) * fabs(X0[2 + j]);
+      e.lo[P] -= rho;
+      e.up[P] += rho;
+      E[i * 2 + j] = e;
+    }
+  L64<P> S[4], Pw[4], T[4];
+  for (int i = 0; i < 4; ++i) {
+    S[i] = l_addc<P>(l_const<P>(0.0), (i == 0 || i == 3) ? 1.0 : 0.0);
+    Pw[i] = E[i];
+    S[i] = l_add<P>(S[i], E[i]);
+  }
+  for (int it = 2; it <= k; ++it) {
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        T[i * 2 + j] = l_add<P>(l_mul<P>(Pw[i * 2 + 0], E[0 * 2 + j]), l_mul<P>(Pw[i * 2 + 1], E[1 * 2 + j]));
+    for (int i = 0; i < 4; ++i) {
+      Pw[i] = T[i];
+      S[i] = l_add<P>(S[i], T[i]);
+    }
+  }
+  double nn = 0.0;
+  for (int i = 0; i < 4; ++i) {
+    double lo, hi;
+    l_bounds<P>(E[i], lo, hi);
+    nn += fmax(lo * lo, hi * hi);
+  }
+  const double nbar = sqrt(nn);
+  if (!(nbar < 1.0)) return false;
+  const double nx0 = sqrt(X0[0] * X0[0] + X0[1] * X0[1] + X0[2] * X0[2] + X0[3] * X0[3]);
+  const double eps = nx0 * pow(nbar, (double)(k + 1)) / (1.0 - nbar);
+  if (!isfinite(eps)) return false;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      L64<P> c = l_add<P>(l_scale<P>(S[0 * 2 + j], X0[i * 2 + 0]), l_scale<P>(S[1 * 2 + j], X0[i * 2 + 1]));
+      c.lo[P] -= eps;
+      c.up[P] += eps;
+      conic[i * 2 + j] = c;
+    }
+  return true;
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void k_project(SceneDev sc, const PoseForms *__restrict__ pose, Params prm,
+                                                float *__restrict__ rec_out, uint64_t *__restrict__ key_out,
+                                                uint64_t *__restrict__ key_sort, uint32_t *__restrict__ perm_out, int32_t *__restrict__ rect_out,
+                                                double *__restrict__ dform_out,
+                                                unsigned long long *__restrict__ counters) {
+  using R = Rec<P>;
+  const int n = sc.n;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  float *rec = rec_out + (size_t)g * R::STRIDE;
+  const double uw[3] = {sc.mean[g], sc.mean[n + g], sc.mean[2 * n + g]};
+  double Mw[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Mw[i] = sc.cov[(size_t)i * n + g];
+  const float o = sc.opac[g];
+  perm_out[g] = (uint32_t)g;
+
+  // line 2: uc = Mmul(A, Add(uw, -tau)) + beta
+  L64<P> y[3];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) y[l] = l_addc<P>(l_neg<P>(load_form<P>(pose->tau[l])), uw[l]);
+  L64<P> uc[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    L64<P> acc = l_mul<P>(load_form<P>(pose->A[k * 3 + 0]), y[0]);
+    acc = l_add<P>(acc, l_mul<P>(load_form<P>(pose->A[k * 3 + 1]), y[1]));
+    acc = l_add<P>(acc, l_mul<P>(load_form<P>(pose->A[k * 3 + 2]), y[2]));
+    uc[k] = l_add<P>(acc, load_form<P>(pose->beta[k]));
+  }
+  const L64<P> &x = uc[0], &yy = uc[1], &d = uc[2];   // line 7: d = uc_z
+  const double fx = prm.fx, fy = prm.fy;
+  // line 4 (non-zero entries of J) and line 5 with the principal point removed
+  const L64<P> J00 = l_scale<P>(d, fx), J02 = l_scale<P>(x, -fx);
+  const L64<P> J11 = l_scale<P>(d, fy), J12 = l_scale<P>(yy, -fy);
+  const L64<P> up0 = l_scale<P>(x, fx), up1 = l_scale<P>(yy, fy);
+  // lines 3 and 6: Mc = Mmul(A, Mw) (Mw constant), Mp = Mmul(J, Mc)
+  L64<P> Mp0[3], Mp1[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    L64<P> Mc[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      L64<P> acc = l_scale<P>(load_form<P>(pose->A[k * 3 + 0]), Mw[0 * 3 + m]);
+      acc = l_add<P>(acc, l_scale<P>(load_form<P>(pose->A[k * 3 + 1]), Mw[1 * 3 + m]));
+      acc = l_add<P>(acc, l_scale<P>(load_form<P>(pose->A[k * 3 + 2]), Mw[2 * 3 + m]));
+      Mc[k] = acc;
+    }
+    Mp0[m] = l_add<P>(l_mul<P>(J00, Mc[0]), l_mul<P>(J02, Mc[2]));
+    Mp1[m] = l_add<P>(l_mul<P>(J11, Mc[1]), l_mul<P>(J12, Mc[2]));
+  }
+  // line 9 factors d*d and d*up
+  const L64<P> D2 = l_sqr<P>(d);
+  const L64<P> DUP0 = l_mul<P>(d, up0), DUP1 = l_mul<P>(d, up1);
+  // line 8: X = Mmul(Mp, Mp^T)
+  L64<P> X00 = l_sqr<P>(Mp0[0]), X11 = l_sqr<P>(Mp1[0]), X01 = l_mul<P>(Mp0[0], Mp1[0]);
+#pragma unroll
+  for (int m = 1; m < 3; ++m) {
+    X00 = l_add<P>(X00, l_sqr<P>(Mp0[m]));
+    X11 = l_add<P>(X11, l_sqr<P>(Mp1[m]));
+    X01 = l_add<P>(X01, l_mul<P>(Mp0[m], Mp1[m]));
+  }
+
+  // near plane and footprint
+  double dlo, dhi;
+  l_bounds<P>(d, dlo, dhi);
+  const bool dropped = dhi <= prm.z_near;
+  const bool straddle = !dropped && dlo <= prm.z_near;
+  double u0lo, u0hi, u1lo, u1hi;
+  l_bounds<P>(up0, u0lo, u0hi);
+  l_bounds<P>(up1, u1lo, u1hi);
+  double alo, ahi, blo, bhi, clo, chi;
+  l_bounds<P>(X00, alo, ahi);
+  l_bounds<P>(X01, blo, bhi);
+  l_bounds<P>(X11, clo, chi);
+  double m0lo = 0, m0hi = 0, m1lo = 0, m1hi = 0, lam = 0, r2 = -1;
+  bool geo_ok = false;
+  if (dlo > 0.0) {
+    m0lo = fmin(u0lo / dlo, u0lo / dhi);
+    m0hi = fmax(u0hi / dlo, u0hi / dhi);
+    m1lo = fmin(u1lo / dlo, u1lo / dhi);
+    m1hi = fmax(u1hi / dlo, u1hi / dhi);
+    const double lamx = 0.5 * (ahi + chi) +
+                        sqrt(0.25 * fmax((ahi - clo) * (ahi - clo), (chi - alo) * (chi - alo)) + fmax(blo * blo, bhi * bhi));
+    const double dl2 = dlo * dlo;
+    lam = lamx / (dl2 * dl2);
+    r2 = ((double)o > prm.eps_cull) ? 2.0 * lam * log((double)o / prm.eps_cull) : -1.0;
+    geo_ok = isfinite(m0lo) && isfinite(m0hi) && isfinite(m1lo) && isfinite(m1hi) && isfinite(lam) &&
+             isfinite(r2) && lam > 0.0;
+  }
+  const bool normal = !dropped && !straddle && geo_ok;
+  int32_t type = dropped ? kDropped : (normal ? kNormal : kWild);
+
+  L64<P> conic[4];
+  if (normal) {
+    if (!matrix_inv<P>(X00, X01, X11, prm.taylor_k, conic)) type = kFallback;
+  }
+  if (type == kFallback) atomicAdd(&counters[2], 1ull);
+  if (type == kWild) atomicAdd(&counters[3], 1ull);
+  if (type == kDropped) atomicAdd(&counters[4], 1ull);
+
+  // depth key and depth forms (rank order, Ind)
+  const uint64_t key = order_key(dropped ? INFINITY : dhi);
+  key_out[g] = key;
+  key_sort[g] = key;
+  double *df = dform_out + (size_t)g * 2 * (kMaxP + 1);
+  for (int k = 0; k <= kMaxP; ++k) { df[k] = 0.0; df[kMaxP + 1 + k] = 0.0; }
+  for (int k = 0; k < P; ++k) { df[k] = d.lo[k]; df[kMaxP + 1 + k] = d.up[k]; }
+  df[kMaxP] = d.lo[P];
+  df[2 * kMaxP + 1] = d.up[P];
+
+  // record
+  store_lf2<P>(rec + R::D2, D2);
+  store_lf2<P>(rec + R::DUP, DUP0);
+  store_lf2<P>(rec + R::DUP + 4 * R::F, DUP1);
+  float *sc_ = rec + R::SC;
+  for (int e = 0; e < 6; ++e) {
+    float *dst = rec + R::B + 2 * R::F * e;
+    if (type == kNormal) {
+      const int k = e / 3, nn = e % 3;
+      const L64<P> &mp0 = Mp0[nn], &mp1 = Mp1[nn];
+      L64<P> b = l_add<P>(l_mul<P>(conic[k * 2 + 0], mp0), l_mul<P>(conic[k * 2 + 1], mp1));
+      store_lf<P>(dst, b);
+    } else {
+      for (int j = 0; j < 2 * R::F; ++j) dst[j] = 0.0f;
+    }
+  }
+  double bmax[2] = {0.0, 0.0}, mb[2] = {0.0, 0.0};
+  for (int e = 0; e < 6; ++e) {
+    const float *bl = rec + R::B + 2 * R::F * e;
+    const float *bh = bl + R::F;
+    double lo, hi;
+    bounds_f32<P>(bl, bh, lo, hi);
+    rec[R::BI + e] = __double2float_rd(lo);
+    rec[R::BI + 6 + e] = __double2float_ru(hi);
+    const int k = e / 3;
+    bmax[k] = fmax(bmax[k], fmax(fabs((double)rec[R::BI + e]), fabs((double)rec[R::BI + 6 + e])));
+    mb[k] = fmax(mb[k], fmax(mag_f32<P>(bl), mag_f32<P>(bh)));
+  }
+  const double slack = 1.0 + 0x1p-30;
+  constexpr int F = R::F;
+  sc_[R::MD2] = __double2float_ru(
+      slack * fmax(mag_f32x2<P>(rec + R::D2, rec + R::D2 + F), mag_f32x2<P>(rec + R::D2 + 2 * F, rec + R::D2 + 3 * F)));
+  for (int k = 0; k < 2; ++k) {
+    const float *b = rec + R::DUP + 4 * F * k;
+    sc_[R::MDUP0 + k] = __double2float_ru(slack * fmax(mag_f32x2<P>(b, b + F), mag_f32x2<P>(b + 2 * F, b + 3 * F)));
+  }
+  sc_[R::MBB0] = __double2float_ru(slack * (mb[0] + bmax[0]));
+  sc_[R::MBB1] = __double2float_ru(slack * (mb[1] + bmax[1]));
+  sc_[R::BMAX0] = __double2float_ru(bmax[0]);
+  sc_[R::BMAX1] = __double2float_ru(bmax[1]);
+  sc_[R::O] = o;
+  sc_[R::C0] = sc.rgb[g];
+  sc_[R::C1] = sc.rgb[n + g];
+  sc_[R::C2] = sc.rgb[2 * n + g];
+  const bool geo = (type == kNormal || type == kFallback);
+  sc_[R::MU0LO] = geo ? __double2float_rd(m0lo) : 0.0f;
+  sc_[R::MU0HI] = geo ? __double2float_ru(m0hi) : 0.0f;
+  sc_[R::MU1LO] = geo ? __double2float_rd(m1lo) : 0.0f;
+  sc_[R::MU1HI] = geo ? __double2float_ru(m1hi) : 0.0f;
+  sc_[R::R2] = geo ? __double2float_ru(r2) : -1.0f;
+  sc_[R::LAM] = geo ? __double2float_ru(lam) : 0.0f;
+  sc_[R::TYPE] = __int_as_float(type);
+  for (int j = R::SC + R::TYPE + 1; j < R::STRIDE; ++j) rec[j] = 0.0f;
+
+  // tile rectangle (inclusive) for binning; empty when the Gaussian cannot contribute
+  int32_t *rc = rect_out + 4 * (size_t)g;
+  if (type == kWild) {
+    rc[0] = 0; rc[1] = 0; rc[2] = prm.ntx - 1; rc[3] = prm.nty - 1;
+  } else if (!geo || r2 < 0.0) {
+    rc[0] = 1; rc[1] = 1; rc[2] = 0; rc[3] = 0;
+  } else {
+    const double R = sqrt(r2) + 1.0;
+    const double c0 = floor(m0lo - R + prm.cx - 0.5), c1 = ceil(m0hi + R + prm.cx - 0.5);
+    const double r0 = floor(m1lo - R + prm.cy - 0.5), r1 = ceil(m1hi + R + prm.cy - 0.5);
+    if (c1 < 0.0 || r1 < 0.0 || c0 > prm.width - 1 || r0 > prm.height - 1) {
+      rc[0] = 1; rc[1] = 1; rc[2] = 0; rc[3] = 0;
+    } else {
+      const int ic0 = (int)fmax(c0, 0.0), ic1 = (int)fmin(c1, (double)(prm.width - 1));
+      const int ir0 = (int)fmax(r0, 0.0), ir1 = (int)fmin(r1, (double)(prm.height - 1));
+      rc[0] = ic0 / kTile; rc[1] = ir0 / kTile; rc[2] = ic1 / kTile; rc[3] = ir1 / kTile;
+    }
+  }
+}
+
+template <int P>
+static hipError_t launch_pose_p(const ar_pose_box *boxes, int ncells, PoseForms *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pose<P>, dim3((ncells + 63) / 64), dim3(64), 0, s, boxes, ncells, out);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_pose_value_p(const ar_pose_box &box, PoseForms *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pose_value<P>, dim3(1), dim3(64), 0, s, box, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pose_value(const ar_pose_box &box, int P, PoseForms *out, hipStream_t s) {
+  switch (P) {
+    case 0: return launch_pose_value_p<0>(box, out, s);
+    case 1: return launch_pose_value_p<1>(box, out, s);
+    case 2: return launch_pose_value_p<2>(box, out, s);
+    case 3: return launch_pose_value_p<3>(box, out, s);
+    case 4: return launch_pose_value_p<4>(box, out, s);
+    case 5: return launch_pose_value_p<5>(box, out, s);
+    case 6: return launch_pose_value_p<6>(box, out, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_pose(const ar_pose_box *boxes, int ncells, int P, PoseForms *out, hipStream_t s) {
+  switch (P) {
+    case 0: return launch_pose_p<0>(boxes, ncells, out, s);
+    case 1: return launch_pose_p<1>(boxes, ncells, out, s);
+    case 2: return launch_pose_p<2>(boxes, ncells, out, s);
+    case 3: return launch_pose_p<3>(boxes, ncells, out, s);
+    case 4: return launch_pose_p<4>(boxes, ncells, out, s);
+    case 5: return launch_pose_p<5>(boxes, ncells, out, s);
+    case 6: return launch_pose_p<6>(boxes, ncells, out, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int P>
+static hipError_t launch_project_p(const SceneDev &sc, const PoseForms *pose, const Params &prm, Workspace &ws,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(k_project<P>, dim3((sc.n + 63) / 64), dim3(64), 0, s, sc, pose, prm, ws.rec, ws.key, ws.key_sort,
+                     ws.perm, ws.rect, ws.dform, ws.counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(int P, const SceneDev &sc, const PoseForms *pose, const Params &prm, Workspace &ws,
+                          hipStream_t s) {
+  switch (P) {
+    case 0: return launch_project_p<0>(sc, pose, prm, ws, s);
+    case 1: return launch_project_p<1>(sc, pose, prm, ws, s);
+    case 2: return launch_project_p<2>(sc, pose, prm, ws, s);
+    case 3: return launch_project_p<3>(sc, pose, prm, ws, s);
+    case 4: return launch_project_p<4>(sc, pose, prm, ws, s);
+    case 5: return launch_project_p<5>(sc, pose, prm, ws, s);
+    case 6: return launch_project_p<6>(sc, pose, prm, ws, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ar

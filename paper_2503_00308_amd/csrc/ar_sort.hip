@@ -1,0 +1,224 @@
+// Stable LSD radix sort (8-bit digits) and exclusive scan for gfx950 (wave64).
+//
+// Used to order Gaussians by depth key (64-bit) and (tile, depth-rank) pairs by tile
+// id (32-bit keys, stable so that each tile's list stays in depth order).
+//
+// One pass = histogram per block -> exclusive scan over the digit-major histogram
+// -> stable scatter.  Within a block the scatter ranks equal digits with 8 wave
+// ballots, then across the block's waves through LDS, so equal keys keep input order.
+#include <hip/hip_runtime.h>
+
+#include "ar_internal.h"
+
+namespace ar {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;                       // per thread per block
+constexpr int kSortTile = kSortThreads * kSortItems; // items per block
+constexpr int kScanThreads = 1024;
+
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K *__restrict__ keys, int n, int shift,
+                                                             uint32_t *__restrict__ hist, int nblocks) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int base = blockIdx.x * kSortTile;
+  for (int i = threadIdx.x; i < kSortTile; i += kSortThreads) {
+    const int idx = base + i;
+    if (idx < n) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                                                K *__restrict__ kout, uint32_t *__restrict__ vout, int n,
+                                                                int shift, const uint32_t *__restrict__ offs, int nblocks) {
+  constexpr int kWaves = kSortThreads / 64;
+  __shared__ uint32_t running[256];
+  __shared__ uint32_t wcount[kWaves][256];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  running[threadIdx.x] = offs[threadIdx.x * nblocks + blockIdx.x];
+  const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  const int base = blockIdx.x * kSortTile;
+  for (int t = 0; t < kSortItems; ++t) {
+    const int idx = base + t * kSortThreads + threadIdx.x;
+    const bool valid = idx < n;
+    K key = 0;
+    uint32_t val = 0;
+    uint32_t digit = 0;
+    if (valid) {
+      key = kin[idx];
+      val = vin[idx];
+      digit = (uint32_t)(key >> shift) & 255u;
+    }
+    for (int w = 0; w < kWaves; ++w) wcount[w][threadIdx.x] = 0;
+    __syncthreads();
+    // lanes of this wave holding the same digit
+    uint64_t match = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t bal = __ballot((digit >> b) & 1u);
+      match &= ((digit >> b) & 1u) ? bal : ~bal;
+    }
+    const uint32_t rank = __popcll(match & below);
+    if (valid && rank == 0) wcount[wave][digit] = __popcll(match);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = running[digit] + rank;
+      for (int w = 0; w < wave; ++w) pos += wcount[w][digit];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    uint32_t tot = 0;
+    for (int w = 0; w < kWaves; ++w) tot += wcount[w][threadIdx.x];
+    running[threadIdx.x] += tot;
+    __syncthreads();
+  }
+}
+
+// Exclusive scan of n uint32 values in one workgroup (used for histograms and block sums).
+__global__ __launch_bounds__(kScanThreads) void k_scan_single(uint32_t *data, int n) {
+  __shared__ uint32_t part[kScanThreads];
+  const int per = (n + kScanThreads - 1) / kScanThreads;
+  const int b = threadIdx.x * per;
+  const int e = min(n, b + per);
+  uint32_t s = 0;
+  for (int i = b; i < e; ++i) s += data[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - s;
+  for (int i = b; i < e; ++i) {
+    const uint32_t v = data[i];
+    data[i] = run;
+    run += v;
+  }
+}
+
+constexpr int kScanBlock = 1024;  // elements per block of the large scan (256 threads x 4)
+
+__global__ __launch_bounds__(256) void k_scan_blocks(const uint32_t *__restrict__ data, int n, uint32_t *__restrict__ sums) {
+  __shared__ uint32_t red[256];
+  const int base = blockIdx.x * kScanBlock + threadIdx.x * 4;
+  uint32_t s = 0;
+  for (int i = 0; i < 4; ++i)
+    if (base + i < n) s += data[base + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(uint32_t *__restrict__ data, int n, const uint32_t *__restrict__ sums) {
+  __shared__ uint32_t part[256];
+  const int base = blockIdx.x * kScanBlock + threadIdx.x * 4;
+  uint32_t v[4];
+  uint32_t s = 0;
+  for (int i = 0; i < 4; ++i) {
+    v[i] = (base + i < n) ? data[base + i] : 0u;
+    s += v[i];
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t t = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += t;
+    __syncthreads();
+  }
+  uint32_t run = sums[blockIdx.x] + part[threadIdx.x] - s;
+  for (int i = 0; i < 4; ++i) {
+    if (base + i < n) data[base + i] = run;
+    run += v[i];
+  }
+}
+
+hipError_t ensure_hist(Workspace &ws, size_t n_entries) {
+  if (n_entries <= ws.cap_hist) return hipSuccess;
+  if (ws.hist) {
+    hipError_t e = hipFree(ws.hist);
+    if (e != hipSuccess) return e;
+    ws.hist = nullptr;
+  }
+  size_t cap = n_entries + n_entries / 2 + 1024;
+  hipError_t e = hipMalloc(&ws.hist, cap * sizeof(uint32_t));
+  if (e == hipSuccess) ws.cap_hist = cap;
+  return e;
+}
+
+static hipError_t ensure_scan_tmp(Workspace &ws, size_t n_entries) {
+  if (n_entries <= ws.cap_scan) return hipSuccess;
+  if (ws.scan_tmp) {
+    hipError_t e = hipFree(ws.scan_tmp);
+    if (e != hipSuccess) return e;
+    ws.scan_tmp = nullptr;
+  }
+  size_t cap = n_entries + n_entries / 2 + 1024;
+  hipError_t e = hipMalloc(&ws.scan_tmp, cap * sizeof(uint32_t));
+  if (e == hipSuccess) ws.cap_scan = cap;
+  return e;
+}
+
+// Exclusive scan in place; block sums go to ws.scan_tmp (so data may be ws.hist).
+hipError_t exclusive_scan_u32(uint32_t *data, int n, Workspace &ws, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (n <= 32768) {
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kScanThreads), 0, s, data, n);
+    return hipGetLastError();
+  }
+  const int nb = (n + kScanBlock - 1) / kScanBlock;
+  if (nb > 32768 * 16) return hipErrorInvalidValue;  // > 5e8 elements: beyond the supported sizes
+  hipError_t e = ensure_scan_tmp(ws, (size_t)nb);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(256), 0, s, data, n, ws.scan_tmp);
+  hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kScanThreads), 0, s, ws.scan_tmp, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, s, data, n, ws.scan_tmp);
+  return hipGetLastError();
+}
+
+template <typename K>
+static hipError_t radix_sort(K *keys, K *keys_alt, uint32_t *vals, uint32_t *vals_alt, int n, int begin_bit,
+                             int end_bit, Workspace &ws, hipStream_t s, bool *in_alt) {
+  *in_alt = false;
+  if (n <= 1) return hipSuccess;
+  const int nb = (n + kSortTile - 1) / kSortTile;
+  hipError_t e = ensure_hist(ws, (size_t)256 * nb);
+  if (e != hipSuccess) return e;
+  K *ki = keys, *ko = keys_alt;
+  uint32_t *vi = vals, *vo = vals_alt;
+  for (int shift = begin_bit; shift < end_bit; shift += 8) {
+    hipLaunchKernelGGL(k_radix_hist<K>, dim3(nb), dim3(kSortThreads), 0, s, ki, n, shift, ws.hist, nb);
+    e = exclusive_scan_u32(ws.hist, 256 * nb, ws, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter<K>, dim3(nb), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, shift, ws.hist, nb);
+    K *tk = ki; ki = ko; ko = tk;
+    uint32_t *tv = vi; vi = vo; vo = tv;
+    *in_alt = !*in_alt;
+  }
+  return hipGetLastError();
+}
+
+hipError_t radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt, int n, int begin_bit,
+                          int end_bit, Workspace &ws, hipStream_t s, bool *in_alt) {
+  return radix_sort<uint64_t>(keys, keys_alt, vals, vals_alt, n, begin_bit, end_bit, ws, s, in_alt);
+}
+
+hipError_t radix_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, uint32_t *vals_alt, int n, int begin_bit,
+                          int end_bit, Workspace &ws, hipStream_t s, bool *in_alt) {
+  return radix_sort<uint32_t>(keys, keys_alt, vals, vals_alt, n, begin_bit, end_bit, ws, s, in_alt);
+}
+
+}  // namespace ar
