@@ -177,12 +177,17 @@ def sqr(x: LF) -> LF:
 
 
 def exp_slope(xlo, xhi):
-    """Slope of the chord of exp over [xlo, xhi], evaluated without cancellation."""
+    """Slope (exp(xhi) - exp(xlo)) / (xhi - xlo) of the chord of exp over [xlo, xhi]:
+    exp(xlo) expm1(dx) / dx for short intervals (no cancellation), the plain
+    difference quotient for long ones (no overflow), exp(xlo) at zero width."""
     xlo = np.asarray(xlo, dtype=np.float64)
     xhi = np.asarray(xhi, dtype=np.float64)
     dx = xhi - xlo
-    with np.errstate(invalid="ignore", divide="ignore"):
-        k = np.exp(xlo) * np.where(dx > 0, np.expm1(dx) / np.where(dx > 0, dx, 1.0), 1.0)
+    with np.errstate(invalid="ignore", divide="ignore", over="ignore", under="ignore"):
+        safe = np.where(dx > 0, dx, 1.0)
+        short = np.exp(xlo) * np.expm1(np.minimum(dx, 1.0)) / np.where(dx > 0, np.minimum(dx, 1.0), 1.0)
+        long_ = (np.exp(xhi) - np.exp(xlo)) / safe
+        k = np.where(dx <= 0, np.exp(xlo), np.where(dx < 1.0, short, long_))
     return k
 
 

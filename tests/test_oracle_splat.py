@@ -22,6 +22,7 @@ RNG = np.random.default_rng(2024)
 
 
 def _sound(sc, intr, box, res, n_samples, tol=1e-9):
+    assert np.all(np.isfinite(res["lo"])) and np.all(np.isfinite(res["hi"]))
     rng = np.random.default_rng(5)
     worst = -np.inf
     for p in pose.sample_poses(box, n_samples, rng):
@@ -204,3 +205,14 @@ def test_translation_only_ind_is_exact():
     assert not np.any(ind == 2) and not border.any()
     d = sc["mean"][:, 2].astype(np.float64)
     assert np.array_equal(ind == 1, d[:, None] > d[None, :])
+
+
+def test_exp_chord_slope_wide_intervals_finite():
+    """The chord slope stays finite for very wide exponent intervals (regression)."""
+    from oracle import lf
+    xlo = np.array([-2000.0, -800.0, -50.0, -1e-9, -3.0])
+    xhi = np.array([0.0, -700.0, -49.0, 0.0, -3.0])
+    k = lf.exp_slope(xlo, xhi)
+    assert np.all(np.isfinite(k))
+    ref = np.where(xhi > xlo, (np.exp(xhi) - np.exp(xlo)) / np.where(xhi > xlo, xhi - xlo, 1.0), np.exp(xlo))
+    np.testing.assert_allclose(k, ref, rtol=1e-9, atol=1e-300)
