@@ -214,5 +214,8 @@ def test_exp_chord_slope_wide_intervals_finite():
     xhi = np.array([0.0, -700.0, -49.0, 0.0, -3.0])
     k = lf.exp_slope(xlo, xhi)
     assert np.all(np.isfinite(k))
-    ref = np.where(xhi > xlo, (np.exp(xhi) - np.exp(xlo)) / np.where(xhi > xlo, xhi - xlo, 1.0), np.exp(xlo))
+    dx = xhi - xlo
+    quotient = (np.exp(xhi) - np.exp(xlo)) / np.where(dx > 0, dx, 1.0)
+    taylor = np.exp(xlo) * (1 + dx / 2 + dx * dx / 6)        # for tiny dx, no cancellation
+    ref = np.where(dx == 0, np.exp(xlo), np.where(dx < 1e-3, taylor, quotient))
     np.testing.assert_allclose(k, ref, rtol=1e-9, atol=1e-300)
