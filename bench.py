@@ -124,7 +124,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "gaussians": len(scene["mean"]), "image": [W, H], "pose_vars": P,
                    "tile": 8, "parallelism": "single GPU"},

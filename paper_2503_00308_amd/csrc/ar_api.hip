@@ -152,10 +152,12 @@ static int ensure_ws(Workspace &ws, int n, int ntiles) {
     HIP_TRY(grow(ws.rect, 4 * c));
     HIP_TRY(grow(ws.dform, 2 * (kMaxP + 1) * c));
     HIP_TRY(grow(ws.count, c + 1));
+    HIP_TRY(grow(ws.dint, 2 * c));
     ws.cap_n = nn;
   }
   if ((size_t)ntiles > ws.cap_tiles || !ws.tile_range) {
     HIP_TRY(grow(ws.tile_range, 2 * (size_t)ntiles + 2));
+    HIP_TRY(grow(ws.wmax, (size_t)ntiles + 2));
     ws.cap_tiles = (size_t)ntiles;
   }
   if (!ws.pose) {
@@ -167,6 +169,30 @@ static int ensure_ws(Workspace &ws, int n, int ntiles) {
     HIP_TRY(hipHostMalloc((void **)&ws.host_counters, 16 * sizeof(unsigned long long), hipHostMallocDefault));
     for (int i = 0; i < 3; ++i) HIP_TRY(hipEventCreate(&ws.ev[i]));
   }
+  return AR_OK;
+}
+
+// buffers of the general path: run counts for npairs list positions, per-pixel prefix sums
+static int ensure_general(Workspace &ws, size_t npairs) {
+  if (2 * npairs + 1 > ws.cap_run_cnt || !ws.run_cnt) {
+    const size_t need = 2 * npairs + 1 + npairs / 2 + 1024;
+    HIP_TRY(grow(ws.run_cnt, need));
+    ws.cap_run_cnt = need;
+  }
+  if (npairs > ws.cap_pre || !ws.pre) {
+    const size_t need = npairs + npairs / 4 + 64;
+    HIP_TRY(grow(ws.pre, need * kTilePix * 2));
+    HIP_TRY(grow(ws.prez, need * kTilePix));
+    ws.cap_pre = need;
+  }
+  return AR_OK;
+}
+
+static int ensure_runs(Workspace &ws, size_t nruns) {
+  if (nruns <= ws.cap_runs && ws.runs) return AR_OK;
+  const size_t need = nruns + nruns / 4 + 1024;
+  HIP_TRY(grow(ws.runs, 2 * need));
+  ws.cap_runs = need;
   return AR_OK;
 }
 
@@ -203,8 +229,7 @@ static int render_one(ar_scene *sc, const Params &prm, const ar_pose_box &box, i
   Workspace &ws = sc->ws;
   const int n = sc->dev.n;
   const int ntiles = prm.ntx * prm.nty;
-  if (rotates) return fail(AR_E_UNSUPPORTED, "pose boxes with rotation are not supported by this build yet");
-  if (P > 3) return fail(AR_E_UNSUPPORTED, "more than 3 translation variables");
+  if (!rotates && P > 3) return fail(AR_E_INVALID, "more than 3 translation variables");
   int rc = ensure_ws(ws, n, ntiles);
   if (rc) return rc;
   HIP_TRY(hipEventRecord(ws.ev[0], s));
@@ -239,9 +264,30 @@ static int render_one(ar_scene *sc, const Params &prm, const ar_pose_box &box, i
     std::swap(ws.pair_val, ws.pair_val_alt);
   }
   HIP_TRY(launch_tile_ranges(ws.pair_key, (int)npairs, ws.tile_range, ntiles, s));
-  HIP_TRY(hipEventRecord(ws.ev[1], s));
-  HIP_TRY(launch_raster_translation(P, ws, ws.pair_val, sc->dev, prm, lo, hi, s));
-  HIP_TRY(hipEventRecord(ws.ev[2], s));
+  if (!rotates) {
+    HIP_TRY(hipEventRecord(ws.ev[1], s));
+    HIP_TRY(launch_raster_translation(P, ws, ws.pair_val, sc->dev, prm, lo, hi, s));
+    HIP_TRY(hipEventRecord(ws.ev[2], s));
+  } else {
+    // depth order may change inside the box: Ind runs per tile list, then the two-phase loop
+    rc = ensure_general(ws, npairs);
+    if (rc) return rc;
+    HIP_TRY(launch_tile_wmax(ws, ws.pair_val, ntiles, s));
+    HIP_TRY(launch_runs(P, ws, ws.pair_val, pose, sc->dev, (int)npairs, false, s));
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.run_cnt + 2 * (size_t)npairs, 1);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(exclusive_scan_u32(ws.run_cnt, (int)(2 * npairs + 1), ws, s));
+    HIP_TRY(hipMemcpyAsync(ws.host_counters, ws.run_cnt + 2 * (size_t)npairs, sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint32_t nruns = *(const uint32_t *)ws.host_counters;
+    rc = ensure_runs(ws, nruns);
+    if (rc) return rc;
+    HIP_TRY(launch_runs(P, ws, ws.pair_val, pose, sc->dev, (int)npairs, true, s));
+    HIP_TRY(hipEventRecord(ws.ev[1], s));
+    HIP_TRY(launch_raster_general(P, ws, ws.pair_val, prm, lo, hi, s));
+    HIP_TRY(hipEventRecord(ws.ev[2], s));
+  }
   HIP_TRY(hipMemcpyAsync(ws.host_counters, ws.counters, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   float ms_raster = 0.0f, ms_total = 0.0f;
@@ -256,6 +302,7 @@ static int render_one(ar_scene *sc, const Params &prm, const ar_pose_box &box, i
     st->P = P;
     st->raster_ms += ms_raster;
     st->total_ms += ms_total;
+    st->max_window = std::max(st->max_window, (int32_t)ws.host_counters[5]);
   }
   return AR_OK;
 }
@@ -344,7 +391,7 @@ void ar_scene_destroy(ar_scene *sc) {
   ar::Workspace &w = sc->ws;
   void *bufs[] = {w.pose, w.rec, w.key, w.key_sort, w.key_alt, w.perm, w.perm_alt, w.rect, w.dform, w.count,
                   w.pair_key, w.pair_key_alt, w.pair_val, w.pair_val_alt, w.tile_range, w.hist, w.scan_tmp,
-                  w.counters, w.win, w.mask_off, w.masks, w.ivl, sc->base};
+                  w.counters, w.dint, w.wmax, w.run_cnt, w.runs, w.pre, w.prez, sc->base};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (w.host_counters) (void)hipHostFree(w.host_counters);

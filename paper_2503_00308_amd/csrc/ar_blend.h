@@ -1,0 +1,199 @@
+// BlendInd colour accumulation shared by the pixel loops (device code).
+//
+// Alg. BlendInd line 3, pc = sum_i T_i a_i c_i, with interval transmittances
+// [T_lo, T_hi] and linear-form alphas: the lower image accumulates the forms
+// c_i T_lo[i] a_i^lower(e), the upper image c_i T_hi[i] a_i^upper(e) and the interval
+// sum c_i T_hi[i] a_hi[i].  Sums are FP64; magnitude sums in FP32 bound their rounding.
+#pragma once
+
+#include "ar_pair.h"
+
+namespace ar {
+
+template <int P>
+struct Acc {
+  double lo[3][P + 1];
+  double hi[3][P + 1];
+  double ihi[3];
+  float magl, magh;  // magnitude sums bounding the FP64 rounding of the sums
+};
+
+template <int P>
+__device__ __forceinline__ void acc_zero(Acc<P> &a) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int j = 0; j <= P; ++j) { a.lo[c][j] = 0.0; a.hi[c][j] = 0.0; }
+    a.ihi[c] = 0.0;
+  }
+  a.magl = 0.0f;
+  a.magh = 0.0f;
+}
+
+// dst += (pre_lo, pre_hi) * src
+template <int P>
+__device__ __forceinline__ void acc_fma(Acc<P> &dst, const Acc<P> &src, double pre_lo, double pre_hi) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int j = 0; j <= P; ++j) {
+      dst.lo[c][j] = fma(pre_lo, src.lo[c][j], dst.lo[c][j]);
+      dst.hi[c][j] = fma(pre_hi, src.hi[c][j], dst.hi[c][j]);
+    }
+    dst.ihi[c] = fma(pre_hi, src.ihi[c], dst.ihi[c]);
+  }
+  dst.magl = fmaf((float)pre_lo, src.magl, dst.magl) * (1.0f + 4.0f * kU32);
+  dst.magh = fmaf((float)pre_hi, src.magh, dst.magh) * (1.0f + 4.0f * kU32);
+}
+
+// Alpha interval of a MatrixInv fallback (footprint bound) or a near-plane straddler.
+template <int P>
+__device__ __forceinline__ double alpha_hi_special(const float *__restrict__ rec, int type, double ux, double uy) {
+  using R = Rec<P>;
+  const double o = (double)rec[R::SC + R::O];
+  if (type != kFallback) return o;
+  const double d2 = dist2_box64(rec + R::SC + R::MU0LO, ux, uy);
+  const double lam = (double)rec[R::SC + R::LAM];
+  return fmin(o, o * exp(-0.5 * d2 * (1.0 - 8.0 * kU) / lam) * (1.0 + 16.0 * kU));
+}
+
+// One (pixel, Gaussian) pair: alpha bounds and its BlendInd contribution with the
+// transmittances (tlo, thi) of the Gaussians in front.  Returns the alpha interval.
+template <int P>
+__device__ __forceinline__ void pair_contrib(const float *__restrict__ rec, int type, double ux, double uy, double tlo,
+                                             double thi, Acc<P> &acc, double &a_lo, double &a_hi) {
+  using R = Rec<P>;
+  const float *sc = rec + R::SC;
+  const double o = (double)sc[R::O];
+  const double c3[3] = {(double)sc[R::C0], (double)sc[R::C1], (double)sc[R::C2]};
+  if (type == kNormal) {
+    SForms<P> s;
+    s_forms<P>(rec, ux, uy, s);
+    ExpBounds b;
+    exp_bounds(s.slo, s.shi, o, b);
+    // lower alpha form  o e_dn (x_lower(e) - xlo + 1),  x_lower = -s_upper / 2
+    // upper alpha form  o e_up + o k_up (x_upper(e) - xlo),  x_upper = -s_lower / 2
+    const double wl = o * b.e_dn;
+    const double wk = o * b.k_up;
+    double gl[P + 1], gh[P + 1];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      gl[j] = wl * (-0.5 * s.sh[j]);
+      gh[j] = wk * (-0.5 * s.sl[j]);
+    }
+    gl[P] = wl * ((-0.5 * s.sh[P] - b.xlo) + 1.0);
+    gh[P] = o * b.e_up + wk * (-0.5 * s.sl[P] - b.xlo);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double wlo = c3[c] * tlo, whi = c3[c] * thi;
+#pragma unroll
+      for (int j = 0; j <= P; ++j) {
+        acc.lo[c][j] = fma(wlo, gl[j], acc.lo[c][j]);
+        acc.hi[c][j] = fma(whi, gh[j], acc.hi[c][j]);
+      }
+      acc.ihi[c] = fma(whi, b.a_hi, acc.ihi[c]);
+    }
+    const float ml = (float)(wl * (0.5 * s.msh + fabs(b.xlo) + 1.0));
+    const float mh = (float)(o * b.e_up + wk * (0.5 * s.msl + fabs(b.xlo)) + b.a_hi);
+    acc.magl = fmaf((float)tlo, ml, acc.magl) * (1.0f + 4.0f * kU32);
+    acc.magh = fmaf((float)thi, mh, acc.magh) * (1.0f + 4.0f * kU32);
+    a_lo = b.a_lo;
+    a_hi = b.a_hi;
+  } else {
+    // MatrixInv fallback: [0, footprint bound]; near-plane straddler: [0, o]
+    const double ah = alpha_hi_special<P>(rec, type, ux, uy);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double whi = c3[c] * thi;
+      acc.hi[c][P] = fma(whi, ah, acc.hi[c][P]);
+      acc.ihi[c] = fma(whi, ah, acc.ihi[c]);
+    }
+    acc.magh = fmaf((float)thi, 2.0f * (float)ah, acc.magh) * (1.0f + 4.0f * kU32);
+    a_lo = 0.0;
+    a_hi = ah;
+  }
+}
+
+// Alpha interval of one pair without the colour forms (types as in pair_contrib).
+template <int P>
+__device__ __forceinline__ void alpha_interval(const float *__restrict__ rec, int type, double ux, double uy,
+                                               double &a_lo, double &a_hi) {
+  using R = Rec<P>;
+  if (type == kNormal) {
+    SForms<P> s;
+    s_forms<P>(rec, ux, uy, s);
+    ExpBounds b;
+    exp_bounds(s.slo, s.shi, (double)rec[R::SC + R::O], b);
+    a_lo = b.a_lo;
+    a_hi = b.a_hi;
+  } else {
+    a_lo = 0.0;
+    a_hi = alpha_hi_special<P>(rec, type, ux, uy);
+  }
+}
+
+// Pruning test of one pair (float32, bit-identical to the definition): true when
+// Gaussian rec may contribute at the pixel.
+template <int P>
+__device__ __forceinline__ bool pair_kept(const float *__restrict__ rec, int type, float ux, float uy) {
+  using R = Rec<P>;
+  if (type == kWild) return true;
+  const float d2 =
+      dist2_box(rec[R::SC + R::MU0LO], rec[R::SC + R::MU0HI], rec[R::SC + R::MU1LO], rec[R::SC + R::MU1HI], ux, uy);
+  return d2 <= rec[R::SC + R::R2];
+}
+
+// Sum the G waves' accumulators into wave 0 through LDS (all threads of the block call it).
+template <int P>
+__device__ void acc_reduce(Acc<P> &acc, double *red, int G, int g, int lane) {
+  constexpr int kRed = 6 * (P + 1) + 3 + 1;
+  for (int w = 1; w < G; ++w) {
+    __syncthreads();
+    if (g == w) {
+      double *dst = red + lane * kRed;
+      int q = 0;
+      for (int c = 0; c < 3; ++c) {
+        for (int j = 0; j <= P; ++j) { dst[q++] = acc.lo[c][j]; dst[q++] = acc.hi[c][j]; }
+        dst[q++] = acc.ihi[c];
+      }
+      float *fm = (float *)(dst + q);  // last slot: the two magnitude sums
+      fm[0] = acc.magl;
+      fm[1] = acc.magh;
+    }
+    __syncthreads();
+    if (g == 0) {
+      const double *src = red + lane * kRed;
+      int q = 0;
+      for (int c = 0; c < 3; ++c) {
+        for (int j = 0; j <= P; ++j) { acc.lo[c][j] += src[q++]; acc.hi[c][j] += src[q++]; }
+        acc.ihi[c] += src[q++];
+      }
+      acc.magl = (acc.magl + ((const float *)(src + q))[0]) * (1.0f + 4.0f * kU32);
+      acc.magh = (acc.magh + ((const float *)(src + q))[1]) * (1.0f + 4.0f * kU32);
+    }
+  }
+}
+
+// Concretise the colour forms over the box and write the pixel's lower / upper RGB.
+// nterm bounds the number of summed terms (for the FP64 rounding bound); extra_hi is
+// added to the upper bound (the transmittance left when a tile stops early).
+template <int P>
+__device__ void write_pixel(const Acc<P> &acc, double nterm, double E, double extra_hi, float *out_lo,
+                            float *out_hi, size_t pix) {
+  const double wlo = (nterm + 16.0) * 0x1p-51 * (double)acc.magl;
+  const double whi = (nterm + 16.0) * 0x1p-51 * (double)acc.magh;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double sl = 0.0, sh = 0.0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) { sl += fabs(acc.lo[c][j]); sh += fabs(acc.hi[c][j]); }
+    double lo = acc.lo[c][P] - sl - E - wlo;
+    double hi = fmin(acc.hi[c][P] + sh, acc.ihi[c]) + E + whi + extra_hi;
+    lo = fmin(fmax(lo, 0.0), 1.0);
+    hi = fmin(fmax(hi, 0.0), 1.0);
+    out_lo[pix + c] = __double2float_rd(lo);
+    out_hi[pix + c] = __double2float_ru(hi);
+  }
+}
+
+}  // namespace ar

@@ -1,0 +1,363 @@
+// General pixel loop for pose boxes whose depth order can change (rotations), gfx950.
+//
+// BlendInd (Alg. BlendInd) with the three-valued Ind(d_i - d_j):
+//   T_hi[i] = prod_{j: Ind_ij = 1} (1 - a_lo[j]),   T_lo[i] = prod_{j: Ind_ij != 0} (1 - a_hi[j]).
+// Ind is a property of the Gaussian pair, not of the pixel, so it is decided once per
+// tile list in FP64 (k_runs) on two sound bounds of d_i - d_j: the identity
+// A_z (uw_i - uw_j) and the literal difference of the depth forms (1e-10 margin).
+// Lists are in order of the upper depth bound; with depth intervals [dlo, dhi] every
+// j whose dhi_j < dlo_i - m is in front of i for sure and every j whose
+// dhi_j >= dhi_i + wmax + m is behind for sure, so only the window between needs
+// the pairwise test.  The sets {j: Ind_ij = 1} and {j: Ind_ij != 0} are stored as
+// runs of list positions.
+//
+// The pixel loop (k_raster_general) has two phases per tile:
+//   A: every wave takes a contiguous segment of the list and writes, per pixel, the
+//      running sums of log(1 - a_lo) and log(1 - a_hi) (FP64) and the running count
+//      of a_hi = 1; segment totals are exchanged through LDS;
+//   B: for each Gaussian i, the product over a run [a, b) is exp(L(b) - L(a)), so
+//      T_lo[i], T_hi[i] cost two loads per run; the colour forms are then accumulated
+//      as in the translation loop.
+// The prefix sums carry a rounding bound that is added outward before exp.
+#include <hip/hip_runtime.h>
+
+#include "ar_blend.h"
+#include "ar_internal.h"
+
+namespace ar {
+
+constexpr double kIndMargin = 1e-10;   // margin of the literal depth-difference test
+constexpr double kWinMargin = 1e-9;    // margin of the depth-interval window
+
+// widest depth interval of each tile's list
+__global__ __launch_bounds__(256) void k_tile_wmax(const uint32_t *__restrict__ ranges,
+                                                   const uint32_t *__restrict__ lists,
+                                                   const double *__restrict__ dint, double *__restrict__ wmax) {
+  __shared__ double red[256];
+  const int tile = blockIdx.x;
+  const uint32_t beg = ranges[2 * tile], end = ranges[2 * tile + 1];
+  double m = 0.0;
+  for (uint32_t p = beg + threadIdx.x; p < end; p += 256) {
+    const uint32_t g = lists[p];
+    m = fmax(m, dint[2 * (size_t)g + 1] - dint[2 * (size_t)g]);
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) wmax[tile] = red[0];
+}
+
+// Ind(d_i - d_j) in {0, 1, 2 = unknown} (see the file comment)
+template <int P>
+__device__ __forceinline__ int ind_pair(const PoseForms *__restrict__ pose, const double *uwi, const double *uwj,
+                                        const double *dfi, const double *dfj) {
+  // identity bound: sum_l A_z,l * (uw_i - uw_j)_l, each term a scaled form
+  double lo[P + 1], up[P + 1];
+#pragma unroll
+  for (int k = 0; k <= P; ++k) { lo[k] = 0.0; up[k] = 0.0; }
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const double c = uwi[l] - uwj[l];
+    const double(*a)[kMaxP + 1] = pose->A[6 + l];
+    const double *fl = c >= 0.0 ? a[0] : a[1];
+    const double *fu = c >= 0.0 ? a[1] : a[0];
+#pragma unroll
+    for (int k = 0; k < P; ++k) { lo[k] += c * fl[k]; up[k] += c * fu[k]; }
+    lo[P] += c * fl[kMaxP];
+    up[P] += c * fu[kMaxP];
+  }
+  double slo = 0.0, sup = 0.0;
+#pragma unroll
+  for (int k = 0; k < P; ++k) { slo += fabs(lo[k]); sup += fabs(up[k]); }
+  const double lo_r = lo[P] - slo, hi_r = up[P] + sup;
+  // literal bound: d_i.lower - d_j.upper and d_i.upper - d_j.lower
+  double sl = 0.0, sh = 0.0;
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    sl += fabs(dfi[k] - dfj[kMaxP + 1 + k]);
+    sh += fabs(dfi[kMaxP + 1 + k] - dfj[k]);
+  }
+  const double lo_l = (dfi[kMaxP] - dfj[2 * kMaxP + 1]) - sl;
+  const double hi_l = (dfi[2 * kMaxP + 1] - dfj[kMaxP]) + sh;
+  if (lo_r > 0.0 || lo_l > kIndMargin) return 1;
+  if (hi_r <= 0.0 || hi_l <= -kIndMargin) return 0;
+  return 2;
+}
+
+// One thread per (tile, list position i): runs of {j: Ind_ij = 1} and {j: Ind_ij != 0}.
+template <int P, bool EMIT>
+__global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey, const uint32_t *__restrict__ ranges,
+                                              const uint32_t *__restrict__ lists, const double *__restrict__ dint,
+                                              const double *__restrict__ dform, const double *__restrict__ wmax,
+                                              const PoseForms *__restrict__ pose, SceneDev sc, int npairs,
+                                              uint32_t *__restrict__ cnt, uint32_t *__restrict__ runs,
+                                              unsigned long long *__restrict__ counters) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const uint32_t tile = pkey[p];
+  const int beg = (int)ranges[2 * tile], n = (int)ranges[2 * tile + 1] - beg;
+  const int i = p - beg;
+  const uint32_t *list = lists + beg;
+  const uint32_t gi = list[i];
+  const double dlo_i = dint[2 * (size_t)gi], dhi_i = dint[2 * (size_t)gi + 1];
+  // first position whose upper depth reaches dlo_i - m (all before are in front)
+  int a = 0, b = i;
+  const double t1 = dlo_i - kWinMargin;
+  while (a < b) {
+    const int mid = (a + b) >> 1;
+    if (dint[2 * (size_t)list[mid] + 1] < t1) a = mid + 1; else b = mid;
+  }
+  const int ps = a;
+  // first position whose upper depth reaches dhi_i + wmax + m (all from there are behind)
+  a = i;
+  b = n;
+  const double t2 = dhi_i + wmax[tile] + kWinMargin;
+  while (a < b) {
+    const int mid = (a + b) >> 1;
+    if (dint[2 * (size_t)list[mid] + 1] < t2) a = mid + 1; else b = mid;
+  }
+  const int qe = a;
+  const double uwi[3] = {sc.mean[gi], sc.mean[sc.n + gi], sc.mean[2 * sc.n + gi]};
+  const double *dfi = dform + (size_t)gi * 2 * (kMaxP + 1);
+  uint32_t *out_def = nullptr, *out_may = nullptr;
+  if (EMIT) {
+    out_def = runs + 2 * (size_t)cnt[2 * (size_t)p];
+    out_may = runs + 2 * (size_t)cnt[2 * (size_t)p + 1];
+  }
+  uint32_t ndef = 0, nmay = 0;
+  int def_start = ps > 0 ? 0 : -1;   // open run [0, ps) of certain occluders
+  int may_start = ps > 0 ? 0 : -1;
+  for (int j = ps; j < qe; ++j) {
+    int ind = 0;
+    if (j != i) {
+      const uint32_t gj = list[j];
+      const double uwj[3] = {sc.mean[gj], sc.mean[sc.n + gj], sc.mean[2 * sc.n + gj]};
+      ind = ind_pair<P>(pose, uwi, uwj, dfi, dform + (size_t)gj * 2 * (kMaxP + 1));
+    }
+    const bool d1 = ind == 1, m1 = ind != 0;
+    if (d1 && def_start < 0) def_start = j;
+    if (!d1 && def_start >= 0) {
+      if (EMIT) { out_def[2 * ndef] = (uint32_t)def_start; out_def[2 * ndef + 1] = (uint32_t)j; }
+      ++ndef;
+      def_start = -1;
+    }
+    if (m1 && may_start < 0) may_start = j;
+    if (!m1 && may_start >= 0) {
+      if (EMIT) { out_may[2 * nmay] = (uint32_t)may_start; out_may[2 * nmay + 1] = (uint32_t)j; }
+      ++nmay;
+      may_start = -1;
+    }
+  }
+  if (def_start >= 0) {
+    if (EMIT) { out_def[2 * ndef] = (uint32_t)def_start; out_def[2 * ndef + 1] = (uint32_t)qe; }
+    ++ndef;
+  }
+  if (may_start >= 0) {
+    if (EMIT) { out_may[2 * nmay] = (uint32_t)may_start; out_may[2 * nmay + 1] = (uint32_t)qe; }
+    ++nmay;
+  }
+  if (!EMIT) {
+    cnt[2 * (size_t)p] = ndef;
+    cnt[2 * (size_t)p + 1] = nmay;
+    atomicMax(&counters[5], (unsigned long long)(qe - ps));
+  }
+}
+
+// offset of list position x: its segment's start total (segments of G waves)
+__device__ __forceinline__ int seg_of(int x, int n, int G) {
+  // segment w covers [w n / G, (w + 1) n / G)
+  int w = (int)(((long long)x * G) / n);
+  while (w > 0 && x < (int)(((long long)w * n) / G)) --w;
+  while (w + 1 < G && x >= (int)(((long long)(w + 1) * n) / G)) ++w;
+  return w;
+}
+
+template <int P>
+__global__ __launch_bounds__(512) void k_raster_general(const float *__restrict__ recs,
+                                                        const uint32_t *__restrict__ ranges,
+                                                        const uint32_t *__restrict__ lists,
+                                                        const uint32_t *__restrict__ cnt,
+                                                        const uint32_t *__restrict__ runs, Params prm,
+                                                        double2 *__restrict__ pre, uint32_t *__restrict__ prez,
+                                                        float *__restrict__ out_lo, float *__restrict__ out_hi,
+                                                        unsigned long long *__restrict__ counters) {
+  using R = Rec<P>;
+  extern __shared__ double smem[];
+  const int G = prm.groups;
+  double *offl = smem;                   // [G][64] segment start of sum log(1 - a_lo)
+  double *offh = smem + G * 64;          // [G][64] segment start of sum log(1 - a_hi)
+  uint32_t *offz = (uint32_t *)(smem + 2 * G * 64);   // [G][64]
+  double *red = smem + 2 * G * 64 + (G * 64 + 1) / 2; // [64][6(P+1)+4]
+  const int lane = threadIdx.x & 63;
+  const int g = threadIdx.x >> 6;
+  const int tile = blockIdx.x;
+  const int tx = tile % prm.ntx, ty = tile / prm.ntx;
+  const int col = tx * kTile + (lane & 7), row = ty * kTile + (lane >> 3);
+  const bool inimg = col < prm.width && row < prm.height;
+  const double uxd = (double)col + 0.5 - prm.cx, uyd = (double)row + 0.5 - prm.cy;
+  const float ux = (float)uxd, uy = (float)uyd;
+  const int beg = (int)ranges[2 * tile];
+  const int n = (int)ranges[2 * tile + 1] - beg;
+  const uint32_t *list = lists + beg;
+  const int s0 = (int)(((long long)g * n) / G), s1 = (int)(((long long)(g + 1) * n) / G);
+
+  // phase A: per-pixel running sums over this wave's segment
+  double Ll = 0.0, Lh = 0.0;
+  uint32_t Z = 0;
+  unsigned long long npairs = 0;
+  for (int j = s0; j < s1; ++j) {
+    const uint32_t gid = list[j];
+    const float *rec = recs + (size_t)gid * R::STRIDE;
+    const int type = __float_as_int(rec[R::SC + R::TYPE]);
+    const bool kept = inimg && pair_kept<P>(rec, type, ux, uy);
+    if (kept) {
+      double alo, ahi;
+      alpha_interval<P>(rec, type, uxd, uyd, alo, ahi);
+      Ll += log(1.0 - alo);
+      if (ahi >= 1.0) ++Z;
+      else Lh += log(1.0 - ahi);
+    }
+    pre[(size_t)(beg + j) * 64 + lane] = make_double2(Ll, Lh);
+    prez[(size_t)(beg + j) * 64 + lane] = Z;
+  }
+  offl[g * 64 + lane] = Ll;
+  offh[g * 64 + lane] = Lh;
+  offz[g * 64 + lane] = Z;
+  __syncthreads();
+  if (g == 0) {
+    double al = 0.0, ah = 0.0;
+    uint32_t az = 0;
+    for (int w = 0; w < G; ++w) {
+      const double tl = offl[w * 64 + lane], th = offh[w * 64 + lane];
+      const uint32_t tz = offz[w * 64 + lane];
+      offl[w * 64 + lane] = al;
+      offh[w * 64 + lane] = ah;
+      offz[w * 64 + lane] = az;
+      al += tl;
+      ah += th;
+      az += tz;
+    }
+  }
+  __syncthreads();
+
+  // phase B: transmittances from the runs, colour forms
+  Acc<P> acc;
+  acc_zero<P>(acc);
+  const double nn = (double)(n + 2);
+  for (int i = s0; i < s1; ++i) {
+    const uint32_t gid = list[i];
+    const float *rec = recs + (size_t)gid * R::STRIDE;
+    const int type = __float_as_int(rec[R::SC + R::TYPE]);
+    const bool kept = inimg && pair_kept<P>(rec, type, ux, uy);
+    if (!kept) continue;
+    const size_t slot = (size_t)(beg + i);
+    // runs of certain occluders and of possible occluders
+    const uint32_t d0 = cnt[2 * slot], d1 = cnt[2 * slot + 1];
+    const uint32_t m0 = cnt[2 * slot + 1], m1 = cnt[2 * slot + 2];
+    double sum_l = 0.0, err_l = 0.0, sum_h = 0.0, err_h = 0.0;
+    uint32_t zc = 0;
+    for (uint32_t r = d0; r < d1; ++r) {
+      const int a = (int)runs[2 * (size_t)r], b = (int)runs[2 * (size_t)r + 1];
+      double La = 0.0, Lb = 0.0;
+      if (a > 0) La = pre[(size_t)(beg + a - 1) * 64 + lane].x + offl[seg_of(a - 1, n, G) * 64 + lane];
+      if (b > 0) Lb = pre[(size_t)(beg + b - 1) * 64 + lane].x + offl[seg_of(b - 1, n, G) * 64 + lane];
+      sum_l += Lb - La;
+      err_l += fabs(La) + fabs(Lb);
+    }
+    for (uint32_t r = m0; r < m1; ++r) {
+      const int a = (int)runs[2 * (size_t)r], b = (int)runs[2 * (size_t)r + 1];
+      double La = 0.0, Lb = 0.0;
+      uint32_t Za = 0, Zb = 0;
+      if (a > 0) {
+        const int w = seg_of(a - 1, n, G);
+        La = pre[(size_t)(beg + a - 1) * 64 + lane].y + offh[w * 64 + lane];
+        Za = prez[(size_t)(beg + a - 1) * 64 + lane] + offz[w * 64 + lane];
+      }
+      if (b > 0) {
+        const int w = seg_of(b - 1, n, G);
+        Lb = pre[(size_t)(beg + b - 1) * 64 + lane].y + offh[w * 64 + lane];
+        Zb = prez[(size_t)(beg + b - 1) * 64 + lane] + offz[w * 64 + lane];
+      }
+      sum_h += Lb - La;
+      err_h += fabs(La) + fabs(Lb);
+      zc += Zb - Za;
+    }
+    // rounding of the logs and of the running sums: (terms + 2) 2^-51 per magnitude
+    const double thi = exp(sum_l + nn * 0x1p-51 * err_l) * (1.0 + 0x1p-50);
+    const double tlo = zc ? 0.0 : exp(sum_h - nn * 0x1p-51 * err_h) * (1.0 - 0x1p-50);
+    double alo, ahi;
+    pair_contrib<P>(rec, type, uxd, uyd, tlo, fmin(thi, 1.0), acc, alo, ahi);
+    ++npairs;
+  }
+  acc_reduce<P>(acc, red, G, g, lane);
+  unsigned long long c = npairs;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if (lane == 0 && c) atomicAdd(&counters[0], c);
+  if (g != 0 || !inimg) return;
+  write_pixel<P>(acc, (double)n, prm.E, 0.0, out_lo, out_hi, ((size_t)row * prm.width + col) * 3);
+}
+
+// ---------------------------------------------------------------------------------
+hipError_t launch_tile_wmax(const Workspace &ws, const uint32_t *lists, int ntiles, hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_wmax, dim3(ntiles), dim3(256), 0, s, ws.tile_range, lists, ws.dint, ws.wmax);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_runs_p(const Workspace &ws, const uint32_t *lists, const PoseForms *pose, const SceneDev &sc,
+                                int npairs, bool emit, hipStream_t s) {
+  const dim3 grid((npairs + 255) / 256), block(256);
+  if (emit)
+    hipLaunchKernelGGL((k_runs<P, true>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint, ws.dform,
+                       ws.wmax, pose, sc, npairs, ws.run_cnt, ws.runs, ws.counters);
+  else
+    hipLaunchKernelGGL((k_runs<P, false>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint, ws.dform,
+                       ws.wmax, pose, sc, npairs, ws.run_cnt, ws.runs, ws.counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *pose, const SceneDev &sc,
+                       int npairs, bool emit, hipStream_t s) {
+  if (npairs <= 0) return hipSuccess;
+  switch (P) {
+    case 0: return launch_runs_p<0>(ws, lists, pose, sc, npairs, emit, s);
+    case 1: return launch_runs_p<1>(ws, lists, pose, sc, npairs, emit, s);
+    case 2: return launch_runs_p<2>(ws, lists, pose, sc, npairs, emit, s);
+    case 3: return launch_runs_p<3>(ws, lists, pose, sc, npairs, emit, s);
+    case 4: return launch_runs_p<4>(ws, lists, pose, sc, npairs, emit, s);
+    case 5: return launch_runs_p<5>(ws, lists, pose, sc, npairs, emit, s);
+    case 6: return launch_runs_p<6>(ws, lists, pose, sc, npairs, emit, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int P>
+static hipError_t launch_general_p(const Workspace &ws, const uint32_t *lists, const Params &prm, float *lo,
+                                   float *hi, hipStream_t s) {
+  const int ntiles = prm.ntx * prm.nty;
+  const int G = prm.groups;
+  constexpr int kRed = 6 * (P + 1) + 3 + 1;
+  const size_t shm = sizeof(double) * (2 * G * 64 + (G * 64 + 1) / 2 + 64 * kRed);
+  hipLaunchKernelGGL(k_raster_general<P>, dim3(ntiles), dim3(64 * G), shm, s, ws.rec, ws.tile_range, lists,
+                     ws.run_cnt, ws.runs, prm, (double2 *)ws.pre, ws.prez, lo, hi, ws.counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_raster_general(int P, const Workspace &ws, const uint32_t *lists, const Params &prm, float *lo,
+                                 float *hi, hipStream_t s) {
+  switch (P) {
+    case 0: return launch_general_p<0>(ws, lists, prm, lo, hi, s);
+    case 1: return launch_general_p<1>(ws, lists, prm, lo, hi, s);
+    case 2: return launch_general_p<2>(ws, lists, prm, lo, hi, s);
+    case 3: return launch_general_p<3>(ws, lists, prm, lo, hi, s);
+    case 4: return launch_general_p<4>(ws, lists, prm, lo, hi, s);
+    case 5: return launch_general_p<5>(ws, lists, prm, lo, hi, s);
+    case 6: return launch_general_p<6>(ws, lists, prm, lo, hi, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ar

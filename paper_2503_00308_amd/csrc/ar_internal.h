@@ -98,13 +98,16 @@ struct Workspace {
   unsigned long long *counters = nullptr;  // [8] stats
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // call start, raster start, raster end
   unsigned long long *host_counters = nullptr;  // pinned
-  // rotation path
-  uint32_t *win = nullptr;     // [pairs][2] window start / end per list position
-  uint32_t *mask_off = nullptr;  // [pairs + 1]
-  uint32_t *masks = nullptr;   // window masks
-  size_t cap_masks = 0;
-  float *ivl = nullptr;        // [pairs][64] alpha intervals (lo, hi) per pixel
-  size_t cap_ivl = 0;
+  // general (rotation) path
+  double *dint = nullptr;      // [n][2] depth interval (lo, hi) by gid
+  double *wmax = nullptr;      // [tiles] widest depth interval of the tile's list
+  uint32_t *run_cnt = nullptr; // [pairs][2] + 1: Def / May run counts, then offsets
+  size_t cap_run_cnt = 0;
+  uint32_t *runs = nullptr;    // [runs][2] list-position ranges [start, end)
+  size_t cap_runs = 0;
+  double *pre = nullptr;       // [pairs][64][2] per-pixel prefix sums of log(1 - a_lo), log(1 - a_hi)
+  uint32_t *prez = nullptr;    // [pairs][64] per-pixel prefix counts of a_hi == 1
+  size_t cap_pre = 0;
 };
 
 // ---- launchers (ar_project.hip) ----
@@ -125,12 +128,11 @@ hipError_t launch_emit_tiles(int P, const Workspace &ws, int n, const Params &pr
 hipError_t launch_tile_ranges(const uint32_t *keys, int npairs, uint32_t *ranges, int ntiles, hipStream_t s);
 hipError_t launch_raster_translation(int P, const Workspace &ws, const uint32_t *lists, const SceneDev &sc,
                                      const Params &prm, float *lo, float *hi, hipStream_t s);
-hipError_t launch_windows(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *pose,
-                          const SceneDev &sc, const Params &prm, int npairs, hipStream_t s,
-                          uint32_t *max_window_dev);
-hipError_t launch_fill_masks(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *pose,
-                             const SceneDev &sc, const Params &prm, int npairs, hipStream_t s);
-hipError_t launch_raster_general(int P, const Workspace &ws, const uint32_t *lists, const SceneDev &sc,
-                                 const Params &prm, float *lo, float *hi, hipStream_t s);
+// general path (ar_general.hip)
+hipError_t launch_tile_wmax(const Workspace &ws, const uint32_t *lists, int ntiles, hipStream_t s);
+hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *pose, const SceneDev &sc,
+                       int npairs, bool emit, hipStream_t s);
+hipError_t launch_raster_general(int P, const Workspace &ws, const uint32_t *lists, const Params &prm, float *lo,
+                                 float *hi, hipStream_t s);
 
 }  // namespace ar

@@ -275,7 +275,7 @@ template <int P>
 __global__ __launch_bounds__(64) void k_project(SceneDev sc, const PoseForms *__restrict__ pose, Params prm,
                                                 float *__restrict__ rec_out, uint64_t *__restrict__ key_out,
                                                 uint64_t *__restrict__ key_sort, uint32_t *__restrict__ perm_out, int32_t *__restrict__ rect_out,
-                                                double *__restrict__ dform_out,
+                                                double *__restrict__ dform_out, double *__restrict__ dint_out,
                                                 unsigned long long *__restrict__ counters) {
   using R = Rec<P>;
   const int n = sc.n;
@@ -381,6 +381,8 @@ __global__ __launch_bounds__(64) void k_project(SceneDev sc, const PoseForms *__
   for (int k = 0; k < P; ++k) { df[k] = d.lo[k]; df[kMaxP + 1 + k] = d.up[k]; }
   df[kMaxP] = d.lo[P];
   df[2 * kMaxP + 1] = d.up[P];
+  dint_out[2 * (size_t)g] = dlo;
+  dint_out[2 * (size_t)g + 1] = dhi;
 
   // record
   store_lf2<P>(rec + R::D2, D2);
@@ -498,7 +500,7 @@ template <int P>
 static hipError_t launch_project_p(const SceneDev &sc, const PoseForms *pose, const Params &prm, Workspace &ws,
                                    hipStream_t s) {
   hipLaunchKernelGGL(k_project<P>, dim3((sc.n + 63) / 64), dim3(64), 0, s, sc, pose, prm, ws.rec, ws.key, ws.key_sort,
-                     ws.perm, ws.rect, ws.dform, ws.counters);
+                     ws.perm, ws.rect, ws.dform, ws.dint, ws.counters);
   return hipGetLastError();
 }
 

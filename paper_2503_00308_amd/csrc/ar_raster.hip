@@ -26,7 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include "ar_internal.h"
-#include "ar_pair.h"
+#include "ar_blend.h"
 
 namespace ar {
 
@@ -138,104 +138,6 @@ hipError_t launch_tile_ranges(const uint32_t *keys, int npairs, uint32_t *ranges
 // ---------------------------------------------------------------------------------
 // translation pixel loop
 // ---------------------------------------------------------------------------------
-template <int P>
-struct Acc {
-  double lo[3][P + 1];
-  double hi[3][P + 1];
-  double ihi[3];
-  float magl, magh;  // magnitude sums bounding the FP64 rounding of the sums
-};
-
-template <int P>
-__device__ __forceinline__ void acc_zero(Acc<P> &a) {
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-#pragma unroll
-    for (int j = 0; j <= P; ++j) { a.lo[c][j] = 0.0; a.hi[c][j] = 0.0; }
-    a.ihi[c] = 0.0;
-  }
-  a.magl = 0.0f;
-  a.magh = 0.0f;
-}
-
-// dst += (pre_lo, pre_hi) * src
-template <int P>
-__device__ __forceinline__ void acc_fma(Acc<P> &dst, const Acc<P> &src, double pre_lo, double pre_hi) {
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-#pragma unroll
-    for (int j = 0; j <= P; ++j) {
-      dst.lo[c][j] = fma(pre_lo, src.lo[c][j], dst.lo[c][j]);
-      dst.hi[c][j] = fma(pre_hi, src.hi[c][j], dst.hi[c][j]);
-    }
-    dst.ihi[c] = fma(pre_hi, src.ihi[c], dst.ihi[c]);
-  }
-  dst.magl = fmaf((float)pre_lo, src.magl, dst.magl) * (1.0f + 4.0f * kU);
-  dst.magh = fmaf((float)pre_hi, src.magh, dst.magh) * (1.0f + 4.0f * kU);
-}
-
-// One (pixel, Gaussian) pair: alpha bounds and its BlendInd contribution with the
-// transmittances (tlo, thi) of the Gaussians in front.  Returns the alpha interval.
-template <int P>
-__device__ __forceinline__ void pair_contrib(const float *__restrict__ rec, int type, float ux, float uy, float dux,
-                                             float duy, float d2, double tlo, double thi, Acc<P> &acc, float &a_lo,
-                                             float &a_hi) {
-  using R = Rec<P>;
-  const float *sc = rec + R::SC;
-  const float o = sc[R::O];
-  const double c3[3] = {(double)sc[R::C0], (double)sc[R::C1], (double)sc[R::C2]};
-  if (type == kNormal) {
-    SForms<P> s;
-    s_forms<P>(rec, ux, uy, dux, duy, s);
-    ExpBounds b;
-    exp_bounds(s.slo, s.shi, o, b);
-    // lower alpha form  o e_dn (x_lower(e) - xlo + 1),  x_lower = -s_upper / 2
-    // upper alpha form  o e_up + o k_up (x_upper(e) - xlo),  x_upper = -s_lower / 2
-    const double wl = (double)o * (double)b.e_dn;
-    const double wk = (double)o * (double)b.k_up;
-    double gl[P + 1], gh[P + 1];
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-      gl[j] = wl * (-0.5 * (double)s.sh[j]);
-      gh[j] = wk * (-0.5 * (double)s.sl[j]);
-    }
-    gl[P] = wl * ((-0.5 * (double)s.sh[P] - (double)b.xlo) + 1.0);
-    gh[P] = (double)o * (double)b.e_up + wk * (-0.5 * (double)s.sl[P] - (double)b.xlo);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double wlo = c3[c] * tlo, whi = c3[c] * thi;
-#pragma unroll
-      for (int j = 0; j <= P; ++j) {
-        acc.lo[c][j] = fma(wlo, gl[j], acc.lo[c][j]);
-        acc.hi[c][j] = fma(whi, gh[j], acc.hi[c][j]);
-      }
-      acc.ihi[c] = fma(whi, (double)b.a_hi, acc.ihi[c]);
-    }
-    const float ml = (o * b.e_dn) * (0.5f * s.msh + fabsf(b.xlo) + 1.0f);
-    const float mh = o * b.e_up + (o * b.k_up) * (0.5f * s.msl + fabsf(b.xlo)) + b.a_hi;
-    acc.magl = fmaf((float)tlo, ml, acc.magl);
-    acc.magh = fmaf((float)thi, mh, acc.magh);
-    a_lo = b.a_lo;
-    a_hi = b.a_hi;
-  } else {
-    // MatrixInv fallback: [0, o exp(-d2 / (2 lam))]; near-plane straddler: [0, o]
-    float ah = o;
-    if (type == kFallback) {
-      const float lam = sc[R::LAM];
-      ah = fminf(o, (o * expf(-0.5f * (d2 * (1.0f - 4.0f * kU)) / lam)) * (1.0f + 16.0f * kU));
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double whi = c3[c] * thi;
-      acc.hi[c][P] = fma(whi, (double)ah, acc.hi[c][P]);
-      acc.ihi[c] = fma(whi, (double)ah, acc.ihi[c]);
-    }
-    acc.magh = fmaf((float)thi, 2.0f * ah, acc.magh);
-    a_lo = 0.0f;
-    a_hi = ah;
-  }
-}
-
 // first list position >= p that starts a new depth value (or n)
 __device__ __forceinline__ int cut_at(const uint32_t *__restrict__ list, const uint64_t *__restrict__ keys, int n, int p) {
   if (p <= 0) return 0;
@@ -261,8 +163,7 @@ __global__ __launch_bounds__(512) void k_raster_translation(const float *__restr
   extern __shared__ double smem[];
   const int G = prm.groups, C = prm.chunk;
   double *tch = smem;                                   // [2][G][64][2]
-  double *red = smem + 2 * G * 64 * 2;                  // [64][nred]
-  constexpr int kRed = 6 * (P + 1) + 3 + 1;             // doubles exchanged in the final reduction
+  double *red = smem + 2 * G * 64 * 2;                  // [64][6(P+1)+4] final reduction
   const int lane = threadIdx.x & 63;
   const int g = threadIdx.x >> 6;
   const int tile = blockIdx.x;
@@ -271,7 +172,6 @@ __global__ __launch_bounds__(512) void k_raster_translation(const float *__restr
   const bool inimg = col < prm.width && row < prm.height;
   const double uxd = (double)col + 0.5 - prm.cx, uyd = (double)row + 0.5 - prm.cy;
   const float ux = (float)uxd, uy = (float)uyd;
-  const float dux = 2.0f * (float)fabs((double)ux - uxd), duy = 2.0f * (float)fabs((double)uy - uyd);
   const int beg = (int)ranges[2 * tile];
   const int n = (int)ranges[2 * tile + 1] - beg;
   const uint32_t *list = lists + beg;
@@ -300,18 +200,12 @@ __global__ __launch_bounds__(512) void k_raster_translation(const float *__restr
         prev_key = key;
       }
       const int type = __float_as_int(rec[R::SC + R::TYPE]);
-      float d2 = 0.0f;
-      bool kept = inimg;
-      if (type != kWild) {
-        d2 = dist2_box(rec[R::SC + R::MU0LO], rec[R::SC + R::MU0HI], rec[R::SC + R::MU1LO], rec[R::SC + R::MU1HI],
-                       ux, uy);
-        kept = kept && (d2 <= rec[R::SC + R::R2]);
-      }
+      const bool kept = inimg && pair_kept<P>(rec, type, ux, uy);
       if (kept) {
-        float alo, ahi;
-        pair_contrib<P>(rec, type, ux, uy, dux, duy, d2, tg_lo, tg_hi, loc, alo, ahi);
-        tl_lo *= 1.0 - (double)ahi;
-        tl_hi *= 1.0 - (double)alo;
+        double alo, ahi;
+        pair_contrib<P>(rec, type, uxd, uyd, tg_lo, tg_hi, loc, alo, ahi);
+        tl_lo *= 1.0 - ahi;
+        tl_hi *= 1.0 - alo;
         ++npairs;
       }
     }
@@ -337,56 +231,13 @@ __global__ __launch_bounds__(512) void k_raster_translation(const float *__restr
     }
   }
 
-  // reduce the G waves' sums into wave 0
-  for (int w = 1; w < G; ++w) {
-    __syncthreads();
-    if (g == w) {
-      double *dst = red + lane * kRed;
-      int q = 0;
-      for (int c = 0; c < 3; ++c) {
-        for (int j = 0; j <= P; ++j) { dst[q++] = acc.lo[c][j]; dst[q++] = acc.hi[c][j]; }
-        dst[q++] = acc.ihi[c];
-      }
-      float *fm = (float *)(dst + q);  // last slot: the two magnitude sums
-      fm[0] = acc.magl;
-      fm[1] = acc.magh;
-    }
-    __syncthreads();
-    if (g == 0) {
-      const double *src = red + lane * kRed;
-      int q = 0;
-      for (int c = 0; c < 3; ++c) {
-        for (int j = 0; j <= P; ++j) { acc.lo[c][j] += src[q++]; acc.hi[c][j] += src[q++]; }
-        acc.ihi[c] += src[q++];
-      }
-      acc.magl = (acc.magl + ((const float *)(src + q))[0]) * (1.0f + 4.0f * kU);
-      acc.magh = (acc.magh + ((const float *)(src + q))[1]) * (1.0f + 4.0f * kU);
-    }
-  }
+  acc_reduce<P>(acc, red, G, g, lane);
   // pair count
   unsigned long long cnt = npairs;
   for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
   if (lane == 0 && cnt) atomicAdd(&counters[0], cnt);
   if (g != 0 || !inimg) return;
-
-  // bound on the FP64 rounding of all sums: (terms + 16) 2^-52 times the magnitudes
-  const double nterm = (double)(n + 16);
-  const double wlo = nterm * 0x1p-51 * (double)acc.magl;
-  const double whi = nterm * 0x1p-51 * (double)acc.magh;
-  const size_t pix = ((size_t)row * prm.width + col) * 3;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    double sl = 0.0, sh = 0.0;
-#pragma unroll
-    for (int j = 0; j < P; ++j) { sl += fabs(acc.lo[c][j]); sh += fabs(acc.hi[c][j]); }
-    double lo = acc.lo[c][P] - sl - prm.E - wlo;
-    double hi = fmin(acc.hi[c][P] + sh, acc.ihi[c]) + prm.E + whi;
-    if (early) hi += tt_hi;
-    lo = fmin(fmax(lo, 0.0), 1.0);
-    hi = fmin(fmax(hi, 0.0), 1.0);
-    out_lo[pix + c] = __double2float_rd(lo);
-    out_hi[pix + c] = __double2float_ru(hi);
-  }
+  write_pixel<P>(acc, (double)n, prm.E, early ? tt_hi : 0.0, out_lo, out_hi, ((size_t)row * prm.width + col) * 3);
 }
 
 template <int P>

@@ -41,6 +41,7 @@ def _oracle(scene, intr, box, opts=None, tiles=None):
 
 def _compare(name, glo, ghi, ref, mask=None):
     rlo, rhi = ref["lo"], ref["hi"]
+    assert np.all(np.isfinite(glo)) and np.all(np.isfinite(ghi))
     ok = ~ref["border"][..., None] & np.isfinite(rlo)
     if mask is not None:
         ok &= mask[..., None]
@@ -59,6 +60,7 @@ def _compare(name, glo, ghi, ref, mask=None):
 
 def _sound(name, scene, intr, box, glo, ghi, n=24):
     from oracle import pose, render
+    assert np.all(np.isfinite(glo)) and np.all(np.isfinite(ghi))
     rng = np.random.default_rng(11)
     worst = -np.inf
     for p in pose.sample_poses(box, n, rng):
@@ -159,3 +161,47 @@ def test_full_size_config2_sampled_tiles():
         mask[ty * 4:(ty + 1) * 4, tx * 4:(tx + 1) * 4] = True
     _compare("cfg2-tiles", glo, ghi, ref, mask)
     print("cfg2 stats", st, flush=True)
+
+
+# ---- pose boxes with rotation (depth order can change inside the box) -----------------
+@pytest.mark.parametrize("seed", [0, 1])
+def test_rotation_6dof_parity_and_soundness(seed):
+    sc = synth.box_surface_scene(300, n_boxes=3, seed=seed)
+    intr = synth.intrinsics(32)
+    box = synth.camera6_box(dt=0.03, drot=np.deg2rad(0.7))
+    glo, ghi, st = _run(sc, intr, box)
+    ref = _oracle(sc, intr, box)
+    print("rotation stats", st, flush=True)
+    _compare(f"rot6-{seed}", glo, ghi, ref)
+    _sound(f"rot6-{seed}", sc, intr, box, glo, ghi, 24)
+
+
+def test_orbit_cells_parity():
+    sc = synth.box_surface_scene(250, n_boxes=4, seed=3)
+    intr = synth.intrinsics(40)
+    cells = synth.orbit_cells(16, 30.0, seed=2)
+    for cell in cells[:3]:
+        glo, ghi, st = _run(sc, intr, cell)
+        ref = _oracle(sc, intr, cell)
+        _compare("orbit", glo, ghi, ref)
+        _sound("orbit", sc, intr, cell, glo, ghi, 12)
+
+
+def test_rotation_box_scene_64px():
+    """cfg-3-style scene (Gaussians on box surfaces, flat) at reduced size, 6-DoF box."""
+    sc = synth.box_surface_scene(2000, n_boxes=20, seed=4)
+    intr = synth.intrinsics(64)
+    box = synth.camera6_box(dt=0.05, drot=np.deg2rad(1.0))
+    glo, ghi, st = _run(sc, intr, box)
+    ref = _oracle(sc, intr, box, opts={"tile": 8})
+    print("box-scene stats", st, flush=True)
+    _compare("boxes64", glo, ghi, ref)
+
+
+def test_single_rotation_axis_parity():
+    sc = synth.random_scene(200, seed=9)
+    intr = synth.intrinsics(32)
+    box = synth.camera6_box(drot=(0.0, 0.0, np.deg2rad(2.0)))  # roll only
+    glo, ghi, _ = _run(sc, intr, box)
+    ref = _oracle(sc, intr, box)
+    _compare("roll", glo, ghi, ref)
