@@ -12,6 +12,8 @@ on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -24,6 +26,48 @@ if ROOT not in sys.path:
 # MI355X peaks used for the roofline (see the design notes for the derivation)
 PEAK_VALU_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, non-packed FP32 = FP64 rate
 PEAK_FP32_PACKED_TFLOPS = 157.3
+
+
+def kernel_fingerprint() -> str:
+    """Hash of the HIP sources; a traffic measurement is only used while it matches."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2503_00308_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(path):
+    """HBM bytes per launch of the per-pixel kernel from a committed counter summary
+    ("key: value" lines), or None when absent or taken on other kernel sources."""
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_fingerprint") != kernel_fingerprint():
+        return None
+    try:
+        return float(kv["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def calibrate_copy(mib: int):
+    """A plain device copy of known size, profiled with the same HBM counters to turn
+    counter readings into bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.rand(n, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 5}), flush=True)
 
 
 def alg_flops_per_pair(P: int) -> int:
@@ -69,16 +113,22 @@ def cpu_baseline(scene, intr, box, budget_s=20.0):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "raster_translation_cfg2_traffic.json"))
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_raster_translation_cfg2_traffic.txt"))
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is designed but not built",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
 
     import numpy as np
     import torch
@@ -109,10 +159,7 @@ def main():
     mean_pairs = float(np.mean(pairs))
     mean_raster_s = float(np.mean(raster_ms)) * 1e-3
     achieved = alg_flops_per_pair(P) * mean_pairs / mean_raster_s / 1e12
-    traffic = None
-    if os.path.exists(args.traffic):
-        with open(args.traffic) as f:
-            traffic = json.load(f).get("bytes_per_launch")
+    traffic = read_traffic(args.traffic)
     out = {
         "metric": "bounded pixel-Gaussian pairs/sec",
         "value": value,
