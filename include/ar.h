@@ -104,8 +104,10 @@ typedef struct {
 /*
  * Options; a zero field takes the default.
  *   tile        pixel tile side of the binning and of one workgroup, 8 (only value)
- *   groups      Gaussian groups (waves) per tile, 1..8 (default: chosen from the size)
- *   chunk       Gaussians per group and round, 4..256 (default 32)
+ *   groups      waves per tile of the rotation path's pixel loop, 1..8 (default: chosen
+ *               from the number of tiles)
+ *   chunk       list positions per segment of the translation path's pixel loop
+ *               (one wave each), 8..4096 (default: chosen from the number of pairs)
  *   taylor_k    MatrixInv order k (Sec. 3.1; default 8, the paper's default), 1..16
  *   cull_budget bound E on the colour change from pruning faint Gaussians (default 1e-7);
  *               Gaussian i is dropped from pixel u when its alpha is provably below
@@ -135,7 +137,7 @@ typedef struct {
   int32_t P;             /* number of pose variables of the box */
   int32_t max_window;    /* largest Ind window of uncertain depth order (rotations) */
   int32_t reserved;
-  double raster_ms;      /* device time of the per-pixel kernels (HIP events on the call's stream) */
+  double raster_ms;      /* device time of the main per-pixel kernel (HIP events on the call's stream) */
   double total_ms;       /* device time of the whole call from its first to its last kernel */
 } ar_stats;
 

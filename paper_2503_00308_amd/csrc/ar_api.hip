@@ -107,7 +107,7 @@ static int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_opt
   if (op) o = *op;
   if (o.tile != 0 && o.tile != kTile) return fail(AR_E_UNSUPPORTED, "tile %d: only %d is built", o.tile, kTile);
   if (o.groups < 0 || o.groups > 8) return fail(AR_E_INVALID, "groups %d outside [0, 8]", o.groups);
-  if (o.chunk != 0 && (o.chunk < 4 || o.chunk > 256)) return fail(AR_E_INVALID, "chunk %d outside [4, 256]", o.chunk);
+  if (o.chunk != 0 && (o.chunk < 8 || o.chunk > 4096)) return fail(AR_E_INVALID, "chunk %d outside [8, 4096]", o.chunk);
   if (o.taylor_k < 0 || o.taylor_k > 16) return fail(AR_E_INVALID, "taylor_k %d outside [1, 16]", o.taylor_k);
   if (!(o.cull_budget >= 0.0) || !isfinite(o.cull_budget) || o.cull_budget >= 1.0)
     return fail(AR_E_INVALID, "cull_budget must be in [0, 1)");
@@ -134,7 +134,7 @@ static int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_opt
     while (G < 8 && ntiles * G < 2048) G *= 2;
   }
   prm.groups = G;
-  prm.chunk = o.chunk ? o.chunk : 32;
+  prm.chunk = o.chunk;  // 0: chosen per call from the number of (tile, Gaussian) pairs
   return AR_OK;
 }
 
@@ -167,7 +167,7 @@ static int ensure_ws(Workspace &ws, int n, int ntiles) {
   if (!ws.counters) {
     HIP_TRY(hipMalloc((void **)&ws.counters, 8 * sizeof(unsigned long long)));
     HIP_TRY(hipHostMalloc((void **)&ws.host_counters, 16 * sizeof(unsigned long long), hipHostMallocDefault));
-    for (int i = 0; i < 3; ++i) HIP_TRY(hipEventCreate(&ws.ev[i]));
+    for (int i = 0; i < 4; ++i) HIP_TRY(hipEventCreate(&ws.ev[i]));
   }
   return AR_OK;
 }
@@ -194,6 +194,35 @@ static int ensure_runs(Workspace &ws, size_t nruns) {
   HIP_TRY(grow(ws.runs, 2 * need));
   ws.cap_runs = need;
   return AR_OK;
+}
+
+// translation path: segment table and partial results for up to nseg segments
+static int ensure_segments(Workspace &ws, size_t ntiles, size_t nseg, int P) {
+  if (ntiles + 2 > ws.cap_seg_off || !ws.seg_off) {
+    HIP_TRY(grow(ws.seg_off, ntiles + 2));
+    ws.cap_seg_off = ntiles + 2;
+  }
+  if (nseg > ws.cap_seg || !ws.seg_tile) {
+    const size_t need = nseg + nseg / 4 + 1024;
+    HIP_TRY(grow(ws.seg_tile, need));
+    ws.cap_seg = need;
+  }
+  const size_t doubles = nseg * (size_t)part_fields(P) * kTilePix;
+  if (doubles > ws.cap_part || !ws.part) {
+    const size_t need = doubles + doubles / 4 + 4096;
+    HIP_TRY(grow(ws.part, need));
+    ws.cap_part = need;
+  }
+  return AR_OK;
+}
+
+// Segment length of the translation pixel loop: about 4096 segments over the whole
+// image (four waves per SIMD of the 256-CU part), at least 32 list positions each.
+static int segment_length(const Params &prm, size_t npairs) {
+  if (prm.chunk > 0) return prm.chunk;
+  size_t L = (npairs + 4095) / 4096;
+  L = (L + 7) / 8 * 8;
+  return (int)std::min<size_t>(std::max<size_t>(L, 32), 4096);
 }
 
 static int ensure_pairs(Workspace &ws, size_t npairs) {
@@ -265,9 +294,14 @@ static int render_one(ar_scene *sc, const Params &prm, const ar_pose_box &box, i
   }
   HIP_TRY(launch_tile_ranges(ws.pair_key, (int)npairs, ws.tile_range, ntiles, s));
   if (!rotates) {
-    HIP_TRY(hipEventRecord(ws.ev[1], s));
-    HIP_TRY(launch_raster_translation(P, ws, ws.pair_val, sc->dev, prm, lo, hi, s));
-    HIP_TRY(hipEventRecord(ws.ev[2], s));
+    const int L = segment_length(prm, npairs);
+    const size_t nseg_max = (npairs + (size_t)L - 1) / (size_t)L + (size_t)ntiles;
+    rc = ensure_segments(ws, (size_t)ntiles, nseg_max, P);
+    if (rc) return rc;
+    HIP_TRY(launch_segments(ws, ntiles, L, s));
+    HIP_TRY(exclusive_scan_u32(ws.seg_off, ntiles + 1, ws, s));
+    HIP_TRY(launch_segment_map(ws, ntiles, s));
+    HIP_TRY(launch_raster_translation(P, ws, ws.pair_val, prm, L, (int)nseg_max, lo, hi, s));
   } else {
     // depth order may change inside the box: Ind runs per tile list, then the two-phase loop
     rc = ensure_general(ws, npairs);
@@ -288,11 +322,12 @@ static int render_one(ar_scene *sc, const Params &prm, const ar_pose_box &box, i
     HIP_TRY(launch_raster_general(P, ws, ws.pair_val, prm, lo, hi, s));
     HIP_TRY(hipEventRecord(ws.ev[2], s));
   }
+  HIP_TRY(hipEventRecord(ws.ev[3], s));
   HIP_TRY(hipMemcpyAsync(ws.host_counters, ws.counters, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   float ms_raster = 0.0f, ms_total = 0.0f;
   HIP_TRY(hipEventElapsedTime(&ms_raster, ws.ev[1], ws.ev[2]));
-  HIP_TRY(hipEventElapsedTime(&ms_total, ws.ev[0], ws.ev[2]));
+  HIP_TRY(hipEventElapsedTime(&ms_total, ws.ev[0], ws.ev[3]));
   if (st) {
     st->pairs += (int64_t)ws.host_counters[0];
     st->tile_pairs += (int64_t)npairs;
@@ -391,11 +426,12 @@ void ar_scene_destroy(ar_scene *sc) {
   ar::Workspace &w = sc->ws;
   void *bufs[] = {w.pose, w.rec, w.key, w.key_sort, w.key_alt, w.perm, w.perm_alt, w.rect, w.dform, w.count,
                   w.pair_key, w.pair_key_alt, w.pair_val, w.pair_val_alt, w.tile_range, w.hist, w.scan_tmp,
-                  w.counters, w.dint, w.wmax, w.run_cnt, w.runs, w.pre, w.prez, sc->base};
+                  w.counters, w.dint, w.wmax, w.run_cnt, w.runs, w.pre, w.prez, w.seg_off, w.seg_tile, w.part,
+                  sc->base};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (w.host_counters) (void)hipHostFree(w.host_counters);
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 4; ++i)
     if (w.ev[i]) (void)hipEventDestroy(w.ev[i]);
   delete sc;
 }

@@ -48,24 +48,23 @@ __device__ __forceinline__ void acc_fma(Acc<P> &dst, const Acc<P> &src, double p
 
 // Alpha interval of a MatrixInv fallback (footprint bound) or a near-plane straddler.
 template <int P>
-__device__ __forceinline__ double alpha_hi_special(const float *__restrict__ rec, int type, double ux, double uy) {
+__device__ __forceinline__ double alpha_hi_special(const double *__restrict__ rec, int type, double ux, double uy) {
   using R = Rec<P>;
-  const double o = (double)rec[R::SC + R::O];
+  const double o = rec[R::O];
   if (type != kFallback) return o;
-  const double d2 = dist2_box64(rec + R::SC + R::MU0LO, ux, uy);
-  const double lam = (double)rec[R::SC + R::LAM];
+  const double d2 = dist2_box64(rec_prune<P>(rec), ux, uy);
+  const double lam = rec[R::LAM];
   return fmin(o, o * exp(-0.5 * d2 * (1.0 - 8.0 * kU) / lam) * (1.0 + 16.0 * kU));
 }
 
 // One (pixel, Gaussian) pair: alpha bounds and its BlendInd contribution with the
 // transmittances (tlo, thi) of the Gaussians in front.  Returns the alpha interval.
 template <int P>
-__device__ __forceinline__ void pair_contrib(const float *__restrict__ rec, int type, double ux, double uy, double tlo,
-                                             double thi, Acc<P> &acc, double &a_lo, double &a_hi) {
+__device__ __forceinline__ void pair_contrib(const double *__restrict__ rec, int type, double ux, double uy,
+                                             double tlo, double thi, Acc<P> &acc, double &a_lo, double &a_hi) {
   using R = Rec<P>;
-  const float *sc = rec + R::SC;
-  const double o = (double)sc[R::O];
-  const double c3[3] = {(double)sc[R::C0], (double)sc[R::C1], (double)sc[R::C2]};
+  const double o = rec[R::O];
+  const double c3[3] = {rec[R::C + 0], rec[R::C + 1], rec[R::C + 2]};
   if (type == kNormal) {
     SForms<P> s;
     s_forms<P>(rec, ux, uy, s);
@@ -116,14 +115,14 @@ __device__ __forceinline__ void pair_contrib(const float *__restrict__ rec, int 
 
 // Alpha interval of one pair without the colour forms (types as in pair_contrib).
 template <int P>
-__device__ __forceinline__ void alpha_interval(const float *__restrict__ rec, int type, double ux, double uy,
+__device__ __forceinline__ void alpha_interval(const double *__restrict__ rec, int type, double ux, double uy,
                                                double &a_lo, double &a_hi) {
   using R = Rec<P>;
   if (type == kNormal) {
     SForms<P> s;
     s_forms<P>(rec, ux, uy, s);
     ExpBounds b;
-    exp_bounds(s.slo, s.shi, (double)rec[R::SC + R::O], b);
+    exp_bounds(s.slo, s.shi, rec[R::O], b);
     a_lo = b.a_lo;
     a_hi = b.a_hi;
   } else {
@@ -135,12 +134,11 @@ __device__ __forceinline__ void alpha_interval(const float *__restrict__ rec, in
 // Pruning test of one pair (float32, bit-identical to the definition): true when
 // Gaussian rec may contribute at the pixel.
 template <int P>
-__device__ __forceinline__ bool pair_kept(const float *__restrict__ rec, int type, float ux, float uy) {
-  using R = Rec<P>;
+__device__ __forceinline__ bool pair_kept(const double *__restrict__ rec, int type, float ux, float uy) {
   if (type == kWild) return true;
-  const float d2 =
-      dist2_box(rec[R::SC + R::MU0LO], rec[R::SC + R::MU0HI], rec[R::SC + R::MU1LO], rec[R::SC + R::MU1HI], ux, uy);
-  return d2 <= rec[R::SC + R::R2];
+  const float *pf = rec_prune<P>(rec);
+  const float d2 = dist2_box(pf[0], pf[1], pf[2], pf[3], ux, uy);
+  return d2 <= pf[4];
 }
 
 // Sum the G waves' accumulators into wave 0 through LDS (all threads of the block call it).

@@ -176,7 +176,7 @@ __device__ __forceinline__ int seg_of(int x, int n, int G) {
 }
 
 template <int P>
-__global__ __launch_bounds__(512) void k_raster_general(const float *__restrict__ recs,
+__global__ __launch_bounds__(512) void k_raster_general(const double *__restrict__ recs,
                                                         const uint32_t *__restrict__ ranges,
                                                         const uint32_t *__restrict__ lists,
                                                         const uint32_t *__restrict__ cnt,
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(512) void k_raster_general(const float *__restrict_
   uint32_t *offz = (uint32_t *)(smem + 2 * G * 64);   // [G][64]
   double *red = smem + 2 * G * 64 + (G * 64 + 1) / 2; // [64][6(P+1)+4]
   const int lane = threadIdx.x & 63;
-  const int g = threadIdx.x >> 6;
+  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile = blockIdx.x;
   const int tx = tile % prm.ntx, ty = tile / prm.ntx;
   const int col = tx * kTile + (lane & 7), row = ty * kTile + (lane >> 3);
@@ -210,8 +210,8 @@ __global__ __launch_bounds__(512) void k_raster_general(const float *__restrict_
   unsigned long long npairs = 0;
   for (int j = s0; j < s1; ++j) {
     const uint32_t gid = list[j];
-    const float *rec = recs + (size_t)gid * R::STRIDE;
-    const int type = __float_as_int(rec[R::SC + R::TYPE]);
+    const double *rec = recs + (size_t)gid * R::STRIDE;
+    const int type = rec_type<P>(rec);
     const bool kept = inimg && pair_kept<P>(rec, type, ux, uy);
     if (kept) {
       double alo, ahi;
@@ -249,8 +249,8 @@ __global__ __launch_bounds__(512) void k_raster_general(const float *__restrict_
   const double nn = (double)(n + 2);
   for (int i = s0; i < s1; ++i) {
     const uint32_t gid = list[i];
-    const float *rec = recs + (size_t)gid * R::STRIDE;
-    const int type = __float_as_int(rec[R::SC + R::TYPE]);
+    const double *rec = recs + (size_t)gid * R::STRIDE;
+    const int type = rec_type<P>(rec);
     const bool kept = inimg && pair_kept<P>(rec, type, ux, uy);
     if (!kept) continue;
     const size_t slot = (size_t)(beg + i);

@@ -6,6 +6,12 @@
 
 #include "../../include/ar.h"
 
+#define HIP_RET(expr)                       \
+  do {                                      \
+    const hipError_t e_ = (expr);           \
+    if (e_ != hipSuccess) return e_;        \
+  } while (0)
+
 namespace ar {
 
 constexpr int kMaxP = 6;        // pose variables: 3 translations + 3 angles
@@ -20,29 +26,45 @@ enum GaussType : int32_t {
   kDropped = 3    // behind the near plane at every pose: never contributes
 };
 
-// Per-Gaussian FP32 record consumed by the pixel loop.  Forms are (P coefficients,
-// constant); every stored lower form is rounded down and every upper form up.
-// d^2 and d*up are stored as two-float sums (hi + lo, about 48 bits): v = u d^2 - d up
-// cancels them, and the rounding of a single float would dominate v near the mean.
+// Per-Gaussian FP64 record consumed by the pixel loops (offsets in doubles).
+// Every pair of linear forms (lower l(e), upper h(e)) is stored in mid-radius form
+// m = (l + h) / 2, r = (h - l) / 2, so that l = m - r and h = m + r coefficient-wise:
+// scaling by a number a of either sign is then a m, |a| r with no per-lane choice of
+// which form to take.  Conversion rounding is absorbed into the constant of r.
+// The header holds the float32 pruning data (mean box, r^2, type) read first.
 template <int P>
 struct Rec {
   static constexpr int F = P + 1;
-  static constexpr int D2 = 0;          // d^2: lower (hi, lo), upper (hi, lo)
-  static constexpr int DUP = 4 * F;     // d*up_k, k = 0,1: lower (hi, lo), upper (hi, lo) each
-  static constexpr int B = 12 * F;      // B = Conic*Mp, entry e = 3k+n: (lower, upper)
-  static constexpr int BI = 24 * F;     // interval of B: lo[6], hi[6]
-  static constexpr int SC = 24 * F + 12;
-  // scalars (offsets from SC)
-  static constexpr int MD2 = 0, MDUP0 = 1, MDUP1 = 2, MBB0 = 3, MBB1 = 4, BMAX0 = 5, BMAX1 = 6;
-  static constexpr int O = 7, C0 = 8, C1 = 9, C2 = 10;
-  static constexpr int MU0LO = 11, MU0HI = 12, MU1LO = 13, MU1HI = 14, R2 = 15, LAM = 16;
-  static constexpr int TYPE = 17;
-  static constexpr int NSC = 20;
-  static constexpr int STRIDE = ((SC + NSC) + 3) / 4 * 4;
+  // header (16 doubles)
+  static constexpr int PRUNE = 0;            // float[0..3] mean box, float[4] r^2, int32[5] type
+  static constexpr int O = 3, LAM = 4;       // opacity, footprint eigenvalue bound
+  static constexpr int C = 5;                // colour (3)
+  static constexpr int MD2 = 8;              // sum_j |dm_j| + |dr_j|
+  static constexpr int MDUP = 9;             // (2) the same for d*up_k
+  static constexpr int MBB = 11;             // (2) max_n sum_j (|Bm| + |Br|) + 2 BMAX, for B_kn
+  static constexpr int BMAX = 13;            // (2) max_n max(|ylo|, |yhi|) of B_kn
+  static constexpr int HDR = 16;
+  static constexpr int DM = HDR, DR = HDR + F;   // d^2
+  static constexpr int PM = HDR + 2 * F;         // d*up_k, [2][F]
+  static constexpr int PR = HDR + 4 * F;         // [2][F]
+  static constexpr int BM = HDR + 6 * F;         // B = Conic*Mp, entry e = 3k+n, [6][F]
+  static constexpr int BR = HDR + 12 * F;        // [6][F]
+  static constexpr int CM = HDR + 18 * F;        // McCormick weights of B_e: [6][4]
+  static constexpr int STRIDE = ((CM + 24) + 7) / 8 * 8;
 };
 
 inline int rec_stride(int P) {
-  return ((24 * (P + 1) + 12 + 20) + 3) / 4 * 4;
+  return ((16 + 18 * (P + 1) + 24) + 7) / 8 * 8;
+}
+
+template <int P>
+__device__ __forceinline__ const float *rec_prune(const double *rec) {
+  return reinterpret_cast<const float *>(rec + Rec<P>::PRUNE);
+}
+
+template <int P>
+__device__ __forceinline__ int rec_type(const double *rec) {
+  return reinterpret_cast<const int32_t *>(rec + Rec<P>::PRUNE)[5];
 }
 
 // Pose set as linear forms over e in [-1,1]^P (FP64): uc = A (uw - tau) + beta.
@@ -79,7 +101,7 @@ struct Workspace {
   size_t cap_n = 0, cap_pairs = 0, cap_tiles = 0, cap_scratch = 0;
   void *pose = nullptr;        // PoseForms (one per cell)
   int32_t cap_cells = 0;
-  float *rec = nullptr;        // [n][stride]
+  double *rec = nullptr;       // [n][stride]
   uint64_t *key = nullptr;     // [n] depth key (by gid, kept for tie tests)
   uint64_t *key_sort = nullptr;  // [n] copy of the keys, sorted in place
   uint64_t *key_alt = nullptr; // [n]
@@ -96,8 +118,14 @@ struct Workspace {
   uint32_t *scan_tmp = nullptr;
   size_t cap_scan = 0;
   unsigned long long *counters = nullptr;  // [8] stats
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // call start, raster start, raster end
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // call start, pixel kernel start / end, call end
   unsigned long long *host_counters = nullptr;  // pinned
+  // translation path: segments of the tile lists and their partial results
+  uint32_t *seg_off = nullptr;   // [tiles + 1] first segment of each tile, then the total
+  uint32_t *seg_tile = nullptr;  // [segments] tile of each segment
+  size_t cap_seg = 0, cap_seg_off = 0;
+  double *part = nullptr;        // [segments][fields][64]
+  size_t cap_part = 0;           // doubles
   // general (rotation) path
   double *dint = nullptr;      // [n][2] depth interval (lo, hi) by gid
   double *wmax = nullptr;      // [tiles] widest depth interval of the tile's list
@@ -126,8 +154,12 @@ hipError_t ensure_hist(Workspace &ws, size_t n_entries);
 hipError_t launch_count_tiles(int P, const Workspace &ws, int n, const Params &prm, hipStream_t s);
 hipError_t launch_emit_tiles(int P, const Workspace &ws, int n, const Params &prm, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t *keys, int npairs, uint32_t *ranges, int ntiles, hipStream_t s);
-hipError_t launch_raster_translation(int P, const Workspace &ws, const uint32_t *lists, const SceneDev &sc,
-                                     const Params &prm, float *lo, float *hi, hipStream_t s);
+int part_fields(int P);
+hipError_t launch_segments(const Workspace &ws, int ntiles, int L, hipStream_t s);
+hipError_t launch_segment_map(const Workspace &ws, int ntiles, hipStream_t s);
+// records ev[1] / ev[2] around the per-segment pixel kernel
+hipError_t launch_raster_translation(int P, const Workspace &ws, const uint32_t *lists, const Params &prm, int L,
+                                     int nseg_max, float *lo, float *hi, hipStream_t s);
 // general path (ar_general.hip)
 hipError_t launch_tile_wmax(const Workspace &ws, const uint32_t *lists, int ntiles, hipStream_t s);
 hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *pose, const SceneDev &sc,

@@ -5,13 +5,13 @@
 //   q = Mmul(v, Conic, Mp) = v B           q_n = Mul(v_0, B_0n) + Mul(v_1, B_1n)
 //   s = Mmul(q, q^T)                       s = sum_n Sqr(q_n)
 //   x = -s / 2,  a = o Exp(x)
-// The forms are read from the FP32 record and evaluated in FP64: on gfx950 an FP64
-// FMA issues at the rate of a non-packed FP32 one, and FP32 evaluation alone moved the
-// upper image by several 1e-6 against the FP64 definition (coefficient roundings add up
-// over the hundreds of Gaussians of a pixel's relational sum).  Every form is computed
-// with round-to-nearest and its constant is then moved outward by a bound on the
-// rounding error of the operation (term magnitudes times small multiples of 2^-53);
-// concretised intervals are moved outward the same way.
+// All arithmetic is FP64 (on gfx950 an FP64 FMA issues at the rate of a non-packed
+// FP32 one).  Form pairs are carried in mid-radius form (m, r): lower = m - r,
+// upper = m + r.  Scaling by a of either sign gives (a m, |a| r), so the relaxations
+// need no per-lane choice between the lower and the upper form.  Every operation is
+// rounded to nearest; a bound on its rounding error (term magnitudes times small
+// multiples of 2^-53) is added to the radius constant, and concretised intervals are
+// moved outward the same way.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,108 +29,104 @@ struct SForms {
   double sl[P + 1];  // lower form of s
   double sh[P + 1];  // upper form of s
   double slo, shi;   // interval of s (outward)
-  double msl, msh;   // max over the box of |lower form|, |upper form|
+  double msl, msh;   // |constant| + sum |coefficients| of sl, sh
 };
 
+// (ux, uy): centred pixel coordinates (exact in FP64).
 template <int P>
-__device__ __forceinline__ double abs_sum(const double *f) {
-  double s = 0.0;
-#pragma unroll
-  for (int j = 0; j < P; ++j) s += fabs(f[j]);
-  return s;
-}
-
-// (ux, uy): centred pixel coordinates (FP64).
-template <int P>
-__device__ __forceinline__ void s_forms(const float *__restrict__ r, double ux, double uy, SForms<P> &o) {
+__device__ __forceinline__ void s_forms(const double *__restrict__ r, double ux, double uy, SForms<P> &o) {
   using R = Rec<P>;
   constexpr int F = P + 1;
-  constexpr double KC = (P + 3) * kU;   // concretisation: P additions, one subtraction, the widening
-  const float *sc = r + R::SC;
+  constexpr double KC = (P + 4) * kU;  // concretisation: P+1 additions, the subtractions, the widening
 
-  // v_k = u_k * D2 - DUP_k; D2, DUP are two-float sums (exact in FP64): one fma each
-  const float *d2l_h = r + R::D2, *d2l_l = d2l_h + F, *d2u_h = d2l_h + 2 * F, *d2u_l = d2l_h + 3 * F;
-  double vl[2][F], vh[2][F], vlo[2], Mv[2];
+  // v_k = u_k D2 - DUP_k:  vm = u dm - pm,  vr = |u| dr + pr
+  double vm[2][F], vr[2][F], vlo[2], Mv[2];
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     const double u = k ? uy : ux;
-    const float *pl_h = r + R::DUP + 4 * F * k, *pl_l = pl_h + F, *pu_h = pl_h + 2 * F, *pu_l = pl_h + 3 * F;
-    const bool pos = u >= 0.0;
+    const double au = fabs(u);
 #pragma unroll
     for (int j = 0; j < F; ++j) {
-      const double dl = (double)d2l_h[j] + (double)d2l_l[j], du = (double)d2u_h[j] + (double)d2u_l[j];
-      const double pl = (double)pl_h[j] + (double)pl_l[j], pu = (double)pu_h[j] + (double)pu_l[j];
-      vl[k][j] = fma(u, pos ? dl : du, -pu);
-      vh[k][j] = fma(u, pos ? du : dl, -pl);
+      vm[k][j] = fma(u, r[R::DM + j], -r[R::PM + F * k + j]);
+      vr[k][j] = fma(au, r[R::DR + j], r[R::PR + F * k + j]);
     }
-    // one rounding per coefficient, plus the rounding of u itself
-    const double ev = 4.0 * kU * fma(fabs(u), (double)sc[R::MD2], (double)sc[R::MDUP0 + k]);
-    vl[k][P] -= ev;
-    vh[k][P] += ev;
-    const double Sl = abs_sum<P>(vl[k]), Sh = abs_sum<P>(vh[k]);
-    const double Ml = fabs(vl[k][P]) + Sl, Mh = fabs(vh[k][P]) + Sh;
-    vlo[k] = (vl[k][P] - Sl) - KC * Ml;
-    Mv[k] = fmax(Ml, Mh);
+    // sum_j |vm_j| + |vr_j| <= |u| MD2 + MDUP_k up to rounding; one rounding per coefficient
+    Mv[k] = fma(au, r[R::MD2], r[R::MDUP + k]) * (1.0 + 8.0 * kU);
+    vr[k][P] += 2.0 * kU * Mv[k];
+    double sl = 0.0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) sl += fabs(vm[k][j] - vr[k][j]);
+    vlo[k] = ((vm[k][P] - vr[k][P]) - sl) - KC * Mv[k];
   }
 
-  // q_n = Mul(v_0, B_0n) + Mul(v_1, B_1n), McCormick with x = v (left operand):
-  //   lower ylo*v_sel + vlo*B_sel - vlo*ylo, upper yhi*v_sel' + vlo*B_sel' - vlo*yhi
-  // at most 6 roundings, each bounded by the magnitude sum Tq
-  const double Tq = fma((double)sc[R::BMAX0], Mv[0],
-                        fma(fabs(vlo[0]), (double)sc[R::MBB0],
-                            fma((double)sc[R::BMAX1], Mv[1], fabs(vlo[1]) * (double)sc[R::MBB1])));
-  const double eq = 8.0 * kU * Tq;
+  // q_n = sum_k Mul(v_k, B_kn), McCormick with x = v, y = B_kn in [ylo, yhi]:
+  //   lower ylo v + vlo B - vlo ylo,  upper yhi v + vlo B - vlo yhi;  in mid-radius form
+  //   qm = c1 vm + c2 vr + vlo Bm - vlo c1,   qr = c3 vm + c4 vr + |vlo| Br - vlo c3
+  // with c1 = (ylo+yhi)/2, c2 = (|yhi|-|ylo|)/2, c3 = (yhi-ylo)/2, c4 = (|ylo|+|yhi|)/2.
+  // The summed term magnitude over all coefficients is at most Tq; six roundings per
+  // coefficient plus the rounding of the weights stay below 8 kU Tq.
+  const double Tq = fma(2.0 * r[R::BMAX + 0], Mv[0],
+                        fma(fabs(vlo[0]), r[R::MBB + 0],
+                            fma(2.0 * r[R::BMAX + 1], Mv[1], fabs(vlo[1]) * r[R::MBB + 1])));
+  const double eq = 8.0 * kU * Tq * (1.0 + 8.0 * kU);
 #pragma unroll
   for (int j = 0; j < F; ++j) { o.sl[j] = 0.0; o.sh[j] = 0.0; }
   double es = 0.0;
 #pragma unroll
   for (int n = 0; n < 3; ++n) {
-    double ql[F], qh[F];
+    double qm[F], qr[F];
 #pragma unroll
-    for (int j = 0; j < F; ++j) { ql[j] = 0.0; qh[j] = 0.0; }
+    for (int j = 0; j < F; ++j) { qm[j] = 0.0; qr[j] = 0.0; }
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int e = 3 * k + n;
-      const float *bl = r + R::B + 2 * F * e;
-      const float *bh = bl + F;
-      const double ylo = (double)r[R::BI + e], yhi = (double)r[R::BI + 6 + e];
-      const bool yl_pos = ylo >= 0.0, yh_pos = yhi >= 0.0, vpos = vlo[k] >= 0.0;
+      const double *bm = r + R::BM + F * e;
+      const double *br = r + R::BR + F * e;
+      const double *cw = r + R::CM + 4 * e;
+      const double a = vlo[k], aa = fabs(vlo[k]);
 #pragma unroll
       for (int j = 0; j < F; ++j) {
-        const double bsl = vpos ? (double)bl[j] : (double)bh[j];
-        const double bsh = vpos ? (double)bh[j] : (double)bl[j];
-        ql[j] = fma(ylo, yl_pos ? vl[k][j] : vh[k][j], fma(vlo[k], bsl, ql[j]));
-        qh[j] = fma(yhi, yh_pos ? vh[k][j] : vl[k][j], fma(vlo[k], bsh, qh[j]));
+        qm[j] = fma(cw[0], vm[k][j], fma(cw[1], vr[k][j], fma(a, bm[j], qm[j])));
+        qr[j] = fma(cw[2], vm[k][j], fma(cw[3], vr[k][j], fma(aa, br[j], qr[j])));
       }
-      ql[P] = fma(-vlo[k], ylo, ql[P]);
-      qh[P] = fma(-vlo[k], yhi, qh[P]);
+      qm[P] = fma(-a, cw[0], qm[P]);
+      qr[P] = fma(-a, cw[2], qr[P]);
     }
-    ql[P] -= eq;
-    qh[P] += eq;
-    const double Sl = abs_sum<P>(ql), Sh = abs_sum<P>(qh);
-    const double Mlq = fabs(ql[P]) + Sl, Mhq = fabs(qh[P]) + Sh;
-    const double qlo = (ql[P] - Sl) - KC * Mlq;
-    const double qhi = (qh[P] + Sh) + KC * Mhq;
-    const double Mq = fmax(Mlq, Mhq);
+    qr[P] += eq;
+    // interval of q_n: lower form qm - qr, upper form qm + qr
+    double Sl = 0.0, Sh = 0.0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      Sl += fabs(qm[j] - qr[j]);
+      Sh += fabs(qm[j] + qr[j]);
+    }
+    const double qlc = qm[P] - qr[P], qhc = qm[P] + qr[P];
+    const double Ml = fabs(qlc) + Sl, Mh = fabs(qhc) + Sh;
+    const double wq = KC * (Ml + Mh);
+    const double qlo = (qlc - Sl) - wq;
+    const double qhi = (qhc + Sh) + wq;
+    const double Mq = fmax(Ml, Mh) * (1.0 + 8.0 * kU);
     // Sqr: tangent at xs = clamp(0, qlo, qhi) below, chord (qlo + qhi) q - qlo qhi above
+    //   lower  t qm - |t| qr - xs^2  (t = 2 xs),   upper  m qm + |m| qr - qlo qhi  (m = qlo + qhi)
     const double xs = fmin(fmax(qlo, 0.0), qhi);
-    const double t = xs + xs;
-    const double m = qlo + qhi;
-    const bool tpos = t >= 0.0, mpos = m >= 0.0;
+    const double t = xs + xs, at = fabs(t);
+    const double m = qlo + qhi, am = fabs(m);
 #pragma unroll
     for (int j = 0; j < F; ++j) {
-      o.sl[j] = fma(t, tpos ? ql[j] : qh[j], o.sl[j]);
-      o.sh[j] = fma(m, mpos ? qh[j] : ql[j], o.sh[j]);
+      o.sl[j] = fma(t, qm[j], fma(-at, qr[j], o.sl[j]));
+      o.sh[j] = fma(m, qm[j], fma(am, qr[j], o.sh[j]));
     }
     o.sl[P] = fma(-xs, xs, o.sl[P]);
     o.sh[P] = fma(-qlo, qhi, o.sh[P]);
     es = fma(Mq, Mq, es);
   }
-  // each term of the three Sqr forms is at most 3 Mq^2 in magnitude; at most 9 roundings
-  const double ees = 40.0 * kU * es;
+  // per n the Sqr terms sum to at most 10 Mq^2 over all coefficients; seven roundings each
+  const double ees = 80.0 * kU * es;
   o.sl[P] -= ees;
   o.sh[P] += ees;
-  const double Ssl = abs_sum<P>(o.sl), Ssh = abs_sum<P>(o.sh);
+  double Ssl = 0.0, Ssh = 0.0;
+#pragma unroll
+  for (int j = 0; j < P; ++j) { Ssl += fabs(o.sl[j]); Ssh += fabs(o.sh[j]); }
   o.msl = fabs(o.sl[P]) + Ssl;
   o.msh = fabs(o.sh[P]) + Ssh;
   o.slo = (o.sl[P] - Ssl) - KC * o.msl;
@@ -151,15 +147,16 @@ __device__ __forceinline__ void exp_bounds(double slo, double shi, double o, Exp
   b.xlo = -0.5 * shi;
   b.xhi = -0.5 * fmax(slo, 0.0);
   const double el = exp(b.xlo);
-  const double eh = exp(b.xhi);
   b.e_dn = el * (1.0 - 4.0 * kU);
   b.e_up = el * (1.0 + 4.0 * kU);
-  const double eh_up = eh * (1.0 + 4.0 * kU);
   const double dx = b.xhi - b.xlo;
-  double k;
+  double k, eh_up;
   if (dx < 0.5) {
-    k = dx > 0.0 ? el * (expm1(dx) / dx) : el;
+    const double em = expm1(dx);
+    k = dx > 0.0 ? el * (em / dx) : el;
+    eh_up = (el + el * em) * (1.0 + 8.0 * kU);
   } else {
+    eh_up = exp(b.xhi) * (1.0 + 4.0 * kU);
     k = (eh_up - b.e_dn) / dx;
   }
   b.k_up = k * (1.0 + 16.0 * kU);

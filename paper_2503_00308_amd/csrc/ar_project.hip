@@ -134,78 +134,43 @@ __device__ __forceinline__ uint64_t order_key(double d) {
   return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
 }
 
-// Round a lower (is_lower) or upper form to FP32, moving the constant outward by the
-// coefficient rounding plus 2^-32 of the form's magnitude (covers the FP64 stage).
+// Store a (lower, upper) form pair in mid-radius form m = (l + h) / 2, r = (h - l) / 2.
+// The radius constant absorbs the conversion rounding (at most 2^-53 of the summed
+// magnitudes) and 2^-32 of the forms' magnitude, which covers the rounding of the FP64
+// per-Gaussian stage.
 template <int P>
-__device__ __forceinline__ void store_f32(float *dst, const double *f, bool is_lower) {
-  double err = 0.0;
+__device__ __forceinline__ void store_mr(double *m, double *r, const L64<P> &x) {
+  double mag = 0.0;
 #pragma unroll
-  for (int k = 0; k < P; ++k) {
-    const float g = (float)f[k];
-    dst[k] = g;
-    err += fabs((double)g - f[k]);
+  for (int j = 0; j <= P; ++j) {
+    m[j] = 0.5 * (x.lo[j] + x.up[j]);
+    r[j] = 0.5 * (x.up[j] - x.lo[j]);
+    mag += fabs(x.lo[j]) + fabs(x.up[j]);
   }
-  const double widen = err + 0x1p-32 * l_mag<P>(f);
-  dst[P] = is_lower ? __double2float_rd(f[P] - widen) : __double2float_ru(f[P] + widen);
+  r[P] += (0x1p-32 + 0x1p-50) * mag;
 }
 
+// sum_j |m_j| + |r_j| (>= the magnitude of both forms), rounded up
 template <int P>
-__device__ __forceinline__ double mag_f32(const float *f) {
-  double s = fabs((double)f[P]);
+__device__ __forceinline__ double mag_mr(const double *m, const double *r) {
+  double s = 0.0;
 #pragma unroll
-  for (int k = 0; k < P; ++k) s += fabs((double)f[k]);
-  return s;
+  for (int j = 0; j <= P; ++j) s += fabs(m[j]) + fabs(r[j]);
+  return s * (1.0 + 0x1p-40);
 }
 
+// interval of a mid-radius form pair over the box, outward
 template <int P>
-__device__ __forceinline__ void bounds_f32(const float *flo, const float *fhi, double &lo, double &hi) {
+__device__ __forceinline__ void bounds_mr(const double *m, const double *r, double &lo, double &hi) {
   double sl = 0.0, sh = 0.0;
 #pragma unroll
-  for (int k = 0; k < P; ++k) { sl += fabs((double)flo[k]); sh += fabs((double)fhi[k]); }
-  lo = (double)flo[P] - sl;
-  hi = (double)fhi[P] + sh;
-}
-
-template <int P>
-__device__ __forceinline__ void store_lf(float *dst, const L64<P> &x) {
-  store_f32<P>(dst, x.lo, true);
-  store_f32<P>(dst + P + 1, x.up, false);
-}
-
-// Round a form to a two-float sum hi + lo (hi = nearest float, lo = nearest float of the
-// rest); the constant's lo part is rounded outward and moved by the representation
-// error of the coefficients plus 2^-32 of the form's magnitude.
-template <int P>
-__device__ __forceinline__ void store_f32x2(float *hi, float *lo, const double *f, bool is_lower) {
-  double err = 0.0;
-#pragma unroll
-  for (int k = 0; k < P; ++k) {
-    const float h = (float)f[k];
-    const float l = (float)(f[k] - (double)h);
-    hi[k] = h;
-    lo[k] = l;
-    err += fabs(f[k] - (double)h - (double)l);
+  for (int j = 0; j < P; ++j) {
+    sl += fabs(m[j] - r[j]);
+    sh += fabs(m[j] + r[j]);
   }
-  const double widen = err + 0x1p-32 * l_mag<P>(f);
-  const float h = (float)f[P];
-  hi[P] = h;
-  lo[P] = is_lower ? __double2float_rd((f[P] - (double)h) - widen) : __double2float_ru((f[P] - (double)h) + widen);
-}
-
-// layout: lower hi, lower lo, upper hi, upper lo (F floats each)
-template <int P>
-__device__ __forceinline__ void store_lf2(float *dst, const L64<P> &x) {
-  constexpr int F = P + 1;
-  store_f32x2<P>(dst, dst + F, x.lo, true);
-  store_f32x2<P>(dst + 2 * F, dst + 3 * F, x.up, false);
-}
-
-template <int P>
-__device__ __forceinline__ double mag_f32x2(const float *h, const float *l) {
-  double s = fabs((double)h[P] + (double)l[P]);
-#pragma unroll
-  for (int k = 0; k < P; ++k) s += fabs((double)h[k] + (double)l[k]);
-  return s;
+  const double w = 0x1p-40 * mag_mr<P>(m, r);
+  lo = ((m[P] - r[P]) - sl) - w;
+  hi = ((m[P] + r[P]) + sh) + w;
 }
 
 // MatrixInv(X; X0, k) for the symmetric 2x2 set X = [[x00, x01], [x01, x11]] (Sec. 3.1):
@@ -273,15 +238,13 @@ __device__ bool matrix_inv(const L64<P> &x00, const L64<P> &x01, const L64<P> &x
 
 template <int P>
 __global__ __launch_bounds__(64) void k_project(SceneDev sc, const PoseForms *__restrict__ pose, Params prm,
-                                                float *__restrict__ rec_out, uint64_t *__restrict__ key_out,
+                                                double *__restrict__ rec_out, uint64_t *__restrict__ key_out,
                                                 uint64_t *__restrict__ key_sort, uint32_t *__restrict__ perm_out, int32_t *__restrict__ rect_out,
                                                 double *__restrict__ dform_out, double *__restrict__ dint_out,
                                                 unsigned long long *__restrict__ counters) {
-  using R = Rec<P>;
   const int n = sc.n;
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
-  float *rec = rec_out + (size_t)g * R::STRIDE;
   const double uw[3] = {sc.mean[g], sc.mean[n + g], sc.mean[2 * n + g]};
   double Mw[9];
 #pragma unroll
@@ -385,58 +348,55 @@ __global__ __launch_bounds__(64) void k_project(SceneDev sc, const PoseForms *__
   dint_out[2 * (size_t)g + 1] = dhi;
 
   // record
-  store_lf2<P>(rec + R::D2, D2);
-  store_lf2<P>(rec + R::DUP, DUP0);
-  store_lf2<P>(rec + R::DUP + 4 * R::F, DUP1);
-  float *sc_ = rec + R::SC;
-  for (int e = 0; e < 6; ++e) {
-    float *dst = rec + R::B + 2 * R::F * e;
-    if (type == kNormal) {
-      const int k = e / 3, nn = e % 3;
-      const L64<P> &mp0 = Mp0[nn], &mp1 = Mp1[nn];
-      L64<P> b = l_add<P>(l_mul<P>(conic[k * 2 + 0], mp0), l_mul<P>(conic[k * 2 + 1], mp1));
-      store_lf<P>(dst, b);
-    } else {
-      for (int j = 0; j < 2 * R::F; ++j) dst[j] = 0.0f;
-    }
-  }
+  using R = Rec<P>;
+  constexpr int F = R::F;
+  double *rec = rec_out + (size_t)g * R::STRIDE;
+  store_mr<P>(rec + R::DM, rec + R::DR, D2);
+  store_mr<P>(rec + R::PM, rec + R::PR, DUP0);
+  store_mr<P>(rec + R::PM + F, rec + R::PR + F, DUP1);
   double bmax[2] = {0.0, 0.0}, mb[2] = {0.0, 0.0};
   for (int e = 0; e < 6; ++e) {
-    const float *bl = rec + R::B + 2 * R::F * e;
-    const float *bh = bl + R::F;
-    double lo, hi;
-    bounds_f32<P>(bl, bh, lo, hi);
-    rec[R::BI + e] = __double2float_rd(lo);
-    rec[R::BI + 6 + e] = __double2float_ru(hi);
-    const int k = e / 3;
-    bmax[k] = fmax(bmax[k], fmax(fabs((double)rec[R::BI + e]), fabs((double)rec[R::BI + 6 + e])));
-    mb[k] = fmax(mb[k], fmax(mag_f32<P>(bl), mag_f32<P>(bh)));
+    double *bm = rec + R::BM + F * e, *br = rec + R::BR + F * e, *cm = rec + R::CM + 4 * e;
+    if (type == kNormal) {
+      const int k = e / 3, nn = e % 3;
+      const L64<P> b = l_add<P>(l_mul<P>(conic[k * 2 + 0], Mp0[nn]), l_mul<P>(conic[k * 2 + 1], Mp1[nn]));
+      store_mr<P>(bm, br, b);
+      double ylo, yhi;
+      bounds_mr<P>(bm, br, ylo, yhi);
+      // McCormick weights: c1 = (ylo + yhi)/2, c2 = (|yhi| - |ylo|)/2, c3 = (yhi - ylo)/2, c4 = (|ylo| + |yhi|)/2
+      cm[0] = 0.5 * (ylo + yhi);
+      cm[1] = 0.5 * (fabs(yhi) - fabs(ylo));
+      cm[2] = 0.5 * (yhi - ylo);
+      cm[3] = 0.5 * (fabs(ylo) + fabs(yhi));
+      bmax[k] = fmax(bmax[k], fmax(fabs(ylo), fabs(yhi)));
+      mb[k] = fmax(mb[k], mag_mr<P>(bm, br));
+    } else {
+      for (int j = 0; j < F; ++j) { bm[j] = 0.0; br[j] = 0.0; }
+      for (int j = 0; j < 4; ++j) cm[j] = 0.0;
+    }
   }
   const double slack = 1.0 + 0x1p-30;
-  constexpr int F = R::F;
-  sc_[R::MD2] = __double2float_ru(
-      slack * fmax(mag_f32x2<P>(rec + R::D2, rec + R::D2 + F), mag_f32x2<P>(rec + R::D2 + 2 * F, rec + R::D2 + 3 * F)));
+  rec[R::MD2] = mag_mr<P>(rec + R::DM, rec + R::DR);
   for (int k = 0; k < 2; ++k) {
-    const float *b = rec + R::DUP + 4 * F * k;
-    sc_[R::MDUP0 + k] = __double2float_ru(slack * fmax(mag_f32x2<P>(b, b + F), mag_f32x2<P>(b + 2 * F, b + 3 * F)));
+    rec[R::MDUP + k] = mag_mr<P>(rec + R::PM + F * k, rec + R::PR + F * k);
+    rec[R::MBB + k] = slack * (mb[k] + 2.0 * bmax[k]);
+    rec[R::BMAX + k] = slack * bmax[k];
   }
-  sc_[R::MBB0] = __double2float_ru(slack * (mb[0] + bmax[0]));
-  sc_[R::MBB1] = __double2float_ru(slack * (mb[1] + bmax[1]));
-  sc_[R::BMAX0] = __double2float_ru(bmax[0]);
-  sc_[R::BMAX1] = __double2float_ru(bmax[1]);
-  sc_[R::O] = o;
-  sc_[R::C0] = sc.rgb[g];
-  sc_[R::C1] = sc.rgb[n + g];
-  sc_[R::C2] = sc.rgb[2 * n + g];
+  rec[R::O] = (double)o;
+  rec[R::C + 0] = (double)sc.rgb[g];
+  rec[R::C + 1] = (double)sc.rgb[n + g];
+  rec[R::C + 2] = (double)sc.rgb[2 * n + g];
   const bool geo = (type == kNormal || type == kFallback);
-  sc_[R::MU0LO] = geo ? __double2float_rd(m0lo) : 0.0f;
-  sc_[R::MU0HI] = geo ? __double2float_ru(m0hi) : 0.0f;
-  sc_[R::MU1LO] = geo ? __double2float_rd(m1lo) : 0.0f;
-  sc_[R::MU1HI] = geo ? __double2float_ru(m1hi) : 0.0f;
-  sc_[R::R2] = geo ? __double2float_ru(r2) : -1.0f;
-  sc_[R::LAM] = geo ? __double2float_ru(lam) : 0.0f;
-  sc_[R::TYPE] = __int_as_float(type);
-  for (int j = R::SC + R::TYPE + 1; j < R::STRIDE; ++j) rec[j] = 0.0f;
+  rec[R::LAM] = geo ? lam * (1.0 + 0x1p-40) : 0.0;
+  float *pf = reinterpret_cast<float *>(rec + R::PRUNE);
+  pf[0] = geo ? __double2float_rd(m0lo) : 0.0f;
+  pf[1] = geo ? __double2float_ru(m0hi) : 0.0f;
+  pf[2] = geo ? __double2float_rd(m1lo) : 0.0f;
+  pf[3] = geo ? __double2float_ru(m1hi) : 0.0f;
+  pf[4] = geo ? __double2float_ru(r2) : -1.0f;
+  reinterpret_cast<int32_t *>(pf)[5] = type;
+  rec[15] = 0.0;
+  for (int j = R::CM + 24; j < R::STRIDE; ++j) rec[j] = 0.0;
 
   // tile rectangle (inclusive) for binning; empty when the Gaussian cannot contribute
   int32_t *rc = rect_out + 4 * (size_t)g;

@@ -15,14 +15,16 @@
 //     lo: sum_i c_i T_lo[i] a_i^lower(e),   hi: sum_i c_i T_hi[i] a_i^upper(e)
 // plus the interval upper sum sum_i c_i T_hi[i] a_hi[i].
 //
-// Work decomposition: one workgroup per tile, one lane per pixel, G waves.  The tile's
-// depth-ordered list is cut into chunks of C Gaussians (cuts moved to the next depth
-// change so ties never straddle a cut); in each round wave g takes chunk g of the
-// round and accumulates with a local transmittance starting at 1.  At the round's end
-// the waves exchange their chunk transmittance products through LDS and scale their
-// local sums by the product of everything in front.  Once every pixel's upper
-// transmittance is below t_min the tile stops; the remaining Gaussians can add at
-// most that transmittance, which is added to the upper bound.
+// Work decomposition: each tile's depth-ordered list is cut into segments of L list
+// positions (cuts moved to the next depth change so ties never straddle a cut); one
+// wave per segment, one lane per pixel, accumulates with transmittances starting at 1
+// and writes its partial sums and transmittance products.  A merge kernel combines a
+// tile's segments front to back (the blend of a concatenation is the blend of the
+// front part plus its transmittance times the blend of the back part).  Equal-length
+// segments keep every wave's work the same whatever the tile's list length.  Once every
+// pixel's upper transmittance inside a segment is below t_min the segment stops; the
+// remaining Gaussians of the tile can add at most that transmittance (scaled by the one
+// in front), which the merge adds to the upper bound.
 #include <hip/hip_runtime.h>
 
 #include "ar_internal.h"
@@ -51,7 +53,7 @@ __device__ __forceinline__ float tile_dist2(const float *mu, int tx, int ty, con
 }
 
 template <int P, bool EMIT>
-__global__ __launch_bounds__(256) void k_bin(const float *__restrict__ recs, const int32_t *__restrict__ rect,
+__global__ __launch_bounds__(256) void k_bin(const double *__restrict__ recs, const int32_t *__restrict__ rect,
                                              const uint32_t *__restrict__ perm, int n, Params prm,
                                              uint32_t *__restrict__ counts, uint32_t *__restrict__ pkey,
                                              uint32_t *__restrict__ pval) {
@@ -59,14 +61,14 @@ __global__ __launch_bounds__(256) void k_bin(const float *__restrict__ recs, con
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   const uint32_t gid = perm[r];
-  const float *rec = recs + (size_t)gid * R::STRIDE;
-  const int type = __float_as_int(rec[R::SC + R::TYPE]);
+  const double *rec = recs + (size_t)gid * R::STRIDE;
+  const int type = rec_type<P>(rec);
   const int32_t *rc = rect + 4 * (size_t)gid;
   uint32_t c = 0;
   uint32_t off = EMIT ? counts[r] : 0u;
   if (type != kDropped && rc[0] <= rc[2] && rc[1] <= rc[3]) {
-    const float *mu = rec + R::SC + R::MU0LO;
-    const float r2 = rec[R::SC + R::R2];
+    const float *mu = rec_prune<P>(rec);
+    const float r2 = mu[4];
     for (int ty = rc[1]; ty <= rc[3]; ++ty)
       for (int tx = rc[0]; tx <= rc[2]; ++tx) {
         const bool keep = (type == kWild) || (tile_dist2(mu, tx, ty, prm) <= r2);
@@ -152,21 +154,60 @@ __device__ __forceinline__ int cut_at(const uint32_t *__restrict__ list, const u
   return p;
 }
 
+// Partial result of one segment, NF columns of 64 doubles (one per pixel lane).
 template <int P>
-__global__ __launch_bounds__(512) void k_raster_translation(const float *__restrict__ recs,
-                                                            const uint64_t *__restrict__ keys,
-                                                            const uint32_t *__restrict__ ranges,
-                                                            const uint32_t *__restrict__ lists, Params prm,
-                                                            float *__restrict__ out_lo, float *__restrict__ out_hi,
-                                                            unsigned long long *__restrict__ counters) {
+struct Part {
+  static constexpr int F = P + 1;
+  static constexpr int LO = 0;               // [3][F] lower colour forms
+  static constexpr int HI = 3 * F;           // [3][F] upper colour forms
+  static constexpr int IHI = 6 * F;          // [3] interval upper sums
+  static constexpr int TLO = 6 * F + 3;      // segment transmittance products
+  static constexpr int THI = 6 * F + 4;
+  static constexpr int MAG = 6 * F + 5;      // magnitude sums (two floats)
+  static constexpr int STOP = 6 * F + 6;     // 1 when the segment stopped early
+  static constexpr int CNT = 6 * F + 7;      // evaluated pairs of the wave (same in every lane)
+  static constexpr int NF = 6 * F + 8;
+};
+
+int part_fields(int P) { return 6 * (P + 1) + 8; }
+
+// Segments: tile t's list is cut into ceil(n_t / L) pieces of L positions.
+__global__ void k_seg_count(const uint32_t *__restrict__ ranges, int ntiles, int L, uint32_t *__restrict__ seg_off) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < ntiles) {
+    const uint32_t n = ranges[2 * t + 1] - ranges[2 * t];
+    seg_off[t] = (n + (uint32_t)L - 1u) / (uint32_t)L;
+  } else if (t == ntiles) {
+    seg_off[t] = 0u;
+  }
+}
+
+// seg_off (scanned): first segment of each tile, then the total; seg_tile[s] = tile of s
+__global__ void k_seg_map(const uint32_t *__restrict__ seg_off, int ntiles, uint32_t *__restrict__ seg_tile) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  for (uint32_t s = seg_off[t]; s < seg_off[t + 1]; ++s) seg_tile[s] = (uint32_t)t;
+}
+
+// One wave per segment, one lane per pixel of the segment's 8x8 tile.  The segment's
+// cut points are moved to the next depth change, so a group of equal depths is never
+// split.  Transmittances start at 1; the merge scales by the product in front.
+template <int P>
+__global__ __launch_bounds__(256) void k_raster_seg(const double *__restrict__ recs, const uint64_t *__restrict__ keys,
+                                                    const uint32_t *__restrict__ ranges,
+                                                    const uint32_t *__restrict__ lists,
+                                                    const uint32_t *__restrict__ seg_off,
+                                                    const uint32_t *__restrict__ seg_tile, int L, Params prm,
+                                                    double *__restrict__ part) {
   using R = Rec<P>;
-  extern __shared__ double smem[];
-  const int G = prm.groups, C = prm.chunk;
-  double *tch = smem;                                   // [2][G][64][2]
-  double *red = smem + 2 * G * 64 * 2;                  // [64][6(P+1)+4] final reduction
+  using Q = Part<P>;
+  constexpr int F = P + 1;
   const int lane = threadIdx.x & 63;
-  const int g = threadIdx.x >> 6;
-  const int tile = blockIdx.x;
+  const int ntiles = prm.ntx * prm.nty;
+  const int s = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+  if (s >= (int)seg_off[ntiles]) return;
+  const int tile = (int)seg_tile[s];
+  const int i = s - (int)seg_off[tile];
   const int tx = tile % prm.ntx, ty = tile / prm.ntx;
   const int col = tx * kTile + (lane & 7), row = ty * kTile + (lane >> 3);
   const bool inimg = col < prm.width && row < prm.height;
@@ -175,90 +216,149 @@ __global__ __launch_bounds__(512) void k_raster_translation(const float *__restr
   const int beg = (int)ranges[2 * tile];
   const int n = (int)ranges[2 * tile + 1] - beg;
   const uint32_t *list = lists + beg;
+  const int p0 = cut_at(list, keys, n, i * L);
+  const int p1 = cut_at(list, keys, n, (i + 1) * L);
 
   Acc<P> acc;
   acc_zero<P>(acc);
-  double tt_lo = 1.0, tt_hi = 1.0;   // transmittance of everything processed so far
-  bool early = false;
-  unsigned long long npairs = 0;
-  int parity = 0;
-  for (int base = 0; base < n; base += G * C) {
-    const int p0 = cut_at(list, keys, n, base + g * C);
-    const int p1 = cut_at(list, keys, n, base + (g + 1) * C);
-    Acc<P> loc;
-    acc_zero<P>(loc);
-    double tl_lo = 1.0, tl_hi = 1.0;     // local transmittance (chunk)
-    double tg_lo = 1.0, tg_hi = 1.0;     // local transmittance at the current depth value
-    uint64_t prev_key = ~0ull;
-    for (int p = p0; p < p1; ++p) {
-      const uint32_t gid = list[p];
-      const float *rec = recs + (size_t)gid * R::STRIDE;
-      const uint64_t key = keys[gid];
-      if (key != prev_key) {
-        tg_lo = tl_lo;
-        tg_hi = tl_hi;
-        prev_key = key;
-      }
-      const int type = __float_as_int(rec[R::SC + R::TYPE]);
-      const bool kept = inimg && pair_kept<P>(rec, type, ux, uy);
-      if (kept) {
-        double alo, ahi;
-        pair_contrib<P>(rec, type, uxd, uyd, tg_lo, tg_hi, loc, alo, ahi);
-        tl_lo *= 1.0 - ahi;
-        tl_hi *= 1.0 - alo;
-        ++npairs;
-      }
-    }
-    // exchange chunk transmittances, scale the local sums by the product in front
-    double *tp = tch + parity * G * 128;
-    tp[(g * 64 + lane) * 2 + 0] = tl_lo;
-    tp[(g * 64 + lane) * 2 + 1] = tl_hi;
-    __syncthreads();
-    double pre_lo = tt_lo, pre_hi = tt_hi;
-    for (int w = 0; w < G; ++w) {
-      const double a = tp[(w * 64 + lane) * 2 + 0], b = tp[(w * 64 + lane) * 2 + 1];
-      if (w == g) { pre_lo = tt_lo; pre_hi = tt_hi; acc_fma<P>(acc, loc, pre_lo, pre_hi); }
-      tt_lo *= a;
-      tt_hi *= b;
-    }
-    parity ^= 1;
-    if (prm.t_min > 0.0) {
-      const bool done = !inimg || tt_hi < prm.t_min;
-      if (__all(done)) {
-        early = cut_at(list, keys, n, base + G * C) < n;
+  double tl_lo = 1.0, tl_hi = 1.0;   // transmittance of the segment so far
+  double tg_lo = 1.0, tg_hi = 1.0;   // ... in front of the current depth value
+  uint64_t prev_key = ~0ull;
+  bool stop = false;
+  unsigned npairs = 0;
+  for (int p = p0; p < p1; ++p) {
+    const uint32_t gid = list[p];
+    const double *rec = recs + (size_t)gid * R::STRIDE;
+    const uint64_t key = keys[gid];
+    if (key != prev_key) {
+      // everything from here on lies behind the processed Gaussians
+      if (prm.t_min > 0.0 && __all(!inimg || tl_hi < prm.t_min)) {
+        stop = true;
         break;
       }
+      tg_lo = tl_lo;
+      tg_hi = tl_hi;
+      prev_key = key;
+    }
+    const int type = rec_type<P>(rec);
+    if (inimg && pair_kept<P>(rec, type, ux, uy)) {
+      double alo, ahi;
+      pair_contrib<P>(rec, type, uxd, uyd, tg_lo, tg_hi, acc, alo, ahi);
+      tl_lo *= 1.0 - ahi;
+      tl_hi *= 1.0 - alo;
+      ++npairs;
     }
   }
-
-  acc_reduce<P>(acc, red, G, g, lane);
-  // pair count
-  unsigned long long cnt = npairs;
+  unsigned cnt = npairs;
   for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+
+  double *q = part + (size_t)s * Q::NF * 64 + lane;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int j = 0; j < F; ++j) {
+      q[(Q::LO + c * F + j) * 64] = acc.lo[c][j];
+      q[(Q::HI + c * F + j) * 64] = acc.hi[c][j];
+    }
+    q[(Q::IHI + c) * 64] = acc.ihi[c];
+  }
+  q[Q::TLO * 64] = tl_lo;
+  q[Q::THI * 64] = tl_hi;
+  float2 mg;
+  mg.x = acc.magl;
+  mg.y = acc.magh;
+  q[Q::MAG * 64] = __builtin_bit_cast(double, mg);
+  q[Q::STOP * 64] = stop ? 1.0 : 0.0;
+  q[Q::CNT * 64] = (double)cnt;
+}
+
+// One wave per tile: combine the tile's segments front to back,
+//   acc += T * acc_s,  T *= T_s  (lower with T_lo, upper with T_hi),
+// and write the pixel bounds.  A segment that stopped early ends the tile: everything
+// behind its stop point adds at most T_hi (in front) * T_hi (segment at the stop).
+template <int P>
+__global__ __launch_bounds__(256) void k_merge(const uint32_t *__restrict__ ranges,
+                                               const uint32_t *__restrict__ seg_off,
+                                               const double *__restrict__ part, Params prm,
+                                               float *__restrict__ out_lo, float *__restrict__ out_hi,
+                                               unsigned long long *__restrict__ counters) {
+  using Q = Part<P>;
+  constexpr int F = P + 1;
+  const int lane = threadIdx.x & 63;
+  const int ntiles = prm.ntx * prm.nty;
+  const int tile = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+  if (tile >= ntiles) return;
+  const int tx = tile % prm.ntx, ty = tile / prm.ntx;
+  const int col = tx * kTile + (lane & 7), row = ty * kTile + (lane >> 3);
+  const bool inimg = col < prm.width && row < prm.height;
+  const int s0 = (int)seg_off[tile], s1 = (int)seg_off[tile + 1];
+  Acc<P> acc, src;
+  acc_zero<P>(acc);
+  double T_lo = 1.0, T_hi = 1.0, extra = 0.0;
+  unsigned long long cnt = 0;
+  for (int s = s0; s < s1; ++s) {
+    const double *q = part + (size_t)s * Q::NF * 64 + lane;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int j = 0; j < F; ++j) {
+        src.lo[c][j] = q[(Q::LO + c * F + j) * 64];
+        src.hi[c][j] = q[(Q::HI + c * F + j) * 64];
+      }
+      src.ihi[c] = q[(Q::IHI + c) * 64];
+    }
+    const float2 mg = __builtin_bit_cast(float2, q[Q::MAG * 64]);
+    src.magl = mg.x;
+    src.magh = mg.y;
+    acc_fma<P>(acc, src, T_lo, T_hi);
+    cnt += (unsigned long long)q[Q::CNT * 64];
+    const double t_lo = q[Q::TLO * 64], t_hi = q[Q::THI * 64];
+    if (q[Q::STOP * 64] != 0.0) {
+      extra = T_hi * t_hi * (1.0 + 0x1p-50);
+      break;
+    }
+    T_lo *= t_lo;
+    T_hi *= t_hi;
+  }
   if (lane == 0 && cnt) atomicAdd(&counters[0], cnt);
-  if (g != 0 || !inimg) return;
-  write_pixel<P>(acc, (double)n, prm.E, early ? tt_hi : 0.0, out_lo, out_hi, ((size_t)row * prm.width + col) * 3);
+  if (!inimg) return;
+  const int n = (int)(ranges[2 * tile + 1] - ranges[2 * tile]);
+  write_pixel<P>(acc, (double)(n + 2 * (s1 - s0)), prm.E, extra, out_lo, out_hi,
+                 ((size_t)row * prm.width + col) * 3);
 }
 
 template <int P>
-static hipError_t launch_trans_p(const Workspace &ws, const uint32_t *lists, const Params &prm, float *lo, float *hi,
-                                 hipStream_t s) {
+static hipError_t launch_trans_p(const Workspace &ws, const uint32_t *lists, const Params &prm, int L, int nseg_max,
+                                 float *lo, float *hi, hipStream_t s) {
   const int ntiles = prm.ntx * prm.nty;
-  const int G = prm.groups;
-  constexpr int kRed = 6 * (P + 1) + 3 + 1;
-  const size_t shm = sizeof(double) * (2 * G * 64 * 2 + 64 * kRed);
-  hipLaunchKernelGGL(k_raster_translation<P>, dim3(ntiles), dim3(64 * G), shm, s, ws.rec, ws.key, ws.tile_range,
-                     lists, prm, lo, hi, ws.counters);
+  HIP_RET(hipEventRecord(ws.ev[1], s));
+  if (nseg_max > 0)
+    hipLaunchKernelGGL(k_raster_seg<P>, dim3((nseg_max + 3) / 4), dim3(256), 0, s, ws.rec, ws.key, ws.tile_range,
+                       lists, ws.seg_off, ws.seg_tile, L, prm, ws.part);
+  HIP_RET(hipEventRecord(ws.ev[2], s));
+  hipLaunchKernelGGL(k_merge<P>, dim3((ntiles + 3) / 4), dim3(256), 0, s, ws.tile_range, ws.seg_off, ws.part, prm,
+                     lo, hi, ws.counters);
   return hipGetLastError();
 }
 
-hipError_t launch_raster_translation(int P, const Workspace &ws, const uint32_t *lists, const SceneDev &,
-                                     const Params &prm, float *lo, float *hi, hipStream_t s) {
+hipError_t launch_segments(const Workspace &ws, int ntiles, int L, hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_count, dim3((ntiles + 1 + 255) / 256), dim3(256), 0, s, ws.tile_range, ntiles, L,
+                     ws.seg_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_segment_map(const Workspace &ws, int ntiles, hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_map, dim3((ntiles + 255) / 256), dim3(256), 0, s, ws.seg_off, ntiles, ws.seg_tile);
+  return hipGetLastError();
+}
+
+hipError_t launch_raster_translation(int P, const Workspace &ws, const uint32_t *lists, const Params &prm, int L,
+                                     int nseg_max, float *lo, float *hi, hipStream_t s) {
   switch (P) {
-    case 0: return launch_trans_p<0>(ws, lists, prm, lo, hi, s);
-    case 1: return launch_trans_p<1>(ws, lists, prm, lo, hi, s);
-    case 2: return launch_trans_p<2>(ws, lists, prm, lo, hi, s);
-    case 3: return launch_trans_p<3>(ws, lists, prm, lo, hi, s);
+    case 0: return launch_trans_p<0>(ws, lists, prm, L, nseg_max, lo, hi, s);
+    case 1: return launch_trans_p<1>(ws, lists, prm, L, nseg_max, lo, hi, s);
+    case 2: return launch_trans_p<2>(ws, lists, prm, L, nseg_max, lo, hi, s);
+    case 3: return launch_trans_p<3>(ws, lists, prm, L, nseg_max, lo, hi, s);
   }
   return hipErrorInvalidValue;
 }
