@@ -48,86 +48,119 @@ __device__ __forceinline__ void acc_fma(Acc<P> &dst, const Acc<P> &src, double p
 
 // Alpha interval of a MatrixInv fallback (footprint bound) or a near-plane straddler.
 template <int P>
-__device__ __forceinline__ double alpha_hi_special(const double *__restrict__ rec, int type, double ux, double uy) {
+__device__ __forceinline__ double alpha_hi_special(const double *__restrict__ rec, int type, double ux, double uy,
+                                                   const double *cf) {
   using R = Rec<P>;
   const double o = rec[R::O];
   if (type != kFallback) return o;
   const double d2 = dist2_box64(rec_prune<P>(rec), ux, uy);
   const double lam = rec[R::LAM];
-  return fmin(o, o * exp(-0.5 * d2 * (1.0 - 8.0 * kU) / lam) * (1.0 + 16.0 * kU));
+  double e_dn, e_up;
+  exp_encl(-0.5 * d2 * (1.0 - 8.0 * kU) / lam, e_dn, e_up, cf);
+  return fmin(o, o * e_up * (1.0 + 4.0 * kU));
+}
+
+// Alpha of one (pixel, Gaussian) pair as linear forms: lower form gl, upper form gh,
+// interval [a_lo, a_hi] and the magnitudes ml >= |gl|, mh >= |gh| + a_hi (for the
+// rounding bound of the sums).  Zero when the pair is not kept.
+template <int P>
+struct PairAlpha {
+  double gl[P + 1], gh[P + 1];
+  double a_lo, a_hi;
+  float ml, mh;
+};
+
+template <int P>
+__device__ __forceinline__ void pair_alpha(const double *__restrict__ rec, int type, bool kept, double ux, double uy,
+                                           PairAlpha<P> &pa, const double *cf) {
+  using R = Rec<P>;
+#pragma unroll
+  for (int j = 0; j <= P; ++j) { pa.gl[j] = 0.0; pa.gh[j] = 0.0; }
+  pa.a_lo = 0.0;
+  pa.a_hi = 0.0;
+  pa.ml = 0.0f;
+  pa.mh = 0.0f;
+  const double o = rec[R::O];
+  if (type == kNormal) {
+    if (kept) {
+      SForms<P> s;
+      s_forms<P>(rec, ux, uy, s);
+      ExpBounds b;
+      exp_bounds(s.slo, s.shi, o, b, cf);
+      // lower alpha form  o e_dn (x_lower(e) - xlo + 1),  x_lower = -s_upper / 2
+      // upper alpha form  o e_up + o k_up (x_upper(e) - xlo),  x_upper = -s_lower / 2
+      const double wl = o * b.e_dn;
+      const double wk = o * b.k_up;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        pa.gl[j] = wl * (-0.5 * s.sh[j]);
+        pa.gh[j] = wk * (-0.5 * s.sl[j]);
+      }
+      pa.gl[P] = wl * ((-0.5 * s.sh[P] - b.xlo) + 1.0);
+      pa.gh[P] = o * b.e_up + wk * (-0.5 * s.sl[P] - b.xlo);
+      pa.ml = (float)(wl * (0.5 * s.msh + fabs(b.xlo) + 1.0));
+      pa.mh = (float)(o * b.e_up + wk * (0.5 * s.msl + fabs(b.xlo)) + b.a_hi);
+      pa.a_lo = b.a_lo;
+      pa.a_hi = b.a_hi;
+    }
+  } else if (kept) {
+    // MatrixInv fallback: [0, footprint bound]; near-plane straddler: [0, o]
+    const double ah = alpha_hi_special<P>(rec, type, ux, uy, cf);
+    pa.gh[P] = ah;
+    pa.a_hi = ah;
+    pa.mh = 2.0f * (float)ah;
+  }
+}
+
+// BlendInd contribution of one pair with the transmittances (tlo, thi) in front:
+// colour forms c T_lo gl, c T_hi gh and the interval sum c T_hi a_hi.
+template <int P>
+__device__ __forceinline__ void acc_pair(Acc<P> &acc, const double *__restrict__ rec, const PairAlpha<P> &pa,
+                                         double tlo, double thi) {
+  using R = Rec<P>;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double cc = rec[R::C + c];
+    const double wlo = cc * tlo, whi = cc * thi;
+#pragma unroll
+    for (int j = 0; j <= P; ++j) {
+      acc.lo[c][j] = fma(wlo, pa.gl[j], acc.lo[c][j]);
+      acc.hi[c][j] = fma(whi, pa.gh[j], acc.hi[c][j]);
+    }
+    acc.ihi[c] = fma(whi, pa.a_hi, acc.ihi[c]);
+  }
+  acc.magl = fmaf((float)tlo, pa.ml, acc.magl) * (1.0f + 4.0f * kU32);
+  acc.magh = fmaf((float)thi, pa.mh, acc.magh) * (1.0f + 4.0f * kU32);
 }
 
 // One (pixel, Gaussian) pair: alpha bounds and its BlendInd contribution with the
 // transmittances (tlo, thi) of the Gaussians in front.  Returns the alpha interval.
 template <int P>
 __device__ __forceinline__ void pair_contrib(const double *__restrict__ rec, int type, double ux, double uy,
-                                             double tlo, double thi, Acc<P> &acc, double &a_lo, double &a_hi) {
-  using R = Rec<P>;
-  const double o = rec[R::O];
-  const double c3[3] = {rec[R::C + 0], rec[R::C + 1], rec[R::C + 2]};
-  if (type == kNormal) {
-    SForms<P> s;
-    s_forms<P>(rec, ux, uy, s);
-    ExpBounds b;
-    exp_bounds(s.slo, s.shi, o, b);
-    // lower alpha form  o e_dn (x_lower(e) - xlo + 1),  x_lower = -s_upper / 2
-    // upper alpha form  o e_up + o k_up (x_upper(e) - xlo),  x_upper = -s_lower / 2
-    const double wl = o * b.e_dn;
-    const double wk = o * b.k_up;
-    double gl[P + 1], gh[P + 1];
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-      gl[j] = wl * (-0.5 * s.sh[j]);
-      gh[j] = wk * (-0.5 * s.sl[j]);
-    }
-    gl[P] = wl * ((-0.5 * s.sh[P] - b.xlo) + 1.0);
-    gh[P] = o * b.e_up + wk * (-0.5 * s.sl[P] - b.xlo);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double wlo = c3[c] * tlo, whi = c3[c] * thi;
-#pragma unroll
-      for (int j = 0; j <= P; ++j) {
-        acc.lo[c][j] = fma(wlo, gl[j], acc.lo[c][j]);
-        acc.hi[c][j] = fma(whi, gh[j], acc.hi[c][j]);
-      }
-      acc.ihi[c] = fma(whi, b.a_hi, acc.ihi[c]);
-    }
-    const float ml = (float)(wl * (0.5 * s.msh + fabs(b.xlo) + 1.0));
-    const float mh = (float)(o * b.e_up + wk * (0.5 * s.msl + fabs(b.xlo)) + b.a_hi);
-    acc.magl = fmaf((float)tlo, ml, acc.magl) * (1.0f + 4.0f * kU32);
-    acc.magh = fmaf((float)thi, mh, acc.magh) * (1.0f + 4.0f * kU32);
-    a_lo = b.a_lo;
-    a_hi = b.a_hi;
-  } else {
-    // MatrixInv fallback: [0, footprint bound]; near-plane straddler: [0, o]
-    const double ah = alpha_hi_special<P>(rec, type, ux, uy);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double whi = c3[c] * thi;
-      acc.hi[c][P] = fma(whi, ah, acc.hi[c][P]);
-      acc.ihi[c] = fma(whi, ah, acc.ihi[c]);
-    }
-    acc.magh = fmaf((float)thi, 2.0f * (float)ah, acc.magh) * (1.0f + 4.0f * kU32);
-    a_lo = 0.0;
-    a_hi = ah;
-  }
+                                             double tlo, double thi, Acc<P> &acc, double &a_lo, double &a_hi,
+                                             const double *cf) {
+  PairAlpha<P> pa;
+  pair_alpha<P>(rec, type, true, ux, uy, pa, cf);
+  acc_pair<P>(acc, rec, pa, tlo, thi);
+  a_lo = pa.a_lo;
+  a_hi = pa.a_hi;
 }
 
 // Alpha interval of one pair without the colour forms (types as in pair_contrib).
 template <int P>
 __device__ __forceinline__ void alpha_interval(const double *__restrict__ rec, int type, double ux, double uy,
-                                               double &a_lo, double &a_hi) {
+                                               double &a_lo, double &a_hi, const double *cf) {
   using R = Rec<P>;
   if (type == kNormal) {
     SForms<P> s;
     s_forms<P>(rec, ux, uy, s);
     ExpBounds b;
-    exp_bounds(s.slo, s.shi, rec[R::O], b);
+    exp_bounds(s.slo, s.shi, rec[R::O], b, cf);
     a_lo = b.a_lo;
     a_hi = b.a_hi;
   } else {
     a_lo = 0.0;
-    a_hi = alpha_hi_special<P>(rec, type, ux, uy);
+    a_hi = alpha_hi_special<P>(rec, type, ux, uy, cf);
   }
 }
 

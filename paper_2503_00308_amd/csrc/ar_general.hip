@@ -215,7 +215,7 @@ __global__ __launch_bounds__(512) void k_raster_general(const double *__restrict
     const bool kept = inimg && pair_kept<P>(rec, type, ux, uy);
     if (kept) {
       double alo, ahi;
-      alpha_interval<P>(rec, type, uxd, uyd, alo, ahi);
+      alpha_interval<P>(rec, type, uxd, uyd, alo, ahi, exp_table(gid));
       Ll += log(1.0 - alo);
       if (ahi >= 1.0) ++Z;
       else Lh += log(1.0 - ahi);
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(512) void k_raster_general(const double *__restrict
     const double thi = exp(sum_l + nn * 0x1p-51 * err_l) * (1.0 + 0x1p-50);
     const double tlo = zc ? 0.0 : exp(sum_h - nn * 0x1p-51 * err_h) * (1.0 - 0x1p-50);
     double alo, ahi;
-    pair_contrib<P>(rec, type, uxd, uyd, tlo, fmin(thi, 1.0), acc, alo, ahi);
+    pair_contrib<P>(rec, type, uxd, uyd, tlo, fmin(thi, 1.0), acc, alo, ahi, exp_table(gid));
     ++npairs;
   }
   acc_reduce<P>(acc, red, G, g, lane);

@@ -17,11 +17,19 @@
 #include <hip/hip_runtime.h>
 
 #include "ar_internal.h"
+#include "ar_expm.h"
 
 namespace ar {
 
 constexpr double kU = 0x1p-53;    // unit roundoff of FP64
 constexpr float kU32 = 0x1p-24f;  // unit roundoff of FP32
+
+// Coefficients of the exp enclosure.  Pixel loops address the table at an offset that
+// is zero at run time but depends on the Gaussian index (gid >> 31, gid < 2^31), so it
+// is read through the scalar cache at every use instead of being kept in registers.
+static __constant__ const double kExpTab[kExpTableLen] = AR_EXP_TABLE;
+
+__device__ __forceinline__ const double *exp_table(uint32_t gid) { return kExpTab + (gid >> 31); }
 
 // s = q q^T bounds at one pixel.
 template <int P>
@@ -45,12 +53,18 @@ __device__ __forceinline__ void s_forms(const double *__restrict__ r, double ux,
   for (int k = 0; k < 2; ++k) {
     const double u = k ? uy : ux;
     const double au = fabs(u);
+    // product and sum rounded separately (both record values are uniform, and one FMA
+    // may read only one of them from a scalar register)
+    {
+#pragma clang fp contract(off)
 #pragma unroll
-    for (int j = 0; j < F; ++j) {
-      vm[k][j] = fma(u, r[R::DM + j], -r[R::PM + F * k + j]);
-      vr[k][j] = fma(au, r[R::DR + j], r[R::PR + F * k + j]);
+      for (int j = 0; j < F; ++j) {
+        vm[k][j] = u * r[R::DM + j] - r[R::PM + F * k + j];
+        vr[k][j] = au * r[R::DR + j] + r[R::PR + F * k + j];
+      }
     }
-    // sum_j |vm_j| + |vr_j| <= |u| MD2 + MDUP_k up to rounding; one rounding per coefficient
+    // sum_j |vm_j| + |vr_j| <= |u| MD2 + MDUP_k up to rounding; two roundings per
+    // coefficient, each at most kU (|u| |dm_j| + |pm_j|) (resp. dr, pr)
     Mv[k] = fma(au, r[R::MD2], r[R::MDUP + k]) * (1.0 + 8.0 * kU);
     vr[k][P] += 2.0 * kU * Mv[k];
     double sl = 0.0;
@@ -143,23 +157,20 @@ struct ExpBounds {
   double a_lo, a_hi;  // alpha interval o * [exp(xlo), exp(xhi)] outward
 };
 
-__device__ __forceinline__ void exp_bounds(double slo, double shi, double o, ExpBounds &b) {
+__device__ __forceinline__ void exp_bounds(double slo, double shi, double o, ExpBounds &b, const double *cf) {
   b.xlo = -0.5 * shi;
   b.xhi = -0.5 * fmax(slo, 0.0);
-  const double el = exp(b.xlo);
-  b.e_dn = el * (1.0 - 4.0 * kU);
-  b.e_up = el * (1.0 + 4.0 * kU);
-  const double dx = b.xhi - b.xlo;
-  double k, eh_up;
-  if (dx < 0.5) {
-    const double em = expm1(dx);
-    k = dx > 0.0 ? el * (em / dx) : el;
-    eh_up = (el + el * em) * (1.0 + 8.0 * kU);
+  double eh_dn, eh_up, phi;
+  const double h = b.xhi - b.xlo;
+  exp_triple(b.xlo, b.xhi, h, b.e_dn, b.e_up, eh_dn, eh_up, phi, cf);
+  double k;
+  if (h <= 0.5) {
+    // e^xlo (e^h - 1) / h; h is within u of the exact width, and the slope grows with h
+    k = b.e_up * phi * (1.0 + 8.0 * kU);
   } else {
-    eh_up = exp(b.xhi) * (1.0 + 4.0 * kU);
-    k = (eh_up - b.e_dn) / dx;
+    k = (eh_up - b.e_dn) / h * (1.0 + 8.0 * kU);
   }
-  b.k_up = k * (1.0 + 16.0 * kU);
+  b.k_up = k;
   b.a_lo = (o * b.e_dn) * (1.0 - 2.0 * kU);
   b.a_hi = fmin(o, (o * eh_up) * (1.0 + 2.0 * kU));
 }

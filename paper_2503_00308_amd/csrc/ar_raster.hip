@@ -241,13 +241,14 @@ __global__ __launch_bounds__(256) void k_raster_seg(const double *__restrict__ r
       prev_key = key;
     }
     const int type = rec_type<P>(rec);
-    if (inimg && pair_kept<P>(rec, type, ux, uy)) {
-      double alo, ahi;
-      pair_contrib<P>(rec, type, uxd, uyd, tg_lo, tg_hi, acc, alo, ahi);
-      tl_lo *= 1.0 - ahi;
-      tl_hi *= 1.0 - alo;
-      ++npairs;
-    }
+    const bool kept = inimg && pair_kept<P>(rec, type, ux, uy);
+    // alpha under the lane mask, accumulation for every lane (zero when not kept)
+    PairAlpha<P> pa;
+    pair_alpha<P>(rec, type, kept, uxd, uyd, pa, exp_table(gid));
+    acc_pair<P>(acc, rec, pa, tg_lo, tg_hi);
+    tl_lo *= 1.0 - pa.a_hi;
+    tl_hi *= 1.0 - pa.a_lo;
+    npairs += kept ? 1u : 0u;
   }
   unsigned cnt = npairs;
   for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
