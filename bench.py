@@ -117,7 +117,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_raster_translation_cfg2_traffic.txt"))
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_raster_seg_cfg2_traffic.txt"))
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -180,7 +180,7 @@ def main():
         "tile_pairs_per_step": stats["tile_pairs"],
         "raster_ms": float(np.mean(raster_ms)),
         "device_ms_per_step": stats["total_ms"],
-        "roofline": {"bound": "alu", "kernel": "k_raster_translation", "achieved": achieved,
+        "roofline": {"bound": "alu", "kernel": "k_raster_seg", "achieved": achieved,
                      "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
                      "frac_vs_packed_fp32_peak": achieved / PEAK_FP32_PACKED_TFLOPS,
                      "flops_per_pair": alg_flops_per_pair(P), "traffic": traffic},

@@ -2,9 +2,11 @@
 // sequence of one abstract render.
 //
 // Sequence for one pose box (AbstractSplat over all pixels, Sec. 3.3):
-//   pose forms -> per-Gaussian records (FP64, stored as outward FP32) -> depth order
+//   pose forms (host) -> per-Gaussian records (FP64 mid-radius forms) -> depth order
 //   (radix sort of the upper depth bound) -> tile lists (count, scan, emit, stable
-//   sort by tile) -> per-pixel BlendInd loop -> lower / upper images.
+//   sort by tile) -> per-pixel BlendInd loop (translation boxes: segments of the tile
+//   lists and a front-to-back merge; rotation boxes: Ind runs and a two-phase loop)
+//   -> lower / upper images.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdarg.h>
@@ -160,10 +162,6 @@ static int ensure_ws(Workspace &ws, int n, int ntiles) {
     HIP_TRY(grow(ws.wmax, (size_t)ntiles + 2));
     ws.cap_tiles = (size_t)ntiles;
   }
-  if (!ws.pose) {
-    HIP_TRY(hipMalloc(&ws.pose, sizeof(PoseForms)));
-    ws.cap_cells = 1;
-  }
   if (!ws.counters) {
     HIP_TRY(hipMalloc((void **)&ws.counters, 8 * sizeof(unsigned long long)));
     HIP_TRY(hipHostMalloc((void **)&ws.host_counters, 16 * sizeof(unsigned long long), hipHostMallocDefault));
@@ -264,8 +262,8 @@ static int render_one(ar_scene *sc, const Params &prm, const ar_pose_box &box, i
   HIP_TRY(hipEventRecord(ws.ev[0], s));
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ws.counters, 8);
   HIP_TRY(hipGetLastError());
-  PoseForms *pose = (PoseForms *)ws.pose;
-  HIP_TRY(launch_pose_value(box, P, pose, s));
+  PoseForms pose;
+  if (pose_forms_host(box, P, pose)) return fail(AR_E_INVALID, "unsupported number of pose variables %d", P);
   HIP_TRY(launch_project(P, sc->dev, pose, prm, ws, s));
   // depth order: the upper depth bound as an orderable 64-bit key; values = gid
   bool alt = false;
@@ -424,7 +422,7 @@ int ar_scene_create(const ar_scene_desc *desc, void *hip_stream, ar_scene **out)
 void ar_scene_destroy(ar_scene *sc) {
   if (!sc) return;
   ar::Workspace &w = sc->ws;
-  void *bufs[] = {w.pose, w.rec, w.key, w.key_sort, w.key_alt, w.perm, w.perm_alt, w.rect, w.dform, w.count,
+  void *bufs[] = {w.rec, w.key, w.key_sort, w.key_alt, w.perm, w.perm_alt, w.rect, w.dform, w.count,
                   w.pair_key, w.pair_key_alt, w.pair_val, w.pair_val_alt, w.tile_range, w.hist, w.scan_tmp,
                   w.counters, w.dint, w.wmax, w.run_cnt, w.runs, w.pre, w.prez, w.seg_off, w.seg_tile, w.part,
                   sc->base};

@@ -205,26 +205,33 @@ __device__ void acc_reduce(Acc<P> &acc, double *red, int G, int g, int lane) {
   }
 }
 
-// Concretise the colour forms over the box and write the pixel's lower / upper RGB.
-// nterm bounds the number of summed terms (for the FP64 rounding bound); extra_hi is
-// added to the upper bound (the transmittance left when a tile stops early).
+// Concretise one colour channel's forms over the box and write the pixel's lower / upper
+// value.  nterm bounds the number of summed terms (for the FP64 rounding bound); extra_hi
+// is added to the upper bound (the transmittance left when a segment stops early).
+template <int P>
+__device__ __forceinline__ void write_channel(const double *lo_f, const double *hi_f, double ihi, float magl, float magh,
+                                              double nterm, double E, double extra_hi, float *out_lo, float *out_hi,
+                                              size_t idx) {
+  const double wlo = (nterm + 16.0) * 0x1p-51 * (double)magl;
+  const double whi = (nterm + 16.0) * 0x1p-51 * (double)magh;
+  double sl = 0.0, sh = 0.0;
+#pragma unroll
+  for (int j = 0; j < P; ++j) { sl += fabs(lo_f[j]); sh += fabs(hi_f[j]); }
+  double lo = lo_f[P] - sl - E - wlo;
+  double hi = fmin(hi_f[P] + sh, ihi) + E + whi + extra_hi;
+  lo = fmin(fmax(lo, 0.0), 1.0);
+  hi = fmin(fmax(hi, 0.0), 1.0);
+  out_lo[idx] = __double2float_rd(lo);
+  out_hi[idx] = __double2float_ru(hi);
+}
+
 template <int P>
 __device__ void write_pixel(const Acc<P> &acc, double nterm, double E, double extra_hi, float *out_lo,
                             float *out_hi, size_t pix) {
-  const double wlo = (nterm + 16.0) * 0x1p-51 * (double)acc.magl;
-  const double whi = (nterm + 16.0) * 0x1p-51 * (double)acc.magh;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    double sl = 0.0, sh = 0.0;
-#pragma unroll
-    for (int j = 0; j < P; ++j) { sl += fabs(acc.lo[c][j]); sh += fabs(acc.hi[c][j]); }
-    double lo = acc.lo[c][P] - sl - E - wlo;
-    double hi = fmin(acc.hi[c][P] + sh, acc.ihi[c]) + E + whi + extra_hi;
-    lo = fmin(fmax(lo, 0.0), 1.0);
-    hi = fmin(fmax(hi, 0.0), 1.0);
-    out_lo[pix + c] = __double2float_rd(lo);
-    out_hi[pix + c] = __double2float_ru(hi);
-  }
+  for (int c = 0; c < 3; ++c)
+    write_channel<P>(acc.lo[c], acc.hi[c], acc.ihi[c], acc.magl, acc.magh, nterm, E, extra_hi, out_lo, out_hi,
+                     pix + c);
 }
 
 }  // namespace ar

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void k_tile_wmax(const uint32_t *__restrict__ 
 
 // Ind(d_i - d_j) in {0, 1, 2 = unknown} (see the file comment)
 template <int P>
-__device__ __forceinline__ int ind_pair(const PoseForms *__restrict__ pose, const double *uwi, const double *uwj,
+__device__ __forceinline__ int ind_pair(const PoseForms &pose, const double *uwi, const double *uwj,
                                         const double *dfi, const double *dfj) {
   // identity bound: sum_l A_z,l * (uw_i - uw_j)_l, each term a scaled form
   double lo[P + 1], up[P + 1];
@@ -61,7 +61,7 @@ __device__ __forceinline__ int ind_pair(const PoseForms *__restrict__ pose, cons
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
     const double c = uwi[l] - uwj[l];
-    const double(*a)[kMaxP + 1] = pose->A[6 + l];
+    const double(*a)[kMaxP + 1] = pose.A[6 + l];
     const double *fl = c >= 0.0 ? a[0] : a[1];
     const double *fu = c >= 0.0 ? a[1] : a[0];
 #pragma unroll
@@ -92,7 +92,7 @@ template <int P, bool EMIT>
 __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey, const uint32_t *__restrict__ ranges,
                                               const uint32_t *__restrict__ lists, const double *__restrict__ dint,
                                               const double *__restrict__ dform, const double *__restrict__ wmax,
-                                              const PoseForms *__restrict__ pose, SceneDev sc, int npairs,
+                                              const PoseForms pose, SceneDev sc, int npairs,
                                               uint32_t *__restrict__ cnt, uint32_t *__restrict__ runs,
                                               unsigned long long *__restrict__ counters) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -307,7 +307,7 @@ hipError_t launch_tile_wmax(const Workspace &ws, const uint32_t *lists, int ntil
 }
 
 template <int P>
-static hipError_t launch_runs_p(const Workspace &ws, const uint32_t *lists, const PoseForms *pose, const SceneDev &sc,
+static hipError_t launch_runs_p(const Workspace &ws, const uint32_t *lists, const PoseForms &pose, const SceneDev &sc,
                                 int npairs, bool emit, hipStream_t s) {
   const dim3 grid((npairs + 255) / 256), block(256);
   if (emit)
@@ -319,7 +319,7 @@ static hipError_t launch_runs_p(const Workspace &ws, const uint32_t *lists, cons
   return hipGetLastError();
 }
 
-hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *pose, const SceneDev &sc,
+hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms &pose, const SceneDev &sc,
                        int npairs, bool emit, hipStream_t s) {
   if (npairs <= 0) return hipSuccess;
   switch (P) {

@@ -99,8 +99,6 @@ struct SceneDev {
 // Device workspace (grown on demand, owned by a scene handle).
 struct Workspace {
   size_t cap_n = 0, cap_pairs = 0, cap_tiles = 0, cap_scratch = 0;
-  void *pose = nullptr;        // PoseForms (one per cell)
-  int32_t cap_cells = 0;
   double *rec = nullptr;       // [n][stride]
   uint64_t *key = nullptr;     // [n] depth key (by gid, kept for tie tests)
   uint64_t *key_sort = nullptr;  // [n] copy of the keys, sorted in place
@@ -139,9 +137,8 @@ struct Workspace {
 };
 
 // ---- launchers (ar_project.hip) ----
-hipError_t launch_pose(const ar_pose_box *boxes_dev, int ncells, int P, PoseForms *out, hipStream_t s);
-hipError_t launch_pose_value(const ar_pose_box &box, int P, PoseForms *out, hipStream_t s);
-hipError_t launch_project(int P, const SceneDev &sc, const PoseForms *pose, const Params &prm,
+int pose_forms_host(const ar_pose_box &box, int P, PoseForms &out);
+hipError_t launch_project(int P, const SceneDev &sc, const PoseForms &pose, const Params &prm,
                           Workspace &ws, hipStream_t s);
 // ---- sorting / scans (ar_sort.hip) ----
 hipError_t radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt, int n,
@@ -162,7 +159,7 @@ hipError_t launch_raster_translation(int P, const Workspace &ws, const uint32_t 
                                      int nseg_max, float *lo, float *hi, hipStream_t s);
 // general path (ar_general.hip)
 hipError_t launch_tile_wmax(const Workspace &ws, const uint32_t *lists, int ntiles, hipStream_t s);
-hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *pose, const SceneDev &sc,
+hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms &pose, const SceneDev &sc,
                        int npairs, bool emit, hipStream_t s);
 hipError_t launch_raster_general(int P, const Workspace &ws, const uint32_t *lists, const Params &prm, float *lo,
                                  float *hi, hipStream_t s);

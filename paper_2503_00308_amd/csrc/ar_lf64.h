@@ -20,7 +20,7 @@ struct L64 {
 };
 
 template <int P>
-__device__ __forceinline__ L64<P> l_const(double c) {
+__host__ __device__ __forceinline__ L64<P> l_const(double c) {
   L64<P> r;
 #pragma unroll
   for (int k = 0; k < P; ++k) { r.lo[k] = 0.0; r.up[k] = 0.0; }
@@ -31,7 +31,7 @@ __device__ __forceinline__ L64<P> l_const(double c) {
 
 // interval [min_e lower form, max_e upper form]
 template <int P>
-__device__ __forceinline__ void l_bounds(const L64<P> &x, double &lo, double &hi) {
+__host__ __device__ __forceinline__ void l_bounds(const L64<P> &x, double &lo, double &hi) {
   double sl = 0.0, sh = 0.0;
 #pragma unroll
   for (int k = 0; k < P; ++k) { sl += fabs(x.lo[k]); sh += fabs(x.up[k]); }
@@ -41,7 +41,7 @@ __device__ __forceinline__ void l_bounds(const L64<P> &x, double &lo, double &hi
 
 // max over the box of |form| (sum of |coefficients| and |constant|)
 template <int P>
-__device__ __forceinline__ double l_mag(const double *f) {
+__host__ __device__ __forceinline__ double l_mag(const double *f) {
   double s = fabs(f[P]);
 #pragma unroll
   for (int k = 0; k < P; ++k) s += fabs(f[k]);
@@ -49,7 +49,7 @@ __device__ __forceinline__ double l_mag(const double *f) {
 }
 
 template <int P>
-__device__ __forceinline__ L64<P> l_add(const L64<P> &a, const L64<P> &b) {
+__host__ __device__ __forceinline__ L64<P> l_add(const L64<P> &a, const L64<P> &b) {
   L64<P> r;
 #pragma unroll
   for (int k = 0; k <= P; ++k) { r.lo[k] = a.lo[k] + b.lo[k]; r.up[k] = a.up[k] + b.up[k]; }
@@ -57,7 +57,7 @@ __device__ __forceinline__ L64<P> l_add(const L64<P> &a, const L64<P> &b) {
 }
 
 template <int P>
-__device__ __forceinline__ L64<P> l_neg(const L64<P> &a) {
+__host__ __device__ __forceinline__ L64<P> l_neg(const L64<P> &a) {
   L64<P> r;
 #pragma unroll
   for (int k = 0; k <= P; ++k) { r.lo[k] = -a.up[k]; r.up[k] = -a.lo[k]; }
@@ -65,12 +65,12 @@ __device__ __forceinline__ L64<P> l_neg(const L64<P> &a) {
 }
 
 template <int P>
-__device__ __forceinline__ L64<P> l_sub(const L64<P> &a, const L64<P> &b) {
+__host__ __device__ __forceinline__ L64<P> l_sub(const L64<P> &a, const L64<P> &b) {
   return l_add<P>(a, l_neg<P>(b));
 }
 
 template <int P>
-__device__ __forceinline__ L64<P> l_addc(const L64<P> &a, double c) {
+__host__ __device__ __forceinline__ L64<P> l_addc(const L64<P> &a, double c) {
   L64<P> r = a;
   r.lo[P] = a.lo[P] + c;
   r.up[P] = a.up[P] + c;
@@ -79,21 +79,21 @@ __device__ __forceinline__ L64<P> l_addc(const L64<P> &a, double c) {
 
 // lower form of c*x for a constant c
 template <int P>
-__device__ __forceinline__ void l_scale_lower(const L64<P> &x, double c, double *out) {
+__host__ __device__ __forceinline__ void l_scale_lower(const L64<P> &x, double c, double *out) {
   const double *f = c >= 0.0 ? x.lo : x.up;
 #pragma unroll
   for (int k = 0; k <= P; ++k) out[k] = c * f[k];
 }
 
 template <int P>
-__device__ __forceinline__ void l_scale_upper(const L64<P> &x, double c, double *out) {
+__host__ __device__ __forceinline__ void l_scale_upper(const L64<P> &x, double c, double *out) {
   const double *f = c >= 0.0 ? x.up : x.lo;
 #pragma unroll
   for (int k = 0; k <= P; ++k) out[k] = c * f[k];
 }
 
 template <int P>
-__device__ __forceinline__ L64<P> l_scale(const L64<P> &x, double c) {
+__host__ __device__ __forceinline__ L64<P> l_scale(const L64<P> &x, double c) {
   L64<P> r;
   l_scale_lower<P>(x, c, r.lo);
   l_scale_upper<P>(x, c, r.up);
@@ -102,7 +102,7 @@ __device__ __forceinline__ L64<P> l_scale(const L64<P> &x, double c) {
 
 // x * y, McCormick: lower ylo*x + xlo*y - xlo*ylo, upper yhi*x + xlo*y - xlo*yhi
 template <int P>
-__device__ __forceinline__ L64<P> l_mul(const L64<P> &x, const L64<P> &y) {
+__host__ __device__ __forceinline__ L64<P> l_mul(const L64<P> &x, const L64<P> &y) {
   double xlo, xhi, ylo, yhi;
   l_bounds<P>(x, xlo, xhi);
   l_bounds<P>(y, ylo, yhi);
@@ -123,7 +123,7 @@ __device__ __forceinline__ L64<P> l_mul(const L64<P> &x, const L64<P> &y) {
 
 // x * x for one operand
 template <int P>
-__device__ __forceinline__ L64<P> l_sqr(const L64<P> &x) {
+__host__ __device__ __forceinline__ L64<P> l_sqr(const L64<P> &x) {
   double xlo, xhi;
   l_bounds<P>(x, xlo, xhi);
   const double xs = fmin(fmax(0.0, xlo), xhi);
@@ -137,7 +137,7 @@ __device__ __forceinline__ L64<P> l_sqr(const L64<P> &x) {
 
 // sin (is_sin) or cos of an angle given as an exact affine form
 template <int P>
-__device__ __forceinline__ L64<P> l_trig(const L64<P> &th, bool is_sin) {
+__host__ __device__ __forceinline__ L64<P> l_trig(const L64<P> &th, bool is_sin) {
   const double c = th.lo[P];
   double rad = 0.0;
 #pragma unroll

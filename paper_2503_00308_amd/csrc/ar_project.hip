@@ -1,12 +1,13 @@
 // Pose stage and per-Gaussian stage of abstract rendering (FP64), gfx950.
 //
-// Pose stage: the set of cameras as linear forms uc = A (uw - tau) + beta
-//   (Alg. GaussianSplat line 2 with R and t replaced by their forms over the box).
+// Pose stage (host and device): the set of cameras as linear forms
+//   uc = A (uw - tau) + beta (Alg. GaussianSplat line 2 with R and t replaced by their
+//   forms over the box).
 // Per-Gaussian stage (one thread per Gaussian): lines 2-8 of Alg. GaussianSplat as
 //   linear-relational operations (Sec. 3.3), MatrixInv for line 8 (Sec. 3.1), and
 //   B = Conic * Mp hoisted out of the pixel loop (line 9 evaluated as v * (Conic Mp)).
-//   The result is stored as an FP32 record with every lower form rounded down and
-//   every upper form rounded up, plus the footprint bound used for pruning.
+//   The result is stored as an FP64 record of mid-radius form pairs, plus the
+//   float32 footprint data used for pruning.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -19,7 +20,7 @@ namespace ar {
 // pose stage
 // ---------------------------------------------------------------------------------
 template <int P>
-__device__ void store_form(double (*dst)[kMaxP + 1], const L64<P> &x) {
+__host__ __device__ void store_form(double (*dst)[kMaxP + 1], const L64<P> &x) {
   for (int k = 0; k <= kMaxP; ++k) { dst[0][k] = 0.0; dst[1][k] = 0.0; }
   for (int k = 0; k < P; ++k) { dst[0][k] = x.lo[k]; dst[1][k] = x.up[k]; }
   dst[0][kMaxP] = x.lo[P];
@@ -27,7 +28,7 @@ __device__ void store_form(double (*dst)[kMaxP + 1], const L64<P> &x) {
 }
 
 template <int P>
-__device__ __forceinline__ L64<P> load_form(const double (*src)[kMaxP + 1]) {
+__host__ __device__ __forceinline__ L64<P> load_form(const double (*src)[kMaxP + 1]) {
   L64<P> x;
 #pragma unroll
   for (int k = 0; k < P; ++k) { x.lo[k] = src[0][k]; x.up[k] = src[1][k]; }
@@ -38,7 +39,7 @@ __device__ __forceinline__ L64<P> load_form(const double (*src)[kMaxP + 1]) {
 
 // elementary right-handed rotation (axis 0 = x, 1 = y, 2 = z) of an exact affine angle
 template <int P>
-__device__ void rot_forms(int axis, const L64<P> &ang, L64<P> R[9]) {
+__host__ __device__ void rot_forms(int axis, const L64<P> &ang, L64<P> R[9]) {
   const L64<P> c = l_trig<P>(ang, false);
   const L64<P> s = l_trig<P>(ang, true);
   const L64<P> ns = l_neg<P>(s);
@@ -54,7 +55,7 @@ __device__ void rot_forms(int axis, const L64<P> &ang, L64<P> R[9]) {
 
 // C = Mmul(A, B) for 3x3 matrices of forms: C_ij = sum_t Mul(A_it, B_tj)
 template <int P>
-__device__ void mmul3(const L64<P> A[9], const L64<P> B[9], L64<P> C[9]) {
+__host__ __device__ void mmul3(const L64<P> A[9], const L64<P> B[9], L64<P> C[9]) {
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
       L64<P> acc = l_mul<P>(A[i * 3 + 0], B[0 * 3 + j]);
@@ -65,7 +66,7 @@ __device__ void mmul3(const L64<P> A[9], const L64<P> B[9], L64<P> C[9]) {
 }
 
 template <int P>
-__device__ L64<P> pose_param(const double *lo, const double *hi, int axis, const int *index) {
+__host__ __device__ L64<P> pose_param(const double *lo, const double *hi, int axis, const int *index) {
   const double c = 0.5 * (lo[axis] + hi[axis]);
   const double r = 0.5 * (hi[axis] - lo[axis]);
   L64<P> x = l_const<P>(c);
@@ -77,7 +78,7 @@ __device__ L64<P> pose_param(const double *lo, const double *hi, int axis, const
 }
 
 template <int P>
-__device__ void pose_forms(const ar_pose_box &b, PoseForms &pf) {
+__host__ __device__ void pose_forms(const ar_pose_box &b, PoseForms &pf) {
   pf.P = P;
   L64<P> A[9], tau[3], beta[3];
   if (b.model == AR_POSE_CAMERA6) {
@@ -113,17 +114,6 @@ __device__ void pose_forms(const ar_pose_box &b, PoseForms &pf) {
     store_form<P>(pf.tau[k], tau[k]);
     store_form<P>(pf.beta[k], beta[k]);
   }
-}
-
-template <int P>
-__global__ void k_pose(const ar_pose_box *boxes, int ncells, PoseForms *out) {
-  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell < ncells) pose_forms<P>(boxes[cell], out[cell]);
-}
-
-template <int P>
-__global__ void k_pose_value(ar_pose_box box, PoseForms *out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) pose_forms<P>(box, out[0]);
 }
 
 // ---------------------------------------------------------------------------------
@@ -237,7 +227,7 @@ __device__ bool matrix_inv(const L64<P> &x00, const L64<P> &x01, const L64<P> &x
 }
 
 template <int P>
-__global__ __launch_bounds__(64) void k_project(SceneDev sc, const PoseForms *__restrict__ pose, Params prm,
+__global__ __launch_bounds__(64) void k_project(SceneDev sc, const PoseForms pose, Params prm,
                                                 double *__restrict__ rec_out, uint64_t *__restrict__ key_out,
                                                 uint64_t *__restrict__ key_sort, uint32_t *__restrict__ perm_out, int32_t *__restrict__ rect_out,
                                                 double *__restrict__ dform_out, double *__restrict__ dint_out,
@@ -255,14 +245,14 @@ __global__ __launch_bounds__(64) void k_project(SceneDev sc, const PoseForms *__
   // line 2: uc = Mmul(A, Add(uw, -tau)) + beta
   L64<P> y[3];
 #pragma unroll
-  for (int l = 0; l < 3; ++l) y[l] = l_addc<P>(l_neg<P>(load_form<P>(pose->tau[l])), uw[l]);
+  for (int l = 0; l < 3; ++l) y[l] = l_addc<P>(l_neg<P>(load_form<P>(pose.tau[l])), uw[l]);
   L64<P> uc[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    L64<P> acc = l_mul<P>(load_form<P>(pose->A[k * 3 + 0]), y[0]);
-    acc = l_add<P>(acc, l_mul<P>(load_form<P>(pose->A[k * 3 + 1]), y[1]));
-    acc = l_add<P>(acc, l_mul<P>(load_form<P>(pose->A[k * 3 + 2]), y[2]));
-    uc[k] = l_add<P>(acc, load_form<P>(pose->beta[k]));
+    L64<P> acc = l_mul<P>(load_form<P>(pose.A[k * 3 + 0]), y[0]);
+    acc = l_add<P>(acc, l_mul<P>(load_form<P>(pose.A[k * 3 + 1]), y[1]));
+    acc = l_add<P>(acc, l_mul<P>(load_form<P>(pose.A[k * 3 + 2]), y[2]));
+    uc[k] = l_add<P>(acc, load_form<P>(pose.beta[k]));
   }
   const L64<P> &x = uc[0], &yy = uc[1], &d = uc[2];   // line 7: d = uc_z
   const double fx = prm.fx, fy = prm.fy;
@@ -277,9 +267,9 @@ __global__ __launch_bounds__(64) void k_project(SceneDev sc, const PoseForms *__
     L64<P> Mc[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      L64<P> acc = l_scale<P>(load_form<P>(pose->A[k * 3 + 0]), Mw[0 * 3 + m]);
-      acc = l_add<P>(acc, l_scale<P>(load_form<P>(pose->A[k * 3 + 1]), Mw[1 * 3 + m]));
-      acc = l_add<P>(acc, l_scale<P>(load_form<P>(pose->A[k * 3 + 2]), Mw[2 * 3 + m]));
+      L64<P> acc = l_scale<P>(load_form<P>(pose.A[k * 3 + 0]), Mw[0 * 3 + m]);
+      acc = l_add<P>(acc, l_scale<P>(load_form<P>(pose.A[k * 3 + 1]), Mw[1 * 3 + m]));
+      acc = l_add<P>(acc, l_scale<P>(load_form<P>(pose.A[k * 3 + 2]), Mw[2 * 3 + m]));
       Mc[k] = acc;
     }
     Mp0[m] = l_add<P>(l_mul<P>(J00, Mc[0]), l_mul<P>(J02, Mc[2]));
@@ -418,53 +408,29 @@ __global__ __launch_bounds__(64) void k_project(SceneDev sc, const PoseForms *__
   }
 }
 
-template <int P>
-static hipError_t launch_pose_p(const ar_pose_box *boxes, int ncells, PoseForms *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_pose<P>, dim3((ncells + 63) / 64), dim3(64), 0, s, boxes, ncells, out);
-  return hipGetLastError();
-}
-
-template <int P>
-static hipError_t launch_pose_value_p(const ar_pose_box &box, PoseForms *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_pose_value<P>, dim3(1), dim3(64), 0, s, box, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_pose_value(const ar_pose_box &box, int P, PoseForms *out, hipStream_t s) {
+// Pose forms on the host: O(1) work, passed to the kernels by value.
+int pose_forms_host(const ar_pose_box &box, int P, PoseForms &out) {
   switch (P) {
-    case 0: return launch_pose_value_p<0>(box, out, s);
-    case 1: return launch_pose_value_p<1>(box, out, s);
-    case 2: return launch_pose_value_p<2>(box, out, s);
-    case 3: return launch_pose_value_p<3>(box, out, s);
-    case 4: return launch_pose_value_p<4>(box, out, s);
-    case 5: return launch_pose_value_p<5>(box, out, s);
-    case 6: return launch_pose_value_p<6>(box, out, s);
+    case 0: pose_forms<0>(box, out); return 0;
+    case 1: pose_forms<1>(box, out); return 0;
+    case 2: pose_forms<2>(box, out); return 0;
+    case 3: pose_forms<3>(box, out); return 0;
+    case 4: pose_forms<4>(box, out); return 0;
+    case 5: pose_forms<5>(box, out); return 0;
+    case 6: pose_forms<6>(box, out); return 0;
   }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_pose(const ar_pose_box *boxes, int ncells, int P, PoseForms *out, hipStream_t s) {
-  switch (P) {
-    case 0: return launch_pose_p<0>(boxes, ncells, out, s);
-    case 1: return launch_pose_p<1>(boxes, ncells, out, s);
-    case 2: return launch_pose_p<2>(boxes, ncells, out, s);
-    case 3: return launch_pose_p<3>(boxes, ncells, out, s);
-    case 4: return launch_pose_p<4>(boxes, ncells, out, s);
-    case 5: return launch_pose_p<5>(boxes, ncells, out, s);
-    case 6: return launch_pose_p<6>(boxes, ncells, out, s);
-  }
-  return hipErrorInvalidValue;
+  return -1;
 }
 
 template <int P>
-static hipError_t launch_project_p(const SceneDev &sc, const PoseForms *pose, const Params &prm, Workspace &ws,
+static hipError_t launch_project_p(const SceneDev &sc, const PoseForms &pose, const Params &prm, Workspace &ws,
                                    hipStream_t s) {
   hipLaunchKernelGGL(k_project<P>, dim3((sc.n + 63) / 64), dim3(64), 0, s, sc, pose, prm, ws.rec, ws.key, ws.key_sort,
                      ws.perm, ws.rect, ws.dform, ws.dint, ws.counters);
   return hipGetLastError();
 }
 
-hipError_t launch_project(int P, const SceneDev &sc, const PoseForms *pose, const Params &prm, Workspace &ws,
+hipError_t launch_project(int P, const SceneDev &sc, const PoseForms &pose, const Params &prm, Workspace &ws,
                           hipStream_t s) {
   switch (P) {
     case 0: return launch_project_p<0>(sc, pose, prm, ws, s);

@@ -52,36 +52,43 @@ __device__ __forceinline__ float tile_dist2(const float *mu, int tx, int ty, con
   return dist2_rect(mu, ux0, ux1, uy0, uy1);
 }
 
+// One wave per Gaussian (in depth-rank order): the lanes walk the tile rectangle 64
+// tiles at a time; a ballot gives each kept tile its slot.
 template <int P, bool EMIT>
 __global__ __launch_bounds__(256) void k_bin(const double *__restrict__ recs, const int32_t *__restrict__ rect,
                                              const uint32_t *__restrict__ perm, int n, Params prm,
                                              uint32_t *__restrict__ counts, uint32_t *__restrict__ pkey,
                                              uint32_t *__restrict__ pval) {
   using R = Rec<P>;
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int r = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   if (r >= n) return;
   const uint32_t gid = perm[r];
   const double *rec = recs + (size_t)gid * R::STRIDE;
   const int type = rec_type<P>(rec);
   const int32_t *rc = rect + 4 * (size_t)gid;
   uint32_t c = 0;
-  uint32_t off = EMIT ? counts[r] : 0u;
+  const uint32_t off = EMIT ? counts[r] : 0u;
   if (type != kDropped && rc[0] <= rc[2] && rc[1] <= rc[3]) {
     const float *mu = rec_prune<P>(rec);
     const float r2 = mu[4];
-    for (int ty = rc[1]; ty <= rc[3]; ++ty)
-      for (int tx = rc[0]; tx <= rc[2]; ++tx) {
-        const bool keep = (type == kWild) || (tile_dist2(mu, tx, ty, prm) <= r2);
-        if (keep) {
-          if (EMIT) {
-            pkey[off + c] = (uint32_t)(ty * prm.ntx + tx);
-            pval[off + c] = gid;
-          }
-          ++c;
-        }
+    const int w = rc[2] - rc[0] + 1;
+    const int total = w * (rc[3] - rc[1] + 1);
+    const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    for (int i0 = 0; i0 < total; i0 += 64) {
+      const int i = i0 + lane;
+      const int tx = rc[0] + i % w, ty = rc[1] + i / w;
+      const bool keep = i < total && ((type == kWild) || (tile_dist2(mu, tx, ty, prm) <= r2));
+      const uint64_t bal = __ballot(keep);
+      if (EMIT && keep) {
+        const uint32_t pos = off + c + (uint32_t)__popcll(bal & below);
+        pkey[pos] = (uint32_t)(ty * prm.ntx + tx);
+        pval[pos] = gid;
       }
+      c += (uint32_t)__popcll(bal);
+    }
   }
-  if (!EMIT) counts[r] = c;
+  if (!EMIT && lane == 0) counts[r] = c;
 }
 
 __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v) {
@@ -99,12 +106,13 @@ __global__ void k_tile_ranges(const uint32_t *__restrict__ keys, int npairs, uin
 
 template <int P>
 static hipError_t launch_bin_p(const Workspace &ws, int n, const Params &prm, bool emit, hipStream_t s) {
+  const dim3 grid((unsigned)((n + 3) / 4));   // four waves (Gaussians) per block
   if (emit)
-    hipLaunchKernelGGL((k_bin<P, true>), dim3((n + 255) / 256), dim3(256), 0, s, ws.rec, ws.rect, ws.perm, n, prm,
-                       ws.count, ws.pair_key, ws.pair_val);
+    hipLaunchKernelGGL((k_bin<P, true>), grid, dim3(256), 0, s, ws.rec, ws.rect, ws.perm, n, prm, ws.count,
+                       ws.pair_key, ws.pair_val);
   else
-    hipLaunchKernelGGL((k_bin<P, false>), dim3((n + 255) / 256), dim3(256), 0, s, ws.rec, ws.rect, ws.perm, n, prm,
-                       ws.count, ws.pair_key, ws.pair_val);
+    hipLaunchKernelGGL((k_bin<P, false>), grid, dim3(256), 0, s, ws.rec, ws.rect, ws.perm, n, prm, ws.count,
+                       ws.pair_key, ws.pair_val);
   return hipGetLastError();
 }
 
@@ -273,12 +281,13 @@ __global__ __launch_bounds__(256) void k_raster_seg(const double *__restrict__ r
   q[Q::CNT * 64] = (double)cnt;
 }
 
-// One wave per tile: combine the tile's segments front to back,
+// Three waves per tile, one per colour channel: combine the tile's segments front to
+// back,
 //   acc += T * acc_s,  T *= T_s  (lower with T_lo, upper with T_hi),
 // and write the pixel bounds.  A segment that stopped early ends the tile: everything
 // behind its stop point adds at most T_hi (in front) * T_hi (segment at the stop).
 template <int P>
-__global__ __launch_bounds__(256) void k_merge(const uint32_t *__restrict__ ranges,
+__global__ __launch_bounds__(192) void k_merge(const uint32_t *__restrict__ ranges,
                                                const uint32_t *__restrict__ seg_off,
                                                const double *__restrict__ part, Params prm,
                                                float *__restrict__ out_lo, float *__restrict__ out_hi,
@@ -286,32 +295,31 @@ __global__ __launch_bounds__(256) void k_merge(const uint32_t *__restrict__ rang
   using Q = Part<P>;
   constexpr int F = P + 1;
   const int lane = threadIdx.x & 63;
+  const int c = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // colour channel
   const int ntiles = prm.ntx * prm.nty;
-  const int tile = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+  const int tile = (int)blockIdx.x;
   if (tile >= ntiles) return;
   const int tx = tile % prm.ntx, ty = tile / prm.ntx;
   const int col = tx * kTile + (lane & 7), row = ty * kTile + (lane >> 3);
   const bool inimg = col < prm.width && row < prm.height;
   const int s0 = (int)seg_off[tile], s1 = (int)seg_off[tile + 1];
-  Acc<P> acc, src;
-  acc_zero<P>(acc);
+  double lo[F], hi[F], ihi = 0.0;
+#pragma unroll
+  for (int j = 0; j < F; ++j) { lo[j] = 0.0; hi[j] = 0.0; }
+  float magl = 0.0f, magh = 0.0f;
   double T_lo = 1.0, T_hi = 1.0, extra = 0.0;
   unsigned long long cnt = 0;
   for (int s = s0; s < s1; ++s) {
     const double *q = part + (size_t)s * Q::NF * 64 + lane;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-#pragma unroll
-      for (int j = 0; j < F; ++j) {
-        src.lo[c][j] = q[(Q::LO + c * F + j) * 64];
-        src.hi[c][j] = q[(Q::HI + c * F + j) * 64];
-      }
-      src.ihi[c] = q[(Q::IHI + c) * 64];
+    for (int j = 0; j < F; ++j) {
+      lo[j] = fma(T_lo, q[(Q::LO + c * F + j) * 64], lo[j]);
+      hi[j] = fma(T_hi, q[(Q::HI + c * F + j) * 64], hi[j]);
     }
+    ihi = fma(T_hi, q[(Q::IHI + c) * 64], ihi);
     const float2 mg = __builtin_bit_cast(float2, q[Q::MAG * 64]);
-    src.magl = mg.x;
-    src.magh = mg.y;
-    acc_fma<P>(acc, src, T_lo, T_hi);
+    magl = fmaf((float)T_lo, mg.x, magl) * (1.0f + 4.0f * kU32);
+    magh = fmaf((float)T_hi, mg.y, magh) * (1.0f + 4.0f * kU32);
     cnt += (unsigned long long)q[Q::CNT * 64];
     const double t_lo = q[Q::TLO * 64], t_hi = q[Q::THI * 64];
     if (q[Q::STOP * 64] != 0.0) {
@@ -321,11 +329,11 @@ __global__ __launch_bounds__(256) void k_merge(const uint32_t *__restrict__ rang
     T_lo *= t_lo;
     T_hi *= t_hi;
   }
-  if (lane == 0 && cnt) atomicAdd(&counters[0], cnt);
+  if (c == 0 && lane == 0 && cnt) atomicAdd(&counters[0], cnt);
   if (!inimg) return;
   const int n = (int)(ranges[2 * tile + 1] - ranges[2 * tile]);
-  write_pixel<P>(acc, (double)(n + 2 * (s1 - s0)), prm.E, extra, out_lo, out_hi,
-                 ((size_t)row * prm.width + col) * 3);
+  write_channel<P>(lo, hi, ihi, magl, magh, (double)(n + 2 * (s1 - s0)), prm.E, extra, out_lo, out_hi,
+                   ((size_t)row * prm.width + col) * 3 + c);
 }
 
 template <int P>
@@ -337,8 +345,8 @@ static hipError_t launch_trans_p(const Workspace &ws, const uint32_t *lists, con
     hipLaunchKernelGGL(k_raster_seg<P>, dim3((nseg_max + 3) / 4), dim3(256), 0, s, ws.rec, ws.key, ws.tile_range,
                        lists, ws.seg_off, ws.seg_tile, L, prm, ws.part);
   HIP_RET(hipEventRecord(ws.ev[2], s));
-  hipLaunchKernelGGL(k_merge<P>, dim3((ntiles + 3) / 4), dim3(256), 0, s, ws.tile_range, ws.seg_off, ws.part, prm,
-                     lo, hi, ws.counters);
+  hipLaunchKernelGGL(k_merge<P>, dim3(ntiles), dim3(192), 0, s, ws.tile_range, ws.seg_off, ws.part, prm, lo, hi,
+                     ws.counters);
   return hipGetLastError();
 }
 

@@ -3,8 +3,8 @@
 // Used to order Gaussians by depth key (64-bit) and (tile, depth-rank) pairs by tile
 // id (32-bit keys, stable so that each tile's list stays in depth order).
 //
-// One pass = histogram per block -> exclusive scan over the digit-major histogram
-// -> stable scatter.  Within a block the scatter ranks equal digits with 8 wave
+// Large inputs: one pass = histogram per block -> exclusive scan over the digit-major
+// histogram -> stable scatter.  Small inputs: all passes in one workgroup.  Within a block the scatter ranks equal digits with 8 wave
 // ballots, then across the block's waves through LDS, so equal keys keep input order.
 #include <hip/hip_runtime.h>
 
@@ -189,11 +189,144 @@ hipError_t exclusive_scan_u32(uint32_t *data, int n, Workspace &ws, hipStream_t 
   return hipGetLastError();
 }
 
+// Whole sort in one workgroup (small n): every pass histograms, scans and scatters
+// through global memory (the data stay in L2) with block barriers in between, so a
+// 64-bit sort is one launch instead of 24.  Passes whose digit is the same for every
+// key are skipped.  The result is copied back to (keys, vals) if it ends in the
+// alternate buffers.
+constexpr int kBlockSortThreads = 1024;
+constexpr int kBlockSortMax = 32768;
+
+template <typename K>
+__global__ __launch_bounds__(kBlockSortThreads) void k_radix_sort_block(K *__restrict__ keys, K *__restrict__ keys_alt,
+                                                                        uint32_t *__restrict__ vals,
+                                                                        uint32_t *__restrict__ vals_alt, int n,
+                                                                        int begin_bit, int end_bit) {
+  constexpr int kWaves = kBlockSortThreads / 64;
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t running[256];
+  __shared__ uint32_t wcount[kWaves][256];
+  __shared__ int skip;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  K *ki = keys, *ko = keys_alt;
+  uint32_t *vi = vals, *vo = vals_alt;
+  for (int shift = begin_bit; shift < end_bit; shift += 8) {
+    if (tid < 256) hist[tid] = 0u;
+    __syncthreads();
+    for (int i = tid; i < n; i += kBlockSortThreads) atomicAdd(&hist[(uint32_t)(ki[i] >> shift) & 255u], 1u);
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t run = 0;
+      int full = 0;
+      for (int d = 0; d < 256; ++d) {
+        const uint32_t h = hist[d];
+        running[d] = run;
+        run += h;
+        full |= (h == (uint32_t)n);
+      }
+      skip = full;
+    }
+    __syncthreads();
+    if (skip) continue;   // every key has this digit: order unchanged
+    for (int base = 0; base < n; base += kBlockSortThreads) {
+      const int idx = base + tid;
+      const bool valid = idx < n;
+      K key = 0;
+      uint32_t val = 0, digit = 0;
+      if (valid) {
+        key = ki[idx];
+        val = vi[idx];
+        digit = (uint32_t)(key >> shift) & 255u;
+      }
+      for (int w = 0; w < kWaves; w += 4) wcount[w + (tid >> 8)][tid & 255] = 0u;
+      __syncthreads();
+      uint64_t match = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const uint64_t bal = __ballot((digit >> b) & 1u);
+        match &= ((digit >> b) & 1u) ? bal : ~bal;
+      }
+      const uint32_t rank = __popcll(match & below);
+      if (valid && rank == 0) wcount[wave][digit] = __popcll(match);
+      __syncthreads();
+      if (valid) {
+        uint32_t pos = running[digit] + rank;
+        for (int w = 0; w < wave; ++w) pos += wcount[w][digit];
+        ko[pos] = key;
+        vo[pos] = val;
+      }
+      __syncthreads();
+      if (tid < 256) {
+        uint32_t tot = 0;
+        for (int w = 0; w < kWaves; ++w) tot += wcount[w][tid];
+        running[tid] += tot;
+      }
+      __syncthreads();
+    }
+    K *tk = ki; ki = ko; ko = tk;
+    uint32_t *tv = vi; vi = vo; vo = tv;
+  }
+  if (ki != keys) {
+    for (int i = tid; i < n; i += kBlockSortThreads) {
+      keys[i] = ki[i];
+      vals[i] = vi[i];
+    }
+  }
+}
+
+// Small depth sorts (n <= kRankMax): the rank of key i is the number of (key_j, j) below
+// (key_i, i) -- a stable order by counting, no passes.  Block (kb, cb) counts the keys
+// of chunk cb (staged in LDS) below the 256 keys of block kb and adds the counts; a
+// second kernel scatters the values by rank.
+constexpr int kRankMax = 16384;
+constexpr int kRankChunk = 512;
+
+__global__ __launch_bounds__(256) void k_rank_count(const uint64_t *__restrict__ keys, int n,
+                                                    uint32_t *__restrict__ rank) {
+  __shared__ uint64_t ck[kRankChunk];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int c0 = blockIdx.y * kRankChunk;
+  const int cn = min(kRankChunk, n - c0);
+  for (int t = threadIdx.x; t < cn; t += 256) ck[t] = keys[c0 + t];
+  __syncthreads();
+  if (i >= n) return;
+  const uint64_t ki = keys[i];
+  uint32_t below = 0;
+  for (int t = 0; t < cn; ++t) {
+    const uint64_t kj = ck[t];
+    below += (kj < ki || (kj == ki && c0 + t < i)) ? 1u : 0u;
+  }
+  if (below) atomicAdd(&rank[i], below);
+}
+
+__global__ void k_rank_scatter(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+                               const uint32_t *__restrict__ rank, int n, uint64_t *__restrict__ kout,
+                               uint32_t *__restrict__ vout) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t r = rank[i];
+  kout[r] = keys[i];
+  vout[r] = vals[i];
+}
+
+__global__ void k_zero_n(uint32_t *__restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
 template <typename K>
 static hipError_t radix_sort(K *keys, K *keys_alt, uint32_t *vals, uint32_t *vals_alt, int n, int begin_bit,
                              int end_bit, Workspace &ws, hipStream_t s, bool *in_alt) {
   *in_alt = false;
   if (n <= 1) return hipSuccess;
+  if (n <= kBlockSortMax) {
+    hipLaunchKernelGGL(k_radix_sort_block<K>, dim3(1), dim3(kBlockSortThreads), 0, s, keys, keys_alt, vals, vals_alt,
+                       n, begin_bit, end_bit);
+    return hipGetLastError();
+  }
   const int nb = (n + kSortTile - 1) / kSortTile;
   hipError_t e = ensure_hist(ws, (size_t)256 * nb);
   if (e != hipSuccess) return e;
@@ -213,6 +346,18 @@ static hipError_t radix_sort(K *keys, K *keys_alt, uint32_t *vals, uint32_t *val
 
 hipError_t radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt, int n, int begin_bit,
                           int end_bit, Workspace &ws, hipStream_t s, bool *in_alt) {
+  if (n > 1 && n <= kRankMax && begin_bit == 0 && end_bit == 64) {
+    // stable order by counting; the sorted keys / values land in the alternate buffers
+    hipError_t e = ensure_hist(ws, (size_t)n);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_n, dim3((n + 255) / 256), dim3(256), 0, s, ws.hist, n);
+    hipLaunchKernelGGL(k_rank_count, dim3((n + 255) / 256, (n + kRankChunk - 1) / kRankChunk), dim3(256), 0, s, keys,
+                       n, ws.hist);
+    hipLaunchKernelGGL(k_rank_scatter, dim3((n + 255) / 256), dim3(256), 0, s, keys, vals, ws.hist, n, keys_alt,
+                       vals_alt);
+    *in_alt = true;
+    return hipGetLastError();
+  }
   return radix_sort<uint64_t>(keys, keys_alt, vals, vals_alt, n, begin_bit, end_bit, ws, s, in_alt);
 }
 
