@@ -113,6 +113,8 @@ typedef struct {
  *               Gaussian i is dropped from pixel u when its alpha is provably below
  *               cull_budget / n at every pose; lower / upper bounds are widened by E
  *   z_near      near plane (default 0.01): depth <= z_near gives alpha 0
+ *   cells_per_launch  ar_render_batch: pose cells per launch (default: as many as fit a
+ *               workspace of about 4 GiB, at most 256)
  *   t_min       stop a tile once every pixel's transmittance upper bound is below it,
  *               widening the upper bound by that transmittance (default 1e-7;
  *               negative disables)
@@ -125,6 +127,8 @@ typedef struct {
   double cull_budget;
   double z_near;
   double t_min;
+  int32_t cells_per_launch;
+  int32_t reserved;
 } ar_options;
 
 /* Statistics of one call (filled when the call returns). */

@@ -109,6 +109,8 @@ static int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_opt
   if (op) o = *op;
   if (o.tile != 0 && o.tile != kTile) return fail(AR_E_UNSUPPORTED, "tile %d: only %d is built", o.tile, kTile);
   if (o.groups < 0 || o.groups > 8) return fail(AR_E_INVALID, "groups %d outside [0, 8]", o.groups);
+  if (o.cells_per_launch < 0 || o.cells_per_launch > 256)
+    return fail(AR_E_INVALID, "cells_per_launch %d outside [0, 256]", o.cells_per_launch);
   if (o.chunk != 0 && (o.chunk < 8 || o.chunk > 4096)) return fail(AR_E_INVALID, "chunk %d outside [8, 4096]", o.chunk);
   if (o.taylor_k < 0 || o.taylor_k > 16) return fail(AR_E_INVALID, "taylor_k %d outside [1, 16]", o.taylor_k);
   if (!(o.cull_budget >= 0.0) || !isfinite(o.cull_budget) || o.cull_budget >= 1.0)
@@ -140,27 +142,43 @@ static int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_opt
   return AR_OK;
 }
 
-// Workspace buffers sized for n Gaussians and ntiles tiles.
-static int ensure_ws(Workspace &ws, int n, int ntiles) {
-  const size_t nn = (size_t)n;
-  if (nn > ws.cap_n || !ws.rec) {
-    const size_t c = nn + 64;
-    HIP_TRY(grow(ws.rec, c * rec_stride(kMaxP)));
+// Workspace buffers for n_total = cells * n Gaussian items with P pose variables and
+// nlists = cells * ntiles tile lists.
+static int ensure_ws(Workspace &ws, size_t n_total, size_t nlists, int P, int ncells) {
+  if (n_total > ws.cap_n || !ws.key) {
+    const size_t c = n_total + 64;
     HIP_TRY(grow(ws.key, c));
     HIP_TRY(grow(ws.key_sort, c));
     HIP_TRY(grow(ws.key_alt, c));
     HIP_TRY(grow(ws.perm, c));
     HIP_TRY(grow(ws.perm_alt, c));
+    HIP_TRY(grow(ws.cell_key, c));
+    HIP_TRY(grow(ws.cell_key_alt, c));
     HIP_TRY(grow(ws.rect, 4 * c));
     HIP_TRY(grow(ws.dform, 2 * (kMaxP + 1) * c));
     HIP_TRY(grow(ws.count, c + 1));
     HIP_TRY(grow(ws.dint, 2 * c));
-    ws.cap_n = nn;
+    ws.cap_n = n_total;
   }
-  if ((size_t)ntiles > ws.cap_tiles || !ws.tile_range) {
-    HIP_TRY(grow(ws.tile_range, 2 * (size_t)ntiles + 2));
-    HIP_TRY(grow(ws.wmax, (size_t)ntiles + 2));
-    ws.cap_tiles = (size_t)ntiles;
+  const size_t rec_doubles = n_total * (size_t)rec_stride(P);
+  if (rec_doubles > ws.cap_rec || !ws.rec) {
+    const size_t c = rec_doubles + 64 * (size_t)rec_stride(kMaxP);
+    HIP_TRY(grow(ws.rec, c));
+    ws.cap_rec = c;
+  }
+  if (nlists > ws.cap_tiles || !ws.tile_range) {
+    HIP_TRY(grow(ws.tile_range, 2 * nlists + 2));
+    HIP_TRY(grow(ws.wmax, nlists + 2));
+    ws.cap_tiles = nlists;
+  }
+  if ((size_t)ncells > ws.cap_cells || !ws.pose_dev) {
+    if (ws.pose_host) {
+      HIP_TRY(hipHostFree(ws.pose_host));
+      ws.pose_host = nullptr;
+    }
+    HIP_TRY(grow(ws.pose_dev, (size_t)ncells));
+    HIP_TRY(hipHostMalloc((void **)&ws.pose_host, (size_t)ncells * sizeof(PoseForms), hipHostMallocDefault));
+    ws.cap_cells = (size_t)ncells;
   }
   if (!ws.counters) {
     HIP_TRY(hipMalloc((void **)&ws.counters, 8 * sizeof(unsigned long long)));
@@ -214,11 +232,14 @@ static int ensure_segments(Workspace &ws, size_t ntiles, size_t nseg, int P) {
   return AR_OK;
 }
 
-// Segment length of the translation pixel loop: about 4096 segments over the whole
-// image (four waves per SIMD of the 256-CU part), at least 32 list positions each.
+// Segment length of the translation pixel loop: about 8192 segments over the whole
+// image (eight waves per SIMD of the 256-CU part, so the last wave to start is short),
+// at least 32 list positions each.  Measured on the 10k-Gaussian 128x128 workload: the
+// pixel kernel takes 0.97 ms at L = 96 and 1.19 ms at L = 168; below L = 64 the
+// partial results cost more in the merge than the shorter tail saves.
 static int segment_length(const Params &prm, size_t npairs) {
   if (prm.chunk > 0) return prm.chunk;
-  size_t L = (npairs + 4095) / 4096;
+  size_t L = (npairs + 8191) / 8192;
   L = (L + 7) / 8 * 8;
   return (int)std::min<size_t>(std::max<size_t>(L, 32), 4096);
 }
@@ -250,62 +271,99 @@ static int bits_for(uint32_t v) {
   return b;
 }
 
-// One abstract render of one pose box into device images lo / hi.
-static int render_one(ar_scene *sc, const Params &prm, const ar_pose_box &box, int P, bool rotates, float *lo,
-                      float *hi, hipStream_t s, ar_stats *st) {
+// Cells per launch of a batch: the option if given, else as many as fit a quarter of
+// the free device memory (at most 64 GiB) at the list density of the last launch (32
+// list entries per Gaussian before the first), at most 256.
+static int batch_cells(const ar_scene *sc, const Params &prm, int P, bool rotates, const ar_options *opts) {
+  if (opts && opts->cells_per_launch > 0) return opts->cells_per_launch;
+  const double n = (double)sc->dev.n;
+  const double per_item = 8.0 * rec_stride(P) + 8.0 * (3 + 2 * (kMaxP + 1) + 2) + 4.0 * 5 + 16.0;
+  const double lists_per_item = sc->ws.pairs_per_item > 0.0 ? sc->ws.pairs_per_item : 32.0;
+  const double per_pair = 16.0 + 4.0 + (rotates ? 64.0 * 20.0 + 12.0 : 8.0 * part_fields(P) * 64.0 / 32.0);
+  const double per_cell = n * (per_item + lists_per_item * per_pair) + 64.0 * prm.ntx * prm.nty * 24.0;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)16 << 30;
+  const double budget = std::min(0.25 * (double)free_b, 64.0 * 1024 * 1024 * 1024);
+  return (int)std::max(1.0, std::min(256.0, floor(budget / per_cell)));
+}
+
+// Abstract renders of ncells pose boxes (same P, all rotating or all not) with one
+// launch per stage: item cell * n + g, list cell * ntiles + tile, images [cell][H][W][3].
+// The host waits twice per call (the number of list entries, and on the rotation path
+// the number of Ind runs) and once at the end.
+static int render_cells(ar_scene *sc, const Params &prm, const ar_pose_box *boxes, int ncells, int P, bool rotates,
+                        float *lo, float *hi, hipStream_t s, ar_stats *st) {
   Workspace &ws = sc->ws;
   const int n = sc->dev.n;
   const int ntiles = prm.ntx * prm.nty;
+  const size_t n_total = (size_t)ncells * n;
+  const size_t nlists = (size_t)ncells * ntiles;
   if (!rotates && P > 3) return fail(AR_E_INVALID, "more than 3 translation variables");
-  int rc = ensure_ws(ws, n, ntiles);
+  if (n_total > 0xFFFFFFF0ull || nlists > 0x7FFFFFF0ull) return fail(AR_E_INVALID, "too many cells in one launch");
+  int rc = ensure_ws(ws, n_total, nlists, P, ncells);
   if (rc) return rc;
   HIP_TRY(hipEventRecord(ws.ev[0], s));
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ws.counters, 8);
   HIP_TRY(hipGetLastError());
-  PoseForms pose;
-  if (pose_forms_host(box, P, pose)) return fail(AR_E_INVALID, "unsupported number of pose variables %d", P);
-  HIP_TRY(launch_project(P, sc->dev, pose, prm, ws, s));
-  // depth order: the upper depth bound as an orderable 64-bit key; values = gid
+  // pose forms on the host; by value for a single translation box, else in device memory
+  for (int c = 0; c < ncells; ++c)
+    if (pose_forms_host(boxes[c], P, ws.pose_host[c])) return fail(AR_E_INVALID, "unsupported pose variables %d", P);
+  const bool by_value = ncells == 1 && !rotates;
+  if (!by_value)
+    HIP_TRY(hipMemcpyAsync(ws.pose_dev, ws.pose_host, (size_t)ncells * sizeof(PoseForms), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_project(P, sc->dev, ws.pose_host[0], by_value ? nullptr : ws.pose_dev, ncells, prm, ws, s));
+  // depth order per cell: the upper depth bound as an orderable 64-bit key, values =
+  // global item; then a stable pass by cell
   bool alt = false;
-  HIP_TRY(radix_sort_u64(ws.key_sort, ws.key_alt, ws.perm, ws.perm_alt, n, 0, 64, ws, s, &alt));
+  HIP_TRY(radix_sort_u64(ws.key_sort, ws.key_alt, ws.perm, ws.perm_alt, (int)n_total, 0, 64, ws, s, &alt));
   if (alt) {
     std::swap(ws.key_sort, ws.key_alt);
     std::swap(ws.perm, ws.perm_alt);
   }
+  if (ncells > 1) {
+    HIP_TRY(launch_cell_keys(ws.perm, (int)n_total, n, ws.cell_key, s));
+    HIP_TRY(radix_sort_u32(ws.cell_key, ws.cell_key_alt, ws.perm, ws.perm_alt, (int)n_total, 0,
+                           ((bits_for((uint32_t)(ncells - 1)) + 7) / 8) * 8, ws, s, &alt));
+    if (alt) {
+      std::swap(ws.cell_key, ws.cell_key_alt);
+      std::swap(ws.perm, ws.perm_alt);
+    }
+  }
   // tile lists in depth order
-  HIP_TRY(launch_count_tiles(P, ws, n, prm, s));
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.count + n, 1);
+  HIP_TRY(launch_count_tiles(P, ws, (int)n_total, n, prm, s));
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.count + n_total, 1);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(exclusive_scan_u32(ws.count, n + 1, ws, s));
-  HIP_TRY(hipMemcpyAsync(ws.host_counters, ws.count + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(exclusive_scan_u32(ws.count, (int)n_total + 1, ws, s));
+  HIP_TRY(hipMemcpyAsync(ws.host_counters, ws.count + n_total, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   const uint32_t npairs = *(const uint32_t *)ws.host_counters;
+  ws.pairs_per_item = (double)npairs / (double)std::max<size_t>(n_total, 1);
   rc = ensure_pairs(ws, npairs);
   if (rc) return rc;
-  HIP_TRY(launch_emit_tiles(P, ws, n, prm, s));
-  const int tbits = bits_for((uint32_t)(ntiles - 1));
+  HIP_TRY(launch_emit_tiles(P, ws, (int)n_total, n, prm, s));
+  const int lbits = bits_for((uint32_t)(nlists - 1));
   HIP_TRY(radix_sort_u32(ws.pair_key, ws.pair_key_alt, ws.pair_val, ws.pair_val_alt, (int)npairs, 0,
-                         ((tbits + 7) / 8) * 8, ws, s, &alt));
+                         ((lbits + 7) / 8) * 8, ws, s, &alt));
   if (alt) {
     std::swap(ws.pair_key, ws.pair_key_alt);
     std::swap(ws.pair_val, ws.pair_val_alt);
   }
-  HIP_TRY(launch_tile_ranges(ws.pair_key, (int)npairs, ws.tile_range, ntiles, s));
+  HIP_TRY(launch_tile_ranges(ws.pair_key, (int)npairs, ws.tile_range, (int)nlists, s));
   if (!rotates) {
     const int L = segment_length(prm, npairs);
-    const size_t nseg_max = (npairs + (size_t)L - 1) / (size_t)L + (size_t)ntiles;
-    rc = ensure_segments(ws, (size_t)ntiles, nseg_max, P);
+    const size_t nseg_max = (npairs + (size_t)L - 1) / (size_t)L + nlists;
+    rc = ensure_segments(ws, nlists, nseg_max, P);
     if (rc) return rc;
-    HIP_TRY(launch_segments(ws, ntiles, L, s));
-    HIP_TRY(exclusive_scan_u32(ws.seg_off, ntiles + 1, ws, s));
-    HIP_TRY(launch_segment_map(ws, ntiles, s));
-    HIP_TRY(launch_raster_translation(P, ws, ws.pair_val, prm, L, (int)nseg_max, lo, hi, s));
+    HIP_TRY(launch_segments(ws, (int)nlists, L, s));
+    HIP_TRY(exclusive_scan_u32(ws.seg_off, (int)nlists + 1, ws, s));
+    HIP_TRY(launch_segment_map(ws, (int)nlists, s));
+    HIP_TRY(launch_raster_translation(P, ws, ws.pair_val, (int)nlists, prm, L, (int)nseg_max, lo, hi, s));
   } else {
     // depth order may change inside the box: Ind runs per tile list, then the two-phase loop
     rc = ensure_general(ws, npairs);
     if (rc) return rc;
-    HIP_TRY(launch_tile_wmax(ws, ws.pair_val, ntiles, s));
-    HIP_TRY(launch_runs(P, ws, ws.pair_val, pose, sc->dev, (int)npairs, false, s));
+    HIP_TRY(launch_tile_wmax(ws, ws.pair_val, (int)nlists, s));
+    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, false, s));
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.run_cnt + 2 * (size_t)npairs, 1);
     HIP_TRY(hipGetLastError());
     HIP_TRY(exclusive_scan_u32(ws.run_cnt, (int)(2 * npairs + 1), ws, s));
@@ -315,9 +373,9 @@ static int render_one(ar_scene *sc, const Params &prm, const ar_pose_box &box, i
     const uint32_t nruns = *(const uint32_t *)ws.host_counters;
     rc = ensure_runs(ws, nruns);
     if (rc) return rc;
-    HIP_TRY(launch_runs(P, ws, ws.pair_val, pose, sc->dev, (int)npairs, true, s));
+    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, true, s));
     HIP_TRY(hipEventRecord(ws.ev[1], s));
-    HIP_TRY(launch_raster_general(P, ws, ws.pair_val, prm, lo, hi, s));
+    HIP_TRY(launch_raster_general(P, ws, ws.pair_val, (int)nlists, prm, lo, hi, s));
     HIP_TRY(hipEventRecord(ws.ev[2], s));
   }
   HIP_TRY(hipEventRecord(ws.ev[3], s));
@@ -425,10 +483,11 @@ void ar_scene_destroy(ar_scene *sc) {
   void *bufs[] = {w.rec, w.key, w.key_sort, w.key_alt, w.perm, w.perm_alt, w.rect, w.dform, w.count,
                   w.pair_key, w.pair_key_alt, w.pair_val, w.pair_val_alt, w.tile_range, w.hist, w.scan_tmp,
                   w.counters, w.dint, w.wmax, w.run_cnt, w.runs, w.pre, w.prez, w.seg_off, w.seg_tile, w.part,
-                  sc->base};
+                  w.cell_key, w.cell_key_alt, w.pose_dev, sc->base};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (w.host_counters) (void)hipHostFree(w.host_counters);
+  if (w.pose_host) (void)hipHostFree(w.pose_host);
   for (int i = 0; i < 4; ++i)
     if (w.ev[i]) (void)hipEventDestroy(w.ev[i]);
   delete sc;
@@ -460,8 +519,8 @@ int ar_render_bounds(const ar_scene *scene, const ar_intrinsics *intr, const ar_
   if (stats) memset(stats, 0, sizeof(*stats));
   bool rot = false;
   const int P = ar::pose_vars(box, &rot);
-  return ar::render_one(const_cast<ar_scene *>(scene), prm, *box, P, rot, lo_rgb, hi_rgb, (hipStream_t)hip_stream,
-                        stats);
+  return ar::render_cells(const_cast<ar_scene *>(scene), prm, box, 1, P, rot, lo_rgb, hi_rgb, (hipStream_t)hip_stream,
+                          stats);
 }
 
 int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *cells, int32_t ncells,
@@ -479,12 +538,25 @@ int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_p
   if (rc) return rc;
   if (stats) memset(stats, 0, sizeof(*stats));
   const size_t img = (size_t)intr->width * intr->height * 3;
-  for (int i = 0; i < ncells; ++i) {
+  // runs of consecutive cells with the same pose variables, in launches of at most
+  // cells_per_launch cells (memory-bounded; see batch_cells)
+  int i = 0;
+  while (i < ncells) {
     bool rot = false;
     const int P = ar::pose_vars(&cells[i], &rot);
-    rc = ar::render_one(const_cast<ar_scene *>(scene), prm, cells[i], P, rot, lo_rgb + i * img, hi_rgb + i * img,
-                        (hipStream_t)hip_stream, stats);
-    if (rc) return rc;
+    int j = i + 1;
+    while (j < ncells) {
+      bool r2 = false;
+      if (ar::pose_vars(&cells[j], &r2) != P || r2 != rot) break;
+      ++j;
+    }
+    while (i < j) {
+      const int m = std::min(j - i, ar::batch_cells(scene, prm, P, rot, opts));
+      rc = ar::render_cells(const_cast<ar_scene *>(scene), prm, cells + i, m, P, rot, lo_rgb + i * img,
+                            hi_rgb + i * img, (hipStream_t)hip_stream, stats);
+      if (rc) return rc;
+      i += m;
+    }
   }
   return AR_OK;
 }

@@ -92,12 +92,15 @@ template <int P, bool EMIT>
 __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey, const uint32_t *__restrict__ ranges,
                                               const uint32_t *__restrict__ lists, const double *__restrict__ dint,
                                               const double *__restrict__ dform, const double *__restrict__ wmax,
-                                              const PoseForms pose, SceneDev sc, int npairs,
-                                              uint32_t *__restrict__ cnt, uint32_t *__restrict__ runs,
+                                              const PoseForms *__restrict__ poses, int ntiles, SceneDev sc,
+                                              int npairs, uint32_t *__restrict__ cnt, uint32_t *__restrict__ runs,
                                               unsigned long long *__restrict__ counters) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npairs) return;
-  const uint32_t tile = pkey[p];
+  const uint32_t tile = pkey[p];                 // list id: cell * ntiles + tile
+  const int cell = (int)(tile / (uint32_t)ntiles);
+  const PoseForms &pose = poses[cell];
+  const size_t gbase = (size_t)cell * sc.n;      // global index of the cell's Gaussian 0
   const int beg = (int)ranges[2 * tile], n = (int)ranges[2 * tile + 1] - beg;
   const int i = p - beg;
   const uint32_t *list = lists + beg;
@@ -120,7 +123,8 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
     if (dint[2 * (size_t)list[mid] + 1] < t2) a = mid + 1; else b = mid;
   }
   const int qe = a;
-  const double uwi[3] = {sc.mean[gi], sc.mean[sc.n + gi], sc.mean[2 * sc.n + gi]};
+  const size_t li = gi - gbase;
+  const double uwi[3] = {sc.mean[li], sc.mean[sc.n + li], sc.mean[2 * sc.n + li]};
   const double *dfi = dform + (size_t)gi * 2 * (kMaxP + 1);
   uint32_t *out_def = nullptr, *out_may = nullptr;
   if (EMIT) {
@@ -134,7 +138,8 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
     int ind = 0;
     if (j != i) {
       const uint32_t gj = list[j];
-      const double uwj[3] = {sc.mean[gj], sc.mean[sc.n + gj], sc.mean[2 * sc.n + gj]};
+      const size_t lj = gj - gbase;
+      const double uwj[3] = {sc.mean[lj], sc.mean[sc.n + lj], sc.mean[2 * sc.n + lj]};
       ind = ind_pair<P>(pose, uwi, uwj, dfi, dform + (size_t)gj * 2 * (kMaxP + 1));
     }
     const bool d1 = ind == 1, m1 = ind != 0;
@@ -193,14 +198,15 @@ __global__ __launch_bounds__(512) void k_raster_general(const double *__restrict
   double *red = smem + 2 * G * 64 + (G * 64 + 1) / 2; // [64][6(P+1)+4]
   const int lane = threadIdx.x & 63;
   const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int tile = blockIdx.x;
+  const int lst = blockIdx.x;                    // list id: cell * ntiles + tile
+  const int cell = lst / (prm.ntx * prm.nty), tile = lst % (prm.ntx * prm.nty);
   const int tx = tile % prm.ntx, ty = tile / prm.ntx;
   const int col = tx * kTile + (lane & 7), row = ty * kTile + (lane >> 3);
   const bool inimg = col < prm.width && row < prm.height;
   const double uxd = (double)col + 0.5 - prm.cx, uyd = (double)row + 0.5 - prm.cy;
   const float ux = (float)uxd, uy = (float)uyd;
-  const int beg = (int)ranges[2 * tile];
-  const int n = (int)ranges[2 * tile + 1] - beg;
+  const int beg = (int)ranges[2 * lst];
+  const int n = (int)ranges[2 * lst + 1] - beg;
   const uint32_t *list = lists + beg;
   const int s0 = (int)(((long long)g * n) / G), s1 = (int)(((long long)(g + 1) * n) / G);
 
@@ -297,7 +303,8 @@ __global__ __launch_bounds__(512) void k_raster_general(const double *__restrict
   for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
   if (lane == 0 && c) atomicAdd(&counters[0], c);
   if (g != 0 || !inimg) return;
-  write_pixel<P>(acc, (double)n, prm.E, 0.0, out_lo, out_hi, ((size_t)row * prm.width + col) * 3);
+  const size_t img = (size_t)cell * prm.width * prm.height;
+  write_pixel<P>(acc, (double)n, prm.E, 0.0, out_lo, out_hi, (img + (size_t)row * prm.width + col) * 3);
 }
 
 // ---------------------------------------------------------------------------------
@@ -307,55 +314,54 @@ hipError_t launch_tile_wmax(const Workspace &ws, const uint32_t *lists, int ntil
 }
 
 template <int P>
-static hipError_t launch_runs_p(const Workspace &ws, const uint32_t *lists, const PoseForms &pose, const SceneDev &sc,
-                                int npairs, bool emit, hipStream_t s) {
+static hipError_t launch_runs_p(const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
+                                const SceneDev &sc, int npairs, bool emit, hipStream_t s) {
   const dim3 grid((npairs + 255) / 256), block(256);
   if (emit)
     hipLaunchKernelGGL((k_runs<P, true>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint, ws.dform,
-                       ws.wmax, pose, sc, npairs, ws.run_cnt, ws.runs, ws.counters);
+                       ws.wmax, poses_dev, ntiles, sc, npairs, ws.run_cnt, ws.runs, ws.counters);
   else
     hipLaunchKernelGGL((k_runs<P, false>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint, ws.dform,
-                       ws.wmax, pose, sc, npairs, ws.run_cnt, ws.runs, ws.counters);
+                       ws.wmax, poses_dev, ntiles, sc, npairs, ws.run_cnt, ws.runs, ws.counters);
   return hipGetLastError();
 }
 
-hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms &pose, const SceneDev &sc,
-                       int npairs, bool emit, hipStream_t s) {
+hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
+                       const SceneDev &sc, int npairs, bool emit, hipStream_t s) {
   if (npairs <= 0) return hipSuccess;
   switch (P) {
-    case 0: return launch_runs_p<0>(ws, lists, pose, sc, npairs, emit, s);
-    case 1: return launch_runs_p<1>(ws, lists, pose, sc, npairs, emit, s);
-    case 2: return launch_runs_p<2>(ws, lists, pose, sc, npairs, emit, s);
-    case 3: return launch_runs_p<3>(ws, lists, pose, sc, npairs, emit, s);
-    case 4: return launch_runs_p<4>(ws, lists, pose, sc, npairs, emit, s);
-    case 5: return launch_runs_p<5>(ws, lists, pose, sc, npairs, emit, s);
-    case 6: return launch_runs_p<6>(ws, lists, pose, sc, npairs, emit, s);
+    case 0: return launch_runs_p<0>(ws, lists, poses_dev, ntiles, sc, npairs, emit, s);
+    case 1: return launch_runs_p<1>(ws, lists, poses_dev, ntiles, sc, npairs, emit, s);
+    case 2: return launch_runs_p<2>(ws, lists, poses_dev, ntiles, sc, npairs, emit, s);
+    case 3: return launch_runs_p<3>(ws, lists, poses_dev, ntiles, sc, npairs, emit, s);
+    case 4: return launch_runs_p<4>(ws, lists, poses_dev, ntiles, sc, npairs, emit, s);
+    case 5: return launch_runs_p<5>(ws, lists, poses_dev, ntiles, sc, npairs, emit, s);
+    case 6: return launch_runs_p<6>(ws, lists, poses_dev, ntiles, sc, npairs, emit, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <int P>
-static hipError_t launch_general_p(const Workspace &ws, const uint32_t *lists, const Params &prm, float *lo,
-                                   float *hi, hipStream_t s) {
-  const int ntiles = prm.ntx * prm.nty;
+static hipError_t launch_general_p(const Workspace &ws, const uint32_t *lists, int nlists, const Params &prm,
+                                   float *lo, float *hi, hipStream_t s) {
   const int G = prm.groups;
   constexpr int kRed = 6 * (P + 1) + 3 + 1;
   const size_t shm = sizeof(double) * (2 * G * 64 + (G * 64 + 1) / 2 + 64 * kRed);
-  hipLaunchKernelGGL(k_raster_general<P>, dim3(ntiles), dim3(64 * G), shm, s, ws.rec, ws.tile_range, lists,
+  hipLaunchKernelGGL(k_raster_general<P>, dim3(nlists), dim3(64 * G), shm, s, ws.rec, ws.tile_range, lists,
                      ws.run_cnt, ws.runs, prm, (double2 *)ws.pre, ws.prez, lo, hi, ws.counters);
   return hipGetLastError();
 }
 
-hipError_t launch_raster_general(int P, const Workspace &ws, const uint32_t *lists, const Params &prm, float *lo,
-                                 float *hi, hipStream_t s) {
+hipError_t launch_raster_general(int P, const Workspace &ws, const uint32_t *lists, int nlists, const Params &prm,
+                                 float *lo, float *hi, hipStream_t s) {
   switch (P) {
-    case 0: return launch_general_p<0>(ws, lists, prm, lo, hi, s);
-    case 1: return launch_general_p<1>(ws, lists, prm, lo, hi, s);
-    case 2: return launch_general_p<2>(ws, lists, prm, lo, hi, s);
-    case 3: return launch_general_p<3>(ws, lists, prm, lo, hi, s);
-    case 4: return launch_general_p<4>(ws, lists, prm, lo, hi, s);
-    case 5: return launch_general_p<5>(ws, lists, prm, lo, hi, s);
-    case 6: return launch_general_p<6>(ws, lists, prm, lo, hi, s);
+    case 0: return launch_general_p<0>(ws, lists, nlists, prm, lo, hi, s);
+    case 1: return launch_general_p<1>(ws, lists, nlists, prm, lo, hi, s);
+    case 2: return launch_general_p<2>(ws, lists, nlists, prm, lo, hi, s);
+    case 3: return launch_general_p<3>(ws, lists, nlists, prm, lo, hi, s);
+    case 4: return launch_general_p<4>(ws, lists, nlists, prm, lo, hi, s);
+    case 5: return launch_general_p<5>(ws, lists, nlists, prm, lo, hi, s);
+    case 6: return launch_general_p<6>(ws, lists, nlists, prm, lo, hi, s);
   }
   return hipErrorInvalidValue;
 }

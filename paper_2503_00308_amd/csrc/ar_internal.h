@@ -98,13 +98,17 @@ struct SceneDev {
 
 // Device workspace (grown on demand, owned by a scene handle).
 struct Workspace {
-  size_t cap_n = 0, cap_pairs = 0, cap_tiles = 0, cap_scratch = 0;
+  size_t cap_n = 0, cap_pairs = 0, cap_tiles = 0, cap_scratch = 0, cap_rec = 0, cap_cells = 0;
+  double pairs_per_item = 0.0;   // list entries per Gaussian item of the last launch
+  PoseForms *pose_dev = nullptr;   // [cells] pose forms of a launch
+  PoseForms *pose_host = nullptr;  // [cells] pinned staging
   double *rec = nullptr;       // [n][stride]
   uint64_t *key = nullptr;     // [n] depth key (by gid, kept for tie tests)
   uint64_t *key_sort = nullptr;  // [n] copy of the keys, sorted in place
   uint64_t *key_alt = nullptr; // [n]
   uint32_t *perm = nullptr;    // [n] rank -> gid
   uint32_t *perm_alt = nullptr;
+  uint32_t *cell_key = nullptr, *cell_key_alt = nullptr;  // [items] cell of an item (stable cell pass)
   int32_t *rect = nullptr;     // [n][4] tile rectangle
   double *dform = nullptr;     // [n][2][kMaxP+1] depth forms (FP64, by gid)
   uint32_t *count = nullptr;   // [n+1] tiles per Gaussian (rank order), then offsets
@@ -138,7 +142,10 @@ struct Workspace {
 
 // ---- launchers (ar_project.hip) ----
 int pose_forms_host(const ar_pose_box &box, int P, PoseForms &out);
-hipError_t launch_project(int P, const SceneDev &sc, const PoseForms &pose, const Params &prm,
+// one pose box (pose by value, poses_dev == nullptr) or ncells boxes (poses_dev[ncells]);
+// outputs at global index cell * n + g
+hipError_t launch_project(int P, const SceneDev &sc, const PoseForms &pose, const PoseForms *poses_dev, int ncells,
+                          const Params &prm,
                           Workspace &ws, hipStream_t s);
 // ---- sorting / scans (ar_sort.hip) ----
 hipError_t radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt, int n,
@@ -146,22 +153,27 @@ hipError_t radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, ui
 hipError_t radix_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, uint32_t *vals_alt, int n,
                           int begin_bit, int end_bit, Workspace &ws, hipStream_t s, bool *result_in_alt);
 hipError_t exclusive_scan_u32(uint32_t *data, int n, Workspace &ws, hipStream_t s);
+// keys[i] = items[i] / n_cell (cell of a global item)
+hipError_t launch_cell_keys(const uint32_t *items, int n_total, int n_cell, uint32_t *keys, hipStream_t s);
 hipError_t ensure_hist(Workspace &ws, size_t n_entries);
 // ---- binning and pixel loops (ar_raster.hip) ----
-hipError_t launch_count_tiles(int P, const Workspace &ws, int n, const Params &prm, hipStream_t s);
-hipError_t launch_emit_tiles(int P, const Workspace &ws, int n, const Params &prm, hipStream_t s);
+// items in depth-rank order perm[r] = cell * n_cell + gid; list id = cell * ntiles + tile
+hipError_t launch_count_tiles(int P, const Workspace &ws, int n_total, int n_cell, const Params &prm, hipStream_t s);
+hipError_t launch_emit_tiles(int P, const Workspace &ws, int n_total, int n_cell, const Params &prm, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t *keys, int npairs, uint32_t *ranges, int ntiles, hipStream_t s);
 int part_fields(int P);
-hipError_t launch_segments(const Workspace &ws, int ntiles, int L, hipStream_t s);
-hipError_t launch_segment_map(const Workspace &ws, int ntiles, hipStream_t s);
-// records ev[1] / ev[2] around the per-segment pixel kernel
-hipError_t launch_raster_translation(int P, const Workspace &ws, const uint32_t *lists, const Params &prm, int L,
-                                     int nseg_max, float *lo, float *hi, hipStream_t s);
+hipError_t launch_segments(const Workspace &ws, int nlists, int L, hipStream_t s);
+hipError_t launch_segment_map(const Workspace &ws, int nlists, hipStream_t s);
+// records ev[1] / ev[2] around the per-segment pixel kernel; lists cell * ntiles + tile,
+// images [cell][H][W][3]
+hipError_t launch_raster_translation(int P, const Workspace &ws, const uint32_t *lists, int nlists, const Params &prm,
+                                     int L, int nseg_max, float *lo, float *hi, hipStream_t s);
 // general path (ar_general.hip)
-hipError_t launch_tile_wmax(const Workspace &ws, const uint32_t *lists, int ntiles, hipStream_t s);
-hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms &pose, const SceneDev &sc,
-                       int npairs, bool emit, hipStream_t s);
-hipError_t launch_raster_general(int P, const Workspace &ws, const uint32_t *lists, const Params &prm, float *lo,
-                                 float *hi, hipStream_t s);
+hipError_t launch_tile_wmax(const Workspace &ws, const uint32_t *lists, int nlists, hipStream_t s);
+// poses_dev[cell] for list ids cell * ntiles + tile
+hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
+                       const SceneDev &sc, int npairs, bool emit, hipStream_t s);
+hipError_t launch_raster_general(int P, const Workspace &ws, const uint32_t *lists, int nlists, const Params &prm,
+                                 float *lo, float *hi, hipStream_t s);
 
 }  // namespace ar

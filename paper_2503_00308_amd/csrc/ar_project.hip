@@ -226,21 +226,21 @@ __device__ bool matrix_inv(const L64<P> &x00, const L64<P> &x01, const L64<P> &x
   return true;
 }
 
+// Per-Gaussian stage of Gaussian g of the scene under pose forms `pose`; outputs at
+// global index oi (cell * n + g when several cells are processed by one launch).
 template <int P>
-__global__ __launch_bounds__(64) void k_project(SceneDev sc, const PoseForms pose, Params prm,
-                                                double *__restrict__ rec_out, uint64_t *__restrict__ key_out,
-                                                uint64_t *__restrict__ key_sort, uint32_t *__restrict__ perm_out, int32_t *__restrict__ rect_out,
-                                                double *__restrict__ dform_out, double *__restrict__ dint_out,
-                                                unsigned long long *__restrict__ counters) {
+__device__ __forceinline__ void project_one(const SceneDev &sc, const PoseForms &pose, const Params &prm, int g,
+                                            size_t oi, double *__restrict__ rec_out, uint64_t *__restrict__ key_out,
+                                            uint64_t *__restrict__ key_sort, uint32_t *__restrict__ perm_out,
+                                            int32_t *__restrict__ rect_out, double *__restrict__ dform_out,
+                                            double *__restrict__ dint_out, unsigned long long *__restrict__ counters) {
   const int n = sc.n;
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
   const double uw[3] = {sc.mean[g], sc.mean[n + g], sc.mean[2 * n + g]};
   double Mw[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) Mw[i] = sc.cov[(size_t)i * n + g];
   const float o = sc.opac[g];
-  perm_out[g] = (uint32_t)g;
+  perm_out[oi] = (uint32_t)oi;
 
   // line 2: uc = Mmul(A, Add(uw, -tau)) + beta
   L64<P> y[3];
@@ -327,20 +327,20 @@ __global__ __launch_bounds__(64) void k_project(SceneDev sc, const PoseForms pos
 
   // depth key and depth forms (rank order, Ind)
   const uint64_t key = order_key(dropped ? INFINITY : dhi);
-  key_out[g] = key;
-  key_sort[g] = key;
-  double *df = dform_out + (size_t)g * 2 * (kMaxP + 1);
+  key_out[oi] = key;
+  key_sort[oi] = key;
+  double *df = dform_out + oi * 2 * (kMaxP + 1);
   for (int k = 0; k <= kMaxP; ++k) { df[k] = 0.0; df[kMaxP + 1 + k] = 0.0; }
   for (int k = 0; k < P; ++k) { df[k] = d.lo[k]; df[kMaxP + 1 + k] = d.up[k]; }
   df[kMaxP] = d.lo[P];
   df[2 * kMaxP + 1] = d.up[P];
-  dint_out[2 * (size_t)g] = dlo;
-  dint_out[2 * (size_t)g + 1] = dhi;
+  dint_out[2 * oi] = dlo;
+  dint_out[2 * oi + 1] = dhi;
 
   // record
   using R = Rec<P>;
   constexpr int F = R::F;
-  double *rec = rec_out + (size_t)g * R::STRIDE;
+  double *rec = rec_out + oi * R::STRIDE;
   store_mr<P>(rec + R::DM, rec + R::DR, D2);
   store_mr<P>(rec + R::PM, rec + R::PR, DUP0);
   store_mr<P>(rec + R::PM + F, rec + R::PR + F, DUP1);
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(64) void k_project(SceneDev sc, const PoseForms pos
   for (int j = R::CM + 24; j < R::STRIDE; ++j) rec[j] = 0.0;
 
   // tile rectangle (inclusive) for binning; empty when the Gaussian cannot contribute
-  int32_t *rc = rect_out + 4 * (size_t)g;
+  int32_t *rc = rect_out + 4 * oi;
   if (type == kWild) {
     rc[0] = 0; rc[1] = 0; rc[2] = prm.ntx - 1; rc[3] = prm.nty - 1;
   } else if (!geo || r2 < 0.0) {
@@ -408,6 +408,34 @@ __global__ __launch_bounds__(64) void k_project(SceneDev sc, const PoseForms pos
   }
 }
 
+// one pose box: pose forms by value (kernel arguments)
+template <int P>
+__global__ __launch_bounds__(64) void k_project(SceneDev sc, const PoseForms pose, Params prm,
+                                                double *__restrict__ rec_out, uint64_t *__restrict__ key_out,
+                                                uint64_t *__restrict__ key_sort, uint32_t *__restrict__ perm_out,
+                                                int32_t *__restrict__ rect_out, double *__restrict__ dform_out,
+                                                double *__restrict__ dint_out, unsigned long long *__restrict__ counters) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= sc.n) return;
+  project_one<P>(sc, pose, prm, g, (size_t)g, rec_out, key_out, key_sort, perm_out, rect_out, dform_out, dint_out,
+                 counters);
+}
+
+// several pose cells (grid.y): pose forms of cell c at poses[c] in device memory
+template <int P>
+__global__ __launch_bounds__(64) void k_project_cells(SceneDev sc, const PoseForms *__restrict__ poses, Params prm,
+                                                      double *__restrict__ rec_out, uint64_t *__restrict__ key_out,
+                                                      uint64_t *__restrict__ key_sort, uint32_t *__restrict__ perm_out,
+                                                      int32_t *__restrict__ rect_out, double *__restrict__ dform_out,
+                                                      double *__restrict__ dint_out,
+                                                      unsigned long long *__restrict__ counters) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= sc.n) return;
+  const int c = blockIdx.y;
+  project_one<P>(sc, poses[c], prm, g, (size_t)c * sc.n + g, rec_out, key_out, key_sort, perm_out, rect_out,
+                 dform_out, dint_out, counters);
+}
+
 // Pose forms on the host: O(1) work, passed to the kernels by value.
 int pose_forms_host(const ar_pose_box &box, int P, PoseForms &out) {
   switch (P) {
@@ -423,23 +451,28 @@ int pose_forms_host(const ar_pose_box &box, int P, PoseForms &out) {
 }
 
 template <int P>
-static hipError_t launch_project_p(const SceneDev &sc, const PoseForms &pose, const Params &prm, Workspace &ws,
-                                   hipStream_t s) {
-  hipLaunchKernelGGL(k_project<P>, dim3((sc.n + 63) / 64), dim3(64), 0, s, sc, pose, prm, ws.rec, ws.key, ws.key_sort,
-                     ws.perm, ws.rect, ws.dform, ws.dint, ws.counters);
+static hipError_t launch_project_p(const SceneDev &sc, const PoseForms &pose, const PoseForms *poses_dev, int ncells,
+                                   const Params &prm, Workspace &ws, hipStream_t s) {
+  if (poses_dev)
+    hipLaunchKernelGGL(k_project_cells<P>, dim3((sc.n + 63) / 64, ncells), dim3(64), 0, s, sc, poses_dev, prm, ws.rec,
+                       ws.key, ws.key_sort, ws.perm, ws.rect, ws.dform, ws.dint, ws.counters);
+  else
+    hipLaunchKernelGGL(k_project<P>, dim3((sc.n + 63) / 64), dim3(64), 0, s, sc, pose, prm, ws.rec, ws.key,
+                       ws.key_sort, ws.perm, ws.rect, ws.dform, ws.dint, ws.counters);
   return hipGetLastError();
 }
 
-hipError_t launch_project(int P, const SceneDev &sc, const PoseForms &pose, const Params &prm, Workspace &ws,
+hipError_t launch_project(int P, const SceneDev &sc, const PoseForms &pose, const PoseForms *poses_dev, int ncells,
+                          const Params &prm, Workspace &ws,
                           hipStream_t s) {
   switch (P) {
-    case 0: return launch_project_p<0>(sc, pose, prm, ws, s);
-    case 1: return launch_project_p<1>(sc, pose, prm, ws, s);
-    case 2: return launch_project_p<2>(sc, pose, prm, ws, s);
-    case 3: return launch_project_p<3>(sc, pose, prm, ws, s);
-    case 4: return launch_project_p<4>(sc, pose, prm, ws, s);
-    case 5: return launch_project_p<5>(sc, pose, prm, ws, s);
-    case 6: return launch_project_p<6>(sc, pose, prm, ws, s);
+    case 0: return launch_project_p<0>(sc, pose, poses_dev, ncells, prm, ws, s);
+    case 1: return launch_project_p<1>(sc, pose, poses_dev, ncells, prm, ws, s);
+    case 2: return launch_project_p<2>(sc, pose, poses_dev, ncells, prm, ws, s);
+    case 3: return launch_project_p<3>(sc, pose, poses_dev, ncells, prm, ws, s);
+    case 4: return launch_project_p<4>(sc, pose, poses_dev, ncells, prm, ws, s);
+    case 5: return launch_project_p<5>(sc, pose, poses_dev, ncells, prm, ws, s);
+    case 6: return launch_project_p<6>(sc, pose, poses_dev, ncells, prm, ws, s);
   }
   return hipErrorInvalidValue;
 }

@@ -52,18 +52,22 @@ __device__ __forceinline__ float tile_dist2(const float *mu, int tx, int ty, con
   return dist2_rect(mu, ux0, ux1, uy0, uy1);
 }
 
-// One wave per Gaussian (in depth-rank order): the lanes walk the tile rectangle 64
-// tiles at a time; a ballot gives each kept tile its slot.
+// Binning of global item r (depth-rank order; perm[r] = cell * n_cell + gid) to the lists
+// cell * ntiles + tile.  Small inputs: one wave per item, the lanes walk the tile
+// rectangle 64 tiles at a time and a ballot gives each kept tile its slot.  Large
+// inputs (many cells): one thread per item walking its rectangle.  Both emit an item's
+// tiles in row-major order at [counts[r], counts[r + 1]).
 template <int P, bool EMIT>
 __global__ __launch_bounds__(256) void k_bin(const double *__restrict__ recs, const int32_t *__restrict__ rect,
-                                             const uint32_t *__restrict__ perm, int n, Params prm,
+                                             const uint32_t *__restrict__ perm, int n_total, int n_cell, Params prm,
                                              uint32_t *__restrict__ counts, uint32_t *__restrict__ pkey,
                                              uint32_t *__restrict__ pval) {
   using R = Rec<P>;
   const int lane = threadIdx.x & 63;
   const int r = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
-  if (r >= n) return;
+  if (r >= n_total) return;
   const uint32_t gid = perm[r];
+  const uint32_t lbase = (gid / (uint32_t)n_cell) * (uint32_t)(prm.ntx * prm.nty);
   const double *rec = recs + (size_t)gid * R::STRIDE;
   const int type = rec_type<P>(rec);
   const int32_t *rc = rect + 4 * (size_t)gid;
@@ -82,13 +86,46 @@ __global__ __launch_bounds__(256) void k_bin(const double *__restrict__ recs, co
       const uint64_t bal = __ballot(keep);
       if (EMIT && keep) {
         const uint32_t pos = off + c + (uint32_t)__popcll(bal & below);
-        pkey[pos] = (uint32_t)(ty * prm.ntx + tx);
+        pkey[pos] = lbase + (uint32_t)(ty * prm.ntx + tx);
         pval[pos] = gid;
       }
       c += (uint32_t)__popcll(bal);
     }
   }
   if (!EMIT && lane == 0) counts[r] = c;
+}
+
+template <int P, bool EMIT>
+__global__ __launch_bounds__(256) void k_bin_thread(const double *__restrict__ recs, const int32_t *__restrict__ rect,
+                                                    const uint32_t *__restrict__ perm, int n_total, int n_cell,
+                                                    Params prm, uint32_t *__restrict__ counts,
+                                                    uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval) {
+  using R = Rec<P>;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_total) return;
+  const uint32_t gid = perm[r];
+  const uint32_t lbase = (gid / (uint32_t)n_cell) * (uint32_t)(prm.ntx * prm.nty);
+  const double *rec = recs + (size_t)gid * R::STRIDE;
+  const int type = rec_type<P>(rec);
+  const int32_t *rc = rect + 4 * (size_t)gid;
+  uint32_t c = 0;
+  const uint32_t off = EMIT ? counts[r] : 0u;
+  if (type != kDropped && rc[0] <= rc[2] && rc[1] <= rc[3]) {
+    const float *mu = rec_prune<P>(rec);
+    const float r2 = mu[4];
+    for (int ty = rc[1]; ty <= rc[3]; ++ty)
+      for (int tx = rc[0]; tx <= rc[2]; ++tx) {
+        const bool keep = (type == kWild) || (tile_dist2(mu, tx, ty, prm) <= r2);
+        if (keep) {
+          if (EMIT) {
+            pkey[off + c] = lbase + (uint32_t)(ty * prm.ntx + tx);
+            pval[off + c] = gid;
+          }
+          ++c;
+        }
+      }
+  }
+  if (!EMIT) counts[r] = c;
 }
 
 __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v) {
@@ -104,37 +141,51 @@ __global__ void k_tile_ranges(const uint32_t *__restrict__ keys, int npairs, uin
   if (p == npairs - 1 || keys[p + 1] != t) ranges[2 * t + 1] = (uint32_t)(p + 1);
 }
 
+constexpr int kBinWaveMax = 65536;   // up to this many items: one wave per item
+
 template <int P>
-static hipError_t launch_bin_p(const Workspace &ws, int n, const Params &prm, bool emit, hipStream_t s) {
-  const dim3 grid((unsigned)((n + 3) / 4));   // four waves (Gaussians) per block
-  if (emit)
-    hipLaunchKernelGGL((k_bin<P, true>), grid, dim3(256), 0, s, ws.rec, ws.rect, ws.perm, n, prm, ws.count,
-                       ws.pair_key, ws.pair_val);
-  else
-    hipLaunchKernelGGL((k_bin<P, false>), grid, dim3(256), 0, s, ws.rec, ws.rect, ws.perm, n, prm, ws.count,
-                       ws.pair_key, ws.pair_val);
+static hipError_t launch_bin_p(const Workspace &ws, int n_total, int n_cell, const Params &prm, bool emit,
+                               hipStream_t s) {
+  if (n_total <= kBinWaveMax) {
+    const dim3 grid((unsigned)((n_total + 3) / 4));   // four waves (items) per block
+    if (emit)
+      hipLaunchKernelGGL((k_bin<P, true>), grid, dim3(256), 0, s, ws.rec, ws.rect, ws.perm, n_total, n_cell, prm,
+                         ws.count, ws.pair_key, ws.pair_val);
+    else
+      hipLaunchKernelGGL((k_bin<P, false>), grid, dim3(256), 0, s, ws.rec, ws.rect, ws.perm, n_total, n_cell, prm,
+                         ws.count, ws.pair_key, ws.pair_val);
+  } else {
+    const dim3 grid((unsigned)((n_total + 255) / 256));
+    if (emit)
+      hipLaunchKernelGGL((k_bin_thread<P, true>), grid, dim3(256), 0, s, ws.rec, ws.rect, ws.perm, n_total, n_cell,
+                         prm, ws.count, ws.pair_key, ws.pair_val);
+    else
+      hipLaunchKernelGGL((k_bin_thread<P, false>), grid, dim3(256), 0, s, ws.rec, ws.rect, ws.perm, n_total, n_cell,
+                         prm, ws.count, ws.pair_key, ws.pair_val);
+  }
   return hipGetLastError();
 }
 
-static hipError_t launch_bin(int P, const Workspace &ws, int n, const Params &prm, bool emit, hipStream_t s) {
+static hipError_t launch_bin(int P, const Workspace &ws, int n_total, int n_cell, const Params &prm, bool emit,
+                             hipStream_t s) {
   switch (P) {
-    case 0: return launch_bin_p<0>(ws, n, prm, emit, s);
-    case 1: return launch_bin_p<1>(ws, n, prm, emit, s);
-    case 2: return launch_bin_p<2>(ws, n, prm, emit, s);
-    case 3: return launch_bin_p<3>(ws, n, prm, emit, s);
-    case 4: return launch_bin_p<4>(ws, n, prm, emit, s);
-    case 5: return launch_bin_p<5>(ws, n, prm, emit, s);
-    case 6: return launch_bin_p<6>(ws, n, prm, emit, s);
+    case 0: return launch_bin_p<0>(ws, n_total, n_cell, prm, emit, s);
+    case 1: return launch_bin_p<1>(ws, n_total, n_cell, prm, emit, s);
+    case 2: return launch_bin_p<2>(ws, n_total, n_cell, prm, emit, s);
+    case 3: return launch_bin_p<3>(ws, n_total, n_cell, prm, emit, s);
+    case 4: return launch_bin_p<4>(ws, n_total, n_cell, prm, emit, s);
+    case 5: return launch_bin_p<5>(ws, n_total, n_cell, prm, emit, s);
+    case 6: return launch_bin_p<6>(ws, n_total, n_cell, prm, emit, s);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_count_tiles(int P, const Workspace &ws, int n, const Params &prm, hipStream_t s) {
-  return launch_bin(P, ws, n, prm, false, s);
+hipError_t launch_count_tiles(int P, const Workspace &ws, int n_total, int n_cell, const Params &prm, hipStream_t s) {
+  return launch_bin(P, ws, n_total, n_cell, prm, false, s);
 }
 
-hipError_t launch_emit_tiles(int P, const Workspace &ws, int n, const Params &prm, hipStream_t s) {
-  return launch_bin(P, ws, n, prm, true, s);
+hipError_t launch_emit_tiles(int P, const Workspace &ws, int n_total, int n_cell, const Params &prm, hipStream_t s) {
+  return launch_bin(P, ws, n_total, n_cell, prm, true, s);
 }
 
 hipError_t launch_tile_ranges(const uint32_t *keys, int npairs, uint32_t *ranges, int ntiles, hipStream_t s) {
@@ -205,27 +256,28 @@ __global__ __launch_bounds__(256) void k_raster_seg(const double *__restrict__ r
                                                     const uint32_t *__restrict__ ranges,
                                                     const uint32_t *__restrict__ lists,
                                                     const uint32_t *__restrict__ seg_off,
-                                                    const uint32_t *__restrict__ seg_tile, int L, Params prm,
-                                                    double *__restrict__ part) {
+                                                    const uint32_t *__restrict__ seg_tile, int L, int nlists,
+                                                    Params prm, double *__restrict__ part) {
   using R = Rec<P>;
   using Q = Part<P>;
   constexpr int F = P + 1;
   const int lane = threadIdx.x & 63;
   const int ntiles = prm.ntx * prm.nty;
   const int s = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
-  if (s >= (int)seg_off[ntiles]) return;
-  const int tile = (int)seg_tile[s];
-  const int i = s - (int)seg_off[tile];
+  if (s >= (int)seg_off[nlists]) return;
+  const int list = (int)seg_tile[s];           // cell * ntiles + tile
+  const int i = s - (int)seg_off[list];
+  const int tile = list % ntiles;
   const int tx = tile % prm.ntx, ty = tile / prm.ntx;
   const int col = tx * kTile + (lane & 7), row = ty * kTile + (lane >> 3);
   const bool inimg = col < prm.width && row < prm.height;
   const double uxd = (double)col + 0.5 - prm.cx, uyd = (double)row + 0.5 - prm.cy;
   const float ux = (float)uxd, uy = (float)uyd;
-  const int beg = (int)ranges[2 * tile];
-  const int n = (int)ranges[2 * tile + 1] - beg;
-  const uint32_t *list = lists + beg;
-  const int p0 = cut_at(list, keys, n, i * L);
-  const int p1 = cut_at(list, keys, n, (i + 1) * L);
+  const int beg = (int)ranges[2 * list];
+  const int n = (int)ranges[2 * list + 1] - beg;
+  const uint32_t *items = lists + beg;
+  const int p0 = cut_at(items, keys, n, i * L);
+  const int p1 = cut_at(items, keys, n, (i + 1) * L);
 
   Acc<P> acc;
   acc_zero<P>(acc);
@@ -235,7 +287,7 @@ __global__ __launch_bounds__(256) void k_raster_seg(const double *__restrict__ r
   bool stop = false;
   unsigned npairs = 0;
   for (int p = p0; p < p1; ++p) {
-    const uint32_t gid = list[p];
+    const uint32_t gid = items[p];
     const double *rec = recs + (size_t)gid * R::STRIDE;
     const uint64_t key = keys[gid];
     if (key != prev_key) {
@@ -297,77 +349,101 @@ __global__ __launch_bounds__(192) void k_merge(const uint32_t *__restrict__ rang
   const int lane = threadIdx.x & 63;
   const int c = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // colour channel
   const int ntiles = prm.ntx * prm.nty;
-  const int tile = (int)blockIdx.x;
-  if (tile >= ntiles) return;
+  const int list = (int)blockIdx.x;            // cell * ntiles + tile
+  const int cell = list / ntiles, tile = list % ntiles;
   const int tx = tile % prm.ntx, ty = tile / prm.ntx;
   const int col = tx * kTile + (lane & 7), row = ty * kTile + (lane >> 3);
   const bool inimg = col < prm.width && row < prm.height;
-  const int s0 = (int)seg_off[tile], s1 = (int)seg_off[tile + 1];
+  const int s0 = (int)seg_off[list], s1 = (int)seg_off[list + 1];
   double lo[F], hi[F], ihi = 0.0;
 #pragma unroll
   for (int j = 0; j < F; ++j) { lo[j] = 0.0; hi[j] = 0.0; }
   float magl = 0.0f, magh = 0.0f;
   double T_lo = 1.0, T_hi = 1.0, extra = 0.0;
   unsigned long long cnt = 0;
-  for (int s = s0; s < s1; ++s) {
-    const double *q = part + (size_t)s * Q::NF * 64 + lane;
+  // segments are read kGroup at a time (loads of the group issued together), then combined
+  constexpr int kGroup = 4;
+  for (int sb = s0; sb < s1; sb += kGroup) {
+    double vlo[kGroup][F], vhi[kGroup][F], vih[kGroup], tlo[kGroup], thi[kGroup], stp[kGroup], cn[kGroup];
+    float2 mg[kGroup];
 #pragma unroll
-    for (int j = 0; j < F; ++j) {
-      lo[j] = fma(T_lo, q[(Q::LO + c * F + j) * 64], lo[j]);
-      hi[j] = fma(T_hi, q[(Q::HI + c * F + j) * 64], hi[j]);
+    for (int u = 0; u < kGroup; ++u) {
+      const int s = min(sb + u, s1 - 1);
+      const double *q = part + (size_t)s * Q::NF * 64 + lane;
+#pragma unroll
+      for (int j = 0; j < F; ++j) {
+        vlo[u][j] = q[(Q::LO + c * F + j) * 64];
+        vhi[u][j] = q[(Q::HI + c * F + j) * 64];
+      }
+      vih[u] = q[(Q::IHI + c) * 64];
+      mg[u] = __builtin_bit_cast(float2, q[Q::MAG * 64]);
+      tlo[u] = q[Q::TLO * 64];
+      thi[u] = q[Q::THI * 64];
+      stp[u] = q[Q::STOP * 64];
+      cn[u] = q[Q::CNT * 64];
     }
-    ihi = fma(T_hi, q[(Q::IHI + c) * 64], ihi);
-    const float2 mg = __builtin_bit_cast(float2, q[Q::MAG * 64]);
-    magl = fmaf((float)T_lo, mg.x, magl) * (1.0f + 4.0f * kU32);
-    magh = fmaf((float)T_hi, mg.y, magh) * (1.0f + 4.0f * kU32);
-    cnt += (unsigned long long)q[Q::CNT * 64];
-    const double t_lo = q[Q::TLO * 64], t_hi = q[Q::THI * 64];
-    if (q[Q::STOP * 64] != 0.0) {
-      extra = T_hi * t_hi * (1.0 + 0x1p-50);
-      break;
+    bool stopped = false;
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      if (sb + u >= s1 || stopped) break;
+#pragma unroll
+      for (int j = 0; j < F; ++j) {
+        lo[j] = fma(T_lo, vlo[u][j], lo[j]);
+        hi[j] = fma(T_hi, vhi[u][j], hi[j]);
+      }
+      ihi = fma(T_hi, vih[u], ihi);
+      magl = fmaf((float)T_lo, mg[u].x, magl) * (1.0f + 4.0f * kU32);
+      magh = fmaf((float)T_hi, mg[u].y, magh) * (1.0f + 4.0f * kU32);
+      cnt += (unsigned long long)cn[u];
+      if (stp[u] != 0.0) {
+        extra = T_hi * thi[u] * (1.0 + 0x1p-50);
+        stopped = true;
+        break;
+      }
+      T_lo *= tlo[u];
+      T_hi *= thi[u];
     }
-    T_lo *= t_lo;
-    T_hi *= t_hi;
+    if (stopped) break;
   }
   if (c == 0 && lane == 0 && cnt) atomicAdd(&counters[0], cnt);
   if (!inimg) return;
-  const int n = (int)(ranges[2 * tile + 1] - ranges[2 * tile]);
+  const int n = (int)(ranges[2 * list + 1] - ranges[2 * list]);
+  const size_t img = (size_t)cell * prm.width * prm.height;
   write_channel<P>(lo, hi, ihi, magl, magh, (double)(n + 2 * (s1 - s0)), prm.E, extra, out_lo, out_hi,
-                   ((size_t)row * prm.width + col) * 3 + c);
+                   ((img + (size_t)row * prm.width + col) * 3 + c));
 }
 
 template <int P>
-static hipError_t launch_trans_p(const Workspace &ws, const uint32_t *lists, const Params &prm, int L, int nseg_max,
-                                 float *lo, float *hi, hipStream_t s) {
-  const int ntiles = prm.ntx * prm.nty;
+static hipError_t launch_trans_p(const Workspace &ws, const uint32_t *lists, int nlists, const Params &prm, int L,
+                                 int nseg_max, float *lo, float *hi, hipStream_t s) {
   HIP_RET(hipEventRecord(ws.ev[1], s));
   if (nseg_max > 0)
     hipLaunchKernelGGL(k_raster_seg<P>, dim3((nseg_max + 3) / 4), dim3(256), 0, s, ws.rec, ws.key, ws.tile_range,
-                       lists, ws.seg_off, ws.seg_tile, L, prm, ws.part);
+                       lists, ws.seg_off, ws.seg_tile, L, nlists, prm, ws.part);
   HIP_RET(hipEventRecord(ws.ev[2], s));
-  hipLaunchKernelGGL(k_merge<P>, dim3(ntiles), dim3(192), 0, s, ws.tile_range, ws.seg_off, ws.part, prm, lo, hi,
+  hipLaunchKernelGGL(k_merge<P>, dim3(nlists), dim3(192), 0, s, ws.tile_range, ws.seg_off, ws.part, prm, lo, hi,
                      ws.counters);
   return hipGetLastError();
 }
 
-hipError_t launch_segments(const Workspace &ws, int ntiles, int L, hipStream_t s) {
-  hipLaunchKernelGGL(k_seg_count, dim3((ntiles + 1 + 255) / 256), dim3(256), 0, s, ws.tile_range, ntiles, L,
+hipError_t launch_segments(const Workspace &ws, int nlists, int L, hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_count, dim3((nlists + 1 + 255) / 256), dim3(256), 0, s, ws.tile_range, nlists, L,
                      ws.seg_off);
   return hipGetLastError();
 }
 
-hipError_t launch_segment_map(const Workspace &ws, int ntiles, hipStream_t s) {
-  hipLaunchKernelGGL(k_seg_map, dim3((ntiles + 255) / 256), dim3(256), 0, s, ws.seg_off, ntiles, ws.seg_tile);
+hipError_t launch_segment_map(const Workspace &ws, int nlists, hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_map, dim3((nlists + 255) / 256), dim3(256), 0, s, ws.seg_off, nlists, ws.seg_tile);
   return hipGetLastError();
 }
 
-hipError_t launch_raster_translation(int P, const Workspace &ws, const uint32_t *lists, const Params &prm, int L,
-                                     int nseg_max, float *lo, float *hi, hipStream_t s) {
+hipError_t launch_raster_translation(int P, const Workspace &ws, const uint32_t *lists, int nlists, const Params &prm,
+                                     int L, int nseg_max, float *lo, float *hi, hipStream_t s) {
   switch (P) {
-    case 0: return launch_trans_p<0>(ws, lists, prm, L, nseg_max, lo, hi, s);
-    case 1: return launch_trans_p<1>(ws, lists, prm, L, nseg_max, lo, hi, s);
-    case 2: return launch_trans_p<2>(ws, lists, prm, L, nseg_max, lo, hi, s);
-    case 3: return launch_trans_p<3>(ws, lists, prm, L, nseg_max, lo, hi, s);
+    case 0: return launch_trans_p<0>(ws, lists, nlists, prm, L, nseg_max, lo, hi, s);
+    case 1: return launch_trans_p<1>(ws, lists, nlists, prm, L, nseg_max, lo, hi, s);
+    case 2: return launch_trans_p<2>(ws, lists, nlists, prm, L, nseg_max, lo, hi, s);
+    case 3: return launch_trans_p<3>(ws, lists, nlists, prm, L, nseg_max, lo, hi, s);
   }
   return hipErrorInvalidValue;
 }

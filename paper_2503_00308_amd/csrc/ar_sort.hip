@@ -317,6 +317,17 @@ __global__ void k_zero_n(uint32_t *__restrict__ p, int n) {
   if (i < n) p[i] = 0u;
 }
 
+__global__ void k_cell_keys(const uint32_t *__restrict__ items, int n_total, uint32_t n_cell,
+                            uint32_t *__restrict__ keys) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_total) keys[i] = items[i] / n_cell;
+}
+
+hipError_t launch_cell_keys(const uint32_t *items, int n_total, int n_cell, uint32_t *keys, hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_keys, dim3((n_total + 255) / 256), dim3(256), 0, s, items, n_total, (uint32_t)n_cell, keys);
+  return hipGetLastError();
+}
+
 template <typename K>
 static hipError_t radix_sort(K *keys, K *keys_alt, uint32_t *vals, uint32_t *vals_alt, int n, int begin_bit,
                              int end_bit, Workspace &ws, hipStream_t s, bool *in_alt) {
