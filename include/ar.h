@@ -47,7 +47,8 @@ enum {
   AR_E_OOM = -2,         /* device memory could not be allocated */
   AR_E_DEVICE = -3,      /* a HIP runtime call failed */
   AR_E_UNSUPPORTED = -4, /* a valid request this build does not handle */
-  AR_E_BUDGET = -5       /* a server request does not fit the memory budget */
+  AR_E_BUDGET = -5,      /* a server request does not fit the memory budget */
+  AR_PENDING = 1         /* ar_server_wait without blocking: the query has not finished */
 };
 
 enum { AR_POSE_CAMERA6 = 0, AR_POSE_ORBIT = 1 };
@@ -168,8 +169,11 @@ int ar_render_bounds(const ar_scene *scene, const ar_intrinsics *intr, const ar_
 
 /*
  * Bounds for ncells pose boxes of one scene (the partition of a larger set of poses,
- * Sec. 4.2 "#part"); lo_rgb / hi_rgb hold ncells images back to back.  Equivalent to
- * ncells calls of ar_render_bounds; stats (may be NULL) accumulates over the cells.
+ * Sec. 4.2 "#part"); lo_rgb / hi_rgb hold ncells images back to back.  The result is
+ * that of ncells calls of ar_render_bounds (bit for bit when opts->chunk is set);
+ * consecutive cells with the same pose variables share one launch per stage, up to
+ * opts->cells_per_launch cells (default: what fits a quarter of the free device
+ * memory).  stats (may be NULL) accumulates over the cells.
  */
 int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *cells,
                     int32_t ncells, const ar_options *opts, float *lo_rgb, float *hi_rgb,
@@ -180,6 +184,70 @@ const char *ar_last_error(void);
 
 /* Library version string. */
 const char *ar_version(void);
+
+/*
+ * Query server: abstract-render queries over resident scenes with continuous batching.
+ * A server owns `slots` HIP streams (default priority), each with its own workspace and
+ * host worker thread.  Queries are taken in submission order; the next query starts as
+ * soon as a slot is free and its estimated workspace fits the device-memory budget next
+ * to the workspaces of the queries in flight, so queries of different scenes, image
+ * sizes and boxes run on the device at the same time.  A query's result is the same as
+ * ar_render_bounds on the same arguments (same kernels, its own workspace).
+ *
+ * hbm_budget  device bytes all slot workspaces may hold (0: a quarter of the free memory
+ *             at creation); scenes are not counted.  A query whose estimate exceeds the
+ *             budget on its own runs when no other query is in flight.
+ * slots       queries in flight at once, 1..16 (0: 4).
+ */
+typedef struct ar_server ar_server;
+
+typedef struct {
+  uint64_t hbm_budget;
+  int32_t slots;
+  int32_t reserved;
+} ar_server_config;
+
+typedef struct {
+  int32_t status;        /* AR_OK, AR_PENDING, or the AR_E_* code of a failed query */
+  int32_t slot;          /* slot (stream) the query ran on */
+  double queue_ms;       /* submission -> start on a slot (host clock) */
+  double latency_ms;     /* submission -> outputs complete (host clock) */
+  ar_stats stats;
+  char error[256];       /* message of a failed query */
+} ar_query_result;
+
+typedef struct {
+  int64_t submitted, completed, failed;
+  int32_t slots, peak_inflight;
+  double p50_ms, p99_ms, mean_ms;   /* latency of the completed queries */
+  double busy_s;                    /* host time with at least one query in flight */
+  uint64_t hbm_budget, peak_bytes;  /* budget and peak workspace bytes held */
+  int64_t pairs;                    /* evaluated (pixel, Gaussian) pairs, all queries */
+} ar_server_stats;
+
+/* cfg may be NULL (defaults).  *out receives the handle. */
+int ar_server_create(const ar_server_config *cfg, ar_server **out);
+
+/* Waits for every submitted query, then frees the streams and workspaces. */
+void ar_server_destroy(ar_server *srv);
+
+/* Registers a scene (not copied; it must outlive the server and not be destroyed while
+ * queries on it run).  *scene_id receives its index. */
+int ar_server_add_scene(ar_server *srv, const ar_scene *scene, int32_t *scene_id);
+
+/* Queues one query (arguments as ar_render_bounds; the structs are copied, the output
+ * device buffers must stay valid until the query completes).  *ticket receives its id.
+ * Invalid arguments are rejected here; errors while running are reported by wait. */
+int ar_server_submit(ar_server *srv, int32_t scene_id, const ar_intrinsics *intr, const ar_pose_box *box,
+                     const ar_options *opts, float *lo_rgb, float *hi_rgb, int64_t *ticket);
+
+/* Result of a query.  block != 0 waits for it; block == 0 returns AR_PENDING in
+ * out->status (and as the return value) while it is queued or running.  A finished
+ * query's record is released by the first wait that returns it. */
+int ar_server_wait(ar_server *srv, int64_t ticket, int32_t block, ar_query_result *out);
+
+/* Latency percentiles and counters over the server's life so far. */
+int ar_server_report(ar_server *srv, ar_server_stats *out);
 
 #ifdef __cplusplus
 }

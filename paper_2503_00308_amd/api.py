@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libabstract_render.so")
 
 AR_OK, AR_E_INVALID, AR_E_OOM, AR_E_DEVICE, AR_E_UNSUPPORTED, AR_E_BUDGET = 0, -1, -2, -3, -4, -5
+AR_PENDING = 1
 AR_POSE_CAMERA6, AR_POSE_ORBIT = 0, 1
 
 
@@ -59,6 +60,26 @@ class Stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class QueryResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("slot", ctypes.c_int32), ("queue_ms", ctypes.c_double),
+                ("latency_ms", ctypes.c_double), ("stats", Stats), ("error", ctypes.c_char * 256)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("slots", ctypes.c_int32), ("peak_inflight", ctypes.c_int32),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("busy_s", ctypes.c_double), ("hbm_budget", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
+                ("pairs", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 # the exported C symbols and their signatures (the same list as include/ar.h)
 SYMBOLS = {
     "ar_scene_create": (ctypes.c_int, [ctypes.POINTER(SceneDesc), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
@@ -72,6 +93,14 @@ SYMBOLS = {
                                        ctypes.c_void_p, ctypes.POINTER(Stats)]),
     "ar_last_error": (ctypes.c_char_p, []),
     "ar_version": (ctypes.c_char_p, []),
+    "ar_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]),
+    "ar_server_destroy": (None, [ctypes.c_void_p]),
+    "ar_server_add_scene": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "ar_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Intrinsics),
+                                        ctypes.POINTER(PoseBox), ctypes.POINTER(Options), ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "ar_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(QueryResult)]),
+    "ar_server_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
 }
 
 _lib = None
@@ -198,3 +227,69 @@ def render_batch(scene: Scene, intr, cells, opts=None, stream=None):
                                ctypes.c_void_p(lo.data_ptr()), ctypes.c_void_p(hi.data_ptr()),
                                _stream_ptr(stream), ctypes.byref(st)))
     return lo, hi, st.as_dict()
+
+
+class Server:
+    """Query server over resident scenes (continuous batching; see include/ar.h).
+
+    submit() allocates the two output tensors with torch and keeps them until wait()
+    returns them; the server writes them from its own streams."""
+
+    def __init__(self, slots: int = 0, hbm_budget: int = 0):
+        lib = load()
+        self.handle = ctypes.c_void_p()
+        cfg = ServerConfig(int(hbm_budget), int(slots), 0)
+        _check(lib.ar_server_create(ctypes.byref(cfg), ctypes.byref(self.handle)))
+        self._scenes = []
+        self._out = {}
+
+    def add_scene(self, scene: "Scene") -> int:
+        sid = ctypes.c_int32()
+        _check(load().ar_server_add_scene(self.handle, scene.handle, ctypes.byref(sid)))
+        self._scenes.append(scene)
+        return sid.value
+
+    def submit(self, scene_id: int, intr, box, opts=None) -> int:
+        import torch
+        ci = intrinsics(intr)
+        lo = torch.empty((ci.height, ci.width, 3), dtype=torch.float32, device="cuda")
+        hi = torch.empty_like(lo)
+        torch.cuda.synchronize()   # the buffers exist before another stream writes them
+        t = ctypes.c_int64()
+        b = pose_box(box)
+        co = options(opts)
+        _check(load().ar_server_submit(self.handle, int(scene_id), ctypes.byref(ci), ctypes.byref(b),
+                                       ctypes.byref(co), ctypes.c_void_p(lo.data_ptr()),
+                                       ctypes.c_void_p(hi.data_ptr()), ctypes.byref(t)))
+        self._out[t.value] = (lo, hi)
+        return t.value
+
+    def wait(self, ticket: int, block: bool = True):
+        """(lo, hi, result dict) of a finished query, or None while it runs (block=False)."""
+        r = QueryResult()
+        code = load().ar_server_wait(self.handle, int(ticket), 1 if block else 0, ctypes.byref(r))
+        if code == AR_PENDING:
+            return None
+        bufs = self._out.pop(ticket, None)
+        _check(code)
+        lo, hi = bufs
+        res = {"status": r.status, "slot": r.slot, "queue_ms": r.queue_ms, "latency_ms": r.latency_ms,
+               "stats": r.stats.as_dict()}
+        return lo, hi, res
+
+    def report(self) -> dict:
+        st = ServerStats()
+        _check(load().ar_server_report(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self.handle:
+            load().ar_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+            self._out.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -17,13 +17,14 @@
 #include <string>
 #include <vector>
 
-#include "ar_internal.h"
+#include "ar_host.h"
 
-namespace {
+using ar::fail;
+
+namespace ar {
 
 thread_local std::string g_error;
 
-int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char *fmt, ...) {
   char buf[512];
   va_list ap;
@@ -34,30 +35,16 @@ int fail(int code, const char *fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                                              \
-  do {                                                                                             \
-    hipError_t e_ = (expr);                                                                        \
-    if (e_ == hipErrorOutOfMemory) return fail(AR_E_OOM, "%s: out of device memory", #expr);      \
-    if (e_ != hipSuccess) return fail(AR_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
-
-template <typename T>
-hipError_t grow(T *&p, size_t need) {
-  if (p) {
-    hipError_t e = hipFree(p);
-    if (e != hipSuccess) return e;
-    p = nullptr;
-  }
-  return hipMalloc((void **)&p, std::max(need, (size_t)64) * sizeof(T));
+void release_workspace(Workspace &ws) {
+  for (auto &kv : ws.sizes) (void)hipFree(kv.first);
+  if (ws.host_counters) (void)hipHostFree(ws.host_counters);
+  if (ws.pose_host) (void)hipHostFree(ws.pose_host);
+  for (int i = 0; i < 4; ++i)
+    if (ws.ev[i]) (void)hipEventDestroy(ws.ev[i]);
+  ws = Workspace{};
 }
 
-}  // namespace
-
-struct ar_scene {
-  ar::SceneDev dev{};
-  ar::Workspace ws{};
-  float *base = nullptr;  // one allocation holding the scene arrays
-};
+}  // namespace ar
 
 namespace ar {
 
@@ -72,7 +59,7 @@ static bool finite_box(const ar_pose_box *b) {
 }
 
 // number of pose variables; *rotates: the depth order may change inside the box
-static int pose_vars(const ar_pose_box *b, bool *rotates) {
+int pose_vars(const ar_pose_box *b, bool *rotates) {
   if (b->model == AR_POSE_ORBIT) {
     *rotates = b->hi[0] > b->lo[0];
     return *rotates ? 1 : 0;
@@ -83,7 +70,7 @@ static int pose_vars(const ar_pose_box *b, bool *rotates) {
   return P;
 }
 
-static int validate_box(const ar_pose_box *b) {
+int validate_box(const ar_pose_box *b) {
   if (!b) return fail(AR_E_INVALID, "pose box is NULL");
   if (b->model != AR_POSE_CAMERA6 && b->model != AR_POSE_ORBIT)
     return fail(AR_E_INVALID, "unknown pose model %d", b->model);
@@ -98,7 +85,7 @@ static int validate_box(const ar_pose_box *b) {
   return AR_OK;
 }
 
-static int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *op, Params &prm) {
+int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *op, Params &prm) {
   if (!in) return fail(AR_E_INVALID, "intrinsics are NULL");
   if (in->width < 1 || in->height < 1 || in->width > 16384 || in->height > 16384)
     return fail(AR_E_INVALID, "image size %dx%d outside [1, 16384]", in->width, in->height);
@@ -147,28 +134,28 @@ static int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_opt
 static int ensure_ws(Workspace &ws, size_t n_total, size_t nlists, int P, int ncells) {
   if (n_total > ws.cap_n || !ws.key) {
     const size_t c = n_total + 64;
-    HIP_TRY(grow(ws.key, c));
-    HIP_TRY(grow(ws.key_sort, c));
-    HIP_TRY(grow(ws.key_alt, c));
-    HIP_TRY(grow(ws.perm, c));
-    HIP_TRY(grow(ws.perm_alt, c));
-    HIP_TRY(grow(ws.cell_key, c));
-    HIP_TRY(grow(ws.cell_key_alt, c));
-    HIP_TRY(grow(ws.rect, 4 * c));
-    HIP_TRY(grow(ws.dform, 2 * (kMaxP + 1) * c));
-    HIP_TRY(grow(ws.count, c + 1));
-    HIP_TRY(grow(ws.dint, 2 * c));
+    HIP_TRY(grow(ws, ws.key, c));
+    HIP_TRY(grow(ws, ws.key_sort, c));
+    HIP_TRY(grow(ws, ws.key_alt, c));
+    HIP_TRY(grow(ws, ws.perm, c));
+    HIP_TRY(grow(ws, ws.perm_alt, c));
+    HIP_TRY(grow(ws, ws.cell_key, c));
+    HIP_TRY(grow(ws, ws.cell_key_alt, c));
+    HIP_TRY(grow(ws, ws.rect, 4 * c));
+    HIP_TRY(grow(ws, ws.dform, 2 * (kMaxP + 1) * c));
+    HIP_TRY(grow(ws, ws.count, c + 1));
+    HIP_TRY(grow(ws, ws.dint, 2 * c));
     ws.cap_n = n_total;
   }
   const size_t rec_doubles = n_total * (size_t)rec_stride(P);
   if (rec_doubles > ws.cap_rec || !ws.rec) {
     const size_t c = rec_doubles + 64 * (size_t)rec_stride(kMaxP);
-    HIP_TRY(grow(ws.rec, c));
+    HIP_TRY(grow(ws, ws.rec, c));
     ws.cap_rec = c;
   }
   if (nlists > ws.cap_tiles || !ws.tile_range) {
-    HIP_TRY(grow(ws.tile_range, 2 * nlists + 2));
-    HIP_TRY(grow(ws.wmax, nlists + 2));
+    HIP_TRY(grow(ws, ws.tile_range, 2 * nlists + 2));
+    HIP_TRY(grow(ws, ws.wmax, nlists + 2));
     ws.cap_tiles = nlists;
   }
   if ((size_t)ncells > ws.cap_cells || !ws.pose_dev) {
@@ -176,12 +163,12 @@ static int ensure_ws(Workspace &ws, size_t n_total, size_t nlists, int P, int nc
       HIP_TRY(hipHostFree(ws.pose_host));
       ws.pose_host = nullptr;
     }
-    HIP_TRY(grow(ws.pose_dev, (size_t)ncells));
+    HIP_TRY(grow(ws, ws.pose_dev, (size_t)ncells));
     HIP_TRY(hipHostMalloc((void **)&ws.pose_host, (size_t)ncells * sizeof(PoseForms), hipHostMallocDefault));
     ws.cap_cells = (size_t)ncells;
   }
   if (!ws.counters) {
-    HIP_TRY(hipMalloc((void **)&ws.counters, 8 * sizeof(unsigned long long)));
+    HIP_TRY(grow(ws, ws.counters, 8));
     HIP_TRY(hipHostMalloc((void **)&ws.host_counters, 16 * sizeof(unsigned long long), hipHostMallocDefault));
     for (int i = 0; i < 4; ++i) HIP_TRY(hipEventCreate(&ws.ev[i]));
   }
@@ -192,13 +179,13 @@ static int ensure_ws(Workspace &ws, size_t n_total, size_t nlists, int P, int nc
 static int ensure_general(Workspace &ws, size_t npairs) {
   if (2 * npairs + 1 > ws.cap_run_cnt || !ws.run_cnt) {
     const size_t need = 2 * npairs + 1 + npairs / 2 + 1024;
-    HIP_TRY(grow(ws.run_cnt, need));
+    HIP_TRY(grow(ws, ws.run_cnt, need));
     ws.cap_run_cnt = need;
   }
   if (npairs > ws.cap_pre || !ws.pre) {
     const size_t need = npairs + npairs / 4 + 64;
-    HIP_TRY(grow(ws.pre, need * kTilePix * 2));
-    HIP_TRY(grow(ws.prez, need * kTilePix));
+    HIP_TRY(grow(ws, ws.pre, need * kTilePix * 2));
+    HIP_TRY(grow(ws, ws.prez, need * kTilePix));
     ws.cap_pre = need;
   }
   return AR_OK;
@@ -207,7 +194,7 @@ static int ensure_general(Workspace &ws, size_t npairs) {
 static int ensure_runs(Workspace &ws, size_t nruns) {
   if (nruns <= ws.cap_runs && ws.runs) return AR_OK;
   const size_t need = nruns + nruns / 4 + 1024;
-  HIP_TRY(grow(ws.runs, 2 * need));
+  HIP_TRY(grow(ws, ws.runs, 2 * need));
   ws.cap_runs = need;
   return AR_OK;
 }
@@ -215,18 +202,18 @@ static int ensure_runs(Workspace &ws, size_t nruns) {
 // translation path: segment table and partial results for up to nseg segments
 static int ensure_segments(Workspace &ws, size_t ntiles, size_t nseg, int P) {
   if (ntiles + 2 > ws.cap_seg_off || !ws.seg_off) {
-    HIP_TRY(grow(ws.seg_off, ntiles + 2));
+    HIP_TRY(grow(ws, ws.seg_off, ntiles + 2));
     ws.cap_seg_off = ntiles + 2;
   }
   if (nseg > ws.cap_seg || !ws.seg_tile) {
     const size_t need = nseg + nseg / 4 + 1024;
-    HIP_TRY(grow(ws.seg_tile, need));
+    HIP_TRY(grow(ws, ws.seg_tile, need));
     ws.cap_seg = need;
   }
   const size_t doubles = nseg * (size_t)part_fields(P) * kTilePix;
   if (doubles > ws.cap_part || !ws.part) {
     const size_t need = doubles + doubles / 4 + 4096;
-    HIP_TRY(grow(ws.part, need));
+    HIP_TRY(grow(ws, ws.part, need));
     ws.cap_part = need;
   }
   return AR_OK;
@@ -247,10 +234,10 @@ static int segment_length(const Params &prm, size_t npairs) {
 static int ensure_pairs(Workspace &ws, size_t npairs) {
   if (npairs <= ws.cap_pairs && ws.pair_key) return AR_OK;
   const size_t need = std::max(npairs + npairs / 4, (size_t)4096);
-  HIP_TRY(grow(ws.pair_key, need));
-  HIP_TRY(grow(ws.pair_key_alt, need));
-  HIP_TRY(grow(ws.pair_val, need));
-  HIP_TRY(grow(ws.pair_val_alt, need));
+  HIP_TRY(grow(ws, ws.pair_key, need));
+  HIP_TRY(grow(ws, ws.pair_key_alt, need));
+  HIP_TRY(grow(ws, ws.pair_val, need));
+  HIP_TRY(grow(ws, ws.pair_val_alt, need));
   ws.cap_pairs = need;
   return AR_OK;
 }
@@ -271,19 +258,33 @@ static int bits_for(uint32_t v) {
   return b;
 }
 
+// Estimated device bytes of a launch of ncells cells (records, per-item arrays, list
+// entries, segment partials or prefix sums), at pairs_per_item list entries per item.
+size_t query_bytes(const ar_scene *sc, const Params &prm, int P, bool rotates, int ncells, double pairs_per_item) {
+  const double items = (double)sc->dev.n * ncells;
+  const double lists = (double)prm.ntx * prm.nty * ncells;
+  const double pairs = items * (pairs_per_item > 0.0 ? pairs_per_item : 32.0);
+  const double per_item = 8.0 * rec_stride(P) + 8.0 * (3 + 2 * (kMaxP + 1) + 2) + 4.0 * 7 + 16.0;
+  double b = items * per_item + pairs * 20.0 + lists * 24.0 + (double)(16 << 20);
+  if (rotates) {
+    b += pairs * (8.0 + 16.0 + 64.0 * 20.0);
+  } else {
+    const double segs = std::min(8192.0 + lists, pairs / 32.0 + lists);
+    b += segs * (8.0 * part_fields(P) * 64.0 + 8.0);
+  }
+  return (size_t)b;
+}
+
 // Cells per launch of a batch: the option if given, else as many as fit a quarter of
 // the free device memory (at most 64 GiB) at the list density of the last launch (32
 // list entries per Gaussian before the first), at most 256.
-static int batch_cells(const ar_scene *sc, const Params &prm, int P, bool rotates, const ar_options *opts) {
+int batch_cells(const ar_scene *sc, const Workspace &ws, const Params &prm, int P, bool rotates,
+                const ar_options *opts) {
   if (opts && opts->cells_per_launch > 0) return opts->cells_per_launch;
-  const double n = (double)sc->dev.n;
-  const double per_item = 8.0 * rec_stride(P) + 8.0 * (3 + 2 * (kMaxP + 1) + 2) + 4.0 * 5 + 16.0;
-  const double lists_per_item = sc->ws.pairs_per_item > 0.0 ? sc->ws.pairs_per_item : 32.0;
-  const double per_pair = 16.0 + 4.0 + (rotates ? 64.0 * 20.0 + 12.0 : 8.0 * part_fields(P) * 64.0 / 32.0);
-  const double per_cell = n * (per_item + lists_per_item * per_pair) + 64.0 * prm.ntx * prm.nty * 24.0;
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)16 << 30;
   const double budget = std::min(0.25 * (double)free_b, 64.0 * 1024 * 1024 * 1024);
+  const double per_cell = (double)query_bytes(sc, prm, P, rotates, 1, ws.pairs_per_item);
   return (int)std::max(1.0, std::min(256.0, floor(budget / per_cell)));
 }
 
@@ -291,9 +292,8 @@ static int batch_cells(const ar_scene *sc, const Params &prm, int P, bool rotate
 // launch per stage: item cell * n + g, list cell * ntiles + tile, images [cell][H][W][3].
 // The host waits twice per call (the number of list entries, and on the rotation path
 // the number of Ind runs) and once at the end.
-static int render_cells(ar_scene *sc, const Params &prm, const ar_pose_box *boxes, int ncells, int P, bool rotates,
-                        float *lo, float *hi, hipStream_t s, ar_stats *st) {
-  Workspace &ws = sc->ws;
+int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm, const ar_pose_box *boxes, int ncells, int P,
+                 bool rotates, float *lo, float *hi, hipStream_t s, ar_stats *st) {
   const int n = sc->dev.n;
   const int ntiles = prm.ntx * prm.nty;
   const size_t n_total = (size_t)ncells * n;
@@ -403,9 +403,26 @@ static int render_cells(ar_scene *sc, const Params &prm, const ar_pose_box *boxe
 // ------------------------------------------------------------------------------------
 // C ABI
 // ------------------------------------------------------------------------------------
+namespace ar {
+
+int check_outputs(const float *lo, const float *hi) {
+  if (!lo || !hi) return fail(AR_E_INVALID, "output image is NULL");
+  hipPointerAttribute_t a{};
+  for (const float *p : {lo, hi}) {
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess || a.type != hipMemoryTypeDevice) {
+      (void)hipGetLastError();
+      return fail(AR_E_INVALID, "output images must be device memory");
+    }
+  }
+  return AR_OK;
+}
+
+}  // namespace ar
+
 extern "C" {
 
-const char *ar_last_error(void) { return g_error.c_str(); }
+const char *ar_last_error(void) { return ar::g_error.c_str(); }
 
 const char *ar_version(void) { return "abstract-render-gfx950 0.1"; }
 
@@ -479,32 +496,11 @@ int ar_scene_create(const ar_scene_desc *desc, void *hip_stream, ar_scene **out)
 
 void ar_scene_destroy(ar_scene *sc) {
   if (!sc) return;
-  ar::Workspace &w = sc->ws;
-  void *bufs[] = {w.rec, w.key, w.key_sort, w.key_alt, w.perm, w.perm_alt, w.rect, w.dform, w.count,
-                  w.pair_key, w.pair_key_alt, w.pair_val, w.pair_val_alt, w.tile_range, w.hist, w.scan_tmp,
-                  w.counters, w.dint, w.wmax, w.run_cnt, w.runs, w.pre, w.prez, w.seg_off, w.seg_tile, w.part,
-                  w.cell_key, w.cell_key_alt, w.pose_dev, sc->base};
-  for (void *b : bufs)
-    if (b) (void)hipFree(b);
-  if (w.host_counters) (void)hipHostFree(w.host_counters);
-  if (w.pose_host) (void)hipHostFree(w.pose_host);
-  for (int i = 0; i < 4; ++i)
-    if (w.ev[i]) (void)hipEventDestroy(w.ev[i]);
+  ar::release_workspace(sc->ws);
+  if (sc->base) (void)hipFree(sc->base);
   delete sc;
 }
 
-static int check_outputs(const float *lo, const float *hi) {
-  if (!lo || !hi) return fail(AR_E_INVALID, "output image is NULL");
-  hipPointerAttribute_t a{};
-  for (const float *p : {lo, hi}) {
-    hipError_t e = hipPointerGetAttributes(&a, p);
-    if (e != hipSuccess || a.type != hipMemoryTypeDevice) {
-      (void)hipGetLastError();
-      return fail(AR_E_INVALID, "output images must be device memory");
-    }
-  }
-  return AR_OK;
-}
 
 int ar_render_bounds(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *box,
                      const ar_options *opts, float *lo_rgb, float *hi_rgb, void *hip_stream, ar_stats *stats) {
@@ -514,13 +510,13 @@ int ar_render_bounds(const ar_scene *scene, const ar_intrinsics *intr, const ar_
   ar::Params prm{};
   rc = ar::make_params(scene, intr, opts, prm);
   if (rc) return rc;
-  rc = check_outputs(lo_rgb, hi_rgb);
+  rc = ar::check_outputs(lo_rgb, hi_rgb);
   if (rc) return rc;
   if (stats) memset(stats, 0, sizeof(*stats));
   bool rot = false;
   const int P = ar::pose_vars(box, &rot);
-  return ar::render_cells(const_cast<ar_scene *>(scene), prm, box, 1, P, rot, lo_rgb, hi_rgb, (hipStream_t)hip_stream,
-                          stats);
+  return ar::render_cells(scene, const_cast<ar_scene *>(scene)->ws, prm, box, 1, P, rot, lo_rgb, hi_rgb,
+                          (hipStream_t)hip_stream, stats);
 }
 
 int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *cells, int32_t ncells,
@@ -534,7 +530,7 @@ int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_p
   ar::Params prm{};
   int rc = ar::make_params(scene, intr, opts, prm);
   if (rc) return rc;
-  rc = check_outputs(lo_rgb, hi_rgb);
+  rc = ar::check_outputs(lo_rgb, hi_rgb);
   if (rc) return rc;
   if (stats) memset(stats, 0, sizeof(*stats));
   const size_t img = (size_t)intr->width * intr->height * 3;
@@ -551,9 +547,10 @@ int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_p
       ++j;
     }
     while (i < j) {
-      const int m = std::min(j - i, ar::batch_cells(scene, prm, P, rot, opts));
-      rc = ar::render_cells(const_cast<ar_scene *>(scene), prm, cells + i, m, P, rot, lo_rgb + i * img,
-                            hi_rgb + i * img, (hipStream_t)hip_stream, stats);
+      ar::Workspace &ws = const_cast<ar_scene *>(scene)->ws;
+      const int m = std::min(j - i, ar::batch_cells(scene, ws, prm, P, rot, opts));
+      rc = ar::render_cells(scene, ws, prm, cells + i, m, P, rot, lo_rgb + i * img, hi_rgb + i * img,
+                            (hipStream_t)hip_stream, stats);
       if (rc) return rc;
       i += m;
     }

@@ -1,0 +1,43 @@
+// Host-side internals shared by the C ABI (ar_api.hip) and the query server
+// (ar_server.hip).
+#pragma once
+
+#include <string>
+
+#include "ar_internal.h"
+
+// A resident scene: device copies of the Gaussians and the workspace of the calls made
+// directly on it (ar_render_bounds / ar_render_batch).
+struct ar_scene {
+  ar::SceneDev dev{};
+  ar::Workspace ws{};
+  float *base = nullptr;  // one allocation holding the scene arrays
+};
+
+namespace ar {
+
+extern thread_local std::string g_error;
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+#define HIP_TRY(expr)                                                                                  \
+  do {                                                                                                 \
+    hipError_t e_ = (expr);                                                                            \
+    if (e_ == hipErrorOutOfMemory) return ::ar::fail(AR_E_OOM, "%s: out of device memory", #expr);    \
+    if (e_ != hipSuccess) return ::ar::fail(AR_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int pose_vars(const ar_pose_box *b, bool *rotates);
+int validate_box(const ar_pose_box *b);
+int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *op, Params &prm);
+int check_outputs(const float *lo, const float *hi);
+// estimated device bytes of a launch of ncells cells
+size_t query_bytes(const ar_scene *sc, const Params &prm, int P, bool rotates, int ncells, double pairs_per_item);
+// cells per launch of a batch (memory-bounded)
+int batch_cells(const ar_scene *sc, const Workspace &ws, const Params &prm, int P, bool rotates,
+                const ar_options *opts);
+// ncells pose boxes with the same pose variables into images [cell][H][W][3] on stream s,
+// using workspace ws; waits for the stream before returning
+int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm, const ar_pose_box *boxes, int ncells, int P,
+                 bool rotates, float *lo, float *hi, hipStream_t s, ar_stats *st);
+
+}  // namespace ar

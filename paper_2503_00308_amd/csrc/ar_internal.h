@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <unordered_map>
+
 #include "../../include/ar.h"
 
 #define HIP_RET(expr)                       \
@@ -99,6 +101,8 @@ struct SceneDev {
 // Device workspace (grown on demand, owned by a scene handle).
 struct Workspace {
   size_t cap_n = 0, cap_pairs = 0, cap_tiles = 0, cap_scratch = 0, cap_rec = 0, cap_cells = 0;
+  size_t bytes = 0;                              // device bytes held by the buffers below
+  std::unordered_map<void *, size_t> sizes;      // allocation -> bytes
   double pairs_per_item = 0.0;   // list entries per Gaussian item of the last launch
   PoseForms *pose_dev = nullptr;   // [cells] pose forms of a launch
   PoseForms *pose_host = nullptr;  // [cells] pinned staging
@@ -156,6 +160,34 @@ hipError_t exclusive_scan_u32(uint32_t *data, int n, Workspace &ws, hipStream_t 
 // keys[i] = items[i] / n_cell (cell of a global item)
 hipError_t launch_cell_keys(const uint32_t *items, int n_total, int n_cell, uint32_t *keys, hipStream_t s);
 hipError_t ensure_hist(Workspace &ws, size_t n_entries);
+
+// (Re)allocate p for `need` elements, keeping the workspace's byte count; old contents
+// are not kept.
+template <typename T>
+inline hipError_t grow(Workspace &ws, T *&p, size_t need) {
+  if (p) {
+    auto it = ws.sizes.find((void *)p);
+    if (it != ws.sizes.end()) {
+      ws.bytes -= it->second;
+      ws.sizes.erase(it);
+    }
+    const hipError_t e = hipFree(p);
+    p = nullptr;
+    if (e != hipSuccess) return e;
+  }
+  const size_t b = std::max(need, (size_t)64) * sizeof(T);
+  const hipError_t e = hipMalloc((void **)&p, b);
+  if (e != hipSuccess) {
+    p = nullptr;
+    return e;
+  }
+  ws.sizes[(void *)p] = b;
+  ws.bytes += b;
+  return hipSuccess;
+}
+
+// Free every buffer, event and pinned block of a workspace and reset it.
+void release_workspace(Workspace &ws);
 // ---- binning and pixel loops (ar_raster.hip) ----
 // items in depth-rank order perm[r] = cell * n_cell + gid; list id = cell * ntiles + tile
 hipError_t launch_count_tiles(int P, const Workspace &ws, int n_total, int n_cell, const Params &prm, hipStream_t s);

@@ -1,0 +1,293 @@
+// Query server with continuous batching over resident scenes (include/ar.h, "Query
+// server").  Host code: one worker thread per slot, each with its own HIP stream and
+// workspace; a FIFO queue with admission by the device-memory budget.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "ar_host.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_between(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+struct Query {
+  int64_t ticket = 0;
+  int32_t scene = 0;
+  ar_pose_box box{};
+  ar::Params prm{};
+  int P = 0;
+  bool rotates = false;
+  size_t est = 0;              // estimated workspace bytes
+  float *lo = nullptr, *hi = nullptr;
+  Clock::time_point t_submit, t_start, t_end;
+  int status = AR_PENDING;
+  int slot = -1;
+  ar_stats stats{};
+  std::string error;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  ar::Workspace ws;
+  bool busy = false;
+  size_t charge = 0;           // bytes counted against the budget (held, or the estimate while running)
+  std::thread worker;
+};
+
+}  // namespace
+
+struct ar_server {
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<Query>> queue;
+  std::map<int64_t, std::shared_ptr<Query>> records;
+  std::vector<const ar_scene *> scenes;
+  std::vector<double> pairs_per_item;   // per scene, from its last query
+  std::vector<std::unique_ptr<Slot>> slots;
+  std::vector<double> latencies;
+  int device = 0;
+  uint64_t budget = 0, peak_bytes = 0;
+  int64_t next_ticket = 1, submitted = 0, completed = 0, failed = 0, pairs = 0;
+  int inflight = 0, peak_inflight = 0;
+  double busy_s = 0.0;
+  Clock::time_point busy_since;
+  bool stop = false;
+
+  size_t charged_except(const Slot *me) const {
+    size_t b = 0;
+    for (auto &s : slots)
+      if (s.get() != me) b += s->charge;
+    return b;
+  }
+
+  void work(int k) {
+    (void)hipSetDevice(device);
+    Slot &slot = *slots[k];
+    for (;;) {
+      std::shared_ptr<Query> q;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+          if (!queue.empty()) {
+            const auto &h = queue.front();
+            const size_t need = std::max(slot.ws.bytes, h->est);
+            if (charged_except(&slot) + need <= budget || inflight == 0) {
+              q = h;
+              queue.pop_front();
+              slot.charge = need;
+              break;
+            }
+          } else if (stop) {
+            return;
+          }
+          cv_work.wait(lk);
+        }
+        slot.busy = true;
+        if (inflight++ == 0) busy_since = Clock::now();
+        peak_inflight = std::max(peak_inflight, inflight);
+        q->t_start = Clock::now();
+        q->slot = k;
+      }
+      ar_stats st{};
+      const int rc = ar::render_cells(scenes[q->scene], slot.ws, q->prm, &q->box, 1, q->P, q->rotates, q->lo, q->hi,
+                                      slot.stream, &st);
+      const std::string err = rc ? ar::g_error : std::string();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        const Clock::time_point now = Clock::now();
+        q->t_end = now;
+        q->status = rc;
+        q->stats = st;
+        q->error = err;
+        if (--inflight == 0) busy_s += std::chrono::duration<double>(now - busy_since).count();
+        if (rc == AR_OK) {
+          ++completed;
+          latencies.push_back(ms_between(q->t_submit, now));
+          pairs += st.pairs;
+          const double n = (double)std::max(1, scenes[q->scene]->dev.n);
+          pairs_per_item[q->scene] = (double)st.tile_pairs / n;
+        } else {
+          ++failed;
+        }
+        slot.busy = false;
+        slot.charge = slot.ws.bytes;
+        peak_bytes = std::max<uint64_t>(peak_bytes, charged_except(nullptr));
+        // hand memory back when the held workspaces exceed the budget
+        if (charged_except(nullptr) > budget) {
+          ar::release_workspace(slot.ws);
+          slot.charge = 0;
+        }
+      }
+      cv_done.notify_all();
+      cv_work.notify_all();
+    }
+  }
+};
+
+extern "C" {
+
+int ar_server_create(const ar_server_config *cfg, ar_server **out) {
+  if (!out) return ar::fail(AR_E_INVALID, "out is NULL");
+  *out = nullptr;
+  ar_server_config c{};
+  if (cfg) c = *cfg;
+  if (c.slots < 0 || c.slots > 16) return ar::fail(AR_E_INVALID, "slots %d outside [0, 16]", c.slots);
+  std::unique_ptr<ar_server> srv(new ar_server());
+  HIP_TRY(hipGetDevice(&srv->device));
+  if (c.hbm_budget == 0) {
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    c.hbm_budget = free_b / 4;
+  }
+  srv->budget = c.hbm_budget;
+  const int nslots = c.slots ? c.slots : 4;
+  for (int k = 0; k < nslots; ++k) {
+    std::unique_ptr<Slot> s(new Slot());
+    HIP_TRY(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+    srv->slots.push_back(std::move(s));
+  }
+  for (int k = 0; k < nslots; ++k) {
+    ar_server *p = srv.get();
+    srv->slots[k]->worker = std::thread([p, k] { p->work(k); });
+  }
+  *out = srv.release();
+  return AR_OK;
+}
+
+void ar_server_destroy(ar_server *srv) {
+  if (!srv) return;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stop = true;
+  }
+  srv->cv_work.notify_all();
+  for (auto &s : srv->slots)
+    if (s->worker.joinable()) s->worker.join();
+  for (auto &s : srv->slots) {
+    ar::release_workspace(s->ws);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+  }
+  delete srv;
+}
+
+int ar_server_add_scene(ar_server *srv, const ar_scene *scene, int32_t *scene_id) {
+  if (!srv || !scene || !scene_id) return ar::fail(AR_E_INVALID, "server, scene or scene_id is NULL");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  *scene_id = (int32_t)srv->scenes.size();
+  srv->scenes.push_back(scene);
+  srv->pairs_per_item.push_back(0.0);
+  return AR_OK;
+}
+
+int ar_server_submit(ar_server *srv, int32_t scene_id, const ar_intrinsics *intr, const ar_pose_box *box,
+                     const ar_options *opts, float *lo_rgb, float *hi_rgb, int64_t *ticket) {
+  if (!srv || !ticket) return ar::fail(AR_E_INVALID, "server or ticket is NULL");
+  const ar_scene *scene = nullptr;
+  double ppi = 0.0;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (scene_id < 0 || scene_id >= (int32_t)srv->scenes.size())
+      return ar::fail(AR_E_INVALID, "unknown scene id %d", scene_id);
+    scene = srv->scenes[scene_id];
+    ppi = srv->pairs_per_item[scene_id];
+  }
+  int rc = ar::validate_box(box);
+  if (rc) return rc;
+  auto q = std::make_shared<Query>();
+  rc = ar::make_params(scene, intr, opts, q->prm);
+  if (rc) return rc;
+  rc = ar::check_outputs(lo_rgb, hi_rgb);
+  if (rc) return rc;
+  q->P = ar::pose_vars(box, &q->rotates);
+  if (!q->rotates && q->P > 3) return ar::fail(AR_E_INVALID, "more than 3 translation variables");
+  q->scene = scene_id;
+  q->box = *box;
+  q->lo = lo_rgb;
+  q->hi = hi_rgb;
+  q->est = ar::query_bytes(scene, q->prm, q->P, q->rotates, 1, ppi);
+  q->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->stop) return ar::fail(AR_E_INVALID, "server is shutting down");
+    q->ticket = srv->next_ticket++;
+    srv->records[q->ticket] = q;
+    srv->queue.push_back(q);
+    ++srv->submitted;
+    *ticket = q->ticket;
+  }
+  srv->cv_work.notify_all();
+  return AR_OK;
+}
+
+int ar_server_wait(ar_server *srv, int64_t ticket, int32_t block, ar_query_result *out) {
+  if (!srv || !out) return ar::fail(AR_E_INVALID, "server or out is NULL");
+  memset(out, 0, sizeof(*out));
+  std::unique_lock<std::mutex> lk(srv->mu);
+  auto it = srv->records.find(ticket);
+  if (it == srv->records.end()) return ar::fail(AR_E_INVALID, "unknown or already collected ticket %lld", (long long)ticket);
+  std::shared_ptr<Query> q = it->second;
+  if (q->status == AR_PENDING) {
+    if (!block) {
+      out->status = AR_PENDING;
+      return AR_PENDING;
+    }
+    srv->cv_done.wait(lk, [&] { return q->status != AR_PENDING; });
+  }
+  out->status = q->status;
+  out->slot = q->slot;
+  out->queue_ms = ms_between(q->t_submit, q->t_start);
+  out->latency_ms = ms_between(q->t_submit, q->t_end);
+  out->stats = q->stats;
+  strncpy(out->error, q->error.c_str(), sizeof(out->error) - 1);
+  srv->records.erase(ticket);
+  if (q->status != AR_OK) return ar::fail(q->status, "%s", q->error.c_str());
+  return AR_OK;
+}
+
+int ar_server_report(ar_server *srv, ar_server_stats *out) {
+  if (!srv || !out) return ar::fail(AR_E_INVALID, "server or out is NULL");
+  memset(out, 0, sizeof(*out));
+  std::lock_guard<std::mutex> lk(srv->mu);
+  out->submitted = srv->submitted;
+  out->completed = srv->completed;
+  out->failed = srv->failed;
+  out->slots = (int32_t)srv->slots.size();
+  out->peak_inflight = srv->peak_inflight;
+  std::vector<double> v = srv->latencies;
+  if (!v.empty()) {
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double p) {
+      const double r = p * (double)(v.size() - 1);
+      const size_t i = (size_t)r;
+      const double f = r - (double)i;
+      return i + 1 < v.size() ? v[i] * (1.0 - f) + v[i + 1] * f : v[i];
+    };
+    out->p50_ms = pct(0.50);
+    out->p99_ms = pct(0.99);
+    double s = 0.0;
+    for (double x : v) s += x;
+    out->mean_ms = s / (double)v.size();
+  }
+  out->busy_s = srv->busy_s + (srv->inflight > 0 ? std::chrono::duration<double>(Clock::now() - srv->busy_since).count()
+                                                 : 0.0);
+  out->hbm_budget = srv->budget;
+  out->peak_bytes = srv->peak_bytes;
+  out->pairs = srv->pairs;
+  return AR_OK;
+}
+
+}  // extern "C"

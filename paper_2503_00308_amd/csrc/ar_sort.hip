@@ -147,27 +147,17 @@ __global__ __launch_bounds__(256) void k_scan_apply(uint32_t *__restrict__ data,
 }
 
 hipError_t ensure_hist(Workspace &ws, size_t n_entries) {
-  if (n_entries <= ws.cap_hist) return hipSuccess;
-  if (ws.hist) {
-    hipError_t e = hipFree(ws.hist);
-    if (e != hipSuccess) return e;
-    ws.hist = nullptr;
-  }
-  size_t cap = n_entries + n_entries / 2 + 1024;
-  hipError_t e = hipMalloc(&ws.hist, cap * sizeof(uint32_t));
+  if (n_entries <= ws.cap_hist && ws.hist) return hipSuccess;
+  const size_t cap = n_entries + n_entries / 2 + 1024;
+  const hipError_t e = grow(ws, ws.hist, cap);
   if (e == hipSuccess) ws.cap_hist = cap;
   return e;
 }
 
 static hipError_t ensure_scan_tmp(Workspace &ws, size_t n_entries) {
-  if (n_entries <= ws.cap_scan) return hipSuccess;
-  if (ws.scan_tmp) {
-    hipError_t e = hipFree(ws.scan_tmp);
-    if (e != hipSuccess) return e;
-    ws.scan_tmp = nullptr;
-  }
-  size_t cap = n_entries + n_entries / 2 + 1024;
-  hipError_t e = hipMalloc(&ws.scan_tmp, cap * sizeof(uint32_t));
+  if (n_entries <= ws.cap_scan && ws.scan_tmp) return hipSuccess;
+  const size_t cap = n_entries + n_entries / 2 + 1024;
+  const hipError_t e = grow(ws, ws.scan_tmp, cap);
   if (e == hipSuccess) ws.cap_scan = cap;
   return e;
 }

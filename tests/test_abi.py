@@ -47,7 +47,8 @@ def test_version_and_last_error_without_gpu():
 def test_struct_layout_matches_c(tmp_path):
     src = tmp_path / "layout.c"
     structs = {"ar_scene_desc": api.SceneDesc, "ar_intrinsics": api.Intrinsics, "ar_pose_box": api.PoseBox,
-               "ar_options": api.Options, "ar_stats": api.Stats}
+               "ar_options": api.Options, "ar_stats": api.Stats, "ar_server_config": api.ServerConfig,
+               "ar_query_result": api.QueryResult, "ar_server_stats": api.ServerStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
@@ -63,3 +64,16 @@ def test_struct_layout_matches_c(tmp_path):
         assert int(got[cname]) == ctypes.sizeof(cls), cname
         for fname, _ in cls._fields_:
             assert int(got[f"{cname}.{fname}"]) == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_server_argument_errors_without_gpu():
+    """Null handles are rejected before any device call."""
+    import ctypes
+    lib = api.load()
+    assert lib.ar_server_create(None, None) == api.AR_E_INVALID
+    sid = ctypes.c_int32()
+    assert lib.ar_server_add_scene(None, None, ctypes.byref(sid)) == api.AR_E_INVALID
+    r = api.QueryResult()
+    assert lib.ar_server_wait(None, 1, 0, ctypes.byref(r)) == api.AR_E_INVALID
+    assert lib.ar_server_report(None, None) == api.AR_E_INVALID
+    lib.ar_server_destroy(None)

@@ -1,0 +1,129 @@
+"""Query server (continuous batching over resident scenes), through the C ABI.
+
+Each query's bounds must be the same alone and in a mix of concurrent queries (same
+kernels, its own workspace and stream), bit for bit; admission must follow the memory
+budget; results are pinned to the oracle.
+"""
+import numpy as np
+import pytest
+
+from paper_2503_00308_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_00308_amd import api
+    api.load()
+    return api
+
+
+def _workload(seed=0, nq=24):
+    scenes = [synth.box_surface_scene(1500, n_boxes=6, seed=21), synth.random_scene(3000, seed=22),
+              synth.box_surface_scene(6000, n_boxes=10, seed=23)]
+    rng = np.random.default_rng(seed)
+    queries = []
+    for _ in range(nq):
+        s = int(rng.integers(0, 3))
+        side = int(rng.choice([32, 48, 64]))
+        if rng.uniform() < 0.5:
+            box = synth.camera6_box(dt=0.5 * rng.uniform(0.01, 0.1, 3))
+        else:
+            box = synth.camera6_box(dt=0.5 * rng.uniform(0.01, 0.1, 3), drot=0.5 * np.deg2rad(rng.uniform(0, 2, 3)))
+        queries.append((s, synth.intrinsics(side), box))
+    return scenes, queries
+
+
+def _alone(api, handles, queries):
+    out = []
+    for s, intr, box in queries:
+        lo, hi, _ = api.render_bounds(handles[s], intr, box)
+        out.append((lo.cpu().numpy(), hi.cpu().numpy()))
+    return out
+
+
+def test_server_results_same_alone_and_in_mix():
+    api = _api()
+    scenes, queries = _workload()
+    handles = [api.Scene(sc) for sc in scenes]
+    srv = api.Server(slots=4)
+    ids = [srv.add_scene(h) for h in handles]
+    tickets = [srv.submit(ids[s], intr, box) for s, intr, box in queries]
+    mixed = []
+    for t in tickets:
+        lo, hi, res = srv.wait(t)
+        assert res["status"] == 0
+        mixed.append((lo.cpu().numpy(), hi.cpu().numpy()))
+    rep = srv.report()
+    srv.close()
+    print("server report", rep, flush=True)
+    assert rep["completed"] == len(queries) and rep["failed"] == 0
+    assert rep["peak_inflight"] >= 2
+    assert rep["p99_ms"] >= rep["p50_ms"] > 0.0
+    alone = _alone(api, handles, queries)
+    for k, ((ml, mh), (al, ah)) in enumerate(zip(mixed, alone)):
+        assert np.array_equal(ml, al) and np.array_equal(mh, ah), k
+    for h in handles:
+        h.close()
+
+
+def test_server_budget_admits_one_query_at_a_time():
+    """A budget smaller than any query: each runs only when nothing else is in flight."""
+    api = _api()
+    scenes, queries = _workload(seed=1, nq=8)
+    handles = [api.Scene(sc) for sc in scenes]
+    srv = api.Server(slots=4, hbm_budget=1)
+    ids = [srv.add_scene(h) for h in handles]
+    tickets = [srv.submit(ids[s], intr, box) for s, intr, box in queries]
+    mixed = [srv.wait(t)[:2] for t in tickets]
+    rep = srv.report()
+    srv.close()
+    assert rep["peak_inflight"] == 1 and rep["completed"] == len(queries)
+    alone = _alone(api, handles, queries)
+    for (ml, mh), (al, ah) in zip(mixed, alone):
+        assert np.array_equal(ml.cpu().numpy(), al) and np.array_equal(mh.cpu().numpy(), ah)
+    for h in handles:
+        h.close()
+
+
+def test_server_parity_with_oracle():
+    from oracle import splat
+    api = _api()
+    scene = synth.box_surface_scene(300, n_boxes=4, seed=24)
+    h = api.Scene(scene)
+    srv = api.Server(slots=2)
+    sid = srv.add_scene(h)
+    jobs = [(synth.intrinsics(32), synth.camera6_box(dt=0.03, drot=np.deg2rad(0.5))),
+            (synth.intrinsics(40), synth.camera6_box(dt=(0.05, 0.02, 0.0)))]
+    tickets = [srv.submit(sid, intr, box) for intr, box in jobs]
+    for t, (intr, box) in zip(tickets, jobs):
+        lo, hi, _ = srv.wait(t)
+        ref = splat.oracle_bounds(scene, intr, box)
+        ok = ~ref["border"][..., None]
+        glo, ghi = lo.cpu().numpy(), hi.cpu().numpy()
+        dlo = np.abs(glo - ref["lo"])[np.broadcast_to(ok, glo.shape)].max()
+        dhi = np.abs(ghi - ref["hi"])[np.broadcast_to(ok, ghi.shape)].max()
+        print(f"[server] max|dlo| {dlo:.3e} max|dhi| {dhi:.3e}", flush=True)
+        assert dlo <= 1e-5 and dhi <= 1e-5
+    srv.close()
+    h.close()
+
+
+def test_server_rejects_bad_requests():
+    api = _api()
+    h = api.Scene(synth.random_scene(50, seed=25))
+    srv = api.Server(slots=1)
+    sid = srv.add_scene(h)
+    with pytest.raises(api.ARError):
+        srv.submit(sid + 1, synth.intrinsics(16), synth.camera6_box(dt=0.01))
+    bad = synth.camera6_box(dt=0.01)
+    bad["lo"][0], bad["hi"][0] = 0.1, -0.1
+    with pytest.raises(api.ARError):
+        srv.submit(sid, synth.intrinsics(16), bad)
+    with pytest.raises(api.ARError):
+        srv.wait(12345)
+    srv.close()
+    h.close()
