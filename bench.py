@@ -7,7 +7,11 @@ binning, per-pixel BlendInd loop) of the workload: 10k Gaussians, 128x128 image,
 Prints ONE JSON line with the throughput in bounded (pixel, Gaussian) pairs per
 second, query latency percentiles, the roofline of the per-pixel kernel (timed with
 HIP events inside the library, on the call's stream) and the FP64 CPU oracle timed
-on a bounded sample of the same workload.
+on a bounded sample of the same workload.  Two more objects in the same line:
+"batched" (50k Gaussians on boxes, 200x200, a 30-degree orbit in 256 cells of uneven
+widths, all cells through ar_render_batch, against the per-query path) and "served"
+(Poisson queries over four resident scenes of 10k-750k Gaussians and images of
+100^2-800^2 through the query server, p50/p99 latency against one-at-a-time service).
 """
 from __future__ import annotations
 
@@ -110,12 +114,126 @@ def cpu_baseline(scene, intr, box, budget_s=20.0):
                       f"stage ({t_rec:.1f} s for all {len(scene['mean'])} Gaussians) charged pro rata"}
 
 
+def log(msg):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def batched_measure(api, synth, runs=2, per_query_cells=32):
+    """All 256 orbit cells in one batched call, against one ar_render_bounds per cell."""
+    import numpy as np
+    import torch
+    scene, intr, cells, desc = synth.config(4)
+    sc = api.Scene(scene)
+    log("batched: warm-up")
+    api.render_batch(sc, intr, cells)       # warm-up (sizes the workspace)
+    torch.cuda.synchronize()
+    times, st = [], None
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        _, _, st = api.render_batch(sc, intr, cells)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t_batch = float(np.median(times))
+    log(f"batched: {t_batch:.3f} s for {len(cells)} cells; per-query path on {per_query_cells} cells")
+    sub = cells[:per_query_cells]
+    H, W = intr["height"], intr["width"]
+    lo = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    hi = torch.empty_like(lo)
+    api.render_bounds(sc, intr, sub[0], out=(lo, hi))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pairs_sub = 0
+    for c in sub:
+        _, _, s1 = api.render_bounds(sc, intr, c, out=(lo, hi))
+        pairs_sub += s1["pairs"]
+    torch.cuda.synchronize()
+    t_single = (time.perf_counter() - t0) / len(sub)
+    sc.close()
+    n = len(cells)
+    return {"workload": desc, "cells": n, "pairs": int(st["pairs"]), "cells_per_s": n / t_batch,
+            "pairs_per_s": st["pairs"] / t_batch, "ms_per_cell": t_batch / n * 1e3,
+            "device_ms": st["total_ms"], "raster_ms": st["raster_ms"],
+            "per_query_ms_per_cell": t_single * 1e3, "per_query_cells_timed": len(sub),
+            "per_query_pairs_per_s": pairs_sub / (t_single * len(sub)),
+            "speedup_vs_per_query": t_single * n / t_batch}
+
+
+def served_measure(api, synth, nq=48, load=0.75, slots=4, seed=0):
+    """Poisson arrivals at `load` x the one-at-a-time capacity; the server's latencies
+    against a FIFO one-at-a-time queue with each query's measured solo service time."""
+    import numpy as np
+    import torch
+    log("served: scenes")
+    scenes = synth.served_scenes(seed)
+    handles = [api.Scene(s) for s in scenes]
+    queries = synth.served_queries(nq, seed)
+    # solo service times (the plain per-query path), each query once after a warm-up
+    for s in range(len(handles)):
+        side = (100, 200, 400, 800)[s]
+        api.render_bounds(handles[s], synth.intrinsics(side), synth.camera6_box(dt=0.01))
+    torch.cuda.synchronize()
+    service, pairs = [], 0
+    for i, (s, side, box) in enumerate(queries):
+        t0 = time.perf_counter()
+        _, _, st = api.render_bounds(handles[s], synth.intrinsics(side), box)
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t0)
+        pairs += st["pairs"]
+        log(f"served: solo query {i} scene {s} side {side}: {service[-1] * 1e3:.1f} ms, {st['pairs']} pairs")
+    service = np.array(service)
+    lam = load / service.mean()
+    rng = np.random.default_rng(seed + 1)
+    arrival = np.cumsum(rng.exponential(1.0 / lam, nq))
+    arrival -= arrival[0]
+    # one at a time, first come first served
+    finish = np.empty(nq)
+    t = 0.0
+    for i in range(nq):
+        t = max(t, arrival[i]) + service[i]
+        finish[i] = t
+    serial_lat = (finish - arrival) * 1e3
+    # the server, queries submitted at their arrival times
+    log(f"served: server run, {nq} queries at {lam:.1f} per s")
+    srv = api.Server(slots=slots)
+    ids = [srv.add_scene(h) for h in handles]
+    tickets = []
+    t0 = time.perf_counter()
+    for i, (s, side, box) in enumerate(queries):
+        now = time.perf_counter() - t0
+        if arrival[i] > now:
+            time.sleep(arrival[i] - now)
+        tickets.append(srv.submit(ids[s], synth.intrinsics(side), box))
+    lat = []
+    for tk in tickets:
+        _, _, res = srv.wait(tk)
+        lat.append(res["latency_ms"])
+    wall = time.perf_counter() - t0
+    rep = srv.report()
+    srv.close()
+    for h in handles:
+        h.close()
+    lat = np.array(lat)
+    return {"workload": "Poisson queries over resident scenes of 10k/100k/300k/750k Gaussians on boxes, "
+                        "images 100^2-800^2, translation full widths U[0.01,0.1], rotation U[0,2] deg",
+            "queries": nq, "load": load, "arrival_qps": lam, "slots": slots,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "throughput_qps": nq / wall, "pairs_per_s": pairs / wall, "peak_inflight": rep["peak_inflight"],
+            "peak_workspace_bytes": rep["peak_bytes"],
+            "one_at_a_time": {"p50_ms": float(np.percentile(serial_lat, 50)),
+                              "p99_ms": float(np.percentile(serial_lat, 99)),
+                              "mean_service_ms": float(service.mean() * 1e3),
+                              "throughput_qps": nq / finish[-1]}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_raster_seg_cfg2_traffic.txt"))
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -185,9 +303,14 @@ def main():
                      "frac_vs_packed_fp32_peak": achieved / PEAK_FP32_PACKED_TFLOPS,
                      "flops_per_pair": alg_flops_per_pair(P), "traffic": traffic},
     }
+    sc.close()
+    log(f"headline workload done: {value:.4g} pairs/s")
+    if not args.no_batched:
+        out["batched"] = batched_measure(api, synth)
+    if not args.no_served:
+        out["served"] = served_measure(api, synth)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, intr, box, args.cpu_budget)
-    sc.close()
     print(json.dumps(out), flush=True)
 
 

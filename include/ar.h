@@ -114,6 +114,9 @@ typedef struct {
  *               Gaussian i is dropped from pixel u when its alpha is provably below
  *               cull_budget / n at every pose; lower / upper bounds are widened by E
  *   z_near      near plane (default 0.01): depth <= z_near gives alpha 0
+ *   prefix_entries  rotation boxes: tile-list entries whose per-pixel prefix sums one
+ *               pixel-loop launch holds (64 x 20 bytes each; default 2^21; a longer
+ *               single list gets its own launch)
  *   cells_per_launch  ar_render_batch: pose cells per launch (default: as many as fit a
  *               workspace of about 4 GiB, at most 256)
  *   t_min       stop a tile once every pixel's transmittance upper bound is below it,
@@ -129,7 +132,7 @@ typedef struct {
   double z_near;
   double t_min;
   int32_t cells_per_launch;
-  int32_t reserved;
+  int32_t prefix_entries;
 } ar_options;
 
 /* Statistics of one call (filled when the call returns). */
@@ -144,6 +147,8 @@ typedef struct {
   int32_t reserved;
   double raster_ms;      /* device time of the main per-pixel kernel (HIP events on the call's stream) */
   double total_ms;       /* device time of the whole call from its first to its last kernel */
+  int64_t runs;          /* rotation boxes: runs of list positions holding the Ind sets */
+  int64_t cycles_a, cycles_b; /* rotation boxes: summed wave clock cycles of the pixel loop's two phases */
 } ar_stats;
 
 /* Copies the scene to the device on `stream` (synchronises it).  *out receives a

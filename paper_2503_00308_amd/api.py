@@ -47,14 +47,15 @@ class Options(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("groups", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("taylor_k", ctypes.c_int32), ("cull_budget", ctypes.c_double),
                 ("z_near", ctypes.c_double), ("t_min", ctypes.c_double),
-                ("cells_per_launch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("cells_per_launch", ctypes.c_int32), ("prefix_entries", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_int64), ("tile_pairs", ctypes.c_int64),
                 ("n_fallback", ctypes.c_int32), ("n_wild", ctypes.c_int32), ("n_dropped", ctypes.c_int32),
                 ("P", ctypes.c_int32), ("max_window", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("raster_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+                ("raster_ms", ctypes.c_double), ("total_ms", ctypes.c_double), ("runs", ctypes.c_int64),
+                ("cycles_a", ctypes.c_int64), ("cycles_b", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -148,7 +149,7 @@ def options(d=None) -> Options:
     return Options(int(d.get("tile", 0)), int(d.get("groups", 0)), int(d.get("chunk", 0)),
                    int(d.get("taylor_k", 0)), float(d.get("cull_budget", 0.0)),
                    float(d.get("z_near", 0.0)), float(d.get("t_min", 0.0)),
-                   int(d.get("cells_per_launch", 0)), 0)
+                   int(d.get("cells_per_launch", 0)), int(d.get("prefix_entries", 0)))
 
 
 class Scene:
@@ -254,7 +255,9 @@ class Server:
         ci = intrinsics(intr)
         lo = torch.empty((ci.height, ci.width, 3), dtype=torch.float32, device="cuda")
         hi = torch.empty_like(lo)
-        torch.cuda.synchronize()   # the buffers exist before another stream writes them
+        # pending work of torch's stream on this memory finishes before the server's
+        # streams write it (waits for torch's stream only, not for queries in flight)
+        torch.cuda.current_stream().synchronize()
         t = ctypes.c_int64()
         b = pose_box(box)
         co = options(opts)

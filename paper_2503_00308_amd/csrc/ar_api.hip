@@ -38,6 +38,7 @@ int fail(int code, const char *fmt, ...) {
 void release_workspace(Workspace &ws) {
   for (auto &kv : ws.sizes) (void)hipFree(kv.first);
   if (ws.host_counters) (void)hipHostFree(ws.host_counters);
+  if (ws.host_ranges) (void)hipHostFree(ws.host_ranges);
   if (ws.pose_host) (void)hipHostFree(ws.pose_host);
   for (int i = 0; i < 4; ++i)
     if (ws.ev[i]) (void)hipEventDestroy(ws.ev[i]);
@@ -96,6 +97,7 @@ int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *o
   if (op) o = *op;
   if (o.tile != 0 && o.tile != kTile) return fail(AR_E_UNSUPPORTED, "tile %d: only %d is built", o.tile, kTile);
   if (o.groups < 0 || o.groups > 8) return fail(AR_E_INVALID, "groups %d outside [0, 8]", o.groups);
+  if (o.prefix_entries < 0) return fail(AR_E_INVALID, "prefix_entries %d is negative", o.prefix_entries);
   if (o.cells_per_launch < 0 || o.cells_per_launch > 256)
     return fail(AR_E_INVALID, "cells_per_launch %d outside [0, 256]", o.cells_per_launch);
   if (o.chunk != 0 && (o.chunk < 8 || o.chunk > 4096)) return fail(AR_E_INVALID, "chunk %d outside [8, 4096]", o.chunk);
@@ -126,6 +128,7 @@ int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *o
   }
   prm.groups = G;
   prm.chunk = o.chunk;  // 0: chosen per call from the number of (tile, Gaussian) pairs
+  prm.prefix_entries = o.prefix_entries;
   return AR_OK;
 }
 
@@ -155,7 +158,7 @@ static int ensure_ws(Workspace &ws, size_t n_total, size_t nlists, int P, int nc
   }
   if (nlists > ws.cap_tiles || !ws.tile_range) {
     HIP_TRY(grow(ws, ws.tile_range, 2 * nlists + 2));
-    HIP_TRY(grow(ws, ws.wmax, nlists + 2));
+    HIP_TRY(grow(ws, ws.lbox, 6 * nlists + 12));
     ws.cap_tiles = nlists;
   }
   if ((size_t)ncells > ws.cap_cells || !ws.pose_dev) {
@@ -175,19 +178,34 @@ static int ensure_ws(Workspace &ws, size_t n_total, size_t nlists, int P, int nc
   return AR_OK;
 }
 
-// buffers of the general path: run counts for npairs list positions, per-pixel prefix sums
-static int ensure_general(Workspace &ws, size_t npairs) {
+// Rotation path: list entries whose per-pixel prefix sums are held at once (the pixel
+// loop runs over chunks of tile lists with at most this many entries, or one list).
+constexpr size_t kPrefixEntries = (size_t)1 << 21;   // 2M entries, 2.7 GB
+
+// buffers of the general path: run counts for npairs list positions, pinned list ranges
+static int ensure_general(Workspace &ws, size_t npairs, size_t nlists) {
   if (2 * npairs + 1 > ws.cap_run_cnt || !ws.run_cnt) {
     const size_t need = 2 * npairs + 1 + npairs / 2 + 1024;
     HIP_TRY(grow(ws, ws.run_cnt, need));
     ws.cap_run_cnt = need;
   }
-  if (npairs > ws.cap_pre || !ws.pre) {
-    const size_t need = npairs + npairs / 4 + 64;
-    HIP_TRY(grow(ws, ws.pre, need * kTilePix * 2));
-    HIP_TRY(grow(ws, ws.prez, need * kTilePix));
-    ws.cap_pre = need;
+  if (2 * nlists + 2 > ws.cap_host_ranges || !ws.host_ranges) {
+    if (ws.host_ranges) HIP_TRY(hipHostFree(ws.host_ranges));
+    ws.host_ranges = nullptr;
+    const size_t need = 2 * nlists + 2;
+    HIP_TRY(hipHostMalloc((void **)&ws.host_ranges, need * sizeof(uint32_t), hipHostMallocDefault));
+    ws.cap_host_ranges = need;
   }
+  return AR_OK;
+}
+
+// per-pixel prefix sums for `entries` list entries
+static int ensure_prefix(Workspace &ws, size_t entries) {
+  if (entries <= ws.cap_pre && ws.pre) return AR_OK;
+  const size_t need = entries + entries / 8 + 64;
+  HIP_TRY(grow(ws, ws.pre, need * kTilePix * 2));
+  HIP_TRY(grow(ws, ws.prez, need * kTilePix));
+  ws.cap_pre = need;
   return AR_OK;
 }
 
@@ -267,7 +285,7 @@ size_t query_bytes(const ar_scene *sc, const Params &prm, int P, bool rotates, i
   const double per_item = 8.0 * rec_stride(P) + 8.0 * (3 + 2 * (kMaxP + 1) + 2) + 4.0 * 7 + 16.0;
   double b = items * per_item + pairs * 20.0 + lists * 24.0 + (double)(16 << 20);
   if (rotates) {
-    b += pairs * (8.0 + 16.0 + 64.0 * 20.0);
+    b += pairs * (8.0 + 16.0) + std::min(pairs, (double)kPrefixEntries) * 64.0 * 20.0 * 1.125;
   } else {
     const double segs = std::min(8192.0 + lists, pairs / 32.0 + lists);
     b += segs * (8.0 * part_fields(P) * 64.0 + 8.0);
@@ -292,8 +310,10 @@ int batch_cells(const ar_scene *sc, const Workspace &ws, const Params &prm, int 
 // launch per stage: item cell * n + g, list cell * ntiles + tile, images [cell][H][W][3].
 // The host waits twice per call (the number of list entries, and on the rotation path
 // the number of Ind runs) and once at the end.
-int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm, const ar_pose_box *boxes, int ncells, int P,
+int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const ar_pose_box *boxes, int ncells, int P,
                  bool rotates, float *lo, float *hi, hipStream_t s, ar_stats *st) {
+  Params prm = prm_in;
+  prm.nominal_order = rotates ? 1 : 0;   // rotation path: lists in order of the nominal depth
   const int n = sc->dev.n;
   const int ntiles = prm.ntx * prm.nty;
   const size_t n_total = (size_t)ncells * n;
@@ -360,22 +380,51 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm, const ar_
     HIP_TRY(launch_raster_translation(P, ws, ws.pair_val, (int)nlists, prm, L, (int)nseg_max, lo, hi, s));
   } else {
     // depth order may change inside the box: Ind runs per tile list, then the two-phase loop
-    rc = ensure_general(ws, npairs);
+    rc = ensure_general(ws, npairs, nlists);
     if (rc) return rc;
-    HIP_TRY(launch_tile_wmax(ws, ws.pair_val, (int)nlists, s));
+    HIP_TRY(launch_list_box(ws, ws.pair_val, (int)nlists, ntiles, sc->dev, s));
     HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, false, s));
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.run_cnt + 2 * (size_t)npairs, 1);
     HIP_TRY(hipGetLastError());
     HIP_TRY(exclusive_scan_u32(ws.run_cnt, (int)(2 * npairs + 1), ws, s));
     HIP_TRY(hipMemcpyAsync(ws.host_counters, ws.run_cnt + 2 * (size_t)npairs, sizeof(uint32_t),
                            hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ws.host_ranges, ws.tile_range, 2 * nlists * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const uint32_t nruns = *(const uint32_t *)ws.host_counters;
+    if (st) st->runs += nruns;
     rc = ensure_runs(ws, nruns);
+    if (rc) return rc;
+    // chunks of consecutive lists with at most kPrefixEntries entries (or one longer list)
+    const uint32_t *R = ws.host_ranges;
+    size_t longest = 0;
+    for (size_t l = 0; l < nlists; ++l) longest = std::max<size_t>(longest, R[2 * l + 1] - R[2 * l]);
+    const size_t want = prm.prefix_entries > 0 ? (size_t)prm.prefix_entries : kPrefixEntries;
+    rc = ensure_prefix(ws, std::min<size_t>(npairs, std::max(want, longest)));
     if (rc) return rc;
     HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, true, s));
     HIP_TRY(hipEventRecord(ws.ev[1], s));
-    HIP_TRY(launch_raster_general(P, ws, ws.pair_val, (int)nlists, prm, lo, hi, s));
+    const size_t cap = std::max(std::min<size_t>(ws.cap_pre, want), longest);
+    size_t l = 0;
+    while (l < nlists) {
+      size_t l1 = l;
+      uint32_t pos0 = 0;
+      bool have = false;
+      while (l1 < nlists) {
+        const uint32_t b = R[2 * l1], e = R[2 * l1 + 1];
+        if (e > b) {
+          if (!have) {
+            pos0 = b;
+            have = true;
+          } else if ((size_t)(e - pos0) > cap) {
+            break;
+          }
+        }
+        ++l1;
+      }
+      HIP_TRY(launch_raster_general(P, ws, ws.pair_val, (int)l, (int)(l1 - l), pos0, prm, lo, hi, s));
+      l = l1;
+    }
     HIP_TRY(hipEventRecord(ws.ev[2], s));
   }
   HIP_TRY(hipEventRecord(ws.ev[3], s));
@@ -394,6 +443,8 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm, const ar_
     st->raster_ms += ms_raster;
     st->total_ms += ms_total;
     st->max_window = std::max(st->max_window, (int32_t)ws.host_counters[5]);
+    st->cycles_a += (int64_t)ws.host_counters[6];
+    st->cycles_b += (int64_t)ws.host_counters[7];
   }
   return AR_OK;
 }

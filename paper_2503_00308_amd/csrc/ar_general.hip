@@ -5,11 +5,15 @@
 // Ind is a property of the Gaussian pair, not of the pixel, so it is decided once per
 // tile list in FP64 (k_runs) on two sound bounds of d_i - d_j: the identity
 // A_z (uw_i - uw_j) and the literal difference of the depth forms (1e-10 margin).
-// Lists are in order of the upper depth bound; with depth intervals [dlo, dhi] every
-// j whose dhi_j < dlo_i - m is in front of i for sure and every j whose
-// dhi_j >= dhi_i + wmax + m is behind for sure, so only the window between needs
-// the pairwise test.  The sets {j: Ind_ij = 1} and {j: Ind_ij != 0} are stored as
-// runs of list positions.
+// Lists are in order of the nominal depth c = m . uw (m: the depth row of A at the box
+// centre).  The identity bound lies within sum_l |uw_i,l - uw_j,l| R_l of c_i - c_j,
+// R_l the total radius of the form A_z,l, so with the bounding box of the list's means
+// every j with c_j < c_i - rho_i - margin has Ind_ij = 1 and every j with
+// c_j > c_i + rho_i + margin has Ind_ij = 0 (rho_i = sum_l R_l times the distance of
+// uw_i,l to the far side of the box); only the window between needs the pairwise
+// test.  Translation uncertainty cancels in d_i - d_j, so the window is much narrower
+// than one from depth intervals.  The sets {j: Ind_ij = 1} and {j: Ind_ij != 0} are
+// stored as runs of list positions.
 //
 // The pixel loop (k_raster_general) has two phases per tile:
 //   A: every wave takes a contiguous segment of the list and writes, per pixel, the
@@ -29,25 +33,41 @@ namespace ar {
 constexpr double kIndMargin = 1e-10;   // margin of the literal depth-difference test
 constexpr double kWinMargin = 1e-9;    // margin of the depth-interval window
 
-// widest depth interval of each tile's list
-__global__ __launch_bounds__(256) void k_tile_wmax(const uint32_t *__restrict__ ranges,
-                                                   const uint32_t *__restrict__ lists,
-                                                   const double *__restrict__ dint, double *__restrict__ wmax) {
-  __shared__ double red[256];
-  const int tile = blockIdx.x;
-  const uint32_t beg = ranges[2 * tile], end = ranges[2 * tile + 1];
-  double m = 0.0;
+// bounding box of the means of each list's Gaussians (items cell * n + g)
+__global__ __launch_bounds__(256) void k_list_box(const uint32_t *__restrict__ ranges,
+                                                  const uint32_t *__restrict__ lists, SceneDev sc, int ntiles,
+                                                  double *__restrict__ lbox) {
+  __shared__ double red[6][256];
+  const int lst = blockIdx.x;
+  const size_t gbase = (size_t)(lst / ntiles) * sc.n;
+  const uint32_t beg = ranges[2 * lst], end = ranges[2 * lst + 1];
+  double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (uint32_t p = beg + threadIdx.x; p < end; p += 256) {
-    const uint32_t g = lists[p];
-    m = fmax(m, dint[2 * (size_t)g + 1] - dint[2 * (size_t)g]);
+    const size_t g = lists[p] - gbase;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const double u = (double)sc.mean[(size_t)l * sc.n + g];
+      mn[l] = fmin(mn[l], u);
+      mx[l] = fmax(mx[l], u);
+    }
   }
-  red[threadIdx.x] = m;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    red[l][threadIdx.x] = mn[l];
+    red[3 + l][threadIdx.x] = mx[l];
+  }
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    if (threadIdx.x < off) {
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        red[l][threadIdx.x] = fmin(red[l][threadIdx.x], red[l][threadIdx.x + off]);
+        red[3 + l][threadIdx.x] = fmax(red[3 + l][threadIdx.x], red[3 + l][threadIdx.x + off]);
+      }
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) wmax[tile] = red[0];
+  if (threadIdx.x < 6) lbox[6 * (size_t)lst + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // Ind(d_i - d_j) in {0, 1, 2 = unknown} (see the file comment)
@@ -91,7 +111,7 @@ __device__ __forceinline__ int ind_pair(const PoseForms &pose, const double *uwi
 template <int P, bool EMIT>
 __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey, const uint32_t *__restrict__ ranges,
                                               const uint32_t *__restrict__ lists, const double *__restrict__ dint,
-                                              const double *__restrict__ dform, const double *__restrict__ wmax,
+                                              const double *__restrict__ dform, const double *__restrict__ lbox,
                                               const PoseForms *__restrict__ poses, int ntiles, SceneDev sc,
                                               int npairs, uint32_t *__restrict__ cnt, uint32_t *__restrict__ runs,
                                               unsigned long long *__restrict__ counters) {
@@ -105,26 +125,37 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
   const int i = p - beg;
   const uint32_t *list = lists + beg;
   const uint32_t gi = list[i];
-  const double dlo_i = dint[2 * (size_t)gi], dhi_i = dint[2 * (size_t)gi + 1];
-  // first position whose upper depth reaches dlo_i - m (all before are in front)
-  int a = 0, b = i;
-  const double t1 = dlo_i - kWinMargin;
-  while (a < b) {
-    const int mid = (a + b) >> 1;
-    if (dint[2 * (size_t)list[mid] + 1] < t1) a = mid + 1; else b = mid;
-  }
-  const int ps = a;
-  // first position whose upper depth reaches dhi_i + wmax + m (all from there are behind)
-  a = i;
-  b = n;
-  const double t2 = dhi_i + wmax[tile] + kWinMargin;
-  while (a < b) {
-    const int mid = (a + b) >> 1;
-    if (dint[2 * (size_t)list[mid] + 1] < t2) a = mid + 1; else b = mid;
-  }
-  const int qe = a;
   const size_t li = gi - gbase;
   const double uwi[3] = {sc.mean[li], sc.mean[sc.n + li], sc.mean[2 * sc.n + li]};
+  // rho_i >= sum_l R_l |uw_i,l - uw_j,l| for every j of the list (see the file comment)
+  const double *bx = lbox + 6 * (size_t)tile;
+  double rho = 0.0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const double *fl = pose.A[6 + l][0], *fu = pose.A[6 + l][1];
+    double R = 0.5 * (fu[kMaxP] - fl[kMaxP]);
+    for (int k = 0; k < kMaxP; ++k) R += fmax(fabs(fl[k]), fabs(fu[k]));
+    rho += R * fmax(uwi[l] - bx[l], bx[3 + l] - uwi[l]);
+  }
+  rho = rho * (1.0 + 0x1p-40) + kWinMargin;
+  const double c_i = dint[2 * (size_t)gi];
+  // first position with c >= c_i - rho (all before are in front for sure)
+  int a = 0, b = i;
+  const double t1 = c_i - rho;
+  while (a < b) {
+    const int mid = (a + b) >> 1;
+    if (dint[2 * (size_t)list[mid]] < t1) a = mid + 1; else b = mid;
+  }
+  const int ps = a;
+  // first position with c > c_i + rho (all from there are behind for sure)
+  a = i;
+  b = n;
+  const double t2 = c_i + rho;
+  while (a < b) {
+    const int mid = (a + b) >> 1;
+    if (dint[2 * (size_t)list[mid]] <= t2) a = mid + 1; else b = mid;
+  }
+  const int qe = a;
   const double *dfi = dform + (size_t)gi * 2 * (kMaxP + 1);
   uint32_t *out_def = nullptr, *out_may = nullptr;
   if (EMIT) {
@@ -188,7 +219,8 @@ __global__ __launch_bounds__(512) void k_raster_general(const double *__restrict
                                                         const uint32_t *__restrict__ runs, Params prm,
                                                         double2 *__restrict__ pre, uint32_t *__restrict__ prez,
                                                         float *__restrict__ out_lo, float *__restrict__ out_hi,
-                                                        unsigned long long *__restrict__ counters) {
+                                                        unsigned long long *__restrict__ counters, int list0,
+                                                        uint32_t pos0) {
   using R = Rec<P>;
   extern __shared__ double smem[];
   const int G = prm.groups;
@@ -198,7 +230,7 @@ __global__ __launch_bounds__(512) void k_raster_general(const double *__restrict
   double *red = smem + 2 * G * 64 + (G * 64 + 1) / 2; // [64][6(P+1)+4]
   const int lane = threadIdx.x & 63;
   const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lst = blockIdx.x;                    // list id: cell * ntiles + tile
+  const int lst = list0 + (int)blockIdx.x;      // list id: cell * ntiles + tile
   const int cell = lst / (prm.ntx * prm.nty), tile = lst % (prm.ntx * prm.nty);
   const int tx = tile % prm.ntx, ty = tile / prm.ntx;
   const int col = tx * kTile + (lane & 7), row = ty * kTile + (lane >> 3);
@@ -209,8 +241,10 @@ __global__ __launch_bounds__(512) void k_raster_general(const double *__restrict
   const int n = (int)ranges[2 * lst + 1] - beg;
   const uint32_t *list = lists + beg;
   const int s0 = (int)(((long long)g * n) / G), s1 = (int)(((long long)(g + 1) * n) / G);
+  const size_t pb = (size_t)((uint32_t)beg - pos0);   // the list's first entry in the prefix buffer
 
   // phase A: per-pixel running sums over this wave's segment
+  const long long c0 = clock64();
   double Ll = 0.0, Lh = 0.0;
   uint32_t Z = 0;
   unsigned long long npairs = 0;
@@ -226,8 +260,8 @@ __global__ __launch_bounds__(512) void k_raster_general(const double *__restrict
       if (ahi >= 1.0) ++Z;
       else Lh += log(1.0 - ahi);
     }
-    pre[(size_t)(beg + j) * 64 + lane] = make_double2(Ll, Lh);
-    prez[(size_t)(beg + j) * 64 + lane] = Z;
+    pre[(pb + j) * 64 + lane] = make_double2(Ll, Lh);
+    prez[(pb + j) * 64 + lane] = Z;
   }
   offl[g * 64 + lane] = Ll;
   offh[g * 64 + lane] = Lh;
@@ -250,6 +284,7 @@ __global__ __launch_bounds__(512) void k_raster_general(const double *__restrict
   __syncthreads();
 
   // phase B: transmittances from the runs, colour forms
+  const long long c1 = clock64();
   Acc<P> acc;
   acc_zero<P>(acc);
   const double nn = (double)(n + 2);
@@ -268,8 +303,8 @@ __global__ __launch_bounds__(512) void k_raster_general(const double *__restrict
     for (uint32_t r = d0; r < d1; ++r) {
       const int a = (int)runs[2 * (size_t)r], b = (int)runs[2 * (size_t)r + 1];
       double La = 0.0, Lb = 0.0;
-      if (a > 0) La = pre[(size_t)(beg + a - 1) * 64 + lane].x + offl[seg_of(a - 1, n, G) * 64 + lane];
-      if (b > 0) Lb = pre[(size_t)(beg + b - 1) * 64 + lane].x + offl[seg_of(b - 1, n, G) * 64 + lane];
+      if (a > 0) La = pre[(pb + a - 1) * 64 + lane].x + offl[seg_of(a - 1, n, G) * 64 + lane];
+      if (b > 0) Lb = pre[(pb + b - 1) * 64 + lane].x + offl[seg_of(b - 1, n, G) * 64 + lane];
       sum_l += Lb - La;
       err_l += fabs(La) + fabs(Lb);
     }
@@ -279,13 +314,13 @@ __global__ __launch_bounds__(512) void k_raster_general(const double *__restrict
       uint32_t Za = 0, Zb = 0;
       if (a > 0) {
         const int w = seg_of(a - 1, n, G);
-        La = pre[(size_t)(beg + a - 1) * 64 + lane].y + offh[w * 64 + lane];
-        Za = prez[(size_t)(beg + a - 1) * 64 + lane] + offz[w * 64 + lane];
+        La = pre[(pb + a - 1) * 64 + lane].y + offh[w * 64 + lane];
+        Za = prez[(pb + a - 1) * 64 + lane] + offz[w * 64 + lane];
       }
       if (b > 0) {
         const int w = seg_of(b - 1, n, G);
-        Lb = pre[(size_t)(beg + b - 1) * 64 + lane].y + offh[w * 64 + lane];
-        Zb = prez[(size_t)(beg + b - 1) * 64 + lane] + offz[w * 64 + lane];
+        Lb = pre[(pb + b - 1) * 64 + lane].y + offh[w * 64 + lane];
+        Zb = prez[(pb + b - 1) * 64 + lane] + offz[w * 64 + lane];
       }
       sum_h += Lb - La;
       err_h += fabs(La) + fabs(Lb);
@@ -298,6 +333,11 @@ __global__ __launch_bounds__(512) void k_raster_general(const double *__restrict
     pair_contrib<P>(rec, type, uxd, uyd, tlo, fmin(thi, 1.0), acc, alo, ahi, exp_table(gid));
     ++npairs;
   }
+  const long long c2 = clock64();
+  if (lane == 0) {
+    atomicAdd(&counters[6], (unsigned long long)(c1 - c0));
+    atomicAdd(&counters[7], (unsigned long long)(c2 - c1));
+  }
   acc_reduce<P>(acc, red, G, g, lane);
   unsigned long long c = npairs;
   for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
@@ -308,8 +348,9 @@ __global__ __launch_bounds__(512) void k_raster_general(const double *__restrict
 }
 
 // ---------------------------------------------------------------------------------
-hipError_t launch_tile_wmax(const Workspace &ws, const uint32_t *lists, int ntiles, hipStream_t s) {
-  hipLaunchKernelGGL(k_tile_wmax, dim3(ntiles), dim3(256), 0, s, ws.tile_range, lists, ws.dint, ws.wmax);
+hipError_t launch_list_box(const Workspace &ws, const uint32_t *lists, int nlists, int ntiles, const SceneDev &sc,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_list_box, dim3(nlists), dim3(256), 0, s, ws.tile_range, lists, sc, ntiles, ws.lbox);
   return hipGetLastError();
 }
 
@@ -319,10 +360,10 @@ static hipError_t launch_runs_p(const Workspace &ws, const uint32_t *lists, cons
   const dim3 grid((npairs + 255) / 256), block(256);
   if (emit)
     hipLaunchKernelGGL((k_runs<P, true>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint, ws.dform,
-                       ws.wmax, poses_dev, ntiles, sc, npairs, ws.run_cnt, ws.runs, ws.counters);
+                       ws.lbox, poses_dev, ntiles, sc, npairs, ws.run_cnt, ws.runs, ws.counters);
   else
     hipLaunchKernelGGL((k_runs<P, false>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint, ws.dform,
-                       ws.wmax, poses_dev, ntiles, sc, npairs, ws.run_cnt, ws.runs, ws.counters);
+                       ws.lbox, poses_dev, ntiles, sc, npairs, ws.run_cnt, ws.runs, ws.counters);
   return hipGetLastError();
 }
 
@@ -342,26 +383,26 @@ hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const 
 }
 
 template <int P>
-static hipError_t launch_general_p(const Workspace &ws, const uint32_t *lists, int nlists, const Params &prm,
-                                   float *lo, float *hi, hipStream_t s) {
+static hipError_t launch_general_p(const Workspace &ws, const uint32_t *lists, int list0, int nl, uint32_t pos0,
+                                   const Params &prm, float *lo, float *hi, hipStream_t s) {
   const int G = prm.groups;
   constexpr int kRed = 6 * (P + 1) + 3 + 1;
   const size_t shm = sizeof(double) * (2 * G * 64 + (G * 64 + 1) / 2 + 64 * kRed);
-  hipLaunchKernelGGL(k_raster_general<P>, dim3(nlists), dim3(64 * G), shm, s, ws.rec, ws.tile_range, lists,
-                     ws.run_cnt, ws.runs, prm, (double2 *)ws.pre, ws.prez, lo, hi, ws.counters);
+  hipLaunchKernelGGL(k_raster_general<P>, dim3(nl), dim3(64 * G), shm, s, ws.rec, ws.tile_range, lists, ws.run_cnt,
+                     ws.runs, prm, (double2 *)ws.pre, ws.prez, lo, hi, ws.counters, list0, pos0);
   return hipGetLastError();
 }
 
-hipError_t launch_raster_general(int P, const Workspace &ws, const uint32_t *lists, int nlists, const Params &prm,
-                                 float *lo, float *hi, hipStream_t s) {
+hipError_t launch_raster_general(int P, const Workspace &ws, const uint32_t *lists, int list0, int nl, uint32_t pos0,
+                                 const Params &prm, float *lo, float *hi, hipStream_t s) {
   switch (P) {
-    case 0: return launch_general_p<0>(ws, lists, nlists, prm, lo, hi, s);
-    case 1: return launch_general_p<1>(ws, lists, nlists, prm, lo, hi, s);
-    case 2: return launch_general_p<2>(ws, lists, nlists, prm, lo, hi, s);
-    case 3: return launch_general_p<3>(ws, lists, nlists, prm, lo, hi, s);
-    case 4: return launch_general_p<4>(ws, lists, nlists, prm, lo, hi, s);
-    case 5: return launch_general_p<5>(ws, lists, nlists, prm, lo, hi, s);
-    case 6: return launch_general_p<6>(ws, lists, nlists, prm, lo, hi, s);
+    case 0: return launch_general_p<0>(ws, lists, list0, nl, pos0, prm, lo, hi, s);
+    case 1: return launch_general_p<1>(ws, lists, list0, nl, pos0, prm, lo, hi, s);
+    case 2: return launch_general_p<2>(ws, lists, list0, nl, pos0, prm, lo, hi, s);
+    case 3: return launch_general_p<3>(ws, lists, list0, nl, pos0, prm, lo, hi, s);
+    case 4: return launch_general_p<4>(ws, lists, list0, nl, pos0, prm, lo, hi, s);
+    case 5: return launch_general_p<5>(ws, lists, list0, nl, pos0, prm, lo, hi, s);
+    case 6: return launch_general_p<6>(ws, lists, list0, nl, pos0, prm, lo, hi, s);
   }
   return hipErrorInvalidValue;
 }

@@ -88,6 +88,8 @@ struct Params {
   double t_min;
   int32_t ntx, nty;    // tiles
   int32_t groups, chunk;
+  int32_t prefix_entries;   // rotation path: list entries per pixel-loop launch
+  int32_t nominal_order;    // rotation path: order lists by the nominal depth (else by the upper bound)
 };
 
 struct SceneDev {
@@ -133,8 +135,8 @@ struct Workspace {
   double *part = nullptr;        // [segments][fields][64]
   size_t cap_part = 0;           // doubles
   // general (rotation) path
-  double *dint = nullptr;      // [n][2] depth interval (lo, hi) by gid
-  double *wmax = nullptr;      // [tiles] widest depth interval of the tile's list
+  double *dint = nullptr;      // [n][2] (nominal depth, upper depth bound) by item
+  double *lbox = nullptr;      // [lists][6] bounding box of the means of a list's Gaussians
   uint32_t *run_cnt = nullptr; // [pairs][2] + 1: Def / May run counts, then offsets
   size_t cap_run_cnt = 0;
   uint32_t *runs = nullptr;    // [runs][2] list-position ranges [start, end)
@@ -142,6 +144,8 @@ struct Workspace {
   double *pre = nullptr;       // [pairs][64][2] per-pixel prefix sums of log(1 - a_lo), log(1 - a_hi)
   uint32_t *prez = nullptr;    // [pairs][64] per-pixel prefix counts of a_hi == 1
   size_t cap_pre = 0;
+  uint32_t *host_ranges = nullptr;   // pinned copy of tile_range (rotation path)
+  size_t cap_host_ranges = 0;
 };
 
 // ---- launchers (ar_project.hip) ----
@@ -201,11 +205,14 @@ hipError_t launch_segment_map(const Workspace &ws, int nlists, hipStream_t s);
 hipError_t launch_raster_translation(int P, const Workspace &ws, const uint32_t *lists, int nlists, const Params &prm,
                                      int L, int nseg_max, float *lo, float *hi, hipStream_t s);
 // general path (ar_general.hip)
-hipError_t launch_tile_wmax(const Workspace &ws, const uint32_t *lists, int nlists, hipStream_t s);
+hipError_t launch_list_box(const Workspace &ws, const uint32_t *lists, int nlists, int ntiles, const SceneDev &sc,
+                           hipStream_t s);
 // poses_dev[cell] for list ids cell * ntiles + tile
 hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
                        const SceneDev &sc, int npairs, bool emit, hipStream_t s);
-hipError_t launch_raster_general(int P, const Workspace &ws, const uint32_t *lists, int nlists, const Params &prm,
-                                 float *lo, float *hi, hipStream_t s);
+// lists list0 .. list0 + nl - 1, whose entries start at position pos0 (the prefix buffer
+// holds the entries of these lists only)
+hipError_t launch_raster_general(int P, const Workspace &ws, const uint32_t *lists, int list0, int nl, uint32_t pos0,
+                                 const Params &prm, float *lo, float *hi, hipStream_t s);
 
 }  // namespace ar

@@ -326,7 +326,12 @@ __device__ __forceinline__ void project_one(const SceneDev &sc, const PoseForms 
   if (type == kDropped) atomicAdd(&counters[4], 1ull);
 
   // depth key and depth forms (rank order, Ind)
-  const uint64_t key = order_key(dropped ? INFINITY : dhi);
+  // nominal depth: the depth row of A at the box centre applied to uw (the terms common
+  // to all Gaussians, tau and beta, are left out: they cancel in depth differences)
+  double cnom = 0.0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) cnom += 0.5 * (pose.A[6 + l][0][kMaxP] + pose.A[6 + l][1][kMaxP]) * uw[l];
+  const uint64_t key = order_key(dropped ? INFINITY : (prm.nominal_order ? cnom : dhi));
   key_out[oi] = key;
   key_sort[oi] = key;
   double *df = dform_out + oi * 2 * (kMaxP + 1);
@@ -334,7 +339,7 @@ __device__ __forceinline__ void project_one(const SceneDev &sc, const PoseForms 
   for (int k = 0; k < P; ++k) { df[k] = d.lo[k]; df[kMaxP + 1 + k] = d.up[k]; }
   df[kMaxP] = d.lo[P];
   df[2 * kMaxP + 1] = d.up[P];
-  dint_out[2 * oi] = dlo;
+  dint_out[2 * oi] = cnom;
   dint_out[2 * oi + 1] = dhi;
 
   // record

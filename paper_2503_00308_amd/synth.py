@@ -61,14 +61,14 @@ def random_scene(n, seed=0, depth=4.0):
     return _pack(mean, R, scales, opacity, rgb)
 
 
-def box_surface_scene(n, n_boxes=20, seed=0):
+def box_surface_scene(n, n_boxes=20, seed=0, scale=1.0):
     """Gaussians on the surfaces of random boxes (object-scale scene).
 
     Box centres uniform in [-1,1]^2 x [3,5], half-extents uniform [0.1, 0.4], random yaw;
     an equal share of Gaussians per box, uniform by area over its six faces; flat
-    Gaussians (tangential scales log-uniform [0.01, 0.05], normal scale 0.2x the
-    smaller tangential one) aligned with the face; RGB = box colour + N(0, 0.05)
-    clipped to [0,1]; opacity ~ Beta(2, 2).
+    Gaussians (tangential scales log-uniform [0.01, 0.05] times `scale`, normal scale
+    0.2x the smaller tangential one) aligned with the face; RGB = box colour +
+    N(0, 0.05) clipped to [0,1]; opacity ~ Beta(2, 2).
     """
     rng = np.random.default_rng(seed)
     per = np.full(n_boxes, n // n_boxes)
@@ -96,7 +96,7 @@ def box_surface_scene(n, n_boxes=20, seed=0):
             local[:, t1] = rng.uniform(-h[t1], h[t1], m)
             local[:, t2] = rng.uniform(-h[t2], h[t2], m)
             means.append(local @ Rb.T + c)
-            tang = np.exp(rng.uniform(np.log(0.01), np.log(0.05), (m, 2)))
+            tang = scale * np.exp(rng.uniform(np.log(0.01), np.log(0.05), (m, 2)))
             sc = np.zeros((m, 3))
             sc[:, t1] = tang[:, 0]
             sc[:, t2] = tang[:, 1]
@@ -175,19 +175,26 @@ def config(idx, seed=0):
 
 
 def served_scenes(seed=0):
-    """Four resident scenes of the serving workload (10k, 100k, 300k, 750k Gaussians)."""
-    return [box_surface_scene(n, seed=seed + i) for i, n in enumerate((10_000, 100_000, 300_000, 750_000))]
+    """Four resident scenes of the serving workload (10k, 100k, 300k, 750k Gaussians).
+
+    Gaussian sizes shrink as the count grows, sqrt(1e5 / n) times those of the 100k
+    object scene, so every scene covers its boxes with a similar number of layers (a
+    trained splat adapts Gaussian size to detail in the same way)."""
+    return [box_surface_scene(n, seed=seed + i, scale=float(np.sqrt(1e5 / n)))
+            for i, n in enumerate((10_000, 100_000, 300_000, 750_000))]
 
 
 def served_queries(n_queries, seed=0):
-    """Query stream: (scene index, image side, box) with translation full widths U[0.01, 0.1]
-    per axis and rotation full widths U[0, 2] degrees per axis."""
+    """Query stream: (scene index, image side, box); scene and image side (100, 200, 400
+    or 800) drawn independently and uniformly, translation full widths U[0.01, 0.1] per
+    axis and rotation full widths U[0, 2] degrees per axis."""
     rng = np.random.default_rng(seed)
     sides = (100, 200, 400, 800)
     out = []
     for _ in range(n_queries):
         s = int(rng.integers(0, 4))
+        side = sides[int(rng.integers(0, 4))]
         dt = 0.5 * rng.uniform(0.01, 0.1, 3)
         dr = 0.5 * np.deg2rad(rng.uniform(0.0, 2.0, 3))
-        out.append((s, sides[s], camera6_box(dt=dt, drot=dr)))
+        out.append((s, side, camera6_box(dt=dt, drot=dr)))
     return out

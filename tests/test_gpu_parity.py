@@ -205,3 +205,15 @@ def test_single_rotation_axis_parity():
     glo, ghi, _ = _run(sc, intr, box)
     ref = _oracle(sc, intr, box)
     _compare("roll", glo, ghi, ref)
+
+
+def test_rotation_pixel_loop_in_chunks_of_lists():
+    """Launching the rotation pixel loop over chunks of tile lists (a small prefix-sum
+    buffer reused per chunk) gives the same bounds as one launch."""
+    sc = synth.box_surface_scene(2000, n_boxes=20, seed=4)
+    intr = synth.intrinsics(64)
+    box = synth.camera6_box(dt=0.05, drot=np.deg2rad(1.0))
+    glo, ghi, _ = _run(sc, intr, box)
+    clo, chi, st = _run(sc, intr, box, {"prefix_entries": 200})
+    print("chunked rotation stats", st, flush=True)
+    assert np.array_equal(glo, clo) and np.array_equal(ghi, chi)
