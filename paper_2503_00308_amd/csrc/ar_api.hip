@@ -39,6 +39,7 @@ void release_workspace(Workspace &ws) {
   for (auto &kv : ws.sizes) (void)hipFree(kv.first);
   if (ws.host_counters) (void)hipHostFree(ws.host_counters);
   if (ws.host_ranges) (void)hipHostFree(ws.host_ranges);
+  if (ws.host_seg) (void)hipHostFree(ws.host_seg);
   if (ws.pose_host) (void)hipHostFree(ws.pose_host);
   for (int i = 0; i < 4; ++i)
     if (ws.ev[i]) (void)hipEventDestroy(ws.ev[i]);
@@ -181,6 +182,8 @@ static int ensure_ws(Workspace &ws, size_t n_total, size_t nlists, int P, int nc
 // Rotation path: list entries whose per-pixel prefix sums are held at once (the pixel
 // loop runs over chunks of tile lists with at most this many entries, or one list).
 constexpr size_t kPrefixEntries = (size_t)1 << 21;   // 2M entries, 2.7 GB
+constexpr size_t kRotChunkSegs = (size_t)1 << 16;    // segments per launch of the rotation pixel loop
+constexpr int kRotSegment = 128;                     // list positions per segment (rotation path)
 
 // buffers of the general path: run counts for npairs list positions, pinned list ranges
 static int ensure_general(Workspace &ws, size_t npairs, size_t nlists) {
@@ -216,6 +219,50 @@ static int ensure_runs(Workspace &ws, size_t nruns) {
   ws.cap_runs = need;
   return AR_OK;
 }
+
+// rotation path: pinned segment table (offsets of nlists lists, then segment -> list)
+// and its device copy
+static int ensure_rot_segments(Workspace &ws, size_t nlists, size_t nseg) {
+  const size_t host_need = nlists + 1 + nseg;
+  if (host_need > ws.cap_host_seg || !ws.host_seg) {
+    if (ws.host_seg) HIP_TRY(hipHostFree(ws.host_seg));
+    ws.host_seg = nullptr;
+    const size_t need = host_need + host_need / 4 + 1024;
+    HIP_TRY(hipHostMalloc((void **)&ws.host_seg, need * sizeof(uint32_t), hipHostMallocDefault));
+    ws.cap_host_seg = need;
+  }
+  if (nlists + 2 > ws.cap_seg_off || !ws.seg_off) {
+    HIP_TRY(grow(ws, ws.seg_off, nlists + 2));
+    ws.cap_seg_off = nlists + 2;
+  }
+  if (nseg > ws.cap_seg || !ws.seg_tile) {
+    const size_t need = nseg + nseg / 4 + 1024;
+    HIP_TRY(grow(ws, ws.seg_tile, need));
+    ws.cap_seg = need;
+  }
+  return AR_OK;
+}
+
+// rotation path: segment totals and partial colour sums for nseg segments of one launch
+static int ensure_rot_parts(Workspace &ws, size_t nseg, int P) {
+  if (nseg > ws.cap_segsum || !ws.segsum) {
+    const size_t need = nseg + nseg / 4 + 256;
+    HIP_TRY(grow(ws, ws.segsum, need * kTilePix * 2));
+    HIP_TRY(grow(ws, ws.segz, need * kTilePix));
+    ws.cap_segsum = need;
+  }
+  const size_t doubles = nseg * (size_t)part_fields(P) * kTilePix;
+  if (doubles > ws.cap_part || !ws.part) {
+    const size_t need = doubles + doubles / 4 + 4096;
+    HIP_TRY(grow(ws, ws.part, need));
+    ws.cap_part = need;
+  }
+  return AR_OK;
+}
+
+// Segment length of the rotation pixel loop: fixed (not tied to the size of the call),
+// so a cell gives the same bounds alone and in a batch.
+static int rot_segment_length(const Params &prm) { return prm.chunk > 0 ? prm.chunk : kRotSegment; }
 
 // translation path: segment table and partial results for up to nseg segments
 static int ensure_segments(Workspace &ws, size_t ntiles, size_t nseg, int P) {
@@ -286,6 +333,8 @@ size_t query_bytes(const ar_scene *sc, const Params &prm, int P, bool rotates, i
   double b = items * per_item + pairs * 20.0 + lists * 24.0 + (double)(16 << 20);
   if (rotates) {
     b += pairs * (8.0 + 16.0) + std::min(pairs, (double)kPrefixEntries) * 64.0 * 20.0 * 1.125;
+    const double segs = pairs / kRotSegment + lists;
+    b += segs * 4.0 + std::min(segs, (double)kRotChunkSegs) * (8.0 * part_fields(P) * 64.0 + 20.0 * 64.0);
   } else {
     const double segs = std::min(8192.0 + lists, pairs / 32.0 + lists);
     b += segs * (8.0 * part_fields(P) * 64.0 + 8.0);
@@ -395,18 +444,35 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
     if (st) st->runs += nruns;
     rc = ensure_runs(ws, nruns);
     if (rc) return rc;
-    // chunks of consecutive lists with at most kPrefixEntries entries (or one longer list)
+    // segments of L positions per list (the last one ragged), then chunks of consecutive
+    // lists with at most kPrefixEntries entries and kRotChunkSegs segments (or one longer list)
     const uint32_t *R = ws.host_ranges;
-    size_t longest = 0;
-    for (size_t l = 0; l < nlists; ++l) longest = std::max<size_t>(longest, R[2 * l + 1] - R[2 * l]);
+    const int L = rot_segment_length(prm);
+    size_t nseg_total = 0, longest = 0;
+    for (size_t l = 0; l < nlists; ++l) {
+      const size_t nl = R[2 * l + 1] - R[2 * l];
+      longest = std::max(longest, nl);
+      nseg_total += (nl + (size_t)L - 1) / (size_t)L;
+    }
     const size_t want = prm.prefix_entries > 0 ? (size_t)prm.prefix_entries : kPrefixEntries;
     rc = ensure_prefix(ws, std::min<size_t>(npairs, std::max(want, longest)));
     if (rc) return rc;
-    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, true, s));
-    HIP_TRY(hipEventRecord(ws.ev[1], s));
+    rc = ensure_rot_segments(ws, nlists, nseg_total);
+    if (rc) return rc;
+    uint32_t *so = ws.host_seg, *stl = ws.host_seg + (nlists + 1);
+    so[0] = 0;
+    for (size_t l = 0, k = 0; l < nlists; ++l) {
+      const uint32_t ns = (R[2 * l + 1] - R[2 * l] + (uint32_t)L - 1) / (uint32_t)L;
+      for (uint32_t j = 0; j < ns; ++j) stl[k++] = (uint32_t)l;
+      so[l + 1] = so[l] + ns;
+    }
+    HIP_TRY(hipMemcpyAsync(ws.seg_off, so, (nlists + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    if (nseg_total)
+      HIP_TRY(hipMemcpyAsync(ws.seg_tile, stl, nseg_total * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     const size_t cap = std::max(std::min<size_t>(ws.cap_pre, want), longest);
-    size_t l = 0;
-    while (l < nlists) {
+    std::vector<RotChunk> chunks;
+    size_t max_segs = 0;
+    for (size_t l = 0; l < nlists;) {
       size_t l1 = l;
       uint32_t pos0 = 0;
       bool have = false;
@@ -416,15 +482,28 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
           if (!have) {
             pos0 = b;
             have = true;
-          } else if ((size_t)(e - pos0) > cap) {
+          } else if ((size_t)(e - pos0) > cap || so[l1 + 1] - so[l] > kRotChunkSegs) {
             break;
           }
         }
         ++l1;
       }
-      HIP_TRY(launch_raster_general(P, ws, ws.pair_val, (int)l, (int)(l1 - l), pos0, prm, lo, hi, s));
+      RotChunk c;
+      c.list0 = (int)l;
+      c.nl = (int)(l1 - l);
+      c.seg0 = (int)so[l];
+      c.nseg = (int)(so[l1] - so[l]);
+      c.L = L;
+      c.pos0 = pos0;
+      chunks.push_back(c);
+      max_segs = std::max(max_segs, (size_t)c.nseg);
       l = l1;
     }
+    rc = ensure_rot_parts(ws, max_segs, P);
+    if (rc) return rc;
+    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, true, s));
+    HIP_TRY(hipEventRecord(ws.ev[1], s));
+    for (const RotChunk &c : chunks) HIP_TRY(launch_raster_general(P, ws, ws.pair_val, c, prm, lo, hi, s));
     HIP_TRY(hipEventRecord(ws.ev[2], s));
   }
   HIP_TRY(hipEventRecord(ws.ev[3], s));

@@ -15,14 +15,18 @@
 // than one from depth intervals.  The sets {j: Ind_ij = 1} and {j: Ind_ij != 0} are
 // stored as runs of list positions.
 //
-// The pixel loop (k_raster_general) has two phases per tile:
-//   A: every wave takes a contiguous segment of the list and writes, per pixel, the
-//      running sums of log(1 - a_lo) and log(1 - a_hi) (FP64) and the running count
-//      of a_hi = 1; segment totals are exchanged through LDS;
-//   B: for each Gaussian i, the product over a run [a, b) is exp(L(b) - L(a)), so
-//      T_lo[i], T_hi[i] cost two loads per run; the colour forms are then accumulated
-//      as in the translation loop.
-// The prefix sums carry a rounding bound that is added outward before exp.
+// The pixel loop works on segments of L list positions, one wave per segment, one lane
+// per pixel of the 8x8 tile:
+//   A (k_rot_prefix): per pixel, running sums of log(1 - a_lo) and log(1 - a_hi) (FP64)
+//      and the running count of a_hi = 1 over the segment, and the segment totals;
+//   k_rot_offsets: per list, the running totals in front of each segment;
+//   B (k_rot_blend): for each Gaussian i, the product over a run [a, b) is
+//      exp(S(b-1) - S(a-1)), S = segment offset + running sum, so T_lo[i] and T_hi[i]
+//      cost two loads per run end; the colour forms are accumulated with these
+//      absolute transmittances, so a tile's bounds are the sum over its segments
+//      (k_rot_merge).
+// Equal-length segments spread a long tile list over many waves.  The prefix sums
+// carry a rounding bound that is added outward before exp.
 #include <hip/hip_runtime.h>
 
 #include "ar_blend.h"
@@ -202,58 +206,62 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
   }
 }
 
-// offset of list position x: its segment's start total (segments of G waves)
-__device__ __forceinline__ int seg_of(int x, int n, int G) {
-  // segment w covers [w n / G, (w + 1) n / G)
-  int w = (int)(((long long)x * G) / n);
-  while (w > 0 && x < (int)(((long long)w * n) / G)) --w;
-  while (w + 1 < G && x >= (int)(((long long)(w + 1) * n) / G)) ++w;
-  return w;
+// ---------------------------------------------------------------------------------
+// pixel loop over list segments (one wave per segment of L list positions)
+// ---------------------------------------------------------------------------------
+// Segment s of list l covers positions [(s - seg_off[l]) L, ...) of the list.  All
+// arrays of a launch are relative to its first segment seg0 and its first list entry
+// pos0 (a launch covers a chunk of consecutive lists).
+
+struct SegRef {
+  int list, beg, n, i0, i1;
+};
+
+__device__ __forceinline__ SegRef seg_ref(const uint32_t *__restrict__ ranges, const uint32_t *__restrict__ seg_off,
+                                          const uint32_t *__restrict__ seg_tile, int s, int L) {
+  SegRef r;
+  r.list = (int)seg_tile[s];
+  r.beg = (int)ranges[2 * r.list];
+  r.n = (int)ranges[2 * r.list + 1] - r.beg;
+  r.i0 = (s - (int)seg_off[r.list]) * L;
+  r.i1 = min(r.i0 + L, r.n);
+  return r;
 }
 
+// A: per pixel, running sums of log(1 - a_lo) and log(1 - a_hi) and the count of
+// a_hi = 1 over the segment (from zero at its start), and the segment totals.
 template <int P>
-__global__ __launch_bounds__(512) void k_raster_general(const double *__restrict__ recs,
-                                                        const uint32_t *__restrict__ ranges,
-                                                        const uint32_t *__restrict__ lists,
-                                                        const uint32_t *__restrict__ cnt,
-                                                        const uint32_t *__restrict__ runs, Params prm,
-                                                        double2 *__restrict__ pre, uint32_t *__restrict__ prez,
-                                                        float *__restrict__ out_lo, float *__restrict__ out_hi,
-                                                        unsigned long long *__restrict__ counters, int list0,
-                                                        uint32_t pos0) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rot_prefix(const double *__restrict__ recs,
+                                                    const uint32_t *__restrict__ ranges,
+                                                    const uint32_t *__restrict__ lists,
+                                                    const uint32_t *__restrict__ seg_off,
+                                                    const uint32_t *__restrict__ seg_tile, int L, int seg0, int nseg,
+                                                    uint32_t pos0, Params prm, double2 *__restrict__ pre,
+                                                    uint32_t *__restrict__ prez, double2 *__restrict__ segsum,
+                                                    uint32_t *__restrict__ segz,
+                                                    unsigned long long *__restrict__ counters) {
   using R = Rec<P>;
-  extern __shared__ double smem[];
-  const int G = prm.groups;
-  double *offl = smem;                   // [G][64] segment start of sum log(1 - a_lo)
-  double *offh = smem + G * 64;          // [G][64] segment start of sum log(1 - a_hi)
-  uint32_t *offz = (uint32_t *)(smem + 2 * G * 64);   // [G][64]
-  double *red = smem + 2 * G * 64 + (G * 64 + 1) / 2; // [64][6(P+1)+4]
   const int lane = threadIdx.x & 63;
-  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lst = list0 + (int)blockIdx.x;      // list id: cell * ntiles + tile
-  const int cell = lst / (prm.ntx * prm.nty), tile = lst % (prm.ntx * prm.nty);
+  const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+  if (w >= nseg) return;
+  const long long c0 = clock64();
+  const SegRef r = seg_ref(ranges, seg_off, seg_tile, seg0 + w, L);
+  const int ntiles = prm.ntx * prm.nty;
+  const int tile = r.list % ntiles;
   const int tx = tile % prm.ntx, ty = tile / prm.ntx;
   const int col = tx * kTile + (lane & 7), row = ty * kTile + (lane >> 3);
   const bool inimg = col < prm.width && row < prm.height;
   const double uxd = (double)col + 0.5 - prm.cx, uyd = (double)row + 0.5 - prm.cy;
   const float ux = (float)uxd, uy = (float)uyd;
-  const int beg = (int)ranges[2 * lst];
-  const int n = (int)ranges[2 * lst + 1] - beg;
-  const uint32_t *list = lists + beg;
-  const int s0 = (int)(((long long)g * n) / G), s1 = (int)(((long long)(g + 1) * n) / G);
-  const size_t pb = (size_t)((uint32_t)beg - pos0);   // the list's first entry in the prefix buffer
-
-  // phase A: per-pixel running sums over this wave's segment
-  const long long c0 = clock64();
+  const uint32_t *items = lists + r.beg;
+  const size_t pb = (size_t)((uint32_t)r.beg - pos0);
   double Ll = 0.0, Lh = 0.0;
   uint32_t Z = 0;
-  unsigned long long npairs = 0;
-  for (int j = s0; j < s1; ++j) {
-    const uint32_t gid = list[j];
+  for (int j = r.i0; j < r.i1; ++j) {
+    const uint32_t gid = items[j];
     const double *rec = recs + (size_t)gid * R::STRIDE;
     const int type = rec_type<P>(rec);
-    const bool kept = inimg && pair_kept<P>(rec, type, ux, uy);
-    if (kept) {
+    if (inimg && pair_kept<P>(rec, type, ux, uy)) {
       double alo, ahi;
       alpha_interval<P>(rec, type, uxd, uyd, alo, ahi, exp_table(gid));
       Ll += log(1.0 - alo);
@@ -263,64 +271,100 @@ __global__ __launch_bounds__(512) void k_raster_general(const double *__restrict
     pre[(pb + j) * 64 + lane] = make_double2(Ll, Lh);
     prez[(pb + j) * 64 + lane] = Z;
   }
-  offl[g * 64 + lane] = Ll;
-  offh[g * 64 + lane] = Lh;
-  offz[g * 64 + lane] = Z;
-  __syncthreads();
-  if (g == 0) {
-    double al = 0.0, ah = 0.0;
-    uint32_t az = 0;
-    for (int w = 0; w < G; ++w) {
-      const double tl = offl[w * 64 + lane], th = offh[w * 64 + lane];
-      const uint32_t tz = offz[w * 64 + lane];
-      offl[w * 64 + lane] = al;
-      offh[w * 64 + lane] = ah;
-      offz[w * 64 + lane] = az;
-      al += tl;
-      ah += th;
-      az += tz;
-    }
-  }
-  __syncthreads();
+  segsum[(size_t)w * 64 + lane] = make_double2(Ll, Lh);
+  segz[(size_t)w * 64 + lane] = Z;
+  if (lane == 0) atomicAdd(&counters[6], (unsigned long long)(clock64() - c0));
+}
 
-  // phase B: transmittances from the runs, colour forms
-  const long long c1 = clock64();
+// per list: exclusive running totals of its segments' sums (in place)
+__global__ __launch_bounds__(256) void k_rot_offsets(const uint32_t *__restrict__ seg_off, int list0, int nl, int seg0,
+                                                     double2 *__restrict__ segsum, uint32_t *__restrict__ segz) {
+  const int lane = threadIdx.x & 63;
+  const int k = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+  if (k >= nl) return;
+  const int s0 = (int)seg_off[list0 + k] - seg0, s1 = (int)seg_off[list0 + k + 1] - seg0;
+  double al = 0.0, ah = 0.0;
+  uint32_t az = 0;
+  for (int s = s0; s < s1; ++s) {
+    const double2 t = segsum[(size_t)s * 64 + lane];
+    const uint32_t tz = segz[(size_t)s * 64 + lane];
+    segsum[(size_t)s * 64 + lane] = make_double2(al, ah);
+    segz[(size_t)s * 64 + lane] = az;
+    al += t.x;
+    ah += t.y;
+    az += tz;
+  }
+}
+
+// B: transmittances from the runs (absolute: everything in front of the Gaussian),
+// colour forms accumulated per segment; the tile's bounds are the sum of its segments.
+template <int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rot_blend(const double *__restrict__ recs, const uint32_t *__restrict__ ranges,
+                                                   const uint32_t *__restrict__ lists,
+                                                   const uint32_t *__restrict__ seg_off,
+                                                   const uint32_t *__restrict__ seg_tile, int L, int seg0, int nseg,
+                                                   uint32_t pos0, const uint32_t *__restrict__ cnt,
+                                                   const uint32_t *__restrict__ runs, Params prm,
+                                                   const double2 *__restrict__ pre, const uint32_t *__restrict__ prez,
+                                                   const double2 *__restrict__ segoff,
+                                                   const uint32_t *__restrict__ segz, double *__restrict__ part,
+                                                   unsigned long long *__restrict__ counters) {
+  using R = Rec<P>;
+  using Q = Part<P>;
+  constexpr int F = P + 1;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+  if (w >= nseg) return;
+  const long long c0 = clock64();
+  const SegRef r = seg_ref(ranges, seg_off, seg_tile, seg0 + w, L);
+  const int ntiles = prm.ntx * prm.nty;
+  const int tile = r.list % ntiles;
+  const int tx = tile % prm.ntx, ty = tile / prm.ntx;
+  const int col = tx * kTile + (lane & 7), row = ty * kTile + (lane >> 3);
+  const bool inimg = col < prm.width && row < prm.height;
+  const double uxd = (double)col + 0.5 - prm.cx, uyd = (double)row + 0.5 - prm.cy;
+  const float ux = (float)uxd, uy = (float)uyd;
+  const uint32_t *items = lists + r.beg;
+  const size_t pb = (size_t)((uint32_t)r.beg - pos0);
+  const int sl = (int)seg_off[r.list] - seg0;     // the list's first segment, relative
+  const double nn = (double)(r.n + 2);
   Acc<P> acc;
   acc_zero<P>(acc);
-  const double nn = (double)(n + 2);
-  for (int i = s0; i < s1; ++i) {
-    const uint32_t gid = list[i];
+  unsigned npairs = 0;
+  for (int i = r.i0; i < r.i1; ++i) {
+    const uint32_t gid = items[i];
     const double *rec = recs + (size_t)gid * R::STRIDE;
     const int type = rec_type<P>(rec);
     const bool kept = inimg && pair_kept<P>(rec, type, ux, uy);
     if (!kept) continue;
-    const size_t slot = (size_t)(beg + i);
-    // runs of certain occluders and of possible occluders
+    const size_t slot = (size_t)(r.beg + i);
+    // runs of certain occluders and of possible occluders: sums of the logs over
+    // [a, b) = S(b - 1) - S(a - 1), S(p) = segment offset + running sum at p
     const uint32_t d0 = cnt[2 * slot], d1 = cnt[2 * slot + 1];
     const uint32_t m0 = cnt[2 * slot + 1], m1 = cnt[2 * slot + 2];
     double sum_l = 0.0, err_l = 0.0, sum_h = 0.0, err_h = 0.0;
     uint32_t zc = 0;
-    for (uint32_t r = d0; r < d1; ++r) {
-      const int a = (int)runs[2 * (size_t)r], b = (int)runs[2 * (size_t)r + 1];
+    for (uint32_t q = d0; q < d1; ++q) {
+      const int a = (int)runs[2 * (size_t)q], b = (int)runs[2 * (size_t)q + 1];
       double La = 0.0, Lb = 0.0;
-      if (a > 0) La = pre[(pb + a - 1) * 64 + lane].x + offl[seg_of(a - 1, n, G) * 64 + lane];
-      if (b > 0) Lb = pre[(pb + b - 1) * 64 + lane].x + offl[seg_of(b - 1, n, G) * 64 + lane];
+      if (a > 0) La = pre[(pb + a - 1) * 64 + lane].x + segoff[(size_t)(sl + (a - 1) / L) * 64 + lane].x;
+      if (b > 0) Lb = pre[(pb + b - 1) * 64 + lane].x + segoff[(size_t)(sl + (b - 1) / L) * 64 + lane].x;
       sum_l += Lb - La;
       err_l += fabs(La) + fabs(Lb);
     }
-    for (uint32_t r = m0; r < m1; ++r) {
-      const int a = (int)runs[2 * (size_t)r], b = (int)runs[2 * (size_t)r + 1];
+    for (uint32_t q = m0; q < m1; ++q) {
+      const int a = (int)runs[2 * (size_t)q], b = (int)runs[2 * (size_t)q + 1];
       double La = 0.0, Lb = 0.0;
       uint32_t Za = 0, Zb = 0;
       if (a > 0) {
-        const int w = seg_of(a - 1, n, G);
-        La = pre[(pb + a - 1) * 64 + lane].y + offh[w * 64 + lane];
-        Za = prez[(pb + a - 1) * 64 + lane] + offz[w * 64 + lane];
+        const size_t so = (size_t)(sl + (a - 1) / L) * 64 + lane;
+        La = pre[(pb + a - 1) * 64 + lane].y + segoff[so].y;
+        Za = prez[(pb + a - 1) * 64 + lane] + segz[so];
       }
       if (b > 0) {
-        const int w = seg_of(b - 1, n, G);
-        Lb = pre[(pb + b - 1) * 64 + lane].y + offh[w * 64 + lane];
-        Zb = prez[(pb + b - 1) * 64 + lane] + offz[w * 64 + lane];
+        const size_t so = (size_t)(sl + (b - 1) / L) * 64 + lane;
+        Lb = pre[(pb + b - 1) * 64 + lane].y + segoff[so].y;
+        Zb = prez[(pb + b - 1) * 64 + lane] + segz[so];
       }
       sum_h += Lb - La;
       err_h += fabs(La) + fabs(Lb);
@@ -333,18 +377,69 @@ __global__ __launch_bounds__(512) void k_raster_general(const double *__restrict
     pair_contrib<P>(rec, type, uxd, uyd, tlo, fmin(thi, 1.0), acc, alo, ahi, exp_table(gid));
     ++npairs;
   }
-  const long long c2 = clock64();
-  if (lane == 0) {
-    atomicAdd(&counters[6], (unsigned long long)(c1 - c0));
-    atomicAdd(&counters[7], (unsigned long long)(c2 - c1));
-  }
-  acc_reduce<P>(acc, red, G, g, lane);
-  unsigned long long c = npairs;
+  unsigned c = npairs;
   for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-  if (lane == 0 && c) atomicAdd(&counters[0], c);
-  if (g != 0 || !inimg) return;
+  double *q = part + (size_t)w * Q::NF * 64 + lane;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+#pragma unroll
+    for (int j = 0; j < F; ++j) {
+      q[(Q::LO + ch * F + j) * 64] = acc.lo[ch][j];
+      q[(Q::HI + ch * F + j) * 64] = acc.hi[ch][j];
+    }
+    q[(Q::IHI + ch) * 64] = acc.ihi[ch];
+  }
+  float2 mg;
+  mg.x = acc.magl;
+  mg.y = acc.magh;
+  q[Q::MAG * 64] = __builtin_bit_cast(double, mg);
+  q[Q::CNT * 64] = (double)c;
+  if (lane == 0) atomicAdd(&counters[7], (unsigned long long)(clock64() - c0));
+}
+
+// per list and colour channel (three waves): sum of the segments' colour sums, then the
+// pixel bounds
+template <int P>
+__global__ __launch_bounds__(192) void k_rot_merge(const uint32_t *__restrict__ ranges,
+                                                   const uint32_t *__restrict__ seg_off, int list0, int seg0,
+                                                   const double *__restrict__ part, Params prm,
+                                                   float *__restrict__ out_lo, float *__restrict__ out_hi,
+                                                   unsigned long long *__restrict__ counters) {
+  using Q = Part<P>;
+  constexpr int F = P + 1;
+  const int lane = threadIdx.x & 63;
+  const int ch = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int ntiles = prm.ntx * prm.nty;
+  const int list = list0 + (int)blockIdx.x;
+  const int cell = list / ntiles, tile = list % ntiles;
+  const int tx = tile % prm.ntx, ty = tile / prm.ntx;
+  const int col = tx * kTile + (lane & 7), row = ty * kTile + (lane >> 3);
+  const bool inimg = col < prm.width && row < prm.height;
+  const int s0 = (int)seg_off[list] - seg0, s1 = (int)seg_off[list + 1] - seg0;
+  double lo[F], hi[F], ihi = 0.0;
+#pragma unroll
+  for (int j = 0; j < F; ++j) { lo[j] = 0.0; hi[j] = 0.0; }
+  float magl = 0.0f, magh = 0.0f;
+  unsigned long long cn = 0;
+  for (int s = s0; s < s1; ++s) {
+    const double *q = part + (size_t)s * Q::NF * 64 + lane;
+#pragma unroll
+    for (int j = 0; j < F; ++j) {
+      lo[j] += q[(Q::LO + ch * F + j) * 64];
+      hi[j] += q[(Q::HI + ch * F + j) * 64];
+    }
+    ihi += q[(Q::IHI + ch) * 64];
+    const float2 mg = __builtin_bit_cast(float2, q[Q::MAG * 64]);
+    magl = (magl + mg.x) * (1.0f + 4.0f * kU32);
+    magh = (magh + mg.y) * (1.0f + 4.0f * kU32);
+    cn += (unsigned long long)q[Q::CNT * 64];
+  }
+  if (ch == 0 && lane == 0 && cn) atomicAdd(&counters[0], cn);
+  if (!inimg) return;
+  const int n = (int)(ranges[2 * list + 1] - ranges[2 * list]);
   const size_t img = (size_t)cell * prm.width * prm.height;
-  write_pixel<P>(acc, (double)n, prm.E, 0.0, out_lo, out_hi, (img + (size_t)row * prm.width + col) * 3);
+  write_channel<P>(lo, hi, ihi, magl, magh, (double)(n + 2 * (s1 - s0)), prm.E, 0.0, out_lo, out_hi,
+                   (img + (size_t)row * prm.width + col) * 3 + ch);
 }
 
 // ---------------------------------------------------------------------------------
@@ -383,26 +478,34 @@ hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const 
 }
 
 template <int P>
-static hipError_t launch_general_p(const Workspace &ws, const uint32_t *lists, int list0, int nl, uint32_t pos0,
-                                   const Params &prm, float *lo, float *hi, hipStream_t s) {
-  const int G = prm.groups;
-  constexpr int kRed = 6 * (P + 1) + 3 + 1;
-  const size_t shm = sizeof(double) * (2 * G * 64 + (G * 64 + 1) / 2 + 64 * kRed);
-  hipLaunchKernelGGL(k_raster_general<P>, dim3(nl), dim3(64 * G), shm, s, ws.rec, ws.tile_range, lists, ws.run_cnt,
-                     ws.runs, prm, (double2 *)ws.pre, ws.prez, lo, hi, ws.counters, list0, pos0);
+static hipError_t launch_rot_p(const Workspace &ws, const uint32_t *lists, const RotChunk &c, const Params &prm,
+                               float *lo, float *hi, hipStream_t s) {
+  const dim3 blk(256), grid((unsigned)((c.nseg + 3) / 4));
+  if (c.nseg > 0) {
+    hipLaunchKernelGGL(k_rot_prefix<P>, grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off, ws.seg_tile, c.L,
+                       c.seg0, c.nseg, c.pos0, prm, (double2 *)ws.pre, ws.prez, (double2 *)ws.segsum, ws.segz,
+                       ws.counters);
+    hipLaunchKernelGGL(k_rot_offsets, dim3((unsigned)((c.nl + 3) / 4)), blk, 0, s, ws.seg_off, c.list0, c.nl, c.seg0,
+                       (double2 *)ws.segsum, ws.segz);
+    hipLaunchKernelGGL(k_rot_blend<P>, grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off, ws.seg_tile, c.L,
+                       c.seg0, c.nseg, c.pos0, ws.run_cnt, ws.runs, prm, (const double2 *)ws.pre, ws.prez,
+                       (const double2 *)ws.segsum, ws.segz, ws.part, ws.counters);
+  }
+  hipLaunchKernelGGL(k_rot_merge<P>, dim3((unsigned)c.nl), dim3(192), 0, s, ws.tile_range, ws.seg_off, c.list0, c.seg0,
+                     ws.part, prm, lo, hi, ws.counters);
   return hipGetLastError();
 }
 
-hipError_t launch_raster_general(int P, const Workspace &ws, const uint32_t *lists, int list0, int nl, uint32_t pos0,
+hipError_t launch_raster_general(int P, const Workspace &ws, const uint32_t *lists, const RotChunk &c,
                                  const Params &prm, float *lo, float *hi, hipStream_t s) {
   switch (P) {
-    case 0: return launch_general_p<0>(ws, lists, list0, nl, pos0, prm, lo, hi, s);
-    case 1: return launch_general_p<1>(ws, lists, list0, nl, pos0, prm, lo, hi, s);
-    case 2: return launch_general_p<2>(ws, lists, list0, nl, pos0, prm, lo, hi, s);
-    case 3: return launch_general_p<3>(ws, lists, list0, nl, pos0, prm, lo, hi, s);
-    case 4: return launch_general_p<4>(ws, lists, list0, nl, pos0, prm, lo, hi, s);
-    case 5: return launch_general_p<5>(ws, lists, list0, nl, pos0, prm, lo, hi, s);
-    case 6: return launch_general_p<6>(ws, lists, list0, nl, pos0, prm, lo, hi, s);
+    case 0: return launch_rot_p<0>(ws, lists, c, prm, lo, hi, s);
+    case 1: return launch_rot_p<1>(ws, lists, c, prm, lo, hi, s);
+    case 2: return launch_rot_p<2>(ws, lists, c, prm, lo, hi, s);
+    case 3: return launch_rot_p<3>(ws, lists, c, prm, lo, hi, s);
+    case 4: return launch_rot_p<4>(ws, lists, c, prm, lo, hi, s);
+    case 5: return launch_rot_p<5>(ws, lists, c, prm, lo, hi, s);
+    case 6: return launch_rot_p<6>(ws, lists, c, prm, lo, hi, s);
   }
   return hipErrorInvalidValue;
 }

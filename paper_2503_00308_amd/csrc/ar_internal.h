@@ -146,6 +146,11 @@ struct Workspace {
   size_t cap_pre = 0;
   uint32_t *host_ranges = nullptr;   // pinned copy of tile_range (rotation path)
   size_t cap_host_ranges = 0;
+  uint32_t *host_seg = nullptr;      // pinned: segment offsets of the lists, then segment -> list
+  size_t cap_host_seg = 0;
+  double *segsum = nullptr;          // [segments][64][2] segment totals, then offsets
+  uint32_t *segz = nullptr;          // [segments][64]
+  size_t cap_segsum = 0;
 };
 
 // ---- launchers (ar_project.hip) ----
@@ -210,9 +215,13 @@ hipError_t launch_list_box(const Workspace &ws, const uint32_t *lists, int nlist
 // poses_dev[cell] for list ids cell * ntiles + tile
 hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
                        const SceneDev &sc, int npairs, bool emit, hipStream_t s);
-// lists list0 .. list0 + nl - 1, whose entries start at position pos0 (the prefix buffer
-// holds the entries of these lists only)
-hipError_t launch_raster_general(int P, const Workspace &ws, const uint32_t *lists, int list0, int nl, uint32_t pos0,
+// one launch of the rotation pixel loop: lists list0 .. list0 + nl - 1 with entries from
+// position pos0, their segments seg0 .. seg0 + nseg - 1 of L positions
+struct RotChunk {
+  int list0, nl, seg0, nseg, L;
+  uint32_t pos0;
+};
+hipError_t launch_raster_general(int P, const Workspace &ws, const uint32_t *lists, const RotChunk &c,
                                  const Params &prm, float *lo, float *hi, hipStream_t s);
 
 }  // namespace ar

@@ -213,21 +213,6 @@ __device__ __forceinline__ int cut_at(const uint32_t *__restrict__ list, const u
   return p;
 }
 
-// Partial result of one segment, NF columns of 64 doubles (one per pixel lane).
-template <int P>
-struct Part {
-  static constexpr int F = P + 1;
-  static constexpr int LO = 0;               // [3][F] lower colour forms
-  static constexpr int HI = 3 * F;           // [3][F] upper colour forms
-  static constexpr int IHI = 6 * F;          // [3] interval upper sums
-  static constexpr int TLO = 6 * F + 3;      // segment transmittance products
-  static constexpr int THI = 6 * F + 4;
-  static constexpr int MAG = 6 * F + 5;      // magnitude sums (two floats)
-  static constexpr int STOP = 6 * F + 6;     // 1 when the segment stopped early
-  static constexpr int CNT = 6 * F + 7;      // evaluated pairs of the wave (same in every lane)
-  static constexpr int NF = 6 * F + 8;
-};
-
 int part_fields(int P) { return 6 * (P + 1) + 8; }
 
 // Segments: tile t's list is cut into ceil(n_t / L) pieces of L positions.
