@@ -16,7 +16,6 @@ widths, all cells through ar_render_batch, against the per-query path) and "serv
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -32,10 +31,14 @@ PEAK_VALU_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, no
 PEAK_FP32_PACKED_TFLOPS = 157.3
 
 
+# sources the translation pixel kernel (k_raster_seg) is compiled from
+PIXEL_KERNEL_SOURCES = ("ar_raster.hip", "ar_blend.h", "ar_pair.h", "ar_expm.h", "ar_internal.h")
+
+
 def kernel_fingerprint() -> str:
-    """Hash of the HIP sources; a traffic measurement is only used while it matches."""
+    """Hash of the pixel kernel's sources; a traffic measurement is only used while it matches."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2503_00308_amd", "csrc", "*"))):
+    for f in [os.path.join(ROOT, "paper_2503_00308_amd", "csrc", n) for n in PIXEL_KERNEL_SOURCES]:
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode())
             h.update(fh.read())
