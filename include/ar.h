@@ -15,8 +15,8 @@
  *
  * Conventions
  *   camera axes x right, y down, z forward; a world point uw maps to
- *   uc = R (uw - t) with R world->camera and t the camera centre (Alg. GaussianSplat
- *   line 2); pixel (col, row) has centre (col + 1/2, row + 1/2); fx, fy, cx, cy the
+ *   uc = R (uw - t) with R world->camera and t the camera centre (Alg. GaussianSplat,
+ *   Step 1); pixel (col, row) has centre (col + 1/2, row + 1/2); fx, fy, cx, cy the
  *   pinhole intrinsics (Sec. 2.2, matrix K).
  *
  * Memory
@@ -105,10 +105,13 @@ typedef struct {
 /*
  * Options; a zero field takes the default.
  *   tile        pixel tile side of the binning and of one workgroup, 8 (only value)
- *   groups      waves per tile of the rotation path's pixel loop, 1..8 (default: chosen
- *               from the number of tiles)
- *   chunk       list positions per segment of the translation path's pixel loop
- *               (one wave each), 8..4096 (default: chosen from the number of pairs)
+ *   ind_window  rotation boxes: which pairs of a tile list get the pairwise Ind test;
+ *               0 = those inside the smaller of the two depth windows (default),
+ *               1 = inside the window from the box of the list's means only,
+ *               2 = every pair (slow; the result is the same, for checking)
+ *   chunk       list positions per segment of the pixel loop (one wave each),
+ *               8..4096 (default: translation boxes chosen from the number of pairs,
+ *               rotation boxes 128)
  *   taylor_k    MatrixInv order k (Sec. 3.1; default 8, the paper's default), 1..16
  *   cull_budget bound E on the colour change from pruning faint Gaussians (default 1e-7);
  *               Gaussian i is dropped from pixel u when its alpha is provably below
@@ -125,7 +128,7 @@ typedef struct {
  */
 typedef struct {
   int32_t tile;
-  int32_t groups;
+  int32_t ind_window;
   int32_t chunk;
   int32_t taylor_k;
   double cull_budget;

@@ -12,7 +12,7 @@ with A (3x3), tau (3) and beta (3) linear forms over the normalised pose box.
   around a nominal camera).  Pose p = (tx, ty, tz, yaw, pitch, roll);
   R(p) = Ry(yaw) Rx(pitch) Rz(roll) R0 (perturbation applied in the camera frame,
   products taken left to right with Mul), t(p) = t0 + (tx, ty, tz).
-  A = R(p), tau = t(p), beta = 0: exactly line 2 of the algorithm.
+  A = R(p), tau = t(p), beta = 0: exactly the camera transform of Step 1.
 * ORBIT -- camera rig turned by phi about the vertical axis through a pivot c:
   t(phi) = c + Ry(phi)(t0 - c), R(phi) = R0 Ry(phi)^T, hence
   uc = R0 Ry(-phi) (uw - c) + R0 (c - t0): A = R0 Ry(-phi), tau = c, beta = R0(c - t0).

@@ -6,7 +6,7 @@ Conventions (the paper leaves them open):
 * camera axes x right, y down, z forward; uc = R (uw - t), R world->camera;
 * pixel (col, row) has centre u = (col + 1/2, row + 1/2); the principal point is
   subtracted from u and dropped from K, so d^2 u - d up is evaluated as
-  d^2 (u - c) - d (fx x, fy y) (the same number, Alg. GaussianSplat line 9);
+  d^2 (u - c) - d (fx x, fy y) (the same number, the q step of Alg. GaussianSplat);
 * a Gaussian whose depth d is not above the near plane z_near has a = 0;
 * Gaussians at equal depth do not occlude one another: the transmittance of
   Gaussian i is the product of (1 - a_j) over the Gaussians strictly in front of
@@ -34,25 +34,25 @@ def project(scene, intr, R, t):
     """Steps 1-3a of the algorithm for every Gaussian at one camera (R, t)."""
     uw = np.asarray(scene["mean"], dtype=np.float64)
     Mw = np.asarray(scene["cov_factor"], dtype=np.float64)
-    uc = (uw - t) @ R.T                                     # line 2
-    Mc = np.einsum("kl,nlm->nkm", R, Mw)                    # line 3
+    uc = (uw - t) @ R.T                                     # Step 1: uc
+    Mc = np.einsum("kl,nlm->nkm", R, Mw)                    # Step 1: Mc
     x, y, z = uc[:, 0], uc[:, 1], uc[:, 2]
     fx, fy = intr["fx"], intr["fy"]
-    J = np.zeros((len(uw), 2, 3))                           # line 4
+    J = np.zeros((len(uw), 2, 3))                           # Step 2: J
     J[:, 0, 0] = fx * z
     J[:, 0, 2] = -fx * x
     J[:, 1, 1] = fy * z
     J[:, 1, 2] = -fy * y
-    upc = np.stack([fx * x, fy * y], axis=1)                # line 5, principal point removed
-    Mp = J @ Mc                                             # line 6
-    d = z                                                   # line 7
+    upc = np.stack([fx * x, fy * y], axis=1)                # Step 2: up, principal point removed
+    Mp = J @ Mc                                             # Step 2: Mp
+    d = z                                                   # Step 2: d
     X = Mp @ np.transpose(Mp, (0, 2, 1))
-    conic, det = inv2(X)                                    # line 8
+    conic, det = inv2(X)                                    # Step 3: Conic
     return {"d": d, "upc": upc, "Mp": Mp, "conic": conic, "det": det}
 
 
 def alpha(scene, intr, proj, ux, uy, z_near):
-    """Effective opacities a[i, pixel] (lines 9-10), shape (N, n_pixels)."""
+    """Effective opacities a[i, pixel] (the q and a steps of Step 3), shape (N, n_pixels)."""
     d = proj["d"][:, None]
     v0 = d * d * ux[None, :] - d * proj["upc"][:, 0:1]
     v1 = d * d * uy[None, :] - d * proj["upc"][:, 1:2]

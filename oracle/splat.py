@@ -3,25 +3,25 @@
 This is the oracle that the HIP path is checked against.  It follows Sec. 3.3
 (AbstractSplat): every input and intermediate of Alg. GaussianSplat becomes a
 pair of linear forms over the normalised pose box, every operation becomes its
-linear-relational counterpart (lf.py), line 8's inverse becomes MatrixInv
-(matinv.py) and line 11's blend becomes BlendInd with interval transmittances.
+linear-relational counterpart (lf.py), the Conic inverse of Step 3 becomes MatrixInv
+(matinv.py) and the Step 4 blend becomes BlendInd with interval transmittances.
 
 Readings where the paper is silent (each one is also listed in the design notes):
 * uc = Mmul(A, Add(uw, -tau)) + beta, see pose.py;
 * pixel coordinates are centred on the principal point (render.py);
 * products of a quantity with itself (d*d, the diagonal of Mp Mp^T, q q^T) use Sqr;
   the off-diagonal of Mp Mp^T is one quantity Mul(Mp_0m, Mp_1m) used twice;
-* line 9 is evaluated as v * (Conic * Mp) with v = u d^2 - d up: B = Conic * Mp is
+* the q step (Step 3) is evaluated as v * (Conic * Mp) with v = u d^2 - d up: B = Conic * Mp is
   formed once per Gaussian;
-* line 10: x = -q q^T / 2 lies in [-s_hi/2, -max(0, s_lo)/2]; a = o * Exp(x) and its
+* the a step (Step 3): x = -q q^T / 2 lies in [-s_hi/2, -max(0, s_lo)/2]; a = o * Exp(x) and its
   interval is [o exp(x_lo), o exp(x_hi)];
 * Ind(d_i - d_j) (Alg. BlendInd) is decided on two bounds of d_i - d_j: the identity
-  d_i - d_j = A_z (uw_i - uw_j) behind line 7 (tau and beta cancel), and the literal
+  d_i - d_j = A_z (uw_i - uw_j) behind the depth d = uc_z (tau and beta cancel), and the literal
   difference of the depth forms with a 1e-10 margin: 1 if a lower bound proves it
   positive, 0 if an upper bound proves it non-positive, unknown otherwise;
-* transmittances are interval products (BlendInd line 2):
+* transmittances are interval products (the T step of BlendInd):
       T_hi[i] = prod_{Ind_ij = 1} (1 - a_lo[j]),  T_lo[i] = prod_{Ind_ij != 0} (1 - a_hi[j]);
-* colour (BlendInd line 3, then item (5) of Sec. 3.3):
+* colour (the pc step of BlendInd, then item (5) of Sec. 3.3):
       lo = max(min_e sum_i c_i T_lo[i] a_i^lower(e), sum_i c_i T_lo[i] a_lo[i]) - E
       hi = min(max_e sum_i c_i T_hi[i] a_i^upper(e), sum_i c_i T_hi[i] a_hi[i]) + E
   clamped to [0, 1];
@@ -64,7 +64,7 @@ def options(opts=None):
 
 
 def gaussian_forms(scene, intr, box, opts=None):
-    """Per-Gaussian part of AbstractSplat (Alg. GaussianSplat lines 2-8 plus Conic*Mp)."""
+    """Per-Gaussian part of AbstractSplat (Alg. GaussianSplat, Steps 1-2 and the Conic of Step 3, plus Conic*Mp)."""
     opts = options(opts)
     A, tau, beta, P = pose_forms(box)
     uw = np.asarray(scene["mean"], dtype=np.float64)
@@ -73,32 +73,32 @@ def gaussian_forms(scene, intr, box, opts=None):
     N = len(uw)
     fx, fy = float(intr["fx"]), float(intr["fy"])
 
-    # line 2: uc = Mmul(A, Add(uw, -tau)) + beta
+    # Step 1, camera coordinates: uc = Mmul(A, Add(uw, -tau)) + beta
     y = lf.add_const(lf.neg(lf.broadcast(tau, (N, 3))), uw)
     uc = lf.mmul(A, y.expand(-1))[:, :, 0]
     uc = lf.add(uc, lf.broadcast(beta, (N, 3)))
-    # line 3: Mc = Mmul(A, Mw), Mw constant
+    # Step 1, camera covariance factor: Mc = Mmul(A, Mw), Mw constant
     Mc = lf.mmul_const_right(A, Mw)
     x, yy, z = uc[:, 0], uc[:, 1], uc[:, 2]
-    # line 4: J (zero entries omitted: Mul with a zero constant is exactly zero)
+    # Step 2, projection Jacobian J (zero entries omitted: Mul with a zero constant is exactly zero)
     J00 = lf.scale(z, fx)
     J02 = lf.scale(x, -fx)
     J11 = lf.scale(z, fy)
     J12 = lf.scale(yy, -fy)
-    # line 5: up with the principal point removed
+    # Step 2, pixel mean up with the principal point removed
     up0 = lf.scale(x, fx)
     up1 = lf.scale(yy, fy)
-    # line 6: Mp = Mmul(J, Mc)
+    # Step 2, pixel covariance factor: Mp = Mmul(J, Mc)
     Mp0 = lf.add(lf.mul(J00.expand(-1), Mc[:, 0, :]), lf.mul(J02.expand(-1), Mc[:, 2, :]))
     Mp1 = lf.add(lf.mul(J11.expand(-1), Mc[:, 1, :]), lf.mul(J12.expand(-1), Mc[:, 2, :]))
     Mp = lf.stack([Mp0, Mp1], axis=1)
-    # line 7
+    # Step 2, depth d = uc_z
     d = z
-    # line 9 factors: d*d and d*up
+    # factors of the q step (Step 3): d*d and d*up
     D2 = lf.sqr(d)
     DUP0 = lf.mul(d, up0)
     DUP1 = lf.mul(d, up1)
-    # line 8: X = Mmul(Mp, Mp^T), Conic = MatrixInv(X; inverse of centre, k)
+    # Step 3, Conic: X = Mmul(Mp, Mp^T), Conic = MatrixInv(X; inverse of centre, k)
     X00 = lf.sqr(Mp0).sum(-1)
     X11 = lf.sqr(Mp1).sum(-1)
     X01 = lf.mul(Mp0, Mp1).sum(-1)
@@ -196,7 +196,7 @@ def tile_candidates(rec, intr, x0, x1, y0, y1):
 
 
 def pixel_alpha(rec, idx, ux, uy):
-    """Alpha forms at pixels (lines 9-10) for Gaussians idx: (LF (n, m), a_lo, a_hi)."""
+    """Alpha forms at pixels (the q and a steps of Step 3) for Gaussians idx: (LF (n, m), a_lo, a_hi)."""
     D2 = rec["D2"][idx].expand(-1)
     DUP = rec["DUP"][idx]
     B = rec["B"][idx]
@@ -226,8 +226,8 @@ def ind_matrix(rec, idx, block=256):
     """Three-valued Ind(d_i - d_j) for Gaussians idx: 1, 0, or 2 (unknown); plus borderline mask.
 
     d_i - d_j is bounded two ways, both sound: the identity d_i - d_j = A_z (uw_i - uw_j)
-    behind line 7 (tau and beta cancel), and the literal Add(d[i], -d[j]) of the two
-    depth forms (Alg. BlendInd line 1).  Ind is 1 if either lower bound proves
+    behind the depth d = uc_z (tau and beta cancel), and the literal Add(d[i], -d[j]) of
+    the two depth forms (the V step of Alg. BlendInd).  Ind is 1 if either lower bound proves
     d_i > d_j, 0 if either upper bound proves d_i <= d_j, unknown otherwise.  The
     literal bound is used with a margin IND_MARGIN: its depth forms carry rounding
     noise, and at an exact tie (identity bound exactly 0) that noise must not decide.
@@ -263,9 +263,9 @@ def blend(al, au, alo_f, aup_f, c, ind, E):
 
     al, au: (n, m) alpha interval per Gaussian and pixel; alo_f, aup_f: (n, m, P+1)
     lower / upper alpha forms; c: (n, 3) colours; ind: (n, n) in {0, 1, 2 = unknown}.
-    Line 1-2: V_ij = 1 - a_j Ind_ij is an interval; T_i = prod_j V_ij:
+    V and T steps: V_ij = 1 - a_j Ind_ij is an interval; T_i = prod_j V_ij:
         T_hi[i] = prod_{Ind_ij = 1} (1 - al[j]),   T_lo[i] = prod_{Ind_ij != 0} (1 - au[j]).
-    Line 3: pc = sum_i T_i a_i c_i, bounded relationally and by intervals.
+    pc step: pc = sum_i T_i a_i c_i, bounded relationally and by intervals.
     Returns lo, hi (m, 3), not clamped.
     """
     n, m = al.shape

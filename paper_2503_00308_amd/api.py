@@ -44,7 +44,7 @@ class PoseBox(ctypes.Structure):
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("tile", ctypes.c_int32), ("groups", ctypes.c_int32), ("chunk", ctypes.c_int32),
+    _fields_ = [("tile", ctypes.c_int32), ("ind_window", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("taylor_k", ctypes.c_int32), ("cull_budget", ctypes.c_double),
                 ("z_near", ctypes.c_double), ("t_min", ctypes.c_double),
                 ("cells_per_launch", ctypes.c_int32), ("prefix_entries", ctypes.c_int32)]
@@ -146,7 +146,7 @@ def pose_box(d) -> PoseBox:
 
 def options(d=None) -> Options:
     d = d or {}
-    return Options(int(d.get("tile", 0)), int(d.get("groups", 0)), int(d.get("chunk", 0)),
+    return Options(int(d.get("tile", 0)), int(d.get("ind_window", 0)), int(d.get("chunk", 0)),
                    int(d.get("taylor_k", 0)), float(d.get("cull_budget", 0.0)),
                    float(d.get("z_near", 0.0)), float(d.get("t_min", 0.0)),
                    int(d.get("cells_per_launch", 0)), int(d.get("prefix_entries", 0)))

@@ -97,7 +97,7 @@ int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *o
   ar_options o{};
   if (op) o = *op;
   if (o.tile != 0 && o.tile != kTile) return fail(AR_E_UNSUPPORTED, "tile %d: only %d is built", o.tile, kTile);
-  if (o.groups < 0 || o.groups > 8) return fail(AR_E_INVALID, "groups %d outside [0, 8]", o.groups);
+  if (o.ind_window < 0 || o.ind_window > 2) return fail(AR_E_INVALID, "ind_window %d outside [0, 2]", o.ind_window);
   if (o.prefix_entries < 0) return fail(AR_E_INVALID, "prefix_entries %d is negative", o.prefix_entries);
   if (o.cells_per_launch < 0 || o.cells_per_launch > 256)
     return fail(AR_E_INVALID, "cells_per_launch %d outside [0, 256]", o.cells_per_launch);
@@ -121,13 +121,7 @@ int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *o
   prm.t_min = o.t_min == 0.0 ? 1e-7 : o.t_min;  // negative disables the early stop
   prm.ntx = (in->width + kTile - 1) / kTile;
   prm.nty = (in->height + kTile - 1) / kTile;
-  const int ntiles = prm.ntx * prm.nty;
-  int G = o.groups;
-  if (G == 0) {
-    G = 1;
-    while (G < 8 && ntiles * G < 2048) G *= 2;
-  }
-  prm.groups = G;
+  prm.ind_window = o.ind_window;
   prm.chunk = o.chunk;  // 0: chosen per call from the number of (tile, Gaussian) pairs
   prm.prefix_entries = o.prefix_entries;
   return AR_OK;
@@ -159,7 +153,7 @@ static int ensure_ws(Workspace &ws, size_t n_total, size_t nlists, int P, int nc
   }
   if (nlists > ws.cap_tiles || !ws.tile_range) {
     HIP_TRY(grow(ws, ws.tile_range, 2 * nlists + 2));
-    HIP_TRY(grow(ws, ws.lbox, 6 * nlists + 12));
+    HIP_TRY(grow(ws, ws.lbox, kListBox * nlists + 2 * kListBox));
     ws.cap_tiles = nlists;
   }
   if ((size_t)ncells > ws.cap_cells || !ws.pose_dev) {
@@ -431,8 +425,8 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
     // depth order may change inside the box: Ind runs per tile list, then the two-phase loop
     rc = ensure_general(ws, npairs, nlists);
     if (rc) return rc;
-    HIP_TRY(launch_list_box(ws, ws.pair_val, (int)nlists, ntiles, sc->dev, s));
-    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, false, s));
+    HIP_TRY(launch_list_box(ws, ws.pair_val, ws.pose_dev, (int)nlists, ntiles, sc->dev, s));
+    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, prm.ind_window, false, s));
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.run_cnt + 2 * (size_t)npairs, 1);
     HIP_TRY(hipGetLastError());
     HIP_TRY(exclusive_scan_u32(ws.run_cnt, (int)(2 * npairs + 1), ws, s));
@@ -501,7 +495,7 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
     }
     rc = ensure_rot_parts(ws, max_segs, P);
     if (rc) return rc;
-    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, true, s));
+    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, prm.ind_window, true, s));
     HIP_TRY(hipEventRecord(ws.ev[1], s));
     for (const RotChunk &c : chunks) HIP_TRY(launch_raster_general(P, ws, ws.pair_val, c, prm, lo, hi, s));
     HIP_TRY(hipEventRecord(ws.ev[2], s));

@@ -1,6 +1,6 @@
 // BlendInd colour accumulation shared by the pixel loops (device code).
 //
-// Alg. BlendInd line 3, pc = sum_i T_i a_i c_i, with interval transmittances
+// The pc step of Alg. BlendInd, pc = sum_i T_i a_i c_i, with interval transmittances
 // [T_lo, T_hi] and linear-form alphas: the lower image accumulates the forms
 // c_i T_lo[i] a_i^lower(e), the upper image c_i T_hi[i] a_i^upper(e) and the interval
 // sum c_i T_hi[i] a_hi[i].  Sums are FP64; magnitude sums in FP32 bound their rounding.

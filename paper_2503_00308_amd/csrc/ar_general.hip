@@ -6,13 +6,21 @@
 // tile list in FP64 (k_runs) on two sound bounds of d_i - d_j: the identity
 // A_z (uw_i - uw_j) and the literal difference of the depth forms (1e-10 margin).
 // Lists are in order of the nominal depth c = m . uw (m: the depth row of A at the box
-// centre).  The identity bound lies within sum_l |uw_i,l - uw_j,l| R_l of c_i - c_j,
-// R_l the total radius of the form A_z,l, so with the bounding box of the list's means
-// every j with c_j < c_i - rho_i - margin has Ind_ij = 1 and every j with
-// c_j > c_i + rho_i + margin has Ind_ij = 0 (rho_i = sum_l R_l times the distance of
-// uw_i,l to the far side of the box); only the window between needs the pairwise
-// test.  Translation uncertainty cancels in d_i - d_j, so the window is much narrower
-// than one from depth intervals.  The sets {j: Ind_ij = 1} and {j: Ind_ij != 0} are
+// centre).  The identity bound lies within sum_l R_l |uw_i,l - uw_j,l| of c_i - c_j,
+// R_l the total radius of the form A_z,l over the box.  Two bounds of that sum hold for
+// every j of a tile list:
+//   (box)   rho_i = sum_l R_l times the distance of uw_i,l to the far side of the box of
+//           the list's means;
+//   (split) uw_i - uw_j = ((c_i - c_j) / |m|^2) m + (v_i - v_j) with v the part of uw
+//           across m, so the sum is at most beta |c_i - c_j| + alpha_i, beta =
+//           sum_l R_l |m_l| / |m|^2 and alpha_i the box bound on the v parts; then
+//           |c_i - c_j| > alpha_i / (1 - beta) suffices.
+// A tile list spans a long stretch of depth but little across it, so the split bound is
+// usually far smaller.  Every j with c_j < c_i - rho_i has Ind_ij = 1 and every j with
+// c_j > c_i + rho_i has Ind_ij = 0 (rho_i the smaller bound, plus rounding margins); only
+// the window between needs the pairwise test.  Translation uncertainty cancels in
+// d_i - d_j, so the window is much narrower than one from depth intervals.  The sets
+// {j: Ind_ij = 1} and {j: Ind_ij != 0} are
 // stored as runs of list positions.
 //
 // The pixel loop works on segments of L list positions, one wave per segment, one lane
@@ -37,29 +45,52 @@ namespace ar {
 constexpr double kIndMargin = 1e-10;   // margin of the literal depth-difference test
 constexpr double kWinMargin = 1e-9;    // margin of the depth-interval window
 
-// bounding box of the means of each list's Gaussians (items cell * n + g)
+// Per tile list (items cell * n + g): the box of the Gaussians' means uw [0, 6), the box
+// of their parts across the nominal depth direction m, v = uw - (m . uw / |m|^2) m,
+// [6, 12), and the largest |uw_l| [12] (the scale of the rounding margins).
 __global__ __launch_bounds__(256) void k_list_box(const uint32_t *__restrict__ ranges,
-                                                  const uint32_t *__restrict__ lists, SceneDev sc, int ntiles,
+                                                  const uint32_t *__restrict__ lists,
+                                                  const PoseForms *__restrict__ poses, SceneDev sc, int ntiles,
                                                   double *__restrict__ lbox) {
-  __shared__ double red[6][256];
+  __shared__ double red[kListBox][256];
   const int lst = blockIdx.x;
-  const size_t gbase = (size_t)(lst / ntiles) * sc.n;
+  const int cell = lst / ntiles;
+  const size_t gbase = (size_t)cell * sc.n;
+  const PoseForms &pose = poses[cell];
+  double m[3], mm = 0.0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    m[l] = 0.5 * (pose.A[6 + l][0][kMaxP] + pose.A[6 + l][1][kMaxP]);
+    mm += m[l] * m[l];
+  }
   const uint32_t beg = ranges[2 * lst], end = ranges[2 * lst + 1];
-  double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  double v[kListBox];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    v[l] = INFINITY;
+    v[3 + l] = -INFINITY;
+    v[6 + l] = INFINITY;
+    v[9 + l] = -INFINITY;
+  }
+  v[12] = 0.0;
   for (uint32_t p = beg + threadIdx.x; p < end; p += 256) {
     const size_t g = lists[p] - gbase;
+    double u[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) u[l] = (double)sc.mean[(size_t)l * sc.n + g];
+    const double c = (m[0] * u[0] + m[1] * u[1] + m[2] * u[2]) / mm;
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-      const double u = (double)sc.mean[(size_t)l * sc.n + g];
-      mn[l] = fmin(mn[l], u);
-      mx[l] = fmax(mx[l], u);
+      const double w = u[l] - c * m[l];
+      v[l] = fmin(v[l], u[l]);
+      v[3 + l] = fmax(v[3 + l], u[l]);
+      v[6 + l] = fmin(v[6 + l], w);
+      v[9 + l] = fmax(v[9 + l], w);
+      v[12] = fmax(v[12], fabs(u[l]));
     }
   }
 #pragma unroll
-  for (int l = 0; l < 3; ++l) {
-    red[l][threadIdx.x] = mn[l];
-    red[3 + l][threadIdx.x] = mx[l];
-  }
+  for (int k = 0; k < kListBox; ++k) red[k][threadIdx.x] = v[k];
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (threadIdx.x < off) {
@@ -67,11 +98,14 @@ __global__ __launch_bounds__(256) void k_list_box(const uint32_t *__restrict__ r
       for (int l = 0; l < 3; ++l) {
         red[l][threadIdx.x] = fmin(red[l][threadIdx.x], red[l][threadIdx.x + off]);
         red[3 + l][threadIdx.x] = fmax(red[3 + l][threadIdx.x], red[3 + l][threadIdx.x + off]);
+        red[6 + l][threadIdx.x] = fmin(red[6 + l][threadIdx.x], red[6 + l][threadIdx.x + off]);
+        red[9 + l][threadIdx.x] = fmax(red[9 + l][threadIdx.x], red[9 + l][threadIdx.x + off]);
       }
+      red[12][threadIdx.x] = fmax(red[12][threadIdx.x], red[12][threadIdx.x + off]);
     }
     __syncthreads();
   }
-  if (threadIdx.x < 6) lbox[6 * (size_t)lst + threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < kListBox) lbox[kListBox * (size_t)lst + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // Ind(d_i - d_j) in {0, 1, 2 = unknown} (see the file comment)
@@ -117,8 +151,8 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
                                               const uint32_t *__restrict__ lists, const double *__restrict__ dint,
                                               const double *__restrict__ dform, const double *__restrict__ lbox,
                                               const PoseForms *__restrict__ poses, int ntiles, SceneDev sc,
-                                              int npairs, uint32_t *__restrict__ cnt, uint32_t *__restrict__ runs,
-                                              unsigned long long *__restrict__ counters) {
+                                              int npairs, int window_mode, uint32_t *__restrict__ cnt,
+                                              uint32_t *__restrict__ runs, unsigned long long *__restrict__ counters) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npairs) return;
   const uint32_t tile = pkey[p];                 // list id: cell * ntiles + tile
@@ -131,17 +165,38 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
   const uint32_t gi = list[i];
   const size_t li = gi - gbase;
   const double uwi[3] = {sc.mean[li], sc.mean[sc.n + li], sc.mean[2 * sc.n + li]};
-  // rho_i >= sum_l R_l |uw_i,l - uw_j,l| for every j of the list (see the file comment)
-  const double *bx = lbox + 6 * (size_t)tile;
-  double rho = 0.0;
+  // rho_i: |c_i - c_j| > rho_i decides Ind_ij (see the file comment)
+  const double *bx = lbox + kListBox * (size_t)tile;
+  double m[3], mm = 0.0, msum = 0.0, rsum = 0.0, rho_box = 0.0, mr = 0.0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const double *fl = pose.A[6 + l][0], *fu = pose.A[6 + l][1];
+    m[l] = 0.5 * (fl[kMaxP] + fu[kMaxP]);
+    double R = 0.5 * (fu[kMaxP] - fl[kMaxP]);
+    for (int k = 0; k < kMaxP; ++k) R += fmax(fabs(fl[k]), fabs(fu[k]));
+    mm += m[l] * m[l];
+    msum += fabs(m[l]);
+    rsum += R;
+    mr += R * fabs(m[l]);
+    rho_box += R * fmax(uwi[l] - bx[l], bx[3 + l] - uwi[l]);
+  }
+  const double beta = mr / mm;
+  const double ci_m = (m[0] * uwi[0] + m[1] * uwi[1] + m[2] * uwi[2]) / mm;
+  double alpha = 0.0;
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
     const double *fl = pose.A[6 + l][0], *fu = pose.A[6 + l][1];
     double R = 0.5 * (fu[kMaxP] - fl[kMaxP]);
     for (int k = 0; k < kMaxP; ++k) R += fmax(fabs(fl[k]), fabs(fu[k]));
-    rho += R * fmax(uwi[l] - bx[l], bx[3 + l] - uwi[l]);
+    const double w = uwi[l] - ci_m * m[l];
+    alpha += R * fmax(w - bx[6 + l], bx[9 + l] - w);
   }
-  rho = rho * (1.0 + 0x1p-40) + kWinMargin;
+  double rho = rho_box;
+  if (beta < 0.5 && window_mode == 0) rho = fmin(rho, alpha / (1.0 - beta));
+  if (window_mode == 2) rho = INFINITY;   // every pair of the list tested
+  // rounding of c, v and the sums: relative 2^-40 and an absolute margin on the scale
+  // of the means
+  rho = rho * (1.0 + 0x1p-40) + 2.0 * (kWinMargin + 0x1p-40 * (1.0 + rsum) * (msum * bx[12] + 1.0));
   const double c_i = dint[2 * (size_t)gi];
   // first position with c >= c_i - rho (all before are in front for sure)
   int a = 0, b = i;
@@ -443,36 +498,36 @@ __global__ __launch_bounds__(192) void k_rot_merge(const uint32_t *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------------
-hipError_t launch_list_box(const Workspace &ws, const uint32_t *lists, int nlists, int ntiles, const SceneDev &sc,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_list_box, dim3(nlists), dim3(256), 0, s, ws.tile_range, lists, sc, ntiles, ws.lbox);
+hipError_t launch_list_box(const Workspace &ws, const uint32_t *lists, const PoseForms *poses, int nlists, int ntiles,
+                           const SceneDev &sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_list_box, dim3(nlists), dim3(256), 0, s, ws.tile_range, lists, poses, sc, ntiles, ws.lbox);
   return hipGetLastError();
 }
 
 template <int P>
 static hipError_t launch_runs_p(const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
-                                const SceneDev &sc, int npairs, bool emit, hipStream_t s) {
+                                const SceneDev &sc, int npairs, int mode, bool emit, hipStream_t s) {
   const dim3 grid((npairs + 255) / 256), block(256);
   if (emit)
     hipLaunchKernelGGL((k_runs<P, true>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint, ws.dform,
-                       ws.lbox, poses_dev, ntiles, sc, npairs, ws.run_cnt, ws.runs, ws.counters);
+                       ws.lbox, poses_dev, ntiles, sc, npairs, mode, ws.run_cnt, ws.runs, ws.counters);
   else
     hipLaunchKernelGGL((k_runs<P, false>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint, ws.dform,
-                       ws.lbox, poses_dev, ntiles, sc, npairs, ws.run_cnt, ws.runs, ws.counters);
+                       ws.lbox, poses_dev, ntiles, sc, npairs, mode, ws.run_cnt, ws.runs, ws.counters);
   return hipGetLastError();
 }
 
 hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
-                       const SceneDev &sc, int npairs, bool emit, hipStream_t s) {
+                       const SceneDev &sc, int npairs, int mode, bool emit, hipStream_t s) {
   if (npairs <= 0) return hipSuccess;
   switch (P) {
-    case 0: return launch_runs_p<0>(ws, lists, poses_dev, ntiles, sc, npairs, emit, s);
-    case 1: return launch_runs_p<1>(ws, lists, poses_dev, ntiles, sc, npairs, emit, s);
-    case 2: return launch_runs_p<2>(ws, lists, poses_dev, ntiles, sc, npairs, emit, s);
-    case 3: return launch_runs_p<3>(ws, lists, poses_dev, ntiles, sc, npairs, emit, s);
-    case 4: return launch_runs_p<4>(ws, lists, poses_dev, ntiles, sc, npairs, emit, s);
-    case 5: return launch_runs_p<5>(ws, lists, poses_dev, ntiles, sc, npairs, emit, s);
-    case 6: return launch_runs_p<6>(ws, lists, poses_dev, ntiles, sc, npairs, emit, s);
+    case 0: return launch_runs_p<0>(ws, lists, poses_dev, ntiles, sc, npairs, mode, emit, s);
+    case 1: return launch_runs_p<1>(ws, lists, poses_dev, ntiles, sc, npairs, mode, emit, s);
+    case 2: return launch_runs_p<2>(ws, lists, poses_dev, ntiles, sc, npairs, mode, emit, s);
+    case 3: return launch_runs_p<3>(ws, lists, poses_dev, ntiles, sc, npairs, mode, emit, s);
+    case 4: return launch_runs_p<4>(ws, lists, poses_dev, ntiles, sc, npairs, mode, emit, s);
+    case 5: return launch_runs_p<5>(ws, lists, poses_dev, ntiles, sc, npairs, mode, emit, s);
+    case 6: return launch_runs_p<6>(ws, lists, poses_dev, ntiles, sc, npairs, mode, emit, s);
   }
   return hipErrorInvalidValue;
 }

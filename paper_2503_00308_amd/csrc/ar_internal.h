@@ -19,6 +19,7 @@ namespace ar {
 constexpr int kMaxP = 6;        // pose variables: 3 translations + 3 angles
 constexpr int kTile = 8;        // pixel tile side (one 64-lane wave covers a tile)
 constexpr int kTilePix = kTile * kTile;
+constexpr int kListBox = 13;   // per tile list: box of the means, box of their parts across m, max |mean|
 
 // Gaussian categories decided in the per-Gaussian stage.
 enum GaussType : int32_t {
@@ -87,7 +88,7 @@ struct Params {
   double E;            // widening for pruning
   double t_min;
   int32_t ntx, nty;    // tiles
-  int32_t groups, chunk;
+  int32_t ind_window, chunk;
   int32_t prefix_entries;   // rotation path: list entries per pixel-loop launch
   int32_t nominal_order;    // rotation path: order lists by the nominal depth (else by the upper bound)
 };
@@ -136,7 +137,7 @@ struct Workspace {
   size_t cap_part = 0;           // doubles
   // general (rotation) path
   double *dint = nullptr;      // [n][2] (nominal depth, upper depth bound) by item
-  double *lbox = nullptr;      // [lists][6] bounding box of the means of a list's Gaussians
+  double *lbox = nullptr;      // [lists][kListBox] bounding boxes of a list's means (see k_list_box)
   uint32_t *run_cnt = nullptr; // [pairs][2] + 1: Def / May run counts, then offsets
   size_t cap_run_cnt = 0;
   uint32_t *runs = nullptr;    // [runs][2] list-position ranges [start, end)
@@ -210,11 +211,12 @@ hipError_t launch_segment_map(const Workspace &ws, int nlists, hipStream_t s);
 hipError_t launch_raster_translation(int P, const Workspace &ws, const uint32_t *lists, int nlists, const Params &prm,
                                      int L, int nseg_max, float *lo, float *hi, hipStream_t s);
 // general path (ar_general.hip)
-hipError_t launch_list_box(const Workspace &ws, const uint32_t *lists, int nlists, int ntiles, const SceneDev &sc,
+hipError_t launch_list_box(const Workspace &ws, const uint32_t *lists, const PoseForms *poses, int nlists, int ntiles,
+                           const SceneDev &sc,
                            hipStream_t s);
 // poses_dev[cell] for list ids cell * ntiles + tile
 hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
-                       const SceneDev &sc, int npairs, bool emit, hipStream_t s);
+                       const SceneDev &sc, int npairs, int window_mode, bool emit, hipStream_t s);
 // one launch of the rotation pixel loop: lists list0 .. list0 + nl - 1 with entries from
 // position pos0, their segments seg0 .. seg0 + nseg - 1 of L positions
 struct RotChunk {

@@ -1,6 +1,7 @@
 // Per (pixel, Gaussian) alpha bounds with outward rounding (device code).
 //
-// Alg. GaussianSplat lines 9-10 as linear-relational operations (Sec. 3.3):
+// The q and a steps of Alg. GaussianSplat (Step 3) as linear-relational operations
+// (Sec. 3.3):
 //   v = Add(Mul(d, d, u), -Mul(d, up))     v_k = u_k D2 - DUP_k       (exact scaling)
 //   q = Mmul(v, Conic, Mp) = v B           q_n = Mul(v_0, B_0n) + Mul(v_1, B_1n)
 //   s = Mmul(q, q^T)                       s = sum_n Sqr(q_n)

@@ -1,11 +1,12 @@
 // Pose stage and per-Gaussian stage of abstract rendering (FP64), gfx950.
 //
 // Pose stage (host and device): the set of cameras as linear forms
-//   uc = A (uw - tau) + beta (Alg. GaussianSplat line 2 with R and t replaced by their
-//   forms over the box).
-// Per-Gaussian stage (one thread per Gaussian): lines 2-8 of Alg. GaussianSplat as
-//   linear-relational operations (Sec. 3.3), MatrixInv for line 8 (Sec. 3.1), and
-//   B = Conic * Mp hoisted out of the pixel loop (line 9 evaluated as v * (Conic Mp)).
+//   uc = A (uw - tau) + beta (the camera transform of Alg. GaussianSplat, Step 1, with R
+//   and t replaced by their forms over the box).
+// Per-Gaussian stage (one thread per Gaussian): Steps 1-2 of Alg. GaussianSplat and the
+//   Conic of Step 3 as linear-relational operations (Sec. 3.3), MatrixInv for the
+//   Conic (Sec. 3.1), and B = Conic * Mp hoisted out of the pixel loop (the q step
+//   evaluated as v * (Conic Mp)).
 //   The result is stored as an FP64 record of mid-radius form pairs, plus the
 //   float32 footprint data used for pruning.
 #include <hip/hip_runtime.h>
@@ -242,7 +243,7 @@ __device__ __forceinline__ void project_one(const SceneDev &sc, const PoseForms 
   const float o = sc.opac[g];
   perm_out[oi] = (uint32_t)oi;
 
-  // line 2: uc = Mmul(A, Add(uw, -tau)) + beta
+  // Step 1: uc = Mmul(A, Add(uw, -tau)) + beta
   L64<P> y[3];
 #pragma unroll
   for (int l = 0; l < 3; ++l) y[l] = l_addc<P>(l_neg<P>(load_form<P>(pose.tau[l])), uw[l]);
@@ -254,13 +255,13 @@ __device__ __forceinline__ void project_one(const SceneDev &sc, const PoseForms 
     acc = l_add<P>(acc, l_mul<P>(load_form<P>(pose.A[k * 3 + 2]), y[2]));
     uc[k] = l_add<P>(acc, load_form<P>(pose.beta[k]));
   }
-  const L64<P> &x = uc[0], &yy = uc[1], &d = uc[2];   // line 7: d = uc_z
+  const L64<P> &x = uc[0], &yy = uc[1], &d = uc[2];   // Step 2: d = uc_z
   const double fx = prm.fx, fy = prm.fy;
-  // line 4 (non-zero entries of J) and line 5 with the principal point removed
+  // Step 2: J (its non-zero entries) and up with the principal point removed
   const L64<P> J00 = l_scale<P>(d, fx), J02 = l_scale<P>(x, -fx);
   const L64<P> J11 = l_scale<P>(d, fy), J12 = l_scale<P>(yy, -fy);
   const L64<P> up0 = l_scale<P>(x, fx), up1 = l_scale<P>(yy, fy);
-  // lines 3 and 6: Mc = Mmul(A, Mw) (Mw constant), Mp = Mmul(J, Mc)
+  // Steps 1-2: Mc = Mmul(A, Mw) (Mw constant), Mp = Mmul(J, Mc)
   L64<P> Mp0[3], Mp1[3];
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
@@ -275,10 +276,10 @@ __device__ __forceinline__ void project_one(const SceneDev &sc, const PoseForms 
     Mp0[m] = l_add<P>(l_mul<P>(J00, Mc[0]), l_mul<P>(J02, Mc[2]));
     Mp1[m] = l_add<P>(l_mul<P>(J11, Mc[1]), l_mul<P>(J12, Mc[2]));
   }
-  // line 9 factors d*d and d*up
+  // factors of the q step: d*d and d*up
   const L64<P> D2 = l_sqr<P>(d);
   const L64<P> DUP0 = l_mul<P>(d, up0), DUP1 = l_mul<P>(d, up1);
-  // line 8: X = Mmul(Mp, Mp^T)
+  // Step 3, Conic: X = Mmul(Mp, Mp^T)
   L64<P> X00 = l_sqr<P>(Mp0[0]), X11 = l_sqr<P>(Mp1[0]), X01 = l_mul<P>(Mp0[0], Mp1[0]);
 #pragma unroll
   for (int m = 1; m < 3; ++m) {

@@ -9,9 +9,9 @@
 // order is the same at every pose (Ind(d_i - d_j) is exact: d_i - d_j does not depend
 // on the pose), so BlendInd's transmittance of Gaussian i is the product of (1 - a_j)
 // over the Gaussians strictly in front, i.e. a prefix product in depth order with
-// equal depths sharing one value (Alg. BlendInd lines 1-2):
+// equal depths sharing one value (the V and T steps of Alg. BlendInd):
 //     T_hi[i] = prod_{front} (1 - a_lo[j]),   T_lo[i] = prod_{front} (1 - a_hi[j]).
-// Colour (line 3) is accumulated as linear forms in FP64:
+// Colour (the pc step) is accumulated as linear forms in FP64:
 //     lo: sum_i c_i T_lo[i] a_i^lower(e),   hi: sum_i c_i T_hi[i] a_i^upper(e)
 // plus the interval upper sum sum_i c_i T_hi[i] a_hi[i].
 //

@@ -217,3 +217,26 @@ def test_rotation_pixel_loop_in_chunks_of_lists():
     clo, chi, st = _run(sc, intr, box, {"prefix_entries": 200})
     print("chunked rotation stats", st, flush=True)
     assert np.array_equal(glo, clo) and np.array_equal(ghi, chi)
+
+
+@pytest.mark.parametrize("case", ["boxes", "orbit"])
+def test_ind_windows_equal_testing_every_pair(case):
+    """The depth windows outside which Ind is decided without the pairwise test are
+    exact: the box window, the split window and testing every pair of each tile list
+    give the same bounds, bit for bit."""
+    if case == "boxes":
+        sc = synth.box_surface_scene(1500, n_boxes=12, seed=7)
+        intr = synth.intrinsics(48)
+        box = synth.camera6_box(dt=0.05, drot=np.deg2rad(1.5))
+    else:
+        sc = synth.box_surface_scene(1200, n_boxes=8, seed=8)
+        intr = synth.intrinsics(40)
+        box = synth.orbit_cells(4, 30.0, seed=6)[1]
+    full = _run(sc, intr, box, {"ind_window": 2})
+    boxw = _run(sc, intr, box, {"ind_window": 1})
+    split = _run(sc, intr, box, {"ind_window": 0})
+    print(f"[{case}] windows: every pair {full[2]['max_window']}, box {boxw[2]['max_window']}, "
+          f"split {split[2]['max_window']}; runs {full[2]['runs']} {boxw[2]['runs']} {split[2]['runs']}", flush=True)
+    assert split[2]["max_window"] <= boxw[2]["max_window"] <= full[2]["max_window"]
+    for lo, hi, _ in (boxw, split):
+        assert np.array_equal(lo, full[0]) and np.array_equal(hi, full[1])

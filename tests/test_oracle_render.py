@@ -42,7 +42,7 @@ def test_blendsort_matches_textbook_front_to_back():
 
 
 def test_alpha_matches_projected_gaussian_density():
-    """Lines 9-10 give o exp(-1/2 (u-mu)^T S^-1 (u-mu)) with S the projected covariance.
+    """The q and a steps give o exp(-1/2 (u-mu)^T S^-1 (u-mu)) with S the projected covariance.
 
     Reference computed independently: mu = (fx x/z, fy y/z), S = G Cov_c G^T with the
     perspective Jacobian G = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]].
