@@ -152,6 +152,7 @@ typedef struct {
   double total_ms;       /* device time of the whole call from its first to its last kernel */
   int64_t runs;          /* rotation boxes: runs of list positions holding the Ind sets */
   int64_t cycles_a, cycles_b; /* rotation boxes: summed wave clock cycles of the pixel loop's two phases */
+  int64_t ind_tests;     /* rotation boxes: pairwise Ind tests (summed window lengths) */
 } ar_stats;
 
 /* Copies the scene to the device on `stream` (synchronises it).  *out receives a

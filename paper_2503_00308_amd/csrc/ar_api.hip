@@ -518,6 +518,7 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
     st->max_window = std::max(st->max_window, (int32_t)ws.host_counters[5]);
     st->cycles_a += (int64_t)ws.host_counters[6];
     st->cycles_b += (int64_t)ws.host_counters[7];
+    st->ind_tests += (int64_t)ws.host_counters[1];
   }
   return AR_OK;
 }

@@ -37,6 +37,8 @@
 // carry a rounding bound that is added outward before exp.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ar_blend.h"
 #include "ar_internal.h"
 
@@ -131,6 +133,10 @@ __device__ __forceinline__ int ind_pair(const PoseForms &pose, const double *uwi
 #pragma unroll
   for (int k = 0; k < P; ++k) { slo += fabs(lo[k]); sup += fabs(up[k]); }
   const double lo_r = lo[P] - slo, hi_r = up[P] + sup;
+  // both bounds are sound, so when the identity decides the literal bound cannot
+  // contradict it; its form loads are skipped
+  if (lo_r > 0.0) return 1;
+  if (hi_r <= 0.0) return 0;
   // literal bound: d_i.lower - d_j.upper and d_i.upper - d_j.lower
   double sl = 0.0, sh = 0.0;
 #pragma unroll
@@ -140,12 +146,87 @@ __device__ __forceinline__ int ind_pair(const PoseForms &pose, const double *uwi
   }
   const double lo_l = (dfi[kMaxP] - dfj[2 * kMaxP + 1]) - sl;
   const double hi_l = (dfi[2 * kMaxP + 1] - dfj[kMaxP]) + sh;
-  if (lo_r > 0.0 || lo_l > kIndMargin) return 1;
-  if (hi_r <= 0.0 || hi_l <= -kIndMargin) return 0;
+  if (lo_l > kIndMargin) return 1;
+  if (hi_l <= -kIndMargin) return 0;
   return 2;
 }
 
-// One thread per (tile, list position i): runs of {j: Ind_ij = 1} and {j: Ind_ij != 0}.
+__device__ __forceinline__ double readlane_d(double x, int k) {
+  const unsigned long long b = __double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, k);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), k);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Runs of one list position i over its window [ps, qe), the whole wave at once: lane b
+// tests j = t + b, and ballots give the run starts (in the set, previous not) and ends
+// (not in the set, previous in it).  Starts and ends are ranked separately, so a run
+// that spans two chunks gets its start and end from different iterations.  Returns the
+// number of runs of each set (wave-uniform).
+template <int P, bool EMIT>
+__device__ __forceinline__ void wave_runs(const PoseForms &pose, const uint32_t *__restrict__ list, int i, int ps,
+                                          int qe, const double *uwi, const double *dfi,
+                                          const double *__restrict__ dform, SceneDev sc, size_t gbase,
+                                          uint32_t *out_def, uint32_t *out_may, int lane, uint32_t &ndef,
+                                          uint32_t &nmay) {
+  uint32_t sd = 0, ed = 0, sm = 0, em = 0;      // run starts / ends so far
+  bool cd = ps > 0, cm = ps > 0;                // the position before the chunk is in the set
+  if (ps > 0) {
+    // open runs [0, ps) of certain occluders
+    if (EMIT && lane == 0) {
+      out_def[0] = 0u;
+      out_may[0] = 0u;
+    }
+    sd = sm = 1;
+  }
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int t = ps; t < qe; t += 64) {
+    const int j = t + lane;
+    const bool valid = j < qe;
+    int ind = 0;
+    if (valid && j != i) {
+      const uint32_t gj = list[j];
+      const size_t lj = gj - gbase;
+      const double uwj[3] = {sc.mean[lj], sc.mean[sc.n + lj], sc.mean[2 * sc.n + lj]};
+      ind = ind_pair<P>(pose, uwi, uwj, dfi, dform + (size_t)gj * 2 * (kMaxP + 1));
+    }
+    const unsigned long long V = __ballot(valid);
+    const unsigned long long D = __ballot(valid && ind == 1), M = __ballot(valid && ind != 0);
+    const unsigned long long Dp = (D << 1) | (cd ? 1ull : 0ull), Mp = (M << 1) | (cm ? 1ull : 0ull);
+    const unsigned long long sD = D & ~Dp, eD = ~D & Dp & V, sM = M & ~Mp, eM = ~M & Mp & V;
+    if (EMIT) {
+      if ((sD >> lane) & 1ull) out_def[2 * (sd + __popcll(sD & below))] = (uint32_t)j;
+      if ((eD >> lane) & 1ull) out_def[2 * (ed + __popcll(eD & below)) + 1] = (uint32_t)j;
+      if ((sM >> lane) & 1ull) out_may[2 * (sm + __popcll(sM & below))] = (uint32_t)j;
+      if ((eM >> lane) & 1ull) out_may[2 * (em + __popcll(eM & below)) + 1] = (uint32_t)j;
+    }
+    sd += __popcll(sD);
+    ed += __popcll(eD);
+    sm += __popcll(sM);
+    em += __popcll(eM);
+    const int last = min(64, qe - t) - 1;
+    cd = (D >> last) & 1ull;
+    cm = (M >> last) & 1ull;
+  }
+  if (cd) {
+    if (EMIT && lane == 0) out_def[2 * ed + 1] = (uint32_t)qe;
+    ++ed;
+  }
+  if (cm) {
+    if (EMIT && lane == 0) out_may[2 * em + 1] = (uint32_t)qe;
+    ++em;
+  }
+  ndef = ed;
+  nmay = em;
+}
+
+// Windows longer than this go to the whole wave, one list position at a time; shorter
+// ones are walked by their own lane.
+constexpr int kWaveWindow = 64;
+
+// Runs of {j: Ind_ij = 1} and {j: Ind_ij != 0} for 64 consecutive (tile, list position)
+// entries per wave and pass: each lane finds its entry's window, walks it alone when it
+// is short, and the wave takes the long windows together (wave_runs).
 template <int P, bool EMIT>
 __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey, const uint32_t *__restrict__ ranges,
                                               const uint32_t *__restrict__ lists, const double *__restrict__ dint,
@@ -153,111 +234,166 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
                                               const PoseForms *__restrict__ poses, int ntiles, SceneDev sc,
                                               int npairs, int window_mode, uint32_t *__restrict__ cnt,
                                               uint32_t *__restrict__ runs, unsigned long long *__restrict__ counters) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npairs) return;
-  const uint32_t tile = pkey[p];                 // list id: cell * ntiles + tile
-  const int cell = (int)(tile / (uint32_t)ntiles);
-  const PoseForms &pose = poses[cell];
-  const size_t gbase = (size_t)cell * sc.n;      // global index of the cell's Gaussian 0
-  const int beg = (int)ranges[2 * tile], n = (int)ranges[2 * tile + 1] - beg;
-  const int i = p - beg;
-  const uint32_t *list = lists + beg;
-  const uint32_t gi = list[i];
-  const size_t li = gi - gbase;
-  const double uwi[3] = {sc.mean[li], sc.mean[sc.n + li], sc.mean[2 * sc.n + li]};
-  // rho_i: |c_i - c_j| > rho_i decides Ind_ij (see the file comment)
-  const double *bx = lbox + kListBox * (size_t)tile;
-  double m[3], mm = 0.0, msum = 0.0, rsum = 0.0, rho_box = 0.0, mr = 0.0;
-#pragma unroll
-  for (int l = 0; l < 3; ++l) {
-    const double *fl = pose.A[6 + l][0], *fu = pose.A[6 + l][1];
-    m[l] = 0.5 * (fl[kMaxP] + fu[kMaxP]);
-    double R = 0.5 * (fu[kMaxP] - fl[kMaxP]);
-    for (int k = 0; k < kMaxP; ++k) R += fmax(fabs(fl[k]), fabs(fu[k]));
-    mm += m[l] * m[l];
-    msum += fabs(m[l]);
-    rsum += R;
-    mr += R * fabs(m[l]);
-    rho_box += R * fmax(uwi[l] - bx[l], bx[3 + l] - uwi[l]);
-  }
-  const double beta = mr / mm;
-  const double ci_m = (m[0] * uwi[0] + m[1] * uwi[1] + m[2] * uwi[2]) / mm;
-  double alpha = 0.0;
-#pragma unroll
-  for (int l = 0; l < 3; ++l) {
-    const double *fl = pose.A[6 + l][0], *fu = pose.A[6 + l][1];
-    double R = 0.5 * (fu[kMaxP] - fl[kMaxP]);
-    for (int k = 0; k < kMaxP; ++k) R += fmax(fabs(fl[k]), fabs(fu[k]));
-    const double w = uwi[l] - ci_m * m[l];
-    alpha += R * fmax(w - bx[6 + l], bx[9 + l] - w);
-  }
-  double rho = rho_box;
-  if (beta < 0.5 && window_mode == 0) rho = fmin(rho, alpha / (1.0 - beta));
-  if (window_mode == 2) rho = INFINITY;   // every pair of the list tested
-  // rounding of c, v and the sums: relative 2^-40 and an absolute margin on the scale
-  // of the means
-  rho = rho * (1.0 + 0x1p-40) + 2.0 * (kWinMargin + 0x1p-40 * (1.0 + rsum) * (msum * bx[12] + 1.0));
-  const double c_i = dint[2 * (size_t)gi];
-  // first position with c >= c_i - rho (all before are in front for sure)
-  int a = 0, b = i;
-  const double t1 = c_i - rho;
-  while (a < b) {
-    const int mid = (a + b) >> 1;
-    if (dint[2 * (size_t)list[mid]] < t1) a = mid + 1; else b = mid;
-  }
-  const int ps = a;
-  // first position with c > c_i + rho (all from there are behind for sure)
-  a = i;
-  b = n;
-  const double t2 = c_i + rho;
-  while (a < b) {
-    const int mid = (a + b) >> 1;
-    if (dint[2 * (size_t)list[mid]] <= t2) a = mid + 1; else b = mid;
-  }
-  const int qe = a;
-  const double *dfi = dform + (size_t)gi * 2 * (kMaxP + 1);
-  uint32_t *out_def = nullptr, *out_may = nullptr;
-  if (EMIT) {
-    out_def = runs + 2 * (size_t)cnt[2 * (size_t)p];
-    out_may = runs + 2 * (size_t)cnt[2 * (size_t)p + 1];
-  }
-  uint32_t ndef = 0, nmay = 0;
-  int def_start = ps > 0 ? 0 : -1;   // open run [0, ps) of certain occluders
-  int may_start = ps > 0 ? 0 : -1;
-  for (int j = ps; j < qe; ++j) {
-    int ind = 0;
-    if (j != i) {
-      const uint32_t gj = list[j];
-      const size_t lj = gj - gbase;
-      const double uwj[3] = {sc.mean[lj], sc.mean[sc.n + lj], sc.mean[2 * sc.n + lj]};
-      ind = ind_pair<P>(pose, uwi, uwj, dfi, dform + (size_t)gj * 2 * (kMaxP + 1));
+  const int lane = threadIdx.x & 63;
+  const int wave0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+  const int nwaves = (int)(gridDim.x * (blockDim.x >> 6));
+  unsigned long long wmax = 0, wsum = 0;   // window statistics of this lane's entries
+  for (int p0 = wave0 * 64; p0 < npairs; p0 += nwaves * 64) {
+    const int p = p0 + lane;
+    const bool have = p < npairs;
+    int cell = 0, beg = 0, i = 0, ps = 0, qe = 0;
+    uint32_t gi = 0;
+    double uwi[3] = {0.0, 0.0, 0.0};
+    if (have) {
+      const uint32_t tile = pkey[p];                 // list id: cell * ntiles + tile
+      cell = (int)(tile / (uint32_t)ntiles);
+      const PoseForms &pose = poses[cell];
+      beg = (int)ranges[2 * tile];
+      const int n = (int)ranges[2 * tile + 1] - beg;
+      i = p - beg;
+      const uint32_t *list = lists + beg;
+      gi = list[i];
+      const size_t li = gi - (size_t)cell * sc.n;
+      uwi[0] = sc.mean[li];
+      uwi[1] = sc.mean[sc.n + li];
+      uwi[2] = sc.mean[2 * sc.n + li];
+      // rho_i: |c_i - c_j| > rho_i decides Ind_ij (see the file comment)
+      const double *bx = lbox + kListBox * (size_t)tile;
+      double m[3], mm = 0.0, msum = 0.0, rsum = 0.0, rho_box = 0.0, mr = 0.0;
+    #pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        const double *fl = pose.A[6 + l][0], *fu = pose.A[6 + l][1];
+        m[l] = 0.5 * (fl[kMaxP] + fu[kMaxP]);
+        double R = 0.5 * (fu[kMaxP] - fl[kMaxP]);
+        for (int k = 0; k < kMaxP; ++k) R += fmax(fabs(fl[k]), fabs(fu[k]));
+        mm += m[l] * m[l];
+        msum += fabs(m[l]);
+        rsum += R;
+        mr += R * fabs(m[l]);
+        rho_box += R * fmax(uwi[l] - bx[l], bx[3 + l] - uwi[l]);
+      }
+      const double beta = mr / mm;
+      const double ci_m = (m[0] * uwi[0] + m[1] * uwi[1] + m[2] * uwi[2]) / mm;
+      double alpha = 0.0;
+    #pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        const double *fl = pose.A[6 + l][0], *fu = pose.A[6 + l][1];
+        double R = 0.5 * (fu[kMaxP] - fl[kMaxP]);
+        for (int k = 0; k < kMaxP; ++k) R += fmax(fabs(fl[k]), fabs(fu[k]));
+        const double w = uwi[l] - ci_m * m[l];
+        alpha += R * fmax(w - bx[6 + l], bx[9 + l] - w);
+      }
+      double rho = rho_box;
+      if (beta < 0.5 && window_mode == 0) rho = fmin(rho, alpha / (1.0 - beta));
+      if (window_mode == 2) rho = INFINITY;   // every pair of the list tested
+      // rounding of c, v and the sums: relative 2^-40 and an absolute margin on the scale
+      // of the means
+      rho = rho * (1.0 + 0x1p-40) + 2.0 * (kWinMargin + 0x1p-40 * (1.0 + rsum) * (msum * bx[12] + 1.0));
+      const double c_i = dint[2 * (size_t)gi];
+      // first position with c >= c_i - rho (all before are in front for sure)
+      int a = 0, b = i;
+      const double t1 = c_i - rho;
+      while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (dint[2 * (size_t)list[mid]] < t1) a = mid + 1; else b = mid;
+      }
+      ps = a;
+      // first position with c > c_i + rho (all from there are behind for sure)
+      a = i;
+      b = n;
+      const double t2 = c_i + rho;
+      while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (dint[2 * (size_t)list[mid]] <= t2) a = mid + 1; else b = mid;
+      }
+      qe = a;
     }
-    const bool d1 = ind == 1, m1 = ind != 0;
-    if (d1 && def_start < 0) def_start = j;
-    if (!d1 && def_start >= 0) {
-      if (EMIT) { out_def[2 * ndef] = (uint32_t)def_start; out_def[2 * ndef + 1] = (uint32_t)j; }
-      ++ndef;
-      def_start = -1;
+    const int W = qe - ps;
+    const bool wide = W > kWaveWindow;
+    uint32_t *out_def = nullptr, *out_may = nullptr;
+    if (EMIT && have) {
+      out_def = runs + 2 * (size_t)cnt[2 * (size_t)p];
+      out_may = runs + 2 * (size_t)cnt[2 * (size_t)p + 1];
     }
-    if (m1 && may_start < 0) may_start = j;
-    if (!m1 && may_start >= 0) {
-      if (EMIT) { out_may[2 * nmay] = (uint32_t)may_start; out_may[2 * nmay + 1] = (uint32_t)j; }
-      ++nmay;
-      may_start = -1;
+    uint32_t ndef = 0, nmay = 0;
+    if (have && !wide) {
+      const PoseForms &pose = poses[cell];
+      const uint32_t *list = lists + beg;
+      const size_t gbase = (size_t)cell * sc.n;
+      const double *dfi = dform + (size_t)gi * 2 * (kMaxP + 1);
+      int def_start = ps > 0 ? 0 : -1;   // open run [0, ps) of certain occluders
+      int may_start = ps > 0 ? 0 : -1;
+      for (int j = ps; j < qe; ++j) {
+        int ind = 0;
+        if (j != i) {
+          const uint32_t gj = list[j];
+          const size_t lj = gj - gbase;
+          const double uwj[3] = {sc.mean[lj], sc.mean[sc.n + lj], sc.mean[2 * sc.n + lj]};
+          ind = ind_pair<P>(pose, uwi, uwj, dfi, dform + (size_t)gj * 2 * (kMaxP + 1));
+        }
+        const bool d1 = ind == 1, m1 = ind != 0;
+        if (d1 && def_start < 0) def_start = j;
+        if (!d1 && def_start >= 0) {
+          if (EMIT) { out_def[2 * ndef] = (uint32_t)def_start; out_def[2 * ndef + 1] = (uint32_t)j; }
+          ++ndef;
+          def_start = -1;
+        }
+        if (m1 && may_start < 0) may_start = j;
+        if (!m1 && may_start >= 0) {
+          if (EMIT) { out_may[2 * nmay] = (uint32_t)may_start; out_may[2 * nmay + 1] = (uint32_t)j; }
+          ++nmay;
+          may_start = -1;
+        }
+      }
+      if (def_start >= 0) {
+        if (EMIT) { out_def[2 * ndef] = (uint32_t)def_start; out_def[2 * ndef + 1] = (uint32_t)qe; }
+        ++ndef;
+      }
+      if (may_start >= 0) {
+        if (EMIT) { out_may[2 * nmay] = (uint32_t)may_start; out_may[2 * nmay + 1] = (uint32_t)qe; }
+        ++nmay;
+      }
     }
-  }
-  if (def_start >= 0) {
-    if (EMIT) { out_def[2 * ndef] = (uint32_t)def_start; out_def[2 * ndef + 1] = (uint32_t)qe; }
-    ++ndef;
-  }
-  if (may_start >= 0) {
-    if (EMIT) { out_may[2 * nmay] = (uint32_t)may_start; out_may[2 * nmay + 1] = (uint32_t)qe; }
-    ++nmay;
+    // long windows: the whole wave on one entry at a time (all values wave-uniform)
+    unsigned long long todo = __ballot(have && wide);
+    while (todo) {
+      const int k = __builtin_ctzll(todo);
+      todo &= todo - 1ull;
+      const int kc = __builtin_amdgcn_readlane(cell, k), kb = __builtin_amdgcn_readlane(beg, k);
+      const int ki = __builtin_amdgcn_readlane(i, k), kps = __builtin_amdgcn_readlane(ps, k);
+      const int kqe = __builtin_amdgcn_readlane(qe, k);
+      const uint32_t kg = (uint32_t)__builtin_amdgcn_readlane((int)gi, k);
+      const double kuw[3] = {readlane_d(uwi[0], k), readlane_d(uwi[1], k), readlane_d(uwi[2], k)};
+      uint32_t *kod = nullptr, *kom = nullptr;
+      if (EMIT) {
+        kod = runs + 2 * (size_t)cnt[2 * (size_t)(p0 + k)];
+        kom = runs + 2 * (size_t)cnt[2 * (size_t)(p0 + k) + 1];
+      }
+      uint32_t kd, km;
+      wave_runs<P, EMIT>(poses[kc], lists + kb, ki, kps, kqe, kuw, dform + (size_t)kg * 2 * (kMaxP + 1), dform, sc,
+                         (size_t)kc * sc.n, kod, kom, lane, kd, km);
+      if (lane == k) {
+        ndef = kd;
+        nmay = km;
+      }
+    }
+    if (!EMIT && have) {
+      cnt[2 * (size_t)p] = ndef;
+      cnt[2 * (size_t)p + 1] = nmay;
+    }
+    wmax = max(wmax, (unsigned long long)W);
+    wsum += (unsigned long long)W;
   }
   if (!EMIT) {
-    cnt[2 * (size_t)p] = ndef;
-    cnt[2 * (size_t)p + 1] = nmay;
-    atomicMax(&counters[5], (unsigned long long)(qe - ps));
+    // window statistics: one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) {
+      wmax = max(wmax, (unsigned long long)__shfl_xor(wmax, off));
+      wsum += (unsigned long long)__shfl_xor(wsum, off);
+    }
+    if (lane == 0) {
+      atomicMax(&counters[5], wmax);
+      atomicAdd(&counters[1], wsum);
+    }
   }
 }
 
@@ -507,7 +643,8 @@ hipError_t launch_list_box(const Workspace &ws, const uint32_t *lists, const Pos
 template <int P>
 static hipError_t launch_runs_p(const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
                                 const SceneDev &sc, int npairs, int mode, bool emit, hipStream_t s) {
-  const dim3 grid((npairs + 255) / 256), block(256);
+  // 64 entries per wave and pass; at most 8192 blocks, each looping over its share
+  const dim3 grid((unsigned)std::min<size_t>(((size_t)npairs + 255) / 256, 8192)), block(256);
   if (emit)
     hipLaunchKernelGGL((k_runs<P, true>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint, ws.dform,
                        ws.lbox, poses_dev, ntiles, sc, npairs, mode, ws.run_cnt, ws.runs, ws.counters);
