@@ -240,3 +240,24 @@ def test_ind_windows_equal_testing_every_pair(case):
     assert split[2]["max_window"] <= boxw[2]["max_window"] <= full[2]["max_window"]
     for lo, hi, _ in (boxw, split):
         assert np.array_equal(lo, full[0]) and np.array_equal(hi, full[1])
+
+
+def test_full_size_workload3_sampled_tiles():
+    """Workload 3 at full size (100k Gaussians on 20 boxes, 400x400, translation +-0.05
+    and yaw/pitch/roll +-1 deg, P = 6) in its default launch configuration; two 8x8
+    tiles against the oracle's values stored by tests/golden/make_workload3_tiles.py,
+    and every pixel finite and ordered."""
+    import os
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "workload3_tiles.npz"))
+    sc, intr, box, _ = synth.config(3)
+    glo, ghi, st = _run(sc, intr, box)
+    print("workload-3 stats", st, flush=True)
+    assert st["P"] == 6
+    assert np.all(np.isfinite(glo)) and np.all(np.isfinite(ghi)) and np.all(glo <= ghi)
+    for k, (tx, ty) in enumerate(gold["tiles"]):
+        sl = (slice(ty * 8, (ty + 1) * 8), slice(tx * 8, (tx + 1) * 8))
+        ok = ~gold[f"border{k}"][..., None]
+        dlo = np.abs(glo[sl] - gold[f"lo{k}"])[np.broadcast_to(ok, glo[sl].shape)].max()
+        dhi = np.abs(ghi[sl] - gold[f"hi{k}"])[np.broadcast_to(ok, ghi[sl].shape)].max()
+        print(f"[workload3 tile {tx},{ty}] max|dlo| {dlo:.3e} max|dhi| {dhi:.3e}", flush=True)
+        assert dlo <= 1e-5 and dhi <= 1e-5
