@@ -278,14 +278,17 @@ static int ensure_segments(Workspace &ws, size_t ntiles, size_t nseg, int P) {
   return AR_OK;
 }
 
-// Segment length of the translation pixel loop: about 8192 segments over the whole
-// image (eight waves per SIMD of the 256-CU part, so the last wave to start is short),
-// at least 32 list positions each.  Measured on the 10k-Gaussian 128x128 workload: the
-// pixel kernel takes 0.97 ms at L = 96 and 1.19 ms at L = 168; below L = 64 the
-// partial results cost more in the merge than the shorter tail saves.
-static int segment_length(const Params &prm, size_t npairs) {
+// Segment length of the translation pixel loop: about two rounds of the waves the
+// device holds at once (each nonempty list adds half a segment on average), so the last
+// round is nearly full and each wave's share is long enough to amortise its loads; at
+// least 32 list positions.  On the 10k-Gaussian 128x128 workload (three waves per SIMD,
+// 3072 resident) this gives L = 112, measured 0.91 ms against 0.98 ms at L = 88 and
+// 1.06 ms at L = 128.
+static int segment_length(const Params &prm, size_t npairs, size_t nlists, int P) {
   if (prm.chunk > 0) return prm.chunk;
-  size_t L = (npairs + 8191) / 8192;
+  const double C = (double)seg_resident_waves(P);
+  const double target = std::max(2.0 * C - 0.5 * (double)nlists, C);
+  size_t L = (size_t)ceil((double)npairs / target);
   L = (L + 7) / 8 * 8;
   return (int)std::min<size_t>(std::max<size_t>(L, 32), 4096);
 }
@@ -413,7 +416,7 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
   }
   HIP_TRY(launch_tile_ranges(ws.pair_key, (int)npairs, ws.tile_range, (int)nlists, s));
   if (!rotates) {
-    const int L = segment_length(prm, npairs);
+    const int L = segment_length(prm, npairs, nlists, P);
     const size_t nseg_max = (npairs + (size_t)L - 1) / (size_t)L + nlists;
     rc = ensure_segments(ws, nlists, nseg_max, P);
     if (rc) return rc;

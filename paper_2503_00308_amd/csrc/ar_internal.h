@@ -204,6 +204,8 @@ hipError_t launch_count_tiles(int P, const Workspace &ws, int n_total, int n_cel
 hipError_t launch_emit_tiles(int P, const Workspace &ws, int n_total, int n_cell, const Params &prm, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t *keys, int npairs, uint32_t *ranges, int ntiles, hipStream_t s);
 int part_fields(int P);
+// waves of the translation pixel kernel the device holds at once
+int seg_resident_waves(int P);
 hipError_t launch_segments(const Workspace &ws, int nlists, int L, hipStream_t s);
 hipError_t launch_segment_map(const Workspace &ws, int nlists, hipStream_t s);
 // records ev[1] / ev[2] around the per-segment pixel kernel; lists cell * ntiles + tile,

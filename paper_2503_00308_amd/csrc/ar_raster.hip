@@ -27,6 +27,9 @@
 // in front), which the merge adds to the upper bound.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
+
 #include "ar_internal.h"
 #include "ar_blend.h"
 
@@ -237,7 +240,7 @@ __global__ void k_seg_map(const uint32_t *__restrict__ seg_off, int ntiles, uint
 // cut points are moved to the next depth change, so a group of equal depths is never
 // split.  Transmittances start at 1; the merge scales by the product in front.
 template <int P>
-__global__ __launch_bounds__(256) void k_raster_seg(const double *__restrict__ recs, const uint64_t *__restrict__ keys,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_raster_seg(const double *__restrict__ recs, const uint64_t *__restrict__ keys,
                                                     const uint32_t *__restrict__ ranges,
                                                     const uint32_t *__restrict__ lists,
                                                     const uint32_t *__restrict__ seg_off,
@@ -271,29 +274,59 @@ __global__ __launch_bounds__(256) void k_raster_seg(const double *__restrict__ r
   uint64_t prev_key = ~0ull;
   bool stop = false;
   unsigned npairs = 0;
-  for (int p = p0; p < p1; ++p) {
-    const uint32_t gid = items[p];
-    const double *rec = recs + (size_t)gid * R::STRIDE;
-    const uint64_t key = keys[gid];
-    if (key != prev_key) {
-      // everything from here on lies behind the processed Gaussians
-      if (prm.t_min > 0.0 && __all(!inimg || tl_hi < prm.t_min)) {
-        stop = true;
-        break;
-      }
-      tg_lo = tl_lo;
-      tg_hi = tl_hi;
-      prev_key = key;
+  // Per 64 list positions, one lane per position fetches the item, its depth key and its
+  // pruning data (box, r2, type) with vector loads; the pair loop takes them with
+  // readlane, so no dependent scalar load stands between two pairs.
+  for (int base = p0; base < p1 && !stop; base += 64) {
+    const int pl = base + lane;
+    uint32_t gv = 0, klo = ~0u, khi = ~0u;
+    int4 bv = make_int4(0, 0, 0, 0);
+    int rv = 0, tv = 0;
+    if (pl < p1) {
+      gv = items[pl];
+      const uint64_t kk = keys[gv];
+      klo = (uint32_t)kk;
+      khi = (uint32_t)(kk >> 32);
+      const int32_t *ph = reinterpret_cast<const int32_t *>(recs + (size_t)gv * R::STRIDE + R::PRUNE);
+      bv = *reinterpret_cast<const int4 *>(ph);
+      const int2 rt = *reinterpret_cast<const int2 *>(ph + 4);
+      rv = rt.x;
+      tv = rt.y;
     }
-    const int type = rec_type<P>(rec);
-    const bool kept = inimg && pair_kept<P>(rec, type, ux, uy);
-    // alpha under the lane mask, accumulation for every lane (zero when not kept)
-    PairAlpha<P> pa;
-    pair_alpha<P>(rec, type, kept, uxd, uyd, pa, exp_table(gid));
-    acc_pair<P>(acc, rec, pa, tg_lo, tg_hi);
-    tl_lo *= 1.0 - pa.a_hi;
-    tl_hi *= 1.0 - pa.a_lo;
-    npairs += kept ? 1u : 0u;
+    const int cnt = min(64, p1 - base);
+    for (int k = 0; k < cnt; ++k) {
+      const uint32_t gid = (uint32_t)__builtin_amdgcn_readlane((int)gv, k);
+      const uint64_t key = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)khi, k) << 32) |
+                           (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)klo, k);
+      if (key != prev_key) {
+        // everything from here on lies behind the processed Gaussians
+        if (prm.t_min > 0.0 && __all(!inimg || tl_hi < prm.t_min)) {
+          stop = true;
+          break;
+        }
+        tg_lo = tl_lo;
+        tg_hi = tl_hi;
+        prev_key = key;
+      }
+      const double *rec = recs + (size_t)gid * R::STRIDE;
+      const int type = __builtin_amdgcn_readlane(tv, k);
+      bool kept = inimg;
+      if (type != kWild) {
+        const float b0 = __int_as_float(__builtin_amdgcn_readlane(bv.x, k));
+        const float b1 = __int_as_float(__builtin_amdgcn_readlane(bv.y, k));
+        const float b2 = __int_as_float(__builtin_amdgcn_readlane(bv.z, k));
+        const float b3 = __int_as_float(__builtin_amdgcn_readlane(bv.w, k));
+        const float r2 = __int_as_float(__builtin_amdgcn_readlane(rv, k));
+        kept = kept && dist2_box(b0, b1, b2, b3, ux, uy) <= r2;
+      }
+      // alpha under the lane mask, accumulation for every lane (zero when not kept)
+      PairAlpha<P> pa;
+      pair_alpha<P>(rec, type, kept, uxd, uyd, pa, exp_table(gid));
+      acc_pair<P>(acc, rec, pa, tg_lo, tg_hi);
+      tl_lo *= 1.0 - pa.a_hi;
+      tl_hi *= 1.0 - pa.a_lo;
+      npairs += kept ? 1u : 0u;
+    }
   }
   unsigned cnt = npairs;
   for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
@@ -420,6 +453,29 @@ hipError_t launch_segments(const Workspace &ws, int nlists, int L, hipStream_t s
 hipError_t launch_segment_map(const Workspace &ws, int nlists, hipStream_t s) {
   hipLaunchKernelGGL(k_seg_map, dim3((nlists + 255) / 256), dim3(256), 0, s, ws.seg_off, nlists, ws.seg_tile);
   return hipGetLastError();
+}
+
+// Waves of k_raster_seg<P> the device holds at once (occupancy times CUs), cached per
+// device and P.
+int seg_resident_waves(int P) {
+  static std::atomic<int> cache[16][4];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16 || P < 0 || P > 3) return 4096;
+  int v = cache[dev][P].load(std::memory_order_relaxed);
+  if (v > 0) return v;
+  const void *fn = P == 0 ? (const void *)k_raster_seg<0>
+                 : P == 1 ? (const void *)k_raster_seg<1>
+                 : P == 2 ? (const void *)k_raster_seg<2>
+                          : (const void *)k_raster_seg<3>;
+  int blocks = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, 256, 0) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 4096;
+  }
+  v = std::max(1, blocks) * 4 * std::max(1, cus);
+  cache[dev][P].store(v, std::memory_order_relaxed);
+  return v;
 }
 
 hipError_t launch_raster_translation(int P, const Workspace &ws, const uint32_t *lists, int nlists, const Params &prm,
