@@ -404,6 +404,40 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
 // arrays of a launch are relative to its first segment seg0 and its first list entry
 // pos0 (a launch covers a chunk of consecutive lists).
 
+// Item and pruning data (box, r2, type) of up to 64 upcoming list positions, one lane
+// each, fetched with vector loads; the loops read them back with readlane, so no
+// dependent scalar load stands between two pairs.
+struct Lookahead {
+  uint32_t gv = 0;
+  int4 bv = make_int4(0, 0, 0, 0);
+  int rv = 0, tv = 0;
+
+  template <int P>
+  __device__ __forceinline__ void fetch(const double *__restrict__ recs, const uint32_t *__restrict__ items, int pos,
+                                        int end) {
+    if (pos < end) {
+      gv = items[pos];
+      const int32_t *ph = reinterpret_cast<const int32_t *>(recs + (size_t)gv * Rec<P>::STRIDE + Rec<P>::PRUNE);
+      bv = *reinterpret_cast<const int4 *>(ph);
+      const int2 rt = *reinterpret_cast<const int2 *>(ph + 4);
+      rv = rt.x;
+      tv = rt.y;
+    }
+  }
+  __device__ __forceinline__ uint32_t gid(int k) const { return (uint32_t)__builtin_amdgcn_readlane((int)gv, k); }
+  __device__ __forceinline__ int type(int k) const { return __builtin_amdgcn_readlane(tv, k); }
+  // the pruning test of the pair (float32, as in the binning)
+  __device__ __forceinline__ bool kept(int k, int type, float ux, float uy) const {
+    if (type == kWild) return true;
+    const float b0 = __int_as_float(__builtin_amdgcn_readlane(bv.x, k));
+    const float b1 = __int_as_float(__builtin_amdgcn_readlane(bv.y, k));
+    const float b2 = __int_as_float(__builtin_amdgcn_readlane(bv.z, k));
+    const float b3 = __int_as_float(__builtin_amdgcn_readlane(bv.w, k));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(rv, k));
+    return dist2_box(b0, b1, b2, b3, ux, uy) <= r2;
+  }
+};
+
 struct SegRef {
   int list, beg, n, i0, i1;
 };
@@ -448,11 +482,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const size_t pb = (size_t)((uint32_t)r.beg - pos0);
   double Ll = 0.0, Lh = 0.0;
   uint32_t Z = 0;
+  Lookahead la;
   for (int j = r.i0; j < r.i1; ++j) {
-    const uint32_t gid = items[j];
+    const int k = (j - r.i0) & 63;
+    if (k == 0) la.fetch<P>(recs, items, j + lane, r.i1);
+    const uint32_t gid = la.gid(k);
     const double *rec = recs + (size_t)gid * R::STRIDE;
-    const int type = rec_type<P>(rec);
-    if (inimg && pair_kept<P>(rec, type, ux, uy)) {
+    const int type = la.type(k);
+    if (inimg && la.kept(k, type, ux, uy)) {
       double alo, ahi;
       alpha_interval<P>(rec, type, uxd, uyd, alo, ahi, exp_table(gid));
       Ll += log(1.0 - alo);
@@ -522,17 +559,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   Acc<P> acc;
   acc_zero<P>(acc);
   unsigned npairs = 0;
+  Lookahead la;
+  uint32_t cv0 = 0, cv1 = 0, cv2 = 0;   // run offsets of the looked-ahead positions
   for (int i = r.i0; i < r.i1; ++i) {
-    const uint32_t gid = items[i];
+    const int k = (i - r.i0) & 63;
+    if (k == 0) {
+      la.fetch<P>(recs, items, i + lane, r.i1);
+      if (i + lane < r.i1) {
+        const size_t sl2 = 2 * (size_t)(r.beg + i + lane);
+        cv0 = cnt[sl2];
+        cv1 = cnt[sl2 + 1];
+        cv2 = cnt[sl2 + 2];
+      }
+    }
+    const uint32_t gid = la.gid(k);
     const double *rec = recs + (size_t)gid * R::STRIDE;
-    const int type = rec_type<P>(rec);
-    const bool kept = inimg && pair_kept<P>(rec, type, ux, uy);
+    const int type = la.type(k);
+    const bool kept = inimg && la.kept(k, type, ux, uy);
     if (!kept) continue;
-    const size_t slot = (size_t)(r.beg + i);
     // runs of certain occluders and of possible occluders: sums of the logs over
     // [a, b) = S(b - 1) - S(a - 1), S(p) = segment offset + running sum at p
-    const uint32_t d0 = cnt[2 * slot], d1 = cnt[2 * slot + 1];
-    const uint32_t m0 = cnt[2 * slot + 1], m1 = cnt[2 * slot + 2];
+    const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)cv0, k);
+    const uint32_t d1 = (uint32_t)__builtin_amdgcn_readlane((int)cv1, k);
+    const uint32_t m0 = d1, m1 = (uint32_t)__builtin_amdgcn_readlane((int)cv2, k);
     double sum_l = 0.0, err_l = 0.0, sum_h = 0.0, err_h = 0.0;
     uint32_t zc = 0;
     for (uint32_t q = d0; q < d1; ++q) {
