@@ -351,21 +351,72 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   q[Q::CNT * 64] = (double)cnt;
 }
 
-// Three waves per tile, one per colour channel: combine the tile's segments front to
-// back,
-//   acc += T * acc_s,  T *= T_s  (lower with T_lo, upper with T_hi),
-// and write the pixel bounds.  A segment that stopped early ends the tile: everything
-// behind its stop point adds at most T_hi (in front) * T_hi (segment at the stop).
+// Waves per colour channel in the merge: each combines a quarter of the tile's segments,
+// then the quarters are combined in order.
+constexpr int kMergeWaves = 4;
+
+// Front-to-back composition of consecutive segments (or runs of segments):
+//   acc += T * acc_s,  T *= T_s  (lower with T_lo, upper with T_hi).
+// A segment that stopped early ends the tile: everything behind its stop point adds at
+// most T_hi (in front) * T_hi (segment at the stop).
 template <int P>
-__global__ __launch_bounds__(192) void k_merge(const uint32_t *__restrict__ ranges,
-                                               const uint32_t *__restrict__ seg_off,
-                                               const double *__restrict__ part, Params prm,
-                                               float *__restrict__ out_lo, float *__restrict__ out_hi,
-                                               unsigned long long *__restrict__ counters) {
+struct MergeAcc {
+  double lo[P + 1], hi[P + 1], ihi;
+  double T_lo, T_hi, extra;
+  float magl, magh;
+  int stopped;
+  unsigned cnt;
+
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int j = 0; j <= P; ++j) { lo[j] = 0.0; hi[j] = 0.0; }
+    ihi = 0.0;
+    T_lo = 1.0;
+    T_hi = 1.0;
+    extra = 0.0;
+    magl = 0.0f;
+    magh = 0.0f;
+    stopped = 0;
+    cnt = 0;
+  }
+  // append b (the part right behind this one)
+  __device__ __forceinline__ void append(const MergeAcc &b) {
+    if (stopped) return;
+#pragma unroll
+    for (int j = 0; j <= P; ++j) {
+      lo[j] = fma(T_lo, b.lo[j], lo[j]);
+      hi[j] = fma(T_hi, b.hi[j], hi[j]);
+    }
+    ihi = fma(T_hi, b.ihi, ihi);
+    magl = fmaf((float)T_lo, b.magl, magl) * (1.0f + 4.0f * kU32);
+    magh = fmaf((float)T_hi, b.magh, magh) * (1.0f + 4.0f * kU32);
+    cnt += b.cnt;
+    if (b.stopped) {
+      extra = T_hi * b.extra * (1.0 + 0x1p-50);
+      stopped = 1;
+      return;
+    }
+    T_lo *= b.T_lo;
+    T_hi *= b.T_hi;
+  }
+};
+
+// One workgroup per tile: kMergeWaves waves per colour channel, each composing a
+// contiguous quarter of the tile's segments (loads of four segments issued together),
+// then wave 0 of the channel composes the quarters in order and writes the pixel bounds.
+template <int P>
+__global__ __launch_bounds__(192 * kMergeWaves) void k_merge(const uint32_t *__restrict__ ranges,
+                                                             const uint32_t *__restrict__ seg_off,
+                                                             const double *__restrict__ part, Params prm,
+                                                             float *__restrict__ out_lo, float *__restrict__ out_hi,
+                                                             unsigned long long *__restrict__ counters) {
   using Q = Part<P>;
+  using M = MergeAcc<P>;
   constexpr int F = P + 1;
+  __shared__ M red[3][kMergeWaves - 1][64];
   const int lane = threadIdx.x & 63;
-  const int c = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // colour channel
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int c = wid / kMergeWaves, w = wid % kMergeWaves;   // colour channel, quarter
   const int ntiles = prm.ntx * prm.nty;
   const int list = (int)blockIdx.x;            // cell * ntiles + tile
   const int cell = list / ntiles, tile = list % ntiles;
@@ -373,61 +424,46 @@ __global__ __launch_bounds__(192) void k_merge(const uint32_t *__restrict__ rang
   const int col = tx * kTile + (lane & 7), row = ty * kTile + (lane >> 3);
   const bool inimg = col < prm.width && row < prm.height;
   const int s0 = (int)seg_off[list], s1 = (int)seg_off[list + 1];
-  double lo[F], hi[F], ihi = 0.0;
-#pragma unroll
-  for (int j = 0; j < F; ++j) { lo[j] = 0.0; hi[j] = 0.0; }
-  float magl = 0.0f, magh = 0.0f;
-  double T_lo = 1.0, T_hi = 1.0, extra = 0.0;
-  unsigned long long cnt = 0;
-  // segments are read kGroup at a time (loads of the group issued together), then combined
+  const int per = (s1 - s0 + kMergeWaves - 1) / kMergeWaves;
+  const int a0 = min(s1, s0 + w * per), a1 = min(s1, a0 + per);
+  M m;
+  m.init();
   constexpr int kGroup = 4;
-  for (int sb = s0; sb < s1; sb += kGroup) {
-    double vlo[kGroup][F], vhi[kGroup][F], vih[kGroup], tlo[kGroup], thi[kGroup], stp[kGroup], cn[kGroup];
-    float2 mg[kGroup];
+  for (int sb = a0; sb < a1 && !m.stopped; sb += kGroup) {
+    M v[kGroup];
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
-      const int s = min(sb + u, s1 - 1);
+      const int s = min(sb + u, a1 - 1);
       const double *q = part + (size_t)s * Q::NF * 64 + lane;
 #pragma unroll
       for (int j = 0; j < F; ++j) {
-        vlo[u][j] = q[(Q::LO + c * F + j) * 64];
-        vhi[u][j] = q[(Q::HI + c * F + j) * 64];
+        v[u].lo[j] = q[(Q::LO + c * F + j) * 64];
+        v[u].hi[j] = q[(Q::HI + c * F + j) * 64];
       }
-      vih[u] = q[(Q::IHI + c) * 64];
-      mg[u] = __builtin_bit_cast(float2, q[Q::MAG * 64]);
-      tlo[u] = q[Q::TLO * 64];
-      thi[u] = q[Q::THI * 64];
-      stp[u] = q[Q::STOP * 64];
-      cn[u] = q[Q::CNT * 64];
+      v[u].ihi = q[(Q::IHI + c) * 64];
+      const float2 mg = __builtin_bit_cast(float2, q[Q::MAG * 64]);
+      v[u].magl = mg.x;
+      v[u].magh = mg.y;
+      v[u].T_lo = q[Q::TLO * 64];
+      v[u].T_hi = q[Q::THI * 64];
+      v[u].extra = v[u].T_hi;
+      v[u].stopped = q[Q::STOP * 64] != 0.0;
+      v[u].cnt = (unsigned)q[Q::CNT * 64];
     }
-    bool stopped = false;
 #pragma unroll
-    for (int u = 0; u < kGroup; ++u) {
-      if (sb + u >= s1 || stopped) break;
-#pragma unroll
-      for (int j = 0; j < F; ++j) {
-        lo[j] = fma(T_lo, vlo[u][j], lo[j]);
-        hi[j] = fma(T_hi, vhi[u][j], hi[j]);
-      }
-      ihi = fma(T_hi, vih[u], ihi);
-      magl = fmaf((float)T_lo, mg[u].x, magl) * (1.0f + 4.0f * kU32);
-      magh = fmaf((float)T_hi, mg[u].y, magh) * (1.0f + 4.0f * kU32);
-      cnt += (unsigned long long)cn[u];
-      if (stp[u] != 0.0) {
-        extra = T_hi * thi[u] * (1.0 + 0x1p-50);
-        stopped = true;
-        break;
-      }
-      T_lo *= tlo[u];
-      T_hi *= thi[u];
-    }
-    if (stopped) break;
+    for (int u = 0; u < kGroup; ++u)
+      if (sb + u < a1) m.append(v[u]);
   }
-  if (c == 0 && lane == 0 && cnt) atomicAdd(&counters[0], cnt);
+  if (w > 0) red[c][w - 1][lane] = m;
+  __syncthreads();
+  if (w > 0) return;
+#pragma unroll
+  for (int k = 0; k < kMergeWaves - 1; ++k) m.append(red[c][k][lane]);
+  if (c == 0 && lane == 0 && m.cnt) atomicAdd(&counters[0], (unsigned long long)m.cnt);
   if (!inimg) return;
   const int n = (int)(ranges[2 * list + 1] - ranges[2 * list]);
   const size_t img = (size_t)cell * prm.width * prm.height;
-  write_channel<P>(lo, hi, ihi, magl, magh, (double)(n + 2 * (s1 - s0)), prm.E, extra, out_lo, out_hi,
+  write_channel<P>(m.lo, m.hi, m.ihi, m.magl, m.magh, (double)(n + 2 * (s1 - s0)), prm.E, m.extra, out_lo, out_hi,
                    ((img + (size_t)row * prm.width + col) * 3 + c));
 }
 
@@ -439,8 +475,8 @@ static hipError_t launch_trans_p(const Workspace &ws, const uint32_t *lists, int
     hipLaunchKernelGGL(k_raster_seg<P>, dim3((nseg_max + 3) / 4), dim3(256), 0, s, ws.rec, ws.key, ws.tile_range,
                        lists, ws.seg_off, ws.seg_tile, L, nlists, prm, ws.part);
   HIP_RET(hipEventRecord(ws.ev[2], s));
-  hipLaunchKernelGGL(k_merge<P>, dim3(nlists), dim3(192), 0, s, ws.tile_range, ws.seg_off, ws.part, prm, lo, hi,
-                     ws.counters);
+  hipLaunchKernelGGL(k_merge<P>, dim3(nlists), dim3(192 * kMergeWaves), 0, s, ws.tile_range, ws.seg_off, ws.part, prm,
+                     lo, hi, ws.counters);
   return hipGetLastError();
 }
 
