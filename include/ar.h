@@ -111,7 +111,7 @@ typedef struct {
  *               2 = every pair (slow; the result is the same, for checking)
  *   chunk       list positions per segment of the pixel loop (one wave each),
  *               8..4096 (default: translation boxes chosen from the number of pairs,
- *               rotation boxes 128)
+ *               rotation boxes 64)
  *   taylor_k    MatrixInv order k (Sec. 3.1; default 8, the paper's default), 1..16
  *   cull_budget bound E on the colour change from pruning faint Gaussians (default 1e-7);
  *               Gaussian i is dropped from pixel u when its alpha is provably below

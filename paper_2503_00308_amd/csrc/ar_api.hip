@@ -177,7 +177,7 @@ static int ensure_ws(Workspace &ws, size_t n_total, size_t nlists, int P, int nc
 // loop runs over chunks of tile lists with at most this many entries, or one list).
 constexpr size_t kPrefixEntries = (size_t)1 << 21;   // 2M entries, 2.7 GB
 constexpr size_t kRotChunkSegs = (size_t)1 << 16;    // segments per launch of the rotation pixel loop
-constexpr int kRotSegment = 128;                     // list positions per segment (rotation path)
+constexpr int kRotSegment = 64;                      // list positions per segment (rotation path)
 
 // buffers of the general path: run counts for npairs list positions, pinned list ranges
 static int ensure_general(Workspace &ws, size_t npairs, size_t nlists) {

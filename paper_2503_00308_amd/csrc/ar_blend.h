@@ -179,15 +179,48 @@ __device__ __forceinline__ void alpha_interval(const double *__restrict__ rec, i
   }
 }
 
-// Pruning test of one pair (float32, bit-identical to the definition): true when
-// Gaussian rec may contribute at the pixel.
-template <int P>
-__device__ __forceinline__ bool pair_kept(const double *__restrict__ rec, int type, float ux, float uy) {
-  if (type == kWild) return true;
-  const float *pf = rec_prune<P>(rec);
-  const float d2 = dist2_box(pf[0], pf[1], pf[2], pf[3], ux, uy);
-  return d2 <= pf[4];
-}
+// Item and pruning data (box, r2, type) of up to 64 upcoming list positions, one lane
+// each, and optionally their depth keys, fetched with vector loads; the pixel loops
+// read them back with readlane, so no dependent scalar load stands between two pairs.
+struct Lookahead {
+  uint32_t gv = 0, klo = ~0u, khi = ~0u;
+  int4 bv = make_int4(0, 0, 0, 0);
+  int rv = 0, tv = 0;
+
+  template <int P>
+  __device__ __forceinline__ void fetch(const double *__restrict__ recs, const uint32_t *__restrict__ items, int pos,
+                                        int end, const uint64_t *__restrict__ keys = nullptr) {
+    if (pos < end) {
+      gv = items[pos];
+      if (keys) {
+        const uint64_t kk = keys[gv];
+        klo = (uint32_t)kk;
+        khi = (uint32_t)(kk >> 32);
+      }
+      const int32_t *ph = reinterpret_cast<const int32_t *>(recs + (size_t)gv * Rec<P>::STRIDE + Rec<P>::PRUNE);
+      bv = *reinterpret_cast<const int4 *>(ph);
+      const int2 rt = *reinterpret_cast<const int2 *>(ph + 4);
+      rv = rt.x;
+      tv = rt.y;
+    }
+  }
+  __device__ __forceinline__ uint32_t gid(int k) const { return (uint32_t)__builtin_amdgcn_readlane((int)gv, k); }
+  __device__ __forceinline__ uint64_t key(int k) const {
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)khi, k) << 32) |
+           (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)klo, k);
+  }
+  __device__ __forceinline__ int type(int k) const { return __builtin_amdgcn_readlane(tv, k); }
+  // the pruning test of the pair (float32, as in the binning)
+  __device__ __forceinline__ bool kept(int k, int type, float ux, float uy) const {
+    if (type == kWild) return true;
+    const float b0 = __int_as_float(__builtin_amdgcn_readlane(bv.x, k));
+    const float b1 = __int_as_float(__builtin_amdgcn_readlane(bv.y, k));
+    const float b2 = __int_as_float(__builtin_amdgcn_readlane(bv.z, k));
+    const float b3 = __int_as_float(__builtin_amdgcn_readlane(bv.w, k));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(rv, k));
+    return dist2_box(b0, b1, b2, b3, ux, uy) <= r2;
+  }
+};
 
 // Sum the G waves' accumulators into wave 0 through LDS (all threads of the block call it).
 template <int P>

@@ -404,40 +404,6 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
 // arrays of a launch are relative to its first segment seg0 and its first list entry
 // pos0 (a launch covers a chunk of consecutive lists).
 
-// Item and pruning data (box, r2, type) of up to 64 upcoming list positions, one lane
-// each, fetched with vector loads; the loops read them back with readlane, so no
-// dependent scalar load stands between two pairs.
-struct Lookahead {
-  uint32_t gv = 0;
-  int4 bv = make_int4(0, 0, 0, 0);
-  int rv = 0, tv = 0;
-
-  template <int P>
-  __device__ __forceinline__ void fetch(const double *__restrict__ recs, const uint32_t *__restrict__ items, int pos,
-                                        int end) {
-    if (pos < end) {
-      gv = items[pos];
-      const int32_t *ph = reinterpret_cast<const int32_t *>(recs + (size_t)gv * Rec<P>::STRIDE + Rec<P>::PRUNE);
-      bv = *reinterpret_cast<const int4 *>(ph);
-      const int2 rt = *reinterpret_cast<const int2 *>(ph + 4);
-      rv = rt.x;
-      tv = rt.y;
-    }
-  }
-  __device__ __forceinline__ uint32_t gid(int k) const { return (uint32_t)__builtin_amdgcn_readlane((int)gv, k); }
-  __device__ __forceinline__ int type(int k) const { return __builtin_amdgcn_readlane(tv, k); }
-  // the pruning test of the pair (float32, as in the binning)
-  __device__ __forceinline__ bool kept(int k, int type, float ux, float uy) const {
-    if (type == kWild) return true;
-    const float b0 = __int_as_float(__builtin_amdgcn_readlane(bv.x, k));
-    const float b1 = __int_as_float(__builtin_amdgcn_readlane(bv.y, k));
-    const float b2 = __int_as_float(__builtin_amdgcn_readlane(bv.z, k));
-    const float b3 = __int_as_float(__builtin_amdgcn_readlane(bv.w, k));
-    const float r2 = __int_as_float(__builtin_amdgcn_readlane(rv, k));
-    return dist2_box(b0, b1, b2, b3, ux, uy) <= r2;
-  }
-};
-
 struct SegRef {
   int list, beg, n, i0, i1;
 };

@@ -274,31 +274,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   uint64_t prev_key = ~0ull;
   bool stop = false;
   unsigned npairs = 0;
-  // Per 64 list positions, one lane per position fetches the item, its depth key and its
-  // pruning data (box, r2, type) with vector loads; the pair loop takes them with
-  // readlane, so no dependent scalar load stands between two pairs.
-  uint32_t gv = 0, klo = ~0u, khi = ~0u;
-  int4 bv = make_int4(0, 0, 0, 0);
-  int rv = 0, tv = 0;
+  // item, key and pruning data of the next 64 list positions, fetched ahead
+  Lookahead la;
   for (int p = p0; p < p1; ++p) {
     const int k = (p - p0) & 63;
-    if (k == 0) {
-      const int pl = p + lane;
-      if (pl < p1) {
-        gv = items[pl];
-        const uint64_t kk = keys[gv];
-        klo = (uint32_t)kk;
-        khi = (uint32_t)(kk >> 32);
-        const int32_t *ph = reinterpret_cast<const int32_t *>(recs + (size_t)gv * R::STRIDE + R::PRUNE);
-        bv = *reinterpret_cast<const int4 *>(ph);
-        const int2 rt = *reinterpret_cast<const int2 *>(ph + 4);
-        rv = rt.x;
-        tv = rt.y;
-      }
-    }
-    const uint32_t gid = (uint32_t)__builtin_amdgcn_readlane((int)gv, k);
-    const uint64_t key = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)khi, k) << 32) |
-                         (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)klo, k);
+    if (k == 0) la.fetch<P>(recs, items, p + lane, p1, keys);
+    const uint32_t gid = la.gid(k);
+    const uint64_t key = la.key(k);
     if (key != prev_key) {
       // everything from here on lies behind the processed Gaussians
       if (prm.t_min > 0.0 && __all(!inimg || tl_hi < prm.t_min)) {
@@ -310,16 +292,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       prev_key = key;
     }
     const double *rec = recs + (size_t)gid * R::STRIDE;
-    const int type = __builtin_amdgcn_readlane(tv, k);
-    bool kept = inimg;
-    if (type != kWild) {
-      const float b0 = __int_as_float(__builtin_amdgcn_readlane(bv.x, k));
-      const float b1 = __int_as_float(__builtin_amdgcn_readlane(bv.y, k));
-      const float b2 = __int_as_float(__builtin_amdgcn_readlane(bv.z, k));
-      const float b3 = __int_as_float(__builtin_amdgcn_readlane(bv.w, k));
-      const float r2 = __int_as_float(__builtin_amdgcn_readlane(rv, k));
-      kept = kept && dist2_box(b0, b1, b2, b3, ux, uy) <= r2;
-    }
+    const int type = la.type(k);
+    const bool kept = inimg && la.kept(k, type, ux, uy);
     // alpha under the lane mask, accumulation for every lane (zero when not kept)
     PairAlpha<P> pa;
     pair_alpha<P>(rec, type, kept, uxd, uyd, pa, exp_table(gid));
