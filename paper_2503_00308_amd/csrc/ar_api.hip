@@ -177,6 +177,7 @@ static int ensure_ws(Workspace &ws, size_t n_total, size_t nlists, int P, int nc
 // loop runs over chunks of tile lists with at most this many entries, or one list).
 constexpr size_t kPrefixEntries = (size_t)1 << 21;   // 2M entries, 2.7 GB
 constexpr size_t kRotChunkSegs = (size_t)1 << 16;    // segments per launch of the rotation pixel loop
+constexpr double kAbsoluteRuns = 8.0;                // runs per list position from which the sums are made absolute
 constexpr int kRotSegment = 64;                      // list positions per segment (rotation path)
 
 // buffers of the general path: run counts for npairs list positions, pinned list ranges
@@ -492,6 +493,9 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
       c.nseg = (int)(so[l1] - so[l]);
       c.L = L;
       c.pos0 = pos0;
+      // with many runs per list position the blend reads each run end once from absolute
+      // sums; with few, adding the offsets in the blend is cheaper than a pass over them
+      c.absolute = (double)nruns >= kAbsoluteRuns * (double)npairs;
       chunks.push_back(c);
       max_segs = std::max(max_segs, (size_t)c.nseg);
       l = l1;

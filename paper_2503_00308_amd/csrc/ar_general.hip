@@ -27,10 +27,11 @@
 // per pixel of the 8x8 tile:
 //   A (k_rot_prefix): per pixel, running sums of log(1 - a_lo) and log(1 - a_hi) (FP64)
 //      and the running count of a_hi = 1 over the segment, and the segment totals;
-//   k_rot_offsets: per list, the running totals in front of each segment;
+//   k_rot_offsets: per list, the running totals in front of each segment, and
+//   k_rot_absolute: those totals added to the segments' running sums;
 //   B (k_rot_blend): for each Gaussian i, the product over a run [a, b) is
-//      exp(S(b-1) - S(a-1)), S = segment offset + running sum, so T_lo[i] and T_hi[i]
-//      cost two loads per run end; the colour forms are accumulated with these
+//      exp(S(b-1) - S(a-1)), S the absolute running sum, so T_lo[i] and T_hi[i]
+//      cost one load per run end; the colour forms are accumulated with these
 //      absolute transmittances, so a tile's bounds are the sum over its segments
 //      (k_rot_merge).
 // Equal-length segments spread a long tile list over many waves.  The prefix sums
@@ -427,8 +428,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                     const uint32_t *__restrict__ lists,
                                                     const uint32_t *__restrict__ seg_off,
                                                     const uint32_t *__restrict__ seg_tile, int L, int seg0, int nseg,
-                                                    uint32_t pos0, Params prm, double2 *__restrict__ pre,
-                                                    uint32_t *__restrict__ prez, double2 *__restrict__ segsum,
+                                                    uint32_t pos0, Params prm, double *__restrict__ preL,
+                                                    double *__restrict__ preH, uint32_t *__restrict__ prez,
+                                                    double2 *__restrict__ segsum,
                                                     uint32_t *__restrict__ segz,
                                                     unsigned long long *__restrict__ counters) {
   using R = Rec<P>;
@@ -462,7 +464,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       if (ahi >= 1.0) ++Z;
       else Lh += log(1.0 - ahi);
     }
-    pre[(pb + j) * 64 + lane] = make_double2(Ll, Lh);
+    preL[(pb + j) * 64 + lane] = Ll;
+    preH[(pb + j) * 64 + lane] = Lh;
     prez[(pb + j) * 64 + lane] = Z;
   }
   segsum[(size_t)w * 64 + lane] = make_double2(Ll, Lh);
@@ -490,16 +493,44 @@ __global__ __launch_bounds__(256) void k_rot_offsets(const uint32_t *__restrict_
   }
 }
 
+// Running sums made absolute: each segment's offset (the totals of the list's segments
+// in front) added to its positions, so S(p) is one load in the blend.  The sum is the
+// one the blend would form itself, so its rounding is unchanged.
+__global__ __launch_bounds__(256) void k_rot_absolute(const uint32_t *__restrict__ ranges,
+                                                      const uint32_t *__restrict__ seg_off,
+                                                      const uint32_t *__restrict__ seg_tile, int L, int seg0,
+                                                      int nseg, uint32_t pos0, const double2 *__restrict__ segoff,
+                                                      const uint32_t *__restrict__ segz, double *__restrict__ preL,
+                                                      double *__restrict__ preH, uint32_t *__restrict__ prez) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+  if (w >= nseg) return;
+  const SegRef r = seg_ref(ranges, seg_off, seg_tile, seg0 + w, L);
+  if (r.i0 == 0) return;   // the list's first segment: nothing in front
+  const double2 o = segoff[(size_t)w * 64 + lane];
+  const uint32_t oz = segz[(size_t)w * 64 + lane];
+  const size_t pb = (size_t)((uint32_t)r.beg - pos0);
+  for (int j = r.i0; j < r.i1; ++j) {
+    const size_t x = (pb + j) * 64 + lane;
+    preL[x] += o.x;
+    preH[x] += o.y;
+    prez[x] += oz;
+  }
+}
+
 // B: transmittances from the runs (absolute: everything in front of the Gaussian),
 // colour forms accumulated per segment; the tile's bounds are the sum of its segments.
-template <int P>
+// ABS: the running sums were made absolute (k_rot_absolute); otherwise each run end
+// adds its segment's offset here.
+template <int P, bool ABS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rot_blend(const double *__restrict__ recs, const uint32_t *__restrict__ ranges,
                                                    const uint32_t *__restrict__ lists,
                                                    const uint32_t *__restrict__ seg_off,
                                                    const uint32_t *__restrict__ seg_tile, int L, int seg0, int nseg,
                                                    uint32_t pos0, const uint32_t *__restrict__ cnt,
                                                    const uint32_t *__restrict__ runs, Params prm,
-                                                   const double2 *__restrict__ pre, const uint32_t *__restrict__ prez,
+                                                   const double *__restrict__ preL, const double *__restrict__ preH,
+                                                   const uint32_t *__restrict__ prez,
                                                    const double2 *__restrict__ segoff,
                                                    const uint32_t *__restrict__ segz, double *__restrict__ part,
                                                    unsigned long long *__restrict__ counters) {
@@ -520,8 +551,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const float ux = (float)uxd, uy = (float)uyd;
   const uint32_t *items = lists + r.beg;
   const size_t pb = (size_t)((uint32_t)r.beg - pos0);
-  const int sl = (int)seg_off[r.list] - seg0;     // the list's first segment, relative
   const double nn = (double)(r.n + 2);
+  const int sl = (int)seg_off[r.list] - seg0;     // the list's first segment, relative
   Acc<P> acc;
   acc_zero<P>(acc);
   unsigned npairs = 0;
@@ -544,33 +575,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const bool kept = inimg && la.kept(k, type, ux, uy);
     if (!kept) continue;
     // runs of certain occluders and of possible occluders: sums of the logs over
-    // [a, b) = S(b - 1) - S(a - 1), S(p) = segment offset + running sum at p
+    // [a, b) = S(b - 1) - S(a - 1), S(p) the absolute running sum at p
     const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)cv0, k);
     const uint32_t d1 = (uint32_t)__builtin_amdgcn_readlane((int)cv1, k);
     const uint32_t m0 = d1, m1 = (uint32_t)__builtin_amdgcn_readlane((int)cv2, k);
+    // S(p) for p >= 1: the running sum at index (pb + p - 1) * 64 + lane, plus (unless
+    // ABS) the offset of the segment holding position p - 1
+    const double *sL = preL + lane, *sH = preH + lane;
+    const uint32_t *sZ = prez + lane;
     double sum_l = 0.0, err_l = 0.0, sum_h = 0.0, err_h = 0.0;
     uint32_t zc = 0;
     for (uint32_t q = d0; q < d1; ++q) {
-      const int a = (int)runs[2 * (size_t)q], b = (int)runs[2 * (size_t)q + 1];
+      const uint2 ab = *reinterpret_cast<const uint2 *>(runs + 2 * (size_t)q);
       double La = 0.0, Lb = 0.0;
-      if (a > 0) La = pre[(pb + a - 1) * 64 + lane].x + segoff[(size_t)(sl + (a - 1) / L) * 64 + lane].x;
-      if (b > 0) Lb = pre[(pb + b - 1) * 64 + lane].x + segoff[(size_t)(sl + (b - 1) / L) * 64 + lane].x;
+      if (ab.x > 0) {
+        La = sL[(pb + ab.x - 1) * 64];
+        if (!ABS) La += segoff[(size_t)(sl + (int)(ab.x - 1) / L) * 64 + lane].x;
+      }
+      if (ab.y > 0) {
+        Lb = sL[(pb + ab.y - 1) * 64];
+        if (!ABS) Lb += segoff[(size_t)(sl + (int)(ab.y - 1) / L) * 64 + lane].x;
+      }
       sum_l += Lb - La;
       err_l += fabs(La) + fabs(Lb);
     }
     for (uint32_t q = m0; q < m1; ++q) {
-      const int a = (int)runs[2 * (size_t)q], b = (int)runs[2 * (size_t)q + 1];
+      const uint2 ab = *reinterpret_cast<const uint2 *>(runs + 2 * (size_t)q);
       double La = 0.0, Lb = 0.0;
       uint32_t Za = 0, Zb = 0;
-      if (a > 0) {
-        const size_t so = (size_t)(sl + (a - 1) / L) * 64 + lane;
-        La = pre[(pb + a - 1) * 64 + lane].y + segoff[so].y;
-        Za = prez[(pb + a - 1) * 64 + lane] + segz[so];
+      if (ab.x > 0) {
+        La = sH[(pb + ab.x - 1) * 64];
+        Za = sZ[(pb + ab.x - 1) * 64];
+        if (!ABS) {
+          const size_t so = (size_t)(sl + (int)(ab.x - 1) / L) * 64 + lane;
+          La += segoff[so].y;
+          Za += segz[so];
+        }
       }
-      if (b > 0) {
-        const size_t so = (size_t)(sl + (b - 1) / L) * 64 + lane;
-        Lb = pre[(pb + b - 1) * 64 + lane].y + segoff[so].y;
-        Zb = prez[(pb + b - 1) * 64 + lane] + segz[so];
+      if (ab.y > 0) {
+        Lb = sH[(pb + ab.y - 1) * 64];
+        Zb = sZ[(pb + ab.y - 1) * 64];
+        if (!ABS) {
+          const size_t so = (size_t)(sl + (int)(ab.y - 1) / L) * 64 + lane;
+          Lb += segoff[so].y;
+          Zb += segz[so];
+        }
       }
       sum_h += Lb - La;
       err_h += fabs(La) + fabs(Lb);
@@ -688,15 +737,23 @@ template <int P>
 static hipError_t launch_rot_p(const Workspace &ws, const uint32_t *lists, const RotChunk &c, const Params &prm,
                                float *lo, float *hi, hipStream_t s) {
   const dim3 blk(256), grid((unsigned)((c.nseg + 3) / 4));
+  double *preL = ws.pre, *preH = ws.pre + ws.cap_pre * kTilePix;
   if (c.nseg > 0) {
     hipLaunchKernelGGL(k_rot_prefix<P>, grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off, ws.seg_tile, c.L,
-                       c.seg0, c.nseg, c.pos0, prm, (double2 *)ws.pre, ws.prez, (double2 *)ws.segsum, ws.segz,
-                       ws.counters);
+                       c.seg0, c.nseg, c.pos0, prm, preL, preH, ws.prez, (double2 *)ws.segsum, ws.segz, ws.counters);
     hipLaunchKernelGGL(k_rot_offsets, dim3((unsigned)((c.nl + 3) / 4)), blk, 0, s, ws.seg_off, c.list0, c.nl, c.seg0,
                        (double2 *)ws.segsum, ws.segz);
-    hipLaunchKernelGGL(k_rot_blend<P>, grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off, ws.seg_tile, c.L,
-                       c.seg0, c.nseg, c.pos0, ws.run_cnt, ws.runs, prm, (const double2 *)ws.pre, ws.prez,
-                       (const double2 *)ws.segsum, ws.segz, ws.part, ws.counters);
+    if (c.absolute) {
+      hipLaunchKernelGGL(k_rot_absolute, grid, blk, 0, s, ws.tile_range, ws.seg_off, ws.seg_tile, c.L, c.seg0, c.nseg,
+                         c.pos0, (const double2 *)ws.segsum, ws.segz, preL, preH, ws.prez);
+      hipLaunchKernelGGL((k_rot_blend<P, true>), grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off,
+                         ws.seg_tile, c.L, c.seg0, c.nseg, c.pos0, ws.run_cnt, ws.runs, prm, preL, preH, ws.prez,
+                         (const double2 *)ws.segsum, ws.segz, ws.part, ws.counters);
+    } else {
+      hipLaunchKernelGGL((k_rot_blend<P, false>), grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off,
+                         ws.seg_tile, c.L, c.seg0, c.nseg, c.pos0, ws.run_cnt, ws.runs, prm, preL, preH, ws.prez,
+                         (const double2 *)ws.segsum, ws.segz, ws.part, ws.counters);
+    }
   }
   hipLaunchKernelGGL(k_rot_merge<P>, dim3((unsigned)c.nl), dim3(192), 0, s, ws.tile_range, ws.seg_off, c.list0, c.seg0,
                      ws.part, prm, lo, hi, ws.counters);

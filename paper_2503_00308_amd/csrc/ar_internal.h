@@ -224,6 +224,7 @@ hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const 
 struct RotChunk {
   int list0, nl, seg0, nseg, L;
   uint32_t pos0;
+  bool absolute;   // add the segment offsets to the running sums in a pass of their own
 };
 hipError_t launch_raster_general(int P, const Workspace &ws, const uint32_t *lists, const RotChunk &c,
                                  const Params &prm, float *lo, float *hi, hipStream_t s);
