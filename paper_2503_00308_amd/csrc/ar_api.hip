@@ -177,6 +177,7 @@ static int ensure_ws(Workspace &ws, size_t n_total, size_t nlists, int P, int nc
 // loop runs over chunks of tile lists with at most this many entries, or one list).
 constexpr size_t kPrefixEntries = (size_t)1 << 21;   // 2M entries, 2.7 GB
 constexpr size_t kRotChunkSegs = (size_t)1 << 16;    // segments per launch of the rotation pixel loop
+constexpr double kMaskBytes = 8.0 * 1024 * 1024 * 1024;   // largest store of Ind masks kept between passes
 constexpr double kAbsoluteRuns = 8.0;                // runs per list position from which the sums are made absolute
 constexpr int kRotSegment = 64;                      // list positions per segment (rotation path)
 
@@ -186,6 +187,12 @@ static int ensure_general(Workspace &ws, size_t npairs, size_t nlists) {
     const size_t need = 2 * npairs + 1 + npairs / 2 + 1024;
     HIP_TRY(grow(ws, ws.run_cnt, need));
     ws.cap_run_cnt = need;
+  }
+  if (npairs + 1 > ws.cap_win || !ws.win) {
+    const size_t need = npairs + npairs / 4 + 1024;
+    HIP_TRY(grow(ws, ws.win, 2 * need));
+    HIP_TRY(grow(ws, ws.woff, need + 1));
+    ws.cap_win = need;
   }
   if (2 * nlists + 2 > ws.cap_host_ranges || !ws.host_ranges) {
     if (ws.host_ranges) HIP_TRY(hipHostFree(ws.host_ranges));
@@ -430,7 +437,31 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
     rc = ensure_general(ws, npairs, nlists);
     if (rc) return rc;
     HIP_TRY(launch_list_box(ws, ws.pair_val, ws.pose_dev, (int)nlists, ntiles, sc->dev, s));
-    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, prm.ind_window, false, s));
+    // Ind windows, and the mask words of the long ones
+    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, prm.ind_window, kRunsWindows,
+                        nullptr, s));
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.woff + npairs, 1);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(exclusive_scan_u32(ws.woff, (int)(npairs + 1), ws, s));
+    HIP_TRY(hipMemcpyAsync(ws.host_counters, ws.woff + npairs, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ws.host_counters + 1, ws.counters + 5, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           s));
+    HIP_TRY(hipStreamSynchronize(s));
+    // masks of the long windows are kept for the emitting pass when their (32-bit) offsets
+    // cannot have wrapped and they fit kMaskBytes; otherwise that pass tests them again
+    const size_t words = *(const uint32_t *)ws.host_counters;
+    const double words_max = (double)npairs * 2.0 * (double)((ws.host_counters[1] + 63) / 64);
+    unsigned long long *masks = nullptr;
+    if (words > 0 && words_max < 4294967295.0 && (double)words * 8.0 <= kMaskBytes) {
+      if (words > ws.cap_masks || !ws.masks) {
+        const size_t need = words + words / 4 + 1024;
+        HIP_TRY(grow(ws, ws.masks, need));
+        ws.cap_masks = need;
+      }
+      masks = ws.masks;
+    }
+    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, prm.ind_window, kRunsCount,
+                        masks, s));
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.run_cnt + 2 * (size_t)npairs, 1);
     HIP_TRY(hipGetLastError());
     HIP_TRY(exclusive_scan_u32(ws.run_cnt, (int)(2 * npairs + 1), ws, s));
@@ -502,7 +533,8 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
     }
     rc = ensure_rot_parts(ws, max_segs, P);
     if (rc) return rc;
-    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, prm.ind_window, true, s));
+    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, prm.ind_window, kRunsEmit,
+                        masks, s));
     HIP_TRY(hipEventRecord(ws.ev[1], s));
     for (const RotChunk &c : chunks) HIP_TRY(launch_raster_general(P, ws, ws.pair_val, c, prm, lo, hi, s));
     HIP_TRY(hipEventRecord(ws.ev[2], s));

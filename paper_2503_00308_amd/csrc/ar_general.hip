@@ -160,16 +160,19 @@ __device__ __forceinline__ double readlane_d(double x, int k) {
 }
 
 // Runs of one list position i over its window [ps, qe), the whole wave at once: lane b
-// tests j = t + b, and ballots give the run starts (in the set, previous not) and ends
-// (not in the set, previous in it).  Starts and ends are ranked separately, so a run
-// that spans two chunks gets its start and end from different iterations.  Returns the
-// number of runs of each set (wave-uniform).
-template <int P, bool EMIT>
+// tests j = t + b (or, when emitting from stored masks, reads the chunk's two mask
+// words), and ballots give the run starts (in the set, previous not) and ends (not in
+// the set, previous in it).  Starts and ends are ranked separately, so a run that spans
+// two chunks gets its start and end from different iterations.  Returns the number of
+// runs of each set (wave-uniform).  masks: two words (Ind = 1, Ind != 0) per chunk of
+// 64 window positions, or null.
+template <int P, int MODE>
 __device__ __forceinline__ void wave_runs(const PoseForms &pose, const uint32_t *__restrict__ list, int i, int ps,
                                           int qe, const double *uwi, const double *dfi,
                                           const double *__restrict__ dform, SceneDev sc, size_t gbase,
-                                          uint32_t *out_def, uint32_t *out_may, int lane, uint32_t &ndef,
-                                          uint32_t &nmay) {
+                                          unsigned long long *masks, uint32_t *out_def, uint32_t *out_may,
+                                          int lane, uint32_t &ndef, uint32_t &nmay) {
+  constexpr bool EMIT = MODE == kRunsEmit;
   uint32_t sd = 0, ed = 0, sm = 0, em = 0;      // run starts / ends so far
   bool cd = ps > 0, cm = ps > 0;                // the position before the chunk is in the set
   if (ps > 0) {
@@ -181,18 +184,29 @@ __device__ __forceinline__ void wave_runs(const PoseForms &pose, const uint32_t 
     sd = sm = 1;
   }
   const unsigned long long below = (1ull << lane) - 1ull;
-  for (int t = ps; t < qe; t += 64) {
+  for (int t = ps, c = 0; t < qe; t += 64, ++c) {
     const int j = t + lane;
     const bool valid = j < qe;
-    int ind = 0;
-    if (valid && j != i) {
-      const uint32_t gj = list[j];
-      const size_t lj = gj - gbase;
-      const double uwj[3] = {sc.mean[lj], sc.mean[sc.n + lj], sc.mean[2 * sc.n + lj]};
-      ind = ind_pair<P>(pose, uwi, uwj, dfi, dform + (size_t)gj * 2 * (kMaxP + 1));
-    }
     const unsigned long long V = __ballot(valid);
-    const unsigned long long D = __ballot(valid && ind == 1), M = __ballot(valid && ind != 0);
+    unsigned long long D, M;
+    if (EMIT && masks) {
+      D = masks[2 * (size_t)c];
+      M = masks[2 * (size_t)c + 1];
+    } else {
+      int ind = 0;
+      if (valid && j != i) {
+        const uint32_t gj = list[j];
+        const size_t lj = gj - gbase;
+        const double uwj[3] = {sc.mean[lj], sc.mean[sc.n + lj], sc.mean[2 * sc.n + lj]};
+        ind = ind_pair<P>(pose, uwi, uwj, dfi, dform + (size_t)gj * 2 * (kMaxP + 1));
+      }
+      D = __ballot(valid && ind == 1);
+      M = __ballot(valid && ind != 0);
+      if (MODE == kRunsCount && masks && lane == 0) {
+        masks[2 * (size_t)c] = D;
+        masks[2 * (size_t)c + 1] = M;
+      }
+    }
     const unsigned long long Dp = (D << 1) | (cd ? 1ull : 0ull), Mp = (M << 1) | (cm ? 1ull : 0ull);
     const unsigned long long sD = D & ~Dp, eD = ~D & Dp & V, sM = M & ~Mp, eM = ~M & Mp & V;
     if (EMIT) {
@@ -226,15 +240,23 @@ __device__ __forceinline__ void wave_runs(const PoseForms &pose, const uint32_t 
 constexpr int kWaveWindow = 64;
 
 // Runs of {j: Ind_ij = 1} and {j: Ind_ij != 0} for 64 consecutive (tile, list position)
-// entries per wave and pass: each lane finds its entry's window, walks it alone when it
-// is short, and the wave takes the long windows together (wave_runs).
-template <int P, bool EMIT>
+// entries per wave and step, in three passes (MODE):
+//   kRunsWindows: each lane finds its entry's window [ps, qe) (win) and the number of
+//     mask words a long window needs (wc: two per 64 positions, scanned into offsets);
+//   kRunsCount: the Ind tests and the run counts (cnt); a short window is walked by its
+//     own lane, the wave takes the long ones together (wave_runs) and stores their
+//     masks when masks is not null;
+//   kRunsEmit: the runs; long windows from their masks (no Ind tests) when stored.
+template <int P, int MODE>
 __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey, const uint32_t *__restrict__ ranges,
                                               const uint32_t *__restrict__ lists, const double *__restrict__ dint,
                                               const double *__restrict__ dform, const double *__restrict__ lbox,
                                               const PoseForms *__restrict__ poses, int ntiles, SceneDev sc,
-                                              int npairs, int window_mode, uint32_t *__restrict__ cnt,
-                                              uint32_t *__restrict__ runs, unsigned long long *__restrict__ counters) {
+                                              int npairs, int window_mode, uint32_t *__restrict__ win,
+                                              uint32_t *__restrict__ woff, unsigned long long *__restrict__ masks,
+                                              uint32_t *__restrict__ cnt, uint32_t *__restrict__ runs,
+                                              unsigned long long *__restrict__ counters) {
+  constexpr bool EMIT = MODE == kRunsEmit;
   const int lane = threadIdx.x & 63;
   const int wave0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   const int nwaves = (int)(gridDim.x * (blockDim.x >> 6));
@@ -248,9 +270,7 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
     if (have) {
       const uint32_t tile = pkey[p];                 // list id: cell * ntiles + tile
       cell = (int)(tile / (uint32_t)ntiles);
-      const PoseForms &pose = poses[cell];
       beg = (int)ranges[2 * tile];
-      const int n = (int)ranges[2 * tile + 1] - beg;
       i = p - beg;
       const uint32_t *list = lists + beg;
       gi = list[i];
@@ -258,59 +278,74 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
       uwi[0] = sc.mean[li];
       uwi[1] = sc.mean[sc.n + li];
       uwi[2] = sc.mean[2 * sc.n + li];
-      // rho_i: |c_i - c_j| > rho_i decides Ind_ij (see the file comment)
-      const double *bx = lbox + kListBox * (size_t)tile;
-      double m[3], mm = 0.0, msum = 0.0, rsum = 0.0, rho_box = 0.0, mr = 0.0;
-    #pragma unroll
-      for (int l = 0; l < 3; ++l) {
-        const double *fl = pose.A[6 + l][0], *fu = pose.A[6 + l][1];
-        m[l] = 0.5 * (fl[kMaxP] + fu[kMaxP]);
-        double R = 0.5 * (fu[kMaxP] - fl[kMaxP]);
-        for (int k = 0; k < kMaxP; ++k) R += fmax(fabs(fl[k]), fabs(fu[k]));
-        mm += m[l] * m[l];
-        msum += fabs(m[l]);
-        rsum += R;
-        mr += R * fabs(m[l]);
-        rho_box += R * fmax(uwi[l] - bx[l], bx[3 + l] - uwi[l]);
+      if (MODE != kRunsWindows) {
+        ps = (int)win[2 * (size_t)p];
+        qe = (int)win[2 * (size_t)p + 1];
+      } else {
+        const PoseForms &pose = poses[cell];
+        const int n = (int)ranges[2 * tile + 1] - beg;
+        // rho_i: |c_i - c_j| > rho_i decides Ind_ij (see the file comment)
+        const double *bx = lbox + kListBox * (size_t)tile;
+        double m[3], mm = 0.0, msum = 0.0, rsum = 0.0, rho_box = 0.0, mr = 0.0;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          const double *fl = pose.A[6 + l][0], *fu = pose.A[6 + l][1];
+          m[l] = 0.5 * (fl[kMaxP] + fu[kMaxP]);
+          double R = 0.5 * (fu[kMaxP] - fl[kMaxP]);
+          for (int k = 0; k < kMaxP; ++k) R += fmax(fabs(fl[k]), fabs(fu[k]));
+          mm += m[l] * m[l];
+          msum += fabs(m[l]);
+          rsum += R;
+          mr += R * fabs(m[l]);
+          rho_box += R * fmax(uwi[l] - bx[l], bx[3 + l] - uwi[l]);
+        }
+        const double beta = mr / mm;
+        const double ci_m = (m[0] * uwi[0] + m[1] * uwi[1] + m[2] * uwi[2]) / mm;
+        double alpha = 0.0;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          const double *fl = pose.A[6 + l][0], *fu = pose.A[6 + l][1];
+          double R = 0.5 * (fu[kMaxP] - fl[kMaxP]);
+          for (int k = 0; k < kMaxP; ++k) R += fmax(fabs(fl[k]), fabs(fu[k]));
+          const double w = uwi[l] - ci_m * m[l];
+          alpha += R * fmax(w - bx[6 + l], bx[9 + l] - w);
+        }
+        double rho = rho_box;
+        if (beta < 0.5 && window_mode == 0) rho = fmin(rho, alpha / (1.0 - beta));
+        if (window_mode == 2) rho = INFINITY;   // every pair of the list tested
+        // rounding of c, v and the sums: relative 2^-40 and an absolute margin on the
+        // scale of the means
+        rho = rho * (1.0 + 0x1p-40) + 2.0 * (kWinMargin + 0x1p-40 * (1.0 + rsum) * (msum * bx[12] + 1.0));
+        const double c_i = dint[2 * (size_t)gi];
+        // first position with c >= c_i - rho (all before are in front for sure)
+        int a = 0, b = i;
+        const double t1 = c_i - rho;
+        while (a < b) {
+          const int mid = (a + b) >> 1;
+          if (dint[2 * (size_t)list[mid]] < t1) a = mid + 1; else b = mid;
+        }
+        ps = a;
+        // first position with c > c_i + rho (all from there are behind for sure)
+        a = i;
+        b = n;
+        const double t2 = c_i + rho;
+        while (a < b) {
+          const int mid = (a + b) >> 1;
+          if (dint[2 * (size_t)list[mid]] <= t2) a = mid + 1; else b = mid;
+        }
+        qe = a;
+        win[2 * (size_t)p] = (uint32_t)ps;
+        win[2 * (size_t)p + 1] = (uint32_t)qe;
       }
-      const double beta = mr / mm;
-      const double ci_m = (m[0] * uwi[0] + m[1] * uwi[1] + m[2] * uwi[2]) / mm;
-      double alpha = 0.0;
-    #pragma unroll
-      for (int l = 0; l < 3; ++l) {
-        const double *fl = pose.A[6 + l][0], *fu = pose.A[6 + l][1];
-        double R = 0.5 * (fu[kMaxP] - fl[kMaxP]);
-        for (int k = 0; k < kMaxP; ++k) R += fmax(fabs(fl[k]), fabs(fu[k]));
-        const double w = uwi[l] - ci_m * m[l];
-        alpha += R * fmax(w - bx[6 + l], bx[9 + l] - w);
-      }
-      double rho = rho_box;
-      if (beta < 0.5 && window_mode == 0) rho = fmin(rho, alpha / (1.0 - beta));
-      if (window_mode == 2) rho = INFINITY;   // every pair of the list tested
-      // rounding of c, v and the sums: relative 2^-40 and an absolute margin on the scale
-      // of the means
-      rho = rho * (1.0 + 0x1p-40) + 2.0 * (kWinMargin + 0x1p-40 * (1.0 + rsum) * (msum * bx[12] + 1.0));
-      const double c_i = dint[2 * (size_t)gi];
-      // first position with c >= c_i - rho (all before are in front for sure)
-      int a = 0, b = i;
-      const double t1 = c_i - rho;
-      while (a < b) {
-        const int mid = (a + b) >> 1;
-        if (dint[2 * (size_t)list[mid]] < t1) a = mid + 1; else b = mid;
-      }
-      ps = a;
-      // first position with c > c_i + rho (all from there are behind for sure)
-      a = i;
-      b = n;
-      const double t2 = c_i + rho;
-      while (a < b) {
-        const int mid = (a + b) >> 1;
-        if (dint[2 * (size_t)list[mid]] <= t2) a = mid + 1; else b = mid;
-      }
-      qe = a;
     }
     const int W = qe - ps;
     const bool wide = W > kWaveWindow;
+    if (MODE == kRunsWindows) {
+      if (have) woff[p] = wide ? 2u * (uint32_t)((W + 63) / 64) : 0u;
+      wmax = max(wmax, (unsigned long long)W);
+      wsum += (unsigned long long)W;
+      continue;
+    }
     uint32_t *out_def = nullptr, *out_may = nullptr;
     if (EMIT && have) {
       out_def = runs + 2 * (size_t)cnt[2 * (size_t)p];
@@ -365,14 +400,16 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
       const int kqe = __builtin_amdgcn_readlane(qe, k);
       const uint32_t kg = (uint32_t)__builtin_amdgcn_readlane((int)gi, k);
       const double kuw[3] = {readlane_d(uwi[0], k), readlane_d(uwi[1], k), readlane_d(uwi[2], k)};
+      const size_t kp = (size_t)(p0 + k);
       uint32_t *kod = nullptr, *kom = nullptr;
       if (EMIT) {
-        kod = runs + 2 * (size_t)cnt[2 * (size_t)(p0 + k)];
-        kom = runs + 2 * (size_t)cnt[2 * (size_t)(p0 + k) + 1];
+        kod = runs + 2 * (size_t)cnt[2 * kp];
+        kom = runs + 2 * (size_t)cnt[2 * kp + 1];
       }
+      unsigned long long *km_ = masks ? masks + woff[kp] : nullptr;
       uint32_t kd, km;
-      wave_runs<P, EMIT>(poses[kc], lists + kb, ki, kps, kqe, kuw, dform + (size_t)kg * 2 * (kMaxP + 1), dform, sc,
-                         (size_t)kc * sc.n, kod, kom, lane, kd, km);
+      wave_runs<P, MODE>(poses[kc], lists + kb, ki, kps, kqe, kuw, dform + (size_t)kg * 2 * (kMaxP + 1), dform, sc,
+                         (size_t)kc * sc.n, km_, kod, kom, lane, kd, km);
       if (lane == k) {
         ndef = kd;
         nmay = km;
@@ -382,10 +419,8 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
       cnt[2 * (size_t)p] = ndef;
       cnt[2 * (size_t)p + 1] = nmay;
     }
-    wmax = max(wmax, (unsigned long long)W);
-    wsum += (unsigned long long)W;
   }
-  if (!EMIT) {
+  if (MODE == kRunsWindows) {
     // window statistics: one atomic per wave
     for (int off = 32; off > 0; off >>= 1) {
       wmax = max(wmax, (unsigned long long)__shfl_xor(wmax, off));
@@ -704,31 +739,45 @@ hipError_t launch_list_box(const Workspace &ws, const uint32_t *lists, const Pos
   return hipGetLastError();
 }
 
-template <int P>
-static hipError_t launch_runs_p(const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
-                                const SceneDev &sc, int npairs, int mode, bool emit, hipStream_t s) {
-  // 64 entries per wave and pass; at most 8192 blocks, each looping over its share
+template <int P, int MODE>
+static hipError_t launch_runs_pm(const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
+                                 const SceneDev &sc, int npairs, int window_mode, unsigned long long *masks,
+                                 hipStream_t s) {
+  // 64 entries per wave and step; at most 8192 blocks, each looping over its share
   const dim3 grid((unsigned)std::min<size_t>(((size_t)npairs + 255) / 256, 8192)), block(256);
-  if (emit)
-    hipLaunchKernelGGL((k_runs<P, true>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint, ws.dform,
-                       ws.lbox, poses_dev, ntiles, sc, npairs, mode, ws.run_cnt, ws.runs, ws.counters);
-  else
-    hipLaunchKernelGGL((k_runs<P, false>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint, ws.dform,
-                       ws.lbox, poses_dev, ntiles, sc, npairs, mode, ws.run_cnt, ws.runs, ws.counters);
+  hipLaunchKernelGGL((k_runs<P, MODE>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint, ws.dform,
+                     ws.lbox, poses_dev, ntiles, sc, npairs, window_mode, ws.win, ws.woff, masks, ws.run_cnt, ws.runs,
+                     ws.counters);
   return hipGetLastError();
 }
 
+template <int P>
+static hipError_t launch_runs_p(const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
+                                const SceneDev &sc, int npairs, int window_mode, int mode, unsigned long long *masks,
+                                hipStream_t s) {
+  switch (mode) {
+    case kRunsWindows:
+      return launch_runs_pm<P, kRunsWindows>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, masks, s);
+    case kRunsCount:
+      return launch_runs_pm<P, kRunsCount>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, masks, s);
+    case kRunsEmit:
+      return launch_runs_pm<P, kRunsEmit>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, masks, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
-                       const SceneDev &sc, int npairs, int mode, bool emit, hipStream_t s) {
+                       const SceneDev &sc, int npairs, int window_mode, int mode, unsigned long long *masks,
+                       hipStream_t s) {
   if (npairs <= 0) return hipSuccess;
   switch (P) {
-    case 0: return launch_runs_p<0>(ws, lists, poses_dev, ntiles, sc, npairs, mode, emit, s);
-    case 1: return launch_runs_p<1>(ws, lists, poses_dev, ntiles, sc, npairs, mode, emit, s);
-    case 2: return launch_runs_p<2>(ws, lists, poses_dev, ntiles, sc, npairs, mode, emit, s);
-    case 3: return launch_runs_p<3>(ws, lists, poses_dev, ntiles, sc, npairs, mode, emit, s);
-    case 4: return launch_runs_p<4>(ws, lists, poses_dev, ntiles, sc, npairs, mode, emit, s);
-    case 5: return launch_runs_p<5>(ws, lists, poses_dev, ntiles, sc, npairs, mode, emit, s);
-    case 6: return launch_runs_p<6>(ws, lists, poses_dev, ntiles, sc, npairs, mode, emit, s);
+    case 0: return launch_runs_p<0>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, s);
+    case 1: return launch_runs_p<1>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, s);
+    case 2: return launch_runs_p<2>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, s);
+    case 3: return launch_runs_p<3>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, s);
+    case 4: return launch_runs_p<4>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, s);
+    case 5: return launch_runs_p<5>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, s);
+    case 6: return launch_runs_p<6>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, s);
   }
   return hipErrorInvalidValue;
 }

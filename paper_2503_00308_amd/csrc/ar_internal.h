@@ -142,7 +142,12 @@ struct Workspace {
   size_t cap_run_cnt = 0;
   uint32_t *runs = nullptr;    // [runs][2] list-position ranges [start, end)
   size_t cap_runs = 0;
-  double *pre = nullptr;       // [pairs][64][2] per-pixel prefix sums of log(1 - a_lo), log(1 - a_hi)
+  uint32_t *win = nullptr;     // [pairs][2] Ind window [ps, qe) of each list position
+  uint32_t *woff = nullptr;    // [pairs + 1] mask words of each long window, then offsets
+  size_t cap_win = 0;
+  unsigned long long *masks = nullptr;   // Ind masks of the long windows (two words per 64 positions)
+  size_t cap_masks = 0;
+  double *pre = nullptr;       // two planes [pairs][64]: running sums of log(1 - a_lo), log(1 - a_hi)
   uint32_t *prez = nullptr;    // [pairs][64] per-pixel prefix counts of a_hi == 1
   size_t cap_pre = 0;
   uint32_t *host_ranges = nullptr;   // pinned copy of tile_range (rotation path)
@@ -217,8 +222,14 @@ hipError_t launch_list_box(const Workspace &ws, const uint32_t *lists, const Pos
                            const SceneDev &sc,
                            hipStream_t s);
 // poses_dev[cell] for list ids cell * ntiles + tile
+// passes of the Ind runs kernel
+constexpr int kRunsWindows = 0;   // the window [ps, qe) of each entry and its mask words
+constexpr int kRunsCount = 1;     // Ind tests; run counts; masks of the long windows stored
+constexpr int kRunsEmit = 2;      // runs written (long windows from the stored masks)
+// one pass of the Ind runs kernel; masks (the long windows' Ind masks) may be null
 hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
-                       const SceneDev &sc, int npairs, int window_mode, bool emit, hipStream_t s);
+                       const SceneDev &sc, int npairs, int window_mode, int mode, unsigned long long *masks,
+                       hipStream_t s);
 // one launch of the rotation pixel loop: lists list0 .. list0 + nl - 1 with entries from
 // position pos0, their segments seg0 .. seg0 + nseg - 1 of L positions
 struct RotChunk {
