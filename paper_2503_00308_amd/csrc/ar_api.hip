@@ -178,6 +178,7 @@ static int ensure_ws(Workspace &ws, size_t n_total, size_t nlists, int P, int nc
 constexpr size_t kPrefixEntries = (size_t)1 << 21;   // 2M entries, 2.7 GB
 constexpr size_t kRotChunkSegs = (size_t)1 << 16;    // segments per launch of the rotation pixel loop
 constexpr double kMaskBytes = 8.0 * 1024 * 1024 * 1024;   // largest store of Ind masks kept between passes
+constexpr double kCompactWindow = 32.0;              // mean Ind window from which the tests read the compact copy
 constexpr double kAbsoluteRuns = 8.0;                // runs per list position from which the sums are made absolute
 constexpr int kRotSegment = 64;                      // list positions per segment (rotation path)
 
@@ -439,12 +440,14 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
     HIP_TRY(launch_list_box(ws, ws.pair_val, ws.pose_dev, (int)nlists, ntiles, sc->dev, s));
     // Ind windows, and the mask words of the long ones
     HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, prm.ind_window, kRunsWindows,
-                        nullptr, s));
+                        nullptr, false, s));
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.woff + npairs, 1);
     HIP_TRY(hipGetLastError());
     HIP_TRY(exclusive_scan_u32(ws.woff, (int)(npairs + 1), ws, s));
     HIP_TRY(hipMemcpyAsync(ws.host_counters, ws.woff + npairs, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(ws.host_counters + 1, ws.counters + 5, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           s));
+    HIP_TRY(hipMemcpyAsync(ws.host_counters + 2, ws.counters + 1, sizeof(unsigned long long), hipMemcpyDeviceToHost,
                            s));
     HIP_TRY(hipStreamSynchronize(s));
     // masks of the long windows are kept for the emitting pass when their (32-bit) offsets
@@ -460,8 +463,24 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
       }
       masks = ws.masks;
     }
+    // long windows on average: the Ind tests read a copy laid out by list position
+    const bool compact = (double)ws.host_counters[2] >= kCompactWindow * (double)npairs;
+    if (compact) {
+      const size_t forms = npairs * (size_t)(2 * (P + 1));
+      if (forms > ws.cap_compact || !ws.cform) {
+        const size_t want = forms + forms / 4 + 1024;
+        HIP_TRY(grow(ws, ws.cform, want));
+        ws.cap_compact = want;
+      }
+      if (npairs > ws.cap_cmean || !ws.cmean) {
+        const size_t want = npairs + npairs / 4 + 256;
+        HIP_TRY(grow(ws, ws.cmean, 4 * want));
+        ws.cap_cmean = want;
+      }
+      HIP_TRY(launch_ind_gather(P, ws, ws.pair_val, sc->dev, ntiles, (int)npairs, s));
+    }
     HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, prm.ind_window, kRunsCount,
-                        masks, s));
+                        masks, compact, s));
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.run_cnt + 2 * (size_t)npairs, 1);
     HIP_TRY(hipGetLastError());
     HIP_TRY(exclusive_scan_u32(ws.run_cnt, (int)(2 * npairs + 1), ws, s));
@@ -534,7 +553,7 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
     rc = ensure_rot_parts(ws, max_segs, P);
     if (rc) return rc;
     HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, prm.ind_window, kRunsEmit,
-                        masks, s));
+                        masks, compact, s));
     HIP_TRY(hipEventRecord(ws.ev[1], s));
     for (const RotChunk &c : chunks) HIP_TRY(launch_raster_general(P, ws, ws.pair_val, c, prm, lo, hi, s));
     HIP_TRY(hipEventRecord(ws.ev[2], s));

@@ -111,8 +111,10 @@ __global__ __launch_bounds__(256) void k_list_box(const uint32_t *__restrict__ r
   if (threadIdx.x < kListBox) lbox[kListBox * (size_t)lst + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// Ind(d_i - d_j) in {0, 1, 2 = unknown} (see the file comment)
-template <int P>
+// Ind(d_i - d_j) in {0, 1, 2 = unknown} (see the file comment).  Depth forms: the lower
+// form's coefficients at [0, P) and its constant at [S - 1], the upper form's at
+// [S, S + P) and [2S - 1] (S = kMaxP + 1 by item, S = P + 1 in the compact copy).
+template <int P, int S = kMaxP + 1>
 __device__ __forceinline__ int ind_pair(const PoseForms &pose, const double *uwi, const double *uwj,
                                         const double *dfi, const double *dfj) {
   // identity bound: sum_l A_z,l * (uw_i - uw_j)_l, each term a scaled form
@@ -142,11 +144,11 @@ __device__ __forceinline__ int ind_pair(const PoseForms &pose, const double *uwi
   double sl = 0.0, sh = 0.0;
 #pragma unroll
   for (int k = 0; k < P; ++k) {
-    sl += fabs(dfi[k] - dfj[kMaxP + 1 + k]);
-    sh += fabs(dfi[kMaxP + 1 + k] - dfj[k]);
+    sl += fabs(dfi[k] - dfj[S + k]);
+    sh += fabs(dfi[S + k] - dfj[k]);
   }
-  const double lo_l = (dfi[kMaxP] - dfj[2 * kMaxP + 1]) - sl;
-  const double hi_l = (dfi[2 * kMaxP + 1] - dfj[kMaxP]) + sh;
+  const double lo_l = (dfi[S - 1] - dfj[2 * S - 1]) - sl;
+  const double hi_l = (dfi[2 * S - 1] - dfj[S - 1]) + sh;
   if (lo_l > kIndMargin) return 1;
   if (hi_l <= -kIndMargin) return 0;
   return 2;
@@ -159,6 +161,62 @@ __device__ __forceinline__ double readlane_d(double x, int k) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Where the Ind tests read the mean and the depth forms of list position j: by item
+// (gathers), or from a copy laid out by list position (COMPACT: consecutive positions
+// are consecutive in memory, so a wave's 64 tests load contiguous data).
+template <int P, bool COMPACT>
+struct IndSrc {
+  static constexpr int S = COMPACT ? P + 1 : kMaxP + 1;
+  const uint32_t *list;      // the list's items
+  const float *mean;         // scene means [3][n] (by item)
+  const double *dform;       // depth forms by item, or by list position (COMPACT)
+  const float4 *cmean;       // means by list position (COMPACT)
+  int n;                     // scene size
+  size_t gbase;              // the cell's first item
+  size_t pos0;               // the list's first position (COMPACT)
+
+  __device__ __forceinline__ void mean_of(int j, double *uw) const {
+    if (COMPACT) {
+      const float4 m = cmean[pos0 + j];
+      uw[0] = m.x;
+      uw[1] = m.y;
+      uw[2] = m.z;
+    } else {
+      const size_t lj = list[j] - gbase;
+      uw[0] = mean[lj];
+      uw[1] = mean[n + lj];
+      uw[2] = mean[2 * (size_t)n + lj];
+    }
+  }
+  __device__ __forceinline__ const double *forms_of(int j) const {
+    return COMPACT ? dform + (pos0 + j) * (size_t)(2 * S) : dform + (size_t)list[j] * (2 * S);
+  }
+};
+
+// Compact copy for the Ind tests: per list position, the item's mean (float4) and depth
+// forms (lower then upper, P + 1 doubles each).
+template <int P>
+__global__ __launch_bounds__(256) void k_ind_gather(const uint32_t *__restrict__ pkey,
+                                                    const uint32_t *__restrict__ lists, const double *__restrict__ dform,
+                                                    SceneDev sc, int ntiles, int npairs, float4 *__restrict__ cmean,
+                                                    double *__restrict__ cform) {
+  constexpr int F = P + 1;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const uint32_t g = lists[p];
+  const size_t lg = g - (size_t)(pkey[p] / (uint32_t)ntiles) * sc.n;
+  cmean[p] = make_float4(sc.mean[lg], sc.mean[sc.n + lg], sc.mean[2 * (size_t)sc.n + lg], 0.0f);
+  const double *d = dform + (size_t)g * 2 * (kMaxP + 1);
+  double *o = cform + (size_t)p * 2 * F;
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    o[k] = d[k];
+    o[F + k] = d[kMaxP + 1 + k];
+  }
+  o[P] = d[kMaxP];
+  o[F + P] = d[2 * kMaxP + 1];
+}
+
 // Runs of one list position i over its window [ps, qe), the whole wave at once: lane b
 // tests j = t + b (or, when emitting from stored masks, reads the chunk's two mask
 // words), and ballots give the run starts (in the set, previous not) and ends (not in
@@ -166,10 +224,9 @@ __device__ __forceinline__ double readlane_d(double x, int k) {
 // two chunks gets its start and end from different iterations.  Returns the number of
 // runs of each set (wave-uniform).  masks: two words (Ind = 1, Ind != 0) per chunk of
 // 64 window positions, or null.
-template <int P, int MODE>
-__device__ __forceinline__ void wave_runs(const PoseForms &pose, const uint32_t *__restrict__ list, int i, int ps,
+template <int P, int MODE, bool COMPACT>
+__device__ __forceinline__ void wave_runs(const PoseForms &pose, const IndSrc<P, COMPACT> &src, int i, int ps,
                                           int qe, const double *uwi, const double *dfi,
-                                          const double *__restrict__ dform, SceneDev sc, size_t gbase,
                                           unsigned long long *masks, uint32_t *out_def, uint32_t *out_may,
                                           int lane, uint32_t &ndef, uint32_t &nmay) {
   constexpr bool EMIT = MODE == kRunsEmit;
@@ -195,10 +252,9 @@ __device__ __forceinline__ void wave_runs(const PoseForms &pose, const uint32_t 
     } else {
       int ind = 0;
       if (valid && j != i) {
-        const uint32_t gj = list[j];
-        const size_t lj = gj - gbase;
-        const double uwj[3] = {sc.mean[lj], sc.mean[sc.n + lj], sc.mean[2 * sc.n + lj]};
-        ind = ind_pair<P>(pose, uwi, uwj, dfi, dform + (size_t)gj * 2 * (kMaxP + 1));
+        double uwj[3];
+        src.mean_of(j, uwj);
+        ind = ind_pair<P, IndSrc<P, COMPACT>::S>(pose, uwi, uwj, dfi, src.forms_of(j));
       }
       D = __ballot(valid && ind == 1);
       M = __ballot(valid && ind != 0);
@@ -247,10 +303,11 @@ constexpr int kWaveWindow = 64;
 //     own lane, the wave takes the long ones together (wave_runs) and stores their
 //     masks when masks is not null;
 //   kRunsEmit: the runs; long windows from their masks (no Ind tests) when stored.
-template <int P, int MODE>
+template <int P, int MODE, bool COMPACT>
 __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey, const uint32_t *__restrict__ ranges,
                                               const uint32_t *__restrict__ lists, const double *__restrict__ dint,
-                                              const double *__restrict__ dform, const double *__restrict__ lbox,
+                                              const double *__restrict__ dform, const float4 *__restrict__ cmean,
+                                              const double *__restrict__ cform, const double *__restrict__ lbox,
                                               const PoseForms *__restrict__ poses, int ntiles, SceneDev sc,
                                               int npairs, int window_mode, uint32_t *__restrict__ win,
                                               uint32_t *__restrict__ woff, unsigned long long *__restrict__ masks,
@@ -354,18 +411,17 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
     uint32_t ndef = 0, nmay = 0;
     if (have && !wide) {
       const PoseForms &pose = poses[cell];
-      const uint32_t *list = lists + beg;
-      const size_t gbase = (size_t)cell * sc.n;
-      const double *dfi = dform + (size_t)gi * 2 * (kMaxP + 1);
+      const IndSrc<P, COMPACT> src{lists + beg, sc.mean, COMPACT ? cform : dform, cmean, sc.n,
+                                   (size_t)cell * sc.n, (size_t)beg};
+      const double *dfi = src.forms_of(i);
       int def_start = ps > 0 ? 0 : -1;   // open run [0, ps) of certain occluders
       int may_start = ps > 0 ? 0 : -1;
       for (int j = ps; j < qe; ++j) {
         int ind = 0;
         if (j != i) {
-          const uint32_t gj = list[j];
-          const size_t lj = gj - gbase;
-          const double uwj[3] = {sc.mean[lj], sc.mean[sc.n + lj], sc.mean[2 * sc.n + lj]};
-          ind = ind_pair<P>(pose, uwi, uwj, dfi, dform + (size_t)gj * 2 * (kMaxP + 1));
+          double uwj[3];
+          src.mean_of(j, uwj);
+          ind = ind_pair<P, IndSrc<P, COMPACT>::S>(pose, uwi, uwj, dfi, src.forms_of(j));
         }
         const bool d1 = ind == 1, m1 = ind != 0;
         if (d1 && def_start < 0) def_start = j;
@@ -398,7 +454,6 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
       const int kc = __builtin_amdgcn_readlane(cell, k), kb = __builtin_amdgcn_readlane(beg, k);
       const int ki = __builtin_amdgcn_readlane(i, k), kps = __builtin_amdgcn_readlane(ps, k);
       const int kqe = __builtin_amdgcn_readlane(qe, k);
-      const uint32_t kg = (uint32_t)__builtin_amdgcn_readlane((int)gi, k);
       const double kuw[3] = {readlane_d(uwi[0], k), readlane_d(uwi[1], k), readlane_d(uwi[2], k)};
       const size_t kp = (size_t)(p0 + k);
       uint32_t *kod = nullptr, *kom = nullptr;
@@ -407,9 +462,10 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
         kom = runs + 2 * (size_t)cnt[2 * kp + 1];
       }
       unsigned long long *km_ = masks ? masks + woff[kp] : nullptr;
+      const IndSrc<P, COMPACT> src{lists + kb, sc.mean, COMPACT ? cform : dform, cmean, sc.n, (size_t)kc * sc.n,
+                                   (size_t)kb};
       uint32_t kd, km;
-      wave_runs<P, MODE>(poses[kc], lists + kb, ki, kps, kqe, kuw, dform + (size_t)kg * 2 * (kMaxP + 1), dform, sc,
-                         (size_t)kc * sc.n, km_, kod, kom, lane, kd, km);
+      wave_runs<P, MODE, COMPACT>(poses[kc], src, ki, kps, kqe, kuw, src.forms_of(ki), km_, kod, kom, lane, kd, km);
       if (lane == k) {
         ndef = kd;
         nmay = km;
@@ -739,45 +795,69 @@ hipError_t launch_list_box(const Workspace &ws, const uint32_t *lists, const Pos
   return hipGetLastError();
 }
 
-template <int P, int MODE>
+template <int P, int MODE, bool COMPACT>
 static hipError_t launch_runs_pm(const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
                                  const SceneDev &sc, int npairs, int window_mode, unsigned long long *masks,
                                  hipStream_t s) {
   // 64 entries per wave and step; at most 8192 blocks, each looping over its share
   const dim3 grid((unsigned)std::min<size_t>(((size_t)npairs + 255) / 256, 8192)), block(256);
-  hipLaunchKernelGGL((k_runs<P, MODE>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint, ws.dform,
-                     ws.lbox, poses_dev, ntiles, sc, npairs, window_mode, ws.win, ws.woff, masks, ws.run_cnt, ws.runs,
-                     ws.counters);
+  hipLaunchKernelGGL((k_runs<P, MODE, COMPACT>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint,
+                     ws.dform, (const float4 *)ws.cmean, ws.cform, ws.lbox, poses_dev, ntiles, sc, npairs,
+                     window_mode, ws.win, ws.woff, masks, ws.run_cnt, ws.runs, ws.counters);
   return hipGetLastError();
 }
 
 template <int P>
 static hipError_t launch_runs_p(const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
                                 const SceneDev &sc, int npairs, int window_mode, int mode, unsigned long long *masks,
-                                hipStream_t s) {
-  switch (mode) {
-    case kRunsWindows:
-      return launch_runs_pm<P, kRunsWindows>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, masks, s);
-    case kRunsCount:
-      return launch_runs_pm<P, kRunsCount>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, masks, s);
-    case kRunsEmit:
-      return launch_runs_pm<P, kRunsEmit>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, masks, s);
+                                bool compact, hipStream_t s) {
+  if (mode == kRunsWindows)
+    return launch_runs_pm<P, kRunsWindows, false>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, masks, s);
+  if (compact) {
+    if (mode == kRunsCount)
+      return launch_runs_pm<P, kRunsCount, true>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, masks, s);
+    return launch_runs_pm<P, kRunsEmit, true>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, masks, s);
+  }
+  if (mode == kRunsCount)
+    return launch_runs_pm<P, kRunsCount, false>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, masks, s);
+  return launch_runs_pm<P, kRunsEmit, false>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, masks, s);
+}
+
+template <int P>
+static hipError_t launch_ind_gather_p(const Workspace &ws, const uint32_t *lists, const SceneDev &sc, int ntiles,
+                                      int npairs, hipStream_t s) {
+  hipLaunchKernelGGL(k_ind_gather<P>, dim3((unsigned)(((size_t)npairs + 255) / 256)), dim3(256), 0, s, ws.pair_key,
+                     lists, ws.dform, sc, ntiles, npairs, (float4 *)ws.cmean, ws.cform);
+  return hipGetLastError();
+}
+
+hipError_t launch_ind_gather(int P, const Workspace &ws, const uint32_t *lists, const SceneDev &sc, int ntiles,
+                             int npairs, hipStream_t s) {
+  if (npairs <= 0) return hipSuccess;
+  switch (P) {
+    case 0: return launch_ind_gather_p<0>(ws, lists, sc, ntiles, npairs, s);
+    case 1: return launch_ind_gather_p<1>(ws, lists, sc, ntiles, npairs, s);
+    case 2: return launch_ind_gather_p<2>(ws, lists, sc, ntiles, npairs, s);
+    case 3: return launch_ind_gather_p<3>(ws, lists, sc, ntiles, npairs, s);
+    case 4: return launch_ind_gather_p<4>(ws, lists, sc, ntiles, npairs, s);
+    case 5: return launch_ind_gather_p<5>(ws, lists, sc, ntiles, npairs, s);
+    case 6: return launch_ind_gather_p<6>(ws, lists, sc, ntiles, npairs, s);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
                        const SceneDev &sc, int npairs, int window_mode, int mode, unsigned long long *masks,
-                       hipStream_t s) {
+                       bool compact, hipStream_t s) {
   if (npairs <= 0) return hipSuccess;
   switch (P) {
-    case 0: return launch_runs_p<0>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, s);
-    case 1: return launch_runs_p<1>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, s);
-    case 2: return launch_runs_p<2>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, s);
-    case 3: return launch_runs_p<3>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, s);
-    case 4: return launch_runs_p<4>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, s);
-    case 5: return launch_runs_p<5>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, s);
-    case 6: return launch_runs_p<6>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, s);
+    case 0: return launch_runs_p<0>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, compact, s);
+    case 1: return launch_runs_p<1>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, compact, s);
+    case 2: return launch_runs_p<2>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, compact, s);
+    case 3: return launch_runs_p<3>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, compact, s);
+    case 4: return launch_runs_p<4>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, compact, s);
+    case 5: return launch_runs_p<5>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, compact, s);
+    case 6: return launch_runs_p<6>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, compact, s);
   }
   return hipErrorInvalidValue;
 }

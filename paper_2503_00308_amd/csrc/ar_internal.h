@@ -147,6 +147,10 @@ struct Workspace {
   size_t cap_win = 0;
   unsigned long long *masks = nullptr;   // Ind masks of the long windows (two words per 64 positions)
   size_t cap_masks = 0;
+  float *cmean = nullptr;      // [pairs][4] means by list position (compact copy for the Ind tests)
+  double *cform = nullptr;     // [pairs][2][P + 1] depth forms by list position
+  size_t cap_compact = 0;      // doubles of cform
+  size_t cap_cmean = 0;        // positions of cmean
   double *pre = nullptr;       // two planes [pairs][64]: running sums of log(1 - a_lo), log(1 - a_hi)
   uint32_t *prez = nullptr;    // [pairs][64] per-pixel prefix counts of a_hi == 1
   size_t cap_pre = 0;
@@ -229,7 +233,10 @@ constexpr int kRunsEmit = 2;      // runs written (long windows from the stored 
 // one pass of the Ind runs kernel; masks (the long windows' Ind masks) may be null
 hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
                        const SceneDev &sc, int npairs, int window_mode, int mode, unsigned long long *masks,
-                       hipStream_t s);
+                       bool compact, hipStream_t s);
+// the compact copy (cmean, cform) of the items' means and depth forms by list position
+hipError_t launch_ind_gather(int P, const Workspace &ws, const uint32_t *lists, const SceneDev &sc, int ntiles,
+                             int npairs, hipStream_t s);
 // one launch of the rotation pixel loop: lists list0 .. list0 + nl - 1 with entries from
 // position pos0, their segments seg0 .. seg0 + nseg - 1 of L positions
 struct RotChunk {
