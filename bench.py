@@ -78,11 +78,14 @@ def calibrate_copy(mib: int):
 
 
 def alg_flops_per_pair(P: int) -> int:
-    """Algorithmic floating-point work of one (pixel, Gaussian) pair (FMA = 2 flops):
-    v forms 8(P+1), v lower bound 2(P+1), q forms 48(P+1)+24, q bounds 6(P+1),
-    Sqr into s 12(P+1)+24, s bounds 2(P+1), alpha forms 2(P+1)+8, exp/chord 8,
-    colour forms 12(P+1)+18, transmittance 4, pruning test 10."""
-    return 92 * (P + 1) + 92
+    """Algorithmic floating-point work of one (pixel, Gaussian) pair, counted on the
+    operations of the method (FMA = 2 flops), F = P + 1 form coefficients:
+    v = u D2 - DUP 4F FMA and its concretisation 4F; the six McCormick Mul of q
+    24F + 12; the q sums 6F and their concretisation 6F; three Sqr 6F; the s sum and
+    its concretisation 6F; Exp two exponentials and 2F; the alpha concretisation 2F;
+    the transmittance two multiplications; the colour forms 6F + 6 FMA.  That is about
+    66F + 70 operations, 110F + 70 flops.  Outward rounding is overhead, not counted."""
+    return 110 * (P + 1) + 70
 
 
 def cpu_baseline(scene, intr, box, budget_s=20.0):
