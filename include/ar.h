@@ -147,7 +147,7 @@ typedef struct {
   int32_t n_dropped;     /* Gaussians behind the near plane at every pose */
   int32_t P;             /* number of pose variables of the box */
   int32_t max_window;    /* largest Ind window of uncertain depth order (rotations) */
-  int32_t reserved;
+  int32_t segment_length; /* list positions per segment of the pixel loop (largest of the call) */
   double raster_ms;      /* device time of the main per-pixel kernel (HIP events on the call's stream) */
   double total_ms;       /* device time of the whole call from its first to its last kernel */
   int64_t runs;          /* rotation boxes: runs of list positions holding the Ind sets */
@@ -187,6 +187,23 @@ int ar_render_bounds(const ar_scene *scene, const ar_intrinsics *intr, const ar_
 int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *cells,
                     int32_t ncells, const ar_options *opts, float *lo_rgb, float *hi_rgb,
                     void *hip_stream, ar_stats *stats);
+
+/*
+ * Autotuning of the pixel loop's segment length (options.chunk) for a workload: one pose
+ * box (ncells = 1) or a batch of cells, rendered as ar_render_batch.  The workload is
+ * rendered with the automatic length, then with candidates (translation boxes: the
+ * automatic length times 1/2, 3/4, 5/4 and 3/2, multiples of 8 in [8, 4096]; rotation
+ * boxes: 32, 48, 64, 96 and 128), reps times each (1..16); *tuned receives a copy of
+ * *opts (or of the defaults when opts is NULL) whose chunk is the candidate with the
+ * least device time (stats.total_ms).  The workload is rendered once more with *tuned,
+ * so lo_rgb / hi_rgb ([ncells][H][W][3], device memory) hold its bounds, and stats (may
+ * be NULL) that render's statistics.  Results with any chunk enclose the same set; with
+ * the tuned chunk they are those of ar_render_batch(..., tuned, ...) bit for bit.
+ * Returns AR_OK or an error code as ar_render_batch (ar_last_error).
+ */
+int ar_autotune(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *cells, int32_t ncells,
+                const ar_options *opts, int32_t reps, float *lo_rgb, float *hi_rgb, void *hip_stream,
+                ar_options *tuned, ar_stats *stats);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *ar_last_error(void);

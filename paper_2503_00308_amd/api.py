@@ -53,12 +53,12 @@ class Options(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_int64), ("tile_pairs", ctypes.c_int64),
                 ("n_fallback", ctypes.c_int32), ("n_wild", ctypes.c_int32), ("n_dropped", ctypes.c_int32),
-                ("P", ctypes.c_int32), ("max_window", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("P", ctypes.c_int32), ("max_window", ctypes.c_int32), ("segment_length", ctypes.c_int32),
                 ("raster_ms", ctypes.c_double), ("total_ms", ctypes.c_double), ("runs", ctypes.c_int64),
                 ("cycles_a", ctypes.c_int64), ("cycles_b", ctypes.c_int64), ("ind_tests", ctypes.c_int64)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class ServerConfig(ctypes.Structure):
@@ -92,6 +92,9 @@ SYMBOLS = {
     "ar_render_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
                                        ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.POINTER(Stats)]),
+    "ar_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox), ctypes.c_int32,
+                                   ctypes.POINTER(Options), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.POINTER(Options), ctypes.POINTER(Stats)]),
     "ar_last_error": (ctypes.c_char_p, []),
     "ar_version": (ctypes.c_char_p, []),
     "ar_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]),
@@ -228,6 +231,33 @@ def render_batch(scene: Scene, intr, cells, opts=None, stream=None):
                                ctypes.c_void_p(lo.data_ptr()), ctypes.c_void_p(hi.data_ptr()),
                                _stream_ptr(stream), ctypes.byref(st)))
     return lo, hi, st.as_dict()
+
+
+def options_dict(o: Options) -> dict:
+    return {f: getattr(o, f) for f, _ in o._fields_}
+
+
+def autotune(scene: Scene, intr, cells, opts=None, reps: int = 2, stream=None):
+    """Segment length of the pixel loop tuned on a workload (a pose box or a list of
+    cells, as render_batch); returns the tuned options (a dict for render_bounds /
+    render_batch), the bounds rendered with them and their stats."""
+    import torch
+    lib = load()
+    if isinstance(cells, dict):
+        cells = [cells]
+    ci = intrinsics(intr)
+    H, W = ci.height, ci.width
+    m = len(cells)
+    arr = (PoseBox * m)(*[pose_box(c) for c in cells])
+    lo = torch.empty((m, H, W, 3), dtype=torch.float32, device="cuda")
+    hi = torch.empty((m, H, W, 3), dtype=torch.float32, device="cuda")
+    st = Stats()
+    co = options(opts)
+    tuned = Options()
+    _check(lib.ar_autotune(scene.handle, ctypes.byref(ci), arr, m, ctypes.byref(co), int(reps),
+                           ctypes.c_void_p(lo.data_ptr()), ctypes.c_void_p(hi.data_ptr()), _stream_ptr(stream),
+                           ctypes.byref(tuned), ctypes.byref(st)))
+    return options_dict(tuned), lo, hi, st.as_dict()
 
 
 class Server:

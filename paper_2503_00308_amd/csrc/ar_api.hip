@@ -426,6 +426,7 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
   HIP_TRY(launch_tile_ranges(ws.pair_key, (int)npairs, ws.tile_range, (int)nlists, s));
   if (!rotates) {
     const int L = segment_length(prm, npairs, nlists, P);
+    if (st) st->segment_length = std::max(st->segment_length, L);
     const size_t nseg_max = (npairs + (size_t)L - 1) / (size_t)L + nlists;
     rc = ensure_segments(ws, nlists, nseg_max, P);
     if (rc) return rc;
@@ -496,6 +497,7 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
     // lists with at most kPrefixEntries entries and kRotChunkSegs segments (or one longer list)
     const uint32_t *R = ws.host_ranges;
     const int L = rot_segment_length(prm);
+    if (st) st->segment_length = std::max(st->segment_length, L);
     size_t nseg_total = 0, longest = 0;
     for (size_t l = 0; l < nlists; ++l) {
       const size_t nl = R[2 * l + 1] - R[2 * l];
@@ -739,6 +741,57 @@ int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_p
     }
   }
   return AR_OK;
+}
+
+int ar_autotune(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *cells, int32_t ncells,
+                const ar_options *opts, int32_t reps, float *lo_rgb, float *hi_rgb, void *hip_stream,
+                ar_options *tuned, ar_stats *stats) {
+  if (!tuned) return fail(AR_E_INVALID, "tuned options are NULL");
+  if (reps < 1 || reps > 16) return fail(AR_E_INVALID, "reps %d outside [1, 16]", reps);
+  if (!cells || ncells < 1) return fail(AR_E_INVALID, "batch needs at least one cell");
+  ar_options base{};
+  if (opts) base = *opts;
+  bool rot = false;
+  for (int i = 0; i < ncells; ++i) {
+    bool r = false;
+    ar::pose_vars(&cells[i], &r);
+    rot = rot || r;
+  }
+  // the automatic length first
+  base.chunk = 0;
+  ar_stats st{};
+  int rc = ar_render_batch(scene, intr, cells, ncells, &base, lo_rgb, hi_rgb, hip_stream, &st);
+  if (rc) return rc;
+  const int L0 = std::max(8, (int)st.segment_length);
+  std::vector<int> cand;
+  if (rot) {
+    cand = {32, 48, 64, 96, 128};
+  } else {
+    for (int num : {2, 3, 4, 5, 6}) {
+      const int L = std::min(4096, std::max(8, (L0 * num / 4 + 7) / 8 * 8));
+      if (std::find(cand.begin(), cand.end(), L) == cand.end()) cand.push_back(L);
+    }
+  }
+  int best = cand[0];
+  double best_ms = 1e300;
+  for (int L : cand) {
+    ar_options o = base;
+    o.chunk = L;
+    double t = 1e300;
+    for (int r = 0; r < reps; ++r) {
+      ar_stats s1{};
+      rc = ar_render_batch(scene, intr, cells, ncells, &o, lo_rgb, hi_rgb, hip_stream, &s1);
+      if (rc) return rc;
+      t = std::min(t, s1.total_ms);
+    }
+    if (t < best_ms) {
+      best_ms = t;
+      best = L;
+    }
+  }
+  *tuned = base;
+  tuned->chunk = best;
+  return ar_render_batch(scene, intr, cells, ncells, tuned, lo_rgb, hi_rgb, hip_stream, stats);
 }
 
 }  // extern "C"

@@ -135,3 +135,34 @@ def test_batch_full_size_orbit_sampled_tiles():
         dhi = np.abs(bhi[k] - ref["hi"])[np.broadcast_to(ok, ref["hi"].shape)].max()
         print(f"[cfg4 cell {k}] max|dlo| {dlo:.3e} max|dhi| {dhi:.3e}", flush=True)
         assert dlo <= TOL and dhi <= TOL
+
+
+def test_autotune_segment_length():
+    """Autotuning returns a candidate segment length; the bounds it leaves are those of a
+    render with the tuned options, bit for bit, and agree with the default render up to
+    rounding and the early-stop allowance (t_min = 1e-7 on the upper bound)."""
+    api = _api()
+    scene = synth.random_scene(2000, seed=31)
+    intr = synth.intrinsics(64)
+    box = synth.camera6_box(dt=0.08)
+    sc = api.Scene(scene)
+    tuned, lo, hi, st = api.autotune(sc, intr, box)
+    print("translation tuned", tuned["chunk"], st, flush=True)
+    assert tuned["chunk"] % 8 == 0 and 8 <= tuned["chunk"] <= 4096
+    assert st["segment_length"] == tuned["chunk"]
+    l2, h2, _ = api.render_bounds(sc, intr, box, tuned)
+    assert np.array_equal(lo[0].cpu().numpy(), l2.cpu().numpy()) and np.array_equal(hi[0].cpu().numpy(),
+                                                                                      h2.cpu().numpy())
+    l0, h0, _ = api.render_bounds(sc, intr, box)
+    assert np.abs(l0.cpu().numpy() - l2.cpu().numpy()).max() <= 1e-12
+    assert np.abs(h0.cpu().numpy() - h2.cpu().numpy()).max() <= 2e-7
+    sc.close()
+    scene = synth.box_surface_scene(1500, n_boxes=8, seed=32)
+    cells = synth.orbit_cells(6, 10.0, seed=3)
+    sc = api.Scene(scene)
+    tuned, lo, hi, st = api.autotune(sc, intr, cells, reps=1)
+    print("rotation tuned", tuned["chunk"], flush=True)
+    assert tuned["chunk"] in (32, 48, 64, 96, 128)
+    l3, h3, _ = _batch(api, sc, intr, cells, tuned)
+    assert np.array_equal(lo.cpu().numpy(), l3) and np.array_equal(hi.cpu().numpy(), h3)
+    sc.close()
