@@ -9,7 +9,8 @@ second, query latency percentiles, the roofline of the per-pixel kernel (timed w
 HIP events inside the library, on the call's stream) and the FP64 CPU oracle timed
 on a bounded sample of the same workload.  Two more objects in the same line:
 "batched" (50k Gaussians on boxes, 200x200, a 30-degree orbit in 256 cells of uneven
-widths, all cells through ar_render_batch, against the per-query path) and "served"
+widths, all cells through ar_render_batch with the segment length from ar_autotune,
+against the per-query path) and "served"
 (Poisson queries over four resident scenes of 10k-750k Gaussians and images of
 100^2-800^2 through the query server, p50/p99 latency against one-at-a-time service).
 """
@@ -125,19 +126,24 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def batched_measure(api, synth, runs=2, per_query_cells=32):
+def batched_measure(api, synth, runs=2, per_query_cells=32, autotune=True):
     """All 256 orbit cells in one batched call, against one ar_render_bounds per cell."""
     import numpy as np
     import torch
     scene, intr, cells, desc = synth.config(4)
     sc = api.Scene(scene)
-    log("batched: warm-up")
-    api.render_batch(sc, intr, cells)       # warm-up (sizes the workspace)
+    opts = None
+    if autotune:
+        log("batched: autotune")
+        opts, _, _, _ = api.autotune(sc, intr, cells, reps=1)    # also the warm-up
+    else:
+        log("batched: warm-up")
+        api.render_batch(sc, intr, cells)       # warm-up (sizes the workspace)
     torch.cuda.synchronize()
     times, st = [], None
     for _ in range(runs):
         t0 = time.perf_counter()
-        _, _, st = api.render_batch(sc, intr, cells)
+        _, _, st = api.render_batch(sc, intr, cells, opts)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
     t_batch = float(np.median(times))
@@ -146,18 +152,20 @@ def batched_measure(api, synth, runs=2, per_query_cells=32):
     H, W = intr["height"], intr["width"]
     lo = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
     hi = torch.empty_like(lo)
-    api.render_bounds(sc, intr, sub[0], out=(lo, hi))
+    api.render_bounds(sc, intr, sub[0], opts, out=(lo, hi))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     pairs_sub = 0
     for c in sub:
-        _, _, s1 = api.render_bounds(sc, intr, c, out=(lo, hi))
+        _, _, s1 = api.render_bounds(sc, intr, c, opts, out=(lo, hi))
         pairs_sub += s1["pairs"]
     torch.cuda.synchronize()
     t_single = (time.perf_counter() - t0) / len(sub)
     sc.close()
     n = len(cells)
-    return {"workload": desc, "cells": n, "pairs": int(st["pairs"]), "cells_per_s": n / t_batch,
+    return {"workload": desc, "cells": n, "segment_length": st["segment_length"], "autotuned": autotune,
+            "pairs": int(st["pairs"]),
+            "cells_per_s": n / t_batch,
             "pairs_per_s": st["pairs"] / t_batch, "ms_per_cell": t_batch / n * 1e3,
             "device_ms": st["total_ms"], "raster_ms": st["raster_ms"],
             "per_query_ms_per_cell": t_single * 1e3, "per_query_cells_timed": len(sub),
@@ -240,6 +248,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="batched workload: automatic segment length")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_raster_seg_cfg2_traffic.txt"))
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -264,15 +273,16 @@ def main():
     H, W = intr["height"], intr["width"]
     lo = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
     hi = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    opts = None   # the automatic segment length (measured rule); the batch below is autotuned
     for _ in range(args.warmup):
-        api.render_bounds(sc, intr, box, out=(lo, hi))
+        api.render_bounds(sc, intr, box, opts, out=(lo, hi))
     torch.cuda.synchronize()
     lat, raster_ms, pairs = [], [], []
     stats = None
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ts = time.perf_counter()
-        _, _, stats = api.render_bounds(sc, intr, box, out=(lo, hi))
+        _, _, stats = api.render_bounds(sc, intr, box, opts, out=(lo, hi))
         lat.append(time.perf_counter() - ts)
         raster_ms.append(stats["raster_ms"])
         pairs.append(stats["pairs"])
@@ -298,7 +308,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "gaussians": len(scene["mean"]), "image": [W, H], "pose_vars": P,
-                   "tile": 8, "parallelism": "single GPU"},
+                   "tile": 8, "segment_length": stats["segment_length"], "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
         "pairs_per_step": mean_pairs,
         "tile_pairs_per_step": stats["tile_pairs"],
@@ -312,7 +322,7 @@ def main():
     sc.close()
     log(f"headline workload done: {value:.4g} pairs/s")
     if not args.no_batched:
-        out["batched"] = batched_measure(api, synth)
+        out["batched"] = batched_measure(api, synth, autotune=not args.no_autotune)
     if not args.no_served:
         out["served"] = served_measure(api, synth)
     if not args.no_cpu_baseline:
