@@ -45,22 +45,6 @@ __device__ __forceinline__ void acc_zero(Acc<P> &a) {
   a.magh = 0.0f;
 }
 
-// dst += (pre_lo, pre_hi) * src
-template <int P>
-__device__ __forceinline__ void acc_fma(Acc<P> &dst, const Acc<P> &src, double pre_lo, double pre_hi) {
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-#pragma unroll
-    for (int j = 0; j <= P; ++j) {
-      dst.lo[c][j] = fma(pre_lo, src.lo[c][j], dst.lo[c][j]);
-      dst.hi[c][j] = fma(pre_hi, src.hi[c][j], dst.hi[c][j]);
-    }
-    dst.ihi[c] = fma(pre_hi, src.ihi[c], dst.ihi[c]);
-  }
-  dst.magl = fmaf((float)pre_lo, src.magl, dst.magl) * (1.0f + 4.0f * kU32);
-  dst.magh = fmaf((float)pre_hi, src.magh, dst.magh) * (1.0f + 4.0f * kU32);
-}
-
 // Alpha interval of a MatrixInv fallback (footprint bound) or a near-plane straddler.
 template <int P>
 __device__ __forceinline__ double alpha_hi_special(const double *__restrict__ rec, int type, double ux, double uy,
@@ -222,37 +206,6 @@ struct Lookahead {
   }
 };
 
-// Sum the G waves' accumulators into wave 0 through LDS (all threads of the block call it).
-template <int P>
-__device__ void acc_reduce(Acc<P> &acc, double *red, int G, int g, int lane) {
-  constexpr int kRed = 6 * (P + 1) + 3 + 1;
-  for (int w = 1; w < G; ++w) {
-    __syncthreads();
-    if (g == w) {
-      double *dst = red + lane * kRed;
-      int q = 0;
-      for (int c = 0; c < 3; ++c) {
-        for (int j = 0; j <= P; ++j) { dst[q++] = acc.lo[c][j]; dst[q++] = acc.hi[c][j]; }
-        dst[q++] = acc.ihi[c];
-      }
-      float *fm = (float *)(dst + q);  // last slot: the two magnitude sums
-      fm[0] = acc.magl;
-      fm[1] = acc.magh;
-    }
-    __syncthreads();
-    if (g == 0) {
-      const double *src = red + lane * kRed;
-      int q = 0;
-      for (int c = 0; c < 3; ++c) {
-        for (int j = 0; j <= P; ++j) { acc.lo[c][j] += src[q++]; acc.hi[c][j] += src[q++]; }
-        acc.ihi[c] += src[q++];
-      }
-      acc.magl = (acc.magl + ((const float *)(src + q))[0]) * (1.0f + 4.0f * kU32);
-      acc.magh = (acc.magh + ((const float *)(src + q))[1]) * (1.0f + 4.0f * kU32);
-    }
-  }
-}
-
 // Concretise one colour channel's forms over the box and write the pixel's lower / upper
 // value.  nterm bounds the number of summed terms (for the FP64 rounding bound); extra_hi
 // is added to the upper bound (the transmittance left when a segment stops early).
@@ -271,15 +224,6 @@ __device__ __forceinline__ void write_channel(const double *lo_f, const double *
   hi = fmin(fmax(hi, 0.0), 1.0);
   out_lo[idx] = __double2float_rd(lo);
   out_hi[idx] = __double2float_ru(hi);
-}
-
-template <int P>
-__device__ void write_pixel(const Acc<P> &acc, double nterm, double E, double extra_hi, float *out_lo,
-                            float *out_hi, size_t pix) {
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-    write_channel<P>(acc.lo[c], acc.hi[c], acc.ihi[c], acc.magl, acc.magh, nterm, E, extra_hi, out_lo, out_hi,
-                     pix + c);
 }
 
 }  // namespace ar
