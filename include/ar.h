@@ -189,6 +189,21 @@ int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_p
                     void *hip_stream, ar_stats *stats);
 
 /*
+ * Bounds over one pose box partitioned into a grid of cells (Sec. 4.2: the set of
+ * cameras split into subsets, bounds computed per subset and united).  Axis a of the box
+ * is cut into splits[a] equal parts (splits: 6 entries, each >= 1; ORBIT boxes use
+ * splits[0] only; a zero-width axis is not cut); the cells are rendered as by
+ * ar_render_batch (in launches of up to 64 cells, or options.cells_per_launch) and the
+ * output is their union, the elementwise minimum of the lower and maximum of the upper
+ * images, which encloses every pose of the box and is usually tighter than the bounds of
+ * the whole box.  lo_rgb / hi_rgb: [H][W][3] float32, device memory.  At most 65536
+ * cells.  stats (may be NULL) accumulates over the cells.  Returns AR_OK or an error code.
+ */
+int ar_render_partitioned(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *box,
+                          const int32_t *splits, const ar_options *opts, float *lo_rgb, float *hi_rgb,
+                          void *hip_stream, ar_stats *stats);
+
+/*
  * Autotuning of the pixel loop's segment length (options.chunk) for a workload: one pose
  * box (ncells = 1) or a batch of cells, rendered as ar_render_batch.  The workload is
  * rendered with the automatic length, then with candidates (translation boxes: the

@@ -92,6 +92,9 @@ SYMBOLS = {
     "ar_render_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
                                        ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.POINTER(Stats)]),
+    "ar_render_partitioned": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
+                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Options), ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Stats)]),
     "ar_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox), ctypes.c_int32,
                                    ctypes.POINTER(Options), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.POINTER(Options), ctypes.POINTER(Stats)]),
@@ -230,6 +233,29 @@ def render_batch(scene: Scene, intr, cells, opts=None, stream=None):
     _check(lib.ar_render_batch(scene.handle, ctypes.byref(ci), arr, m, ctypes.byref(co),
                                ctypes.c_void_p(lo.data_ptr()), ctypes.c_void_p(hi.data_ptr()),
                                _stream_ptr(stream), ctypes.byref(st)))
+    return lo, hi, st.as_dict()
+
+
+def render_partitioned(scene: Scene, intr, box, splits, opts=None, stream=None, out=None):
+    """Bounds over a pose box cut into a grid of cells (splits: cuts per axis, up to 6),
+    the union of the cells' bounds: tensors (H, W, 3) and the cells' accumulated stats."""
+    import torch
+    lib = load()
+    ci = intrinsics(intr)
+    H, W = ci.height, ci.width
+    if out is None:
+        lo = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+        hi = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    else:
+        lo, hi = out
+    sp = list(splits) + [1] * (6 - len(splits))
+    arr = (ctypes.c_int32 * 6)(*[int(v) for v in sp[:6]])
+    st = Stats()
+    cb = pose_box(box)
+    co = options(opts)
+    _check(lib.ar_render_partitioned(scene.handle, ctypes.byref(ci), ctypes.byref(cb), arr, ctypes.byref(co),
+                                     ctypes.c_void_p(lo.data_ptr()), ctypes.c_void_p(hi.data_ptr()),
+                                     _stream_ptr(stream), ctypes.byref(st)))
     return lo, hi, st.as_dict()
 
 

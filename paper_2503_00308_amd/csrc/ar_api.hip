@@ -348,6 +348,38 @@ size_t query_bytes(const ar_scene *sc, const Params &prm, int P, bool rotates, i
   return (size_t)b;
 }
 
+// Union of m cell images (each n floats) into out: minimum of the lower images, maximum of
+// the upper ones; with first, out is overwritten, else included.
+__global__ void k_union(const float *__restrict__ lo_c, const float *__restrict__ hi_c, int m, size_t n, bool first,
+                        float *__restrict__ lo, float *__restrict__ hi) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float l = first ? INFINITY : lo[i], h = first ? -INFINITY : hi[i];
+  for (int c = 0; c < m; ++c) {
+    l = fminf(l, lo_c[(size_t)c * n + i]);
+    h = fmaxf(h, hi_c[(size_t)c * n + i]);
+  }
+  lo[i] = l;
+  hi[i] = h;
+}
+
+void add_stats(ar_stats &a, const ar_stats &b) {
+  a.pairs += b.pairs;
+  a.tile_pairs += b.tile_pairs;
+  a.n_fallback += b.n_fallback;
+  a.n_wild += b.n_wild;
+  a.n_dropped += b.n_dropped;
+  a.P = std::max(a.P, b.P);
+  a.max_window = std::max(a.max_window, b.max_window);
+  a.segment_length = std::max(a.segment_length, b.segment_length);
+  a.raster_ms += b.raster_ms;
+  a.total_ms += b.total_ms;
+  a.runs += b.runs;
+  a.cycles_a += b.cycles_a;
+  a.cycles_b += b.cycles_b;
+  a.ind_tests += b.ind_tests;
+}
+
 // Cells per launch of a batch: the option if given, else as many as fit a quarter of
 // the free device memory (at most 64 GiB) at the list density of the last launch (32
 // list entries per Gaussian before the first), at most 256.
@@ -740,6 +772,63 @@ int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_p
       i += m;
     }
   }
+  return AR_OK;
+}
+
+int ar_render_partitioned(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *box,
+                          const int32_t *splits, const ar_options *opts, float *lo_rgb, float *hi_rgb,
+                          void *hip_stream, ar_stats *stats) {
+  if (!scene) return fail(AR_E_INVALID, "scene is NULL");
+  int rc = ar::validate_box(box);
+  if (rc) return rc;
+  if (!splits) return fail(AR_E_INVALID, "splits is NULL");
+  if (!intr || intr->width < 1 || intr->height < 1) return fail(AR_E_INVALID, "bad intrinsics");
+  rc = ar::check_outputs(lo_rgb, hi_rgb);
+  if (rc) return rc;
+  const int na = box->model == AR_POSE_ORBIT ? 1 : 6;
+  int s[6] = {1, 1, 1, 1, 1, 1};
+  size_t ncells = 1;
+  for (int a = 0; a < na; ++a) {
+    if (splits[a] < 1 || splits[a] > 65536) return fail(AR_E_INVALID, "splits[%d] = %d outside [1, 65536]", a, splits[a]);
+    s[a] = box->hi[a] > box->lo[a] ? splits[a] : 1;
+    ncells *= (size_t)s[a];
+    if (ncells > 65536) return fail(AR_E_INVALID, "more than 65536 cells");
+  }
+  // the grid of cells; adjacent cells share the computed cut exactly, the last ends at hi
+  std::vector<ar_pose_box> cells(ncells, *box);
+  for (size_t c = 0; c < ncells; ++c) {
+    size_t r = c;
+    for (int a = 0; a < na; ++a) {
+      const int k = (int)(r % (size_t)s[a]);
+      r /= (size_t)s[a];
+      if (s[a] == 1) continue;
+      const double lo = box->lo[a], w = box->hi[a] - box->lo[a];
+      cells[c].lo[a] = lo + w * k / s[a];
+      cells[c].hi[a] = k + 1 == s[a] ? box->hi[a] : lo + w * (k + 1) / s[a];
+    }
+  }
+  const int per = opts && opts->cells_per_launch > 0 ? opts->cells_per_launch : 64;
+  const size_t img = (size_t)intr->width * intr->height * 3;
+  const int m_max = (int)std::min<size_t>(ncells, (size_t)per);
+  ar::Workspace &ws = const_cast<ar_scene *>(scene)->ws;
+  if (2 * (size_t)m_max * img > ws.cap_union || !ws.union_img) {
+    HIP_TRY(ar::grow(ws, ws.union_img, 2 * (size_t)m_max * img));
+    ws.cap_union = 2 * (size_t)m_max * img;
+  }
+  float *tlo = ws.union_img, *thi = ws.union_img + (size_t)m_max * img;
+  ar_stats total{};
+  for (size_t c0 = 0; c0 < ncells; c0 += (size_t)m_max) {
+    const int m = (int)std::min<size_t>((size_t)m_max, ncells - c0);
+    ar_stats st{};
+    rc = ar_render_batch(scene, intr, cells.data() + c0, m, opts, tlo, thi, hip_stream, &st);
+    if (rc) return rc;
+    ar::add_stats(total, st);
+    hipLaunchKernelGGL(ar::k_union, dim3((unsigned)((img + 255) / 256)), dim3(256), 0, (hipStream_t)hip_stream, tlo,
+                       thi, m, img, c0 == 0, lo_rgb, hi_rgb);
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipStreamSynchronize((hipStream_t)hip_stream));
+  if (stats) *stats = total;
   return AR_OK;
 }
 

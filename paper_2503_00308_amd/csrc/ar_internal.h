@@ -151,6 +151,8 @@ struct Workspace {
   double *cform = nullptr;     // [pairs][2][P + 1] depth forms by list position
   size_t cap_compact = 0;      // doubles of cform
   size_t cap_cmean = 0;        // positions of cmean
+  float *union_img = nullptr;  // cell images of a partitioned render (lower, then upper)
+  size_t cap_union = 0;
   double *pre = nullptr;       // two planes [pairs][64]: running sums of log(1 - a_lo), log(1 - a_hi)
   uint32_t *prez = nullptr;    // [pairs][64] per-pixel prefix counts of a_hi == 1
   size_t cap_pre = 0;
