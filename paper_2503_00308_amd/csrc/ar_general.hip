@@ -664,59 +664,111 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const double *rec = recs + (size_t)gid * R::STRIDE;
     const int type = la.type(k);
     const bool kept = inimg && la.kept(k, type, ux, uy);
-    if (!kept) continue;
     // runs of certain occluders and of possible occluders: sums of the logs over
-    // [a, b) = S(b - 1) - S(a - 1), S(p) the absolute running sum at p
+    // [a, b) = S(b - 1) - S(a - 1), S(p) for p >= 1 the running sum at index
+    // (pb + p - 1) * 64 + lane, plus (unless ABS) the offset of the segment holding p - 1
     const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)cv0, k);
     const uint32_t d1 = (uint32_t)__builtin_amdgcn_readlane((int)cv1, k);
     const uint32_t m0 = d1, m1 = (uint32_t)__builtin_amdgcn_readlane((int)cv2, k);
-    // S(p) for p >= 1: the running sum at index (pb + p - 1) * 64 + lane, plus (unless
-    // ABS) the offset of the segment holding position p - 1
     const double *sL = preL + lane, *sH = preH + lane;
     const uint32_t *sZ = prez + lane;
     double sum_l = 0.0, err_l = 0.0, sum_h = 0.0, err_h = 0.0;
     uint32_t zc = 0;
-    for (uint32_t q = d0; q < d1; ++q) {
-      const uint2 ab = *reinterpret_cast<const uint2 *>(runs + 2 * (size_t)q);
-      double La = 0.0, Lb = 0.0;
-      if (ab.x > 0) {
-        La = sL[(pb + ab.x - 1) * 64];
-        if (!ABS) La += segoff[(size_t)(sl + (int)(ab.x - 1) / L) * 64 + lane].x;
+    if (ABS) {
+      // many runs per entry: the runs are read 64 at a time (one per lane) and their ends
+      // four runs at a time, so eight loads are in flight; the sums are taken in run
+      // order.  The run ends are read back with readlane from the lane that loaded them,
+      // so every lane takes part (a lane whose pixel is not kept uses none of the sums);
+      // entries no lane keeps are skipped as a whole.
+      if (!__any(kept)) continue;
+      // S(p) at the clamped index (a valid position of the list when p = 0), zero for p = 0
+      auto ix = [&](uint32_t p) -> size_t { return pb + (p > 0 ? p - 1 : 0); };
+      const uint2 *runs2 = reinterpret_cast<const uint2 *>(runs);
+      constexpr int kRunGroup = 4;
+      for (uint32_t qb = d0; qb < d1; qb += 64) {
+        const int nq = (int)min(64u, d1 - qb);
+        uint2 abv = make_uint2(0u, 0u);
+        if (lane < nq) abv = runs2[qb + lane];
+        for (int u = 0; u < nq; u += kRunGroup) {
+          double La[kRunGroup], Lb[kRunGroup];
+#pragma unroll
+          for (int t = 0; t < kRunGroup; ++t) {
+            const int r = min(u + t, nq - 1);
+            const uint32_t pa = (uint32_t)__builtin_amdgcn_readlane((int)abv.x, r);
+            const uint32_t pe = (uint32_t)__builtin_amdgcn_readlane((int)abv.y, r);
+            const double va = sL[ix(pa) * 64], ve = sL[ix(pe) * 64];
+            La[t] = pa > 0 ? va : 0.0;
+            Lb[t] = pe > 0 ? ve : 0.0;
+          }
+#pragma unroll
+          for (int t = 0; t < kRunGroup; ++t) {
+            if (u + t < nq) {
+              sum_l += Lb[t] - La[t];
+              err_l += fabs(La[t]) + fabs(Lb[t]);
+            }
+          }
+        }
       }
-      if (ab.y > 0) {
-        Lb = sL[(pb + ab.y - 1) * 64];
-        if (!ABS) Lb += segoff[(size_t)(sl + (int)(ab.y - 1) / L) * 64 + lane].x;
+      for (uint32_t qb = m0; qb < m1; qb += 64) {
+        const int nq = (int)min(64u, m1 - qb);
+        uint2 abv = make_uint2(0u, 0u);
+        if (lane < nq) abv = runs2[qb + lane];
+        for (int u = 0; u < nq; u += kRunGroup) {
+          double La[kRunGroup], Lb[kRunGroup];
+          uint32_t Za[kRunGroup], Zb[kRunGroup];
+#pragma unroll
+          for (int t = 0; t < kRunGroup; ++t) {
+            const int r = min(u + t, nq - 1);
+            const uint32_t pa = (uint32_t)__builtin_amdgcn_readlane((int)abv.x, r);
+            const uint32_t pe = (uint32_t)__builtin_amdgcn_readlane((int)abv.y, r);
+            const double va = sH[ix(pa) * 64], ve = sH[ix(pe) * 64];
+            const uint32_t za = sZ[ix(pa) * 64], ze = sZ[ix(pe) * 64];
+            La[t] = pa > 0 ? va : 0.0;
+            Lb[t] = pe > 0 ? ve : 0.0;
+            Za[t] = pa > 0 ? za : 0u;
+            Zb[t] = pe > 0 ? ze : 0u;
+          }
+#pragma unroll
+          for (int t = 0; t < kRunGroup; ++t) {
+            if (u + t < nq) {
+              sum_h += Lb[t] - La[t];
+              err_h += fabs(La[t]) + fabs(Lb[t]);
+              zc += Zb[t] - Za[t];
+            }
+          }
+        }
       }
-      sum_l += Lb - La;
-      err_l += fabs(La) + fabs(Lb);
-    }
-    for (uint32_t q = m0; q < m1; ++q) {
-      const uint2 ab = *reinterpret_cast<const uint2 *>(runs + 2 * (size_t)q);
-      double La = 0.0, Lb = 0.0;
-      uint32_t Za = 0, Zb = 0;
-      if (ab.x > 0) {
-        La = sH[(pb + ab.x - 1) * 64];
-        Za = sZ[(pb + ab.x - 1) * 64];
-        if (!ABS) {
+    } else {
+      // few runs per entry: one run at a time, kept lanes only
+      if (!kept) continue;
+      for (uint32_t q = d0; q < d1; ++q) {
+        const uint2 ab = *reinterpret_cast<const uint2 *>(runs + 2 * (size_t)q);
+        double La = 0.0, Lb = 0.0;
+        if (ab.x > 0) La = sL[(pb + ab.x - 1) * 64] + segoff[(size_t)(sl + (int)(ab.x - 1) / L) * 64 + lane].x;
+        if (ab.y > 0) Lb = sL[(pb + ab.y - 1) * 64] + segoff[(size_t)(sl + (int)(ab.y - 1) / L) * 64 + lane].x;
+        sum_l += Lb - La;
+        err_l += fabs(La) + fabs(Lb);
+      }
+      for (uint32_t q = m0; q < m1; ++q) {
+        const uint2 ab = *reinterpret_cast<const uint2 *>(runs + 2 * (size_t)q);
+        double La = 0.0, Lb = 0.0;
+        uint32_t Za = 0, Zb = 0;
+        if (ab.x > 0) {
           const size_t so = (size_t)(sl + (int)(ab.x - 1) / L) * 64 + lane;
-          La += segoff[so].y;
-          Za += segz[so];
+          La = sH[(pb + ab.x - 1) * 64] + segoff[so].y;
+          Za = sZ[(pb + ab.x - 1) * 64] + segz[so];
         }
-      }
-      if (ab.y > 0) {
-        Lb = sH[(pb + ab.y - 1) * 64];
-        Zb = sZ[(pb + ab.y - 1) * 64];
-        if (!ABS) {
+        if (ab.y > 0) {
           const size_t so = (size_t)(sl + (int)(ab.y - 1) / L) * 64 + lane;
-          Lb += segoff[so].y;
-          Zb += segz[so];
+          Lb = sH[(pb + ab.y - 1) * 64] + segoff[so].y;
+          Zb = sZ[(pb + ab.y - 1) * 64] + segz[so];
         }
+        sum_h += Lb - La;
+        err_h += fabs(La) + fabs(Lb);
+        zc += Zb - Za;
       }
-      sum_h += Lb - La;
-      err_h += fabs(La) + fabs(Lb);
-      zc += Zb - Za;
     }
-    // rounding of the logs and of the running sums: (terms + 2) 2^-51 per magnitude
+    if (!kept) continue;
     const double thi = exp(sum_l + nn * 0x1p-51 * err_l) * (1.0 + 0x1p-50);
     const double tlo = zc ? 0.0 : exp(sum_h - nn * 0x1p-51 * err_h) * (1.0 - 0x1p-50);
     double alo, ahi;
