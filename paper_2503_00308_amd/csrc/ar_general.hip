@@ -117,25 +117,29 @@ __global__ __launch_bounds__(256) void k_list_box(const uint32_t *__restrict__ r
 template <int P, int S = kMaxP + 1>
 __device__ __forceinline__ int ind_pair(const PoseForms &pose, const double *uwi, const double *uwj,
                                         const double *dfi, const double *dfj) {
-  // identity bound: sum_l A_z,l * (uw_i - uw_j)_l, each term a scaled form
-  double lo[P + 1], up[P + 1];
+  // identity bound: sum_l A_z,l * (uw_i - uw_j)_l, each term a scaled form; with A_z,l
+  // in mid-radius form (m, r), c A_z,l has lower form c m - |c| r and upper c m + |c| r
+  double mid[P + 1], rad[P + 1];
 #pragma unroll
-  for (int k = 0; k <= P; ++k) { lo[k] = 0.0; up[k] = 0.0; }
+  for (int k = 0; k <= P; ++k) { mid[k] = 0.0; rad[k] = 0.0; }
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
-    const double c = uwi[l] - uwj[l];
-    const double(*a)[kMaxP + 1] = pose.A[6 + l];
-    const double *fl = c >= 0.0 ? a[0] : a[1];
-    const double *fu = c >= 0.0 ? a[1] : a[0];
+    const double c = uwi[l] - uwj[l], ac = fabs(c);
 #pragma unroll
-    for (int k = 0; k < P; ++k) { lo[k] += c * fl[k]; up[k] += c * fu[k]; }
-    lo[P] += c * fl[kMaxP];
-    up[P] += c * fu[kMaxP];
+    for (int k = 0; k < P; ++k) {
+      mid[k] = fma(c, pose.Zm[l][k], mid[k]);
+      rad[k] = fma(ac, pose.Zr[l][k], rad[k]);
+    }
+    mid[P] = fma(c, pose.Zm[l][kMaxP], mid[P]);
+    rad[P] = fma(ac, pose.Zr[l][kMaxP], rad[P]);
   }
   double slo = 0.0, sup = 0.0;
 #pragma unroll
-  for (int k = 0; k < P; ++k) { slo += fabs(lo[k]); sup += fabs(up[k]); }
-  const double lo_r = lo[P] - slo, hi_r = up[P] + sup;
+  for (int k = 0; k < P; ++k) {
+    slo += fabs(mid[k] - rad[k]);
+    sup += fabs(mid[k] + rad[k]);
+  }
+  const double lo_r = (mid[P] - rad[P]) - slo, hi_r = (mid[P] + rad[P]) + sup;
   // both bounds are sound, so when the identity decides the literal bound cannot
   // contradict it; its form loads are skipped
   if (lo_r > 0.0) return 1;
@@ -485,6 +489,119 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
     if (lane == 0) {
       atomicMax(&counters[5], wmax);
       atomicAdd(&counters[1], wsum);
+    }
+  }
+}
+
+// Counting pass for long windows (the compact copy in use): the lanes hold 64 consecutive
+// entries and walk the union of their windows together, so list position j is the same
+// for every lane and its mean and depth forms are scalar loads shared by the wave (the
+// wave-wide walk of wave_runs loads them per lane, once for every entry whose window
+// holds j).  Entries of different lists in one wave are taken list by list.  Each lane
+// counts its runs and stores its long window's masks in the layout of wave_runs.
+template <int P>
+__global__ __launch_bounds__(256) void k_runs_count_lanes(const uint32_t *__restrict__ pkey,
+                                                          const uint32_t *__restrict__ ranges,
+                                                          const uint32_t *__restrict__ lists,
+                                                          const float4 *__restrict__ cmean,
+                                                          const double *__restrict__ cform,
+                                                          const PoseForms *__restrict__ poses, int ntiles,
+                                                          SceneDev sc, int npairs, const uint32_t *__restrict__ win,
+                                                          const uint32_t *__restrict__ woff,
+                                                          unsigned long long *__restrict__ masks,
+                                                          uint32_t *__restrict__ cnt) {
+  using Src = IndSrc<P, true>;
+  constexpr int S = Src::S;
+  const int lane = threadIdx.x & 63;
+  const int wave0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+  const int nwaves = (int)(gridDim.x * (blockDim.x >> 6));
+  for (int p0 = wave0 * 64; p0 < npairs; p0 += nwaves * 64) {
+    const int p = p0 + lane;
+    const bool have = p < npairs;
+    uint32_t tile = 0;
+    int beg = 0, i = 0, ps = 0, qe = 0;
+    double uwi[3] = {0.0, 0.0, 0.0}, dfi[2 * S];
+#pragma unroll
+    for (int k = 0; k < 2 * S; ++k) dfi[k] = 0.0;
+    if (have) {
+      tile = pkey[p];
+      beg = (int)ranges[2 * tile];
+      i = p - beg;
+      ps = (int)win[2 * (size_t)p];
+      qe = (int)win[2 * (size_t)p + 1];
+      const float4 m = cmean[p];
+      uwi[0] = m.x;
+      uwi[1] = m.y;
+      uwi[2] = m.z;
+#pragma unroll
+      for (int k = 0; k < 2 * S; ++k) dfi[k] = cform[(size_t)p * (2 * S) + k];
+    }
+    uint32_t ndef = 0, nmay = 0;
+    bool pending = have;
+    for (;;) {
+      const unsigned long long pend = __ballot(pending);
+      if (!pend) break;
+      const int l0 = __builtin_ctzll(pend);
+      const uint32_t gtile = (uint32_t)__builtin_amdgcn_readlane((int)tile, l0);
+      const bool mine = pending && tile == gtile;
+      pending = pending && !mine;
+      // the union of the group's windows
+      int lo = mine ? ps : 0x7fffffff, hi = mine ? qe : 0;
+      for (int off = 32; off > 0; off >>= 1) {
+        lo = min(lo, __shfl_xor(lo, off));
+        hi = max(hi, __shfl_xor(hi, off));
+      }
+      lo = __builtin_amdgcn_readfirstlane(lo);
+      hi = __builtin_amdgcn_readfirstlane(hi);
+      const int gbeg = __builtin_amdgcn_readlane(beg, l0);
+      const int gcell = (int)(gtile / (uint32_t)ntiles);
+      const PoseForms &pose = poses[gcell];
+      const Src src{lists + gbeg, sc.mean, cform, cmean, sc.n, (size_t)gcell * sc.n, (size_t)gbeg};
+      int def_start = (mine && ps > 0) ? 0 : -1;   // open run [0, ps) of certain occluders
+      int may_start = def_start;
+      uint32_t nd = 0, nm = 0;
+      const bool store = mine && masks != nullptr && qe - ps > kWaveWindow;
+      unsigned long long *mk = store ? masks + woff[p] : nullptr;
+      unsigned long long wd = 0, wm = 0;
+      for (int j = lo; j < hi; ++j) {
+        double uwj[3];
+        src.mean_of(j, uwj);
+        const double *dfj = src.forms_of(j);
+        if (mine && j >= ps && j < qe) {
+          const int ind = j != i ? ind_pair<P, S>(pose, uwi, uwj, dfi, dfj) : 0;
+          const bool d1 = ind == 1, m1 = ind != 0;
+          if (d1 && def_start < 0) def_start = j;
+          if (!d1 && def_start >= 0) {
+            ++nd;
+            def_start = -1;
+          }
+          if (m1 && may_start < 0) may_start = j;
+          if (!m1 && may_start >= 0) {
+            ++nm;
+            may_start = -1;
+          }
+          if (store) {
+            const int b = (j - ps) & 63;
+            if (d1) wd |= 1ull << b;
+            if (m1) wm |= 1ull << b;
+            if (b == 63 || j == qe - 1) {
+              const int w = (j - ps) >> 6;
+              mk[2 * w] = wd;
+              mk[2 * w + 1] = wm;
+              wd = 0;
+              wm = 0;
+            }
+          }
+        }
+      }
+      if (mine) {
+        ndef = nd + (def_start >= 0 ? 1u : 0u);
+        nmay = nm + (may_start >= 0 ? 1u : 0u);
+      }
+    }
+    if (have) {
+      cnt[2 * (size_t)p] = ndef;
+      cnt[2 * (size_t)p + 1] = nmay;
     }
   }
 }
@@ -866,8 +983,13 @@ static hipError_t launch_runs_p(const Workspace &ws, const uint32_t *lists, cons
   if (mode == kRunsWindows)
     return launch_runs_pm<P, kRunsWindows, false>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, masks, s);
   if (compact) {
-    if (mode == kRunsCount)
-      return launch_runs_pm<P, kRunsCount, true>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, masks, s);
+    if (mode == kRunsCount) {
+      const dim3 grid((unsigned)std::min<size_t>(((size_t)npairs + 255) / 256, 8192)), block(256);
+      hipLaunchKernelGGL(k_runs_count_lanes<P>, grid, block, 0, s, ws.pair_key, ws.tile_range, lists,
+                         (const float4 *)ws.cmean, ws.cform, poses_dev, ntiles, sc, npairs, ws.win, ws.woff, masks,
+                         ws.run_cnt);
+      return hipGetLastError();
+    }
     return launch_runs_pm<P, kRunsEmit, true>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, masks, s);
   }
   if (mode == kRunsCount)

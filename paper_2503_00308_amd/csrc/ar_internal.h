@@ -77,6 +77,7 @@ struct PoseForms {
   double A[9][2][kMaxP + 1];
   double tau[3][2][kMaxP + 1];
   double beta[3][2][kMaxP + 1];
+  double Zm[3][kMaxP + 1], Zr[3][kMaxP + 1];   // depth row of A in mid-radius form (Ind tests)
 };
 
 struct Params {

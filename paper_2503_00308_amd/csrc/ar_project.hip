@@ -115,6 +115,11 @@ __host__ __device__ void pose_forms(const ar_pose_box &b, PoseForms &pf) {
     store_form<P>(pf.tau[k], tau[k]);
     store_form<P>(pf.beta[k], beta[k]);
   }
+  for (int l = 0; l < 3; ++l)
+    for (int k = 0; k <= kMaxP; ++k) {
+      pf.Zm[l][k] = 0.5 * (pf.A[6 + l][0][k] + pf.A[6 + l][1][k]);
+      pf.Zr[l][k] = 0.5 * (pf.A[6 + l][1][k] - pf.A[6 + l][0][k]);
+    }
 }
 
 // ---------------------------------------------------------------------------------
