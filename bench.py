@@ -11,7 +11,8 @@ on a bounded sample of the same workload.  More objects in the same line:
 "batched" (50k Gaussians on boxes, 200x200, a 30-degree orbit in 256 cells of uneven
 widths, all cells through ar_render_batch with the segment length from ar_autotune,
 against the per-query path), with --partitioned "partitioned" (the bench box cut into
-2x2x2 cells whose bounds are united: time and mean bound width against the whole box), and
+2x2x2 cells whose bounds are united: time and mean bound width against the whole box), with
+--refined "refined" (an orbit box over the batched scene bisected where MatrixInv fails), and
 "served"
 (Poisson queries over four resident scenes of 10k-750k Gaussians and images of
 100^2-800^2 through the query server, p50/p99 latency against one-at-a-time service).
@@ -198,6 +199,50 @@ def partitioned_measure(api, sc, intr, box, splits=(2, 2, 2), runs=3):
             "mean_width": width, "mean_width_whole_box": whole}
 
 
+def refined_measure(api, synth, deg=3.0, max_cells=64, runs=3):
+    """Adaptive refinement (cells bisected where MatrixInv fails, united) of one orbit box
+    over the batched workload's scene: time, leaves, and the mean bound width against the
+    whole box and against an even cut into as many cells."""
+    import numpy as np
+    import torch
+    scene = synth.box_surface_scene(50_000, n_boxes=20, seed=0)
+    intr = synth.intrinsics(200)
+    a = np.deg2rad(deg)
+    box = {"model": synth.ORBIT, "R0": np.eye(3), "t0": np.zeros(3), "pivot": np.array([0.0, 0.0, 4.0]),
+           "lo": np.array([-a, 0, 0, 0, 0, 0]), "hi": np.array([a, 0, 0, 0, 0, 0])}
+    sc = api.Scene(scene)
+    api.render_refined(sc, intr, box, max_cells)      # warm-up
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        lo, hi, leaves, st = api.render_refined(sc, intr, box, max_cells)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t = float(np.median(times))
+    width = float((hi - lo).mean().item())
+    wlo, whi, _ = api.render_bounds(sc, intr, box)
+    plo, phi, _ = api.render_partitioned(sc, intr, box, (len(leaves),))
+    torch.cuda.synchronize()
+    counts = api.classify_cells(sc, intr, [box] + leaves)
+    n = len(leaves)
+    even = []
+    for k in range(n):
+        c = {**box, "lo": box["lo"].copy(), "hi": box["hi"].copy()}
+        c["lo"][0] = -a + 2 * a * k / n
+        c["hi"][0] = a if k + 1 == n else -a + 2 * a * (k + 1) / n
+        even.append(c)
+    even_counts = api.classify_cells(sc, intr, even)
+    out = {"workload": f"50k Gaussians on 20 boxes, 200x200, orbit +-{deg:g} deg, at most {max_cells} cells",
+           "ms": t * 1e3, "leaves": len(leaves), "pairs_per_s": st["pairs"] / t,
+           "matinv_failures_whole_box": int(counts[0, 0]), "leaves_with_failures": int(np.count_nonzero(counts[1:, 0])),
+           "mean_width": width, "mean_width_whole_box": float((whi - wlo).mean().item()),
+           "mean_width_even_cut": float((phi - plo).mean().item()),
+           "even_cut_cells_with_failures": int(np.count_nonzero(even_counts[:, 0]))}
+    sc.close()
+    return out
+
+
 def served_measure(api, synth, nq=48, load=0.75, slots=4, seed=0):
     """Poisson arrivals at `load` x the one-at-a-time capacity; the server's latencies
     against a FIFO one-at-a-time queue with each query's measured solo service time."""
@@ -274,6 +319,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="batched workload: automatic segment length")
+    ap.add_argument("--refined", action="store_true",
+                    help="also an orbit box refined where MatrixInv fails (left out of the default run, as "
+                         "--partitioned)")
     ap.add_argument("--partitioned", action="store_true",
                     help="also the bench box cut into 2x2x2 cells (its pixel-kernel launches are of another size, "
                          "so it is left out of the default run that the kernel trace covers)")
@@ -351,6 +399,8 @@ def main():
     if args.partitioned:
         out["partitioned"] = partitioned_measure(api, sc, intr, box)
     sc.close()
+    if args.refined:
+        out["refined"] = refined_measure(api, synth)
     if not args.no_batched:
         out["batched"] = batched_measure(api, synth, autotune=not args.no_autotune)
     if not args.no_served:

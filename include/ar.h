@@ -204,6 +204,43 @@ int ar_render_partitioned(const ar_scene *scene, const ar_intrinsics *intr, cons
                           void *hip_stream, ar_stats *stats);
 
 /*
+ * Per pose cell, the counts that drive the adaptive refinement (ar_render_refined):
+ * counts[2c] = Gaussians whose MatrixInv convergence assertion fails over cell c
+ * (Sec. 3.1, Alg. MatrixInv) and that the pruning test keeps at some pixel of the
+ * image (the binning's float32 test on the rectangle of all pixel centres);
+ * counts[2c + 1] = Gaussians straddling the near plane over cell c (alpha in [0, o]).
+ * counts: host memory, 2 * ncells int64.  Synchronises the stream.  Returns AR_OK or an
+ * error code (invalid cell, options or intrinsics; device failure).
+ */
+int ar_classify_cells(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *cells, int32_t ncells,
+                      const ar_options *opts, int64_t *counts, void *hip_stream);
+
+/* Criteria of ar_render_refined (bit mask; 0 means AR_REFINE_MATINV). */
+enum {
+  AR_REFINE_MATINV = 1,   /* cut cells holding a MatrixInv failure kept in the image */
+  AR_REFINE_NEAR = 2      /* cut cells holding a near-plane straddler */
+};
+
+/*
+ * Bounds over a pose box refined where MatrixInv fails (Sec. 3.1: the input range is
+ * divided until the convergence assertion holds; Sec. 4.2: bounds of subsets of the
+ * cameras, united).  Cells are taken level by level, in order, starting from the whole
+ * box; a cell flagged by the criteria (counts of ar_classify_cells) at depth k (k
+ * bisections from the box) is cut at the midpoint 0.5 (lo + hi) of its active axis
+ * number k mod (number of active axes) (ORBIT: the angle), lower half first, while the
+ * number of cells stays within max_cells (1..65536) and k < 24; every other cell is a
+ * leaf.  The leaves are rendered as ar_render_batch and united (elementwise minimum of
+ * the lower, maximum of the upper images) into lo_rgb / hi_rgb ([H][W][3] float32,
+ * device memory), which enclose every pose of the box.  cells_out (may be NULL; room for
+ * max_cells boxes) receives the leaves in the order they were settled and *ncells_out
+ * (may be NULL) their number; stats (may be NULL) accumulates over the leaves' renders.
+ * Returns AR_OK or an error code (AR_E_INVALID for max_cells or criteria out of range).
+ */
+int ar_render_refined(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *box,
+                      const ar_options *opts, int32_t max_cells, int32_t criteria, float *lo_rgb, float *hi_rgb,
+                      void *hip_stream, ar_pose_box *cells_out, int32_t *ncells_out, ar_stats *stats);
+
+/*
  * Autotuning of the pixel loop's segment length (options.chunk) for a workload: one pose
  * box (ncells = 1) or a batch of cells, rendered as ar_render_batch.  The workload is
  * rendered with the automatic length, then with candidates (translation boxes: the

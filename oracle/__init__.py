@@ -11,6 +11,7 @@ Modules:
   matinv  MatrixInv (Sec. 3.1) on 2x2 linear forms
   render  concrete renderer (Alg. GaussianSplat, BlendSort, BlendInd), FP64
   splat   AbstractSplat (Sec. 3.3): lower/upper images over a pose box
+  refine  adaptive refinement of a pose box where MatrixInv fails (Sec. 3.1, 4.2)
 
 Parity status: every function is pinned by the CPU tests (tests/test_oracle_*.py)
 against closed forms, the paper's printed examples, brute force on small inputs,

@@ -95,6 +95,13 @@ SYMBOLS = {
     "ar_render_partitioned": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
                                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Options), ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Stats)]),
+    "ar_classify_cells": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
+                                         ctypes.c_int32, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.c_void_p]),
+    "ar_render_refined": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
+                                         ctypes.POINTER(Options), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(PoseBox),
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Stats)]),
     "ar_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox), ctypes.c_int32,
                                    ctypes.POINTER(Options), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.POINTER(Options), ctypes.POINTER(Stats)]),
@@ -257,6 +264,53 @@ def render_partitioned(scene: Scene, intr, box, splits, opts=None, stream=None, 
                                      ctypes.c_void_p(lo.data_ptr()), ctypes.c_void_p(hi.data_ptr()),
                                      _stream_ptr(stream), ctypes.byref(st)))
     return lo, hi, st.as_dict()
+
+
+REFINE_MATINV = 1
+REFINE_NEAR = 2
+
+
+def classify_cells(scene: Scene, intr, cells, opts=None, stream=None):
+    """Per pose cell: (MatrixInv failures kept somewhere in the image, near-plane
+    straddlers), an int64 array (ncells, 2)."""
+    lib = load()
+    ci = intrinsics(intr)
+    arr = (PoseBox * len(cells))(*[pose_box(c) for c in cells])
+    out = (ctypes.c_int64 * (2 * len(cells)))()
+    co = options(opts)
+    _check(lib.ar_classify_cells(scene.handle, ctypes.byref(ci), arr, len(cells), ctypes.byref(co), out,
+                                 _stream_ptr(stream)))
+    return np.array(out[:], dtype=np.int64).reshape(len(cells), 2)
+
+
+def _box_dict(b: PoseBox) -> dict:
+    return {"model": b.model, "R0": np.array(b.R0[:], np.float64).reshape(3, 3), "t0": np.array(b.t0[:], np.float64),
+            "pivot": np.array(b.pivot[:], np.float64), "lo": np.array(b.lo[:], np.float64),
+            "hi": np.array(b.hi[:], np.float64)}
+
+
+def render_refined(scene: Scene, intr, box, max_cells=64, criteria=REFINE_MATINV, opts=None, stream=None, out=None):
+    """Bounds over a pose box refined where MatrixInv fails (cells bisected level by
+    level, united): tensors (H, W, 3), the leaf cells (pose-box dicts, in the order they
+    were settled) and the leaves' accumulated stats."""
+    import torch
+    lib = load()
+    ci = intrinsics(intr)
+    H, W = ci.height, ci.width
+    if out is None:
+        lo = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+        hi = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    else:
+        lo, hi = out
+    cells = (PoseBox * int(max_cells))()
+    n = ctypes.c_int32(0)
+    st = Stats()
+    cb = pose_box(box)
+    co = options(opts)
+    _check(lib.ar_render_refined(scene.handle, ctypes.byref(ci), ctypes.byref(cb), ctypes.byref(co), int(max_cells),
+                                 int(criteria), ctypes.c_void_p(lo.data_ptr()), ctypes.c_void_p(hi.data_ptr()),
+                                 _stream_ptr(stream), cells, ctypes.byref(n), ctypes.byref(st)))
+    return lo, hi, [_box_dict(cells[i]) for i in range(n.value)], st.as_dict()
 
 
 def options_dict(o: Options) -> dict:

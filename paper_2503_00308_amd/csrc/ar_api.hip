@@ -181,6 +181,8 @@ constexpr double kMaskBytes = 8.0 * 1024 * 1024 * 1024;   // largest store of In
 constexpr double kCompactWindow = 32.0;              // mean Ind window from which the tests read the compact copy
 constexpr double kAbsoluteRuns = 8.0;                // runs per list position from which the sums are made absolute
 constexpr int kRotSegment = 64;                      // list positions per segment (rotation path)
+constexpr int kClassifyCells = 1024;                 // pose cells per launch of the classification
+constexpr int kMaxRefineDepth = 24;                  // bisections of a cell in the adaptive refinement
 
 // buffers of the general path: run counts for npairs list positions, pinned list ranges
 static int ensure_general(Workspace &ws, size_t npairs, size_t nlists) {
@@ -635,6 +637,88 @@ int check_outputs(const float *lo, const float *hi) {
   return AR_OK;
 }
 
+
+// Cells rendered as ar_render_batch in launches of up to 64 cells (or
+// options.cells_per_launch) and united into lo / hi: minimum of the lower images,
+// maximum of the upper ones.  stats (may be NULL) accumulates over the cells.
+int render_union(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *cells, size_t ncells,
+                 const ar_options *opts, float *lo_rgb, float *hi_rgb, hipStream_t s, ar_stats *stats) {
+  const int per = opts && opts->cells_per_launch > 0 ? opts->cells_per_launch : 64;
+  const size_t img = (size_t)intr->width * intr->height * 3;
+  const int m_max = (int)std::min<size_t>(ncells, (size_t)per);
+  Workspace &ws = const_cast<ar_scene *>(scene)->ws;
+  if (2 * (size_t)m_max * img > ws.cap_union || !ws.union_img) {
+    HIP_TRY(grow(ws, ws.union_img, 2 * (size_t)m_max * img));
+    ws.cap_union = 2 * (size_t)m_max * img;
+  }
+  float *tlo = ws.union_img, *thi = ws.union_img + (size_t)m_max * img;
+  ar_stats total{};
+  for (size_t c0 = 0; c0 < ncells; c0 += (size_t)m_max) {
+    const int m = (int)std::min<size_t>((size_t)m_max, ncells - c0);
+    ar_stats st{};
+    int rc = ar_render_batch(scene, intr, cells + c0, m, opts, tlo, thi, s, &st);
+    if (rc) return rc;
+    add_stats(total, st);
+    hipLaunchKernelGGL(k_union, dim3((unsigned)((img + 255) / 256)), dim3(256), 0, s, tlo, thi, m, img, c0 == 0,
+                       lo_rgb, hi_rgb);
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (stats) *stats = total;
+  return AR_OK;
+}
+
+__global__ void k_zero_u64_n(unsigned long long *p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// Device memory released when the holder goes out of scope.
+struct DeviceBuffer {
+  void *p = nullptr;
+  ~DeviceBuffer() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+// Per cell: MatrixInv failures that the pruning test keeps somewhere in the image, and
+// near-plane straddlers (counts[2c], counts[2c + 1]).  Runs of consecutive cells with
+// the same pose variables share a launch of up to kClassifyCells cells.
+int classify_cells(const ar_scene *sc, const Params &prm, const ar_pose_box *cells, int ncells, int64_t *counts,
+                   hipStream_t s) {
+  const int cap = std::min(ncells, kClassifyCells);
+  std::vector<PoseForms> pf((size_t)cap);
+  std::vector<unsigned long long> host((size_t)2 * cap);
+  DeviceBuffer dpose, dcount;
+  HIP_TRY(hipMalloc(&dpose.p, (size_t)cap * sizeof(PoseForms)));
+  HIP_TRY(hipMalloc(&dcount.p, (size_t)2 * cap * sizeof(unsigned long long)));
+  PoseForms *pd = static_cast<PoseForms *>(dpose.p);
+  unsigned long long *cd = static_cast<unsigned long long *>(dcount.p);
+  int i = 0;
+  while (i < ncells) {
+    bool rot = false;
+    const int P = pose_vars(&cells[i], &rot);
+    int j = i + 1;
+    while (j < ncells && j - i < cap) {
+      bool r2 = false;
+      if (pose_vars(&cells[j], &r2) != P) break;
+      ++j;
+    }
+    const int m = j - i;
+    for (int c = 0; c < m; ++c)
+      if (pose_forms_host(cells[i + c], P, pf[c])) return fail(AR_E_INVALID, "unsupported pose variables %d", P);
+    HIP_TRY(hipMemcpyAsync(pd, pf.data(), (size_t)m * sizeof(PoseForms), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_zero_u64_n, dim3((unsigned)((2 * m + 255) / 256)), dim3(256), 0, s, cd, (size_t)2 * m);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(launch_classify(P, sc->dev, pd, m, prm, cd, s));
+    HIP_TRY(hipMemcpyAsync(host.data(), cd, (size_t)2 * m * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int c = 0; c < 2 * m; ++c) counts[2 * (size_t)i + c] = (int64_t)host[c];
+    i = j;
+  }
+  return AR_OK;
+}
+
 }  // namespace ar
 
 extern "C" {
@@ -807,28 +891,82 @@ int ar_render_partitioned(const ar_scene *scene, const ar_intrinsics *intr, cons
       cells[c].hi[a] = k + 1 == s[a] ? box->hi[a] : lo + w * (k + 1) / s[a];
     }
   }
-  const int per = opts && opts->cells_per_launch > 0 ? opts->cells_per_launch : 64;
-  const size_t img = (size_t)intr->width * intr->height * 3;
-  const int m_max = (int)std::min<size_t>(ncells, (size_t)per);
-  ar::Workspace &ws = const_cast<ar_scene *>(scene)->ws;
-  if (2 * (size_t)m_max * img > ws.cap_union || !ws.union_img) {
-    HIP_TRY(ar::grow(ws, ws.union_img, 2 * (size_t)m_max * img));
-    ws.cap_union = 2 * (size_t)m_max * img;
-  }
-  float *tlo = ws.union_img, *thi = ws.union_img + (size_t)m_max * img;
-  ar_stats total{};
-  for (size_t c0 = 0; c0 < ncells; c0 += (size_t)m_max) {
-    const int m = (int)std::min<size_t>((size_t)m_max, ncells - c0);
-    ar_stats st{};
-    rc = ar_render_batch(scene, intr, cells.data() + c0, m, opts, tlo, thi, hip_stream, &st);
+  return ar::render_union(scene, intr, cells.data(), ncells, opts, lo_rgb, hi_rgb, (hipStream_t)hip_stream, stats);
+}
+
+int ar_classify_cells(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *cells, int32_t ncells,
+                      const ar_options *opts, int64_t *counts, void *hip_stream) {
+  if (!scene) return fail(AR_E_INVALID, "scene is NULL");
+  if (!cells || ncells < 1) return fail(AR_E_INVALID, "classification needs at least one cell");
+  if (!counts) return fail(AR_E_INVALID, "counts is NULL");
+  for (int i = 0; i < ncells; ++i) {
+    int rc = ar::validate_box(&cells[i]);
     if (rc) return rc;
-    ar::add_stats(total, st);
-    hipLaunchKernelGGL(ar::k_union, dim3((unsigned)((img + 255) / 256)), dim3(256), 0, (hipStream_t)hip_stream, tlo,
-                       thi, m, img, c0 == 0, lo_rgb, hi_rgb);
-    HIP_TRY(hipGetLastError());
   }
-  HIP_TRY(hipStreamSynchronize((hipStream_t)hip_stream));
-  if (stats) *stats = total;
+  ar::Params prm{};
+  int rc = ar::make_params(scene, intr, opts, prm);
+  if (rc) return rc;
+  return ar::classify_cells(scene, prm, cells, ncells, counts, (hipStream_t)hip_stream);
+}
+
+int ar_render_refined(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *box,
+                      const ar_options *opts, int32_t max_cells, int32_t criteria, float *lo_rgb, float *hi_rgb,
+                      void *hip_stream, ar_pose_box *cells_out, int32_t *ncells_out, ar_stats *stats) {
+  if (!scene) return fail(AR_E_INVALID, "scene is NULL");
+  int rc = ar::validate_box(box);
+  if (rc) return rc;
+  if (max_cells < 1 || max_cells > 65536) return fail(AR_E_INVALID, "max_cells %d outside [1, 65536]", max_cells);
+  if (criteria == 0) criteria = AR_REFINE_MATINV;
+  if (criteria & ~(AR_REFINE_MATINV | AR_REFINE_NEAR)) return fail(AR_E_INVALID, "unknown refinement criteria %d", criteria);
+  ar::Params prm{};
+  rc = ar::make_params(scene, intr, opts, prm);
+  if (rc) return rc;
+  rc = ar::check_outputs(lo_rgb, hi_rgb);
+  if (rc) return rc;
+  const hipStream_t s = (hipStream_t)hip_stream;
+  // active axes of the box, in order (ORBIT: its angle)
+  int axes[6], naxes = 0;
+  const int na = box->model == AR_POSE_ORBIT ? 1 : 6;
+  for (int a = 0; a < na; ++a)
+    if (box->hi[a] > box->lo[a]) axes[naxes++] = a;
+  // level by level: classify the level's cells, cut the flagged ones in order while the
+  // number of cells stays within max_cells (lower half first), settle the others
+  std::vector<ar_pose_box> level(1, *box), next, leaves;
+  std::vector<int> depth(1, 0), next_depth;
+  std::vector<int64_t> counts;
+  size_t total = 1;
+  while (!level.empty()) {
+    counts.assign(2 * level.size(), 0);
+    rc = ar::classify_cells(scene, prm, level.data(), (int)level.size(), counts.data(), s);
+    if (rc) return rc;
+    next.clear();
+    next_depth.clear();
+    for (size_t i = 0; i < level.size(); ++i) {
+      const bool flagged = ((criteria & AR_REFINE_MATINV) && counts[2 * i] > 0) ||
+                           ((criteria & AR_REFINE_NEAR) && counts[2 * i + 1] > 0);
+      if (flagged && naxes > 0 && depth[i] < ar::kMaxRefineDepth && total + 1 <= (size_t)max_cells) {
+        const int a = axes[depth[i] % naxes];
+        const double lo = level[i].lo[a], hi = level[i].hi[a], m = 0.5 * (lo + hi);
+        if (lo < m && m < hi) {
+          ++total;
+          next.push_back(level[i]);
+          next.back().hi[a] = m;
+          next.push_back(level[i]);
+          next.back().lo[a] = m;
+          next_depth.push_back(depth[i] + 1);
+          next_depth.push_back(depth[i] + 1);
+          continue;
+        }
+      }
+      leaves.push_back(level[i]);
+    }
+    level.swap(next);
+    depth.swap(next_depth);
+  }
+  rc = ar::render_union(scene, intr, leaves.data(), leaves.size(), opts, lo_rgb, hi_rgb, s, stats);
+  if (rc) return rc;
+  if (cells_out) std::copy(leaves.begin(), leaves.end(), cells_out);
+  if (ncells_out) *ncells_out = (int32_t)leaves.size();
   return AR_OK;
 }
 

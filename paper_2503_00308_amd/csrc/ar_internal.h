@@ -60,6 +60,15 @@ inline int rec_stride(int P) {
   return ((16 + 18 * (P + 1) + 24) + 7) / 8 * 8;
 }
 
+// Squared distance from the mean box to the rectangle [ux0, ux1] x [uy0, uy1] (float32,
+// no contraction): the per-pixel pruning test evaluated at the nearest point.
+__device__ __forceinline__ float dist2_rect(const float *mu, float ux0, float ux1, float uy0, float uy1) {
+#pragma clang fp contract(off)
+  const float dx = fmaxf(fmaxf(mu[0] - ux1, 0.0f), ux0 - mu[1]);
+  const float dy = fmaxf(fmaxf(mu[2] - uy1, 0.0f), uy0 - mu[3]);
+  return dx * dx + dy * dy;
+}
+
 template <int P>
 __device__ __forceinline__ const float *rec_prune(const double *rec) {
   return reinterpret_cast<const float *>(rec + Rec<P>::PRUNE);
@@ -173,6 +182,11 @@ int pose_forms_host(const ar_pose_box &box, int P, PoseForms &out);
 hipError_t launch_project(int P, const SceneDev &sc, const PoseForms &pose, const PoseForms *poses_dev, int ncells,
                           const Params &prm,
                           Workspace &ws, hipStream_t s);
+// types only for ncells boxes (poses_dev[ncells]); counts[2 * ncells] (zeroed by the
+// caller) receive per cell the MatrixInv failures kept somewhere in the image and the
+// near-plane straddlers
+hipError_t launch_classify(int P, const SceneDev &sc, const PoseForms *poses_dev, int ncells, const Params &prm,
+                           unsigned long long *counts, hipStream_t s);
 // ---- sorting / scans (ar_sort.hip) ----
 hipError_t radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt, int n,
                           int begin_bit, int end_bit, Workspace &ws, hipStream_t s, bool *result_in_alt);

@@ -234,7 +234,10 @@ __device__ bool matrix_inv(const L64<P> &x00, const L64<P> &x01, const L64<P> &x
 
 // Per-Gaussian stage of Gaussian g of the scene under pose forms `pose`; outputs at
 // global index oi (cell * n + g when several cells are processed by one launch).
-template <int P>
+// CLASSIFY: only the Gaussian's type is decided, and counters points at its cell's two
+// counts (MatrixInv failures the pruning test keeps somewhere in the image, near-plane
+// straddlers); nothing else is written.
+template <int P, bool CLASSIFY = false>
 __device__ __forceinline__ void project_one(const SceneDev &sc, const PoseForms &pose, const Params &prm, int g,
                                             size_t oi, double *__restrict__ rec_out, uint64_t *__restrict__ key_out,
                                             uint64_t *__restrict__ key_sort, uint32_t *__restrict__ perm_out,
@@ -246,7 +249,7 @@ __device__ __forceinline__ void project_one(const SceneDev &sc, const PoseForms 
 #pragma unroll
   for (int i = 0; i < 9; ++i) Mw[i] = sc.cov[(size_t)i * n + g];
   const float o = sc.opac[g];
-  perm_out[oi] = (uint32_t)oi;
+  if constexpr (!CLASSIFY) perm_out[oi] = (uint32_t)oi;
 
   // Step 1: uc = Mmul(A, Add(uw, -tau)) + beta
   L64<P> y[3];
@@ -326,6 +329,18 @@ __device__ __forceinline__ void project_one(const SceneDev &sc, const PoseForms 
   L64<P> conic[4];
   if (normal) {
     if (!matrix_inv<P>(X00, X01, X11, prm.taylor_k, conic)) type = kFallback;
+  }
+  if constexpr (CLASSIFY) {
+    if (type == kFallback) {
+      // kept at some pixel: the binning's float32 test on the rectangle of all pixel centres
+      const float mu[4] = {__double2float_rd(m0lo), __double2float_ru(m0hi), __double2float_rd(m1lo),
+                           __double2float_ru(m1hi)};
+      const float ux0 = (float)(0.5 - prm.cx), ux1 = (float)((double)(prm.width - 1) + 0.5 - prm.cx);
+      const float uy0 = (float)(0.5 - prm.cy), uy1 = (float)((double)(prm.height - 1) + 0.5 - prm.cy);
+      if (dist2_rect(mu, ux0, ux1, uy0, uy1) <= __double2float_ru(r2)) atomicAdd(&counters[0], 1ull);
+    }
+    if (type == kWild) atomicAdd(&counters[1], 1ull);
+    return;
   }
   if (type == kFallback) atomicAdd(&counters[2], 1ull);
   if (type == kWild) atomicAdd(&counters[3], 1ull);
@@ -447,6 +462,19 @@ __global__ __launch_bounds__(64) void k_project_cells(SceneDev sc, const PoseFor
                  dform_out, dint_out, counters);
 }
 
+// Types only, for several pose cells (grid.y): counts[2c] = MatrixInv failures of cell c
+// that the pruning test keeps somewhere in the image, counts[2c + 1] = its near-plane
+// straddlers (the criteria of the adaptive refinement of a pose box).
+template <int P>
+__global__ __launch_bounds__(64) void k_classify_cells(SceneDev sc, const PoseForms *__restrict__ poses, Params prm,
+                                                       unsigned long long *__restrict__ counts) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= sc.n) return;
+  const int c = blockIdx.y;
+  project_one<P, true>(sc, poses[c], prm, g, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                       counts + 2 * (size_t)c);
+}
+
 // Pose forms on the host: O(1) work, passed to the kernels by value.
 int pose_forms_host(const ar_pose_box &box, int P, PoseForms &out) {
   switch (P) {
@@ -486,6 +514,22 @@ hipError_t launch_project(int P, const SceneDev &sc, const PoseForms &pose, cons
     case 6: return launch_project_p<6>(sc, pose, poses_dev, ncells, prm, ws, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_classify(int P, const SceneDev &sc, const PoseForms *poses_dev, int ncells, const Params &prm,
+                           unsigned long long *counts, hipStream_t s) {
+  const dim3 grid((unsigned)((sc.n + 63) / 64), (unsigned)ncells);
+  switch (P) {
+    case 0: hipLaunchKernelGGL(k_classify_cells<0>, grid, dim3(64), 0, s, sc, poses_dev, prm, counts); break;
+    case 1: hipLaunchKernelGGL(k_classify_cells<1>, grid, dim3(64), 0, s, sc, poses_dev, prm, counts); break;
+    case 2: hipLaunchKernelGGL(k_classify_cells<2>, grid, dim3(64), 0, s, sc, poses_dev, prm, counts); break;
+    case 3: hipLaunchKernelGGL(k_classify_cells<3>, grid, dim3(64), 0, s, sc, poses_dev, prm, counts); break;
+    case 4: hipLaunchKernelGGL(k_classify_cells<4>, grid, dim3(64), 0, s, sc, poses_dev, prm, counts); break;
+    case 5: hipLaunchKernelGGL(k_classify_cells<5>, grid, dim3(64), 0, s, sc, poses_dev, prm, counts); break;
+    case 6: hipLaunchKernelGGL(k_classify_cells<6>, grid, dim3(64), 0, s, sc, poses_dev, prm, counts); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace ar

@@ -38,15 +38,6 @@ namespace ar {
 // ---------------------------------------------------------------------------------
 // binning
 // ---------------------------------------------------------------------------------
-// squared distance from the mean box to the rectangle [ux0, ux1] x [uy0, uy1] (float32,
-// no contraction): the per-pixel test of dist2_box evaluated at the nearest point
-__device__ __forceinline__ float dist2_rect(const float *mu, float ux0, float ux1, float uy0, float uy1) {
-#pragma clang fp contract(off)
-  const float dx = fmaxf(fmaxf(mu[0] - ux1, 0.0f), ux0 - mu[1]);
-  const float dy = fmaxf(fmaxf(mu[2] - uy1, 0.0f), uy0 - mu[3]);
-  return dx * dx + dy * dy;
-}
-
 __device__ __forceinline__ float tile_dist2(const float *mu, int tx, int ty, const Params &prm) {
   const int x0 = tx * kTile, y0 = ty * kTile;
   const int x1 = min(x0 + kTile, prm.width) - 1, y1 = min(y0 + kTile, prm.height) - 1;
