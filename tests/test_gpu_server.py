@@ -112,6 +112,34 @@ def test_server_parity_with_oracle():
     h.close()
 
 
+def test_server_heaviest_query_full_size_sampled_tiles():
+    """The heaviest query of the serving workload at full size (750k Gaussians on 20
+    boxes, 400x400, all six pose axes) through the server; two 8x8 tiles against the
+    oracle's values stored by tests/golden/make_served_heavy_tiles.py, every pixel
+    finite and ordered."""
+    import os
+    api = _api()
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "served_heavy_tiles.npz"))
+    s, side, box = synth.served_queries(48, 0)[int(gold["query"])]
+    scene = synth.served_scenes(0)[s]
+    h = api.Scene(scene)
+    srv = api.Server(slots=1)
+    sid = srv.add_scene(h)
+    lo, hi, res = srv.wait(srv.submit(sid, synth.intrinsics(side), box))
+    srv.close()
+    h.close()
+    print("heaviest query", res["latency_ms"], "ms", res["stats"], flush=True)
+    glo, ghi = lo.cpu().numpy(), hi.cpu().numpy()
+    assert np.all(np.isfinite(glo)) and np.all(np.isfinite(ghi)) and np.all(glo <= ghi)
+    for k, (tx, ty) in enumerate(gold["tiles"]):
+        sl = (slice(ty * 8, (ty + 1) * 8), slice(tx * 8, (tx + 1) * 8))
+        ok = ~gold[f"border{k}"][..., None]
+        dlo = np.abs(glo[sl] - gold[f"lo{k}"])[np.broadcast_to(ok, glo[sl].shape)].max()
+        dhi = np.abs(ghi[sl] - gold[f"hi{k}"])[np.broadcast_to(ok, ghi[sl].shape)].max()
+        print(f"[heaviest query tile {tx},{ty}] max|dlo| {dlo:.3e} max|dhi| {dhi:.3e}", flush=True)
+        assert dlo <= 1e-5 and dhi <= 1e-5
+
+
 def test_server_rejects_bad_requests():
     api = _api()
     h = api.Scene(synth.random_scene(50, seed=25))
