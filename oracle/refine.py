@@ -6,8 +6,8 @@ renders subsets of the camera set and unites their bounds.  Here the divided ran
 the pose box:
 
 * a cell is flagged when it holds a Gaussian whose MatrixInv assertion fails and that
-  the pruning test keeps at some pixel of the image (with `near`, also one that
-  straddles the near plane, which gets alpha in [0, o] everywhere);
+  the pruning test keeps at some pixel of the image (criterion `matinv`), or one that
+  straddles the near plane, which gets alpha in [0, o] everywhere (criterion `near`);
 * cells are taken level by level, in order; a flagged cell of depth k (k bisections
   from the whole box) is cut in two at the midpoint 0.5 (lo + hi) of its active axis
   number k mod (number of active axes), as long as the number of cells stays within
@@ -55,8 +55,9 @@ def _half(box, a, upper):
     return out
 
 
-def refine(scene, intr, box, max_cells, near=False, opts=None):
-    """Leaves of the refinement, in the order they are settled."""
+def refine(scene, intr, box, max_cells, near=False, opts=None, matinv=True):
+    """Leaves of the refinement, in the order they are settled (criteria: MatrixInv
+    failures kept in the image when matinv, near-plane straddlers when near)."""
     axes = active_axes(box)
     level = [(box, 0)]
     leaves = []
@@ -65,7 +66,7 @@ def refine(scene, intr, box, max_cells, near=False, opts=None):
         nxt = []
         for cell, depth in level:
             fb, wild = flagged_counts(scene, intr, cell, opts)
-            flagged = fb > 0 or (near and wild > 0)
+            flagged = (matinv and fb > 0) or (near and wild > 0)
             if flagged and axes and depth < MAX_DEPTH and total + 1 <= max_cells:
                 a = axes[depth % len(axes)]
                 lo, hi = float(cell["lo"][a]), float(cell["hi"][a])
@@ -80,9 +81,9 @@ def refine(scene, intr, box, max_cells, near=False, opts=None):
     return leaves
 
 
-def refined_bounds(scene, intr, box, max_cells, near=False, opts=None):
+def refined_bounds(scene, intr, box, max_cells, near=False, opts=None, matinv=True):
     """United lower / upper images of the leaves (H, W, 3), and the leaves."""
-    leaves = refine(scene, intr, box, max_cells, near, opts)
+    leaves = refine(scene, intr, box, max_cells, near, opts, matinv)
     lo = hi = None
     for cell in leaves:
         r = splat.oracle_bounds(scene, intr, cell, opts)

@@ -637,7 +637,6 @@ int check_outputs(const float *lo, const float *hi) {
   return AR_OK;
 }
 
-
 // Cells rendered as ar_render_batch in launches of up to 64 cells (or
 // options.cells_per_launch) and united into lo / hi: minimum of the lower images,
 // maximum of the upper ones.  stats (may be NULL) accumulates over the cells.

@@ -1,7 +1,9 @@
-"""Writes served_heavy_tiles.npz: the oracle's bounds on two 8x8 tiles of the heaviest
-query of the serving workload (query 0 of the seeded stream: 750k Gaussians on 20 boxes,
-400x400, all six pose axes), the largest scene and box the serving tests run.  Calls
-only the oracle and the seeded generators.
+"""Writes served_heavy_tiles.npz: the oracle's bounds on 8x8 tiles of the heaviest query
+of the serving workload (query 0 of the seeded stream: 750k Gaussians on 20 boxes,
+400x400, all six pose axes), the largest scene and box the serving tests run: two dense
+tiles (19k and 4.7k candidate Gaussians; bounds [0, 1]; about eight minutes for the FP64
+oracle) and four sparse ones whose upper bounds fall below 1.  Calls only the oracle and
+the seeded generators.
 
     python tests/golden/make_served_heavy_tiles.py
 """
@@ -18,7 +20,7 @@ from oracle import splat                       # noqa: E402
 from paper_2503_00308_amd import synth         # noqa: E402
 
 QUERY = 0
-TILES = [(25, 25), (10, 40)]
+TILES = [(25, 25), (10, 40), (42, 33), (12, 9), (6, 21), (6, 12)]   # two dense, four with bounds below 1
 
 
 def main():

@@ -1,6 +1,7 @@
-"""Writes workload3_tiles.npz: the oracle's bounds on two 8x8 tiles of the full-size
+"""Writes workload3_tiles.npz: the oracle's bounds on 8x8 tiles of the full-size
 workload 3 (100k Gaussians on 20 boxes, 400x400, translation +-0.05 and yaw/pitch/roll
-+-1 deg), which take the FP64 oracle about a minute per tile.  Calls only the oracle and
++-1 deg): two dense tiles (about a minute each for the FP64 oracle; their bounds are
+[0, 1]) and three sparse ones whose upper bounds fall below 1.  Calls only the oracle and
 the seeded scene generator.
 
     python tests/golden/make_workload3_tiles.py
@@ -16,7 +17,7 @@ sys.path.insert(0, ROOT)
 from oracle import splat                       # noqa: E402
 from paper_2503_00308_amd import synth         # noqa: E402
 
-TILES = [(25, 25), (10, 30)]
+TILES = [(25, 25), (10, 30), (9, 3), (6, 6), (42, 9)]   # two dense tiles, three with bounds below 1
 
 
 def main():

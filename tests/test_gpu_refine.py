@@ -34,10 +34,23 @@ def orbit_box(deg):
             "lo": np.array([-a, 0, 0, 0, 0, 0], np.float64), "hi": np.array([a, 0, 0, 0, 0, 0], np.float64)}
 
 
+def near_scene():
+    """40 random Gaussians at depth 3-5 and one whose mean sits at depth 0.02."""
+    s = synth.random_scene(40, seed=5)
+    t = synth.random_scene(1, seed=6)
+    t["mean"][0] = (0.05, -0.03, 0.02)
+    return {k: np.concatenate([s[k], t[k]]) for k in s}
+
+
+MATINV, NEAR = 1, 2
+NEAR_SCENE = near_scene()
+# name: (scene, box, max_cells, criteria)
 CASES = {
-    "orbit3": (orbit_box(3.0), 16),
-    "orbit3_budget4": (orbit_box(3.0), 4),
-    "camera4": (synth.camera6_box(dt=(0.05, 0.0, 0.05), drot=(np.deg2rad(2), np.deg2rad(2), 0.0)), 16),
+    "orbit3": (SCENE, orbit_box(3.0), 16, MATINV),
+    "orbit3_budget4": (SCENE, orbit_box(3.0), 4, MATINV),
+    "camera4": (SCENE, synth.camera6_box(dt=(0.05, 0.0, 0.05), drot=(np.deg2rad(2), np.deg2rad(2), 0.0)), 16, MATINV),
+    "near_only": (NEAR_SCENE, synth.camera6_box(dt=(0.0, 0.0, 0.04)), 6, NEAR),
+    "near_and_matinv": (NEAR_SCENE, synth.camera6_box(dt=(0.0, 0.0, 0.04)), 6, MATINV | NEAR),
 }
 
 
@@ -45,10 +58,10 @@ CASES = {
 def test_counts_and_leaves_equal_the_oracle(name):
     from oracle import refine
     api = _api()
-    box, max_cells = CASES[name]
-    sc = api.Scene(SCENE)
-    lo, hi, leaves, st = api.render_refined(sc, INTR, box, max_cells, opts={"chunk": 32})
-    ref = refine.refine(SCENE, INTR, box, max_cells)
+    scene, box, max_cells, crit = CASES[name]
+    sc = api.Scene(scene)
+    lo, hi, leaves, st = api.render_refined(sc, INTR, box, max_cells, criteria=crit, opts={"chunk": 32})
+    ref = refine.refine(scene, INTR, box, max_cells, near=bool(crit & NEAR), matinv=bool(crit & MATINV))
     print(f"[refine {name}] {len(leaves)} leaves (oracle {len(ref)}), stats {st}", flush=True)
     assert len(leaves) == len(ref)
     for a, b in zip(leaves, ref):
@@ -57,8 +70,8 @@ def test_counts_and_leaves_equal_the_oracle(name):
         assert np.array_equal(a["hi"], np.asarray(b["hi"], np.float64))
     counts = api.classify_cells(sc, INTR, [box] + leaves)
     sc.close()
-    want = np.array([refine.flagged_counts(SCENE, INTR, c) for c in [box] + ref], np.int64)
-    print(f"[refine {name}] counts {counts[:, 0].tolist()}", flush=True)
+    want = np.array([refine.flagged_counts(scene, INTR, c) for c in [box] + ref], np.int64)
+    print(f"[refine {name}] counts {counts.tolist()}", flush=True)
     assert np.array_equal(counts, want)
 
 
@@ -66,7 +79,8 @@ def test_counts_and_leaves_equal_the_oracle(name):
 def test_refined_bounds_union_parity_and_soundness(name):
     from oracle import pose, refine, render
     api = _api()
-    box, max_cells = CASES[name]
+    scene, box, max_cells, _ = CASES[name]
+    assert scene is SCENE
     sc = api.Scene(SCENE)
     opts = {"chunk": 32}
     rlo, rhi, leaves, _ = api.render_refined(sc, INTR, box, max_cells, opts=opts)

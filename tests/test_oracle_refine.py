@@ -108,3 +108,33 @@ def test_refined_bounds_enclose_concrete_renders_and_tighten():
         worst = max(worst, (lo - img).max(), (img - hi).max())
     assert worst <= 1e-9
     assert (hi - lo).mean() <= (whole["hi"] - whole["lo"]).mean()
+
+
+def near_scene():
+    """40 random Gaussians at depth 3-5 and one whose mean sits at depth 0.02."""
+    s = synth.random_scene(40, seed=5)
+    t = synth.random_scene(1, seed=6)
+    t["mean"][0] = (0.05, -0.03, 0.02)
+    return {k: np.concatenate([s[k], t[k]]) for k in s}
+
+
+def test_near_plane_criterion_isolates_the_crossing():
+    """With the camera moving along z by tz in [-0.04, 0.04], the near Gaussian's depth is
+    m - tz (m its stored depth, float32 0.02): over a cell [lo, hi] of tz it straddles
+    z_near = 0.01 exactly when lo < m - 0.01 <= hi.  Refining on the near-plane criterion
+    alone bisects toward that point, so exactly one leaf holds it; the MatrixInv
+    criterion alone leaves the box whole."""
+    scene = near_scene()
+    box = synth.camera6_box(dt=(0.0, 0.0, 0.04))
+    assert refine.flagged_counts(scene, INTR, box) == (0, 1)
+    assert len(refine.refine(scene, INTR, box, 6)) == 1
+    leaves = refine.refine(scene, INTR, box, 6, near=True, matinv=False)
+    assert len(leaves) == 6
+    t_cross = float(np.float32(0.02)) - 0.01
+    hits = 0
+    for c in leaves:
+        lo, hi = float(c["lo"][2]), float(c["hi"][2])
+        straddles = refine.flagged_counts(scene, INTR, c)[1] == 1
+        assert straddles == (lo < t_cross <= hi), (lo, hi)
+        hits += straddles
+    assert hits == 1
