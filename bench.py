@@ -331,7 +331,7 @@ def main():
                     help="only run a plain copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is designed but not built",
+        print(json.dumps({"error": "one GPU only: sharding over several GPUs is designed but not built",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

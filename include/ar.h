@@ -46,7 +46,7 @@ enum {
   AR_E_INVALID = -1,     /* an argument is out of range, non-finite or inconsistent */
   AR_E_OOM = -2,         /* device memory could not be allocated */
   AR_E_DEVICE = -3,      /* a HIP runtime call failed */
-  AR_E_UNSUPPORTED = -4, /* a valid request this build does not handle */
+  AR_E_UNSUPPORTED = -4, /* a valid request the library does not handle */
   AR_E_BUDGET = -5,      /* a server request does not fit the memory budget */
   AR_PENDING = 1         /* ar_server_wait without blocking: the query has not finished */
 };
