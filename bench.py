@@ -81,6 +81,28 @@ def calibrate_copy(mib: int):
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 5}), flush=True)
 
 
+def served_query(index: int, seed: int = 0):
+    """Query `index` of the seeded serving stream rendered alone (one warm-up, one timed
+    call): one JSON line with its time and statistics, for profiling that query's kernels."""
+    import torch
+    from paper_2503_00308_amd import api, synth
+    torch.cuda.set_device(0)
+    api.load()
+    s, side, box = synth.served_queries(48, seed)[index]
+    scene = synth.served_scenes(seed)[s]
+    h = api.Scene(scene)
+    intr = synth.intrinsics(side)
+    api.render_bounds(h, intr, box)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, st = api.render_bounds(h, intr, box)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    h.close()
+    print(json.dumps({"served_query": index, "gaussians": int(len(scene["opacity"])), "side": side,
+                      "pose_vars": st["P"], "ms": ms, "stats": st}), flush=True)
+
+
 def alg_flops_per_pair(P: int) -> int:
     """Algorithmic floating-point work of one (pixel, Gaussian) pair, counted on the
     operations of the method (FMA = 2 flops), F = P + 1 form coefficients:
@@ -327,6 +349,8 @@ def main():
                          "so it is left out of the default run that the kernel trace covers)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_raster_seg_cfg2_traffic.txt"))
+    ap.add_argument("--served-query", type=int, default=None, metavar="K",
+                    help="only render query K of the seeded serving stream alone (twice) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -337,6 +361,9 @@ def main():
 
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
+        return
+    if args.served_query is not None:
+        served_query(args.served_query)
         return
 
     import numpy as np
