@@ -118,7 +118,7 @@ typedef struct {
  *               cull_budget / n at every pose; lower / upper bounds are widened by E
  *   z_near      near plane (default 0.01): depth <= z_near gives alpha 0
  *   prefix_entries  rotation boxes: tile-list entries whose per-pixel prefix sums one
- *               pixel-loop launch holds (64 x 20 bytes each; default 2^21; a longer
+ *               pixel-loop launch holds (64 x 16 bytes each; default 2^21; a longer
  *               single list gets its own launch)
  *   cells_per_launch  ar_render_batch: pose cells per launch (default: as many as fit a
  *               workspace of about 4 GiB, at most 256)

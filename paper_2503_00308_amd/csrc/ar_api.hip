@@ -175,7 +175,7 @@ static int ensure_ws(Workspace &ws, size_t n_total, size_t nlists, int P, int nc
 
 // Rotation path: list entries whose per-pixel prefix sums are held at once (the pixel
 // loop runs over chunks of tile lists with at most this many entries, or one list).
-constexpr size_t kPrefixEntries = (size_t)1 << 21;   // 2M entries, 2.7 GB
+constexpr size_t kPrefixEntries = (size_t)1 << 21;   // 2M entries, 2.1 GB
 constexpr size_t kRotChunkSegs = (size_t)1 << 16;    // segments per launch of the rotation pixel loop
 constexpr double kMaskBytes = 8.0 * 1024 * 1024 * 1024;   // largest store of Ind masks kept between passes
 constexpr double kCompactWindow = 32.0;              // mean Ind window from which the tests read the compact copy
@@ -212,7 +212,6 @@ static int ensure_prefix(Workspace &ws, size_t entries) {
   if (entries <= ws.cap_pre && ws.pre) return AR_OK;
   const size_t need = entries + entries / 8 + 64;
   HIP_TRY(grow(ws, ws.pre, need * kTilePix * 2));
-  HIP_TRY(grow(ws, ws.prez, need * kTilePix));
   ws.cap_pre = need;
   return AR_OK;
 }
@@ -253,7 +252,6 @@ static int ensure_rot_parts(Workspace &ws, size_t nseg, int P) {
   if (nseg > ws.cap_segsum || !ws.segsum) {
     const size_t need = nseg + nseg / 4 + 256;
     HIP_TRY(grow(ws, ws.segsum, need * kTilePix * 2));
-    HIP_TRY(grow(ws, ws.segz, need * kTilePix));
     ws.cap_segsum = need;
   }
   const size_t doubles = nseg * (size_t)part_fields(P) * kTilePix;

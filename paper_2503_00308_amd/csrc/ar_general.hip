@@ -25,8 +25,8 @@
 //
 // The pixel loop works on segments of L list positions, one wave per segment, one lane
 // per pixel of the 8x8 tile:
-//   A (k_rot_prefix): per pixel, running sums of log(1 - a_lo) and log(1 - a_hi) (FP64)
-//      and the running count of a_hi = 1 over the segment, and the segment totals;
+//   A (k_rot_prefix): per pixel, running sums of log(1 - a_lo) and log(1 - a_hi) (FP64;
+//      a_hi = 1 enters as log 2^-60, see below), and the segment totals;
 //   k_rot_offsets: per list, the running totals in front of each segment, and
 //   k_rot_absolute: those totals added to the segments' running sums;
 //   B (k_rot_blend): for each Gaussian i, the product over a run [a, b) is
@@ -35,7 +35,10 @@
 //      absolute transmittances, so a tile's bounds are the sum over its segments
 //      (k_rot_merge).
 // Equal-length segments spread a long tile list over many waves.  The prefix sums
-// carry a rounding bound that is added outward before exp.
+// carry a rounding bound that is added outward before exp.  A factor 1 - a_hi = 0 (an
+// alpha that may reach 1) enters the upper sums as 2^-60 instead, so a lower
+// transmittance that should be 0 is at most 2^-60; the merge widens every lower bound
+// by n 2^-60 (n list entries), which keeps it sound without a count row per pixel.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -47,6 +50,7 @@ namespace ar {
 
 constexpr double kIndMargin = 1e-10;   // margin of the literal depth-difference test
 constexpr double kWinMargin = 1e-9;    // margin of the depth-interval window
+constexpr double kZeroFactor = 0x1p-60; // stands for a factor 1 - a_hi = 0 in the upper log sums
 
 // Per tile list (items cell * n + g): the box of the Gaussians' means uw [0, 6), the box
 // of their parts across the nominal depth direction m, v = uw - (m . uw / |m|^2) m,
@@ -628,8 +632,8 @@ __device__ __forceinline__ SegRef seg_ref(const uint32_t *__restrict__ ranges, c
   return r;
 }
 
-// A: per pixel, running sums of log(1 - a_lo) and log(1 - a_hi) and the count of
-// a_hi = 1 over the segment (from zero at its start), and the segment totals.
+// A: per pixel, running sums of log(1 - a_lo) and log(max(1 - a_hi, 2^-60)) over the
+// segment (from zero at its start), and the segment totals.
 template <int P>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rot_prefix(const double *__restrict__ recs,
                                                     const uint32_t *__restrict__ ranges,
@@ -637,9 +641,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                     const uint32_t *__restrict__ seg_off,
                                                     const uint32_t *__restrict__ seg_tile, int L, int seg0, int nseg,
                                                     uint32_t pos0, Params prm, double *__restrict__ preL,
-                                                    double *__restrict__ preH, uint32_t *__restrict__ prez,
-                                                    double2 *__restrict__ segsum,
-                                                    uint32_t *__restrict__ segz,
+                                                    double *__restrict__ preH, double2 *__restrict__ segsum,
                                                     unsigned long long *__restrict__ counters) {
   using R = Rec<P>;
   const int lane = threadIdx.x & 63;
@@ -657,7 +659,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const uint32_t *items = lists + r.beg;
   const size_t pb = (size_t)((uint32_t)r.beg - pos0);
   double Ll = 0.0, Lh = 0.0;
-  uint32_t Z = 0;
   Lookahead la;
   for (int j = r.i0; j < r.i1; ++j) {
     const int k = (j - r.i0) & 63;
@@ -669,35 +670,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       double alo, ahi;
       alpha_interval<P>(rec, type, uxd, uyd, alo, ahi, exp_table(gid));
       Ll += log(1.0 - alo);
-      if (ahi >= 1.0) ++Z;
-      else Lh += log(1.0 - ahi);
+      Lh += log(ahi >= 1.0 ? kZeroFactor : 1.0 - ahi);
     }
     preL[(pb + j) * 64 + lane] = Ll;
     preH[(pb + j) * 64 + lane] = Lh;
-    prez[(pb + j) * 64 + lane] = Z;
   }
   segsum[(size_t)w * 64 + lane] = make_double2(Ll, Lh);
-  segz[(size_t)w * 64 + lane] = Z;
   if (lane == 0) atomicAdd(&counters[6], (unsigned long long)(clock64() - c0));
 }
 
 // per list: exclusive running totals of its segments' sums (in place)
 __global__ __launch_bounds__(256) void k_rot_offsets(const uint32_t *__restrict__ seg_off, int list0, int nl, int seg0,
-                                                     double2 *__restrict__ segsum, uint32_t *__restrict__ segz) {
+                                                     double2 *__restrict__ segsum) {
   const int lane = threadIdx.x & 63;
   const int k = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   if (k >= nl) return;
   const int s0 = (int)seg_off[list0 + k] - seg0, s1 = (int)seg_off[list0 + k + 1] - seg0;
   double al = 0.0, ah = 0.0;
-  uint32_t az = 0;
   for (int s = s0; s < s1; ++s) {
     const double2 t = segsum[(size_t)s * 64 + lane];
-    const uint32_t tz = segz[(size_t)s * 64 + lane];
     segsum[(size_t)s * 64 + lane] = make_double2(al, ah);
-    segz[(size_t)s * 64 + lane] = az;
     al += t.x;
     ah += t.y;
-    az += tz;
   }
 }
 
@@ -708,21 +702,18 @@ __global__ __launch_bounds__(256) void k_rot_absolute(const uint32_t *__restrict
                                                       const uint32_t *__restrict__ seg_off,
                                                       const uint32_t *__restrict__ seg_tile, int L, int seg0,
                                                       int nseg, uint32_t pos0, const double2 *__restrict__ segoff,
-                                                      const uint32_t *__restrict__ segz, double *__restrict__ preL,
-                                                      double *__restrict__ preH, uint32_t *__restrict__ prez) {
+                                                      double *__restrict__ preL, double *__restrict__ preH) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   if (w >= nseg) return;
   const SegRef r = seg_ref(ranges, seg_off, seg_tile, seg0 + w, L);
   if (r.i0 == 0) return;   // the list's first segment: nothing in front
   const double2 o = segoff[(size_t)w * 64 + lane];
-  const uint32_t oz = segz[(size_t)w * 64 + lane];
   const size_t pb = (size_t)((uint32_t)r.beg - pos0);
   for (int j = r.i0; j < r.i1; ++j) {
     const size_t x = (pb + j) * 64 + lane;
     preL[x] += o.x;
     preH[x] += o.y;
-    prez[x] += oz;
   }
 }
 
@@ -738,9 +729,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                    uint32_t pos0, const uint32_t *__restrict__ cnt,
                                                    const uint32_t *__restrict__ runs, Params prm,
                                                    const double *__restrict__ preL, const double *__restrict__ preH,
-                                                   const uint32_t *__restrict__ prez,
-                                                   const double2 *__restrict__ segoff,
-                                                   const uint32_t *__restrict__ segz, double *__restrict__ part,
+                                                   const double2 *__restrict__ segoff, double *__restrict__ part,
                                                    unsigned long long *__restrict__ counters) {
   using R = Rec<P>;
   using Q = Part<P>;
@@ -788,9 +777,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const uint32_t d1 = (uint32_t)__builtin_amdgcn_readlane((int)cv1, k);
     const uint32_t m0 = d1, m1 = (uint32_t)__builtin_amdgcn_readlane((int)cv2, k);
     const double *sL = preL + lane, *sH = preH + lane;
-    const uint32_t *sZ = prez + lane;
     double sum_l = 0.0, err_l = 0.0, sum_h = 0.0, err_h = 0.0;
-    uint32_t zc = 0;
     if (ABS) {
       // many runs per entry: the runs are read 64 at a time (one per lane) and their ends
       // four runs at a time, so eight loads are in flight; the sums are taken in run
@@ -832,25 +819,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         if (lane < nq) abv = runs2[qb + lane];
         for (int u = 0; u < nq; u += kRunGroup) {
           double La[kRunGroup], Lb[kRunGroup];
-          uint32_t Za[kRunGroup], Zb[kRunGroup];
 #pragma unroll
           for (int t = 0; t < kRunGroup; ++t) {
             const int r = min(u + t, nq - 1);
             const uint32_t pa = (uint32_t)__builtin_amdgcn_readlane((int)abv.x, r);
             const uint32_t pe = (uint32_t)__builtin_amdgcn_readlane((int)abv.y, r);
             const double va = sH[ix(pa) * 64], ve = sH[ix(pe) * 64];
-            const uint32_t za = sZ[ix(pa) * 64], ze = sZ[ix(pe) * 64];
             La[t] = pa > 0 ? va : 0.0;
             Lb[t] = pe > 0 ? ve : 0.0;
-            Za[t] = pa > 0 ? za : 0u;
-            Zb[t] = pe > 0 ? ze : 0u;
           }
 #pragma unroll
           for (int t = 0; t < kRunGroup; ++t) {
             if (u + t < nq) {
               sum_h += Lb[t] - La[t];
               err_h += fabs(La[t]) + fabs(Lb[t]);
-              zc += Zb[t] - Za[t];
             }
           }
         }
@@ -869,25 +851,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       for (uint32_t q = m0; q < m1; ++q) {
         const uint2 ab = *reinterpret_cast<const uint2 *>(runs + 2 * (size_t)q);
         double La = 0.0, Lb = 0.0;
-        uint32_t Za = 0, Zb = 0;
-        if (ab.x > 0) {
-          const size_t so = (size_t)(sl + (int)(ab.x - 1) / L) * 64 + lane;
-          La = sH[(pb + ab.x - 1) * 64] + segoff[so].y;
-          Za = sZ[(pb + ab.x - 1) * 64] + segz[so];
-        }
-        if (ab.y > 0) {
-          const size_t so = (size_t)(sl + (int)(ab.y - 1) / L) * 64 + lane;
-          Lb = sH[(pb + ab.y - 1) * 64] + segoff[so].y;
-          Zb = sZ[(pb + ab.y - 1) * 64] + segz[so];
-        }
+        if (ab.x > 0) La = sH[(pb + ab.x - 1) * 64] + segoff[(size_t)(sl + (int)(ab.x - 1) / L) * 64 + lane].y;
+        if (ab.y > 0) Lb = sH[(pb + ab.y - 1) * 64] + segoff[(size_t)(sl + (int)(ab.y - 1) / L) * 64 + lane].y;
         sum_h += Lb - La;
         err_h += fabs(La) + fabs(Lb);
-        zc += Zb - Za;
       }
     }
     if (!kept) continue;
     const double thi = exp(sum_l + nn * 0x1p-51 * err_l) * (1.0 + 0x1p-50);
-    const double tlo = zc ? 0.0 : exp(sum_h - nn * 0x1p-51 * err_h) * (1.0 - 0x1p-50);
+    const double tlo = exp(sum_h - nn * 0x1p-51 * err_h) * (1.0 - 0x1p-50);
     double alo, ahi;
     pair_contrib<P>(rec, type, uxd, uyd, tlo, fmin(thi, 1.0), acc, alo, ahi, exp_table(gid));
     ++npairs;
@@ -953,8 +925,10 @@ __global__ __launch_bounds__(192) void k_rot_merge(const uint32_t *__restrict__ 
   if (!inimg) return;
   const int n = (int)(ranges[2 * list + 1] - ranges[2 * list]);
   const size_t img = (size_t)cell * prm.width * prm.height;
-  write_channel<P>(lo, hi, ihi, magl, magh, (double)(n + 2 * (s1 - s0)), prm.E, 0.0, out_lo, out_hi,
-                   (img + (size_t)row * prm.width + col) * 3 + ch);
+  // widened by n 2^-59: each lower transmittance that should be 0 is at most 2^-60 (with
+  // its rounding), and colours and alphas are at most 1
+  write_channel<P>(lo, hi, ihi, magl, magh, (double)(n + 2 * (s1 - s0)), prm.E + (double)n * 0x1p-59, 0.0,
+                   out_lo, out_hi, (img + (size_t)row * prm.width + col) * 3 + ch);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1043,19 +1017,19 @@ static hipError_t launch_rot_p(const Workspace &ws, const uint32_t *lists, const
   double *preL = ws.pre, *preH = ws.pre + ws.cap_pre * kTilePix;
   if (c.nseg > 0) {
     hipLaunchKernelGGL(k_rot_prefix<P>, grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off, ws.seg_tile, c.L,
-                       c.seg0, c.nseg, c.pos0, prm, preL, preH, ws.prez, (double2 *)ws.segsum, ws.segz, ws.counters);
+                       c.seg0, c.nseg, c.pos0, prm, preL, preH, (double2 *)ws.segsum, ws.counters);
     hipLaunchKernelGGL(k_rot_offsets, dim3((unsigned)((c.nl + 3) / 4)), blk, 0, s, ws.seg_off, c.list0, c.nl, c.seg0,
-                       (double2 *)ws.segsum, ws.segz);
+                       (double2 *)ws.segsum);
     if (c.absolute) {
       hipLaunchKernelGGL(k_rot_absolute, grid, blk, 0, s, ws.tile_range, ws.seg_off, ws.seg_tile, c.L, c.seg0, c.nseg,
-                         c.pos0, (const double2 *)ws.segsum, ws.segz, preL, preH, ws.prez);
+                         c.pos0, (const double2 *)ws.segsum, preL, preH);
       hipLaunchKernelGGL((k_rot_blend<P, true>), grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off,
-                         ws.seg_tile, c.L, c.seg0, c.nseg, c.pos0, ws.run_cnt, ws.runs, prm, preL, preH, ws.prez,
-                         (const double2 *)ws.segsum, ws.segz, ws.part, ws.counters);
+                         ws.seg_tile, c.L, c.seg0, c.nseg, c.pos0, ws.run_cnt, ws.runs, prm, preL, preH,
+                         (const double2 *)ws.segsum, ws.part, ws.counters);
     } else {
       hipLaunchKernelGGL((k_rot_blend<P, false>), grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off,
-                         ws.seg_tile, c.L, c.seg0, c.nseg, c.pos0, ws.run_cnt, ws.runs, prm, preL, preH, ws.prez,
-                         (const double2 *)ws.segsum, ws.segz, ws.part, ws.counters);
+                         ws.seg_tile, c.L, c.seg0, c.nseg, c.pos0, ws.run_cnt, ws.runs, prm, preL, preH,
+                         (const double2 *)ws.segsum, ws.part, ws.counters);
     }
   }
   hipLaunchKernelGGL(k_rot_merge<P>, dim3((unsigned)c.nl), dim3(192), 0, s, ws.tile_range, ws.seg_off, c.list0, c.seg0,

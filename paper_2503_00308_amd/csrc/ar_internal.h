@@ -164,14 +164,12 @@ struct Workspace {
   float *union_img = nullptr;  // cell images of a partitioned render (lower, then upper)
   size_t cap_union = 0;
   double *pre = nullptr;       // two planes [pairs][64]: running sums of log(1 - a_lo), log(1 - a_hi)
-  uint32_t *prez = nullptr;    // [pairs][64] per-pixel prefix counts of a_hi == 1
   size_t cap_pre = 0;
   uint32_t *host_ranges = nullptr;   // pinned copy of tile_range (rotation path)
   size_t cap_host_ranges = 0;
   uint32_t *host_seg = nullptr;      // pinned: segment offsets of the lists, then segment -> list
   size_t cap_host_seg = 0;
   double *segsum = nullptr;          // [segments][64][2] segment totals, then offsets
-  uint32_t *segz = nullptr;          // [segments][64]
   size_t cap_segsum = 0;
 };
 
