@@ -7,6 +7,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -77,3 +78,19 @@ def test_server_argument_errors_without_gpu():
     assert lib.ar_server_wait(None, 1, 0, ctypes.byref(r)) == api.AR_E_INVALID
     assert lib.ar_server_report(None, None) == api.AR_E_INVALID
     lib.ar_server_destroy(None)
+
+
+def test_product_path_does_not_use_the_oracle():
+    """The package and its HIP sources never import, include or name the oracle package,
+    and importing the binding does not load it."""
+    pkg = os.path.join(ROOT, "paper_2503_00308_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle\b", text, flags=re.M), f
+                assert "oracle/" not in text, f
+    code = ("import sys; sys.path.insert(0, %r); import paper_2503_00308_amd.api, paper_2503_00308_amd.synth; "
+            "print(any(m == 'oracle' or m.startswith('oracle.') for m in sys.modules))" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300).stdout.strip()
+    assert out == "False"
