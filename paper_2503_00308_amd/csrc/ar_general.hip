@@ -780,7 +780,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     double sum_l = 0.0, err_l = 0.0, sum_h = 0.0, err_h = 0.0;
     if (ABS) {
       // many runs per entry: the runs are read 64 at a time (one per lane) and their ends
-      // four runs at a time, so eight loads are in flight; the sums are taken in run
+      // eight runs at a time, so sixteen loads are in flight; the sums are taken in run
       // order.  The run ends are read back with readlane from the lane that loaded them,
       // so every lane takes part (a lane whose pixel is not kept uses none of the sums);
       // entries no lane keeps are skipped as a whole.
@@ -788,7 +788,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       // S(p) at the clamped index (a valid position of the list when p = 0), zero for p = 0
       auto ix = [&](uint32_t p) -> size_t { return pb + (p > 0 ? p - 1 : 0); };
       const uint2 *runs2 = reinterpret_cast<const uint2 *>(runs);
-      constexpr int kRunGroup = 4;
+      constexpr int kRunGroup = 8;
       for (uint32_t qb = d0; qb < d1; qb += 64) {
         const int nq = (int)min(64u, d1 - qb);
         uint2 abv = make_uint2(0u, 0u);
