@@ -125,6 +125,24 @@ typedef struct {
  *   t_min       stop a tile once every pixel's transmittance upper bound is below it,
  *               widening the upper bound by that transmittance (default 1e-7;
  *               negative disables)
+ *   abs_sums, ind_copy, ind_masks   rotation boxes: switches of three layouts the
+ *               library otherwise picks from the size of the call (0 = automatic,
+ *               1 = on, 2 = off; any other value is rejected).  They change the speed,
+ *               never the result (bit for bit):
+ *                 abs_sums   the per-pixel running sums of the transmittance logs made
+ *                            absolute in a pass of their own (automatic: on with at
+ *                            least 8 Ind runs per list entry);
+ *                 ind_copy   the Ind tests read a copy of the means and depth forms laid
+ *                            out by list position (automatic: on when the Ind windows
+ *                            average 32 positions or more);
+ *                 ind_masks  the Ind masks of windows longer than 64 positions kept
+ *                            between the counting and emitting passes (automatic and 1:
+ *                            kept when they fit 8 GiB; 2: tested again instead)
+ *   group_entries  rotation boxes: the Ind passes (windows, tests, runs) and the pixel
+ *               loop run over groups of consecutive whole tile lists holding at most
+ *               this many entries each (a longer single list is a group of its own;
+ *               default 2^27).  Bounds the 32-bit counts of a group; the result does not
+ *               depend on it (bit for bit).
  */
 typedef struct {
   int32_t tile;
@@ -136,6 +154,10 @@ typedef struct {
   double t_min;
   int32_t cells_per_launch;
   int32_t prefix_entries;
+  int32_t abs_sums;
+  int32_t ind_copy;
+  int32_t ind_masks;
+  int32_t group_entries;
 } ar_options;
 
 /* Statistics of one call (filled when the call returns). */
@@ -291,6 +313,8 @@ typedef struct {
   double queue_ms;       /* submission -> start on a slot (host clock) */
   double latency_ms;     /* submission -> outputs complete (host clock) */
   ar_stats stats;
+  uint64_t est_bytes;    /* workspace bytes estimated for the query at admission */
+  uint64_t ws_bytes;     /* workspace bytes the slot held when the query finished */
   char error[256];       /* message of a failed query */
 } ar_query_result;
 

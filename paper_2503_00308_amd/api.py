@@ -47,7 +47,9 @@ class Options(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("ind_window", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("taylor_k", ctypes.c_int32), ("cull_budget", ctypes.c_double),
                 ("z_near", ctypes.c_double), ("t_min", ctypes.c_double),
-                ("cells_per_launch", ctypes.c_int32), ("prefix_entries", ctypes.c_int32)]
+                ("cells_per_launch", ctypes.c_int32), ("prefix_entries", ctypes.c_int32),
+                ("abs_sums", ctypes.c_int32), ("ind_copy", ctypes.c_int32), ("ind_masks", ctypes.c_int32),
+                ("group_entries", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -67,7 +69,8 @@ class ServerConfig(ctypes.Structure):
 
 class QueryResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("slot", ctypes.c_int32), ("queue_ms", ctypes.c_double),
-                ("latency_ms", ctypes.c_double), ("stats", Stats), ("error", ctypes.c_char * 256)]
+                ("latency_ms", ctypes.c_double), ("stats", Stats), ("est_bytes", ctypes.c_uint64),
+                ("ws_bytes", ctypes.c_uint64), ("error", ctypes.c_char * 256)]
 
 
 class ServerStats(ctypes.Structure):
@@ -162,7 +165,9 @@ def options(d=None) -> Options:
     return Options(int(d.get("tile", 0)), int(d.get("ind_window", 0)), int(d.get("chunk", 0)),
                    int(d.get("taylor_k", 0)), float(d.get("cull_budget", 0.0)),
                    float(d.get("z_near", 0.0)), float(d.get("t_min", 0.0)),
-                   int(d.get("cells_per_launch", 0)), int(d.get("prefix_entries", 0)))
+                   int(d.get("cells_per_launch", 0)), int(d.get("prefix_entries", 0)),
+                   int(d.get("abs_sums", 0)), int(d.get("ind_copy", 0)), int(d.get("ind_masks", 0)),
+                   int(d.get("group_entries", 0)))
 
 
 class Scene:
@@ -387,7 +392,7 @@ class Server:
         _check(code)
         lo, hi = bufs
         res = {"status": r.status, "slot": r.slot, "queue_ms": r.queue_ms, "latency_ms": r.latency_ms,
-               "stats": r.stats.as_dict()}
+               "stats": r.stats.as_dict(), "est_bytes": r.est_bytes, "ws_bytes": r.ws_bytes}
         return lo, hi, res
 
     def report(self) -> dict:

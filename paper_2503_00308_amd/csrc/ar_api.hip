@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "ar_host.h"
+#include "ar_limits.h"
 
 using ar::fail;
 
@@ -107,6 +108,9 @@ int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *o
     return fail(AR_E_INVALID, "cull_budget must be in [0, 1)");
   if (!(o.z_near >= 0.0) || !isfinite(o.z_near)) return fail(AR_E_INVALID, "z_near must be finite and >= 0");
   if (!isfinite(o.t_min) || o.t_min >= 1.0) return fail(AR_E_INVALID, "t_min must be finite and < 1");
+  for (int32_t v : {o.abs_sums, o.ind_copy, o.ind_masks})
+    if (v < 0 || v > 2) return fail(AR_E_INVALID, "layout switch %d outside [0, 2]", v);
+  if (o.group_entries < 0) return fail(AR_E_INVALID, "group_entries %d is negative", o.group_entries);
   prm.width = in->width;
   prm.height = in->height;
   prm.fx = in->fx;
@@ -124,6 +128,10 @@ int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *o
   prm.ind_window = o.ind_window;
   prm.chunk = o.chunk;  // 0: chosen per call from the number of (tile, Gaussian) pairs
   prm.prefix_entries = o.prefix_entries;
+  prm.abs_sums = o.abs_sums;
+  prm.ind_copy = o.ind_copy;
+  prm.ind_masks = o.ind_masks;
+  prm.group_entries = o.group_entries;
   return AR_OK;
 }
 
@@ -166,7 +174,7 @@ static int ensure_ws(Workspace &ws, size_t n_total, size_t nlists, int P, int nc
     ws.cap_cells = (size_t)ncells;
   }
   if (!ws.counters) {
-    HIP_TRY(grow(ws, ws.counters, 8));
+    HIP_TRY(grow(ws, ws.counters, 16));
     HIP_TRY(hipHostMalloc((void **)&ws.host_counters, 16 * sizeof(unsigned long long), hipHostMallocDefault));
     for (int i = 0; i < 4; ++i) HIP_TRY(hipEventCreate(&ws.ev[i]));
   }
@@ -183,9 +191,11 @@ constexpr double kAbsoluteRuns = 8.0;                // runs per list position f
 constexpr int kRotSegment = 64;                      // list positions per segment (rotation path)
 constexpr int kClassifyCells = 1024;                 // pose cells per launch of the classification
 constexpr int kMaxRefineDepth = 24;                  // bisections of a cell in the adaptive refinement
+constexpr uint64_t kGroupEntries = 1ull << 27;       // list entries per group of the Ind passes (rotation path)
 
-// buffers of the general path: run counts for npairs list positions, pinned list ranges
-static int ensure_general(Workspace &ws, size_t npairs, size_t nlists) {
+// buffers of the general path: run counts, windows and mask offsets for a list group of
+// npairs entries
+static int ensure_general(Workspace &ws, size_t npairs) {
   if (2 * npairs + 1 > ws.cap_run_cnt || !ws.run_cnt) {
     const size_t need = 2 * npairs + 1 + npairs / 2 + 1024;
     HIP_TRY(grow(ws, ws.run_cnt, need));
@@ -196,13 +206,6 @@ static int ensure_general(Workspace &ws, size_t npairs, size_t nlists) {
     HIP_TRY(grow(ws, ws.win, 2 * need));
     HIP_TRY(grow(ws, ws.woff, need + 1));
     ws.cap_win = need;
-  }
-  if (2 * nlists + 2 > ws.cap_host_ranges || !ws.host_ranges) {
-    if (ws.host_ranges) HIP_TRY(hipHostFree(ws.host_ranges));
-    ws.host_ranges = nullptr;
-    const size_t need = 2 * nlists + 2;
-    HIP_TRY(hipHostMalloc((void **)&ws.host_ranges, need * sizeof(uint32_t), hipHostMallocDefault));
-    ws.cap_host_ranges = need;
   }
   return AR_OK;
 }
@@ -329,21 +332,33 @@ static int bits_for(uint32_t v) {
   return b;
 }
 
-// Estimated device bytes of a launch of ncells cells (records, per-item arrays, list
-// entries, segment partials or prefix sums), at pairs_per_item list entries per item.
-size_t query_bytes(const ar_scene *sc, const Params &prm, int P, bool rotates, int ncells, double pairs_per_item) {
+// Estimated device bytes of a launch of ncells cells: the buffers the launch sequence
+// grows (records and per-item arrays, list entries, list boxes, segment partials; on the
+// rotation path the windows, run counts, runs, stored masks, the compact copy, prefix
+// sums and segment totals of one list group), with their headroom, at the list density d.
+size_t query_bytes(const ar_scene *sc, const Params &prm, int P, bool rotates, int ncells, const Density &d) {
   const double items = (double)sc->dev.n * ncells;
   const double lists = (double)prm.ntx * prm.nty * ncells;
-  const double pairs = items * (pairs_per_item > 0.0 ? pairs_per_item : 32.0);
-  const double per_item = 8.0 * rec_stride(P) + 8.0 * (3 + 2 * (kMaxP + 1) + 2) + 4.0 * 7 + 16.0;
-  double b = items * per_item + pairs * 20.0 + lists * 24.0 + (double)(16 << 20);
+  const double pairs = items * (d.pairs_per_item > 0.0 ? d.pairs_per_item : 32.0);
+  // per item: record, 3 depth keys, 4 permutation / cell arrays, rectangle, depth forms,
+  // count, depth pair
+  const double per_item = 8.0 * rec_stride(P) + 24.0 + 16.0 + 16.0 + 16.0 * (kMaxP + 1) + 4.0 + 16.0;
+  // list entries (4 arrays of 4 B, 1.25x), radix histograms and scan sums (about 1 B per entry)
+  double b = items * per_item + pairs * (20.0 + 1.0) + lists * (8.0 + 8.0 * kListBox) + (double)(16 << 20);
   if (rotates) {
-    b += pairs * (8.0 + 16.0) + std::min(pairs, (double)kPrefixEntries) * 64.0 * 20.0 * 1.125;
+    const double gcap = prm.group_entries > 0 ? (double)prm.group_entries : (double)kGroupEntries;
+    const double g = std::min(pairs, gcap);
+    b += g * (10.0 + 10.0 + 5.0);                                    // run counts, windows, mask offsets
+    b += 1.25 * g * 8.0 * (d.runs_per_entry > 0.0 ? d.runs_per_entry : 16.0);   // runs
+    b += std::min(1.25 * g * 8.0 * d.mask_words_per_entry, kMaskBytes);         // stored masks
+    if (d.compact || prm.ind_copy == 1) b += 1.25 * g * (16.0 * (P + 1) + 16.0);   // compact copy
+    const double pre = prm.prefix_entries > 0 ? (double)prm.prefix_entries : (double)kPrefixEntries;
+    b += 1.125 * std::min(pairs, pre) * 64.0 * 16.0;                // prefix sums (two planes)
     const double segs = pairs / kRotSegment + lists;
-    b += segs * 4.0 + std::min(segs, (double)kRotChunkSegs) * (8.0 * part_fields(P) * 64.0 + 20.0 * 64.0);
+    b += 1.25 * segs * 4.0 + 1.25 * std::min(segs, (double)kRotChunkSegs) * (8.0 * part_fields(P) * 64.0 + 16.0 * 64.0);
   } else {
     const double segs = std::min(8192.0 + lists, pairs / 32.0 + lists);
-    b += segs * (8.0 * part_fields(P) * 64.0 + 8.0);
+    b += 1.25 * segs * (8.0 * part_fields(P) * 64.0 + 4.0);
   }
   return (size_t)b;
 }
@@ -389,8 +404,237 @@ int batch_cells(const ar_scene *sc, const Workspace &ws, const Params &prm, int 
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)16 << 30;
   const double budget = std::min(0.25 * (double)free_b, 64.0 * 1024 * 1024 * 1024);
-  const double per_cell = (double)query_bytes(sc, prm, P, rotates, 1, ws.pairs_per_item);
+  const double per_cell = (double)query_bytes(sc, prm, P, rotates, 1, ws.density);
   return (int)std::max(1.0, std::min(256.0, floor(budget / per_cell)));
+}
+
+// Rotation path after the tile lists are built: per list group, the Ind windows, tests
+// and runs (k_runs, three passes), then the two-phase pixel loop over chunks of the
+// group's lists.  A group is a run of consecutive whole lists with at most
+// prm.group_entries entries (default kGroupEntries), so the 32-bit scans of a group's
+// mask words and run counts cover a bounded number of entries; the group's run total is
+// summed in 64 bits and a group with more runs than uint32 offsets hold is rejected.
+// One group (no extra synchronisation) when all entries fit.
+static int render_rotation(const ar_scene *sc, Workspace &ws, const Params &prm, int P, uint32_t npairs,
+                           size_t nlists, int ntiles, float *lo, float *hi, hipStream_t s, ar_stats *st) {
+  const uint64_t gcap = prm.group_entries > 0 ? (uint64_t)prm.group_entries : kGroupEntries;
+  const bool split = (uint64_t)npairs > gcap;
+  if (2 * nlists + 2 > ws.cap_host_ranges || !ws.host_ranges) {
+    if (ws.host_ranges) HIP_TRY(hipHostFree(ws.host_ranges));
+    ws.host_ranges = nullptr;
+    const size_t need = 2 * nlists + 2;
+    HIP_TRY(hipHostMalloc((void **)&ws.host_ranges, need * sizeof(uint32_t), hipHostMallocDefault));
+    ws.cap_host_ranges = need;
+  }
+  const uint32_t *R = ws.host_ranges;
+  HIP_TRY(launch_list_box(ws, ws.pair_val, ws.pose_dev, (int)nlists, ntiles, sc->dev, s));
+  std::vector<size_t> groups;
+  bool have_ranges = false;
+  if (split) {
+    // the list ranges first: they define the groups
+    HIP_TRY(hipMemcpyAsync(ws.host_ranges, ws.tile_range, 2 * nlists * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    have_ranges = true;
+    if (!plan_groups(R, nlists, gcap, groups))
+      return fail(AR_E_UNSUPPORTED, "a tile list holds more than %llu entries", (unsigned long long)kMaxGroupEntries);
+  } else {
+    groups = {0, nlists};
+  }
+  // first and end list position of group g (lists are contiguous and in order; an empty
+  // list has the range [0, 0))
+  auto span = [&](size_t g, uint32_t &pa, uint32_t &pb) {
+    if (!have_ranges) {
+      pa = 0;
+      pb = npairs;
+      return;
+    }
+    pa = pb = 0;
+    bool any = false;
+    for (size_t l = groups[g]; l < groups[g + 1]; ++l) {
+      if (R[2 * l + 1] > R[2 * l]) {
+        if (!any) pa = R[2 * l];
+        pb = R[2 * l + 1];
+        any = true;
+      }
+    }
+  };
+  size_t gmax = 0;
+  for (size_t g = 0; g + 1 < groups.size(); ++g) {
+    uint32_t pa, pb;
+    span(g, pa, pb);
+    gmax = std::max<size_t>(gmax, pb - pa);
+  }
+  int rc = ensure_general(ws, gmax);
+  if (rc) return rc;
+  const int L = rot_segment_length(prm);
+  if (st) st->segment_length = std::max(st->segment_length, L);
+  // segment table of all lists (segments of L positions, the last one ragged) and the
+  // prefix-sum buffer; built once the list ranges are on the host
+  const size_t want = prm.prefix_entries > 0 ? (size_t)prm.prefix_entries : kPrefixEntries;
+  size_t cap = 0;
+  uint32_t *so = nullptr;
+  bool tables = false;
+  auto build_tables = [&]() -> int {
+    size_t nseg_total = 0, longest = 0;
+    for (size_t l = 0; l < nlists; ++l) {
+      const size_t nl = R[2 * l + 1] - R[2 * l];
+      longest = std::max(longest, nl);
+      nseg_total += (nl + (size_t)L - 1) / (size_t)L;
+    }
+    int r = ensure_prefix(ws, std::min<size_t>(npairs, std::max(want, longest)));
+    if (r) return r;
+    r = ensure_rot_segments(ws, nlists, nseg_total);
+    if (r) return r;
+    so = ws.host_seg;
+    uint32_t *stl = ws.host_seg + (nlists + 1);
+    so[0] = 0;
+    for (size_t l = 0, k = 0; l < nlists; ++l) {
+      const uint32_t ns = (R[2 * l + 1] - R[2 * l] + (uint32_t)L - 1) / (uint32_t)L;
+      for (uint32_t j = 0; j < ns; ++j) stl[k++] = (uint32_t)l;
+      so[l + 1] = so[l] + ns;
+    }
+    HIP_TRY(hipMemcpyAsync(ws.seg_off, so, (nlists + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    if (nseg_total)
+      HIP_TRY(hipMemcpyAsync(ws.seg_tile, stl, nseg_total * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    cap = std::max(std::min<size_t>(ws.cap_pre, want), longest);
+    tables = true;
+    return AR_OK;
+  };
+  if (have_ranges) {
+    rc = build_tables();
+    if (rc) return rc;
+  }
+  unsigned long long tests_before = 0;   // window statistic counters[1] is cumulative over groups
+  bool first_pixel_chunk = true;
+  for (size_t g = 0; g + 1 < groups.size(); ++g) {
+    const size_t la = groups[g], lb = groups[g + 1];
+    uint32_t pa, pb;
+    span(g, pa, pb);
+    const int ng = (int)(pb - pa);
+    // Ind windows, and the mask words of the long ones
+    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, pa, ng, prm.ind_window, kRunsWindows,
+                        nullptr, false, s));
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.woff + ng, 1);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(exclusive_scan_u32(ws.woff, ng + 1, ws, s));
+    HIP_TRY(hipMemcpyAsync(ws.host_counters, ws.woff + ng, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ws.host_counters + 1, ws.counters + 5, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           s));
+    HIP_TRY(hipMemcpyAsync(ws.host_counters + 2, ws.counters + 1, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           s));
+    HIP_TRY(hipStreamSynchronize(s));
+    // masks of the long windows are kept for the emitting pass when their (32-bit) offsets
+    // cannot have wrapped and they fit kMaskBytes; otherwise that pass tests them again
+    const size_t words = *(const uint32_t *)ws.host_counters;
+    const double words_max = (double)ng * 2.0 * (double)((ws.host_counters[1] + 63) / 64);
+    const unsigned long long tests = ws.host_counters[2] - tests_before;
+    tests_before = ws.host_counters[2];
+    unsigned long long *masks = nullptr;
+    if (prm.ind_masks != 2 && words > 0 && words_max < 4294967295.0 && (double)words * 8.0 <= kMaskBytes) {
+      if (words > ws.cap_masks || !ws.masks) {
+        const size_t need = words + words / 4 + 1024;
+        HIP_TRY(grow(ws, ws.masks, need));
+        ws.cap_masks = need;
+      }
+      masks = ws.masks;
+    }
+    // long windows on average: the Ind tests read a copy laid out by list position
+    const bool compact = prm.ind_copy == 1 || (prm.ind_copy == 0 && (double)tests >= kCompactWindow * (double)ng);
+    if (compact && ng > 0) {
+      const size_t forms = (size_t)ng * (size_t)(2 * (P + 1));
+      if (forms > ws.cap_compact || !ws.cform) {
+        const size_t w2 = forms + forms / 4 + 1024;
+        HIP_TRY(grow(ws, ws.cform, w2));
+        ws.cap_compact = w2;
+      }
+      if ((size_t)ng > ws.cap_cmean || !ws.cmean) {
+        const size_t w2 = (size_t)ng + (size_t)ng / 4 + 256;
+        HIP_TRY(grow(ws, ws.cmean, 4 * w2));
+        ws.cap_cmean = w2;
+      }
+      HIP_TRY(launch_ind_gather(P, ws, ws.pair_val, sc->dev, ntiles, pa, ng, s));
+    }
+    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, pa, ng, prm.ind_window, kRunsCount, masks,
+                        compact, s));
+    // run counts: their 64-bit total beside the 32-bit scan into offsets
+    const size_t ncnt = 2 * (size_t)ng;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.run_cnt + ncnt, 1);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ws.counters + 9, 1);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(sum_u32_u64(ws.run_cnt, ncnt, ws.counters + 9, s));
+    HIP_TRY(exclusive_scan_u32(ws.run_cnt, (int)(ncnt + 1), ws, s));
+    HIP_TRY(hipMemcpyAsync(ws.host_counters + 9, ws.counters + 9, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           s));
+    if (!have_ranges)
+      HIP_TRY(hipMemcpyAsync(ws.host_ranges, ws.tile_range, 2 * nlists * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint64_t nruns64 = ws.host_counters[9];
+    if (const char *why = group_runs_limit(nruns64))
+      return fail(AR_E_UNSUPPORTED, "%s: %llu runs in %d entries (set a smaller group_entries)", why,
+                  (unsigned long long)nruns64, ng);
+    const size_t nruns = (size_t)nruns64;
+    if (st) st->runs += (int64_t)nruns;
+    if (ng > 0) {
+      Density &dn = ws.density;
+      dn.runs_per_entry = std::max(dn.runs_per_entry, (double)nruns / ng);
+      dn.mask_words_per_entry = std::max(dn.mask_words_per_entry, masks ? (double)words / ng : 0.0);
+      dn.compact = dn.compact || compact;
+    }
+    rc = ensure_runs(ws, nruns);
+    if (rc) return rc;
+    if (!have_ranges) {
+      have_ranges = true;
+      rc = build_tables();
+      if (rc) return rc;
+    }
+    // chunks of consecutive lists of the group with at most cap entries and kRotChunkSegs
+    // segments (or one longer list)
+    const bool absolute =
+        prm.abs_sums == 1 || (prm.abs_sums == 0 && (double)nruns >= kAbsoluteRuns * (double)std::max(ng, 1));
+    std::vector<RotChunk> chunks;
+    size_t max_segs = 0;
+    for (size_t l = la; l < lb;) {
+      size_t l1 = l;
+      uint32_t pos0 = 0;
+      bool have = false;
+      while (l1 < lb) {
+        const uint32_t b = R[2 * l1], e = R[2 * l1 + 1];
+        if (e > b) {
+          if (!have) {
+            pos0 = b;
+            have = true;
+          } else if ((size_t)(e - pos0) > cap || so[l1 + 1] - so[l] > kRotChunkSegs) {
+            break;
+          }
+        }
+        ++l1;
+      }
+      RotChunk c;
+      c.list0 = (int)l;
+      c.nl = (int)(l1 - l);
+      c.seg0 = (int)so[l];
+      c.nseg = (int)(so[l1] - so[l]);
+      c.L = L;
+      c.pos0 = pos0;
+      c.gbase = pa;
+      // with many runs per list position the blend reads each run end once from absolute
+      // sums; with few, adding the offsets in the blend is cheaper than a pass over them
+      c.absolute = absolute;
+      chunks.push_back(c);
+      max_segs = std::max(max_segs, (size_t)c.nseg);
+      l = l1;
+    }
+    rc = ensure_rot_parts(ws, max_segs, P);
+    if (rc) return rc;
+    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, pa, ng, prm.ind_window, kRunsEmit, masks,
+                        compact, s));
+    if (first_pixel_chunk) HIP_TRY(hipEventRecord(ws.ev[1], s));
+    first_pixel_chunk = false;
+    for (const RotChunk &c : chunks) HIP_TRY(launch_raster_general(P, ws, ws.pair_val, c, prm, lo, hi, s));
+  }
+  HIP_TRY(hipEventRecord(ws.ev[2], s));
+  return AR_OK;
 }
 
 // Abstract renders of ncells pose boxes (same P, all rotating or all not) with one
@@ -406,11 +650,12 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
   const size_t n_total = (size_t)ncells * n;
   const size_t nlists = (size_t)ncells * ntiles;
   if (!rotates && P > 3) return fail(AR_E_INVALID, "more than 3 translation variables");
-  if (n_total > 0xFFFFFFF0ull || nlists > 0x7FFFFFF0ull) return fail(AR_E_INVALID, "too many cells in one launch");
+  if (launch_limit(n_total, 0) || nlists >= kScanMax)
+    return fail(AR_E_UNSUPPORTED, "too many cells in one launch (%zu items, %zu tile lists)", n_total, nlists);
   int rc = ensure_ws(ws, n_total, nlists, P, ncells);
   if (rc) return rc;
   HIP_TRY(hipEventRecord(ws.ev[0], s));
-  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ws.counters, 8);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ws.counters, 16);
   HIP_TRY(hipGetLastError());
   // pose forms on the host; by value for a single translation box, else in device memory
   for (int c = 0; c < ncells; ++c)
@@ -436,15 +681,22 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
       std::swap(ws.perm, ws.perm_alt);
     }
   }
-  // tile lists in depth order
+  // tile lists in depth order; the number of entries is summed in 64 bits beside the
+  // 32-bit scan, so a total that would wrap is rejected instead of used
   HIP_TRY(launch_count_tiles(P, ws, (int)n_total, n, prm, s));
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.count + n_total, 1);
   HIP_TRY(hipGetLastError());
+  HIP_TRY(sum_u32_u64(ws.count, n_total, ws.counters + 8, s));
   HIP_TRY(exclusive_scan_u32(ws.count, (int)n_total + 1, ws, s));
-  HIP_TRY(hipMemcpyAsync(ws.host_counters, ws.count + n_total, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(ws.host_counters + 8, ws.counters + 8, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  const uint32_t npairs = *(const uint32_t *)ws.host_counters;
-  ws.pairs_per_item = (double)npairs / (double)std::max<size_t>(n_total, 1);
+  const uint64_t npairs64 = ws.host_counters[8];
+  if (const char *why = launch_limit(n_total, npairs64))
+    return fail(AR_E_UNSUPPORTED, "%s: %llu entries of %zu items (use fewer cells per launch or a smaller image)", why,
+                (unsigned long long)npairs64, n_total);
+  const uint32_t npairs = (uint32_t)npairs64;
+  ws.density = Density{};
+  ws.density.pairs_per_item = (double)npairs / (double)std::max<size_t>(n_total, 1);
   rc = ensure_pairs(ws, npairs);
   if (rc) return rc;
   HIP_TRY(launch_emit_tiles(P, ws, (int)n_total, n, prm, s));
@@ -467,130 +719,8 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
     HIP_TRY(launch_segment_map(ws, (int)nlists, s));
     HIP_TRY(launch_raster_translation(P, ws, ws.pair_val, (int)nlists, prm, L, (int)nseg_max, lo, hi, s));
   } else {
-    // depth order may change inside the box: Ind runs per tile list, then the two-phase loop
-    rc = ensure_general(ws, npairs, nlists);
+    rc = render_rotation(sc, ws, prm, P, npairs, nlists, ntiles, lo, hi, s, st);
     if (rc) return rc;
-    HIP_TRY(launch_list_box(ws, ws.pair_val, ws.pose_dev, (int)nlists, ntiles, sc->dev, s));
-    // Ind windows, and the mask words of the long ones
-    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, prm.ind_window, kRunsWindows,
-                        nullptr, false, s));
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.woff + npairs, 1);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(exclusive_scan_u32(ws.woff, (int)(npairs + 1), ws, s));
-    HIP_TRY(hipMemcpyAsync(ws.host_counters, ws.woff + npairs, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(ws.host_counters + 1, ws.counters + 5, sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                           s));
-    HIP_TRY(hipMemcpyAsync(ws.host_counters + 2, ws.counters + 1, sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                           s));
-    HIP_TRY(hipStreamSynchronize(s));
-    // masks of the long windows are kept for the emitting pass when their (32-bit) offsets
-    // cannot have wrapped and they fit kMaskBytes; otherwise that pass tests them again
-    const size_t words = *(const uint32_t *)ws.host_counters;
-    const double words_max = (double)npairs * 2.0 * (double)((ws.host_counters[1] + 63) / 64);
-    unsigned long long *masks = nullptr;
-    if (words > 0 && words_max < 4294967295.0 && (double)words * 8.0 <= kMaskBytes) {
-      if (words > ws.cap_masks || !ws.masks) {
-        const size_t need = words + words / 4 + 1024;
-        HIP_TRY(grow(ws, ws.masks, need));
-        ws.cap_masks = need;
-      }
-      masks = ws.masks;
-    }
-    // long windows on average: the Ind tests read a copy laid out by list position
-    const bool compact = (double)ws.host_counters[2] >= kCompactWindow * (double)npairs;
-    if (compact) {
-      const size_t forms = npairs * (size_t)(2 * (P + 1));
-      if (forms > ws.cap_compact || !ws.cform) {
-        const size_t want = forms + forms / 4 + 1024;
-        HIP_TRY(grow(ws, ws.cform, want));
-        ws.cap_compact = want;
-      }
-      if (npairs > ws.cap_cmean || !ws.cmean) {
-        const size_t want = npairs + npairs / 4 + 256;
-        HIP_TRY(grow(ws, ws.cmean, 4 * want));
-        ws.cap_cmean = want;
-      }
-      HIP_TRY(launch_ind_gather(P, ws, ws.pair_val, sc->dev, ntiles, (int)npairs, s));
-    }
-    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, prm.ind_window, kRunsCount,
-                        masks, compact, s));
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.run_cnt + 2 * (size_t)npairs, 1);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(exclusive_scan_u32(ws.run_cnt, (int)(2 * npairs + 1), ws, s));
-    HIP_TRY(hipMemcpyAsync(ws.host_counters, ws.run_cnt + 2 * (size_t)npairs, sizeof(uint32_t),
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(ws.host_ranges, ws.tile_range, 2 * nlists * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const uint32_t nruns = *(const uint32_t *)ws.host_counters;
-    if (st) st->runs += nruns;
-    rc = ensure_runs(ws, nruns);
-    if (rc) return rc;
-    // segments of L positions per list (the last one ragged), then chunks of consecutive
-    // lists with at most kPrefixEntries entries and kRotChunkSegs segments (or one longer list)
-    const uint32_t *R = ws.host_ranges;
-    const int L = rot_segment_length(prm);
-    if (st) st->segment_length = std::max(st->segment_length, L);
-    size_t nseg_total = 0, longest = 0;
-    for (size_t l = 0; l < nlists; ++l) {
-      const size_t nl = R[2 * l + 1] - R[2 * l];
-      longest = std::max(longest, nl);
-      nseg_total += (nl + (size_t)L - 1) / (size_t)L;
-    }
-    const size_t want = prm.prefix_entries > 0 ? (size_t)prm.prefix_entries : kPrefixEntries;
-    rc = ensure_prefix(ws, std::min<size_t>(npairs, std::max(want, longest)));
-    if (rc) return rc;
-    rc = ensure_rot_segments(ws, nlists, nseg_total);
-    if (rc) return rc;
-    uint32_t *so = ws.host_seg, *stl = ws.host_seg + (nlists + 1);
-    so[0] = 0;
-    for (size_t l = 0, k = 0; l < nlists; ++l) {
-      const uint32_t ns = (R[2 * l + 1] - R[2 * l] + (uint32_t)L - 1) / (uint32_t)L;
-      for (uint32_t j = 0; j < ns; ++j) stl[k++] = (uint32_t)l;
-      so[l + 1] = so[l] + ns;
-    }
-    HIP_TRY(hipMemcpyAsync(ws.seg_off, so, (nlists + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    if (nseg_total)
-      HIP_TRY(hipMemcpyAsync(ws.seg_tile, stl, nseg_total * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    const size_t cap = std::max(std::min<size_t>(ws.cap_pre, want), longest);
-    std::vector<RotChunk> chunks;
-    size_t max_segs = 0;
-    for (size_t l = 0; l < nlists;) {
-      size_t l1 = l;
-      uint32_t pos0 = 0;
-      bool have = false;
-      while (l1 < nlists) {
-        const uint32_t b = R[2 * l1], e = R[2 * l1 + 1];
-        if (e > b) {
-          if (!have) {
-            pos0 = b;
-            have = true;
-          } else if ((size_t)(e - pos0) > cap || so[l1 + 1] - so[l] > kRotChunkSegs) {
-            break;
-          }
-        }
-        ++l1;
-      }
-      RotChunk c;
-      c.list0 = (int)l;
-      c.nl = (int)(l1 - l);
-      c.seg0 = (int)so[l];
-      c.nseg = (int)(so[l1] - so[l]);
-      c.L = L;
-      c.pos0 = pos0;
-      // with many runs per list position the blend reads each run end once from absolute
-      // sums; with few, adding the offsets in the blend is cheaper than a pass over them
-      c.absolute = (double)nruns >= kAbsoluteRuns * (double)npairs;
-      chunks.push_back(c);
-      max_segs = std::max(max_segs, (size_t)c.nseg);
-      l = l1;
-    }
-    rc = ensure_rot_parts(ws, max_segs, P);
-    if (rc) return rc;
-    HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, (int)npairs, prm.ind_window, kRunsEmit,
-                        masks, compact, s));
-    HIP_TRY(hipEventRecord(ws.ev[1], s));
-    for (const RotChunk &c : chunks) HIP_TRY(launch_raster_general(P, ws, ws.pair_val, c, prm, lo, hi, s));
-    HIP_TRY(hipEventRecord(ws.ev[2], s));
   }
   HIP_TRY(hipEventRecord(ws.ev[3], s));
   HIP_TRY(hipMemcpyAsync(ws.host_counters, ws.counters, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));

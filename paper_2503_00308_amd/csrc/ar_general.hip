@@ -181,7 +181,7 @@ struct IndSrc {
   const float4 *cmean;       // means by list position (COMPACT)
   int n;                     // scene size
   size_t gbase;              // the cell's first item
-  size_t pos0;               // the list's first position (COMPACT)
+  size_t pos0;               // the list's first position relative to the group's first (COMPACT)
 
   __device__ __forceinline__ void mean_of(int j, double *uw) const {
     if (COMPACT) {
@@ -201,21 +201,23 @@ struct IndSrc {
   }
 };
 
-// Compact copy for the Ind tests: per list position, the item's mean (float4) and depth
-// forms (lower then upper, P + 1 doubles each).
+// Compact copy for the Ind tests: per list position of a group (positions pbase + q,
+// q < ng), the item's mean (float4) and depth forms (lower then upper, P + 1 doubles
+// each), at index q.
 template <int P>
 __global__ __launch_bounds__(256) void k_ind_gather(const uint32_t *__restrict__ pkey,
                                                     const uint32_t *__restrict__ lists, const double *__restrict__ dform,
-                                                    SceneDev sc, int ntiles, int npairs, float4 *__restrict__ cmean,
-                                                    double *__restrict__ cform) {
+                                                    SceneDev sc, int ntiles, uint32_t pbase, int ng,
+                                                    float4 *__restrict__ cmean, double *__restrict__ cform) {
   constexpr int F = P + 1;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npairs) return;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= ng) return;
+  const size_t p = (size_t)pbase + q;
   const uint32_t g = lists[p];
   const size_t lg = g - (size_t)(pkey[p] / (uint32_t)ntiles) * sc.n;
-  cmean[p] = make_float4(sc.mean[lg], sc.mean[sc.n + lg], sc.mean[2 * (size_t)sc.n + lg], 0.0f);
+  cmean[q] = make_float4(sc.mean[lg], sc.mean[sc.n + lg], sc.mean[2 * (size_t)sc.n + lg], 0.0f);
   const double *d = dform + (size_t)g * 2 * (kMaxP + 1);
-  double *o = cform + (size_t)p * 2 * F;
+  double *o = cform + (size_t)q * 2 * F;
 #pragma unroll
   for (int k = 0; k < P; ++k) {
     o[k] = d[k];
@@ -304,7 +306,9 @@ __device__ __forceinline__ void wave_runs(const PoseForms &pose, const IndSrc<P,
 constexpr int kWaveWindow = 64;
 
 // Runs of {j: Ind_ij = 1} and {j: Ind_ij != 0} for 64 consecutive (tile, list position)
-// entries per wave and step, in three passes (MODE):
+// entries per wave and step, over the entries pbase .. pbase + ng - 1 of a group of whole
+// lists (win, woff, cnt, the compact copy and the runs are indexed relative to the group),
+// in three passes (MODE):
 //   kRunsWindows: each lane finds its entry's window [ps, qe) (win) and the number of
 //     mask words a long window needs (wc: two per 64 positions, scanned into offsets);
 //   kRunsCount: the Ind tests and the run counts (cnt); a short window is walked by its
@@ -317,7 +321,7 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
                                               const double *__restrict__ dform, const float4 *__restrict__ cmean,
                                               const double *__restrict__ cform, const double *__restrict__ lbox,
                                               const PoseForms *__restrict__ poses, int ntiles, SceneDev sc,
-                                              int npairs, int window_mode, uint32_t *__restrict__ win,
+                                              uint32_t pbase, int ng, int window_mode, uint32_t *__restrict__ win,
                                               uint32_t *__restrict__ woff, unsigned long long *__restrict__ masks,
                                               uint32_t *__restrict__ cnt, uint32_t *__restrict__ runs,
                                               unsigned long long *__restrict__ counters) {
@@ -326,17 +330,17 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
   const int wave0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   const int nwaves = (int)(gridDim.x * (blockDim.x >> 6));
   unsigned long long wmax = 0, wsum = 0;   // window statistics of this lane's entries
-  for (int p0 = wave0 * 64; p0 < npairs; p0 += nwaves * 64) {
-    const int p = p0 + lane;
-    const bool have = p < npairs;
+  for (int p0 = wave0 * 64; p0 < ng; p0 += nwaves * 64) {
+    const int p = p0 + lane;                       // entry of the group; list position pbase + p
+    const bool have = p < ng;
     int cell = 0, beg = 0, i = 0, ps = 0, qe = 0;
     uint32_t gi = 0;
     double uwi[3] = {0.0, 0.0, 0.0};
     if (have) {
-      const uint32_t tile = pkey[p];                 // list id: cell * ntiles + tile
+      const uint32_t tile = pkey[(size_t)pbase + p];   // list id: cell * ntiles + tile
       cell = (int)(tile / (uint32_t)ntiles);
       beg = (int)ranges[2 * tile];
-      i = p - beg;
+      i = (int)(pbase + (uint32_t)p) - beg;
       const uint32_t *list = lists + beg;
       gi = list[i];
       const size_t li = gi - (size_t)cell * sc.n;
@@ -420,7 +424,7 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
     if (have && !wide) {
       const PoseForms &pose = poses[cell];
       const IndSrc<P, COMPACT> src{lists + beg, sc.mean, COMPACT ? cform : dform, cmean, sc.n,
-                                   (size_t)cell * sc.n, (size_t)beg};
+                                   (size_t)cell * sc.n, (size_t)((uint32_t)beg - pbase)};
       const double *dfi = src.forms_of(i);
       int def_start = ps > 0 ? 0 : -1;   // open run [0, ps) of certain occluders
       int may_start = ps > 0 ? 0 : -1;
@@ -471,7 +475,7 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
       }
       unsigned long long *km_ = masks ? masks + woff[kp] : nullptr;
       const IndSrc<P, COMPACT> src{lists + kb, sc.mean, COMPACT ? cform : dform, cmean, sc.n, (size_t)kc * sc.n,
-                                   (size_t)kb};
+                                   (size_t)((uint32_t)kb - pbase)};
       uint32_t kd, km;
       wave_runs<P, MODE, COMPACT>(poses[kc], src, ki, kps, kqe, kuw, src.forms_of(ki), km_, kod, kom, lane, kd, km);
       if (lane == k) {
@@ -510,7 +514,8 @@ __global__ __launch_bounds__(256) void k_runs_count_lanes(const uint32_t *__rest
                                                           const float4 *__restrict__ cmean,
                                                           const double *__restrict__ cform,
                                                           const PoseForms *__restrict__ poses, int ntiles,
-                                                          SceneDev sc, int npairs, const uint32_t *__restrict__ win,
+                                                          SceneDev sc, uint32_t pbase, int ng,
+                                                          const uint32_t *__restrict__ win,
                                                           const uint32_t *__restrict__ woff,
                                                           unsigned long long *__restrict__ masks,
                                                           uint32_t *__restrict__ cnt) {
@@ -519,18 +524,18 @@ __global__ __launch_bounds__(256) void k_runs_count_lanes(const uint32_t *__rest
   const int lane = threadIdx.x & 63;
   const int wave0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   const int nwaves = (int)(gridDim.x * (blockDim.x >> 6));
-  for (int p0 = wave0 * 64; p0 < npairs; p0 += nwaves * 64) {
-    const int p = p0 + lane;
-    const bool have = p < npairs;
+  for (int p0 = wave0 * 64; p0 < ng; p0 += nwaves * 64) {
+    const int p = p0 + lane;                       // entry of the group; list position pbase + p
+    const bool have = p < ng;
     uint32_t tile = 0;
     int beg = 0, i = 0, ps = 0, qe = 0;
     double uwi[3] = {0.0, 0.0, 0.0}, dfi[2 * S];
 #pragma unroll
     for (int k = 0; k < 2 * S; ++k) dfi[k] = 0.0;
     if (have) {
-      tile = pkey[p];
+      tile = pkey[(size_t)pbase + p];
       beg = (int)ranges[2 * tile];
-      i = p - beg;
+      i = (int)(pbase + (uint32_t)p) - beg;
       ps = (int)win[2 * (size_t)p];
       qe = (int)win[2 * (size_t)p + 1];
       const float4 m = cmean[p];
@@ -560,7 +565,7 @@ __global__ __launch_bounds__(256) void k_runs_count_lanes(const uint32_t *__rest
       const int gbeg = __builtin_amdgcn_readlane(beg, l0);
       const int gcell = (int)(gtile / (uint32_t)ntiles);
       const PoseForms &pose = poses[gcell];
-      const Src src{lists + gbeg, sc.mean, cform, cmean, sc.n, (size_t)gcell * sc.n, (size_t)gbeg};
+      const Src src{lists + gbeg, sc.mean, cform, cmean, sc.n, (size_t)gcell * sc.n, (size_t)((uint32_t)gbeg - pbase)};
       int def_start = (mine && ps > 0) ? 0 : -1;   // open run [0, ps) of certain occluders
       int may_start = def_start;
       uint32_t nd = 0, nm = 0;
@@ -719,6 +724,8 @@ __global__ __launch_bounds__(256) void k_rot_absolute(const uint32_t *__restrict
 
 // B: transmittances from the runs (absolute: everything in front of the Gaussian),
 // colour forms accumulated per segment; the tile's bounds are the sum of its segments.
+// Run counts (then offsets) cnt and the runs are those of the list group that starts at
+// list position gbase.
 // ABS: the running sums were made absolute (k_rot_absolute); otherwise each run end
 // adds its segment's offset here.
 template <int P, bool ABS>
@@ -726,7 +733,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                    const uint32_t *__restrict__ lists,
                                                    const uint32_t *__restrict__ seg_off,
                                                    const uint32_t *__restrict__ seg_tile, int L, int seg0, int nseg,
-                                                   uint32_t pos0, const uint32_t *__restrict__ cnt,
+                                                   uint32_t pos0, uint32_t gbase, const uint32_t *__restrict__ cnt,
                                                    const uint32_t *__restrict__ runs, Params prm,
                                                    const double *__restrict__ preL, const double *__restrict__ preH,
                                                    const double2 *__restrict__ segoff, double *__restrict__ part,
@@ -760,7 +767,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     if (k == 0) {
       la.fetch<P>(recs, items, i + lane, r.i1);
       if (i + lane < r.i1) {
-        const size_t sl2 = 2 * (size_t)(r.beg + i + lane);
+        const size_t sl2 = 2 * (size_t)((uint32_t)(r.beg + i + lane) - gbase);
         cv0 = cnt[sl2];
         cv1 = cnt[sl2 + 1];
         cv2 = cnt[sl2 + 2];
@@ -940,72 +947,69 @@ hipError_t launch_list_box(const Workspace &ws, const uint32_t *lists, const Pos
 
 template <int P, int MODE, bool COMPACT>
 static hipError_t launch_runs_pm(const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
-                                 const SceneDev &sc, int npairs, int window_mode, unsigned long long *masks,
-                                 hipStream_t s) {
+                                 const SceneDev &sc, uint32_t pbase, int ng, int window_mode,
+                                 unsigned long long *masks, hipStream_t s) {
   // 64 entries per wave and step; at most 8192 blocks, each looping over its share
-  const dim3 grid((unsigned)std::min<size_t>(((size_t)npairs + 255) / 256, 8192)), block(256);
+  const dim3 grid((unsigned)std::min<size_t>(((size_t)ng + 255) / 256, 8192)), block(256);
   hipLaunchKernelGGL((k_runs<P, MODE, COMPACT>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint,
-                     ws.dform, (const float4 *)ws.cmean, ws.cform, ws.lbox, poses_dev, ntiles, sc, npairs,
+                     ws.dform, (const float4 *)ws.cmean, ws.cform, ws.lbox, poses_dev, ntiles, sc, pbase, ng,
                      window_mode, ws.win, ws.woff, masks, ws.run_cnt, ws.runs, ws.counters);
   return hipGetLastError();
 }
 
 template <int P>
 static hipError_t launch_runs_p(const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
-                                const SceneDev &sc, int npairs, int window_mode, int mode, unsigned long long *masks,
-                                bool compact, hipStream_t s) {
+                                const SceneDev &sc, uint32_t pbase, int ng, int window_mode, int mode,
+                                unsigned long long *masks, bool compact, hipStream_t s) {
   if (mode == kRunsWindows)
-    return launch_runs_pm<P, kRunsWindows, false>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, masks, s);
+    return launch_runs_pm<P, kRunsWindows, false>(ws, lists, poses_dev, ntiles, sc, pbase, ng, window_mode, masks, s);
   if (compact) {
     if (mode == kRunsCount) {
-      const dim3 grid((unsigned)std::min<size_t>(((size_t)npairs + 255) / 256, 8192)), block(256);
+      const dim3 grid((unsigned)std::min<size_t>(((size_t)ng + 255) / 256, 8192)), block(256);
       hipLaunchKernelGGL(k_runs_count_lanes<P>, grid, block, 0, s, ws.pair_key, ws.tile_range, lists,
-                         (const float4 *)ws.cmean, ws.cform, poses_dev, ntiles, sc, npairs, ws.win, ws.woff, masks,
+                         (const float4 *)ws.cmean, ws.cform, poses_dev, ntiles, sc, pbase, ng, ws.win, ws.woff, masks,
                          ws.run_cnt);
       return hipGetLastError();
     }
-    return launch_runs_pm<P, kRunsEmit, true>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, masks, s);
+    return launch_runs_pm<P, kRunsEmit, true>(ws, lists, poses_dev, ntiles, sc, pbase, ng, window_mode, masks, s);
   }
   if (mode == kRunsCount)
-    return launch_runs_pm<P, kRunsCount, false>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, masks, s);
-  return launch_runs_pm<P, kRunsEmit, false>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, masks, s);
+    return launch_runs_pm<P, kRunsCount, false>(ws, lists, poses_dev, ntiles, sc, pbase, ng, window_mode, masks, s);
+  return launch_runs_pm<P, kRunsEmit, false>(ws, lists, poses_dev, ntiles, sc, pbase, ng, window_mode, masks, s);
 }
 
 template <int P>
 static hipError_t launch_ind_gather_p(const Workspace &ws, const uint32_t *lists, const SceneDev &sc, int ntiles,
-                                      int npairs, hipStream_t s) {
-  hipLaunchKernelGGL(k_ind_gather<P>, dim3((unsigned)(((size_t)npairs + 255) / 256)), dim3(256), 0, s, ws.pair_key,
-                     lists, ws.dform, sc, ntiles, npairs, (float4 *)ws.cmean, ws.cform);
+                                      uint32_t pbase, int ng, hipStream_t s) {
+  hipLaunchKernelGGL(k_ind_gather<P>, dim3((unsigned)(((size_t)ng + 255) / 256)), dim3(256), 0, s, ws.pair_key,
+                     lists, ws.dform, sc, ntiles, pbase, ng, (float4 *)ws.cmean, ws.cform);
   return hipGetLastError();
 }
 
 hipError_t launch_ind_gather(int P, const Workspace &ws, const uint32_t *lists, const SceneDev &sc, int ntiles,
-                             int npairs, hipStream_t s) {
-  if (npairs <= 0) return hipSuccess;
+                             uint32_t pbase, int ng, hipStream_t s) {
+  if (ng <= 0) return hipSuccess;
   switch (P) {
-    case 0: return launch_ind_gather_p<0>(ws, lists, sc, ntiles, npairs, s);
-    case 1: return launch_ind_gather_p<1>(ws, lists, sc, ntiles, npairs, s);
-    case 2: return launch_ind_gather_p<2>(ws, lists, sc, ntiles, npairs, s);
-    case 3: return launch_ind_gather_p<3>(ws, lists, sc, ntiles, npairs, s);
-    case 4: return launch_ind_gather_p<4>(ws, lists, sc, ntiles, npairs, s);
-    case 5: return launch_ind_gather_p<5>(ws, lists, sc, ntiles, npairs, s);
-    case 6: return launch_ind_gather_p<6>(ws, lists, sc, ntiles, npairs, s);
+    case 0: return launch_ind_gather_p<0>(ws, lists, sc, ntiles, pbase, ng, s);
+    case 1: return launch_ind_gather_p<1>(ws, lists, sc, ntiles, pbase, ng, s);
+    case 2: return launch_ind_gather_p<2>(ws, lists, sc, ntiles, pbase, ng, s);
+    case 3: return launch_ind_gather_p<3>(ws, lists, sc, ntiles, pbase, ng, s);
+    case 4: return launch_ind_gather_p<4>(ws, lists, sc, ntiles, pbase, ng, s);
+    case 5: return launch_ind_gather_p<5>(ws, lists, sc, ntiles, pbase, ng, s);
+    case 6: return launch_ind_gather_p<6>(ws, lists, sc, ntiles, pbase, ng, s);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
-                       const SceneDev &sc, int npairs, int window_mode, int mode, unsigned long long *masks,
-                       bool compact, hipStream_t s) {
-  if (npairs <= 0) return hipSuccess;
+                       const SceneDev &sc, uint32_t pbase, int ng, int window_mode, int mode,
+                       unsigned long long *masks, bool compact, hipStream_t s) {
+  if (ng <= 0) return hipSuccess;
   switch (P) {
-    case 0: return launch_runs_p<0>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, compact, s);
-    case 1: return launch_runs_p<1>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, compact, s);
-    case 2: return launch_runs_p<2>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, compact, s);
-    case 3: return launch_runs_p<3>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, compact, s);
-    case 4: return launch_runs_p<4>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, compact, s);
-    case 5: return launch_runs_p<5>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, compact, s);
-    case 6: return launch_runs_p<6>(ws, lists, poses_dev, ntiles, sc, npairs, window_mode, mode, masks, compact, s);
+#define AR_RUNS_CASE(PP) \
+    case PP: return launch_runs_p<PP>(ws, lists, poses_dev, ntiles, sc, pbase, ng, window_mode, mode, masks, compact, s);
+    AR_RUNS_CASE(0) AR_RUNS_CASE(1) AR_RUNS_CASE(2) AR_RUNS_CASE(3) AR_RUNS_CASE(4) AR_RUNS_CASE(5) AR_RUNS_CASE(6)
+#undef AR_RUNS_CASE
   }
   return hipErrorInvalidValue;
 }
@@ -1024,11 +1028,11 @@ static hipError_t launch_rot_p(const Workspace &ws, const uint32_t *lists, const
       hipLaunchKernelGGL(k_rot_absolute, grid, blk, 0, s, ws.tile_range, ws.seg_off, ws.seg_tile, c.L, c.seg0, c.nseg,
                          c.pos0, (const double2 *)ws.segsum, preL, preH);
       hipLaunchKernelGGL((k_rot_blend<P, true>), grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off,
-                         ws.seg_tile, c.L, c.seg0, c.nseg, c.pos0, ws.run_cnt, ws.runs, prm, preL, preH,
-                         (const double2 *)ws.segsum, ws.part, ws.counters);
+                         ws.seg_tile, c.L, c.seg0, c.nseg, c.pos0, c.gbase, ws.run_cnt, ws.runs, prm, preL,
+                         preH, (const double2 *)ws.segsum, ws.part, ws.counters);
     } else {
       hipLaunchKernelGGL((k_rot_blend<P, false>), grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off,
-                         ws.seg_tile, c.L, c.seg0, c.nseg, c.pos0, ws.run_cnt, ws.runs, prm, preL, preH,
+                         ws.seg_tile, c.L, c.seg0, c.nseg, c.pos0, c.gbase, ws.run_cnt, ws.runs, prm, preL, preH,
                          (const double2 *)ws.segsum, ws.part, ws.counters);
     }
   }

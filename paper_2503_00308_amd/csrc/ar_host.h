@@ -30,8 +30,9 @@ int pose_vars(const ar_pose_box *b, bool *rotates);
 int validate_box(const ar_pose_box *b);
 int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *op, Params &prm);
 int check_outputs(const float *lo, const float *hi);
-// estimated device bytes of a launch of ncells cells
-size_t query_bytes(const ar_scene *sc, const Params &prm, int P, bool rotates, int ncells, double pairs_per_item);
+// estimated device bytes of a launch of ncells cells at the list density d (of an earlier
+// launch on the scene; zeros: a first guess)
+size_t query_bytes(const ar_scene *sc, const Params &prm, int P, bool rotates, int ncells, const Density &d);
 // cells per launch of a batch (memory-bounded)
 int batch_cells(const ar_scene *sc, const Workspace &ws, const Params &prm, int P, bool rotates,
                 const ar_options *opts);

@@ -101,6 +101,8 @@ struct Params {
   int32_t ind_window, chunk;
   int32_t prefix_entries;   // rotation path: list entries per pixel-loop launch
   int32_t nominal_order;    // rotation path: order lists by the nominal depth (else by the upper bound)
+  int32_t abs_sums, ind_copy, ind_masks;   // rotation path layouts: 0 automatic, 1 on, 2 off
+  int32_t group_entries;    // rotation path: list entries per group of the Ind passes (0: default)
 };
 
 struct SceneDev {
@@ -111,12 +113,22 @@ struct SceneDev {
   float *rgb;    // [3][n]
 };
 
+// List density of a launch, used to estimate the workspace of the next one on the same
+// scene: list entries per Gaussian item and, on the rotation path, Ind runs and stored
+// mask words per list entry and whether the compact copy was used (largest over groups).
+struct Density {
+  double pairs_per_item = 0.0;
+  double runs_per_entry = 0.0;
+  double mask_words_per_entry = 0.0;
+  bool compact = false;
+};
+
 // Device workspace (grown on demand, owned by a scene handle).
 struct Workspace {
   size_t cap_n = 0, cap_pairs = 0, cap_tiles = 0, cap_scratch = 0, cap_rec = 0, cap_cells = 0;
   size_t bytes = 0;                              // device bytes held by the buffers below
   std::unordered_map<void *, size_t> sizes;      // allocation -> bytes
-  double pairs_per_item = 0.0;   // list entries per Gaussian item of the last launch
+  Density density;               // of the last launch
   PoseForms *pose_dev = nullptr;   // [cells] pose forms of a launch
   PoseForms *pose_host = nullptr;  // [cells] pinned staging
   double *rec = nullptr;       // [n][stride]
@@ -191,6 +203,9 @@ hipError_t radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, ui
 hipError_t radix_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, uint32_t *vals_alt, int n,
                           int begin_bit, int end_bit, Workspace &ws, hipStream_t s, bool *result_in_alt);
 hipError_t exclusive_scan_u32(uint32_t *data, int n, Workspace &ws, hipStream_t s);
+// *total (zeroed by the caller) += sum of data[0 .. n) in 64 bits (the true total of counts
+// whose 32-bit scan may wrap)
+hipError_t sum_u32_u64(const uint32_t *data, size_t n, unsigned long long *total, hipStream_t s);
 // keys[i] = items[i] / n_cell (cell of a global item)
 hipError_t launch_cell_keys(const uint32_t *items, int n_total, int n_cell, uint32_t *keys, hipStream_t s);
 hipError_t ensure_hist(Workspace &ws, size_t n_entries);
@@ -245,18 +260,22 @@ hipError_t launch_list_box(const Workspace &ws, const uint32_t *lists, const Pos
 constexpr int kRunsWindows = 0;   // the window [ps, qe) of each entry and its mask words
 constexpr int kRunsCount = 1;     // Ind tests; run counts; masks of the long windows stored
 constexpr int kRunsEmit = 2;      // runs written (long windows from the stored masks)
-// one pass of the Ind runs kernel; masks (the long windows' Ind masks) may be null
+// one pass of the Ind runs kernel over the list entries pbase .. pbase + ng - 1 (a group
+// of whole lists; win, woff, run_cnt, runs and the compact copy are indexed relative to
+// pbase); masks (the long windows' Ind masks) may be null
 hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
-                       const SceneDev &sc, int npairs, int window_mode, int mode, unsigned long long *masks,
-                       bool compact, hipStream_t s);
-// the compact copy (cmean, cform) of the items' means and depth forms by list position
+                       const SceneDev &sc, uint32_t pbase, int ng, int window_mode, int mode,
+                       unsigned long long *masks, bool compact, hipStream_t s);
+// the compact copy (cmean, cform) of the items' means and depth forms by list position,
+// for the entries pbase .. pbase + ng - 1
 hipError_t launch_ind_gather(int P, const Workspace &ws, const uint32_t *lists, const SceneDev &sc, int ntiles,
-                             int npairs, hipStream_t s);
+                             uint32_t pbase, int ng, hipStream_t s);
 // one launch of the rotation pixel loop: lists list0 .. list0 + nl - 1 with entries from
 // position pos0, their segments seg0 .. seg0 + nseg - 1 of L positions
 struct RotChunk {
   int list0, nl, seg0, nseg, L;
   uint32_t pos0;
+  uint32_t gbase;  // first list position of the list group whose run counts and runs are held
   bool absolute;   // add the segment offsets to the running sums in a pass of their own
 };
 hipError_t launch_raster_general(int P, const Workspace &ws, const uint32_t *lists, const RotChunk &c,

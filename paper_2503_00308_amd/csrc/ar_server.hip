@@ -32,6 +32,7 @@ struct Query {
   int P = 0;
   bool rotates = false;
   size_t est = 0;              // estimated workspace bytes
+  size_t ws_bytes = 0;         // workspace bytes held by its slot when it finished
   float *lo = nullptr, *hi = nullptr;
   Clock::time_point t_submit, t_start, t_end;
   int status = AR_PENDING;
@@ -56,7 +57,8 @@ struct ar_server {
   std::deque<std::shared_ptr<Query>> queue;
   std::map<int64_t, std::shared_ptr<Query>> records;
   std::vector<const ar_scene *> scenes;
-  std::vector<double> pairs_per_item;   // per scene, from its last query
+  std::vector<ar::Density> density;   // per scene, from its last query (rotating and not)
+  std::vector<ar::Density> density_rot;
   std::vector<std::unique_ptr<Slot>> slots;
   std::vector<double> latencies;
   int device = 0;
@@ -118,12 +120,12 @@ struct ar_server {
           ++completed;
           latencies.push_back(ms_between(q->t_submit, now));
           pairs += st.pairs;
-          const double n = (double)std::max(1, scenes[q->scene]->dev.n);
-          pairs_per_item[q->scene] = (double)st.tile_pairs / n;
+          (q->rotates ? density_rot : density)[q->scene] = slot.ws.density;
         } else {
           ++failed;
         }
         slot.busy = false;
+        q->ws_bytes = slot.ws.bytes;
         slot.charge = slot.ws.bytes;
         peak_bytes = std::max<uint64_t>(peak_bytes, charged_except(nullptr));
         // hand memory back when the held workspaces exceed the budget
@@ -189,7 +191,8 @@ int ar_server_add_scene(ar_server *srv, const ar_scene *scene, int32_t *scene_id
   std::lock_guard<std::mutex> lk(srv->mu);
   *scene_id = (int32_t)srv->scenes.size();
   srv->scenes.push_back(scene);
-  srv->pairs_per_item.push_back(0.0);
+  srv->density.push_back(ar::Density{});
+  srv->density_rot.push_back(ar::Density{});
   return AR_OK;
 }
 
@@ -197,13 +200,14 @@ int ar_server_submit(ar_server *srv, int32_t scene_id, const ar_intrinsics *intr
                      const ar_options *opts, float *lo_rgb, float *hi_rgb, int64_t *ticket) {
   if (!srv || !ticket) return ar::fail(AR_E_INVALID, "server or ticket is NULL");
   const ar_scene *scene = nullptr;
-  double ppi = 0.0;
+  ar::Density dens, dens_rot;
   {
     std::lock_guard<std::mutex> lk(srv->mu);
     if (scene_id < 0 || scene_id >= (int32_t)srv->scenes.size())
       return ar::fail(AR_E_INVALID, "unknown scene id %d", scene_id);
     scene = srv->scenes[scene_id];
-    ppi = srv->pairs_per_item[scene_id];
+    dens = srv->density[scene_id];
+    dens_rot = srv->density_rot[scene_id];
   }
   int rc = ar::validate_box(box);
   if (rc) return rc;
@@ -218,7 +222,7 @@ int ar_server_submit(ar_server *srv, int32_t scene_id, const ar_intrinsics *intr
   q->box = *box;
   q->lo = lo_rgb;
   q->hi = hi_rgb;
-  q->est = ar::query_bytes(scene, q->prm, q->P, q->rotates, 1, ppi);
+  q->est = ar::query_bytes(scene, q->prm, q->P, q->rotates, 1, q->rotates ? dens_rot : dens);
   q->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> lk(srv->mu);
@@ -252,6 +256,8 @@ int ar_server_wait(ar_server *srv, int64_t ticket, int32_t block, ar_query_resul
   out->queue_ms = ms_between(q->t_submit, q->t_start);
   out->latency_ms = ms_between(q->t_submit, q->t_end);
   out->stats = q->stats;
+  out->est_bytes = q->est;
+  out->ws_bytes = q->ws_bytes;
   strncpy(out->error, q->error.c_str(), sizeof(out->error) - 1);
   srv->records.erase(ticket);
   if (q->status != AR_OK) return ar::fail(q->status, "%s", q->error.c_str());

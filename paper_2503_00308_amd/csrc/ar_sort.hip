@@ -8,6 +8,8 @@
 // ballots, then across the block's waves through LDS, so equal keys keep input order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ar_internal.h"
 
 namespace ar {
@@ -176,6 +178,24 @@ hipError_t exclusive_scan_u32(uint32_t *data, int n, Workspace &ws, hipStream_t 
   hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(256), 0, s, data, n, ws.scan_tmp);
   hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kScanThreads), 0, s, ws.scan_tmp, nb);
   hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, s, data, n, ws.scan_tmp);
+  return hipGetLastError();
+}
+
+// 64-bit total of n uint32 counts: a grid-stride sum per thread, a wave reduction and
+// one atomic per wave.
+__global__ __launch_bounds__(256) void k_sum_u32_u64(const uint32_t *__restrict__ data, size_t n,
+                                                     unsigned long long *__restrict__ total) {
+  unsigned long long s = 0;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) s += data[i];
+  for (int off = 32; off > 0; off >>= 1) s += (unsigned long long)__shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0 && s) atomicAdd(total, s);
+}
+
+hipError_t sum_u32_u64(const uint32_t *data, size_t n, unsigned long long *total, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 1023) / 1024, 2048);
+  hipLaunchKernelGGL(k_sum_u32_u64, dim3(blocks), dim3(256), 0, s, data, n, total);
   return hipGetLastError();
 }
 

@@ -141,6 +141,29 @@ def test_server_heaviest_query_full_size_sampled_tiles():
         assert dlo <= 1e-5 and dhi <= 1e-5
 
 
+@pytest.mark.parametrize("opts", [None, {"ind_copy": 1, "ind_window": 2}, {"group_entries": 5000}])
+def test_server_admission_estimate_covers_the_workspace(opts):
+    """The admission estimate of a query (at the list density of the scene's last query
+    of the same kind) is at least the workspace its slot holds afterwards, for rotation
+    boxes (Ind runs, windows, stored masks, the compact copy) and translation boxes."""
+    api = _api()
+    scene = synth.box_surface_scene(20000, n_boxes=12, seed=26)
+    h = api.Scene(scene)
+    jobs = [(synth.intrinsics(96), synth.camera6_box(dt=0.02, drot=np.deg2rad(0.5))),
+            (synth.intrinsics(96), synth.camera6_box(dt=(0.05, 0.02, 0.01)))]
+    for intr, box in jobs:
+        srv = api.Server(slots=1)
+        sid = srv.add_scene(h)
+        first = srv.wait(srv.submit(sid, intr, box, opts))[2]
+        second = srv.wait(srv.submit(sid, intr, box, opts))[2]
+        srv.close()
+        print(f"[admission {opts}] P {second['stats']['P']} runs {second['stats']['runs']}: first est "
+              f"{first['est_bytes'] / 2**20:.1f} MiB held {first['ws_bytes'] / 2**20:.1f} MiB; second est "
+              f"{second['est_bytes'] / 2**20:.1f} MiB held {second['ws_bytes'] / 2**20:.1f} MiB", flush=True)
+        assert 0 < second["ws_bytes"] <= second["est_bytes"]
+    h.close()
+
+
 def test_server_rejects_bad_requests():
     api = _api()
     h = api.Scene(synth.random_scene(50, seed=25))
