@@ -206,6 +206,27 @@ def exp(x: LF, xlo, xhi) -> LF:
     return LF(lo, up)
 
 
+def recip(x: LF, tangent: str = "lo") -> LF:
+    """Div (Table "Bounds for operations Exp, Div and Ind"): 1/x for x in [xlo, xhi], xlo > 0.
+
+    1/x is convex there, so any tangent lies below and the chord above:
+      lower: -(x - t)/t^2 + 1/t, tangent at t = xlo as the table prints it (tangent="lo"),
+             or at t = xhi (tangent="hi", an alternative the table does not give);
+      upper: -(x - xlo)/(xlo xhi) + 1/xlo (the chord).
+    Entries with xlo <= 0 are not bounded: their forms are NaN (callers check).
+    """
+    xlo, xhi = x.bounds()
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t = xlo if tangent == "lo" else xhi
+        ok = xlo > 0
+        t = np.where(ok, t, np.nan)
+        lo = _scale_lower(x, -1.0 / (t * t))
+        up = _scale_upper(x, -1.0 / (np.where(ok, xlo, np.nan) * xhi))
+        lo[..., -1] += 2.0 / t
+        up[..., -1] += 1.0 / xlo + 1.0 / xhi
+    return LF(lo, up)
+
+
 def trig(theta: LF, which: str) -> LF:
     """sin or cos of an angle theta = c + sum_k r_k e_k that is exactly affine in e.
 

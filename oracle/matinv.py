@@ -72,6 +72,27 @@ def matrix_inv(X: lf.LF, k: int = 8):
     return lf.LF(lo, up), ok, {"X0": X0, "nbar": nbar, "eps": eps, "det": det}
 
 
+def adjugate_inv(X: lf.LF, tangent: str = "lo"):
+    """The direct inverse of a 2x2 set of matrices that Example 'matinv-vs-direct' of
+    Sec. 3.1 compares MatrixInv with: adj(X) times Div(det X), every step a
+    linear-relational operation (det = Mul(X00, X11) - Mul(X01, X10); Div as in Table
+    "Bounds for operations Exp, Div and Ind"; the four entries Mul(adj_ij, 1/det)).
+
+    Returns (LF of quantity shape (..., 2, 2), ok mask): ok is False where the determinant
+    is not provably positive (Div needs x > 0), and those entries are zero.
+    """
+    det = lf.sub(lf.mul(X[..., 0, 0], X[..., 1, 1]), lf.mul(X[..., 0, 1], X[..., 1, 0]))
+    rdet = lf.recip(det, tangent)
+    dlo, _ = det.bounds()
+    ok = dlo > 0
+    adj = lf.stack([lf.stack([X[..., 1, 1], lf.neg(X[..., 0, 1])], axis=-1),
+                    lf.stack([lf.neg(X[..., 1, 0]), X[..., 0, 0]], axis=-1)], axis=-2)
+    r = lf.LF(np.where(ok[..., None], rdet.lo, 0.0), np.where(ok[..., None], rdet.up, 0.0))
+    out = lf.mul(adj, lf.broadcast(r.expand(-1).expand(-1), adj.shape))
+    okm = ok[..., None, None, None]
+    return lf.LF(np.where(okm, out.lo, 0.0), np.where(okm, out.up, 0.0)), ok
+
+
 def interval_matrix(lo, hi, symmetric=False):
     """A constant interval matrix as linear forms: every free entry is its own variable.
 

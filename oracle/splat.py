@@ -38,10 +38,13 @@ from __future__ import annotations
 import numpy as np
 
 from . import lf
-from .matinv import matrix_inv
+from .matinv import adjugate_inv, matrix_inv
 from .pose import pose_forms
 
-DEFAULTS = {"taylor_k": 8, "z_near": 0.01, "cull_budget": 1e-7, "tile": 16}
+DEFAULTS = {"taylor_k": 8, "z_near": 0.01, "cull_budget": 1e-7, "tile": 16,
+            # precision baselines of Sec. 3.1 / 3.2 (Examples 'matinv-vs-direct' and '3g-scene'):
+            # "inverse": "matrixinv" | "adjugate"; "blend": "ind" | "ind_interval" | "sort"
+            "inverse": "matrixinv", "blend": "ind"}
 
 
 def _f32_down(x):
@@ -103,7 +106,13 @@ def gaussian_forms(scene, intr, box, opts=None):
     X11 = lf.sqr(Mp1).sum(-1)
     X01 = lf.mul(Mp0, Mp1).sum(-1)
     X = lf.stack([lf.stack([X00, X01], axis=1), lf.stack([X01, X11], axis=1)], axis=1)
-    conic, inv_ok, inv_info = matrix_inv(X, int(opts["taylor_k"]))
+    if opts["inverse"] == "adjugate":
+        # the direct inverse Example 'matinv-vs-direct' compares with (a failed Div, where the
+        # determinant is not provably positive, is treated as a MatrixInv failure)
+        conic, inv_ok = adjugate_inv(X)
+        inv_info = {}
+    else:
+        conic, inv_ok, inv_info = matrix_inv(X, int(opts["taylor_k"]))
     # B = Mmul(Conic, Mp), hoisted out of the pixel loop
     B = lf.mmul(conic, Mp)
 
@@ -140,6 +149,7 @@ def gaussian_forms(scene, intr, box, opts=None):
     mu32 = np.stack([_f32_down(np.where(normal, m0lo, 0.0)), _f32_up(np.where(normal, m0hi, 0.0)),
                      _f32_down(np.where(normal, m1lo, 0.0)), _f32_up(np.where(normal, m1hi, 0.0))], axis=1)
     r2_32 = _f32_up(np.where(normal, r2, -1.0))
+    mu64 = np.stack([m0lo, m0hi, m1lo, m1hi], axis=1)
 
     return {
         "P": P, "N": N, "A": A, "uc": uc, "d": d, "Mp": Mp, "X": X, "conic": conic, "B": B,
@@ -147,7 +157,7 @@ def gaussian_forms(scene, intr, box, opts=None):
         "o": o, "rgb": np.asarray(scene["rgb"], dtype=np.float64), "uw": uw,
         "dropped": dropped, "straddle": straddle, "wild": wild, "normal": normal,
         "fallback": fallback, "inv_ok": inv_ok, "inv_info": inv_info,
-        "lam": np.where(normal, lam, np.inf), "mu32": mu32, "r2_32": r2_32,
+        "lam": np.where(normal, lam, np.inf), "mu32": mu32, "r2_32": r2_32, "mu64": mu64,
         "eps_cull": eps_cull, "E": float(opts["cull_budget"]) * (1.0 + 2.0 ** -10),
         "opts": opts,
     }
@@ -290,6 +300,66 @@ def blend(al, au, alo_f, aup_f, c, ind, E):
     return lo, hi
 
 
+def blend_interval(al, au, c, ind, E):
+    """BlendInd with the interval colour sum only (the relational sum of blend() left out):
+    the T step as in blend(), pc in [sum c T_lo a_lo, sum c T_hi a_hi].  A precision
+    baseline for the comparison with the abstract BlendSort."""
+    n, m = al.shape
+    T_hi = np.empty((n, m))
+    T_lo = np.empty((n, m))
+    for i in range(n):
+        T_hi[i] = np.prod(1.0 - al[ind[i] == 1], axis=0)
+        T_lo[i] = np.prod(1.0 - au[ind[i] != 0], axis=0)
+    lo = np.einsum("nm,nc->mc", T_lo * al, c) - E
+    hi = np.einsum("nm,nc->mc", T_hi * au, c) + E
+    return lo, hi
+
+
+def blend_sort_abstract(al, au, c, dlo, dhi, E):
+    """Abstract BlendSort (Alg. BlendSort with an abstract Sort): the precision baseline of
+    Sec. 3.2 that BlendInd replaces (Example '3g-scene').
+
+    Sort is not linearly over-approximable (Sec. 2.1); an abstract sort sees each depth as
+    the set of its values, the interval [dlo_i, dhi_i], and not the relation between two
+    depths that Ind(d_i - d_j) uses.  Gaussian i can then only sit at sorted positions k
+    with r_lo[i] <= k <= r_hi[i]: r_lo[i] counts the Gaussians surely strictly in front of
+    it (dhi_j < dlo_i), r_hi[i] those that may be sorted before it (dlo_j <= dhi_i, j != i).
+    Slot k holds one of its candidates C_k, so its alpha lies in
+    [min_{C_k} a_lo, max_{C_k} a_hi].  The Ts step is the interval product over the slots in
+    front:
+        Gaussian i at slot k:  prod_{j<k} (1 - max a_hi of slot j)
+                               <= T_i <=  prod_{j<r_lo[i]} (1 - min a_lo of slot j)
+    (the strictly-in-front Gaussians fill the first slots, at least r_lo[i] of them; ties
+    share a transmittance, so the upper product stops at r_lo[i], not at k).  pc step:
+        lo = sum_k prod_{j<k}(1 - a_hi slot j) * min_{i in C_k} a_lo[i] c_i
+        hi = sum_k max_{i in C_k} prod_{j<r_lo[i]}(1 - a_lo slot j) a_hi[i] c_i
+    A Gaussian can be counted at several slots, the over-counting Sec. 3.2 attributes to
+    index-based accumulation.  al, au: (n, m); c: (n, 3); dlo, dhi: (n,).
+    Returns lo, hi (m, 3), widened by E, not clamped.
+    """
+    n, m = al.shape
+    c = np.asarray(c, dtype=np.float64)
+    if n == 0:
+        return np.zeros((m, 3)) - E, np.zeros((m, 3)) + E
+    dlo = np.asarray(dlo, dtype=np.float64)
+    dhi = np.asarray(dhi, dtype=np.float64)
+    r_lo = (dhi[None, :] < dlo[:, None]).sum(axis=1)
+    r_hi = (dlo[None, :] <= dhi[:, None]).sum(axis=1) - 1
+    cand = [(r_lo <= k) & (k <= r_hi) for k in range(n)]
+    al_slot = np.stack([al[ck].min(axis=0) for ck in cand])      # (n slots, m)
+    au_slot = np.stack([au[ck].max(axis=0) for ck in cand])
+    T_lo_slot = np.cumprod(np.vstack([np.ones((1, m)), 1.0 - au_slot]), axis=0)[:n]
+    T_hi_rank = np.cumprod(np.vstack([np.ones((1, m)), 1.0 - al_slot]), axis=0)   # row r: r slots
+    term_hi = T_hi_rank[r_lo][:, :, None] * au[:, :, None] * c[:, None, :]        # (n, m, 3)
+    term_lo = al[:, :, None] * c[:, None, :]
+    lo = np.zeros((m, 3))
+    hi = np.zeros((m, 3))
+    for k in range(n):
+        lo += T_lo_slot[k][:, None] * term_lo[cand[k]].min(axis=0)
+        hi += term_hi[cand[k]].max(axis=0)
+    return lo - E, hi + E
+
+
 def blend_tile(rec, idx, ux, uy, ux32, uy32):
     """BlendInd with interval transmittances and the relational colour sum for one pixel set.
 
@@ -340,7 +410,14 @@ def blend_tile(rec, idx, ux, uy, ux32, uy32):
     aup_f = np.where(keep[..., None], aup_f, 0.0)
 
     ind, border = ind_matrix(rec, idx)
-    lo, hi = blend(al, au, alo_f, aup_f, rec["rgb"][idx], ind, rec["E"])
+    mode = rec["opts"]["blend"]
+    if mode == "sort":
+        dlo, dhi = rec["d"][idx].bounds()
+        lo, hi = blend_sort_abstract(al, au, rec["rgb"][idx], dlo, dhi, rec["E"])
+    elif mode == "ind_interval":
+        lo, hi = blend_interval(al, au, rec["rgb"][idx], ind, rec["E"])
+    else:
+        lo, hi = blend(al, au, alo_f, aup_f, rec["rgb"][idx], ind, rec["E"])
     bflag = np.zeros(m, bool)
     if border.any():
         bi, bj = np.nonzero(border)
