@@ -95,6 +95,16 @@ def variable(centre, radius, index, P):
     return LF(f, f.copy())
 
 
+def extend(x: LF, extra: int) -> LF:
+    """The same forms over extra further variables (zero coefficients), placed after the
+    existing ones and before the constant."""
+    if extra == 0:
+        return x
+    z = np.zeros(x.lo.shape[:-1] + (extra,))
+    return LF(np.concatenate([x.lo[..., :-1], z, x.lo[..., -1:]], axis=-1),
+              np.concatenate([x.up[..., :-1], z, x.up[..., -1:]], axis=-1))
+
+
 def broadcast(x: LF, shape) -> LF:
     """Broadcast the quantity shape of x to `shape` (copies)."""
     shape = tuple(shape) + (x.lo.shape[-1],)

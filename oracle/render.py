@@ -93,6 +93,28 @@ def blend_ind(a, c, d):
     return np.einsum("np,nc->pc", T * a, np.asarray(c, dtype=np.float64))
 
 
+def instantiate(scene, s=None, t_rgb=0.0, t_o=1.0):
+    """One concrete scene of a set of scenes (Sec. 4.6; keys as splat.scene_set): means moved
+    by the scene variables s, colours rgb + t_rgb (rgb_hi - rgb), opacities
+    opacity_lo + t_o (opacity - opacity_lo); t_rgb, t_o in [0, 1], scalars or per Gaussian."""
+    mean = np.asarray(scene["mean"], dtype=np.float64).copy()
+    if s is not None and len(np.atleast_1d(s)):
+        mvar = np.asarray(scene["mean_var"])
+        mdir = np.asarray(scene["mean_dir"], dtype=np.float64)
+        s = np.asarray(s, dtype=np.float64)
+        rows = mvar >= 0
+        mean[rows] += mdir[rows] * s[mvar[rows]][:, None]
+    rgb = np.asarray(scene["rgb"], dtype=np.float64)
+    rgb_hi = np.asarray(scene.get("rgb_hi", rgb), dtype=np.float64)
+    o = np.asarray(scene["opacity"], dtype=np.float64)
+    o_lo = np.asarray(scene.get("opacity_lo", o), dtype=np.float64)
+    t_rgb = np.asarray(t_rgb, dtype=np.float64)
+    t_o = np.asarray(t_o, dtype=np.float64)
+    return {"mean": mean, "cov_factor": scene["cov_factor"],
+            "rgb": rgb + (t_rgb[..., None] if t_rgb.ndim else t_rgb) * (rgb_hi - rgb),
+            "opacity": o_lo + t_o * (o - o_lo)}
+
+
 def render(scene, intr, box, p, z_near=0.01, chunk=4096):
     """Concrete image (H, W, 3) at pose p of the box (FP64)."""
     R, t = concrete_camera(box, p)

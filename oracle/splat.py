@@ -28,6 +28,11 @@ Readings where the paper is silent (each one is also listed in the design notes)
 * near plane: d_hi <= z_near drops the Gaussian (the concrete renderer gives it
   a = 0); d_lo <= z_near < d_hi gives a in [0, o] at every pixel;
 * MatrixInv assertion failure: a in [0, o exp(-dist^2 / (2 lam))] (the footprint bound);
+* sets of scenes (Sec. 4.6, see scene_set): colours and opacities given as per-Gaussian
+  intervals enter the pc step as c_lo in the lower and c_hi in the upper sums (pc does not
+  decrease in any colour, since T and a are non-negative) and the a step as o_lo for the
+  lower and o for the upper alpha; means moved along a direction by a scene variable
+  become linear forms in that variable, an extra variable after the pose variables;
 * per-pixel pruning: Gaussian i is removed from pixel u when o_i exp(-dist(u, mu_box)^2
   / (2 lam_i)) < eps with eps = cull_budget / N, decided in float32 on float32 inputs
   rounded outward; removing Gaussians whose alpha is at most eps moves any concrete
@@ -66,18 +71,58 @@ def options(opts=None):
     return o
 
 
+def scene_set(scene):
+    """The set of scenes a scene dict stands for (Sec. 4.6, sets of colours, means and opacities).
+
+    Optional keys beside the plain scene's:
+      "rgb_hi" (n, 3)      colour upper bounds ("rgb" is then the lower bound);
+      "opacity_lo" (n,)    opacity lower bounds ("opacity" is then the upper bound);
+      "set_lo", "set_hi"   bounds of the scene variables s_0 .. s_{k-1};
+      "mean_var" (n,)      the variable that moves Gaussian i's mean (-1: none) and
+      "mean_dir" (n, 3)    its direction: uw_i(s) = uw_i + mean_dir_i s_{mean_var[i]}.
+    Returns (rgb_lo, rgb_hi, o_lo, o_hi, nvar, centre, radius, mean_var, mean_dir).
+    """
+    rgb = np.asarray(scene["rgb"], dtype=np.float64)
+    o = np.asarray(scene["opacity"], dtype=np.float64)
+    rgb_hi = np.asarray(scene.get("rgb_hi", rgb), dtype=np.float64)
+    o_lo = np.asarray(scene.get("opacity_lo", o), dtype=np.float64)
+    lo = np.asarray(scene.get("set_lo", []), dtype=np.float64).reshape(-1)
+    hi = np.asarray(scene.get("set_hi", []), dtype=np.float64).reshape(-1)
+    n = len(o)
+    mvar = np.asarray(scene.get("mean_var", np.full(n, -1)), dtype=np.int64)
+    mdir = np.asarray(scene.get("mean_dir", np.zeros((n, 3))), dtype=np.float64)
+    return rgb, rgb_hi, o_lo, o, len(lo), 0.5 * (lo + hi), 0.5 * (hi - lo), mvar, mdir
+
+
 def gaussian_forms(scene, intr, box, opts=None):
-    """Per-Gaussian part of AbstractSplat (Alg. GaussianSplat, Steps 1-2 and the Conic of Step 3, plus Conic*Mp)."""
+    """Per-Gaussian part of AbstractSplat (Alg. GaussianSplat, Steps 1-2 and the Conic of Step 3, plus Conic*Mp).
+
+    A set of scenes (scene_set) adds its variables after the pose variables: the forms are
+    over e in [-1, 1]^(P_pose + k), and a moved mean uw_i + mean_dir_i s is the linear form
+    uw_i + mean_dir_i (centre + radius e_(P_pose + v)) in Step 1 (Sec. 4.6).
+    """
     opts = options(opts)
-    A, tau, beta, P = pose_forms(box)
+    A, tau, beta, Pp = pose_forms(box)
     uw = np.asarray(scene["mean"], dtype=np.float64)
     Mw = np.asarray(scene["cov_factor"], dtype=np.float64)
-    o = np.asarray(scene["opacity"], dtype=np.float64)
+    rgb_lo, rgb_hi, o_lo, o, nvar, s_cen, s_rad, mvar, mdir = scene_set(scene)
     N = len(uw)
     fx, fy = float(intr["fx"]), float(intr["fy"])
+    P = Pp + nvar
+    moving = mvar >= 0
 
     # Step 1, camera coordinates: uc = Mmul(A, Add(uw, -tau)) + beta
-    y = lf.add_const(lf.neg(lf.broadcast(tau, (N, 3))), uw)
+    if nvar == 0:
+        y = lf.add_const(lf.neg(lf.broadcast(tau, (N, 3))), uw)
+    else:
+        A, tau, beta = lf.extend(A, nvar), lf.extend(tau, nvar), lf.extend(beta, nvar)
+        uwf = lf.const(uw, P)
+        for v in range(nvar):
+            rows = mvar == v
+            for f in (uwf.lo, uwf.up):
+                f[rows, :, Pp + v] = mdir[rows] * s_rad[v]
+                f[rows, :, -1] = uw[rows] + mdir[rows] * s_cen[v]
+        y = lf.add(uwf, lf.neg(lf.broadcast(tau, (N, 3))))
     uc = lf.mmul(A, y.expand(-1))[:, :, 0]
     uc = lf.add(uc, lf.broadcast(beta, (N, 3)))
     # Step 1, camera covariance factor: Mc = Mmul(A, Mw), Mw constant
@@ -154,7 +199,7 @@ def gaussian_forms(scene, intr, box, opts=None):
     return {
         "P": P, "N": N, "A": A, "uc": uc, "d": d, "Mp": Mp, "X": X, "conic": conic, "B": B,
         "D2": D2, "DUP": lf.stack([DUP0, DUP1], axis=1), "up": lf.stack([up0, up1], axis=1),
-        "o": o, "rgb": np.asarray(scene["rgb"], dtype=np.float64), "uw": uw,
+        "o": o, "o_lo": o_lo, "rgb": rgb_lo, "rgb_hi": rgb_hi, "uw": uw, "moving": moving,
         "dropped": dropped, "straddle": straddle, "wild": wild, "normal": normal,
         "fallback": fallback, "inv_ok": inv_ok, "inv_info": inv_info,
         "lam": np.where(normal, lam, np.inf), "mu32": mu32, "r2_32": r2_32, "mu64": mu64,
@@ -211,6 +256,7 @@ def pixel_alpha(rec, idx, ux, uy):
     DUP = rec["DUP"][idx]
     B = rec["B"][idx]
     o = rec["o"][idx]
+    o_lo = rec["o_lo"][idx]
     ux = np.asarray(ux, dtype=np.float64)[None, :]
     uy = np.asarray(uy, dtype=np.float64)[None, :]
     # v = Add(Mul(d, d, u), -Mul(d, up))
@@ -224,9 +270,11 @@ def pixel_alpha(rec, idx, ux, uy):
     xlo = -0.5 * shi
     xhi = -0.5 * np.maximum(0.0, slo)
     x = lf.scale(s, -0.5)
-    # a = o Exp(x)
-    a = lf.scale(lf.exp(x, xlo, xhi), o[:, None])
-    return a, o[:, None] * np.exp(xlo), o[:, None] * np.exp(xhi)
+    # a = o Exp(x); with an opacity interval [o_lo, o] the lower form scales by o_lo
+    # (Exp's forms and values are positive where they bound alpha from the right side)
+    ex = lf.exp(x, xlo, xhi)
+    a = lf.LF(lf.scale(ex, o_lo[:, None]).lo, lf.scale(ex, o[:, None]).up)
+    return a, o_lo[:, None] * np.exp(xlo), o[:, None] * np.exp(xhi)
 
 
 IND_MARGIN = 1e-10
@@ -241,11 +289,15 @@ def ind_matrix(rec, idx, block=256):
     d_i > d_j, 0 if either upper bound proves d_i <= d_j, unknown otherwise.  The
     literal bound is used with a margin IND_MARGIN: its depth forms carry rounding
     noise, and at an exact tie (identity bound exactly 0) that noise must not decide.
-    Rows are evaluated in blocks to bound memory.
+    The identity is used only for pairs of Gaussians whose means are fixed: a mean moved
+    by a scene variable (Sec. 4.6) is not the constant uw_i of the identity, and the
+    literal bound alone decides pairs that involve one.  Rows are evaluated in blocks to
+    bound memory.
     """
     A3 = rec["A"][2]                       # z-row of A, quantity shape (3,)
     uw = rec["uw"][idx]
     d = rec["d"][idx]
+    mov = rec["moving"][idx]
     n = len(idx)
     ind = np.empty((n, n), np.int8)
     border = np.empty((n, n), bool)
@@ -256,8 +308,9 @@ def ind_matrix(rec, idx, block=256):
         lo_r, hi_r = delta.bounds()
         lit = lf.sub(d[b0:b1].expand(-1), d.expand(0))
         lo_l, hi_l = lit.bounds()
-        one = (lo_r > 0) | (lo_l > IND_MARGIN)
-        zero = (hi_r <= 0) | (hi_l <= -IND_MARGIN)
+        fixed = ~(mov[b0:b1, None] | mov[None, :])
+        one = ((lo_r > 0) & fixed) | (lo_l > IND_MARGIN)
+        zero = ((hi_r <= 0) & fixed) | (hi_l <= -IND_MARGIN)
         ind[b0:b1] = np.where(one, 1, np.where(zero, 0, 2))
         s = 1e-12 * (1.0 + np.abs(duw).sum(axis=-1))
         exact_tie = (lo_r == hi_r) & (lo_r == 0)
@@ -268,7 +321,7 @@ def ind_matrix(rec, idx, block=256):
     return ind, border
 
 
-def blend(al, au, alo_f, aup_f, c, ind, E):
+def blend(al, au, alo_f, aup_f, c, ind, E, c_hi=None):
     """BlendInd (Alg. BlendInd) on interval / linear-form alphas; colour bounds per pixel.
 
     al, au: (n, m) alpha interval per Gaussian and pixel; alo_f, aup_f: (n, m, P+1)
@@ -287,8 +340,9 @@ def blend(al, au, alo_f, aup_f, c, ind, E):
     for i in range(n):
         T_hi[i] = np.prod(one_m_al[ind[i] == 1], axis=0)
         T_lo[i] = np.prod(one_m_au[ind[i] != 0], axis=0)
+    c_hi = c if c_hi is None else c_hi                     # colour interval [c, c_hi] (Sec. 4.6)
     w_lo = T_lo[:, :, None] * c[:, None, :]               # (n, m, 3)
-    w_hi = T_hi[:, :, None] * c[:, None, :]
+    w_hi = T_hi[:, :, None] * c_hi[:, None, :]
     f_lo = np.einsum("nmc,nmp->mcp", w_lo, alo_f)         # (m, 3, P+1)
     f_hi = np.einsum("nmc,nmp->mcp", w_hi, aup_f)
     rel_lo = f_lo[..., -1] - np.abs(f_lo[..., :P]).sum(axis=-1)
@@ -300,7 +354,7 @@ def blend(al, au, alo_f, aup_f, c, ind, E):
     return lo, hi
 
 
-def blend_interval(al, au, c, ind, E):
+def blend_interval(al, au, c, ind, E, c_hi=None):
     """BlendInd with the interval colour sum only (the relational sum of blend() left out):
     the T step as in blend(), pc in [sum c T_lo a_lo, sum c T_hi a_hi].  A precision
     baseline for the comparison with the abstract BlendSort."""
@@ -310,12 +364,13 @@ def blend_interval(al, au, c, ind, E):
     for i in range(n):
         T_hi[i] = np.prod(1.0 - al[ind[i] == 1], axis=0)
         T_lo[i] = np.prod(1.0 - au[ind[i] != 0], axis=0)
+    c_hi = c if c_hi is None else c_hi
     lo = np.einsum("nm,nc->mc", T_lo * al, c) - E
-    hi = np.einsum("nm,nc->mc", T_hi * au, c) + E
+    hi = np.einsum("nm,nc->mc", T_hi * au, c_hi) + E
     return lo, hi
 
 
-def blend_sort_abstract(al, au, c, dlo, dhi, E):
+def blend_sort_abstract(al, au, c, dlo, dhi, E, c_hi=None):
     """Abstract BlendSort (Alg. BlendSort with an abstract Sort): the precision baseline of
     Sec. 3.2 that BlendInd replaces (Example '3g-scene').
 
@@ -339,6 +394,7 @@ def blend_sort_abstract(al, au, c, dlo, dhi, E):
     """
     n, m = al.shape
     c = np.asarray(c, dtype=np.float64)
+    c_hi = c if c_hi is None else np.asarray(c_hi, dtype=np.float64)
     if n == 0:
         return np.zeros((m, 3)) - E, np.zeros((m, 3)) + E
     dlo = np.asarray(dlo, dtype=np.float64)
@@ -350,7 +406,7 @@ def blend_sort_abstract(al, au, c, dlo, dhi, E):
     au_slot = np.stack([au[ck].max(axis=0) for ck in cand])
     T_lo_slot = np.cumprod(np.vstack([np.ones((1, m)), 1.0 - au_slot]), axis=0)[:n]
     T_hi_rank = np.cumprod(np.vstack([np.ones((1, m)), 1.0 - al_slot]), axis=0)   # row r: r slots
-    term_hi = T_hi_rank[r_lo][:, :, None] * au[:, :, None] * c[:, None, :]        # (n, m, 3)
+    term_hi = T_hi_rank[r_lo][:, :, None] * au[:, :, None] * c_hi[:, None, :]     # (n, m, 3)
     term_lo = al[:, :, None] * c[:, None, :]
     lo = np.zeros((m, 3))
     hi = np.zeros((m, 3))
@@ -411,13 +467,14 @@ def blend_tile(rec, idx, ux, uy, ux32, uy32):
 
     ind, border = ind_matrix(rec, idx)
     mode = rec["opts"]["blend"]
+    c_lo, c_hi = rec["rgb"][idx], rec["rgb_hi"][idx]
     if mode == "sort":
         dlo, dhi = rec["d"][idx].bounds()
-        lo, hi = blend_sort_abstract(al, au, rec["rgb"][idx], dlo, dhi, rec["E"])
+        lo, hi = blend_sort_abstract(al, au, c_lo, dlo, dhi, rec["E"], c_hi)
     elif mode == "ind_interval":
-        lo, hi = blend_interval(al, au, rec["rgb"][idx], ind, rec["E"])
+        lo, hi = blend_interval(al, au, c_lo, ind, rec["E"], c_hi)
     else:
-        lo, hi = blend(al, au, alo_f, aup_f, rec["rgb"][idx], ind, rec["E"])
+        lo, hi = blend(al, au, alo_f, aup_f, c_lo, ind, rec["E"], c_hi)
     bflag = np.zeros(m, bool)
     if border.any():
         bi, bj = np.nonzero(border)

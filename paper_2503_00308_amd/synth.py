@@ -198,3 +198,41 @@ def served_queries(n_queries, seed=0):
         dr = 0.5 * np.deg2rad(rng.uniform(0.0, 2.0, 3))
         out.append((s, side, camera6_box(dt=dt, drot=dr)))
     return out
+
+
+def perturbed_scene(scene, kinds=("colour",), frac=0.3, shift=0.1, seed=0):
+    """A set of scenes around `scene` in the manner of the paper's scene-perturbation
+    experiments (Sec. 4.6), applied to a spatially contiguous subset of the Gaussians (the
+    fraction `frac` with the smallest x of their means, an object of the scene):
+      "colour"  the red channel raised by up to 0.5 (upper bound min(1, r + 0.5));
+      "mean"    the subset's means moved along +y by s * shift, s in [0, 1] (one shared
+                scene variable);
+      "opacity" the opacities scaled by 0.1 and raised by up to 0.1 (interval
+                [0.1 o, min(1, 0.1 o + 0.1)]).
+    Returns a copy of the scene dict with the set keys (rgb_hi, opacity_lo, set_lo,
+    set_hi, mean_var, mean_dir) that apply."""
+    out = dict(scene)
+    n = len(scene["opacity"])
+    order = np.argsort(np.asarray(scene["mean"])[:, 0], kind="stable")
+    sub = np.zeros(n, bool)
+    sub[order[:max(1, int(round(frac * n)))]] = True
+    if "colour" in kinds:
+        rgb_hi = np.array(scene["rgb"], dtype=np.float32)
+        rgb_hi[sub, 0] = np.minimum(1.0, rgb_hi[sub, 0] + np.float32(0.5))
+        out["rgb_hi"] = rgb_hi
+    if "opacity" in kinds:
+        o = np.array(scene["opacity"], dtype=np.float32)
+        lo = o.copy()
+        hi = o.copy()
+        lo[sub] = np.float32(0.1) * o[sub]
+        hi[sub] = np.minimum(np.float32(1.0), np.float32(0.1) * o[sub] + np.float32(0.1))
+        out["opacity"] = hi
+        out["opacity_lo"] = lo
+    if "mean" in kinds:
+        out["set_lo"] = np.array([0.0])
+        out["set_hi"] = np.array([1.0])
+        out["mean_var"] = np.where(sub, 0, -1).astype(np.int32)
+        d = np.zeros((n, 3), np.float32)
+        d[sub, 1] = np.float32(shift)
+        out["mean_dir"] = d
+    return out
