@@ -8,7 +8,8 @@ share no code.
 Modules:
   lf      linear forms over the normalised pose box and their relaxations
   pose    the camera sets (CAMERA6 box, ORBIT cell) as linear forms
-  matinv  MatrixInv (Sec. 3.1) on 2x2 linear forms
+  matinv  MatrixInv (Sec. 3.1) on 2x2 linear forms, and the adjugate inverse it is compared with
+  crown   MatrixInv with its linear bounds propagated backward (CROWN-style)
   render  concrete renderer (Alg. GaussianSplat, BlendSort, BlendInd), FP64
   splat   AbstractSplat (Sec. 3.3): lower/upper images over a pose box
   refine  adaptive refinement of a pose box where MatrixInv fails (Sec. 3.1, 4.2)

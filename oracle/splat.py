@@ -43,12 +43,14 @@ from __future__ import annotations
 import numpy as np
 
 from . import lf
+from .crown import matrix_inv_backward
 from .matinv import adjugate_inv, matrix_inv
 from .pose import pose_forms
 
 DEFAULTS = {"taylor_k": 8, "z_near": 0.01, "cull_budget": 1e-7, "tile": 16,
             # precision baselines of Sec. 3.1 / 3.2 (Examples 'matinv-vs-direct' and '3g-scene'):
-            # "inverse": "matrixinv" | "adjugate"; "blend": "ind" | "ind_interval" | "sort"
+            # "inverse": "matrixinv" | "matrixinv_backward" | "adjugate";
+            # "blend": "ind" | "ind_interval" | "sort"
             "inverse": "matrixinv", "blend": "ind"}
 
 
@@ -156,6 +158,9 @@ def gaussian_forms(scene, intr, box, opts=None):
         # determinant is not provably positive, is treated as a MatrixInv failure)
         conic, inv_ok = adjugate_inv(X)
         inv_info = {}
+    elif opts["inverse"] == "matrixinv_backward":
+        # MatrixInv with its linear bounds propagated backward (CROWN-style, crown.py)
+        conic, inv_ok, inv_info = matrix_inv_backward(X, int(opts["taylor_k"]))
     else:
         conic, inv_ok, inv_info = matrix_inv(X, int(opts["taylor_k"]))
     # B = Mmul(Conic, Mp), hoisted out of the pixel loop
