@@ -199,6 +199,28 @@ int ar_render_bounds(const ar_scene *scene, const ar_intrinsics *intr, const ar_
                      ar_stats *stats);
 
 /*
+ * For callers that cannot allocate memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): ar_render_bounds without any allocation.
+ * Arguments, result (bit for bit) and errors are those of ar_render_bounds, with these
+ * limits:
+ *   - translation boxes only (no yaw / pitch / roll, ORBIT width 0); a rotation box is
+ *     rejected with AR_E_UNSUPPORTED;
+ *   - every device buffer of the render comes from one static device array of 256 MiB
+ *     per GPU, which each GPU the library runs on holds until the process ends; a render
+ *     that needs more (e.g. above about 10k Gaussians at 128x128 with a wide box) fails
+ *     with AR_E_UNSUPPORTED and a message, nothing else is touched;
+ *   - stats->raster_ms and stats->total_ms are 0 (no events are created).
+ * All calls on one GPU share that array, which keeps the last call's contents; calls on
+ * one GPU are serialised by a lock held until the call's work is complete, and work of
+ * other code that reads the array's contents after a call races with the next call.
+ * The call makes no hipMalloc, hipFree, hipHostMalloc or hipEventCreate; on its first
+ * call on a device it looks up the array's address there (hipGetSymbolAddress).
+ */
+int ar_render_bounds_noalloc(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *box,
+                             const ar_options *opts, float *lo_rgb, float *hi_rgb, void *hip_stream,
+                             ar_stats *stats);
+
+/*
  * Bounds for ncells pose boxes of one scene (the partition of a larger set of poses,
  * Sec. 4.2 "#part"); lo_rgb / hi_rgb hold ncells images back to back.  The result is
  * that of ncells calls of ar_render_bounds (bit for bit when opts->chunk is set);

@@ -92,6 +92,9 @@ SYMBOLS = {
     "ar_render_bounds": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
                                         ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.POINTER(Stats)]),
+    "ar_render_bounds_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
+                                                ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_void_p, ctypes.POINTER(Stats)]),
     "ar_render_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
                                        ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.POINTER(Stats)]),
@@ -228,6 +231,22 @@ def render_bounds(scene: Scene, intr, box, opts=None, stream=None, out=None):
                                 ctypes.c_void_p(lo.data_ptr()), ctypes.c_void_p(hi.data_ptr()),
                                 _stream_ptr(stream), ctypes.byref(st)))
     return lo, hi, st.as_dict()
+
+
+def render_bounds_noalloc(scene: Scene, intr, box, out, opts=None, stream=None):
+    """ar_render_bounds_noalloc into the caller's output tensors out = (lo, hi) (device,
+    float32 (H, W, 3)); returns the stats.  Translation boxes only; the library's static
+    scratch array holds every buffer, so the call allocates nothing."""
+    lib = load()
+    ci = intrinsics(intr)
+    lo, hi = out
+    st = Stats()
+    cb = pose_box(box)
+    co = options(opts)
+    _check(lib.ar_render_bounds_noalloc(scene.handle, ctypes.byref(ci), ctypes.byref(cb), ctypes.byref(co),
+                                        ctypes.c_void_p(lo.data_ptr()), ctypes.c_void_p(hi.data_ptr()),
+                                        _stream_ptr(stream), ctypes.byref(st)))
+    return st.as_dict()
 
 
 def render_batch(scene: Scene, intr, cells, opts=None, stream=None):

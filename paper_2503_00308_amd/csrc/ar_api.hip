@@ -165,18 +165,24 @@ static int ensure_ws(Workspace &ws, size_t n_total, size_t nlists, int P, int nc
     ws.cap_tiles = nlists;
   }
   if ((size_t)ncells > ws.cap_cells || !ws.pose_dev) {
-    if (ws.pose_host) {
+    if (ws.arena) {
+      // arena mode: pose_host is the caller's host storage for one pose box
+      if (ncells != 1 || !ws.pose_host) return fail(AR_E_UNSUPPORTED, "arena workspace holds one pose box");
+    } else if (ws.pose_host) {
       HIP_TRY(hipHostFree(ws.pose_host));
       ws.pose_host = nullptr;
     }
     HIP_TRY(grow(ws, ws.pose_dev, (size_t)ncells));
-    HIP_TRY(hipHostMalloc((void **)&ws.pose_host, (size_t)ncells * sizeof(PoseForms), hipHostMallocDefault));
+    if (!ws.arena)
+      HIP_TRY(hipHostMalloc((void **)&ws.pose_host, (size_t)ncells * sizeof(PoseForms), hipHostMallocDefault));
     ws.cap_cells = (size_t)ncells;
   }
   if (!ws.counters) {
     HIP_TRY(grow(ws, ws.counters, 16));
-    HIP_TRY(hipHostMalloc((void **)&ws.host_counters, 16 * sizeof(unsigned long long), hipHostMallocDefault));
-    for (int i = 0; i < 4; ++i) HIP_TRY(hipEventCreate(&ws.ev[i]));
+    if (!ws.arena) {
+      HIP_TRY(hipHostMalloc((void **)&ws.host_counters, 16 * sizeof(unsigned long long), hipHostMallocDefault));
+      for (int i = 0; i < 4; ++i) HIP_TRY(hipEventCreate(&ws.ev[i]));
+    }
   }
   return AR_OK;
 }
@@ -629,11 +635,11 @@ static int render_rotation(const ar_scene *sc, Workspace &ws, const Params &prm,
     if (rc) return rc;
     HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, pa, ng, prm.ind_window, kRunsEmit, masks,
                         compact, s));
-    if (first_pixel_chunk) HIP_TRY(hipEventRecord(ws.ev[1], s));
+    if (first_pixel_chunk && ws.ev[1]) HIP_TRY(hipEventRecord(ws.ev[1], s));
     first_pixel_chunk = false;
     for (const RotChunk &c : chunks) HIP_TRY(launch_raster_general(P, ws, ws.pair_val, c, prm, lo, hi, s));
   }
-  HIP_TRY(hipEventRecord(ws.ev[2], s));
+  if (ws.ev[2]) HIP_TRY(hipEventRecord(ws.ev[2], s));
   return AR_OK;
 }
 
@@ -654,7 +660,8 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
     return fail(AR_E_UNSUPPORTED, "too many cells in one launch (%zu items, %zu tile lists)", n_total, nlists);
   int rc = ensure_ws(ws, n_total, nlists, P, ncells);
   if (rc) return rc;
-  HIP_TRY(hipEventRecord(ws.ev[0], s));
+  const bool timed = ws.ev[0] != nullptr;   // no events in arena mode
+  if (timed) HIP_TRY(hipEventRecord(ws.ev[0], s));
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ws.counters, 16);
   HIP_TRY(hipGetLastError());
   // pose forms on the host; by value for a single translation box, else in device memory
@@ -722,12 +729,14 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
     rc = render_rotation(sc, ws, prm, P, npairs, nlists, ntiles, lo, hi, s, st);
     if (rc) return rc;
   }
-  HIP_TRY(hipEventRecord(ws.ev[3], s));
+  if (timed) HIP_TRY(hipEventRecord(ws.ev[3], s));
   HIP_TRY(hipMemcpyAsync(ws.host_counters, ws.counters, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   float ms_raster = 0.0f, ms_total = 0.0f;
-  HIP_TRY(hipEventElapsedTime(&ms_raster, ws.ev[1], ws.ev[2]));
-  HIP_TRY(hipEventElapsedTime(&ms_total, ws.ev[0], ws.ev[3]));
+  if (timed) {
+    HIP_TRY(hipEventElapsedTime(&ms_raster, ws.ev[1], ws.ev[2]));
+    HIP_TRY(hipEventElapsedTime(&ms_total, ws.ev[0], ws.ev[3]));
+  }
   if (st) {
     st->pairs += (int64_t)ws.host_counters[0];
     st->tile_pairs += (int64_t)npairs;

@@ -183,6 +183,13 @@ struct Workspace {
   size_t cap_host_seg = 0;
   double *segsum = nullptr;          // [segments][64][2] segment totals, then offsets
   size_t cap_segsum = 0;
+  // Arena mode (the allocation-free entry point): buffers are carved from [arena,
+  // arena + arena_cap) by a bump pointer instead of hipMalloc; nothing is freed, pinned
+  // host blocks and events are not created (pose_host / host_counters point to host
+  // storage set by the caller), and arena_overflow records a request past the end.
+  unsigned char *arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
+  bool arena_overflow = false;
 };
 
 // ---- launchers (ar_project.hip) ----
@@ -214,6 +221,17 @@ hipError_t ensure_hist(Workspace &ws, size_t n_entries);
 // are not kept.
 template <typename T>
 inline hipError_t grow(Workspace &ws, T *&p, size_t need) {
+  if (ws.arena) {
+    const size_t b = std::max(need, (size_t)64) * sizeof(T);
+    const size_t at = (ws.arena_used + 255) / 256 * 256;
+    if (at > ws.arena_cap || b > ws.arena_cap - at) {
+      ws.arena_overflow = true;
+      return hipErrorOutOfMemory;
+    }
+    p = reinterpret_cast<T *>(ws.arena + at);
+    ws.arena_used = at + b;
+    return hipSuccess;
+  }
   if (p) {
     auto it = ws.sizes.find((void *)p);
     if (it != ws.sizes.end()) {

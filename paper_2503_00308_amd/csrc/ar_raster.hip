@@ -435,11 +435,11 @@ __global__ __launch_bounds__(192 * kMergeWaves) void k_merge(const uint32_t *__r
 template <int P>
 static hipError_t launch_trans_p(const Workspace &ws, const uint32_t *lists, int nlists, const Params &prm, int L,
                                  int nseg_max, float *lo, float *hi, hipStream_t s) {
-  HIP_RET(hipEventRecord(ws.ev[1], s));
+  if (ws.ev[1]) HIP_RET(hipEventRecord(ws.ev[1], s));
   if (nseg_max > 0)
     hipLaunchKernelGGL(k_raster_seg<P>, dim3((nseg_max + 3) / 4), dim3(256), 0, s, ws.rec, ws.key, ws.tile_range,
                        lists, ws.seg_off, ws.seg_tile, L, nlists, prm, ws.part);
-  HIP_RET(hipEventRecord(ws.ev[2], s));
+  if (ws.ev[2]) HIP_RET(hipEventRecord(ws.ev[2], s));
   hipLaunchKernelGGL(k_merge<P>, dim3(nlists), dim3(192 * kMergeWaves), 0, s, ws.tile_range, ws.seg_off, ws.part, prm,
                      lo, hi, ws.counters);
   return hipGetLastError();
