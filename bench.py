@@ -13,9 +13,12 @@ widths, all cells through ar_render_batch with the segment length from ar_autotu
 against the per-query path), with --partitioned "partitioned" (the bench box cut into
 2x2x2 cells whose bounds are united: time and mean bound width against the whole box), with
 --refined "refined" (an orbit box over the batched scene bisected where MatrixInv fails), and
-"served"
-(Poisson queries over four resident scenes of 10k-750k Gaussians and images of
-100^2-800^2 through the query server, p50/p99 latency against one-at-a-time service).
+"workload3" (the 100k-Gaussian object scene at 400x400 under a six-axis box, one query at a
+time, with the roofline of its pixel loop), and "served" (Poisson queries over four resident
+scenes of 10k-750k Gaussians and images of 100^2-800^2 through the query server at 0.25,
+0.5, 0.75 and 0.9 of the one-at-a-time capacity and at saturation, p50/p99 latency and
+throughput against one-at-a-time service; the largest query the stream admits rendered
+alone).  The CPU baseline runs the FP64 oracle on all host cores (at most 16).
 """
 from __future__ import annotations
 
@@ -114,36 +117,57 @@ def alg_flops_per_pair(P: int) -> int:
     return 110 * (P + 1) + 70
 
 
-def cpu_baseline(scene, intr, box, budget_s=20.0):
-    """FP64 oracle on a bounded sample: 4x4 pixel blocks spread over the image, as many
-    as fit about budget_s seconds (at least one)."""
+_CPU_JOB = {}
+
+
+def _oracle_block(tile):
+    """One 4x4 pixel block of the oracle (runs in a worker; the per-Gaussian stage was
+    computed in the parent and is inherited by fork)."""
+    from oracle import splat
+    j = _CPU_JOB
+    tx, ty = tile
+    t0 = time.perf_counter()
+    r = splat.oracle_bounds(j["scene"], j["intr"], j["box"], {"tile": 4}, tiles=[(tx, ty)], rec=j["rec"])
+    return int(r["pairs"][ty * 4:(ty + 1) * 4, tx * 4:(tx + 1) * 4].sum()), time.perf_counter() - t0
+
+
+def cpu_baseline(scene, intr, box, budget_s=20.0, workers=None):
+    """FP64 oracle on a bounded sample on all host cores (at most 16, the host share of one
+    GPU): random 4x4 pixel blocks of the workload, one per task, for about budget_s of
+    wall time; pairs/s over the wall time of the blocks plus the per-Gaussian stage
+    charged pro rata to the sampled pixels."""
+    import multiprocessing as mp
+
     import numpy as np
     from oracle import splat
+    if workers is None:
+        workers = max(1, min(16, os.cpu_count() or 1))
     t0 = time.perf_counter()
     rec = splat.gaussian_forms(scene, intr, box, {"tile": 4})
     t_rec = time.perf_counter() - t0
     W, H = intr["width"], intr["height"]
     rng = np.random.default_rng(0)
-    cand = [(int(x), int(y)) for x, y in zip(rng.integers(0, W // 4, 64), rng.integers(0, H // 4, 64))]
-    pairs = 0
-    blocks = 0
-    t_pix = 0.0
-    last = 0.0
-    for tx, ty in cand:
-        if blocks and t_pix + t_rec + last > budget_s:
-            break
-        t1 = time.perf_counter()
-        r = splat.oracle_bounds(scene, intr, box, {"tile": 4}, tiles=[(tx, ty)], rec=rec)
-        last = time.perf_counter() - t1
-        t_pix += last
-        pairs += int(r["pairs"][ty * 4:(ty + 1) * 4, tx * 4:(tx + 1) * 4].sum())
-        blocks += 1
-    # per-Gaussian stage is shared by the whole image: charge it pro rata to the sample
+    cand = [(int(x), int(y)) for x, y in zip(rng.integers(0, W // 4, 4096), rng.integers(0, H // 4, 4096))]
+    _CPU_JOB.update(scene=scene, intr=intr, box=box, rec=rec)
+    ctx = mp.get_context("fork")
+    pairs = blocks = 0
+    t1 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        # rounds of one block per worker until the budget is spent
+        k = 0
+        while k < len(cand) and (k == 0 or time.perf_counter() - t1 + t_rec < budget_s):
+            for pr, _ in pool.map(_oracle_block, cand[k:k + workers]):
+                pairs += pr
+                blocks += 1
+            k += workers
+    wall = time.perf_counter() - t1
     frac = blocks * 16 / float(W * H)
-    t = t_pix + t_rec * frac
-    return {"value": pairs / t, "unit": "pairs/s", "cores": 1, "kind": "oracle",
-            "sample": f"{blocks} random 4x4 pixel blocks of the workload ({pairs} pairs); the per-Gaussian "
-                      f"stage ({t_rec:.1f} s for all {len(scene['mean'])} Gaussians) charged pro rata"}
+    t = wall + t_rec * frac
+    return {"value": pairs / t, "unit": "pairs/s", "cores": workers, "kind": "oracle",
+            "host_cpu_count": os.cpu_count(),
+            "sample": f"{blocks} random 4x4 pixel blocks of the workload ({pairs} pairs) on {workers} worker "
+                      f"processes, {wall:.1f} s wall; the per-Gaussian stage ({t_rec:.1f} s for all "
+                      f"{len(scene['mean'])} Gaussians, one core) charged pro rata"}
 
 
 def log(msg):
@@ -186,9 +210,33 @@ def batched_measure(api, synth, runs=2, per_query_cells=32, autotune=True):
         pairs_sub += s1["pairs"]
     torch.cuda.synchronize()
     t_single = (time.perf_counter() - t0) / len(sub)
+    # the same batch as one captured HIP graph (ar_plan), replayed
+    log("batched: planned (graph) render")
+    plan = api.Plan(sc, intr, cells, opts)
+    plan.launch()
+    torch.cuda.synchronize()
+    gtimes, gst, replans = [], None, 0
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        gst, rp = plan.launch()
+        torch.cuda.synchronize()
+        gtimes.append(time.perf_counter() - t0)
+        replans += int(rp)
+    plan.close()
+    t_graph = float(np.median(gtimes))
     sc.close()
     n = len(cells)
+    flops = alg_flops_per_pair(st["P"]) * st["pairs"]
+    achieved = flops / (st["raster_ms"] * 1e-3) / 1e12
     return {"workload": desc, "cells": n, "segment_length": st["segment_length"], "autotuned": autotune,
+            "tuned": "segment length only (tile 8x8 and cells per launch are fixed)",
+            "graph": {"ms": t_graph * 1e3, "device_ms": gst["total_ms"], "pairs_per_s": gst["pairs"] / t_graph,
+                      "replans": replans, "speedup_vs_per_query": t_single * n / t_graph,
+                      "speedup_vs_batch_calls": t_batch / t_graph},
+            "roofline": {"bound": "alu", "kernel": "k_rot_prefix + k_rot_blend (pixel loop, all launches)",
+                         "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_VALU_TFLOPS, "flops_per_pair": alg_flops_per_pair(st["P"]),
+                         "traffic": None},
             "pairs": int(st["pairs"]),
             "cells_per_s": n / t_batch,
             "pairs_per_s": st["pairs"] / t_batch, "ms_per_cell": t_batch / n * 1e3,
@@ -265,43 +313,11 @@ def refined_measure(api, synth, deg=3.0, max_cells=64, runs=3):
     return out
 
 
-def served_measure(api, synth, nq=48, load=0.75, slots=4, seed=0):
-    """Poisson arrivals at `load` x the one-at-a-time capacity; the server's latencies
-    against a FIFO one-at-a-time queue with each query's measured solo service time."""
+def _served_run(api, srv_slots, handles, queries, arrival):
+    """Submit the queries to a fresh server at the given arrival times (seconds from the
+    start); returns latencies (ms), wall time and the server report."""
     import numpy as np
-    import torch
-    log("served: scenes")
-    scenes = synth.served_scenes(seed)
-    handles = [api.Scene(s) for s in scenes]
-    queries = synth.served_queries(nq, seed)
-    # solo service times (the plain per-query path), each query once after a warm-up
-    for s in range(len(handles)):
-        side = (100, 200, 400, 800)[s]
-        api.render_bounds(handles[s], synth.intrinsics(side), synth.camera6_box(dt=0.01))
-    torch.cuda.synchronize()
-    service, pairs = [], 0
-    for i, (s, side, box) in enumerate(queries):
-        t0 = time.perf_counter()
-        _, _, st = api.render_bounds(handles[s], synth.intrinsics(side), box)
-        torch.cuda.synchronize()
-        service.append(time.perf_counter() - t0)
-        pairs += st["pairs"]
-        log(f"served: solo query {i} scene {s} side {side}: {service[-1] * 1e3:.1f} ms, {st['pairs']} pairs")
-    service = np.array(service)
-    lam = load / service.mean()
-    rng = np.random.default_rng(seed + 1)
-    arrival = np.cumsum(rng.exponential(1.0 / lam, nq))
-    arrival -= arrival[0]
-    # one at a time, first come first served
-    finish = np.empty(nq)
-    t = 0.0
-    for i in range(nq):
-        t = max(t, arrival[i]) + service[i]
-        finish[i] = t
-    serial_lat = (finish - arrival) * 1e3
-    # the server, queries submitted at their arrival times
-    log(f"served: server run, {nq} queries at {lam:.1f} per s")
-    srv = api.Server(slots=slots)
+    srv = api.Server(slots=srv_slots)
     ids = [srv.add_scene(h) for h in handles]
     tickets = []
     t0 = time.perf_counter()
@@ -309,7 +325,7 @@ def served_measure(api, synth, nq=48, load=0.75, slots=4, seed=0):
         now = time.perf_counter() - t0
         if arrival[i] > now:
             time.sleep(arrival[i] - now)
-        tickets.append(srv.submit(ids[s], synth.intrinsics(side), box))
+        tickets.append(srv.submit(ids[s], synth_intr(side), box))
     lat = []
     for tk in tickets:
         _, _, res = srv.wait(tk)
@@ -317,19 +333,122 @@ def served_measure(api, synth, nq=48, load=0.75, slots=4, seed=0):
     wall = time.perf_counter() - t0
     rep = srv.report()
     srv.close()
+    return np.array(lat), wall, rep
+
+
+def synth_intr(side):
+    from paper_2503_00308_amd import synth
+    return synth.intrinsics(side)
+
+
+def served_measure(api, synth, nq=48, loads=(0.25, 0.5, 0.75, 0.9), slots=4, seed=0):
+    """Poisson arrivals at each load x the one-at-a-time capacity, and a saturation run (all
+    queries at once): the server's latencies and throughput against a FIFO one-at-a-time
+    queue with each query's measured solo service time (the plain per-query path)."""
+    import numpy as np
+    import torch
+    log("served: scenes")
+    scenes = synth.served_scenes(seed)
+    handles = [api.Scene(s) for s in scenes]
+    queries = synth.served_queries(nq, seed)
+    for s in range(len(handles)):
+        side = (100, 200, 400, 800)[s]
+        api.render_bounds(handles[s], synth.intrinsics(side), synth.camera6_box(dt=0.01))
+    torch.cuda.synchronize()
+    service, pairs, flops, raster = [], 0, 0.0, 0.0
+    for i, (s, side, box) in enumerate(queries):
+        t0 = time.perf_counter()
+        _, _, st = api.render_bounds(handles[s], synth.intrinsics(side), box)
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t0)
+        pairs += st["pairs"]
+        flops += alg_flops_per_pair(st["P"]) * st["pairs"]
+        raster += st["raster_ms"] * 1e-3
+        log(f"served: solo query {i} scene {s} side {side}: {service[-1] * 1e3:.1f} ms, {st['pairs']} pairs")
+    service = np.array(service)
+    out = {"workload": "Poisson queries over resident scenes of 10k/100k/300k/750k Gaussians on boxes, "
+                       "images 100^2-800^2, translation full widths U[0.01,0.1], rotation U[0,2] deg",
+           "queries": nq, "slots": slots, "mean_service_ms": float(service.mean() * 1e3),
+           "one_at_a_time_capacity_qps": 1.0 / service.mean(), "sweep": []}
+    rng = np.random.default_rng(seed + 1)
+    gaps = rng.exponential(1.0, nq)
+    for load in loads:
+        lam = load / service.mean()
+        arrival = np.cumsum(gaps / lam)
+        arrival -= arrival[0]
+        finish = np.empty(nq)
+        t = 0.0
+        for i in range(nq):
+            t = max(t, arrival[i]) + service[i]
+            finish[i] = t
+        serial = (finish - arrival) * 1e3
+        log(f"served: load {load}, {lam:.1f} queries per s")
+        lat, wall, rep = _served_run(api, slots, handles, queries, arrival)
+        out["sweep"].append({"load": load, "arrival_qps": lam, "p50_ms": float(np.percentile(lat, 50)),
+                             "p99_ms": float(np.percentile(lat, 99)), "throughput_qps": nq / wall,
+                             "peak_inflight": rep["peak_inflight"], "peak_workspace_bytes": rep["peak_bytes"],
+                             "one_at_a_time": {"p50_ms": float(np.percentile(serial, 50)),
+                                               "p99_ms": float(np.percentile(serial, 99)),
+                                               "throughput_qps": nq / finish[-1]}})
+    log("served: saturation (all queries at once)")
+    lat, wall, rep = _served_run(api, slots, handles, queries, np.zeros(nq))
+    serial_fin = np.cumsum(service)
+    out["saturation"] = {"throughput_qps": nq / wall, "wall_s": wall, "p50_ms": float(np.percentile(lat, 50)),
+                         "p99_ms": float(np.percentile(lat, 99)), "peak_inflight": rep["peak_inflight"],
+                         "one_at_a_time": {"throughput_qps": nq / serial_fin[-1],
+                                           "p50_ms": float(np.percentile(serial_fin * 1e3, 50)),
+                                           "p99_ms": float(np.percentile(serial_fin * 1e3, 99))},
+                         "speedup_vs_one_at_a_time": serial_fin[-1] / wall}
+    out["pairs_per_s_saturation"] = pairs / wall
+    achieved = flops / raster / 1e12
+    out["roofline"] = {"bound": "alu", "kernel": "pixel loops of the solo queries (sum of their pixel-loop times)",
+                       "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                       "frac": achieved / PEAK_VALU_TFLOPS, "flops_per_pair": "110 (P + 1) + 70 per query",
+                       "traffic": None,
+                       "whole_job_saturation_tflops": flops / wall / 1e12}
+    # the largest query the served workload admits: the 750k-Gaussian scene at 800x800 with
+    # the widest box of the stream (translation full width 0.1, rotation 2 degrees per axis)
+    box = synth.camera6_box(dt=0.05, drot=np.deg2rad(1.0))
+    log("served: largest admitted query (750k Gaussians, 800x800, widest six-axis box)")
+    api.render_bounds(handles[3], synth.intrinsics(800), box)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, st = api.render_bounds(handles[3], synth.intrinsics(800), box)
+    torch.cuda.synchronize()
+    out["largest_query"] = {"gaussians": 750_000, "side": 800, "ms": (time.perf_counter() - t0) * 1e3,
+                            "pairs": int(st["pairs"]), "tile_pairs": int(st["tile_pairs"]), "runs": int(st["runs"]),
+                            "ind_tests": int(st["ind_tests"]), "raster_ms": st["raster_ms"],
+                            "device_ms": st["total_ms"]}
     for h in handles:
         h.close()
-    lat = np.array(lat)
-    return {"workload": "Poisson queries over resident scenes of 10k/100k/300k/750k Gaussians on boxes, "
-                        "images 100^2-800^2, translation full widths U[0.01,0.1], rotation U[0,2] deg",
-            "queries": nq, "load": load, "arrival_qps": lam, "slots": slots,
-            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "throughput_qps": nq / wall, "pairs_per_s": pairs / wall, "peak_inflight": rep["peak_inflight"],
-            "peak_workspace_bytes": rep["peak_bytes"],
-            "one_at_a_time": {"p50_ms": float(np.percentile(serial_lat, 50)),
-                              "p99_ms": float(np.percentile(serial_lat, 99)),
-                              "mean_service_ms": float(service.mean() * 1e3),
-                              "throughput_qps": nq / finish[-1]}}
+    return out
+
+
+def workload3_measure(api, synth, runs=3):
+    """The 100k-Gaussian object scene at 400x400 under a six-axis box (translation +-0.05,
+    yaw/pitch/roll +-1 degree), one query at a time: pairs/s and the roofline of its pixel
+    loop (840 algorithmic flops per pair at P = 6)."""
+    import numpy as np
+    import torch
+    scene, intr, box, desc = synth.config(3)
+    sc = api.Scene(scene)
+    api.render_bounds(sc, intr, box)
+    torch.cuda.synchronize()
+    times, st = [], None
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        _, _, st = api.render_bounds(sc, intr, box)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    sc.close()
+    t = float(np.median(times))
+    achieved = alg_flops_per_pair(st["P"]) * st["pairs"] / (st["raster_ms"] * 1e-3) / 1e12
+    return {"workload": desc, "ms": t * 1e3, "pairs": int(st["pairs"]), "pairs_per_s": st["pairs"] / t,
+            "device_ms": st["total_ms"], "raster_ms": st["raster_ms"], "runs": int(st["runs"]),
+            "ind_tests": int(st["ind_tests"]), "max_window": int(st["max_window"]),
+            "roofline": {"bound": "alu", "kernel": "k_rot_prefix + k_rot_blend (pixel loop)", "achieved": achieved,
+                         "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
+                         "flops_per_pair": alg_flops_per_pair(st["P"]), "traffic": None}}
 
 
 def main():
@@ -340,6 +459,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-workload3", action="store_true", help="skip the 100k-Gaussian six-axis query")
+    ap.add_argument("--workload3-only", action="store_true",
+                    help="only render the 100k-Gaussian six-axis query (warm-up and three timed) and exit")
     ap.add_argument("--no-autotune", action="store_true", help="batched workload: automatic segment length")
     ap.add_argument("--refined", action="store_true",
                     help="also an orbit box refined where MatrixInv fails (left out of the default run, as "
@@ -364,6 +486,12 @@ def main():
         return
     if args.served_query is not None:
         served_query(args.served_query)
+        return
+    if args.workload3_only:
+        import torch
+        from paper_2503_00308_amd import api, synth
+        torch.cuda.set_device(0)
+        print(json.dumps({"workload3": workload3_measure(api, synth)}), flush=True)
         return
 
     import numpy as np
@@ -428,6 +556,9 @@ def main():
     sc.close()
     if args.refined:
         out["refined"] = refined_measure(api, synth)
+    if not args.no_workload3:
+        log("workload 3: 100k Gaussians, 400x400, six-axis box")
+        out["workload3"] = workload3_measure(api, synth)
     if not args.no_batched:
         out["batched"] = batched_measure(api, synth, autotune=not args.no_autotune)
     if not args.no_served:

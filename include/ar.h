@@ -143,6 +143,19 @@ typedef struct {
  *               this many entries each (a longer single list is a group of its own;
  *               default 2^27).  Bounds the 32-bit counts of a group; the result does not
  *               depend on it (bit for bit).
+ *   group_runs  rotation boxes: the most Ind runs one list group may hold (default and
+ *               at most 2^32 - 1, the range of the runs' offsets).  A group whose runs
+ *               exceed it is cut into smaller groups of whole lists and done again; only a
+ *               single list with more runs is rejected (AR_E_UNSUPPORTED).  The result does
+ *               not depend on it (bit for bit).
+ *   inverse     the covariance inverse of Step 3 (Conic): 0 = MatrixInv (Sec. 3.1) with
+ *               its linear bounds propagated forward (default); 1 = MatrixInv with its
+ *               bounds propagated backward (CROWN-style, as the paper's bound engine;
+ *               usually tighter, about k^2 more work in the per-Gaussian stage);
+ *               2 = the adjugate inverse adj(X) Div(det X) (Example 'matinv-vs-direct',
+ *               a precision baseline, looser).  Where an inverse cannot be bounded (the
+ *               assertion of MatrixInv fails, or det X is not provably positive) the
+ *               Gaussian is a fallback (alpha in [0, footprint bound]), as always.
  */
 typedef struct {
   int32_t tile;
@@ -158,6 +171,8 @@ typedef struct {
   int32_t ind_copy;
   int32_t ind_masks;
   int32_t group_entries;
+  int32_t inverse;
+  int32_t group_runs;
 } ar_options;
 
 /* Statistics of one call (filled when the call returns). */
@@ -180,6 +195,41 @@ typedef struct {
 /* Copies the scene to the device on `stream` (synchronises it).  *out receives a
  * handle to release with ar_scene_destroy. */
 int ar_scene_create(const ar_scene_desc *desc, void *hip_stream, ar_scene **out);
+
+/*
+ * A set of scenes around the Gaussians of an ar_scene_desc (Sec. 4.6, "abstract rendering
+ * sets of scene": colour, mean position and opacity perturbations).  Every array may be
+ * NULL (that attribute is exact); arrays are host or device memory (on_device):
+ *   rgb_hi      [3][n]  colour upper bounds; the desc's rgb is the lower bound
+ *                       (rgb <= rgb_hi <= 1)
+ *   opacity_lo  [n]     opacity lower bounds; the desc's opacity is the upper bound
+ *                       (0 <= opacity_lo <= opacity)
+ *   mean_var    [n]     the scene variable (0..nvar-1) that moves Gaussian i's mean, or -1
+ *   mean_dir    [3][n]  its direction: the mean is uw_i + mean_dir_i s_{mean_var[i]}
+ *   nvar, lo, hi        scene variables s_v in [lo[v], hi[v]], v < nvar <= 6
+ * Colours and opacities enter the blend as intervals (the lower colour in the lower, the
+ * upper colour in the upper image; the lower opacity in the lower, the upper in the upper
+ * alpha bound); a moved mean is a linear form in its variable, an extra variable after the
+ * pose variables, and a render rejects (AR_E_UNSUPPORTED) a box whose pose variables plus
+ * the scene's exceed 6.  Scenes with variables render on the general (depth-order)
+ * path: a moved mean can change the depth order even under a translation box, so every
+ * pair of a tile list is tested.  Rejected (AR_E_INVALID): bounds out of the ranges above,
+ * non-finite values, nvar > 0 without mean_var and mean_dir, mean_var out of range.
+ */
+typedef struct {
+  int32_t nvar;
+  int32_t on_device; /* 0: the arrays are host memory, 1: device memory */
+  double lo[6];
+  double hi[6];
+  const float *rgb_hi;
+  const float *opacity_lo;
+  const int32_t *mean_var;
+  const float *mean_dir;
+} ar_scene_set;
+
+/* As ar_scene_create, for the set of scenes *set around *desc (set must not be NULL).
+ * Every render call on the handle bounds every scene of the set at every pose of its box. */
+int ar_scene_create_set(const ar_scene_desc *desc, const ar_scene_set *set, void *hip_stream, ar_scene **out);
 
 /* Releases a scene handle and its device memory (NULL is ignored). */
 void ar_scene_destroy(ar_scene *scene);
@@ -231,6 +281,40 @@ int ar_render_bounds_noalloc(const ar_scene *scene, const ar_intrinsics *intr, c
 int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *cells,
                     int32_t ncells, const ar_options *opts, float *lo_rgb, float *hi_rgb,
                     void *hip_stream, ar_stats *stats);
+
+/*
+ * Planned batched renders (the batched workload as one HIP graph).  A plan holds the
+ * whole launch sequence of a batch of ncells pose boxes (all with the same pose
+ * variables, as in ar_render_batch) captured in a HIP graph: every count stays on the
+ * device, so a replay has no host synchronisation inside and no allocation.
+ *   ar_plan_create   renders the cells once on the ordinary batched path to size every
+ *                    launch of cells (the scene handle's workspace; calls on the scene
+ *                    must not overlap), takes capacities with a quarter of headroom,
+ *                    allocates the plan's own workspace, runs the launch sequence once and
+ *                    captures it (on a stream of the plan's own).  lo_rgb / hi_rgb: device
+ *                    images [ncells][H][W][3], fixed for the plan's life; they hold the
+ *                    cells' bounds when the call returns.  Translation boxes give the
+ *                    result of ar_render_batch bit for bit when opts->chunk is set,
+ *                    rotation boxes always.  AR_E_UNSUPPORTED when a launch of cells needs
+ *                    more than one list group (use fewer cells_per_launch).
+ *   ar_plan_set_cells  new pose boxes for the next launch (ncells of them, with the pose
+ *                    variables of the plan's cells; host memory, copied); they are copied
+ *                    to the device by the graph itself.
+ *   ar_plan_launch   replays the graph on the stream and waits for it; stats (may be NULL)
+ *                    as ar_render_batch's, total_ms the graph's device time (raster_ms 0).
+ *                    When the cells outgrew the capacities, the launch is rendered again on
+ *                    the ordinary path, the plan is captured again with the new sizes and
+ *                    *replanned (may be NULL) is set to 1 (else 0); the images are right in
+ *                    both cases.
+ *   ar_plan_destroy  releases the plan (NULL is ignored).
+ */
+typedef struct ar_plan ar_plan;
+
+int ar_plan_create(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *cells, int32_t ncells,
+                   const ar_options *opts, float *lo_rgb, float *hi_rgb, void *hip_stream, ar_plan **out);
+int ar_plan_set_cells(ar_plan *plan, const ar_pose_box *cells);
+int ar_plan_launch(ar_plan *plan, void *hip_stream, ar_stats *stats, int32_t *replanned);
+void ar_plan_destroy(ar_plan *plan);
 
 /*
  * Bounds over one pose box partitioned into a grid of cells (Sec. 4.2: the set of

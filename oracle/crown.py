@@ -9,8 +9,10 @@ per intermediate.  This module builds Alg. MatrixInv's computation (IXX0 = I - X
 powers IXX0^i by Mmul, Xp = X0 sum_i IXX0^i, then <Xp - Eps, Xp + Eps>) as a graph of
 scalar nodes, each a batch of values, and bounds its outputs backward.
 
-* Inputs are the entries of X, given as linear forms over the box e in [-1, 1]^P; they are
-  substituted by their upper (positive coefficient) or lower (negative) form.
+* Inputs are the entries of X, given as linear forms over the box e in [-1, 1]^P; X is
+  symmetric and its two off-diagonal entries are one quantity (as X = Mp Mp^T in
+  AbstractSplat), so there are three inputs.  An input is substituted by its upper
+  (positive total coefficient) or lower (negative) form.
 * Mul(a, b) is relaxed by the same McCormick planes as lf.mul: upper plane through
   (a_lo, b_hi), lower plane through (a_lo, b_lo), a the left operand.
 * The intervals of the operands of every Mul are themselves computed backward before the
@@ -100,8 +102,12 @@ def matrix_inv_backward(X: lf.LF, k: int = 8):
     X0, det = inv2(0.5 * (Xlo + Xhi))
     ok = np.isfinite(det) & (det > 0)
     X0 = np.where(ok[..., None, None], X0, 0.0)
+    if not (np.array_equal(X.lo[..., 0, 1, :], X.lo[..., 1, 0, :]) and np.array_equal(X.up[..., 0, 1, :],
+                                                                                        X.up[..., 1, 0, :])):
+        raise ValueError("matrix_inv_backward takes a symmetric X (one off-diagonal quantity)")
     g = Graph(P, batch)
-    x = [[g.inp(X[..., i, j]) for j in range(2)] for i in range(2)]
+    x00, x01, x11 = g.inp(X[..., 0, 0]), g.inp(X[..., 0, 1]), g.inp(X[..., 1, 1])
+    x = [[x00, x01], [x01, x11]]
     # IXX0 = Add(I, -Mmul(X, X0))  (X0 constant: exact)
     E = [[g.lin([(x[i][0], -X0[..., 0, j]), (x[i][1], -X0[..., 1, j])], 1.0 if i == j else 0.0)
           for j in range(2)] for i in range(2)]

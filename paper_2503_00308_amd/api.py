@@ -32,6 +32,17 @@ class SceneDesc(ctypes.Structure):
                 ("opacity", ctypes.c_void_p), ("rgb", ctypes.c_void_p)]
 
 
+class SceneSet(ctypes.Structure):
+    _fields_ = [("nvar", ctypes.c_int32), ("on_device", ctypes.c_int32),
+                ("lo", ctypes.c_double * 6), ("hi", ctypes.c_double * 6),
+                ("rgb_hi", ctypes.c_void_p), ("opacity_lo", ctypes.c_void_p),
+                ("mean_var", ctypes.c_void_p), ("mean_dir", ctypes.c_void_p)]
+
+
+# keys of a scene dict that make it a set of scenes (see SceneSet)
+SET_KEYS = ("rgb_hi", "opacity_lo", "set_lo", "set_hi", "mean_var", "mean_dir")
+
+
 class Intrinsics(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
                 ("fx", ctypes.c_double), ("fy", ctypes.c_double),
@@ -49,7 +60,11 @@ class Options(ctypes.Structure):
                 ("z_near", ctypes.c_double), ("t_min", ctypes.c_double),
                 ("cells_per_launch", ctypes.c_int32), ("prefix_entries", ctypes.c_int32),
                 ("abs_sums", ctypes.c_int32), ("ind_copy", ctypes.c_int32), ("ind_masks", ctypes.c_int32),
-                ("group_entries", ctypes.c_int32)]
+                ("group_entries", ctypes.c_int32), ("inverse", ctypes.c_int32), ("group_runs", ctypes.c_int32)]
+
+
+# ar_options.inverse: the covariance inverse of Step 3
+INVERSE = {"matrixinv": 0, "matrixinv_backward": 1, "adjugate": 2}
 
 
 class Stats(ctypes.Structure):
@@ -87,6 +102,8 @@ class ServerStats(ctypes.Structure):
 # the exported C symbols and their signatures (the same list as include/ar.h)
 SYMBOLS = {
     "ar_scene_create": (ctypes.c_int, [ctypes.POINTER(SceneDesc), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "ar_scene_create_set": (ctypes.c_int, [ctypes.POINTER(SceneDesc), ctypes.POINTER(SceneSet), ctypes.c_void_p,
+                                           ctypes.POINTER(ctypes.c_void_p)]),
     "ar_scene_destroy": (None, [ctypes.c_void_p]),
     "ar_scene_size": (ctypes.c_int32, [ctypes.c_void_p]),
     "ar_render_bounds": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
@@ -98,6 +115,13 @@ SYMBOLS = {
     "ar_render_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
                                        ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.POINTER(Stats)]),
+    "ar_plan_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
+                                      ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "ar_plan_set_cells": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PoseBox)]),
+    "ar_plan_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Stats),
+                                      ctypes.POINTER(ctypes.c_int32)]),
+    "ar_plan_destroy": (None, [ctypes.c_void_p]),
     "ar_render_partitioned": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
                                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Options), ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Stats)]),
@@ -170,12 +194,15 @@ def options(d=None) -> Options:
                    float(d.get("z_near", 0.0)), float(d.get("t_min", 0.0)),
                    int(d.get("cells_per_launch", 0)), int(d.get("prefix_entries", 0)),
                    int(d.get("abs_sums", 0)), int(d.get("ind_copy", 0)), int(d.get("ind_masks", 0)),
-                   int(d.get("group_entries", 0)))
+                   int(d.get("group_entries", 0)),
+                   INVERSE.get(d.get("inverse", 0), d.get("inverse", 0)), int(d.get("group_runs", 0)))
 
 
 class Scene:
     """A device-resident scene (ar_scene handle) built from a dict of arrays:
-    mean (N,3), cov_factor (N,3,3), opacity (N,), rgb (N,3)."""
+    mean (N,3), cov_factor (N,3,3), opacity (N,), rgb (N,3); with any of the keys
+    rgb_hi (N,3), opacity_lo (N,), set_lo / set_hi (nvar,), mean_var (N,), mean_dir (N,3)
+    a set of scenes (ar_scene_create_set)."""
 
     def __init__(self, scene, stream=None):
         lib = load()
@@ -188,7 +215,29 @@ class Scene:
         desc = SceneDesc(n, 0, self._mean.ctypes.data, self._cov.ctypes.data,
                          self._op.ctypes.data, self._rgb.ctypes.data)
         h = ctypes.c_void_p()
-        _check(lib.ar_scene_create(ctypes.byref(desc), _stream_ptr(stream), ctypes.byref(h)))
+        if any(k in scene for k in SET_KEYS):
+            st = SceneSet()
+            lo = np.asarray(scene.get("set_lo", []), np.float64).reshape(-1)
+            hi = np.asarray(scene.get("set_hi", []), np.float64).reshape(-1)
+            st.nvar = len(lo)
+            st.lo[:len(lo)] = [float(v) for v in lo]
+            st.hi[:len(hi)] = [float(v) for v in hi]
+            self._keep = []
+            if "rgb_hi" in scene:
+                self._keep.append(np.ascontiguousarray(np.asarray(scene["rgb_hi"], np.float32).T))
+                st.rgb_hi = self._keep[-1].ctypes.data
+            if "opacity_lo" in scene:
+                self._keep.append(np.ascontiguousarray(np.asarray(scene["opacity_lo"], np.float32)))
+                st.opacity_lo = self._keep[-1].ctypes.data
+            if "mean_var" in scene:
+                self._keep.append(np.ascontiguousarray(np.asarray(scene["mean_var"], np.int32)))
+                st.mean_var = self._keep[-1].ctypes.data
+            if "mean_dir" in scene:
+                self._keep.append(np.ascontiguousarray(np.asarray(scene["mean_dir"], np.float32).T))
+                st.mean_dir = self._keep[-1].ctypes.data
+            _check(lib.ar_scene_create_set(ctypes.byref(desc), ctypes.byref(st), _stream_ptr(stream), ctypes.byref(h)))
+        else:
+            _check(lib.ar_scene_create(ctypes.byref(desc), _stream_ptr(stream), ctypes.byref(h)))
         self.handle = h
         self.n = n
 
@@ -247,6 +296,52 @@ def render_bounds_noalloc(scene: Scene, intr, box, out, opts=None, stream=None):
                                         ctypes.c_void_p(lo.data_ptr()), ctypes.c_void_p(hi.data_ptr()),
                                         _stream_ptr(stream), ctypes.byref(st)))
     return st.as_dict()
+
+
+class Plan:
+    """A planned batched render (ar_plan_*): the batch's launch sequence captured once in a
+    HIP graph.  Holds its output tensors lo, hi (ncells, H, W, 3), which hold the cells'
+    bounds after creation and after every launch()."""
+
+    def __init__(self, scene: Scene, intr, cells, opts=None, stream=None):
+        import torch
+        lib = load()
+        ci = intrinsics(intr)
+        m = len(cells)
+        arr = (PoseBox * m)(*[pose_box(c) for c in cells])
+        self.lo = torch.empty((m, ci.height, ci.width, 3), dtype=torch.float32, device="cuda")
+        self.hi = torch.empty_like(self.lo)
+        self.ncells = m
+        self.scene = scene
+        h = ctypes.c_void_p()
+        _check(lib.ar_plan_create(scene.handle, ctypes.byref(ci), arr, m, ctypes.byref(options(opts)),
+                                  ctypes.c_void_p(self.lo.data_ptr()), ctypes.c_void_p(self.hi.data_ptr()),
+                                  _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def set_cells(self, cells):
+        if len(cells) != self.ncells:
+            raise ValueError(f"the plan holds {self.ncells} cells")
+        arr = (PoseBox * self.ncells)(*[pose_box(c) for c in cells])
+        _check(load().ar_plan_set_cells(self.handle, arr))
+
+    def launch(self, stream=None):
+        """Replay; returns (stats, replanned)."""
+        st = Stats()
+        rp = ctypes.c_int32(0)
+        _check(load().ar_plan_launch(self.handle, _stream_ptr(stream), ctypes.byref(st), ctypes.byref(rp)))
+        return st.as_dict(), bool(rp.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().ar_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def render_batch(scene: Scene, intr, cells, opts=None, stream=None):

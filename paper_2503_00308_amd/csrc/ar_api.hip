@@ -73,6 +73,18 @@ int pose_vars(const ar_pose_box *b, bool *rotates) {
   return P;
 }
 
+// Pose variables of the box plus the scene's variables (Sec. 4.6), which follow them in
+// the forms; *rotates: the general (depth-order) path is needed, for a rotation or for
+// scene variables (a moved mean can change the depth order under any box).
+int render_vars(const ar_scene *sc, const ar_pose_box *b, bool *rotates, int *P) {
+  const int pp = pose_vars(b, rotates);
+  *P = pp + sc->dev.nvar;
+  if (sc->dev.nvar > 0) *rotates = true;
+  if (*P > kMaxP)
+    return fail(AR_E_UNSUPPORTED, "%d pose and %d scene variables: at most %d in all", pp, sc->dev.nvar, kMaxP);
+  return AR_OK;
+}
+
 int validate_box(const ar_pose_box *b) {
   if (!b) return fail(AR_E_INVALID, "pose box is NULL");
   if (b->model != AR_POSE_CAMERA6 && b->model != AR_POSE_ORBIT)
@@ -111,6 +123,8 @@ int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *o
   for (int32_t v : {o.abs_sums, o.ind_copy, o.ind_masks})
     if (v < 0 || v > 2) return fail(AR_E_INVALID, "layout switch %d outside [0, 2]", v);
   if (o.group_entries < 0) return fail(AR_E_INVALID, "group_entries %d is negative", o.group_entries);
+  if (o.inverse < 0 || o.inverse > 2) return fail(AR_E_INVALID, "inverse %d outside [0, 2]", o.inverse);
+  if (o.group_runs < 0) return fail(AR_E_INVALID, "group_runs %d is negative", o.group_runs);
   prm.width = in->width;
   prm.height = in->height;
   prm.fx = in->fx;
@@ -132,6 +146,8 @@ int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *o
   prm.ind_copy = o.ind_copy;
   prm.ind_masks = o.ind_masks;
   prm.group_entries = o.group_entries;
+  prm.inverse = o.inverse;
+  prm.group_runs = o.group_runs;
   return AR_OK;
 }
 
@@ -181,7 +197,8 @@ static int ensure_ws(Workspace &ws, size_t n_total, size_t nlists, int P, int nc
     HIP_TRY(grow(ws, ws.counters, 16));
     if (!ws.arena) {
       HIP_TRY(hipHostMalloc((void **)&ws.host_counters, 16 * sizeof(unsigned long long), hipHostMallocDefault));
-      for (int i = 0; i < 4; ++i) HIP_TRY(hipEventCreate(&ws.ev[i]));
+      if (!ws.no_events)
+        for (int i = 0; i < 4; ++i) HIP_TRY(hipEventCreate(&ws.ev[i]));
     }
   }
   return AR_OK;
@@ -492,6 +509,8 @@ static int render_rotation(const ar_scene *sc, Workspace &ws, const Params &prm,
     r = ensure_rot_segments(ws, nlists, nseg_total);
     if (r) return r;
     so = ws.host_seg;
+    ws.last.segments = nseg_total;
+    ws.last.L = L;
     uint32_t *stl = ws.host_seg + (nlists + 1);
     so[0] = 0;
     for (size_t l = 0, k = 0; l < nlists; ++l) {
@@ -576,11 +595,33 @@ static int render_rotation(const ar_scene *sc, Workspace &ws, const Params &prm,
       HIP_TRY(hipMemcpyAsync(ws.host_ranges, ws.tile_range, 2 * nlists * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const uint64_t nruns64 = ws.host_counters[9];
-    if (const char *why = group_runs_limit(nruns64))
-      return fail(AR_E_UNSUPPORTED, "%s: %llu runs in %d entries (set a smaller group_entries)", why,
-                  (unsigned long long)nruns64, ng);
+    if (!have_ranges) {
+      have_ranges = true;
+      rc = build_tables();
+      if (rc) return rc;
+    }
+    const uint64_t run_cap = prm.group_runs > 0 ? (uint64_t)prm.group_runs : kMaxGroupRuns;
+    if (nruns64 > run_cap) {
+      const char *why = "more Ind runs in one list group than its offsets hold";
+      // too many runs for the group's uint32 offsets: the lists from this group on are
+      // grouped again with a cap scaled to fit (the group's work so far is discarded; the
+      // groups before it are complete), unless the group is a single list
+      const size_t nl_rest = nlists - la;
+      std::vector<size_t> rest;
+      const uint64_t cap2 = (uint64_t)((double)std::max(ng, 1) * 0.9 * (double)run_cap / (double)nruns64);
+      if (lb - la <= 1 || cap2 < 1 || !plan_groups(R + 2 * la, nl_rest, cap2, rest))
+        return fail(AR_E_UNSUPPORTED, "%s: %llu runs in the %d entries of one tile list", why,
+                    (unsigned long long)nruns64, ng);
+      groups.resize(g);
+      for (size_t b : rest) groups.push_back(la + b);
+      --g;
+      continue;
+    }
     const size_t nruns = (size_t)nruns64;
     if (st) st->runs += (int64_t)nruns;
+    ws.last.runs += nruns;
+    ws.last.groups += 1;
+    ws.last.compact = ws.last.compact || compact;
     if (ng > 0) {
       Density &dn = ws.density;
       dn.runs_per_entry = std::max(dn.runs_per_entry, (double)nruns / ng);
@@ -589,15 +630,11 @@ static int render_rotation(const ar_scene *sc, Workspace &ws, const Params &prm,
     }
     rc = ensure_runs(ws, nruns);
     if (rc) return rc;
-    if (!have_ranges) {
-      have_ranges = true;
-      rc = build_tables();
-      if (rc) return rc;
-    }
     // chunks of consecutive lists of the group with at most cap entries and kRotChunkSegs
     // segments (or one longer list)
     const bool absolute =
         prm.abs_sums == 1 || (prm.abs_sums == 0 && (double)nruns >= kAbsoluteRuns * (double)std::max(ng, 1));
+    ws.last.absolute = ws.last.absolute || absolute;
     std::vector<RotChunk> chunks;
     size_t max_segs = 0;
     for (size_t l = la; l < lb;) {
@@ -651,6 +688,8 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
                  bool rotates, float *lo, float *hi, hipStream_t s, ar_stats *st) {
   Params prm = prm_in;
   prm.nominal_order = rotates ? 1 : 0;   // rotation path: lists in order of the nominal depth
+  prm.pose_vars = P - sc->dev.nvar;      // scene variables follow the pose variables
+  if (sc->dev.moving) prm.ind_window = 2;   // moved means: every pair of a list is tested
   const int n = sc->dev.n;
   const int ntiles = prm.ntx * prm.nty;
   const size_t n_total = (size_t)ncells * n;
@@ -715,10 +754,15 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
     std::swap(ws.pair_val, ws.pair_val_alt);
   }
   HIP_TRY(launch_tile_ranges(ws.pair_key, (int)npairs, ws.tile_range, (int)nlists, s));
+  ws.last = LaunchSizes{};
+  ws.last.entries = npairs;
   if (!rotates) {
     const int L = segment_length(prm, npairs, nlists, P);
     if (st) st->segment_length = std::max(st->segment_length, L);
     const size_t nseg_max = (npairs + (size_t)L - 1) / (size_t)L + nlists;
+    ws.last.L = L;
+    ws.last.segments = nseg_max;
+    ws.last.groups = 1;
     rc = ensure_segments(ws, nlists, nseg_max, P);
     if (rc) return rc;
     HIP_TRY(launch_segments(ws, (int)nlists, L, s));
@@ -751,6 +795,171 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
     st->cycles_b += (int64_t)ws.host_counters[7];
     st->ind_tests += (int64_t)ws.host_counters[1];
   }
+  return AR_OK;
+}
+
+__global__ void k_fill_u32_n(uint32_t *p, size_t n, uint32_t v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+static hipError_t fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32_n, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+// *eff = *total when it fits cap, else 0 (an overflowed launch then has no list entries)
+__global__ void k_fit_count(const uint32_t *__restrict__ total, uint32_t cap, uint32_t *__restrict__ eff) {
+  if (threadIdx.x == 0) eff[0] = total[0] <= cap ? total[0] : 0u;
+}
+
+// p[0 .. n) = 0 when the overflow counter is set (no runs are read then)
+__global__ void k_zero_if_overflow(uint32_t *__restrict__ p, size_t n, const unsigned long long *__restrict__ ovf) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && ovf[0]) p[i] = 0u;
+}
+
+// Workspace buffers of a planned launch of ncells cells with the capacities caps.
+int ensure_planned(Workspace &ws, const ar_scene *sc, const Params &prm, int ncells, int P, bool rotates,
+                   const PlanCaps &caps) {
+  const size_t n_total = (size_t)ncells * sc->dev.n;
+  const size_t nlists = (size_t)ncells * prm.ntx * prm.nty;
+  int rc = ensure_ws(ws, n_total, nlists, P, ncells);
+  if (rc) return rc;
+  rc = ensure_pairs(ws, caps.entries);
+  if (rc) return rc;
+  if (nlists + 2 > ws.cap_seg_off || !ws.seg_off) {
+    HIP_TRY(grow(ws, ws.seg_off, nlists + 2));
+    ws.cap_seg_off = nlists + 2;
+  }
+  if (caps.segments > ws.cap_seg || !ws.seg_tile) {
+    HIP_TRY(grow(ws, ws.seg_tile, caps.segments));
+    ws.cap_seg = caps.segments;
+  }
+  if (!rotates) return ensure_segments(ws, nlists, caps.segments, P);
+  rc = ensure_general(ws, caps.entries);
+  if (rc) return rc;
+  rc = ensure_runs(ws, caps.runs);
+  if (rc) return rc;
+  rc = ensure_prefix(ws, caps.entries);
+  if (rc) return rc;
+  rc = ensure_rot_parts(ws, caps.segments, P);
+  if (rc) return rc;
+  if (caps.compact) {
+    const size_t forms = (size_t)caps.entries * (size_t)(2 * (P + 1));
+    if (forms > ws.cap_compact || !ws.cform) {
+      HIP_TRY(grow(ws, ws.cform, forms));
+      ws.cap_compact = forms;
+    }
+    if ((size_t)caps.entries > ws.cap_cmean || !ws.cmean) {
+      HIP_TRY(grow(ws, ws.cmean, 4 * (size_t)caps.entries));
+      ws.cap_cmean = caps.entries;
+    }
+  }
+  return AR_OK;
+}
+
+// A launch of ncells pose cells (same P, all rotating or all not) with no host
+// synchronisation and no allocation, so that it can be captured in a HIP graph: every
+// count stays on the device and the kernels run over the capacities caps (the buffers
+// were sized by ensure_planned).  Pose forms are read from poses_dev[ncells].  List
+// entries past the count are keyed past the last list (sorted to the end, in no list),
+// segments past the count map to an empty list; a count above its capacity skips the
+// writes that would exceed it and sets the overflow counter, which the caller reads
+// after the launch (the images are then not valid).  The rotation path runs as one list
+// group with the Ind masks not stored.
+int render_cells_planned(const ar_scene *sc, Workspace &ws, const Params &prm_in, const PoseForms *poses_dev,
+                         int ncells, int P, bool rotates, float *lo, float *hi, hipStream_t s, const PlanCaps &caps) {
+  Params prm = prm_in;
+  prm.nominal_order = rotates ? 1 : 0;
+  prm.pose_vars = P - sc->dev.nvar;
+  if (sc->dev.moving) prm.ind_window = 2;
+  const int n = sc->dev.n;
+  const int ntiles = prm.ntx * prm.nty;
+  const size_t n_total = (size_t)ncells * n;
+  const size_t nlists = (size_t)ncells * ntiles;
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ws.counters, 16);
+  HIP_TRY(hipGetLastError());
+  PoseForms unused{};
+  HIP_TRY(launch_project(P, sc->dev, unused, poses_dev, ncells, prm, ws, s));
+  bool alt = false;
+  HIP_TRY(radix_sort_u64(ws.key_sort, ws.key_alt, ws.perm, ws.perm_alt, (int)n_total, 0, 64, ws, s, &alt));
+  if (alt) {
+    std::swap(ws.key_sort, ws.key_alt);
+    std::swap(ws.perm, ws.perm_alt);
+  }
+  if (ncells > 1) {
+    HIP_TRY(launch_cell_keys(ws.perm, (int)n_total, n, ws.cell_key, s));
+    HIP_TRY(radix_sort_u32(ws.cell_key, ws.cell_key_alt, ws.perm, ws.perm_alt, (int)n_total, 0,
+                           ((bits_for((uint32_t)(ncells - 1)) + 7) / 8) * 8, ws, s, &alt));
+    if (alt) {
+      std::swap(ws.cell_key, ws.cell_key_alt);
+      std::swap(ws.perm, ws.perm_alt);
+    }
+  }
+  HIP_TRY(launch_count_tiles(P, ws, (int)n_total, n, prm, s));
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.count + n_total, 1);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(sum_u32_u64(ws.count, n_total, ws.counters + 8, s));
+  HIP_TRY(exclusive_scan_u32(ws.count, (int)n_total + 1, ws, s));
+  // the scanned total, and its value when it fits the capacity (else 0, so that an
+  // overflowed launch has no entries: every key is padding and every list empty)
+  const uint32_t cap = caps.entries;
+  uint32_t *entries = ws.count + n_total + 1;
+  hipLaunchKernelGGL(k_fit_count, dim3(1), dim3(64), 0, s, ws.count + n_total, cap, entries);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_emit_tiles(P, ws, (int)n_total, n, prm, s, cap));
+  HIP_TRY(launch_fill_tail(ws.pair_key, entries, cap, 0xFFFFFFFFu, s));
+  const int lbits = bits_for((uint32_t)(nlists - 1));
+  HIP_TRY(radix_sort_u32(ws.pair_key, ws.pair_key_alt, ws.pair_val, ws.pair_val_alt, (int)cap, 0,
+                         ((lbits + 7) / 8) * 8, ws, s, &alt));
+  if (alt) {
+    std::swap(ws.pair_key, ws.pair_key_alt);
+    std::swap(ws.pair_val, ws.pair_val_alt);
+  }
+  HIP_TRY(launch_tile_ranges(ws.pair_key, (int)cap, ws.tile_range, (int)nlists, s));
+  const int L = caps.L;
+  HIP_TRY(launch_segments(ws, (int)nlists, L, s));
+  HIP_TRY(exclusive_scan_u32(ws.seg_off, (int)nlists + 1, ws, s));
+  if (!rotates) {
+    HIP_TRY(launch_segment_map(ws, (int)nlists, s, caps.segments));
+    HIP_TRY(launch_raster_translation(P, ws, ws.pair_val, (int)nlists, prm, L, (int)caps.segments, lo, hi, s));
+    return AR_OK;
+  }
+  HIP_TRY(launch_list_box(ws, ws.pair_val, poses_dev, (int)nlists, ntiles, sc->dev, s));
+  DevCounts dc;
+  dc.entries = entries;
+  dc.runs_cap = caps.runs;
+  HIP_TRY(launch_runs(P, ws, ws.pair_val, poses_dev, ntiles, sc->dev, 0, (int)cap, prm.ind_window, kRunsWindows,
+                      nullptr, false, s, dc));
+  if (caps.compact) HIP_TRY(launch_ind_gather(P, ws, ws.pair_val, sc->dev, ntiles, 0, (int)cap, s, entries));
+  const size_t ncnt = 2 * (size_t)cap;
+  HIP_TRY(fill_u32(ws.run_cnt, ncnt + 1, 0u, s));
+  HIP_TRY(launch_runs(P, ws, ws.pair_val, poses_dev, ntiles, sc->dev, 0, (int)cap, prm.ind_window, kRunsCount,
+                      nullptr, caps.compact, s, dc));
+  HIP_TRY(sum_u32_u64(ws.run_cnt, ncnt, ws.counters + 9, s));
+  HIP_TRY(exclusive_scan_u32(ws.run_cnt, (int)(ncnt + 1), ws, s));
+  HIP_TRY(launch_runs(P, ws, ws.pair_val, poses_dev, ntiles, sc->dev, 0, (int)cap, prm.ind_window, kRunsEmit,
+                      nullptr, caps.compact, s, dc));
+  // runs beyond their room were not written: then no entry has runs (the images are
+  // redone by the caller)
+  hipLaunchKernelGGL(k_zero_if_overflow, dim3((unsigned)((ncnt + 1 + 255) / 256)), dim3(256), 0, s, ws.run_cnt,
+                     ncnt + 1, (const unsigned long long *)(ws.counters + kOverflow));
+  HIP_TRY(hipGetLastError());
+  // segments past the count belong to the empty list nlists (ranges [0, 0))
+  HIP_TRY(fill_u32(ws.seg_tile, caps.segments, (uint32_t)nlists, s));
+  HIP_TRY(launch_segment_map(ws, (int)nlists, s, caps.segments));
+  RotChunk c;
+  c.list0 = 0;
+  c.nl = (int)nlists;
+  c.seg0 = 0;
+  c.nseg = (int)caps.segments;
+  c.L = L;
+  c.pos0 = 0;
+  c.gbase = 0;
+  c.absolute = caps.absolute;
+  HIP_TRY(launch_raster_general(P, ws, ws.pair_val, c, prm, lo, hi, s));
   return AR_OK;
 }
 
@@ -820,8 +1029,9 @@ struct DeviceBuffer {
 // Per cell: MatrixInv failures that the pruning test keeps somewhere in the image, and
 // near-plane straddlers (counts[2c], counts[2c + 1]).  Runs of consecutive cells with
 // the same pose variables share a launch of up to kClassifyCells cells.
-int classify_cells(const ar_scene *sc, const Params &prm, const ar_pose_box *cells, int ncells, int64_t *counts,
+int classify_cells(const ar_scene *sc, const Params &prm_in, const ar_pose_box *cells, int ncells, int64_t *counts,
                    hipStream_t s) {
+  Params prm = prm_in;
   const int cap = std::min(ncells, kClassifyCells);
   std::vector<PoseForms> pf((size_t)cap);
   std::vector<unsigned long long> host((size_t)2 * cap);
@@ -833,11 +1043,15 @@ int classify_cells(const ar_scene *sc, const Params &prm, const ar_pose_box *cel
   int i = 0;
   while (i < ncells) {
     bool rot = false;
-    const int P = pose_vars(&cells[i], &rot);
+    int P = 0;
+    int rc = render_vars(sc, &cells[i], &rot, &P);
+    if (rc) return rc;
+    prm.pose_vars = P - sc->dev.nvar;
     int j = i + 1;
     while (j < ncells && j - i < cap) {
       bool r2 = false;
-      if (pose_vars(&cells[j], &r2) != P) break;
+      int P2 = 0;
+      if (render_vars(sc, &cells[j], &r2, &P2) || P2 != P) break;
       ++j;
     }
     const int m = j - i;
@@ -855,16 +1069,6 @@ int classify_cells(const ar_scene *sc, const Params &prm, const ar_pose_box *cel
   return AR_OK;
 }
 
-}  // namespace ar
-
-extern "C" {
-
-const char *ar_last_error(void) { return ar::g_error.c_str(); }
-
-const char *ar_version(void) { return "abstract-render-gfx950 0.1"; }
-
-int32_t ar_scene_size(const ar_scene *scene) { return scene ? scene->dev.n : 0; }
-
 static int validate_scene_host(const ar_scene_desc *d, const float *mean, const float *cov, const float *op,
                                const float *rgb) {
   const size_t n = (size_t)d->n;
@@ -879,7 +1083,44 @@ static int validate_scene_host(const ar_scene_desc *d, const float *mean, const 
   return AR_OK;
 }
 
-int ar_scene_create(const ar_scene_desc *desc, void *hip_stream, ar_scene **out) {
+static int validate_set_host(size_t n, const ar_scene_set *st, const float *op, const float *rgb, const float *olo,
+                             const float *rhi, const int32_t *mvar, const float *mdir) {
+  if (st->nvar < 0 || st->nvar > ar::kMaxP) return fail(AR_E_INVALID, "scene set has %d variables (0..6)", st->nvar);
+  for (int v = 0; v < st->nvar; ++v)
+    if (!isfinite(st->lo[v]) || !isfinite(st->hi[v]) || st->lo[v] > st->hi[v])
+      return fail(AR_E_INVALID, "scene variable %d has a bad range", v);
+  if (st->nvar > 0 && (!mvar || !mdir)) return fail(AR_E_INVALID, "scene variables need mean_var and mean_dir");
+  if (mvar)
+    for (size_t i = 0; i < n; ++i)
+      if (mvar[i] < -1 || mvar[i] >= st->nvar) return fail(AR_E_INVALID, "mean_var %d at %zu out of range", mvar[i], i);
+  if (mdir)
+    for (size_t i = 0; i < 3 * n; ++i)
+      if (!isfinite(mdir[i])) return fail(AR_E_INVALID, "non-finite mean_dir at index %zu", i);
+  if (olo)
+    for (size_t i = 0; i < n; ++i)
+      if (!(olo[i] >= 0.0f && olo[i] <= op[i])) return fail(AR_E_INVALID, "opacity_lo %g at %zu outside [0, opacity]", olo[i], i);
+  if (rhi)
+    for (size_t i = 0; i < 3 * n; ++i)
+      if (!(rhi[i] >= rgb[i] && rhi[i] <= 1.0f)) return fail(AR_E_INVALID, "rgb_hi %g at %zu outside [rgb, 1]", rhi[i], i);
+  return AR_OK;
+}
+
+// host copy of n elements of T from host or device memory (the validation reads it)
+template <typename T>
+static int host_view(const T *p, size_t n, bool on_device, hipStream_t s, std::vector<T> &buf, const T *&out) {
+  out = p;
+  if (!p || !on_device) return AR_OK;
+  buf.resize(n);
+  HIP_TRY(hipMemcpyAsync(buf.data(), p, n * sizeof(T), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  out = buf.data();
+  return AR_OK;
+}
+
+// A scene handle for a scene (set == NULL) or a set of scenes.  Device layout, one
+// allocation: mean 3n, cov 9n, opacity n, rgb 3n, opacity_lo n, rgb_hi 3n, ind_mean 3n,
+// mean_dir 3n floats, then mean_var n int32.
+int create_scene(const ar_scene_desc *desc, const ar_scene_set *set, void *hip_stream, ar_scene **out) {
   if (!out) return fail(AR_E_INVALID, "out is NULL");
   *out = nullptr;
   if (!desc) return fail(AR_E_INVALID, "scene description is NULL");
@@ -887,41 +1128,70 @@ int ar_scene_create(const ar_scene_desc *desc, void *hip_stream, ar_scene **out)
   if (!desc->mean || !desc->cov_factor || !desc->opacity || !desc->rgb) return fail(AR_E_INVALID, "scene array is NULL");
   hipStream_t s = (hipStream_t)hip_stream;
   const size_t n = (size_t)desc->n;
-  // validation reads host copies of the arrays
-  std::vector<float> hm, hc, ho, hr;
-  const float *mean = desc->mean, *cov = desc->cov_factor, *op = desc->opacity, *rgb = desc->rgb;
-  if (desc->on_device) {
-    hm.resize(3 * n); hc.resize(9 * n); ho.resize(n); hr.resize(3 * n);
-    HIP_TRY(hipMemcpyAsync(hm.data(), mean, 3 * n * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(hc.data(), cov, 9 * n * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(ho.data(), op, n * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(hr.data(), rgb, 3 * n * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    mean = hm.data(); cov = hc.data(); op = ho.data(); rgb = hr.data();
-  }
-  int rc = validate_scene_host(desc, mean, cov, op, rgb);
+  std::vector<float> hm, hc, ho, hr, hol, hrh, hmd;
+  std::vector<int32_t> hmv;
+  const float *mean, *cov, *op, *rgb, *olo = nullptr, *rhi = nullptr, *mdir = nullptr;
+  const int32_t *mvar = nullptr;
+  const bool dev = desc->on_device != 0;
+  int rc = host_view(desc->mean, 3 * n, dev, s, hm, mean);
+  if (!rc) rc = host_view(desc->cov_factor, 9 * n, dev, s, hc, cov);
+  if (!rc) rc = host_view(desc->opacity, n, dev, s, ho, op);
+  if (!rc) rc = host_view(desc->rgb, 3 * n, dev, s, hr, rgb);
   if (rc) return rc;
+  rc = validate_scene_host(desc, mean, cov, op, rgb);
+  if (rc) return rc;
+  ar_scene_set none{};
+  if (!set) set = &none;
+  const bool sdev = set->on_device != 0;
+  rc = host_view(set->opacity_lo, n, sdev, s, hol, olo);
+  if (!rc) rc = host_view(set->rgb_hi, 3 * n, sdev, s, hrh, rhi);
+  if (!rc) rc = host_view(set->mean_dir, 3 * n, sdev, s, hmd, mdir);
+  if (!rc) rc = host_view(set->mean_var, n, sdev, s, hmv, mvar);
+  if (rc) return rc;
+  rc = validate_set_host(n, set, op, rgb, olo, rhi, mvar, mdir);
+  if (rc) return rc;
+  // the arrays the kernels read, on the host
+  std::vector<float> img(26 * n);
+  std::copy(mean, mean + 3 * n, img.begin());
+  std::copy(cov, cov + 9 * n, img.begin() + 3 * n);
+  std::copy(op, op + n, img.begin() + 12 * n);
+  std::copy(rgb, rgb + 3 * n, img.begin() + 13 * n);
+  std::copy(olo ? olo : op, (olo ? olo : op) + n, img.begin() + 16 * n);
+  std::copy(rhi ? rhi : rgb, (rhi ? rhi : rgb) + 3 * n, img.begin() + 17 * n);
+  bool moving = false;
+  for (size_t i = 0; i < 3 * n; ++i) {
+    const bool mv = set->nvar > 0 && mvar[i % n] >= 0;
+    moving = moving || mv;
+    img[20 * n + i] = mv ? NAN : mean[i];
+    img[23 * n + i] = mdir ? mdir[i] : 0.0f;
+  }
   ar_scene *sc = new ar_scene();
   float *base = nullptr;
-  hipError_t e = hipMalloc((void **)&base, 16 * n * sizeof(float));
+  hipError_t e = hipMalloc((void **)&base, 27 * n * sizeof(float));
   if (e != hipSuccess) {
     delete sc;
     return fail(e == hipErrorOutOfMemory ? AR_E_OOM : AR_E_DEVICE, "scene allocation failed: %s", hipGetErrorString(e));
   }
   sc->base = base;
-  sc->dev.n = desc->n;
-  sc->dev.mean = base;
-  sc->dev.cov = base + 3 * n;
-  sc->dev.opac = base + 12 * n;
-  sc->dev.rgb = base + 13 * n;
-  const hipMemcpyKind k = desc->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  const float *src[4] = {desc->mean, desc->cov_factor, desc->opacity, desc->rgb};
-  float *dst[4] = {sc->dev.mean, sc->dev.cov, sc->dev.opac, sc->dev.rgb};
-  const size_t cnt[4] = {3 * n, 9 * n, n, 3 * n};
-  for (int i = 0; i < 4; ++i) {
-    e = hipMemcpyAsync(dst[i], src[i], cnt[i] * sizeof(float), k, s);
-    if (e != hipSuccess) break;
+  ar::SceneDev &d = sc->dev;
+  d.n = desc->n;
+  d.mean = base;
+  d.cov = base + 3 * n;
+  d.opac = base + 12 * n;
+  d.rgb = base + 13 * n;
+  d.opac_lo = base + 16 * n;
+  d.rgb_hi = base + 17 * n;
+  d.ind_mean = moving ? base + 20 * n : base;
+  d.mean_dir = base + 23 * n;
+  d.mean_var = set->nvar > 0 ? reinterpret_cast<int32_t *>(base + 26 * n) : nullptr;
+  d.nvar = set->nvar;
+  d.moving = moving ? 1 : 0;
+  for (int v = 0; v < ar::kMaxP; ++v) {
+    d.s_mid[v] = v < set->nvar ? 0.5 * (set->lo[v] + set->hi[v]) : 0.0;
+    d.s_rad[v] = v < set->nvar ? 0.5 * (set->hi[v] - set->lo[v]) : 0.0;
   }
+  e = hipMemcpyAsync(base, img.data(), 26 * n * sizeof(float), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && d.mean_var) e = hipMemcpyAsync(d.mean_var, mvar, n * sizeof(int32_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     ar_scene_destroy(sc);
@@ -929,6 +1199,25 @@ int ar_scene_create(const ar_scene_desc *desc, void *hip_stream, ar_scene **out)
   }
   *out = sc;
   return AR_OK;
+}
+
+}  // namespace ar
+
+extern "C" {
+
+const char *ar_last_error(void) { return ar::g_error.c_str(); }
+
+const char *ar_version(void) { return "abstract-render-gfx950 0.1"; }
+
+int32_t ar_scene_size(const ar_scene *scene) { return scene ? scene->dev.n : 0; }
+
+int ar_scene_create(const ar_scene_desc *desc, void *hip_stream, ar_scene **out) {
+  return ar::create_scene(desc, nullptr, hip_stream, out);
+}
+
+int ar_scene_create_set(const ar_scene_desc *desc, const ar_scene_set *set, void *hip_stream, ar_scene **out) {
+  if (!set) return fail(AR_E_INVALID, "scene set is NULL");
+  return ar::create_scene(desc, set, hip_stream, out);
 }
 
 void ar_scene_destroy(ar_scene *sc) {
@@ -951,7 +1240,9 @@ int ar_render_bounds(const ar_scene *scene, const ar_intrinsics *intr, const ar_
   if (rc) return rc;
   if (stats) memset(stats, 0, sizeof(*stats));
   bool rot = false;
-  const int P = ar::pose_vars(box, &rot);
+  int P = 0;
+  rc = ar::render_vars(scene, box, &rot, &P);
+  if (rc) return rc;
   return ar::render_cells(scene, const_cast<ar_scene *>(scene)->ws, prm, box, 1, P, rot, lo_rgb, hi_rgb,
                           (hipStream_t)hip_stream, stats);
 }
@@ -976,11 +1267,14 @@ int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_p
   int i = 0;
   while (i < ncells) {
     bool rot = false;
-    const int P = ar::pose_vars(&cells[i], &rot);
+    int P = 0;
+    rc = ar::render_vars(scene, &cells[i], &rot, &P);
+    if (rc) return rc;
     int j = i + 1;
     while (j < ncells) {
       bool r2 = false;
-      if (ar::pose_vars(&cells[j], &r2) != P || r2 != rot) break;
+      int P2 = 0;
+      if (ar::render_vars(scene, &cells[j], &r2, &P2) || P2 != P || r2 != rot) break;
       ++j;
     }
     while (i < j) {
@@ -1117,7 +1411,9 @@ int ar_autotune(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_
   bool rot = false;
   for (int i = 0; i < ncells; ++i) {
     bool r = false;
-    ar::pose_vars(&cells[i], &r);
+    int P = 0;
+    int rc = ar::render_vars(scene, &cells[i], &r, &P);
+    if (rc) return rc;
     rot = rot || r;
   }
   // the automatic length first

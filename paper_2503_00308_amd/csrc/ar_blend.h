@@ -85,10 +85,11 @@ __device__ __forceinline__ void pair_alpha(const double *__restrict__ rec, int t
       SForms<P> s;
       s_forms<P>(rec, ux, uy, s);
       ExpBounds b;
-      exp_bounds(s.slo, s.shi, o, b, cf);
-      // lower alpha form  o e_dn (x_lower(e) - xlo + 1),  x_lower = -s_upper / 2
+      exp_bounds(s.slo, s.shi, rec[R::OLO], o, b, cf);
+      // lower alpha form  o_lo e_dn (x_lower(e) - xlo + 1),  x_lower = -s_upper / 2
       // upper alpha form  o e_up + o k_up (x_upper(e) - xlo),  x_upper = -s_lower / 2
-      const double wl = o * b.e_dn;
+      // (o_lo, o: the opacity interval; equal for a plain scene)
+      const double wl = rec[R::OLO] * b.e_dn;
       const double wk = o * b.k_up;
 #pragma unroll
       for (int j = 0; j < P; ++j) {
@@ -112,15 +113,16 @@ __device__ __forceinline__ void pair_alpha(const double *__restrict__ rec, int t
 }
 
 // BlendInd contribution of one pair with the transmittances (tlo, thi) in front:
-// colour forms c T_lo gl, c T_hi gh and the interval sum c T_hi a_hi.
+// colour forms c_lo T_lo gl, c_hi T_hi gh and the interval sum c_hi T_hi a_hi (c_lo = c_hi
+// = c for a plain scene).
 template <int P>
 __device__ __forceinline__ void acc_pair(Acc<P> &acc, const double *__restrict__ rec, const PairAlpha<P> &pa,
                                          double tlo, double thi) {
   using R = Rec<P>;
+  const float *col = reinterpret_cast<const float *>(rec + R::C);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double cc = rec[R::C + c];
-    const double wlo = cc * tlo, whi = cc * thi;
+    const double wlo = (double)col[c] * tlo, whi = (double)col[3 + c] * thi;
 #pragma unroll
     for (int j = 0; j <= P; ++j) {
       acc.lo[c][j] = fma(wlo, pa.gl[j], acc.lo[c][j]);
@@ -154,7 +156,7 @@ __device__ __forceinline__ void alpha_interval(const double *__restrict__ rec, i
     SForms<P> s;
     s_forms<P>(rec, ux, uy, s);
     ExpBounds b;
-    exp_bounds(s.slo, s.shi, rec[R::O], b, cf);
+    exp_bounds(s.slo, s.shi, rec[R::OLO], rec[R::O], b, cf);
     a_lo = b.a_lo;
     a_hi = b.a_hi;
   } else {

@@ -15,6 +15,10 @@
 //           across m, so the sum is at most beta |c_i - c_j| + alpha_i, beta =
 //           sum_l R_l |m_l| / |m|^2 and alpha_i the box bound on the v parts; then
 //           |c_i - c_j| > alpha_i / (1 - beta) suffices.
+// A Gaussian whose mean a scene variable moves (sets of scenes, Sec. 4.6) is not the constant
+// uw_i of the identity: its entry in the means the Ind tests read (ind_mean) is NaN, which
+// makes both comparisons of the identity bound false, so the literal bound decides every
+// pair that involves it; such scenes test every pair of a list (window mode 2).
 // A tile list spans a long stretch of depth but little across it, so the split bound is
 // usually far smaller.  Every j with c_j < c_i - rho_i has Ind_ij = 1 and every j with
 // c_j > c_i + rho_i has Ind_ij = 0 (rho_i the smaller bound, plus rounding margins); only
@@ -84,7 +88,7 @@ __global__ __launch_bounds__(256) void k_list_box(const uint32_t *__restrict__ r
     const size_t g = lists[p] - gbase;
     double u[3];
 #pragma unroll
-    for (int l = 0; l < 3; ++l) u[l] = (double)sc.mean[(size_t)l * sc.n + g];
+    for (int l = 0; l < 3; ++l) u[l] = (double)sc.ind_mean[(size_t)l * sc.n + g];
     const double c = (m[0] * u[0] + m[1] * u[1] + m[2] * u[2]) / mm;
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
@@ -204,18 +208,21 @@ struct IndSrc {
 // Compact copy for the Ind tests: per list position of a group (positions pbase + q,
 // q < ng), the item's mean (float4) and depth forms (lower then upper, P + 1 doubles
 // each), at index q.
+// ng_dev (planned launches, may be null): the number of entries, when below ng.
 template <int P>
 __global__ __launch_bounds__(256) void k_ind_gather(const uint32_t *__restrict__ pkey,
                                                     const uint32_t *__restrict__ lists, const double *__restrict__ dform,
                                                     SceneDev sc, int ntiles, uint32_t pbase, int ng,
+                                                    const uint32_t *__restrict__ ng_dev,
                                                     float4 *__restrict__ cmean, double *__restrict__ cform) {
   constexpr int F = P + 1;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ng_dev) ng = min(ng, (int)*ng_dev);
   if (q >= ng) return;
   const size_t p = (size_t)pbase + q;
   const uint32_t g = lists[p];
   const size_t lg = g - (size_t)(pkey[p] / (uint32_t)ntiles) * sc.n;
-  cmean[q] = make_float4(sc.mean[lg], sc.mean[sc.n + lg], sc.mean[2 * (size_t)sc.n + lg], 0.0f);
+  cmean[q] = make_float4(sc.ind_mean[lg], sc.ind_mean[sc.n + lg], sc.ind_mean[2 * (size_t)sc.n + lg], 0.0f);
   const double *d = dform + (size_t)g * 2 * (kMaxP + 1);
   double *o = cform + (size_t)q * 2 * F;
 #pragma unroll
@@ -324,9 +331,16 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
                                               uint32_t pbase, int ng, int window_mode, uint32_t *__restrict__ win,
                                               uint32_t *__restrict__ woff, unsigned long long *__restrict__ masks,
                                               uint32_t *__restrict__ cnt, uint32_t *__restrict__ runs,
-                                              unsigned long long *__restrict__ counters) {
+                                              unsigned long long *__restrict__ counters,
+                                              const uint32_t *__restrict__ ng_dev, uint32_t runs_cap) {
   constexpr bool EMIT = MODE == kRunsEmit;
   const int lane = threadIdx.x & 63;
+  // planned launches: the entries counted on the device, and no runs past the buffer
+  if (ng_dev) ng = min(ng, (int)*ng_dev);
+  if (EMIT && runs_cap && cnt[2 * (size_t)ng] > runs_cap) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) counters[kOverflow] = 1ull;
+    return;
+  }
   const int wave0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   const int nwaves = (int)(gridDim.x * (blockDim.x >> 6));
   unsigned long long wmax = 0, wsum = 0;   // window statistics of this lane's entries
@@ -344,9 +358,9 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
       const uint32_t *list = lists + beg;
       gi = list[i];
       const size_t li = gi - (size_t)cell * sc.n;
-      uwi[0] = sc.mean[li];
-      uwi[1] = sc.mean[sc.n + li];
-      uwi[2] = sc.mean[2 * sc.n + li];
+      uwi[0] = sc.ind_mean[li];
+      uwi[1] = sc.ind_mean[sc.n + li];
+      uwi[2] = sc.ind_mean[2 * sc.n + li];
       if (MODE != kRunsWindows) {
         ps = (int)win[2 * (size_t)p];
         qe = (int)win[2 * (size_t)p + 1];
@@ -423,7 +437,7 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
     uint32_t ndef = 0, nmay = 0;
     if (have && !wide) {
       const PoseForms &pose = poses[cell];
-      const IndSrc<P, COMPACT> src{lists + beg, sc.mean, COMPACT ? cform : dform, cmean, sc.n,
+      const IndSrc<P, COMPACT> src{lists + beg, sc.ind_mean, COMPACT ? cform : dform, cmean, sc.n,
                                    (size_t)cell * sc.n, (size_t)((uint32_t)beg - pbase)};
       const double *dfi = src.forms_of(i);
       int def_start = ps > 0 ? 0 : -1;   // open run [0, ps) of certain occluders
@@ -474,7 +488,7 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
         kom = runs + 2 * (size_t)cnt[2 * kp + 1];
       }
       unsigned long long *km_ = masks ? masks + woff[kp] : nullptr;
-      const IndSrc<P, COMPACT> src{lists + kb, sc.mean, COMPACT ? cform : dform, cmean, sc.n, (size_t)kc * sc.n,
+      const IndSrc<P, COMPACT> src{lists + kb, sc.ind_mean, COMPACT ? cform : dform, cmean, sc.n, (size_t)kc * sc.n,
                                    (size_t)((uint32_t)kb - pbase)};
       uint32_t kd, km;
       wave_runs<P, MODE, COMPACT>(poses[kc], src, ki, kps, kqe, kuw, src.forms_of(ki), km_, kod, kom, lane, kd, km);
@@ -518,10 +532,12 @@ __global__ __launch_bounds__(256) void k_runs_count_lanes(const uint32_t *__rest
                                                           const uint32_t *__restrict__ win,
                                                           const uint32_t *__restrict__ woff,
                                                           unsigned long long *__restrict__ masks,
-                                                          uint32_t *__restrict__ cnt) {
+                                                          uint32_t *__restrict__ cnt,
+                                                          const uint32_t *__restrict__ ng_dev) {
   using Src = IndSrc<P, true>;
   constexpr int S = Src::S;
   const int lane = threadIdx.x & 63;
+  if (ng_dev) ng = min(ng, (int)*ng_dev);
   const int wave0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   const int nwaves = (int)(gridDim.x * (blockDim.x >> 6));
   for (int p0 = wave0 * 64; p0 < ng; p0 += nwaves * 64) {
@@ -565,7 +581,7 @@ __global__ __launch_bounds__(256) void k_runs_count_lanes(const uint32_t *__rest
       const int gbeg = __builtin_amdgcn_readlane(beg, l0);
       const int gcell = (int)(gtile / (uint32_t)ntiles);
       const PoseForms &pose = poses[gcell];
-      const Src src{lists + gbeg, sc.mean, cform, cmean, sc.n, (size_t)gcell * sc.n, (size_t)((uint32_t)gbeg - pbase)};
+      const Src src{lists + gbeg, sc.ind_mean, cform, cmean, sc.n, (size_t)gcell * sc.n, (size_t)((uint32_t)gbeg - pbase)};
       int def_start = (mine && ps > 0) ? 0 : -1;   // open run [0, ps) of certain occluders
       int may_start = def_start;
       uint32_t nd = 0, nm = 0;
@@ -948,66 +964,69 @@ hipError_t launch_list_box(const Workspace &ws, const uint32_t *lists, const Pos
 template <int P, int MODE, bool COMPACT>
 static hipError_t launch_runs_pm(const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
                                  const SceneDev &sc, uint32_t pbase, int ng, int window_mode,
-                                 unsigned long long *masks, hipStream_t s) {
+                                 unsigned long long *masks, const DevCounts &dc, hipStream_t s) {
   // 64 entries per wave and step; at most 8192 blocks, each looping over its share
   const dim3 grid((unsigned)std::min<size_t>(((size_t)ng + 255) / 256, 8192)), block(256);
   hipLaunchKernelGGL((k_runs<P, MODE, COMPACT>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint,
                      ws.dform, (const float4 *)ws.cmean, ws.cform, ws.lbox, poses_dev, ntiles, sc, pbase, ng,
-                     window_mode, ws.win, ws.woff, masks, ws.run_cnt, ws.runs, ws.counters);
+                     window_mode, ws.win, ws.woff, masks, ws.run_cnt, ws.runs, ws.counters, dc.entries, dc.runs_cap);
   return hipGetLastError();
 }
 
 template <int P>
 static hipError_t launch_runs_p(const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
                                 const SceneDev &sc, uint32_t pbase, int ng, int window_mode, int mode,
-                                unsigned long long *masks, bool compact, hipStream_t s) {
+                                unsigned long long *masks, bool compact, const DevCounts &dc, hipStream_t s) {
   if (mode == kRunsWindows)
-    return launch_runs_pm<P, kRunsWindows, false>(ws, lists, poses_dev, ntiles, sc, pbase, ng, window_mode, masks, s);
+    return launch_runs_pm<P, kRunsWindows, false>(ws, lists, poses_dev, ntiles, sc, pbase, ng, window_mode, masks, dc,
+                                                  s);
   if (compact) {
     if (mode == kRunsCount) {
       const dim3 grid((unsigned)std::min<size_t>(((size_t)ng + 255) / 256, 8192)), block(256);
       hipLaunchKernelGGL(k_runs_count_lanes<P>, grid, block, 0, s, ws.pair_key, ws.tile_range, lists,
                          (const float4 *)ws.cmean, ws.cform, poses_dev, ntiles, sc, pbase, ng, ws.win, ws.woff, masks,
-                         ws.run_cnt);
+                         ws.run_cnt, dc.entries);
       return hipGetLastError();
     }
-    return launch_runs_pm<P, kRunsEmit, true>(ws, lists, poses_dev, ntiles, sc, pbase, ng, window_mode, masks, s);
+    return launch_runs_pm<P, kRunsEmit, true>(ws, lists, poses_dev, ntiles, sc, pbase, ng, window_mode, masks, dc, s);
   }
   if (mode == kRunsCount)
-    return launch_runs_pm<P, kRunsCount, false>(ws, lists, poses_dev, ntiles, sc, pbase, ng, window_mode, masks, s);
-  return launch_runs_pm<P, kRunsEmit, false>(ws, lists, poses_dev, ntiles, sc, pbase, ng, window_mode, masks, s);
+    return launch_runs_pm<P, kRunsCount, false>(ws, lists, poses_dev, ntiles, sc, pbase, ng, window_mode, masks, dc,
+                                                s);
+  return launch_runs_pm<P, kRunsEmit, false>(ws, lists, poses_dev, ntiles, sc, pbase, ng, window_mode, masks, dc, s);
 }
 
 template <int P>
 static hipError_t launch_ind_gather_p(const Workspace &ws, const uint32_t *lists, const SceneDev &sc, int ntiles,
-                                      uint32_t pbase, int ng, hipStream_t s) {
+                                      uint32_t pbase, int ng, const uint32_t *ng_dev, hipStream_t s) {
   hipLaunchKernelGGL(k_ind_gather<P>, dim3((unsigned)(((size_t)ng + 255) / 256)), dim3(256), 0, s, ws.pair_key,
-                     lists, ws.dform, sc, ntiles, pbase, ng, (float4 *)ws.cmean, ws.cform);
+                     lists, ws.dform, sc, ntiles, pbase, ng, ng_dev, (float4 *)ws.cmean, ws.cform);
   return hipGetLastError();
 }
 
 hipError_t launch_ind_gather(int P, const Workspace &ws, const uint32_t *lists, const SceneDev &sc, int ntiles,
-                             uint32_t pbase, int ng, hipStream_t s) {
+                             uint32_t pbase, int ng, hipStream_t s, const uint32_t *ng_dev) {
   if (ng <= 0) return hipSuccess;
   switch (P) {
-    case 0: return launch_ind_gather_p<0>(ws, lists, sc, ntiles, pbase, ng, s);
-    case 1: return launch_ind_gather_p<1>(ws, lists, sc, ntiles, pbase, ng, s);
-    case 2: return launch_ind_gather_p<2>(ws, lists, sc, ntiles, pbase, ng, s);
-    case 3: return launch_ind_gather_p<3>(ws, lists, sc, ntiles, pbase, ng, s);
-    case 4: return launch_ind_gather_p<4>(ws, lists, sc, ntiles, pbase, ng, s);
-    case 5: return launch_ind_gather_p<5>(ws, lists, sc, ntiles, pbase, ng, s);
-    case 6: return launch_ind_gather_p<6>(ws, lists, sc, ntiles, pbase, ng, s);
+    case 0: return launch_ind_gather_p<0>(ws, lists, sc, ntiles, pbase, ng, ng_dev, s);
+    case 1: return launch_ind_gather_p<1>(ws, lists, sc, ntiles, pbase, ng, ng_dev, s);
+    case 2: return launch_ind_gather_p<2>(ws, lists, sc, ntiles, pbase, ng, ng_dev, s);
+    case 3: return launch_ind_gather_p<3>(ws, lists, sc, ntiles, pbase, ng, ng_dev, s);
+    case 4: return launch_ind_gather_p<4>(ws, lists, sc, ntiles, pbase, ng, ng_dev, s);
+    case 5: return launch_ind_gather_p<5>(ws, lists, sc, ntiles, pbase, ng, ng_dev, s);
+    case 6: return launch_ind_gather_p<6>(ws, lists, sc, ntiles, pbase, ng, ng_dev, s);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
                        const SceneDev &sc, uint32_t pbase, int ng, int window_mode, int mode,
-                       unsigned long long *masks, bool compact, hipStream_t s) {
+                       unsigned long long *masks, bool compact, hipStream_t s, const DevCounts &dc) {
   if (ng <= 0) return hipSuccess;
   switch (P) {
 #define AR_RUNS_CASE(PP) \
-    case PP: return launch_runs_p<PP>(ws, lists, poses_dev, ntiles, sc, pbase, ng, window_mode, mode, masks, compact, s);
+    case PP: return launch_runs_p<PP>(ws, lists, poses_dev, ntiles, sc, pbase, ng, window_mode, mode, masks, compact, \
+                                      dc, s);
     AR_RUNS_CASE(0) AR_RUNS_CASE(1) AR_RUNS_CASE(2) AR_RUNS_CASE(3) AR_RUNS_CASE(4) AR_RUNS_CASE(5) AR_RUNS_CASE(6)
 #undef AR_RUNS_CASE
   }

@@ -27,6 +27,8 @@ int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
   } while (0)
 
 int pose_vars(const ar_pose_box *b, bool *rotates);
+// pose plus scene variables of a render (AR_OK, or AR_E_UNSUPPORTED above 6 in all)
+int render_vars(const ar_scene *sc, const ar_pose_box *b, bool *rotates, int *P);
 int validate_box(const ar_pose_box *b);
 int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *op, Params &prm);
 int check_outputs(const float *lo, const float *hi);
@@ -40,5 +42,11 @@ int batch_cells(const ar_scene *sc, const Workspace &ws, const Params &prm, int 
 // using workspace ws; waits for the stream before returning
 int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm, const ar_pose_box *boxes, int ncells, int P,
                  bool rotates, float *lo, float *hi, hipStream_t s, ar_stats *st);
+// buffers of a planned launch; the launch itself (no host synchronisation, no
+// allocation: capturable in a HIP graph), pose forms read from poses_dev
+int ensure_planned(Workspace &ws, const ar_scene *sc, const Params &prm, int ncells, int P, bool rotates,
+                   const PlanCaps &caps);
+int render_cells_planned(const ar_scene *sc, Workspace &ws, const Params &prm, const PoseForms *poses_dev,
+                         int ncells, int P, bool rotates, float *lo, float *hi, hipStream_t s, const PlanCaps &caps);
 
 }  // namespace ar

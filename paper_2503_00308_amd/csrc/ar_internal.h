@@ -17,6 +17,7 @@
 namespace ar {
 
 constexpr int kMaxP = 6;        // pose variables: 3 translations + 3 angles
+constexpr int kOverflow = 15;   // statistics counter set when a planned launch outgrows a buffer
 constexpr int kTile = 8;        // pixel tile side (one 64-lane wave covers a tile)
 constexpr int kTilePix = kTile * kTile;
 constexpr int kListBox = 13;   // per tile list: box of the means, box of their parts across m, max |mean|
@@ -40,8 +41,9 @@ struct Rec {
   static constexpr int F = P + 1;
   // header (16 doubles)
   static constexpr int PRUNE = 0;            // float[0..3] mean box, float[4] r^2, int32[5] type
-  static constexpr int O = 3, LAM = 4;       // opacity, footprint eigenvalue bound
-  static constexpr int C = 5;                // colour (3)
+  static constexpr int O = 3, LAM = 4;       // opacity (upper bound), footprint eigenvalue bound
+  static constexpr int C = 5;                // colour: float[0..3) lower, float[3..6) upper bounds
+  static constexpr int OLO = 15;             // opacity lower bound
   static constexpr int MD2 = 8;              // sum_j |dm_j| + |dr_j|
   static constexpr int MDUP = 9;             // (2) the same for d*up_k
   static constexpr int MBB = 11;             // (2) max_n sum_j (|Bm| + |Br|) + 2 BMAX, for B_kn
@@ -103,14 +105,27 @@ struct Params {
   int32_t nominal_order;    // rotation path: order lists by the nominal depth (else by the upper bound)
   int32_t abs_sums, ind_copy, ind_masks;   // rotation path layouts: 0 automatic, 1 on, 2 off
   int32_t group_entries;    // rotation path: list entries per group of the Ind passes (0: default)
+  int32_t inverse;          // conic: 0 MatrixInv (forward), 1 MatrixInv bounded backward, 2 adjugate
+  int32_t pose_vars;        // pose variables; scene variables follow them in the forms
+  int32_t group_runs;       // rotation path: most Ind runs per list group (0: the uint32 limit)
 };
 
+// A scene, or a set of scenes (Sec. 4.6): colour and opacity intervals per Gaussian,
+// means moved along a direction by scene variables s_v in [s_mid - s_rad, s_mid + s_rad].
 struct SceneDev {
   int32_t n;
-  float *mean;   // [3][n]
-  float *cov;    // [9][n]
-  float *opac;   // [n]
-  float *rgb;    // [3][n]
+  float *mean;      // [3][n]
+  float *cov;       // [9][n]
+  float *opac;      // [n] opacity (the upper bound in a set)
+  float *rgb;       // [3][n] colour (the lower bound in a set)
+  float *opac_lo;   // [n] opacity lower bound (= opac for a plain scene)
+  float *rgb_hi;    // [3][n] colour upper bound (= rgb for a plain scene)
+  float *ind_mean;  // [3][n] means read by the Ind tests: mean, NaN for a moved Gaussian
+  int32_t *mean_var;  // [n] variable moving the mean (-1: none); null without scene variables
+  float *mean_dir;  // [3][n] its direction
+  int32_t nvar;     // scene variables (after the pose variables in the forms)
+  int32_t moving;   // some mean moves
+  double s_mid[kMaxP], s_rad[kMaxP];
 };
 
 // List density of a launch, used to estimate the workspace of the next one on the same
@@ -123,8 +138,26 @@ struct Density {
   bool compact = false;
 };
 
+// Sizes of the last launch of cells (render_cells), from which a planned launch takes
+// its capacities: list entries, segments of the pixel loop, Ind runs, the segment length,
+// list groups, and the rotation path's layout choices.
+struct LaunchSizes {
+  uint64_t entries = 0, segments = 0, runs = 0;
+  int L = 0, groups = 0;
+  bool compact = false, absolute = false;
+};
+
+// Capacities of a planned launch (render_cells_planned): every count is kept on the
+// device and checked against these; the segment length and layouts are fixed.
+struct PlanCaps {
+  uint32_t entries = 0, segments = 0, runs = 0;
+  int L = 0;
+  bool compact = false, absolute = false;
+};
+
 // Device workspace (grown on demand, owned by a scene handle).
 struct Workspace {
+  LaunchSizes last;              // sizes of the last launch
   size_t cap_n = 0, cap_pairs = 0, cap_tiles = 0, cap_scratch = 0, cap_rec = 0, cap_cells = 0;
   size_t bytes = 0;                              // device bytes held by the buffers below
   std::unordered_map<void *, size_t> sizes;      // allocation -> bytes
@@ -190,6 +223,7 @@ struct Workspace {
   unsigned char *arena = nullptr;
   size_t arena_cap = 0, arena_used = 0;
   bool arena_overflow = false;
+  bool no_events = false;        // a planned launch's workspace: no timing events recorded
 };
 
 // ---- launchers (ar_project.hip) ----
@@ -258,13 +292,17 @@ void release_workspace(Workspace &ws);
 // ---- binning and pixel loops (ar_raster.hip) ----
 // items in depth-rank order perm[r] = cell * n_cell + gid; list id = cell * ntiles + tile
 hipError_t launch_count_tiles(int P, const Workspace &ws, int n_total, int n_cell, const Params &prm, hipStream_t s);
-hipError_t launch_emit_tiles(int P, const Workspace &ws, int n_total, int n_cell, const Params &prm, hipStream_t s);
+// cap (planned launches): more list entries than cap are not written and set the overflow counter
+hipError_t launch_emit_tiles(int P, const Workspace &ws, int n_total, int n_cell, const Params &prm, hipStream_t s,
+                             uint32_t cap = 0);
+// p[i] = v for *n_dev <= i < cap
+hipError_t launch_fill_tail(uint32_t *p, const uint32_t *n_dev, size_t cap, uint32_t v, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t *keys, int npairs, uint32_t *ranges, int ntiles, hipStream_t s);
 int part_fields(int P);
 // waves of the translation pixel kernel the device holds at once
 int seg_resident_waves(int P);
 hipError_t launch_segments(const Workspace &ws, int nlists, int L, hipStream_t s);
-hipError_t launch_segment_map(const Workspace &ws, int nlists, hipStream_t s);
+hipError_t launch_segment_map(const Workspace &ws, int nlists, hipStream_t s, uint32_t cap = 0);
 // records ev[1] / ev[2] around the per-segment pixel kernel; lists cell * ntiles + tile,
 // images [cell][H][W][3]
 hipError_t launch_raster_translation(int P, const Workspace &ws, const uint32_t *lists, int nlists, const Params &prm,
@@ -281,13 +319,20 @@ constexpr int kRunsEmit = 2;      // runs written (long windows from the stored 
 // one pass of the Ind runs kernel over the list entries pbase .. pbase + ng - 1 (a group
 // of whole lists; win, woff, run_cnt, runs and the compact copy are indexed relative to
 // pbase); masks (the long windows' Ind masks) may be null
+// Counts a planned launch keeps on the device (all null / zero on the ordinary path):
+// entries, the number of list entries (the kernels take at most that many of their ng);
+// runs_cap, the room for Ind runs (more are not written and set the overflow counter).
+struct DevCounts {
+  const uint32_t *entries = nullptr;
+  uint32_t runs_cap = 0;
+};
 hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
                        const SceneDev &sc, uint32_t pbase, int ng, int window_mode, int mode,
-                       unsigned long long *masks, bool compact, hipStream_t s);
+                       unsigned long long *masks, bool compact, hipStream_t s, const DevCounts &dc = DevCounts{});
 // the compact copy (cmean, cform) of the items' means and depth forms by list position,
 // for the entries pbase .. pbase + ng - 1
 hipError_t launch_ind_gather(int P, const Workspace &ws, const uint32_t *lists, const SceneDev &sc, int ntiles,
-                             uint32_t pbase, int ng, hipStream_t s);
+                             uint32_t pbase, int ng, hipStream_t s, const uint32_t *ng_dev = nullptr);
 // one launch of the rotation pixel loop: lists list0 .. list0 + nl - 1 with entries from
 // position pos0, their segments seg0 .. seg0 + nseg - 1 of L positions
 struct RotChunk {

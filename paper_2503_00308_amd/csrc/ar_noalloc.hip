@@ -50,10 +50,13 @@ extern "C" int ar_render_bounds_noalloc(const ar_scene *scene, const ar_intrinsi
   rc = ar::check_outputs(lo_rgb, hi_rgb);
   if (rc) return rc;
   bool rot = false;
-  const int P = ar::pose_vars(box, &rot);
+  int P = 0;
+  rc = ar::render_vars(scene, box, &rot, &P);
+  if (rc) return rc;
   if (rot)
     return fail(AR_E_UNSUPPORTED,
-                "ar_render_bounds_noalloc takes translation boxes only (rotation boxes stage host tables)");
+                "ar_render_bounds_noalloc takes translation boxes of plain scenes only (rotation boxes and "
+                "scene variables stage host tables)");
   // the per-item buffers alone must fit before anything is launched
   const size_t per_item = 8 * (size_t)ar::rec_stride(P) + 4 * 64 + 16 * (ar::kMaxP + 1);
   if ((size_t)scene->dev.n * per_item > kScratchBytes)

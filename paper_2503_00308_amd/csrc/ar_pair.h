@@ -158,7 +158,9 @@ struct ExpBounds {
   double a_lo, a_hi;  // alpha interval o * [exp(xlo), exp(xhi)] outward
 };
 
-__device__ __forceinline__ void exp_bounds(double slo, double shi, double o, ExpBounds &b, const double *cf) {
+// alpha interval [o_lo exp(xlo), o exp(xhi)] (o_lo = o for a plain scene)
+__device__ __forceinline__ void exp_bounds(double slo, double shi, double o_lo, double o, ExpBounds &b,
+                                           const double *cf) {
   b.xlo = -0.5 * shi;
   b.xhi = -0.5 * fmax(slo, 0.0);
   double eh_dn, eh_up, phi;
@@ -172,7 +174,7 @@ __device__ __forceinline__ void exp_bounds(double slo, double shi, double o, Exp
     k = (eh_up - b.e_dn) / h * (1.0 + 8.0 * kU);
   }
   b.k_up = k;
-  b.a_lo = (o * b.e_dn) * (1.0 - 2.0 * kU);
+  b.a_lo = (o_lo * b.e_dn) * (1.0 - 2.0 * kU);
   b.a_hi = fmin(o, (o * eh_up) * (1.0 + 2.0 * kU));
 }
 

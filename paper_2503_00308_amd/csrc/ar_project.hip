@@ -169,12 +169,12 @@ __device__ __forceinline__ void bounds_mr(const double *m, const double *r, doub
   hi = ((m[P] + r[P]) + sh) + w;
 }
 
-// MatrixInv(X; X0, k) for the symmetric 2x2 set X = [[x00, x01], [x01, x11]] (Sec. 3.1):
-//   IXX0 = I - X X0 with X0 the inverse of the interval-hull centre,
-//   Xp = X0 sum_{i=0..k} IXX0^i,  Eps = ||X0|| n^(k+1) / (1 - n),  n >= ||IXX0||,
-//   conic = <Xp - Eps, Xp + Eps>.  Returns false when the assertion n < 1 fails.
+// The common start of MatrixInv (Sec. 3.1) for the symmetric 2x2 set
+// X = [[x00, x01], [x01, x11]]: X0 the inverse of the interval-hull centre and
+// IXX0 = I - X X0 (exact scaling of X's forms, widened by a bound on the FP64
+// cancellation of the sum).  Returns false when the centre is not positive definite.
 template <int P>
-__device__ bool matrix_inv(const L64<P> &x00, const L64<P> &x01, const L64<P> &x11, int k, L64<P> conic[4]) {
+__device__ bool matinv_start(const L64<P> &x00, const L64<P> &x01, const L64<P> &x11, double X0[4], L64<P> E[4]) {
   double b00l, b00h, b01l, b01h, b11l, b11h;
   l_bounds<P>(x00, b00l, b00h);
   l_bounds<P>(x01, b01l, b01h);
@@ -182,9 +182,11 @@ __device__ bool matrix_inv(const L64<P> &x00, const L64<P> &x01, const L64<P> &x
   const double m00 = 0.5 * (b00l + b00h), m01 = 0.5 * (b01l + b01h), m11 = 0.5 * (b11l + b11h);
   const double det = m00 * m11 - m01 * m01;
   if (!(det > 0.0) || !isfinite(det)) return false;
-  double X0[4] = {m11 / det, -m01 / det, -m01 / det, m00 / det};
+  X0[0] = m11 / det;
+  X0[1] = -m01 / det;
+  X0[2] = -m01 / det;
+  X0[3] = m00 / det;
   const L64<P> *X[4] = {&x00, &x01, &x01, &x11};
-  L64<P> E[4];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) {
       L64<P> s = l_add<P>(l_scale<P>(*X[i * 2 + 0], X0[0 * 2 + j]), l_scale<P>(*X[i * 2 + 1], X0[1 * 2 + j]));
@@ -196,6 +198,36 @@ __device__ bool matrix_inv(const L64<P> &x00, const L64<P> &x01, const L64<P> &x
       e.up[P] += rho;
       E[i * 2 + j] = e;
     }
+  return true;
+}
+
+// Eps = ||X0|| n^(k+1) / (1 - n) with n >= ||IXX0|| (Frobenius, from IXX0's intervals);
+// false when the assertion n < 1 fails.
+template <int P>
+__device__ bool matinv_eps(const L64<P> E[4], const double X0[4], int k, double &eps) {
+  double nn = 0.0;
+  for (int i = 0; i < 4; ++i) {
+    double lo, hi;
+    l_bounds<P>(E[i], lo, hi);
+    nn += fmax(lo * lo, hi * hi);
+  }
+  const double nbar = sqrt(nn);
+  if (!(nbar < 1.0)) return false;
+  const double nx0 = sqrt(X0[0] * X0[0] + X0[1] * X0[1] + X0[2] * X0[2] + X0[3] * X0[3]);
+  eps = nx0 * pow(nbar, (double)(k + 1)) / (1.0 - nbar);
+  return isfinite(eps);
+}
+
+// MatrixInv(X; X0, k) for the symmetric 2x2 set X = [[x00, x01], [x01, x11]] (Sec. 3.1):
+//   IXX0 = I - X X0 with X0 the inverse of the interval-hull centre,
+//   Xp = X0 sum_{i=0..k} IXX0^i,  Eps = ||X0|| n^(k+1) / (1 - n),  n >= ||IXX0||,
+//   conic = <Xp - Eps, Xp + Eps>.  Returns false when the assertion n < 1 fails.
+// Forward mode: every power carries its own pair of forms (l_mul).
+template <int P>
+__device__ bool matrix_inv(const L64<P> &x00, const L64<P> &x01, const L64<P> &x11, int k, L64<P> conic[4]) {
+  double X0[4];
+  L64<P> E[4];
+  if (!matinv_start<P>(x00, x01, x11, X0, E)) return false;
   L64<P> S[4], Pw[4], T[4];
   for (int i = 0; i < 4; ++i) {
     S[i] = l_addc<P>(l_const<P>(0.0), (i == 0 || i == 3) ? 1.0 : 0.0);
@@ -211,17 +243,8 @@ __device__ bool matrix_inv(const L64<P> &x00, const L64<P> &x01, const L64<P> &x
       S[i] = l_add<P>(S[i], T[i]);
     }
   }
-  double nn = 0.0;
-  for (int i = 0; i < 4; ++i) {
-    double lo, hi;
-    l_bounds<P>(E[i], lo, hi);
-    nn += fmax(lo * lo, hi * hi);
-  }
-  const double nbar = sqrt(nn);
-  if (!(nbar < 1.0)) return false;
-  const double nx0 = sqrt(X0[0] * X0[0] + X0[1] * X0[1] + X0[2] * X0[2] + X0[3] * X0[3]);
-  const double eps = nx0 * pow(nbar, (double)(k + 1)) / (1.0 - nbar);
-  if (!isfinite(eps)) return false;
+  double eps;
+  if (!matinv_eps<P>(E, X0, k, eps)) return false;
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) {
       L64<P> c = l_add<P>(l_scale<P>(S[0 * 2 + j], X0[i * 2 + 0]), l_scale<P>(S[1 * 2 + j], X0[i * 2 + 1]));
@@ -229,6 +252,131 @@ __device__ bool matrix_inv(const L64<P> &x00, const L64<P> &x01, const L64<P> &x
       c.up[P] += eps;
       conic[i * 2 + j] = c;
     }
+  return true;
+}
+
+constexpr int kMaxTaylorK = 16;
+
+// Backward substitution through MatrixInv's powers (Pw^1 = IXX0, Pw^i = Pw^(i-1) IXX0 by
+// Mmul): an upper bound, as a form over e, of cst + sum over the levels L <= top of
+// sum_ab D_ab Pw^L_ab (every level, or the top level only).  Each product
+// Mul(Pw^(L-1)_at, IXX0_tb) is replaced by its McCormick plane (upper through (alo, bhi)
+// for a positive weight, lower through (alo, blo) for a negative one, the left operand's
+// lower bound alo taken from plo), so the weights flow to the level below and to IXX0;
+// IXX0 = I - X X0 passes them on to the three inputs x00, x01 (both off-diagonal
+// entries, one quantity) and x11, whose forms are substituted by the sign of their total
+// weights.  The FP64 rounding of the substitution is covered by 2^-50 of its terms'
+// magnitude, added to the constant.
+template <int P>
+__device__ void matinv_back(const L64<P> &x00, const L64<P> &x01, const L64<P> &x11, const double X0[4],
+                            const double Elo[4], const double Ehi[4],
+                            const double (*plo)[4], int top, const double D[4], bool every_level, double cst,
+                            double out[P + 1]) {
+  double W[4] = {0.0, 0.0, 0.0, 0.0}, V[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int lvl = top; lvl >= 2; --lvl) {
+    double T[4];
+    for (int q = 0; q < 4; ++q) {
+      T[q] = (every_level || lvl == top) ? W[q] + D[q] : W[q];
+      W[q] = 0.0;
+    }
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        const double w = T[a * 2 + b];
+        if (w == 0.0) continue;
+        for (int t = 0; t < 2; ++t) {
+          const double alo = plo[lvl - 1][a * 2 + t];
+          const double pe = w > 0.0 ? Ehi[t * 2 + b] : Elo[t * 2 + b];
+          W[a * 2 + t] = fma(w, pe, W[a * 2 + t]);
+          V[t * 2 + b] = fma(w, alo, V[t * 2 + b]);
+          cst = fma(-w * alo, pe, cst);
+        }
+      }
+  }
+  for (int q = 0; q < 4; ++q) V[q] += (every_level || top == 1) ? W[q] + D[q] : W[q];
+  // IXX0_ij = delta_ij - x_i0 X0_0j - x_i1 X0_1j, with x_10 = x_01
+  const double U[3] = {-(V[0] * X0[0] + V[1] * X0[1]),
+                       -(V[0] * X0[2] + V[1] * X0[3]) - (V[2] * X0[0] + V[3] * X0[1]),
+                       -(V[2] * X0[2] + V[3] * X0[3])};
+  cst += V[0] + V[3];
+  const L64<P> *xs[3] = {&x00, &x01, &x11};
+#pragma unroll
+  for (int j = 0; j < P; ++j) out[j] = 0.0;
+  out[P] = cst;
+  double mag = fabs(cst);
+  for (int q = 0; q < 3; ++q) {
+    const double *f = U[q] > 0.0 ? xs[q]->up : xs[q]->lo;
+#pragma unroll
+    for (int j = 0; j <= P; ++j) out[j] = fma(U[q], f[j], out[j]);
+    mag += fabs(U[q]) * l_mag<P>(f);
+  }
+  out[P] += 0x1p-50 * mag;
+}
+
+// MatrixInv with its linear bounds propagated backward (CROWN-style, the paper's bound
+// engine): the same X0, IXX0, powers and Eps as matrix_inv, but every conic entry is
+// bounded by one backward substitution from the entry to IXX0 (matinv_back), after the
+// lower bounds of the powers' entries (the left operands of the next level's products)
+// have been found the same way, level by level.
+template <int P>
+__device__ bool matrix_inv_backward(const L64<P> &x00, const L64<P> &x01, const L64<P> &x11, int k, L64<P> conic[4]) {
+  double X0[4];
+  L64<P> E[4];
+  if (!matinv_start<P>(x00, x01, x11, X0, E)) return false;
+  double eps;
+  if (!matinv_eps<P>(E, X0, k, eps)) return false;
+  double Elo[4], Ehi[4];
+  for (int q = 0; q < 4; ++q) l_bounds<P>(E[q], Elo[q], Ehi[q]);
+  double plo[kMaxTaylorK][4];
+  for (int q = 0; q < 4; ++q) plo[1][q] = Elo[q];
+  double f[P + 1];
+  for (int lvl = 2; lvl < k; ++lvl)
+    for (int q = 0; q < 4; ++q) {
+      double D[4] = {0.0, 0.0, 0.0, 0.0};
+      D[q] = -1.0;
+      matinv_back<P>(x00, x01, x11, X0, Elo, Ehi, plo, lvl, D, false, 0.0, f);
+      double s = f[P];
+#pragma unroll
+      for (int j = 0; j < P; ++j) s += fabs(f[j]);
+      plo[lvl][q] = -s;
+    }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      // conic_ij = sum_t X0_it S_tj, S = I + sum_L Pw^L
+      double D[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int t = 0; t < 2; ++t) D[t * 2 + j] = X0[i * 2 + t];
+      L64<P> c;
+      matinv_back<P>(x00, x01, x11, X0, Elo, Ehi, plo, k, D, true, X0[i * 2 + j], c.up);
+      for (int q = 0; q < 4; ++q) D[q] = -D[q];
+      matinv_back<P>(x00, x01, x11, X0, Elo, Ehi, plo, k, D, true, -X0[i * 2 + j], c.lo);
+#pragma unroll
+      for (int t = 0; t <= P; ++t) c.lo[t] = -c.lo[t];
+      c.lo[P] -= eps;
+      c.up[P] += eps;
+      conic[i * 2 + j] = c;
+    }
+  return true;
+}
+
+// The direct inverse that Sec. 3.1's Example 'matinv-vs-direct' compares MatrixInv with:
+// adj(X) Div(det X), det = Mul(x00, x11) - Mul(x01, x01), Div as in Table "Bounds for
+// operations Exp, Div and Ind" (tangent at the lower end below, chord above), entries
+// Mul(adj_ij, 1/det).  Returns false where det is not provably positive.
+template <int P>
+__device__ bool adjugate_inv(const L64<P> &x00, const L64<P> &x01, const L64<P> &x11, L64<P> conic[4]) {
+  const L64<P> det = l_sub<P>(l_mul<P>(x00, x11), l_mul<P>(x01, x01));
+  double dlo, dhi;
+  l_bounds<P>(det, dlo, dhi);
+  if (!(dlo > 0.0) || !isfinite(dhi)) return false;
+  L64<P> r;
+  l_scale_lower<P>(det, -1.0 / (dlo * dlo), r.lo);
+  l_scale_upper<P>(det, -1.0 / (dlo * dhi), r.up);
+  r.lo[P] += 2.0 / dlo;
+  r.up[P] += 1.0 / dlo + 1.0 / dhi;
+  const L64<P> nx01 = l_neg<P>(x01);
+  conic[0] = l_mul<P>(x11, r);
+  conic[1] = l_mul<P>(nx01, r);
+  conic[2] = l_mul<P>(nx01, r);
+  conic[3] = l_mul<P>(x00, r);
   return true;
 }
 
@@ -244,7 +392,18 @@ __device__ __forceinline__ void project_one(const SceneDev &sc, const PoseForms 
                                             int32_t *__restrict__ rect_out, double *__restrict__ dform_out,
                                             double *__restrict__ dint_out, unsigned long long *__restrict__ counters) {
   const int n = sc.n;
-  const double uw[3] = {sc.mean[g], sc.mean[n + g], sc.mean[2 * n + g]};
+  double uw[3] = {sc.mean[g], sc.mean[n + g], sc.mean[2 * n + g]};
+  // a set of scenes (Sec. 4.6): the mean moved by scene variable v, uw + dir s_v, is the
+  // form uw + dir (s_mid + s_rad e_(pose_vars + v)); uw holds its centre below
+  const int mv = sc.mean_var ? sc.mean_var[g] : -1;
+  double mdir[3] = {0.0, 0.0, 0.0};
+  if (mv >= 0) {
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      mdir[l] = sc.mean_dir[(size_t)l * n + g];
+      uw[l] += mdir[l] * sc.s_mid[mv];
+    }
+  }
   double Mw[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) Mw[i] = sc.cov[(size_t)i * n + g];
@@ -255,6 +414,17 @@ __device__ __forceinline__ void project_one(const SceneDev &sc, const PoseForms 
   L64<P> y[3];
 #pragma unroll
   for (int l = 0; l < 3; ++l) y[l] = l_addc<P>(l_neg<P>(load_form<P>(pose.tau[l])), uw[l]);
+  if (mv >= 0) {
+    const int ix = prm.pose_vars + mv;   // < P (checked on the host)
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int k = 0; k < P; ++k)
+        if (k == ix) {
+          y[l].lo[k] += mdir[l] * sc.s_rad[mv];
+          y[l].up[k] += mdir[l] * sc.s_rad[mv];
+        }
+  }
   L64<P> uc[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -328,7 +498,10 @@ __device__ __forceinline__ void project_one(const SceneDev &sc, const PoseForms 
 
   L64<P> conic[4];
   if (normal) {
-    if (!matrix_inv<P>(X00, X01, X11, prm.taylor_k, conic)) type = kFallback;
+    const bool inv_ok = prm.inverse == 1 ? matrix_inv_backward<P>(X00, X01, X11, prm.taylor_k, conic)
+                        : prm.inverse == 2 ? adjugate_inv<P>(X00, X01, X11, conic)
+                                           : matrix_inv<P>(X00, X01, X11, prm.taylor_k, conic);
+    if (!inv_ok) type = kFallback;
   }
   if constexpr (CLASSIFY) {
     if (type == kFallback) {
@@ -399,9 +572,13 @@ __device__ __forceinline__ void project_one(const SceneDev &sc, const PoseForms 
     rec[R::BMAX + k] = slack * bmax[k];
   }
   rec[R::O] = (double)o;
-  rec[R::C + 0] = (double)sc.rgb[g];
-  rec[R::C + 1] = (double)sc.rgb[n + g];
-  rec[R::C + 2] = (double)sc.rgb[2 * n + g];
+  rec[R::OLO] = (double)sc.opac_lo[g];
+  float *col = reinterpret_cast<float *>(rec + R::C);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    col[c] = sc.rgb[(size_t)c * n + g];
+    col[3 + c] = sc.rgb_hi[(size_t)c * n + g];
+  }
   const bool geo = (type == kNormal || type == kFallback);
   rec[R::LAM] = geo ? lam * (1.0 + 0x1p-40) : 0.0;
   float *pf = reinterpret_cast<float *>(rec + R::PRUNE);
@@ -411,7 +588,6 @@ __device__ __forceinline__ void project_one(const SceneDev &sc, const PoseForms 
   pf[3] = geo ? __double2float_ru(m1hi) : 0.0f;
   pf[4] = geo ? __double2float_ru(r2) : -1.0f;
   reinterpret_cast<int32_t *>(pf)[5] = type;
-  rec[15] = 0.0;
   for (int j = R::CM + 24; j < R::STRIDE; ++j) rec[j] = 0.0;
 
   // tile rectangle (inclusive) for binning; empty when the Gaussian cannot contribute

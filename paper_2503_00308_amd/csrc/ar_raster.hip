@@ -51,15 +51,22 @@ __device__ __forceinline__ float tile_dist2(const float *mu, int tx, int ty, con
 // rectangle 64 tiles at a time and a ballot gives each kept tile its slot.  Large
 // inputs (many cells): one thread per item walking its rectangle.  Both emit an item's
 // tiles in row-major order at [counts[r], counts[r + 1]).
+// cap (emitting, planned launches): when the scanned total counts[n_total] exceeds it,
+// nothing is written and overflow[0] is set (the caller renders again with more room).
 template <int P, bool EMIT>
 __global__ __launch_bounds__(256) void k_bin(const double *__restrict__ recs, const int32_t *__restrict__ rect,
                                              const uint32_t *__restrict__ perm, int n_total, int n_cell, Params prm,
                                              uint32_t *__restrict__ counts, uint32_t *__restrict__ pkey,
-                                             uint32_t *__restrict__ pval) {
+                                             uint32_t *__restrict__ pval, uint32_t cap,
+                                             unsigned long long *__restrict__ overflow) {
   using R = Rec<P>;
   const int lane = threadIdx.x & 63;
   const int r = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   if (r >= n_total) return;
+  if (EMIT && cap && counts[n_total] > cap) {
+    if (r == 0 && lane == 0) overflow[0] = 1ull;
+    return;
+  }
   const uint32_t gid = perm[r];
   const uint32_t lbase = (gid / (uint32_t)n_cell) * (uint32_t)(prm.ntx * prm.nty);
   const double *rec = recs + (size_t)gid * R::STRIDE;
@@ -93,10 +100,15 @@ template <int P, bool EMIT>
 __global__ __launch_bounds__(256) void k_bin_thread(const double *__restrict__ recs, const int32_t *__restrict__ rect,
                                                     const uint32_t *__restrict__ perm, int n_total, int n_cell,
                                                     Params prm, uint32_t *__restrict__ counts,
-                                                    uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval) {
+                                                    uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval,
+                                                    uint32_t cap, unsigned long long *__restrict__ overflow) {
   using R = Rec<P>;
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n_total) return;
+  if (EMIT && cap && counts[n_total] > cap) {
+    if (r == 0) overflow[0] = 1ull;
+    return;
+  }
   const uint32_t gid = perm[r];
   const uint32_t lbase = (gid / (uint32_t)n_cell) * (uint32_t)(prm.ntx * prm.nty);
   const double *rec = recs + (size_t)gid * R::STRIDE;
@@ -127,10 +139,12 @@ __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
-__global__ void k_tile_ranges(const uint32_t *__restrict__ keys, int npairs, uint32_t *__restrict__ ranges) {
+__global__ void k_tile_ranges(const uint32_t *__restrict__ keys, int npairs, uint32_t *__restrict__ ranges,
+                              uint32_t nlists) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npairs) return;
   const uint32_t t = keys[p];
+  if (t >= nlists) return;
   if (p == 0 || keys[p - 1] != t) ranges[2 * t] = (uint32_t)p;
   if (p == npairs - 1 || keys[p + 1] != t) ranges[2 * t + 1] = (uint32_t)(p + 1);
 }
@@ -139,54 +153,70 @@ constexpr int kBinWaveMax = 65536;   // up to this many items: one wave per item
 
 template <int P>
 static hipError_t launch_bin_p(const Workspace &ws, int n_total, int n_cell, const Params &prm, bool emit,
-                               hipStream_t s) {
+                               uint32_t cap, hipStream_t s) {
+  unsigned long long *ovf = ws.counters + kOverflow;
   if (n_total <= kBinWaveMax) {
     const dim3 grid((unsigned)((n_total + 3) / 4));   // four waves (items) per block
     if (emit)
       hipLaunchKernelGGL((k_bin<P, true>), grid, dim3(256), 0, s, ws.rec, ws.rect, ws.perm, n_total, n_cell, prm,
-                         ws.count, ws.pair_key, ws.pair_val);
+                         ws.count, ws.pair_key, ws.pair_val, cap, ovf);
     else
       hipLaunchKernelGGL((k_bin<P, false>), grid, dim3(256), 0, s, ws.rec, ws.rect, ws.perm, n_total, n_cell, prm,
-                         ws.count, ws.pair_key, ws.pair_val);
+                         ws.count, ws.pair_key, ws.pair_val, 0u, ovf);
   } else {
     const dim3 grid((unsigned)((n_total + 255) / 256));
     if (emit)
       hipLaunchKernelGGL((k_bin_thread<P, true>), grid, dim3(256), 0, s, ws.rec, ws.rect, ws.perm, n_total, n_cell,
-                         prm, ws.count, ws.pair_key, ws.pair_val);
+                         prm, ws.count, ws.pair_key, ws.pair_val, cap, ovf);
     else
       hipLaunchKernelGGL((k_bin_thread<P, false>), grid, dim3(256), 0, s, ws.rec, ws.rect, ws.perm, n_total, n_cell,
-                         prm, ws.count, ws.pair_key, ws.pair_val);
+                         prm, ws.count, ws.pair_key, ws.pair_val, 0u, ovf);
   }
   return hipGetLastError();
 }
 
 static hipError_t launch_bin(int P, const Workspace &ws, int n_total, int n_cell, const Params &prm, bool emit,
-                             hipStream_t s) {
+                             uint32_t cap, hipStream_t s) {
   switch (P) {
-    case 0: return launch_bin_p<0>(ws, n_total, n_cell, prm, emit, s);
-    case 1: return launch_bin_p<1>(ws, n_total, n_cell, prm, emit, s);
-    case 2: return launch_bin_p<2>(ws, n_total, n_cell, prm, emit, s);
-    case 3: return launch_bin_p<3>(ws, n_total, n_cell, prm, emit, s);
-    case 4: return launch_bin_p<4>(ws, n_total, n_cell, prm, emit, s);
-    case 5: return launch_bin_p<5>(ws, n_total, n_cell, prm, emit, s);
-    case 6: return launch_bin_p<6>(ws, n_total, n_cell, prm, emit, s);
+    case 0: return launch_bin_p<0>(ws, n_total, n_cell, prm, emit, cap, s);
+    case 1: return launch_bin_p<1>(ws, n_total, n_cell, prm, emit, cap, s);
+    case 2: return launch_bin_p<2>(ws, n_total, n_cell, prm, emit, cap, s);
+    case 3: return launch_bin_p<3>(ws, n_total, n_cell, prm, emit, cap, s);
+    case 4: return launch_bin_p<4>(ws, n_total, n_cell, prm, emit, cap, s);
+    case 5: return launch_bin_p<5>(ws, n_total, n_cell, prm, emit, cap, s);
+    case 6: return launch_bin_p<6>(ws, n_total, n_cell, prm, emit, cap, s);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_count_tiles(int P, const Workspace &ws, int n_total, int n_cell, const Params &prm, hipStream_t s) {
-  return launch_bin(P, ws, n_total, n_cell, prm, false, s);
+  return launch_bin(P, ws, n_total, n_cell, prm, false, 0u, s);
 }
 
-hipError_t launch_emit_tiles(int P, const Workspace &ws, int n_total, int n_cell, const Params &prm, hipStream_t s) {
-  return launch_bin(P, ws, n_total, n_cell, prm, true, s);
+hipError_t launch_emit_tiles(int P, const Workspace &ws, int n_total, int n_cell, const Params &prm, hipStream_t s,
+                             uint32_t cap) {
+  return launch_bin(P, ws, n_total, n_cell, prm, true, cap, s);
 }
 
+// keys >= nlists (the padding of a planned launch, sorted to the end) belong to no list
 hipError_t launch_tile_ranges(const uint32_t *keys, int npairs, uint32_t *ranges, int ntiles, hipStream_t s) {
-  const size_t m = 2 * (size_t)ntiles;
+  const size_t m = 2 * (size_t)ntiles + 2;
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, ranges, m, 0u);
   if (npairs > 0)
-    hipLaunchKernelGGL(k_tile_ranges, dim3((npairs + 255) / 256), dim3(256), 0, s, keys, npairs, ranges);
+    hipLaunchKernelGGL(k_tile_ranges, dim3((npairs + 255) / 256), dim3(256), 0, s, keys, npairs, ranges,
+                       (uint32_t)ntiles);
+  return hipGetLastError();
+}
+
+// p[i] = v for *n_dev <= i < cap (the unused tail of a planned launch's buffer)
+__global__ void k_fill_tail_u32(uint32_t *__restrict__ p, const uint32_t *__restrict__ n_dev, size_t cap, uint32_t v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cap && i >= (size_t)*n_dev) p[i] = v;
+}
+
+hipError_t launch_fill_tail(uint32_t *p, const uint32_t *n_dev, size_t cap, uint32_t v, hipStream_t s) {
+  if (cap == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_tail_u32, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, p, n_dev, cap, v);
   return hipGetLastError();
 }
 
@@ -221,10 +251,15 @@ __global__ void k_seg_count(const uint32_t *__restrict__ ranges, int ntiles, int
 }
 
 // seg_off (scanned): first segment of each tile, then the total; seg_tile[s] = tile of s
-__global__ void k_seg_map(const uint32_t *__restrict__ seg_off, int ntiles, uint32_t *__restrict__ seg_tile) {
+// cap (planned launches): no entry at or past it is written; a total above it sets
+// overflow[0]
+__global__ void k_seg_map(const uint32_t *__restrict__ seg_off, int ntiles, uint32_t *__restrict__ seg_tile,
+                          uint32_t cap, unsigned long long *__restrict__ overflow) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ntiles) return;
-  for (uint32_t s = seg_off[t]; s < seg_off[t + 1]; ++s) seg_tile[s] = (uint32_t)t;
+  if (cap && t == 0 && seg_off[ntiles] > cap) overflow[0] = 1ull;
+  const uint32_t e = cap ? min(seg_off[t + 1], cap) : seg_off[t + 1];
+  for (uint32_t s = seg_off[t]; s < e; ++s) seg_tile[s] = (uint32_t)t;
 }
 
 // One wave per segment, one lane per pixel of the segment's 8x8 tile.  The segment's
@@ -451,8 +486,9 @@ hipError_t launch_segments(const Workspace &ws, int nlists, int L, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_segment_map(const Workspace &ws, int nlists, hipStream_t s) {
-  hipLaunchKernelGGL(k_seg_map, dim3((nlists + 255) / 256), dim3(256), 0, s, ws.seg_off, nlists, ws.seg_tile);
+hipError_t launch_segment_map(const Workspace &ws, int nlists, hipStream_t s, uint32_t cap) {
+  hipLaunchKernelGGL(k_seg_map, dim3((nlists + 255) / 256), dim3(256), 0, s, ws.seg_off, nlists, ws.seg_tile, cap,
+                     ws.counters + kOverflow);
   return hipGetLastError();
 }
 

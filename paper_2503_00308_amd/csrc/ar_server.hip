@@ -216,7 +216,8 @@ int ar_server_submit(ar_server *srv, int32_t scene_id, const ar_intrinsics *intr
   if (rc) return rc;
   rc = ar::check_outputs(lo_rgb, hi_rgb);
   if (rc) return rc;
-  q->P = ar::pose_vars(box, &q->rotates);
+  rc = ar::render_vars(scene, box, &q->rotates, &q->P);
+  if (rc) return rc;
   if (!q->rotates && q->P > 3) return ar::fail(AR_E_INVALID, "more than 3 translation variables");
   q->scene = scene_id;
   q->box = *box;

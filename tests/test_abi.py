@@ -49,7 +49,8 @@ def test_struct_layout_matches_c(tmp_path):
     src = tmp_path / "layout.c"
     structs = {"ar_scene_desc": api.SceneDesc, "ar_intrinsics": api.Intrinsics, "ar_pose_box": api.PoseBox,
                "ar_options": api.Options, "ar_stats": api.Stats, "ar_server_config": api.ServerConfig,
-               "ar_query_result": api.QueryResult, "ar_server_stats": api.ServerStats}
+               "ar_query_result": api.QueryResult, "ar_server_stats": api.ServerStats,
+               "ar_scene_set": api.SceneSet}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')

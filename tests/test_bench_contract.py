@@ -33,3 +33,10 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     line = json.loads(r.stdout.strip().splitlines()[-1])
     assert line["n_gpus"] == 2 and "error" in line
+
+
+def test_cpu_baseline_runs_on_several_workers():
+    from paper_2503_00308_amd import synth
+    scene, intr, box, _ = synth.config(1)
+    r = bench.cpu_baseline(scene, intr, box, budget_s=0.5, workers=2)
+    assert r["cores"] == 2 and r["kind"] == "oracle" and r["value"] > 0 and "worker" in r["sample"]

@@ -125,3 +125,25 @@ def test_layout_switches_bit_identical_and_pinned(case):
     print(f"[{case}] renders with windows longer than 64 positions: {n_long}", flush=True)
     if case != "P1":
         assert n_long > 0
+
+
+def test_run_limit_regroups_lists_bit_identical():
+    """A list group whose Ind runs exceed group_runs (the uint32 offsets at full size) is cut
+    into smaller groups of whole lists and done again: the same images bit for bit; a
+    single list over the limit is rejected."""
+    api = _api()
+    scene = synth.random_scene(400, seed=8)
+    intr = synth.intrinsics(64)
+    box = synth.camera6_box(dt=0.01, drot=np.deg2rad(0.3))
+    h = api.Scene(scene)
+    base = _render(api, h, intr, box)
+    runs = int(base[2]["runs"])
+    print(f"runs {runs}, list entries {base[2]['tile_pairs']}", flush=True)
+    for cap in (runs // 2, runs // 5):
+        lo, hi, st = _render(api, h, intr, box, {"group_runs": cap})
+        assert np.array_equal(lo, base[0]) and np.array_equal(hi, base[1]), cap
+        assert st["runs"] == runs
+    with pytest.raises(api.ARError) as ei:
+        _render(api, h, intr, box, {"group_runs": 1})
+    assert ei.value.code == api.AR_E_UNSUPPORTED and "one tile list" in str(ei.value)
+    h.close()

@@ -128,9 +128,11 @@ def test_example1_adjugate_wider_than_matrixinv():
     assert g["width_adjugate_paper"] > g["width_matrixinv_paper"] > g["width_empirical_paper"]
 
 
-def test_adjugate_scene_sound_and_wider():
-    """The adjugate inverse in the whole pipeline: sound at sampled poses and no tighter on
-    average than MatrixInv (the image-level form of Example 'matinv-vs-direct')."""
+def test_adjugate_scene_sound():
+    """The adjugate inverse in the whole pipeline: sound at sampled poses.  On this
+    translation case it is no tighter on average than MatrixInv; on relational inputs in
+    general it can be (Example 'matinv-vs-direct' ranks them on a constant interval
+    matrix), so that comparison is this case's, not a law."""
     sc = synth.random_scene(24, seed=3)
     intr = synth.intrinsics(24)
     box = synth.camera6_box(dt=0.04)
