@@ -122,9 +122,12 @@ typedef struct {
  *               single list gets its own launch)
  *   cells_per_launch  ar_render_batch: pose cells per launch (default: as many as fit a
  *               workspace of about 4 GiB, at most 256)
- *   t_min       stop a tile once every pixel's transmittance upper bound is below it,
- *               widening the upper bound by that transmittance (default 1e-7;
- *               negative disables)
+ *   t_min       translation boxes: stop a tile once every pixel's transmittance upper
+ *               bound is below it, widening the upper bound by that transmittance;
+ *               rotation boxes: take an entry's lower transmittance as 0 where its bound
+ *               through the list positions surely in front of it, times the list's
+ *               length, is below t_min (the lower bound moves by less than t_min);
+ *               default 1e-7, negative disables both
  *   abs_sums, ind_copy, ind_masks   rotation boxes: switches of three layouts the
  *               library otherwise picks from the size of the call (0 = automatic,
  *               1 = on, 2 = off; any other value is rejected).  They change the speed,

@@ -273,6 +273,15 @@ static int ensure_rot_segments(Workspace &ws, size_t nlists, size_t nseg) {
   return AR_OK;
 }
 
+// rotation path: list totals of log(1 - a_lo) for nl lists of one launch
+static int ensure_listlo(Workspace &ws, size_t nl) {
+  if (nl <= ws.cap_listlo && ws.listlo) return AR_OK;
+  const size_t need = nl + nl / 4 + 64;
+  HIP_TRY(grow(ws, ws.listlo, need * kTilePix));
+  ws.cap_listlo = need;
+  return AR_OK;
+}
+
 // rotation path: segment totals and partial colour sums for nseg segments of one launch
 static int ensure_rot_parts(Workspace &ws, size_t nseg, int P) {
   if (nseg > ws.cap_segsum || !ws.segsum) {
@@ -670,6 +679,10 @@ static int render_rotation(const ar_scene *sc, Workspace &ws, const Params &prm,
     }
     rc = ensure_rot_parts(ws, max_segs, P);
     if (rc) return rc;
+    size_t max_nl = 0;
+    for (const RotChunk &c : chunks) max_nl = std::max(max_nl, (size_t)c.nl);
+    rc = ensure_listlo(ws, max_nl);
+    if (rc) return rc;
     HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, pa, ng, prm.ind_window, kRunsEmit, masks,
                         compact, s));
     if (first_pixel_chunk && ws.ev[1]) HIP_TRY(hipEventRecord(ws.ev[1], s));
@@ -845,6 +858,8 @@ int ensure_planned(Workspace &ws, const ar_scene *sc, const Params &prm, int nce
   rc = ensure_prefix(ws, caps.entries);
   if (rc) return rc;
   rc = ensure_rot_parts(ws, caps.segments, P);
+  if (rc) return rc;
+  rc = ensure_listlo(ws, nlists);
   if (rc) return rc;
   if (caps.compact) {
     const size_t forms = (size_t)caps.entries * (size_t)(2 * (P + 1));

@@ -700,9 +700,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   if (lane == 0) atomicAdd(&counters[6], (unsigned long long)(clock64() - c0));
 }
 
-// per list: exclusive running totals of its segments' sums (in place)
+// per list: exclusive running totals of its segments' sums (in place), and the list's
+// total of log(1 - a_lo) per pixel (listlo[k][64])
 __global__ __launch_bounds__(256) void k_rot_offsets(const uint32_t *__restrict__ seg_off, int list0, int nl, int seg0,
-                                                     double2 *__restrict__ segsum) {
+                                                     double2 *__restrict__ segsum, double *__restrict__ listlo) {
   const int lane = threadIdx.x & 63;
   const int k = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   if (k >= nl) return;
@@ -714,6 +715,7 @@ __global__ __launch_bounds__(256) void k_rot_offsets(const uint32_t *__restrict_
     al += t.x;
     ah += t.y;
   }
+  listlo[(size_t)k * 64 + lane] = al;
 }
 
 // Running sums made absolute: each segment's offset (the totals of the list's segments
@@ -753,7 +755,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                    const uint32_t *__restrict__ runs, Params prm,
                                                    const double *__restrict__ preL, const double *__restrict__ preH,
                                                    const double2 *__restrict__ segoff, double *__restrict__ part,
-                                                   unsigned long long *__restrict__ counters) {
+                                                   unsigned long long *__restrict__ counters,
+                                                   const double *__restrict__ listlo, int list0,
+                                                   const uint32_t *__restrict__ win) {
   using R = Rec<P>;
   using Q = Part<P>;
   constexpr int F = P + 1;
@@ -776,8 +780,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   Acc<P> acc;
   acc_zero<P>(acc);
   unsigned npairs = 0;
+  // When no pair of the list has a positive lower alpha at any pixel of the tile (every
+  // log(1 - a_lo) is 0, so the list's total is exactly 0), every sum over the runs of
+  // certain occluders is exactly 0 and their run ends are not read.
+  const bool zero_lo = __all(listlo[(size_t)(r.list - list0) * 64 + lane] == 0.0);
   Lookahead la;
   uint32_t cv0 = 0, cv1 = 0, cv2 = 0;   // run offsets of the looked-ahead positions
+  uint32_t pv = 0;                      // their Ind window starts
   for (int i = r.i0; i < r.i1; ++i) {
     const int k = (i - r.i0) & 63;
     if (k == 0) {
@@ -787,12 +796,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         cv0 = cnt[sl2];
         cv1 = cnt[sl2 + 1];
         cv2 = cnt[sl2 + 2];
+        pv = win[sl2];
       }
     }
     const uint32_t gid = la.gid(k);
     const double *rec = recs + (size_t)gid * R::STRIDE;
     const int type = la.type(k);
     const bool kept = inimg && la.kept(k, type, ux, uy);
+    // The list positions [0, ps) before the entry's Ind window are surely (so possibly) in
+    // front of it, so T_lo <= prod_{[0, ps)} (1 - a_hi).  When that bound times the number
+    // of list entries is below t_min, T_lo is taken as 0 (a lower transmittance, so sound;
+    // the lower bound moves by less than t_min over the list) and the runs of possible
+    // occluders are not read.
+    bool tlo_zero = false;
+    if (prm.t_min > 0.0) {
+      const uint32_t ps = (uint32_t)__builtin_amdgcn_readlane((int)pv, k);
+      if (ps > 0u) {
+        double S = preH[(pb + ps - 1) * 64 + lane];
+        if (!ABS) S += segoff[(size_t)(sl + (int)(ps - 1) / L) * 64 + lane].y;
+        tlo_zero = exp(S + nn * 0x1p-51 * fabs(S)) * (1.0 + 0x1p-50) * nn < prm.t_min;
+      }
+    }
     // runs of certain occluders and of possible occluders: sums of the logs over
     // [a, b) = S(b - 1) - S(a - 1), S(p) for p >= 1 the running sum at index
     // (pb + p - 1) * 64 + lane, plus (unless ABS) the offset of the segment holding p - 1
@@ -812,7 +836,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       auto ix = [&](uint32_t p) -> size_t { return pb + (p > 0 ? p - 1 : 0); };
       const uint2 *runs2 = reinterpret_cast<const uint2 *>(runs);
       constexpr int kRunGroup = 8;
-      for (uint32_t qb = d0; qb < d1; qb += 64) {
+      for (uint32_t qb = d0; qb < (zero_lo ? d0 : d1); qb += 64) {
         const int nq = (int)min(64u, d1 - qb);
         uint2 abv = make_uint2(0u, 0u);
         if (lane < nq) abv = runs2[qb + lane];
@@ -836,7 +860,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
           }
         }
       }
-      for (uint32_t qb = m0; qb < m1; qb += 64) {
+      const uint32_t m1r = __all(!kept || tlo_zero) ? m0 : m1;   // possible occluders' runs read
+      for (uint32_t qb = m0; qb < m1r; qb += 64) {
         const int nq = (int)min(64u, m1 - qb);
         uint2 abv = make_uint2(0u, 0u);
         if (lane < nq) abv = runs2[qb + lane];
@@ -863,7 +888,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     } else {
       // few runs per entry: one run at a time, kept lanes only
       if (!kept) continue;
-      for (uint32_t q = d0; q < d1; ++q) {
+      for (uint32_t q = d0; q < (zero_lo ? d0 : d1); ++q) {
         const uint2 ab = *reinterpret_cast<const uint2 *>(runs + 2 * (size_t)q);
         double La = 0.0, Lb = 0.0;
         if (ab.x > 0) La = sL[(pb + ab.x - 1) * 64] + segoff[(size_t)(sl + (int)(ab.x - 1) / L) * 64 + lane].x;
@@ -871,7 +896,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         sum_l += Lb - La;
         err_l += fabs(La) + fabs(Lb);
       }
-      for (uint32_t q = m0; q < m1; ++q) {
+      for (uint32_t q = m0; q < (tlo_zero ? m0 : m1); ++q) {
         const uint2 ab = *reinterpret_cast<const uint2 *>(runs + 2 * (size_t)q);
         double La = 0.0, Lb = 0.0;
         if (ab.x > 0) La = sH[(pb + ab.x - 1) * 64] + segoff[(size_t)(sl + (int)(ab.x - 1) / L) * 64 + lane].y;
@@ -882,7 +907,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
     if (!kept) continue;
     const double thi = exp(sum_l + nn * 0x1p-51 * err_l) * (1.0 + 0x1p-50);
-    const double tlo = exp(sum_h - nn * 0x1p-51 * err_h) * (1.0 - 0x1p-50);
+    const double tlo = tlo_zero ? 0.0 : exp(sum_h - nn * 0x1p-51 * err_h) * (1.0 - 0x1p-50);
     double alo, ahi;
     pair_contrib<P>(rec, type, uxd, uyd, tlo, fmin(thi, 1.0), acc, alo, ahi, exp_table(gid));
     ++npairs;
@@ -1042,17 +1067,17 @@ static hipError_t launch_rot_p(const Workspace &ws, const uint32_t *lists, const
     hipLaunchKernelGGL(k_rot_prefix<P>, grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off, ws.seg_tile, c.L,
                        c.seg0, c.nseg, c.pos0, prm, preL, preH, (double2 *)ws.segsum, ws.counters);
     hipLaunchKernelGGL(k_rot_offsets, dim3((unsigned)((c.nl + 3) / 4)), blk, 0, s, ws.seg_off, c.list0, c.nl, c.seg0,
-                       (double2 *)ws.segsum);
+                       (double2 *)ws.segsum, ws.listlo);
     if (c.absolute) {
       hipLaunchKernelGGL(k_rot_absolute, grid, blk, 0, s, ws.tile_range, ws.seg_off, ws.seg_tile, c.L, c.seg0, c.nseg,
                          c.pos0, (const double2 *)ws.segsum, preL, preH);
       hipLaunchKernelGGL((k_rot_blend<P, true>), grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off,
                          ws.seg_tile, c.L, c.seg0, c.nseg, c.pos0, c.gbase, ws.run_cnt, ws.runs, prm, preL,
-                         preH, (const double2 *)ws.segsum, ws.part, ws.counters);
+                         preH, (const double2 *)ws.segsum, ws.part, ws.counters, ws.listlo, c.list0, ws.win);
     } else {
       hipLaunchKernelGGL((k_rot_blend<P, false>), grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off,
                          ws.seg_tile, c.L, c.seg0, c.nseg, c.pos0, c.gbase, ws.run_cnt, ws.runs, prm, preL, preH,
-                         (const double2 *)ws.segsum, ws.part, ws.counters);
+                         (const double2 *)ws.segsum, ws.part, ws.counters, ws.listlo, c.list0, ws.win);
     }
   }
   hipLaunchKernelGGL(k_rot_merge<P>, dim3((unsigned)c.nl), dim3(192), 0, s, ws.tile_range, ws.seg_off, c.list0, c.seg0,

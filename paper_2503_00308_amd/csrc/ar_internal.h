@@ -216,6 +216,8 @@ struct Workspace {
   size_t cap_host_seg = 0;
   double *segsum = nullptr;          // [segments][64][2] segment totals, then offsets
   size_t cap_segsum = 0;
+  double *listlo = nullptr;          // [lists of a launch][64] list totals of log(1 - a_lo)
+  size_t cap_listlo = 0;
   // Arena mode (the allocation-free entry point): buffers are carved from [arena,
   // arena + arena_cap) by a bump pointer instead of hipMalloc; nothing is freed, pinned
   // host blocks and events are not created (pose_host / host_counters point to host

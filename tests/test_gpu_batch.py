@@ -154,7 +154,9 @@ def test_autotune_segment_length():
     assert np.array_equal(lo[0].cpu().numpy(), l2.cpu().numpy()) and np.array_equal(hi[0].cpu().numpy(),
                                                                                       h2.cpu().numpy())
     l0, h0, _ = api.render_bounds(sc, intr, box)
-    assert np.abs(l0.cpu().numpy() - l2.cpu().numpy()).max() <= 1e-12
+    # another segment length sums in another order: FP64 rounding, then directed rounding to
+    # float32 (one float32 ulp of a small lower bound)
+    assert np.abs(l0.cpu().numpy() - l2.cpu().numpy()).max() <= 1e-9
     assert np.abs(h0.cpu().numpy() - h2.cpu().numpy()).max() <= 2e-7
     sc.close()
     scene = synth.box_surface_scene(1500, n_boxes=8, seed=32)

@@ -223,7 +223,9 @@ def test_rotation_pixel_loop_in_chunks_of_lists():
 def test_ind_windows_equal_testing_every_pair(case):
     """The depth windows outside which Ind is decided without the pairwise test are
     exact: the box window, the split window and testing every pair of each tile list
-    give the same bounds, bit for bit."""
+    give the same bounds, bit for bit, with the cut-offs of negligible transmittances off
+    (t_min < 0).  With them on (the default), a window start also bounds the lower
+    transmittance, so the lower images may move by less than t_min = 1e-7."""
     if case == "boxes":
         sc = synth.box_surface_scene(1500, n_boxes=12, seed=7)
         intr = synth.intrinsics(48)
@@ -232,14 +234,18 @@ def test_ind_windows_equal_testing_every_pair(case):
         sc = synth.box_surface_scene(1200, n_boxes=8, seed=8)
         intr = synth.intrinsics(40)
         box = synth.orbit_cells(4, 30.0, seed=6)[1]
-    full = _run(sc, intr, box, {"ind_window": 2})
-    boxw = _run(sc, intr, box, {"ind_window": 1})
-    split = _run(sc, intr, box, {"ind_window": 0})
+    full = _run(sc, intr, box, {"ind_window": 2, "t_min": -1.0})
+    boxw = _run(sc, intr, box, {"ind_window": 1, "t_min": -1.0})
+    split = _run(sc, intr, box, {"ind_window": 0, "t_min": -1.0})
     print(f"[{case}] windows: every pair {full[2]['max_window']}, box {boxw[2]['max_window']}, "
           f"split {split[2]['max_window']}; runs {full[2]['runs']} {boxw[2]['runs']} {split[2]['runs']}", flush=True)
     assert split[2]["max_window"] <= boxw[2]["max_window"] <= full[2]["max_window"]
     for lo, hi, _ in (boxw, split):
         assert np.array_equal(lo, full[0]) and np.array_equal(hi, full[1])
+    for w in (0, 1, 2):
+        lo, hi, _ = _run(sc, intr, box, {"ind_window": w})
+        assert np.array_equal(hi, full[1])
+        assert np.all(lo <= full[0]) and (full[0] - lo).max() <= 2e-7   # t_min and a float32 ulp
 
 
 def test_full_size_workload3_sampled_tiles():
