@@ -233,11 +233,14 @@ static int ensure_general(Workspace &ws, size_t npairs) {
   return AR_OK;
 }
 
-// per-pixel prefix sums for `entries` list entries
-static int ensure_prefix(Workspace &ws, size_t entries) {
-  if (entries <= ws.cap_pre && ws.pre) return AR_OK;
-  const size_t need = entries + entries / 8 + 64;
-  HIP_TRY(grow(ws, ws.pre, need * kTilePix * 2));
+// per-pixel prefix sums: `rows` rows of 64 doubles in each of three planes, the running
+// sums of log(1 - a_lo) and of log(1 - a_hi), then the transmittance bounds (a float pair
+// per pixel); a launch of the pixel loop takes one row per list entry and one zero row per
+// list
+static int ensure_prefix(Workspace &ws, size_t rows) {
+  if (rows <= ws.cap_pre && ws.pre) return AR_OK;
+  const size_t need = rows + rows / 8 + 64;
+  HIP_TRY(grow(ws, ws.pre, need * kTilePix * 3));
   ws.cap_pre = need;
   return AR_OK;
 }
@@ -385,7 +388,7 @@ size_t query_bytes(const ar_scene *sc, const Params &prm, int P, bool rotates, i
     b += std::min(1.25 * g * 8.0 * d.mask_words_per_entry, kMaskBytes);         // stored masks
     if (d.compact || prm.ind_copy == 1) b += 1.25 * g * (16.0 * (P + 1) + 16.0);   // compact copy
     const double pre = prm.prefix_entries > 0 ? (double)prm.prefix_entries : (double)kPrefixEntries;
-    b += 1.125 * std::min(pairs, pre) * 64.0 * 16.0;                // prefix sums (two planes)
+    b += 1.125 * std::min(pairs + lists, pre) * 64.0 * 24.0;        // prefix sums and transmittances
     const double segs = pairs / kRotSegment + lists;
     b += 1.25 * segs * 4.0 + 1.25 * std::min(segs, (double)kRotChunkSegs) * (8.0 * part_fields(P) * 64.0 + 16.0 * 64.0);
   } else {
@@ -513,7 +516,7 @@ static int render_rotation(const ar_scene *sc, Workspace &ws, const Params &prm,
       longest = std::max(longest, nl);
       nseg_total += (nl + (size_t)L - 1) / (size_t)L;
     }
-    int r = ensure_prefix(ws, std::min<size_t>(npairs, std::max(want, longest)));
+    int r = ensure_prefix(ws, std::min<size_t>(npairs + nlists, std::max(want, longest + 1)));
     if (r) return r;
     r = ensure_rot_segments(ws, nlists, nseg_total);
     if (r) return r;
@@ -640,7 +643,9 @@ static int render_rotation(const ar_scene *sc, Workspace &ws, const Params &prm,
     rc = ensure_runs(ws, nruns);
     if (rc) return rc;
     // chunks of consecutive lists of the group with at most cap entries and kRotChunkSegs
-    // segments (or one longer list)
+    // segments (or one longer list), whose rows (entries plus one zero row per list up to
+    // the last non-empty one) fit the prefix planes; leading empty lists that would not
+    // fit with the next list form a chunk of their own
     const bool absolute =
         prm.abs_sums == 1 || (prm.abs_sums == 0 && (double)nruns >= kAbsoluteRuns * (double)std::max(ng, 1));
     ws.last.absolute = ws.last.absolute || absolute;
@@ -652,11 +657,14 @@ static int render_rotation(const ar_scene *sc, Workspace &ws, const Params &prm,
       bool have = false;
       while (l1 < lb) {
         const uint32_t b = R[2 * l1], e = R[2 * l1 + 1];
+        const size_t rows = (size_t)(l1 - l) + 1;   // zero rows up to this list
         if (e > b) {
           if (!have) {
+            if (l1 > l && (size_t)(e - b) + rows > ws.cap_pre) break;
             pos0 = b;
             have = true;
-          } else if ((size_t)(e - pos0) > cap || so[l1 + 1] - so[l] > kRotChunkSegs) {
+          } else if ((size_t)(e - pos0) > cap || (size_t)(e - pos0) + rows > ws.cap_pre ||
+                     so[l1 + 1] - so[l] > kRotChunkSegs) {
             break;
           }
         }
@@ -855,7 +863,7 @@ int ensure_planned(Workspace &ws, const ar_scene *sc, const Params &prm, int nce
   if (rc) return rc;
   rc = ensure_runs(ws, caps.runs);
   if (rc) return rc;
-  rc = ensure_prefix(ws, caps.entries);
+  rc = ensure_prefix(ws, (size_t)caps.entries + nlists);
   if (rc) return rc;
   rc = ensure_rot_parts(ws, caps.segments, P);
   if (rc) return rc;

@@ -642,6 +642,20 @@ struct SegRef {
   int list, beg, n, i0, i1;
 };
 
+// Workgroups are handed to the eight XCDs round robin (block b runs on XCD b % 8), and
+// each XCD has its own L2.  xcd_block renumbers the blocks so that every XCD takes runs of
+// kXcdChunk consecutive logical blocks: the waves of one tile list then share one L2.
+// A bijection of [0, nb); the blocks past the last whole round keep their numbers.
+constexpr int kXcds = 8;
+constexpr int kXcdChunk = 32;
+
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  constexpr int per = kXcds * kXcdChunk;
+  if (b >= nb / per * per) return b;
+  const int round = b / per, r = b % per;
+  return round * per + (r % kXcds) * kXcdChunk + r / kXcds;
+}
+
 __device__ __forceinline__ SegRef seg_ref(const uint32_t *__restrict__ ranges, const uint32_t *__restrict__ seg_off,
                                           const uint32_t *__restrict__ seg_tile, int s, int L) {
   SegRef r;
@@ -653,15 +667,24 @@ __device__ __forceinline__ SegRef seg_ref(const uint32_t *__restrict__ ranges, c
   return r;
 }
 
+// Rows of the per-pixel running sums (64 doubles each, one per pixel): the lists of a
+// launch in order, each a row S(0) = 0 followed by S(1) .. S(n), S(p) the sum over list
+// positions [0, p).  A list's first row is at its entry offset in the launch plus its
+// index among the launch's lists.
+__device__ __forceinline__ size_t row0(const SegRef &r, uint32_t pos0, int list0) {
+  return (size_t)((uint32_t)r.beg - pos0) + (size_t)(r.list - list0);
+}
+
 // A: per pixel, running sums of log(1 - a_lo) and log(max(1 - a_hi, 2^-60)) over the
-// segment (from zero at its start), and the segment totals.
+// segment (from zero at its start), and the segment totals; the list's first segment
+// also writes its zero row.
 template <int P>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rot_prefix(const double *__restrict__ recs,
                                                     const uint32_t *__restrict__ ranges,
                                                     const uint32_t *__restrict__ lists,
                                                     const uint32_t *__restrict__ seg_off,
                                                     const uint32_t *__restrict__ seg_tile, int L, int seg0, int nseg,
-                                                    uint32_t pos0, Params prm, double *__restrict__ preL,
+                                                    uint32_t pos0, int list0, Params prm, double *__restrict__ preL,
                                                     double *__restrict__ preH, double2 *__restrict__ segsum,
                                                     unsigned long long *__restrict__ counters) {
   using R = Rec<P>;
@@ -678,7 +701,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const double uxd = (double)col + 0.5 - prm.cx, uyd = (double)row + 0.5 - prm.cy;
   const float ux = (float)uxd, uy = (float)uyd;
   const uint32_t *items = lists + r.beg;
-  const size_t pb = (size_t)((uint32_t)r.beg - pos0);
+  const size_t rb = row0(r, pos0, list0) + 1;   // row of S(1)
+  // (an empty list has no rows: the padding segments of a planned launch belong to one)
+  if (r.i0 == 0 && r.n > 0) {
+    preL[(rb - 1) * 64 + lane] = 0.0;
+    preH[(rb - 1) * 64 + lane] = 0.0;
+  }
   double Ll = 0.0, Lh = 0.0;
   Lookahead la;
   for (int j = r.i0; j < r.i1; ++j) {
@@ -693,8 +721,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       Ll += log(1.0 - alo);
       Lh += log(ahi >= 1.0 ? kZeroFactor : 1.0 - ahi);
     }
-    preL[(pb + j) * 64 + lane] = Ll;
-    preH[(pb + j) * 64 + lane] = Lh;
+    preL[(rb + j) * 64 + lane] = Ll;
+    preH[(rb + j) * 64 + lane] = Lh;
   }
   segsum[(size_t)w * 64 + lane] = make_double2(Ll, Lh);
   if (lane == 0) atomicAdd(&counters[6], (unsigned long long)(clock64() - c0));
@@ -724,40 +752,196 @@ __global__ __launch_bounds__(256) void k_rot_offsets(const uint32_t *__restrict_
 __global__ __launch_bounds__(256) void k_rot_absolute(const uint32_t *__restrict__ ranges,
                                                       const uint32_t *__restrict__ seg_off,
                                                       const uint32_t *__restrict__ seg_tile, int L, int seg0,
-                                                      int nseg, uint32_t pos0, const double2 *__restrict__ segoff,
-                                                      double *__restrict__ preL, double *__restrict__ preH) {
+                                                      int nseg, uint32_t pos0, int list0,
+                                                      const double2 *__restrict__ segoff, double *__restrict__ preL,
+                                                      double *__restrict__ preH) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   if (w >= nseg) return;
   const SegRef r = seg_ref(ranges, seg_off, seg_tile, seg0 + w, L);
   if (r.i0 == 0) return;   // the list's first segment: nothing in front
   const double2 o = segoff[(size_t)w * 64 + lane];
-  const size_t pb = (size_t)((uint32_t)r.beg - pos0);
+  const size_t rb = row0(r, pos0, list0) + 1;
   for (int j = r.i0; j < r.i1; ++j) {
-    const size_t x = (pb + j) * 64 + lane;
+    const size_t x = (rb + j) * 64 + lane;
     preL[x] += o.x;
     preH[x] += o.y;
   }
 }
 
-// B: transmittances from the runs (absolute: everything in front of the Gaussian),
-// colour forms accumulated per segment; the tile's bounds are the sum of its segments.
+// B1 (k_rot_trans): the transmittance bounds of every (entry, pixel) from the runs
+// (absolute: everything in front of the Gaussian), stored as floats rounded outward (T_lo
+// down, T_hi up: any T' in [0, T] gives a lower colour form below T a_i c_i, as the alpha
+// lower form is below a_i >= 0, and the same above for T_hi), one row per entry in the
+// third plane.
 // Run counts (then offsets) cnt and the runs are those of the list group that starts at
 // list position gbase.
+// Every entry's transmittances come from the list's running sums, so any split of a
+// list's entries over its K waves gives the same values.  Wave k of the list takes
+// positions k, k + K, k + 2K, ...: the waves of a list then advance through the list side
+// by side, and the run ends they read (within the entries' Ind windows) lie in one band of
+// positions that the L2 of their XCD holds (xcd_block), where contiguous segments would
+// spread the reads over the whole list.  The kernel holds few registers, so many waves
+// keep their run-end loads in flight together.
 // ABS: the running sums were made absolute (k_rot_absolute); otherwise each run end
 // adds its segment's offset here.
 template <int P, bool ABS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rot_blend(const double *__restrict__ recs, const uint32_t *__restrict__ ranges,
+__global__ __launch_bounds__(256) void k_rot_trans(const double *__restrict__ recs, const uint32_t *__restrict__ ranges,
                                                    const uint32_t *__restrict__ lists,
                                                    const uint32_t *__restrict__ seg_off,
                                                    const uint32_t *__restrict__ seg_tile, int L, int seg0, int nseg,
                                                    uint32_t pos0, uint32_t gbase, const uint32_t *__restrict__ cnt,
                                                    const uint32_t *__restrict__ runs, Params prm,
                                                    const double *__restrict__ preL, const double *__restrict__ preH,
-                                                   const double2 *__restrict__ segoff, double *__restrict__ part,
+                                                   const double2 *__restrict__ segoff, float2 *__restrict__ tpl,
                                                    unsigned long long *__restrict__ counters,
                                                    const double *__restrict__ listlo, int list0,
                                                    const uint32_t *__restrict__ win) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(
+      (int)(xcd_block((int)blockIdx.x, (int)gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+  if (w >= nseg) return;
+  const long long c0 = clock64();
+  const SegRef r = seg_ref(ranges, seg_off, seg_tile, seg0 + w, L);
+  // this wave's positions: sidx + m K for m < nent
+  const int sidx = r.i0 / L;
+  const int K = r.n > 0 ? (int)(seg_off[r.list + 1] - seg_off[r.list]) : 1;
+  const int nent = r.n > sidx ? (r.n - sidx + K - 1) / K : 0;
+  const int ntiles = prm.ntx * prm.nty;
+  const int tile = r.list % ntiles;
+  const int tx = tile % prm.ntx, ty = tile / prm.ntx;
+  const int col = tx * kTile + (lane & 7), row = ty * kTile + (lane >> 3);
+  const bool inimg = col < prm.width && row < prm.height;
+  const float ux = (float)((double)col + 0.5 - prm.cx), uy = (float)((double)row + 0.5 - prm.cy);
+  const uint32_t *items = lists + r.beg;
+  const size_t rb = row0(r, pos0, list0);          // row of S(0)
+  const double nn = (double)(r.n + 2);
+  const int sl = (int)seg_off[r.list] - seg0;     // the list's first segment, relative
+  // When no pair of the list has a positive lower alpha at any pixel of the tile (every
+  // log(1 - a_lo) is 0, so the list's total is exactly 0), every sum over the runs of
+  // certain occluders is exactly 0 and their run ends are not read.
+  const bool zero_lo = __all(listlo[(size_t)(r.list - list0) * 64 + lane] == 0.0);
+  Lookahead la;
+  uint32_t cv0 = 0, cv1 = 0, cv2 = 0;   // run offsets of the looked-ahead positions
+  uint32_t pv = 0;                      // their Ind window starts
+  for (int m = 0; m < nent; ++m) {
+    const int k = m & 63;
+    const int i = sidx + m * K;
+    if (k == 0) {
+      const int pl = sidx + (m + lane) * K;   // position looked ahead by this lane
+      la.fetch<P>(recs, items, pl, r.n);
+      if (pl < r.n) {
+        const size_t sl2 = 2 * (size_t)((uint32_t)(r.beg + pl) - gbase);
+        cv0 = cnt[sl2];
+        cv1 = cnt[sl2 + 1];
+        cv2 = cnt[sl2 + 2];
+        pv = win[sl2];
+      }
+    }
+    const int type = la.type(k);
+    const bool kept = inimg && la.kept(k, type, ux, uy);
+    // The list positions [0, ps) before the entry's Ind window are surely (so possibly) in
+    // front of it, so T_lo <= prod_{[0, ps)} (1 - a_hi).  When that bound times the number
+    // of list entries is below t_min, T_lo is taken as 0 (a lower transmittance, so sound;
+    // the lower bound moves by less than t_min over the list) and the runs of possible
+    // occluders are not read.
+    bool tlo_zero = false;
+    if (prm.t_min > 0.0) {
+      const uint32_t ps = (uint32_t)__builtin_amdgcn_readlane((int)pv, k);
+      if (ps > 0u) {
+        double S = preH[(rb + ps) * 64 + lane];
+        if (!ABS) S += segoff[(size_t)(sl + (int)(ps - 1) / L) * 64 + lane].y;
+        tlo_zero = exp(S + nn * (0x1p-51 * fabs(S) + 0x1p-52)) * (1.0 + 0x1p-50) * nn < prm.t_min;
+      }
+    }
+    // Runs of certain occluders and of possible occluders: the log sum over [a, b) is
+    // S(b) - S(a), S(p) in row rb + p (plus, unless ABS, the offset of the segment holding
+    // position p - 1; for p = 0 the zero row and the list's first offset, also 0).  Every
+    // S(p) is <= 0, so the ends are summed apart, A = sum S(a), B = sum S(b), and
+    // |A| + |B| is the sum of the ends' magnitudes that bounds the rounding.
+    const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)cv0, k);
+    const uint32_t d1 = (uint32_t)__builtin_amdgcn_readlane((int)cv1, k);
+    const uint32_t m0 = d1, m1 = (uint32_t)__builtin_amdgcn_readlane((int)cv2, k);
+    double A_l = 0.0, B_l = 0.0, A_h = 0.0, B_h = 0.0;
+    if (ABS) {
+      // many runs per entry: the runs are read 64 at a time (one per lane) and their ends
+      // eight runs at a time, so sixteen loads are in flight; the sums are taken in run
+      // order.  The run ends are read back with readlane from the lane that loaded them,
+      // so every lane takes part (a lane whose pixel is not kept uses none of the sums);
+      // entries no lane keeps are skipped as a whole.
+      if (!__any(kept)) continue;
+      const uint2 *runs2 = reinterpret_cast<const uint2 *>(runs);
+      constexpr int kRunGroup = 8;
+      // groups of kRunGroup runs; each run end is one load of a row at a wave-uniform
+      // address (the lane's pixel is the load's offset).  Lanes past the last run hold the
+      // run (0, 0), whose ends are the zero row (u + t <= 63: u < nq <= 64 in steps of 8).
+      auto run_sums = [&](const double *rows, uint32_t q0, uint32_t q1, double &A, double &B) {
+        for (uint32_t qb = q0; qb < q1; qb += 64) {
+          const int nq = (int)min(64u, q1 - qb);
+          uint2 abv = make_uint2(0u, 0u);
+          if (lane < nq) abv = runs2[qb + lane];
+          for (int u = 0; u < nq; u += kRunGroup) {
+            double La[kRunGroup], Lb[kRunGroup];
+#pragma unroll
+            for (int t = 0; t < kRunGroup; ++t) {
+              const uint32_t pa = (uint32_t)__builtin_amdgcn_readlane((int)abv.x, u + t);
+              const uint32_t pe = (uint32_t)__builtin_amdgcn_readlane((int)abv.y, u + t);
+              La[t] = (rows + (size_t)pa * 64)[lane];
+              Lb[t] = (rows + (size_t)pe * 64)[lane];
+            }
+#pragma unroll
+            for (int t = 0; t < kRunGroup; ++t) {
+              A += La[t];
+              B += Lb[t];
+            }
+          }
+        }
+      };
+      run_sums(preL + rb * 64, d0, zero_lo ? d0 : d1, A_l, B_l);
+      // possible occluders' runs, unless no kept lane needs T_lo
+      run_sums(preH + rb * 64, m0, __all(!kept || tlo_zero) ? m0 : m1, A_h, B_h);
+    } else {
+      // few runs per entry: one run at a time, kept lanes only
+      if (!kept) continue;
+      auto S_at = [&](const double *pre, uint32_t p, int half) -> double {
+        const double2 o = segoff[(size_t)(sl + (p > 0 ? (int)(p - 1) / L : 0)) * 64 + lane];
+        return pre[(rb + p) * 64 + lane] + (half ? o.y : o.x);
+      };
+      for (uint32_t q = d0; q < (zero_lo ? d0 : d1); ++q) {
+        const uint2 ab = *reinterpret_cast<const uint2 *>(runs + 2 * (size_t)q);
+        A_l += S_at(preL, ab.x, 0);
+        B_l += S_at(preL, ab.y, 0);
+      }
+      for (uint32_t q = m0; q < (tlo_zero ? m0 : m1); ++q) {
+        const uint2 ab = *reinterpret_cast<const uint2 *>(runs + 2 * (size_t)q);
+        A_h += S_at(preH, ab.x, 1);
+        B_h += S_at(preH, ab.y, 1);
+      }
+    }
+    if (!kept) continue;
+    // Rounding: a stored S(p) is within p u of the exact sum through the roundings of the
+    // factors 1 - a (the runs of one set are disjoint, so at most n u over all of them)
+    // and within (p + 2) u |S(p)| through the logs and the additions; the sums A and B
+    // and the difference add (runs + 1) u (|A| + |B|).  nn 2^-51 (|A| + |B|) + nn 2^-52
+    // covers the total, and the factor 1 +- 2^-50 the rounding of exp.
+    const double thi = exp((B_l - A_l) + nn * (0x1p-51 * (fabs(A_l) + fabs(B_l)) + 0x1p-52)) * (1.0 + 0x1p-50);
+    const double tlo =
+        tlo_zero ? 0.0 : exp((B_h - A_h) - nn * (0x1p-51 * (fabs(A_h) + fabs(B_h)) + 0x1p-52)) * (1.0 - 0x1p-50);
+    tpl[(rb + 1 + i) * 64 + lane] = make_float2(__double2float_rd(tlo), __double2float_ru(fmin(thi, 1.0)));
+  }
+  if (lane == 0) atomicAdd(&counters[7], (unsigned long long)(clock64() - c0));
+}
+
+// B2 (k_rot_blend): colour forms of every kept pair with its stored transmittances,
+// accumulated per segment; the tile's bounds are the sum over its segments.
+template <int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rot_blend(const double *__restrict__ recs, const uint32_t *__restrict__ ranges,
+                                                   const uint32_t *__restrict__ lists,
+                                                   const uint32_t *__restrict__ seg_off,
+                                                   const uint32_t *__restrict__ seg_tile, int L, int seg0, int nseg,
+                                                   uint32_t pos0, int list0, Params prm,
+                                                   const float2 *__restrict__ tpl, double *__restrict__ part,
+                                                   unsigned long long *__restrict__ counters) {
   using R = Rec<P>;
   using Q = Part<P>;
   constexpr int F = P + 1;
@@ -774,142 +958,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const double uxd = (double)col + 0.5 - prm.cx, uyd = (double)row + 0.5 - prm.cy;
   const float ux = (float)uxd, uy = (float)uyd;
   const uint32_t *items = lists + r.beg;
-  const size_t pb = (size_t)((uint32_t)r.beg - pos0);
-  const double nn = (double)(r.n + 2);
-  const int sl = (int)seg_off[r.list] - seg0;     // the list's first segment, relative
+  const float2 *trow = tpl + (row0(r, pos0, list0) + 1) * 64 + lane;   // entry j: trow[j * 64]
   Acc<P> acc;
   acc_zero<P>(acc);
   unsigned npairs = 0;
-  // When no pair of the list has a positive lower alpha at any pixel of the tile (every
-  // log(1 - a_lo) is 0, so the list's total is exactly 0), every sum over the runs of
-  // certain occluders is exactly 0 and their run ends are not read.
-  const bool zero_lo = __all(listlo[(size_t)(r.list - list0) * 64 + lane] == 0.0);
   Lookahead la;
-  uint32_t cv0 = 0, cv1 = 0, cv2 = 0;   // run offsets of the looked-ahead positions
-  uint32_t pv = 0;                      // their Ind window starts
-  for (int i = r.i0; i < r.i1; ++i) {
-    const int k = (i - r.i0) & 63;
-    if (k == 0) {
-      la.fetch<P>(recs, items, i + lane, r.i1);
-      if (i + lane < r.i1) {
-        const size_t sl2 = 2 * (size_t)((uint32_t)(r.beg + i + lane) - gbase);
-        cv0 = cnt[sl2];
-        cv1 = cnt[sl2 + 1];
-        cv2 = cnt[sl2 + 2];
-        pv = win[sl2];
-      }
-    }
+  // the next entry's transmittances are loaded while this one is evaluated (rows of
+  // entries no lane keeps were not written; their values are not used)
+  float2 tn = r.i0 < r.i1 ? trow[(size_t)r.i0 * 64] : make_float2(0.0f, 0.0f);
+  for (int j = r.i0; j < r.i1; ++j) {
+    const int k = (j - r.i0) & 63;
+    if (k == 0) la.fetch<P>(recs, items, j + lane, r.i1);
+    const float2 t = tn;
+    if (j + 1 < r.i1) tn = trow[(size_t)(j + 1) * 64];
     const uint32_t gid = la.gid(k);
     const double *rec = recs + (size_t)gid * R::STRIDE;
     const int type = la.type(k);
-    const bool kept = inimg && la.kept(k, type, ux, uy);
-    // The list positions [0, ps) before the entry's Ind window are surely (so possibly) in
-    // front of it, so T_lo <= prod_{[0, ps)} (1 - a_hi).  When that bound times the number
-    // of list entries is below t_min, T_lo is taken as 0 (a lower transmittance, so sound;
-    // the lower bound moves by less than t_min over the list) and the runs of possible
-    // occluders are not read.
-    bool tlo_zero = false;
-    if (prm.t_min > 0.0) {
-      const uint32_t ps = (uint32_t)__builtin_amdgcn_readlane((int)pv, k);
-      if (ps > 0u) {
-        double S = preH[(pb + ps - 1) * 64 + lane];
-        if (!ABS) S += segoff[(size_t)(sl + (int)(ps - 1) / L) * 64 + lane].y;
-        tlo_zero = exp(S + nn * 0x1p-51 * fabs(S)) * (1.0 + 0x1p-50) * nn < prm.t_min;
-      }
-    }
-    // runs of certain occluders and of possible occluders: sums of the logs over
-    // [a, b) = S(b - 1) - S(a - 1), S(p) for p >= 1 the running sum at index
-    // (pb + p - 1) * 64 + lane, plus (unless ABS) the offset of the segment holding p - 1
-    const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)cv0, k);
-    const uint32_t d1 = (uint32_t)__builtin_amdgcn_readlane((int)cv1, k);
-    const uint32_t m0 = d1, m1 = (uint32_t)__builtin_amdgcn_readlane((int)cv2, k);
-    const double *sL = preL + lane, *sH = preH + lane;
-    double sum_l = 0.0, err_l = 0.0, sum_h = 0.0, err_h = 0.0;
-    if (ABS) {
-      // many runs per entry: the runs are read 64 at a time (one per lane) and their ends
-      // eight runs at a time, so sixteen loads are in flight; the sums are taken in run
-      // order.  The run ends are read back with readlane from the lane that loaded them,
-      // so every lane takes part (a lane whose pixel is not kept uses none of the sums);
-      // entries no lane keeps are skipped as a whole.
-      if (!__any(kept)) continue;
-      // S(p) at the clamped index (a valid position of the list when p = 0), zero for p = 0
-      auto ix = [&](uint32_t p) -> size_t { return pb + (p > 0 ? p - 1 : 0); };
-      const uint2 *runs2 = reinterpret_cast<const uint2 *>(runs);
-      constexpr int kRunGroup = 8;
-      for (uint32_t qb = d0; qb < (zero_lo ? d0 : d1); qb += 64) {
-        const int nq = (int)min(64u, d1 - qb);
-        uint2 abv = make_uint2(0u, 0u);
-        if (lane < nq) abv = runs2[qb + lane];
-        for (int u = 0; u < nq; u += kRunGroup) {
-          double La[kRunGroup], Lb[kRunGroup];
-#pragma unroll
-          for (int t = 0; t < kRunGroup; ++t) {
-            const int r = min(u + t, nq - 1);
-            const uint32_t pa = (uint32_t)__builtin_amdgcn_readlane((int)abv.x, r);
-            const uint32_t pe = (uint32_t)__builtin_amdgcn_readlane((int)abv.y, r);
-            const double va = sL[ix(pa) * 64], ve = sL[ix(pe) * 64];
-            La[t] = pa > 0 ? va : 0.0;
-            Lb[t] = pe > 0 ? ve : 0.0;
-          }
-#pragma unroll
-          for (int t = 0; t < kRunGroup; ++t) {
-            if (u + t < nq) {
-              sum_l += Lb[t] - La[t];
-              err_l += fabs(La[t]) + fabs(Lb[t]);
-            }
-          }
-        }
-      }
-      const uint32_t m1r = __all(!kept || tlo_zero) ? m0 : m1;   // possible occluders' runs read
-      for (uint32_t qb = m0; qb < m1r; qb += 64) {
-        const int nq = (int)min(64u, m1 - qb);
-        uint2 abv = make_uint2(0u, 0u);
-        if (lane < nq) abv = runs2[qb + lane];
-        for (int u = 0; u < nq; u += kRunGroup) {
-          double La[kRunGroup], Lb[kRunGroup];
-#pragma unroll
-          for (int t = 0; t < kRunGroup; ++t) {
-            const int r = min(u + t, nq - 1);
-            const uint32_t pa = (uint32_t)__builtin_amdgcn_readlane((int)abv.x, r);
-            const uint32_t pe = (uint32_t)__builtin_amdgcn_readlane((int)abv.y, r);
-            const double va = sH[ix(pa) * 64], ve = sH[ix(pe) * 64];
-            La[t] = pa > 0 ? va : 0.0;
-            Lb[t] = pe > 0 ? ve : 0.0;
-          }
-#pragma unroll
-          for (int t = 0; t < kRunGroup; ++t) {
-            if (u + t < nq) {
-              sum_h += Lb[t] - La[t];
-              err_h += fabs(La[t]) + fabs(Lb[t]);
-            }
-          }
-        }
-      }
-    } else {
-      // few runs per entry: one run at a time, kept lanes only
-      if (!kept) continue;
-      for (uint32_t q = d0; q < (zero_lo ? d0 : d1); ++q) {
-        const uint2 ab = *reinterpret_cast<const uint2 *>(runs + 2 * (size_t)q);
-        double La = 0.0, Lb = 0.0;
-        if (ab.x > 0) La = sL[(pb + ab.x - 1) * 64] + segoff[(size_t)(sl + (int)(ab.x - 1) / L) * 64 + lane].x;
-        if (ab.y > 0) Lb = sL[(pb + ab.y - 1) * 64] + segoff[(size_t)(sl + (int)(ab.y - 1) / L) * 64 + lane].x;
-        sum_l += Lb - La;
-        err_l += fabs(La) + fabs(Lb);
-      }
-      for (uint32_t q = m0; q < (tlo_zero ? m0 : m1); ++q) {
-        const uint2 ab = *reinterpret_cast<const uint2 *>(runs + 2 * (size_t)q);
-        double La = 0.0, Lb = 0.0;
-        if (ab.x > 0) La = sH[(pb + ab.x - 1) * 64] + segoff[(size_t)(sl + (int)(ab.x - 1) / L) * 64 + lane].y;
-        if (ab.y > 0) Lb = sH[(pb + ab.y - 1) * 64] + segoff[(size_t)(sl + (int)(ab.y - 1) / L) * 64 + lane].y;
-        sum_h += Lb - La;
-        err_h += fabs(La) + fabs(Lb);
-      }
-    }
-    if (!kept) continue;
-    const double thi = exp(sum_l + nn * 0x1p-51 * err_l) * (1.0 + 0x1p-50);
-    const double tlo = tlo_zero ? 0.0 : exp(sum_h - nn * 0x1p-51 * err_h) * (1.0 - 0x1p-50);
+    if (!(inimg && la.kept(k, type, ux, uy))) continue;
     double alo, ahi;
-    pair_contrib<P>(rec, type, uxd, uyd, tlo, fmin(thi, 1.0), acc, alo, ahi, exp_table(gid));
+    pair_contrib<P>(rec, type, uxd, uyd, (double)t.x, (double)t.y, acc, alo, ahi, exp_table(gid));
     ++npairs;
   }
   unsigned c = npairs;
@@ -1065,20 +1132,23 @@ static hipError_t launch_rot_p(const Workspace &ws, const uint32_t *lists, const
   double *preL = ws.pre, *preH = ws.pre + ws.cap_pre * kTilePix;
   if (c.nseg > 0) {
     hipLaunchKernelGGL(k_rot_prefix<P>, grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off, ws.seg_tile, c.L,
-                       c.seg0, c.nseg, c.pos0, prm, preL, preH, (double2 *)ws.segsum, ws.counters);
+                       c.seg0, c.nseg, c.pos0, c.list0, prm, preL, preH, (double2 *)ws.segsum, ws.counters);
     hipLaunchKernelGGL(k_rot_offsets, dim3((unsigned)((c.nl + 3) / 4)), blk, 0, s, ws.seg_off, c.list0, c.nl, c.seg0,
                        (double2 *)ws.segsum, ws.listlo);
+    float2 *tpl = reinterpret_cast<float2 *>(ws.pre + 2 * ws.cap_pre * kTilePix);
     if (c.absolute) {
       hipLaunchKernelGGL(k_rot_absolute, grid, blk, 0, s, ws.tile_range, ws.seg_off, ws.seg_tile, c.L, c.seg0, c.nseg,
-                         c.pos0, (const double2 *)ws.segsum, preL, preH);
-      hipLaunchKernelGGL((k_rot_blend<P, true>), grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off,
+                         c.pos0, c.list0, (const double2 *)ws.segsum, preL, preH);
+      hipLaunchKernelGGL((k_rot_trans<P, true>), grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off,
                          ws.seg_tile, c.L, c.seg0, c.nseg, c.pos0, c.gbase, ws.run_cnt, ws.runs, prm, preL,
-                         preH, (const double2 *)ws.segsum, ws.part, ws.counters, ws.listlo, c.list0, ws.win);
+                         preH, (const double2 *)ws.segsum, tpl, ws.counters, ws.listlo, c.list0, ws.win);
     } else {
-      hipLaunchKernelGGL((k_rot_blend<P, false>), grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off,
+      hipLaunchKernelGGL((k_rot_trans<P, false>), grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off,
                          ws.seg_tile, c.L, c.seg0, c.nseg, c.pos0, c.gbase, ws.run_cnt, ws.runs, prm, preL, preH,
-                         (const double2 *)ws.segsum, ws.part, ws.counters, ws.listlo, c.list0, ws.win);
+                         (const double2 *)ws.segsum, tpl, ws.counters, ws.listlo, c.list0, ws.win);
     }
+    hipLaunchKernelGGL(k_rot_blend<P>, grid, blk, 0, s, ws.rec, ws.tile_range, lists, ws.seg_off, ws.seg_tile, c.L,
+                       c.seg0, c.nseg, c.pos0, c.list0, prm, (const float2 *)tpl, ws.part, ws.counters);
   }
   hipLaunchKernelGGL(k_rot_merge<P>, dim3((unsigned)c.nl), dim3(192), 0, s, ws.tile_range, ws.seg_off, c.list0, c.seg0,
                      ws.part, prm, lo, hi, ws.counters);
