@@ -69,7 +69,7 @@ struct PairAlpha {
   float ml, mh;
 };
 
-template <int P, bool LEAN = false>
+template <int P>
 __device__ __forceinline__ void pair_alpha(const double *__restrict__ rec, int type, bool kept, double ux, double uy,
                                            PairAlpha<P> &pa, const double *cf) {
   using R = Rec<P>;
@@ -83,7 +83,7 @@ __device__ __forceinline__ void pair_alpha(const double *__restrict__ rec, int t
   if (type == kNormal) {
     if (kept) {
       SForms<P> s;
-      s_forms<P, LEAN>(rec, ux, uy, s);
+      s_forms<P>(rec, ux, uy, s);
       ExpBounds b;
       exp_bounds(s.slo, s.shi, rec[R::OLO], o, b, cf);
       // lower alpha form  o_lo e_dn (x_lower(e) - xlo + 1),  x_lower = -s_upper / 2
@@ -136,13 +136,12 @@ __device__ __forceinline__ void acc_pair(Acc<P> &acc, const double *__restrict__
 
 // One (pixel, Gaussian) pair: alpha bounds and its BlendInd contribution with the
 // transmittances (tlo, thi) of the Gaussians in front.  Returns the alpha interval.
-// LEAN as in s_forms (same values, fewer registers).
-template <int P, bool LEAN = false>
+template <int P>
 __device__ __forceinline__ void pair_contrib(const double *__restrict__ rec, int type, double ux, double uy,
                                              double tlo, double thi, Acc<P> &acc, double &a_lo, double &a_hi,
                                              const double *cf) {
   PairAlpha<P> pa;
-  pair_alpha<P, LEAN>(rec, type, true, ux, uy, pa, cf);
+  pair_alpha<P>(rec, type, true, ux, uy, pa, cf);
   acc_pair<P>(acc, rec, pa, tlo, thi);
   a_lo = pa.a_lo;
   a_hi = pa.a_hi;

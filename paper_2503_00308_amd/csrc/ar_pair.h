@@ -42,39 +42,36 @@ struct SForms {
 };
 
 // (ux, uy): centred pixel coordinates (exact in FP64).
-// LEAN: the forms of v are not kept through the q loop but formed again for each q_n
-// (the same roundings, so the same values), which frees 4 (P + 1) doubles of registers
-// for kernels that hold large accumulators.
-template <int P, bool LEAN = false>
+template <int P>
 __device__ __forceinline__ void s_forms(const double *__restrict__ r, double ux, double uy, SForms<P> &o) {
   using R = Rec<P>;
   constexpr int F = P + 1;
   constexpr double KC = (P + 4) * kU;  // concretisation: P+1 additions, the subtractions, the widening
 
   // v_k = u_k D2 - DUP_k:  vm = u dm - pm,  vr = |u| dr + pr
-  double vm[LEAN ? 1 : 2][F], vr[LEAN ? 1 : 2][F], vlo[2], Mv[2];
-  // coefficient j of v_k (product and sum rounded separately: both record values are
-  // uniform, and one FMA may read only one of them from a scalar register)
-  auto v_coef = [&](int k, int j, double &m, double &rr, double ux, double uy) {
-#pragma clang fp contract(off)
-    const double u = k ? uy : ux;
-    m = u * r[R::DM + j] - r[R::PM + F * k + j];
-    rr = fabs(u) * r[R::DR + j] + r[R::PR + F * k + j];
-  };
+  double vm[2][F], vr[2][F], vlo[2], Mv[2];
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    const double au = fabs(k ? uy : ux);
-    const int kk = LEAN ? 0 : k;
+    const double u = k ? uy : ux;
+    const double au = fabs(u);
+    // product and sum rounded separately (both record values are uniform, and one FMA
+    // may read only one of them from a scalar register)
+    {
+#pragma clang fp contract(off)
 #pragma unroll
-    for (int j = 0; j < F; ++j) v_coef(k, j, vm[kk][j], vr[kk][j], ux, uy);
+      for (int j = 0; j < F; ++j) {
+        vm[k][j] = u * r[R::DM + j] - r[R::PM + F * k + j];
+        vr[k][j] = au * r[R::DR + j] + r[R::PR + F * k + j];
+      }
+    }
     // sum_j |vm_j| + |vr_j| <= |u| MD2 + MDUP_k up to rounding; two roundings per
     // coefficient, each at most kU (|u| |dm_j| + |pm_j|) (resp. dr, pr)
     Mv[k] = fma(au, r[R::MD2], r[R::MDUP + k]) * (1.0 + 8.0 * kU);
-    vr[kk][P] += 2.0 * kU * Mv[k];
+    vr[k][P] += 2.0 * kU * Mv[k];
     double sl = 0.0;
 #pragma unroll
-    for (int j = 0; j < P; ++j) sl += fabs(vm[kk][j] - vr[kk][j]);
-    vlo[k] = ((vm[kk][P] - vr[kk][P]) - sl) - KC * Mv[k];
+    for (int j = 0; j < P; ++j) sl += fabs(vm[k][j] - vr[k][j]);
+    vlo[k] = ((vm[k][P] - vr[k][P]) - sl) - KC * Mv[k];
   }
 
   // q_n = sum_k Mul(v_k, B_kn), McCormick with x = v, y = B_kn in [ylo, yhi]:
@@ -92,13 +89,6 @@ __device__ __forceinline__ void s_forms(const double *__restrict__ r, double ux,
   double es = 0.0;
 #pragma unroll
   for (int n = 0; n < 3; ++n) {
-    // LEAN: copies of the pixel coordinates the compiler cannot see through, so the v
-    // forms are formed again here and not kept from the previous q_n
-    double uxn = ux, uyn = uy;
-    if (LEAN) {
-      asm volatile("" : "+v"(uxn));
-      asm volatile("" : "+v"(uyn));
-    }
     double qm[F], qr[F];
 #pragma unroll
     for (int j = 0; j < F; ++j) { qm[j] = 0.0; qr[j] = 0.0; }
@@ -111,16 +101,8 @@ __device__ __forceinline__ void s_forms(const double *__restrict__ r, double ux,
       const double a = vlo[k], aa = fabs(vlo[k]);
 #pragma unroll
       for (int j = 0; j < F; ++j) {
-        double m, rr;
-        if (LEAN) {
-          v_coef(k, j, m, rr, uxn, uyn);
-          if (j == P) rr += 2.0 * kU * Mv[k];
-        } else {
-          m = vm[k][j];
-          rr = vr[k][j];
-        }
-        qm[j] = fma(cw[0], m, fma(cw[1], rr, fma(a, bm[j], qm[j])));
-        qr[j] = fma(cw[2], m, fma(cw[3], rr, fma(aa, br[j], qr[j])));
+        qm[j] = fma(cw[0], vm[k][j], fma(cw[1], vr[k][j], fma(a, bm[j], qm[j])));
+        qr[j] = fma(cw[2], vm[k][j], fma(cw[3], vr[k][j], fma(aa, br[j], qr[j])));
       }
       qm[P] = fma(-a, cw[0], qm[P]);
       qr[P] = fma(-a, cw[2], qr[P]);
