@@ -40,21 +40,24 @@ PEAK_FP32_PACKED_TFLOPS = 157.3
 
 # sources the translation pixel kernel (k_raster_seg) is compiled from
 PIXEL_KERNEL_SOURCES = ("ar_raster.hip", "ar_blend.h", "ar_pair.h", "ar_expm.h", "ar_internal.h")
+# sources of the rotation pixel loop (k_rot_prefix, k_rot_offsets, k_rot_absolute,
+# k_rot_trans, k_rot_blend, k_rot_merge) and of its launch sizes
+ROTATION_LOOP_SOURCES = ("ar_general.hip", "ar_api.hip", "ar_blend.h", "ar_pair.h", "ar_expm.h", "ar_internal.h")
 
 
-def kernel_fingerprint() -> str:
-    """Hash of the pixel kernel's sources; a traffic measurement is only used while it matches."""
+def kernel_fingerprint(sources=PIXEL_KERNEL_SOURCES) -> str:
+    """Hash of a kernel's sources; a traffic measurement is only used while it matches."""
     h = hashlib.sha256()
-    for f in [os.path.join(ROOT, "paper_2503_00308_amd", "csrc", n) for n in PIXEL_KERNEL_SOURCES]:
+    for f in [os.path.join(ROOT, "paper_2503_00308_amd", "csrc", n) for n in sources]:
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(path):
-    """HBM bytes per launch of the per-pixel kernel from a committed counter summary
-    ("key: value" lines), or None when absent or taken on other kernel sources."""
+def read_traffic(path, key="bytes_per_launch", sources=PIXEL_KERNEL_SOURCES):
+    """HBM bytes (the value of `key`) from a committed counter summary ("key: value"
+    lines), or None when absent or taken on other kernel sources."""
     if not os.path.exists(path):
         return None
     kv = {}
@@ -63,10 +66,10 @@ def read_traffic(path):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("kernel_fingerprint") != kernel_fingerprint():
+    if kv.get("kernel_fingerprint") != kernel_fingerprint(sources):
         return None
     try:
-        return float(kv["bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
 
@@ -233,7 +236,7 @@ def batched_measure(api, synth, runs=2, per_query_cells=32, autotune=True):
             "graph": {"ms": t_graph * 1e3, "device_ms": gst["total_ms"], "pairs_per_s": gst["pairs"] / t_graph,
                       "replans": replans, "speedup_vs_per_query": t_single * n / t_graph,
                       "speedup_vs_batch_calls": t_batch / t_graph},
-            "roofline": {"bound": "alu", "kernel": "k_rot_prefix + k_rot_blend (pixel loop, all launches)",
+            "roofline": {"bound": "alu", "kernel": "k_rot_prefix .. k_rot_merge (pixel loop, all launches)",
                          "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / PEAK_VALU_TFLOPS, "flops_per_pair": alg_flops_per_pair(st["P"]),
                          "traffic": None},
@@ -446,9 +449,12 @@ def workload3_measure(api, synth, runs=3):
     return {"workload": desc, "ms": t * 1e3, "pairs": int(st["pairs"]), "pairs_per_s": st["pairs"] / t,
             "device_ms": st["total_ms"], "raster_ms": st["raster_ms"], "runs": int(st["runs"]),
             "ind_tests": int(st["ind_tests"]), "max_window": int(st["max_window"]),
-            "roofline": {"bound": "alu", "kernel": "k_rot_prefix + k_rot_blend (pixel loop)", "achieved": achieved,
+            "roofline": {"bound": "alu", "kernel": "k_rot_prefix .. k_rot_merge (pixel loop)", "achieved": achieved,
                          "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
-                         "flops_per_pair": alg_flops_per_pair(st["P"]), "traffic": None}}
+                         "flops_per_pair": alg_flops_per_pair(st["P"]),
+                         "traffic": read_traffic(os.path.join(ROOT, "profiles", "k_rot_pixel_loop_workload3.md"),
+                                                 "pixel_loop_bytes_per_query", ROTATION_LOOP_SOURCES),
+                         "traffic_unit": "HBM bytes per query (FETCH_SIZE + WRITE_SIZE of the pixel loop)"}}
 
 
 def main():

@@ -25,6 +25,13 @@ def test_traffic_reader_needs_the_current_kernel_sources(tmp_path):
     stale.write_text("bytes_per_launch: 12345\nkernel_fingerprint: 0000000000000000\n")
     assert bench.read_traffic(str(stale)) is None
     assert bench.read_traffic(str(tmp_path / "missing.txt")) is None
+    # the rotation loop's summary: its own key and sources
+    rot = tmp_path / "rot.txt"
+    rot.write_text(f"pixel_loop_bytes_per_query: 777\n"
+                   f"kernel_fingerprint: {bench.kernel_fingerprint(bench.ROTATION_LOOP_SOURCES)}\n")
+    assert bench.read_traffic(str(rot), "pixel_loop_bytes_per_query", bench.ROTATION_LOOP_SOURCES) == 777.0
+    assert bench.read_traffic(str(rot), "pixel_loop_bytes_per_query") is None   # other sources
+    assert bench.kernel_fingerprint(bench.ROTATION_LOOP_SOURCES) != bench.kernel_fingerprint()
 
 
 def test_more_than_one_gpu_is_refused():
