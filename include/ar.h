@@ -346,17 +346,36 @@ int ar_render_partitioned(const ar_scene *scene, const ar_intrinsics *intr, cons
 int ar_classify_cells(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *cells, int32_t ncells,
                       const ar_options *opts, int64_t *counts, void *hip_stream);
 
+/*
+ * Per pose cell, the number of undecided depth-order tests (Sec. 3.2: Ind(d_i - d_j) is
+ * piecewise constant, tight on every part of the pose domain where d_i - d_j keeps its
+ * sign, so a cell whose tests stay undecided is one to cut): counts[c] = the ordered pairs
+ * (i, j), i != j, of Gaussians in one tile list of cell c (summed over the tile lists)
+ * whose three-valued Ind is 2 (unknown), with the bounds of ar_render_bounds (the
+ * identity A_z (uw_i - uw_j) and the literal difference of the depth forms).  A box
+ * whose depth order cannot change (translations only, scene without moved means) has 0.
+ * counts: host memory, ncells int64.  Runs the rotation path up to its Ind tests (no
+ * images); synchronises the stream.  Returns AR_OK or an error code as
+ * ar_classify_cells.
+ */
+int ar_count_ind_uncertain(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *cells,
+                           int32_t ncells, const ar_options *opts, int64_t *counts, void *hip_stream);
+
 /* Criteria of ar_render_refined (bit mask; 0 means AR_REFINE_MATINV). */
 enum {
   AR_REFINE_MATINV = 1,   /* cut cells holding a MatrixInv failure kept in the image */
-  AR_REFINE_NEAR = 2      /* cut cells holding a near-plane straddler */
+  AR_REFINE_NEAR = 2,     /* cut cells holding a near-plane straddler */
+  AR_REFINE_IND = 4       /* cut cells with undecided depth-order tests (ar_count_ind_uncertain) */
 };
 
 /*
  * Bounds over a pose box refined where MatrixInv fails (Sec. 3.1: the input range is
- * divided until the convergence assertion holds; Sec. 4.2: bounds of subsets of the
- * cameras, united).  Cells are taken level by level, in order, starting from the whole
- * box; a cell flagged by the criteria (counts of ar_classify_cells) at depth k (k
+ * divided until the convergence assertion holds), where Gaussians straddle the near
+ * plane, or where depth-order tests stay undecided (Sec. 3.2: Ind is tight on parts of
+ * the domain where its argument keeps its sign); Sec. 4.2: bounds of subsets of the
+ * cameras, united.  Cells are taken level by level, in order, starting from the whole
+ * box; a cell flagged by the criteria (counts of ar_classify_cells, and with
+ * AR_REFINE_IND of ar_count_ind_uncertain) at depth k (k
  * bisections from the box) is cut at the midpoint 0.5 (lo + hi) of its active axis
  * number k mod (number of active axes) (ORBIT: the angle), lower half first, while the
  * number of cells stays within max_cells (1..65536) and k < 24; every other cell is a

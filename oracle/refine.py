@@ -7,7 +7,10 @@ the pose box:
 
 * a cell is flagged when it holds a Gaussian whose MatrixInv assertion fails and that
   the pruning test keeps at some pixel of the image (criterion `matinv`), or one that
-  straddles the near plane, which gets alpha in [0, o] everywhere (criterion `near`);
+  straddles the near plane, which gets alpha in [0, o] everywhere (criterion `near`), or
+  when some depth-order test Ind of two Gaussians sharing a tile list stays undecided
+  (criterion `ind`; Sec. 3.2: Ind is piecewise constant, tight on every part of the
+  domain where its argument keeps its sign, splat.ind_uncertain_count);
 * cells are taken level by level, in order; a flagged cell of depth k (k bisections
   from the whole box) is cut in two at the midpoint 0.5 (lo + hi) of its active axis
   number k mod (number of active axes), as long as the number of cells stays within
@@ -55,9 +58,10 @@ def _half(box, a, upper):
     return out
 
 
-def refine(scene, intr, box, max_cells, near=False, opts=None, matinv=True):
+def refine(scene, intr, box, max_cells, near=False, opts=None, matinv=True, ind=False):
     """Leaves of the refinement, in the order they are settled (criteria: MatrixInv
-    failures kept in the image when matinv, near-plane straddlers when near)."""
+    failures kept in the image when matinv, near-plane straddlers when near, undecided
+    Ind tests when ind)."""
     axes = active_axes(box)
     level = [(box, 0)]
     leaves = []
@@ -67,6 +71,8 @@ def refine(scene, intr, box, max_cells, near=False, opts=None, matinv=True):
         for cell, depth in level:
             fb, wild = flagged_counts(scene, intr, cell, opts)
             flagged = (matinv and fb > 0) or (near and wild > 0)
+            if ind and not flagged:
+                flagged = splat.ind_uncertain_count(scene, intr, cell, opts)[0] > 0
             if flagged and axes and depth < MAX_DEPTH and total + 1 <= max_cells:
                 a = axes[depth % len(axes)]
                 lo, hi = float(cell["lo"][a]), float(cell["hi"][a])
@@ -81,9 +87,9 @@ def refine(scene, intr, box, max_cells, near=False, opts=None, matinv=True):
     return leaves
 
 
-def refined_bounds(scene, intr, box, max_cells, near=False, opts=None, matinv=True):
+def refined_bounds(scene, intr, box, max_cells, near=False, opts=None, matinv=True, ind=False):
     """United lower / upper images of the leaves (H, W, 3), and the leaves."""
-    leaves = refine(scene, intr, box, max_cells, near, opts, matinv)
+    leaves = refine(scene, intr, box, max_cells, near, opts, matinv, ind)
     lo = hi = None
     for cell in leaves:
         r = splat.oracle_bounds(scene, intr, cell, opts)

@@ -45,6 +45,7 @@ import numpy as np
 from . import lf
 from .crown import matrix_inv_backward
 from .matinv import adjugate_inv, matrix_inv
+from . import pose
 from .pose import pose_forms
 
 DEFAULTS = {"taylor_k": 8, "z_near": 0.01, "cull_budget": 1e-7, "tile": 16,
@@ -520,3 +521,48 @@ def oracle_bounds(scene, intr, box, opts=None, tiles=None, rec=None):
         pairs[rows, cols] = k
         border[rows, cols] = b
     return {"lo": lo, "hi": hi, "pairs": pairs, "border": border, "rec": rec}
+
+
+def box_rotates(scene, box):
+    """Whether the depth order of the scene can change over the box: a rotation axis of a
+    CAMERA6 box or the angle of an ORBIT box has positive width, or the scene has set
+    variables (a moved mean can change the order under any box).  Otherwise the camera
+    only translates, the depth difference of two Gaussians is constant over the box
+    (translations cancel in d_i - d_j), and no Ind is ever undecided."""
+    lo = np.asarray(box["lo"], dtype=np.float64)
+    hi = np.asarray(box["hi"], dtype=np.float64)
+    if box.get("model", pose.CAMERA6) == pose.ORBIT:
+        rot = bool(hi[0] > lo[0])
+    else:
+        rot = bool((hi[3:6] > lo[3:6]).any())
+    return rot or scene_set(scene)[4] > 0
+
+
+def ind_uncertain_count(scene, intr, box, opts=None, rec=None):
+    """Undecided depth-order tests over a pose cell (Sec. 3.2: Ind(d_i - d_j) is piecewise
+    constant, tight on every part of the domain where d_i - d_j keeps its sign, which is
+    what partitioning the input aims at): the ordered pairs (i, j), i != j, of Gaussians in
+    one tile list (the binning's candidates of the tile) whose three-valued Ind is 2,
+    summed over the tile lists; 0 when the box cannot change the depth order.  Also
+    returns the number of pairs whose bound sits within rounding of a decision
+    threshold (ind_matrix's borderline mask), where an evaluation in another order of
+    operations may decide differently.  The tile lists are those of 8x8-pixel tiles (the
+    library's) unless opts gives another tile.  Returns (count, borderline)."""
+    opts = options({"tile": 8, **(opts or {})})
+    if not box_rotates(scene, box):
+        return 0, 0
+    if rec is None:
+        rec = gaussian_forms(scene, intr, box, opts)
+    W, H = int(intr["width"]), int(intr["height"])
+    TS = int(opts["tile"])
+    total = border_total = 0
+    for ty in range((H + TS - 1) // TS):
+        for tx in range((W + TS - 1) // TS):
+            x0, y0 = tx * TS, ty * TS
+            idx = tile_candidates(rec, intr, x0, min(x0 + TS, W), y0, min(y0 + TS, H))
+            if len(idx) < 2:
+                continue
+            ind, border = ind_matrix(rec, idx)
+            total += int((ind == 2).sum())
+            border_total += int(border.sum())
+    return total, border_total

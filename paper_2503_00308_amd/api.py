@@ -128,6 +128,9 @@ SYMBOLS = {
     "ar_classify_cells": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
                                          ctypes.c_int32, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.c_void_p]),
+    "ar_count_ind_uncertain": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
+                                              ctypes.c_int32, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_int64),
+                                              ctypes.c_void_p]),
     "ar_render_refined": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
                                          ctypes.POINTER(Options), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(PoseBox),
@@ -387,6 +390,7 @@ def render_partitioned(scene: Scene, intr, box, splits, opts=None, stream=None, 
 
 REFINE_MATINV = 1
 REFINE_NEAR = 2
+REFINE_IND = 4
 
 
 def classify_cells(scene: Scene, intr, cells, opts=None, stream=None):
@@ -402,6 +406,19 @@ def classify_cells(scene: Scene, intr, cells, opts=None, stream=None):
     return np.array(out[:], dtype=np.int64).reshape(len(cells), 2)
 
 
+def count_ind_uncertain(scene: Scene, intr, cells, opts=None, stream=None):
+    """Per pose cell: the ordered pairs of Gaussians sharing a tile list whose depth-order
+    test Ind stays undecided (summed over the tile lists), an int64 array (ncells,)."""
+    lib = load()
+    ci = intrinsics(intr)
+    arr = (PoseBox * len(cells))(*[pose_box(c) for c in cells])
+    out = (ctypes.c_int64 * len(cells))()
+    co = options(opts)
+    _check(lib.ar_count_ind_uncertain(scene.handle, ctypes.byref(ci), arr, len(cells), ctypes.byref(co), out,
+                                      _stream_ptr(stream)))
+    return np.array(out[:], dtype=np.int64)
+
+
 def _box_dict(b: PoseBox) -> dict:
     return {"model": b.model, "R0": np.array(b.R0[:], np.float64).reshape(3, 3), "t0": np.array(b.t0[:], np.float64),
             "pivot": np.array(b.pivot[:], np.float64), "lo": np.array(b.lo[:], np.float64),
@@ -409,9 +426,10 @@ def _box_dict(b: PoseBox) -> dict:
 
 
 def render_refined(scene: Scene, intr, box, max_cells=64, criteria=REFINE_MATINV, opts=None, stream=None, out=None):
-    """Bounds over a pose box refined where MatrixInv fails (cells bisected level by
-    level, united): tensors (H, W, 3), the leaf cells (pose-box dicts, in the order they
-    were settled) and the leaves' accumulated stats."""
+    """Bounds over a pose box refined where the criteria flag a cell (REFINE_MATINV,
+    REFINE_NEAR, REFINE_IND; cells bisected level by level, united): tensors (H, W, 3),
+    the leaf cells (pose-box dicts, in the order they were settled) and the leaves'
+    accumulated stats."""
     import torch
     lib = load()
     ci = intrinsics(intr)

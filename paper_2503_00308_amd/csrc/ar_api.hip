@@ -567,7 +567,8 @@ static int render_rotation(const ar_scene *sc, Workspace &ws, const Params &prm,
     const unsigned long long tests = ws.host_counters[2] - tests_before;
     tests_before = ws.host_counters[2];
     unsigned long long *masks = nullptr;
-    if (prm.ind_masks != 2 && words > 0 && words_max < 4294967295.0 && (double)words * 8.0 <= kMaskBytes) {
+    if (!prm.ind_only && prm.ind_masks != 2 && words > 0 && words_max < 4294967295.0 &&
+        (double)words * 8.0 <= kMaskBytes) {
       if (words > ws.cap_masks || !ws.masks) {
         const size_t need = words + words / 4 + 1024;
         HIP_TRY(grow(ws, ws.masks, need));
@@ -591,8 +592,11 @@ static int render_rotation(const ar_scene *sc, Workspace &ws, const Params &prm,
       }
       HIP_TRY(launch_ind_gather(P, ws, ws.pair_val, sc->dev, ntiles, pa, ng, s));
     }
+    DevCounts dcount;
+    dcount.ind_und = prm.ind_und;
     HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, pa, ng, prm.ind_window, kRunsCount, masks,
-                        compact, s));
+                        compact, s, dcount));
+    if (prm.ind_only) continue;   // the undecided pairs were all that was asked for
     // run counts: their 64-bit total beside the 32-bit scan into offsets
     const size_t ncnt = 2 * (size_t)ng;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.run_cnt + ncnt, 1);
@@ -799,7 +803,7 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
   HIP_TRY(hipStreamSynchronize(s));
   float ms_raster = 0.0f, ms_total = 0.0f;
   if (timed) {
-    HIP_TRY(hipEventElapsedTime(&ms_raster, ws.ev[1], ws.ev[2]));
+    if (!prm.ind_only) HIP_TRY(hipEventElapsedTime(&ms_raster, ws.ev[1], ws.ev[2]));
     HIP_TRY(hipEventElapsedTime(&ms_total, ws.ev[0], ws.ev[3]));
   }
   if (st) {
@@ -1092,6 +1096,56 @@ int classify_cells(const ar_scene *sc, const Params &prm_in, const ar_pose_box *
   return AR_OK;
 }
 
+// Per cell, the (list entry, list position) pairs of its tile lists whose Ind is undecided
+// (Ind = 2; both orders of a pair count): the rotation path up to the Ind counting pass,
+// in launches of cells with the same pose variables.  Boxes whose depth order cannot
+// change (translation only, plain scenes) have none.
+int count_ind_cells(const ar_scene *sc, const Params &prm_in, const ar_pose_box *cells, int ncells,
+                    const ar_options *opts, int64_t *counts, hipStream_t s) {
+  Workspace &ws = const_cast<ar_scene *>(sc)->ws;
+  std::vector<unsigned long long> host;
+  int i = 0;
+  while (i < ncells) {
+    bool rot = false;
+    int P = 0;
+    int rc = render_vars(sc, &cells[i], &rot, &P);
+    if (rc) return rc;
+    int j = i + 1;
+    while (j < ncells) {
+      bool r2 = false;
+      int P2 = 0;
+      if (render_vars(sc, &cells[j], &r2, &P2) || P2 != P || r2 != rot) break;
+      ++j;
+    }
+    if (!rot) {
+      for (int c = i; c < j; ++c) counts[c] = 0;
+      i = j;
+      continue;
+    }
+    while (i < j) {
+      const int m = std::min(j - i, batch_cells(sc, ws, prm_in, P, rot, opts));
+      if ((size_t)m > ws.cap_ind_und || !ws.ind_und) {
+        HIP_TRY(grow(ws, ws.ind_und, (size_t)m));
+        ws.cap_ind_und = (size_t)m;
+      }
+      hipLaunchKernelGGL(k_zero_u64_n, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, ws.ind_und, (size_t)m);
+      HIP_TRY(hipGetLastError());
+      Params prm = prm_in;
+      prm.ind_und = ws.ind_und;
+      prm.ind_only = 1;
+      rc = render_cells(sc, ws, prm, cells + i, m, P, rot, nullptr, nullptr, s, nullptr);
+      if (rc) return rc;
+      host.resize((size_t)m);
+      HIP_TRY(hipMemcpyAsync(host.data(), ws.ind_und, (size_t)m * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                             s));
+      HIP_TRY(hipStreamSynchronize(s));
+      for (int c = 0; c < m; ++c) counts[i + c] = (int64_t)host[c];
+      i += m;
+    }
+  }
+  return AR_OK;
+}
+
 static int validate_scene_host(const ar_scene_desc *d, const float *mean, const float *cov, const float *op,
                                const float *rgb) {
   const size_t n = (size_t)d->n;
@@ -1362,6 +1416,21 @@ int ar_classify_cells(const ar_scene *scene, const ar_intrinsics *intr, const ar
   return ar::classify_cells(scene, prm, cells, ncells, counts, (hipStream_t)hip_stream);
 }
 
+int ar_count_ind_uncertain(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *cells,
+                           int32_t ncells, const ar_options *opts, int64_t *counts, void *hip_stream) {
+  if (!scene) return fail(AR_E_INVALID, "scene is NULL");
+  if (!cells || ncells < 1) return fail(AR_E_INVALID, "counting needs at least one cell");
+  if (!counts) return fail(AR_E_INVALID, "counts is NULL");
+  for (int i = 0; i < ncells; ++i) {
+    int rc = ar::validate_box(&cells[i]);
+    if (rc) return rc;
+  }
+  ar::Params prm{};
+  int rc = ar::make_params(scene, intr, opts, prm);
+  if (rc) return rc;
+  return ar::count_ind_cells(scene, prm, cells, ncells, opts, counts, (hipStream_t)hip_stream);
+}
+
 int ar_render_refined(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *box,
                       const ar_options *opts, int32_t max_cells, int32_t criteria, float *lo_rgb, float *hi_rgb,
                       void *hip_stream, ar_pose_box *cells_out, int32_t *ncells_out, ar_stats *stats) {
@@ -1370,7 +1439,8 @@ int ar_render_refined(const ar_scene *scene, const ar_intrinsics *intr, const ar
   if (rc) return rc;
   if (max_cells < 1 || max_cells > 65536) return fail(AR_E_INVALID, "max_cells %d outside [1, 65536]", max_cells);
   if (criteria == 0) criteria = AR_REFINE_MATINV;
-  if (criteria & ~(AR_REFINE_MATINV | AR_REFINE_NEAR)) return fail(AR_E_INVALID, "unknown refinement criteria %d", criteria);
+  if (criteria & ~(AR_REFINE_MATINV | AR_REFINE_NEAR | AR_REFINE_IND))
+    return fail(AR_E_INVALID, "unknown refinement criteria %d", criteria);
   ar::Params prm{};
   rc = ar::make_params(scene, intr, opts, prm);
   if (rc) return rc;
@@ -1386,17 +1456,23 @@ int ar_render_refined(const ar_scene *scene, const ar_intrinsics *intr, const ar
   // number of cells stays within max_cells (lower half first), settle the others
   std::vector<ar_pose_box> level(1, *box), next, leaves;
   std::vector<int> depth(1, 0), next_depth;
-  std::vector<int64_t> counts;
+  std::vector<int64_t> counts, und;
   size_t total = 1;
   while (!level.empty()) {
     counts.assign(2 * level.size(), 0);
     rc = ar::classify_cells(scene, prm, level.data(), (int)level.size(), counts.data(), s);
     if (rc) return rc;
+    und.assign(level.size(), 0);
+    if (criteria & AR_REFINE_IND) {
+      rc = ar::count_ind_cells(scene, prm, level.data(), (int)level.size(), opts, und.data(), s);
+      if (rc) return rc;
+    }
     next.clear();
     next_depth.clear();
     for (size_t i = 0; i < level.size(); ++i) {
       const bool flagged = ((criteria & AR_REFINE_MATINV) && counts[2 * i] > 0) ||
-                           ((criteria & AR_REFINE_NEAR) && counts[2 * i + 1] > 0);
+                           ((criteria & AR_REFINE_NEAR) && counts[2 * i + 1] > 0) ||
+                           ((criteria & AR_REFINE_IND) && und[i] > 0);
       if (flagged && naxes > 0 && depth[i] < ar::kMaxRefineDepth && total + 1 <= (size_t)max_cells) {
         const int a = axes[depth[i] % naxes];
         const double lo = level[i].lo[a], hi = level[i].hi[a], m = 0.5 * (lo + hi);

@@ -239,13 +239,14 @@ __global__ __launch_bounds__(256) void k_ind_gather(const uint32_t *__restrict__
 // words), and ballots give the run starts (in the set, previous not) and ends (not in
 // the set, previous in it).  Starts and ends are ranked separately, so a run that spans
 // two chunks gets its start and end from different iterations.  Returns the number of
-// runs of each set (wave-uniform).  masks: two words (Ind = 1, Ind != 0) per chunk of
-// 64 window positions, or null.
+// runs of each set (wave-uniform) and, when tested, the number of undecided pairs (Ind
+// = 2: in the second set and not in the first).  masks: two words (Ind = 1, Ind != 0)
+// per chunk of 64 window positions, or null.
 template <int P, int MODE, bool COMPACT>
 __device__ __forceinline__ void wave_runs(const PoseForms &pose, const IndSrc<P, COMPACT> &src, int i, int ps,
                                           int qe, const double *uwi, const double *dfi,
                                           unsigned long long *masks, uint32_t *out_def, uint32_t *out_may,
-                                          int lane, uint32_t &ndef, uint32_t &nmay) {
+                                          int lane, uint32_t &ndef, uint32_t &nmay, uint32_t &nund) {
   constexpr bool EMIT = MODE == kRunsEmit;
   uint32_t sd = 0, ed = 0, sm = 0, em = 0;      // run starts / ends so far
   bool cd = ps > 0, cm = ps > 0;                // the position before the chunk is in the set
@@ -258,6 +259,7 @@ __device__ __forceinline__ void wave_runs(const PoseForms &pose, const IndSrc<P,
     sd = sm = 1;
   }
   const unsigned long long below = (1ull << lane) - 1ull;
+  nund = 0;
   for (int t = ps, c = 0; t < qe; t += 64, ++c) {
     const int j = t + lane;
     const bool valid = j < qe;
@@ -275,6 +277,7 @@ __device__ __forceinline__ void wave_runs(const PoseForms &pose, const IndSrc<P,
       }
       D = __ballot(valid && ind == 1);
       M = __ballot(valid && ind != 0);
+      nund += (uint32_t)__popcll(M & ~D);
       if (MODE == kRunsCount && masks && lane == 0) {
         masks[2 * (size_t)c] = D;
         masks[2 * (size_t)c + 1] = M;
@@ -332,7 +335,8 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
                                               uint32_t *__restrict__ woff, unsigned long long *__restrict__ masks,
                                               uint32_t *__restrict__ cnt, uint32_t *__restrict__ runs,
                                               unsigned long long *__restrict__ counters,
-                                              const uint32_t *__restrict__ ng_dev, uint32_t runs_cap) {
+                                              const uint32_t *__restrict__ ng_dev, uint32_t runs_cap,
+                                              unsigned long long *__restrict__ ind_und) {
   constexpr bool EMIT = MODE == kRunsEmit;
   const int lane = threadIdx.x & 63;
   // planned launches: the entries counted on the device, and no runs past the buffer
@@ -434,7 +438,7 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
       out_def = runs + 2 * (size_t)cnt[2 * (size_t)p];
       out_may = runs + 2 * (size_t)cnt[2 * (size_t)p + 1];
     }
-    uint32_t ndef = 0, nmay = 0;
+    uint32_t ndef = 0, nmay = 0, nund = 0;
     if (have && !wide) {
       const PoseForms &pose = poses[cell];
       const IndSrc<P, COMPACT> src{lists + beg, sc.ind_mean, COMPACT ? cform : dform, cmean, sc.n,
@@ -450,6 +454,7 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
           ind = ind_pair<P, IndSrc<P, COMPACT>::S>(pose, uwi, uwj, dfi, src.forms_of(j));
         }
         const bool d1 = ind == 1, m1 = ind != 0;
+        nund += ind == 2 ? 1u : 0u;
         if (d1 && def_start < 0) def_start = j;
         if (!d1 && def_start >= 0) {
           if (EMIT) { out_def[2 * ndef] = (uint32_t)def_start; out_def[2 * ndef + 1] = (uint32_t)j; }
@@ -490,16 +495,20 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
       unsigned long long *km_ = masks ? masks + woff[kp] : nullptr;
       const IndSrc<P, COMPACT> src{lists + kb, sc.ind_mean, COMPACT ? cform : dform, cmean, sc.n, (size_t)kc * sc.n,
                                    (size_t)((uint32_t)kb - pbase)};
-      uint32_t kd, km;
-      wave_runs<P, MODE, COMPACT>(poses[kc], src, ki, kps, kqe, kuw, src.forms_of(ki), km_, kod, kom, lane, kd, km);
+      uint32_t kd, km, ku;
+      wave_runs<P, MODE, COMPACT>(poses[kc], src, ki, kps, kqe, kuw, src.forms_of(ki), km_, kod, kom, lane, kd, km,
+                                  ku);
       if (lane == k) {
         ndef = kd;
         nmay = km;
+        nund = ku;
       }
     }
     if (!EMIT && have) {
       cnt[2 * (size_t)p] = ndef;
       cnt[2 * (size_t)p + 1] = nmay;
+      // undecided pairs of the cell (counted when asked for)
+      if (ind_und && nund) atomicAdd(&ind_und[cell], (unsigned long long)nund);
     }
   }
   if (MODE == kRunsWindows) {
@@ -533,7 +542,8 @@ __global__ __launch_bounds__(256) void k_runs_count_lanes(const uint32_t *__rest
                                                           const uint32_t *__restrict__ woff,
                                                           unsigned long long *__restrict__ masks,
                                                           uint32_t *__restrict__ cnt,
-                                                          const uint32_t *__restrict__ ng_dev) {
+                                                          const uint32_t *__restrict__ ng_dev,
+                                                          unsigned long long *__restrict__ ind_und) {
   using Src = IndSrc<P, true>;
   constexpr int S = Src::S;
   const int lane = threadIdx.x & 63;
@@ -561,7 +571,7 @@ __global__ __launch_bounds__(256) void k_runs_count_lanes(const uint32_t *__rest
 #pragma unroll
       for (int k = 0; k < 2 * S; ++k) dfi[k] = cform[(size_t)p * (2 * S) + k];
     }
-    uint32_t ndef = 0, nmay = 0;
+    uint32_t ndef = 0, nmay = 0, nund = 0;
     bool pending = have;
     for (;;) {
       const unsigned long long pend = __ballot(pending);
@@ -595,6 +605,7 @@ __global__ __launch_bounds__(256) void k_runs_count_lanes(const uint32_t *__rest
         if (mine && j >= ps && j < qe) {
           const int ind = j != i ? ind_pair<P, S>(pose, uwi, uwj, dfi, dfj) : 0;
           const bool d1 = ind == 1, m1 = ind != 0;
+          nund += ind == 2 ? 1u : 0u;
           if (d1 && def_start < 0) def_start = j;
           if (!d1 && def_start >= 0) {
             ++nd;
@@ -627,6 +638,7 @@ __global__ __launch_bounds__(256) void k_runs_count_lanes(const uint32_t *__rest
     if (have) {
       cnt[2 * (size_t)p] = ndef;
       cnt[2 * (size_t)p + 1] = nmay;
+      if (ind_und && nund) atomicAdd(&ind_und[tile / (uint32_t)ntiles], (unsigned long long)nund);
     }
   }
 }
@@ -1061,7 +1073,8 @@ static hipError_t launch_runs_pm(const Workspace &ws, const uint32_t *lists, con
   const dim3 grid((unsigned)std::min<size_t>(((size_t)ng + 255) / 256, 8192)), block(256);
   hipLaunchKernelGGL((k_runs<P, MODE, COMPACT>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint,
                      ws.dform, (const float4 *)ws.cmean, ws.cform, ws.lbox, poses_dev, ntiles, sc, pbase, ng,
-                     window_mode, ws.win, ws.woff, masks, ws.run_cnt, ws.runs, ws.counters, dc.entries, dc.runs_cap);
+                     window_mode, ws.win, ws.woff, masks, ws.run_cnt, ws.runs, ws.counters, dc.entries, dc.runs_cap,
+                     dc.ind_und);
   return hipGetLastError();
 }
 
@@ -1077,7 +1090,7 @@ static hipError_t launch_runs_p(const Workspace &ws, const uint32_t *lists, cons
       const dim3 grid((unsigned)std::min<size_t>(((size_t)ng + 255) / 256, 8192)), block(256);
       hipLaunchKernelGGL(k_runs_count_lanes<P>, grid, block, 0, s, ws.pair_key, ws.tile_range, lists,
                          (const float4 *)ws.cmean, ws.cform, poses_dev, ntiles, sc, pbase, ng, ws.win, ws.woff, masks,
-                         ws.run_cnt, dc.entries);
+                         ws.run_cnt, dc.entries, dc.ind_und);
       return hipGetLastError();
     }
     return launch_runs_pm<P, kRunsEmit, true>(ws, lists, poses_dev, ntiles, sc, pbase, ng, window_mode, masks, dc, s);

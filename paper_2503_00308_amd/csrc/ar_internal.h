@@ -108,6 +108,11 @@ struct Params {
   int32_t inverse;          // conic: 0 MatrixInv (forward), 1 MatrixInv bounded backward, 2 adjugate
   int32_t pose_vars;        // pose variables; scene variables follow them in the forms
   int32_t group_runs;       // rotation path: most Ind runs per list group (0: the uint32 limit)
+  // rotation path: per cell of the launch, the number of (list entry, list position) pairs
+  // whose Ind is undecided, added here by the counting pass when not null; with ind_only
+  // the render stops after that pass (no images)
+  unsigned long long *ind_und;
+  int32_t ind_only;
 };
 
 // A scene, or a set of scenes (Sec. 4.6): colour and opacity intervals per Gaussian,
@@ -218,6 +223,8 @@ struct Workspace {
   size_t cap_segsum = 0;
   double *listlo = nullptr;          // [lists of a launch][64] list totals of log(1 - a_lo)
   size_t cap_listlo = 0;
+  unsigned long long *ind_und = nullptr;   // [cells of a launch] undecided Ind pairs
+  size_t cap_ind_und = 0;
   // Arena mode (the allocation-free entry point): buffers are carved from [arena,
   // arena + arena_cap) by a bump pointer instead of hipMalloc; nothing is freed, pinned
   // host blocks and events are not created (pose_host / host_counters point to host
@@ -327,6 +334,7 @@ constexpr int kRunsEmit = 2;      // runs written (long windows from the stored 
 struct DevCounts {
   const uint32_t *entries = nullptr;
   uint32_t runs_cap = 0;
+  unsigned long long *ind_und = nullptr;   // counting pass: undecided Ind pairs per cell (or null)
 };
 hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
                        const SceneDev &sc, uint32_t pbase, int ng, int window_mode, int mode,

@@ -1,0 +1,170 @@
+"""Refinement where Ind is uncertain (Sec. 3.2) on the GPU through the C ABI:
+ar_count_ind_uncertain against the oracle's count, and ar_render_refined with
+AR_REFINE_IND.
+
+Bar: per cell, the GPU's number of undecided Ind tests equals the oracle's, up to the
+pairs the oracle flags as borderline (a bound within rounding of a decision threshold);
+the count is the same with every pair tested and with the Ind windows, and through each
+layout of the counting pass; the mirrored pair of Gaussians is undecided exactly on the
+yaw boxes that contain its swap; the refined bounds are the union of their leaves' renders
+bit for bit, enclose concrete renders at sampled poses, and match the oracle's union of the
+same leaves within 1e-5.
+"""
+import numpy as np
+import pytest
+
+from paper_2503_00308_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _api():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_00308_amd import api
+    api.load()
+    return api
+
+
+def _cells():
+    deg = np.deg2rad
+    yaw = synth.camera6_box(dt=0.01)
+    yaw["lo"][3], yaw["hi"][3] = -deg(0.8), deg(0.8)
+    return [synth.camera6_box(dt=0.02),                                      # translation only: none
+            yaw,                                                             # one angle
+            synth.camera6_box(dt=0.01, drot=(deg(0.4), deg(0.3), deg(0.2))),  # six axes
+            synth.orbit_cells(1, 3.0, seed=2)[0]]                            # orbit
+
+
+@pytest.mark.parametrize("layout", ["auto", "compact", "gathers", "every_pair"])
+def test_counts_match_the_oracle(layout):
+    from oracle import splat
+    api = _api()
+    scene = synth.box_surface_scene(400, n_boxes=5, seed=7)
+    intr = synth.intrinsics(32)
+    cells = _cells()
+    opts = {"auto": None, "compact": {"ind_copy": 1}, "gathers": {"ind_copy": 2},
+            "every_pair": {"ind_window": 2}}[layout]
+    sc = api.Scene(scene)
+    got = api.count_ind_uncertain(sc, intr, cells, opts)
+    sc.close()
+    for k, box in enumerate(cells):
+        want, border = splat.ind_uncertain_count(scene, intr, box)
+        print(f"[{layout}] cell {k}: gpu {got[k]} oracle {want} borderline {border}", flush=True)
+        assert abs(int(got[k]) - want) <= border
+    assert got[0] == 0 and all(got[k] > 0 for k in (1, 2, 3))
+
+
+def test_counts_do_not_depend_on_windows_or_layouts():
+    api = _api()
+    scene = synth.random_scene(300, seed=12)
+    intr = synth.intrinsics(40)
+    cells = _cells()[1:]
+    sc = api.Scene(scene)
+    base = api.count_ind_uncertain(sc, intr, cells)
+    for opts in ({"ind_window": 1}, {"ind_window": 2}, {"ind_copy": 1}, {"ind_copy": 2}, {"ind_masks": 2}):
+        assert np.array_equal(api.count_ind_uncertain(sc, intr, cells, opts), base), opts
+    sc.close()
+
+
+def test_mirrored_pair_is_undecided_exactly_where_its_order_swaps():
+    api = _api()
+    mean = np.array([[0.5, 0.0, 5.0], [-0.5, 0.0, 5.0]])
+    scene = synth._pack(mean, np.stack([np.eye(3)] * 2), np.full((2, 3), 0.6), np.array([0.6, 0.6]),
+                        np.array([[1.0, 0.2, 0.2], [0.2, 0.2, 1.0]]))
+    intr = synth.intrinsics(8)
+    boxes = []
+    for lo, hi in ((-1.0, 1.0), (0.2, 1.0), (-1.0, -0.2)):
+        b = synth.camera6_box()
+        b["lo"][3], b["hi"][3] = np.deg2rad(lo), np.deg2rad(hi)
+        boxes.append(b)
+    sc = api.Scene(scene)
+    assert list(api.count_ind_uncertain(sc, intr, boxes)) == [2, 0, 0]
+    sc.close()
+
+
+def test_refined_where_ind_is_uncertain():
+    import torch
+    from oracle import pose, render, splat
+    api = _api()
+    scene = synth.box_surface_scene(300, n_boxes=4, seed=9)
+    intr = synth.intrinsics(32)
+    box = synth.camera6_box(dt=0.01, drot=(np.deg2rad(1.0), np.deg2rad(0.6), 0.0))
+    sc = api.Scene(scene)
+    whole = api.count_ind_uncertain(sc, intr, [box])[0]
+    lo, hi, leaves, st = api.render_refined(sc, intr, box, max_cells=8, criteria=api.REFINE_IND)
+    torch.cuda.synchronize()
+    lo, hi = lo.cpu().numpy(), hi.cpu().numpy()
+    assert 2 <= len(leaves) <= 8
+    counts = api.count_ind_uncertain(sc, intr, leaves)
+    print(f"whole box {whole} undecided; leaves {list(counts)}", flush=True)
+    assert whole > 0 and counts.max() < whole
+    # the leaves tile the box: their volumes add up to the box's
+    act = box["hi"] > box["lo"]
+    vol = lambda b: np.prod((b["hi"] - b["lo"])[act])
+    assert abs(sum(vol(b) for b in leaves) - vol(box)) <= 1e-12 * vol(box)
+    # the union of the leaves' own renders, bit for bit
+    llo, lhi, _ = api.render_batch(sc, intr, leaves)
+    torch.cuda.synchronize()
+    assert np.array_equal(lo, llo.cpu().numpy().min(axis=0)) and np.array_equal(hi, lhi.cpu().numpy().max(axis=0))
+    # tighter than the whole box on average
+    wlo, whi, _ = api.render_bounds(sc, intr, box)
+    torch.cuda.synchronize()
+    assert (hi - lo).mean() <= (whi - wlo).cpu().numpy().mean() + 1e-7
+    sc.close()
+    # against the oracle's union over the same leaves
+    olo = np.full(lo.shape, np.inf)
+    ohi = np.full(hi.shape, -np.inf)
+    for b in leaves:
+        r = splat.oracle_bounds(scene, intr, b)
+        olo = np.minimum(olo, r["lo"])
+        ohi = np.maximum(ohi, r["hi"])
+    assert np.abs(lo - olo).max() <= TOL and np.abs(hi - ohi).max() <= TOL
+    # sound at concrete poses of the box
+    rng = np.random.default_rng(4)
+    for p in pose.sample_poses(box, 12, rng):
+        img = render.render(scene, intr, box, p)
+        assert (lo - img).max() <= 1e-7 and (img - hi).max() <= 1e-7
+
+
+@pytest.mark.parametrize("kind", ["mirrored_pair", "box_scene"])
+def test_refined_leaves_equal_the_oracle(kind):
+    from oracle import refine
+    api = _api()
+    if kind == "mirrored_pair":
+        mean = np.array([[0.5, 0.0, 5.0], [-0.5, 0.0, 5.0]])
+        scene = synth._pack(mean, np.stack([np.eye(3)] * 2), np.full((2, 3), 0.6), np.array([0.6, 0.6]),
+                            np.array([[1.0, 0.2, 0.2], [0.2, 0.2, 1.0]]))
+        intr = synth.intrinsics(8)
+        box = synth.camera6_box()
+        box["lo"][3], box["hi"][3] = np.deg2rad(-1.0), np.deg2rad(3.0)
+        budget = 8
+    else:
+        scene = synth.box_surface_scene(200, n_boxes=3, seed=2)
+        intr = synth.intrinsics(24)
+        box = synth.camera6_box(dt=0.005, drot=(np.deg2rad(0.6), 0.0, 0.0))
+        budget = 6
+    sc = api.Scene(scene)
+    _, _, leaves, _ = api.render_refined(sc, intr, box, max_cells=budget, criteria=api.REFINE_IND)
+    sc.close()
+    ref = refine.refine(scene, intr, box, budget, matinv=False, ind=True)
+    print(f"[{kind}] {len(leaves)} leaves (oracle {len(ref)})", flush=True)
+    assert len(leaves) == len(ref) and len(leaves) > 1
+    for a, b in zip(leaves, ref):
+        assert np.array_equal(a["lo"], np.asarray(b["lo"], np.float64))
+        assert np.array_equal(a["hi"], np.asarray(b["hi"], np.float64))
+
+
+def test_count_rejections():
+    api = _api()
+    sc = api.Scene(synth.random_scene(20, seed=1))
+    with pytest.raises(api.ARError) as ei:
+        api.count_ind_uncertain(sc, synth.intrinsics(16), [])
+    assert ei.value.code == api.AR_E_INVALID
+    with pytest.raises(api.ARError) as ei:
+        api.render_refined(sc, synth.intrinsics(16), synth.camera6_box(dt=0.01), max_cells=4, criteria=8)
+    assert ei.value.code == api.AR_E_INVALID
+    sc.close()

@@ -138,3 +138,29 @@ def test_near_plane_criterion_isolates_the_crossing():
         assert straddles == (lo < t_cross <= hi), (lo, hi)
         hits += straddles
     assert hits == 1
+
+
+def test_ind_criterion_cuts_only_cells_that_hold_the_order_swap():
+    """Two Gaussians mirrored across the optical axis swap their depth order at yaw 0
+    (depth -sin(yaw) x + cos(yaw) z).  Refining a yaw box [-1, 3] degrees on the Ind
+    criterion alone cuts only cells whose closure holds yaw 0 (there the pair's Ind is
+    undecided, elsewhere decided; a cut lands within rounding of 0, where the depth
+    difference is far too small to decide), so the leaves around 0 shrink and the others
+    are not cut again; MatrixInv alone leaves the box whole."""
+    mean = np.array([[0.5, 0.0, 5.0], [-0.5, 0.0, 5.0]])
+    scene = synth._pack(mean, np.stack([np.eye(3)] * 2), np.full((2, 3), 0.6), np.array([0.6, 0.6]),
+                        np.array([[1.0, 0.2, 0.2], [0.2, 0.2, 1.0]]))
+    intr = synth.intrinsics(8)
+    box = synth.camera6_box()
+    box["lo"][3], box["hi"][3] = np.deg2rad(-1.0), np.deg2rad(3.0)
+    assert len(refine.refine(scene, intr, box, 8)) == 1
+    leaves = refine.refine(scene, intr, box, 8, matinv=False, ind=True)
+    assert len(leaves) == 8
+    for c in leaves:
+        lo, hi = float(c["lo"][3]), float(c["hi"][3])
+        holds_swap = lo <= 1e-12 and hi >= -1e-12   # the midpoints land within rounding of 0
+        assert (splat.ind_uncertain_count(scene, intr, c)[0] > 0) == holds_swap, (lo, hi)
+        if holds_swap:
+            assert hi - lo <= np.deg2rad(4.0) / 8
+    m1 = 0.5 * (float(box["lo"][3]) + float(box["hi"][3]))   # the first cut
+    assert any(float(c["lo"][3]) == m1 and float(c["hi"][3]) == float(box["hi"][3]) for c in leaves)
