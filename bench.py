@@ -316,11 +316,11 @@ def refined_measure(api, synth, deg=3.0, max_cells=64, runs=3):
     return out
 
 
-def _served_run(api, srv_slots, handles, queries, arrival):
+def _served_run(api, srv_slots, handles, queries, arrival, overlap_queue=0):
     """Submit the queries to a fresh server at the given arrival times (seconds from the
     start); returns latencies (ms), wall time and the server report."""
     import numpy as np
-    srv = api.Server(slots=srv_slots)
+    srv = api.Server(slots=srv_slots, overlap_queue=overlap_queue)
     ids = [srv.add_scene(h) for h in handles]
     tickets = []
     t0 = time.perf_counter()
@@ -390,6 +390,7 @@ def served_measure(api, synth, nq=48, loads=(0.25, 0.5, 0.75, 0.9), slots=4, see
         out["sweep"].append({"load": load, "arrival_qps": lam, "p50_ms": float(np.percentile(lat, 50)),
                              "p99_ms": float(np.percentile(lat, 99)), "throughput_qps": nq / wall,
                              "peak_inflight": rep["peak_inflight"], "peak_workspace_bytes": rep["peak_bytes"],
+                             "workspace_releases": rep["releases"],
                              "one_at_a_time": {"p50_ms": float(np.percentile(serial, 50)),
                                                "p99_ms": float(np.percentile(serial, 99)),
                                                "throughput_qps": nq / finish[-1]}})
@@ -398,6 +399,7 @@ def served_measure(api, synth, nq=48, loads=(0.25, 0.5, 0.75, 0.9), slots=4, see
     serial_fin = np.cumsum(service)
     out["saturation"] = {"throughput_qps": nq / wall, "wall_s": wall, "p50_ms": float(np.percentile(lat, 50)),
                          "p99_ms": float(np.percentile(lat, 99)), "peak_inflight": rep["peak_inflight"],
+                         "workspace_releases": rep["releases"],
                          "one_at_a_time": {"throughput_qps": nq / serial_fin[-1],
                                            "p50_ms": float(np.percentile(serial_fin * 1e3, 50)),
                                            "p99_ms": float(np.percentile(serial_fin * 1e3, 99))},

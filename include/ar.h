@@ -419,20 +419,27 @@ const char *ar_version(void);
  * host worker thread.  Queries are taken in submission order; the next query starts as
  * soon as a slot is free and its estimated workspace fits the device-memory budget next
  * to the workspaces of the queries in flight, so queries of different scenes, image
- * sizes and boxes run on the device at the same time.  A query's result is the same as
+ * sizes and boxes run on the device at the same time once a backlog builds up: a query
+ * starts beside running ones only while at least overlap_queue queries wait (kernels of
+ * concurrent queries interleave without preemption, so a query beside a long one takes
+ * longer; overlap pays when it drains a backlog).  A query's result is the same as
  * ar_render_bounds on the same arguments (same kernels, its own workspace).
  *
- * hbm_budget  device bytes all slot workspaces may hold (0: a quarter of the free memory
- *             at creation); scenes are not counted.  A query whose estimate exceeds the
- *             budget on its own runs when no other query is in flight.
+ * hbm_budget  device bytes all slot workspaces may hold (0: half of the free memory at
+ *             creation); scenes are not counted.  A query whose estimate exceeds the
+ *             budget on its own runs when no other query is in flight.  A slot keeps its
+ *             workspace between queries unless the workspaces held exceed the budget,
+ *             then it frees it (counted in ar_server_stats.releases).
  * slots       queries in flight at once, 1..16 (0: 4).
+ * overlap_queue  queries waiting from which the next starts beside running ones (0: the
+ *             number of slots; 1: whenever a slot is free).
  */
 typedef struct ar_server ar_server;
 
 typedef struct {
   uint64_t hbm_budget;
   int32_t slots;
-  int32_t reserved;
+  int32_t overlap_queue;
 } ar_server_config;
 
 typedef struct {
@@ -453,6 +460,7 @@ typedef struct {
   double busy_s;                    /* host time with at least one query in flight */
   uint64_t hbm_budget, peak_bytes;  /* budget and peak workspace bytes held */
   int64_t pairs;                    /* evaluated (pixel, Gaussian) pairs, all queries */
+  int64_t releases;                 /* slot workspaces freed to stay within the budget */
 } ar_server_stats;
 
 /* cfg may be NULL (defaults).  *out receives the handle. */

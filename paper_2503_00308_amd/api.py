@@ -79,7 +79,7 @@ class Stats(ctypes.Structure):
 
 
 class ServerConfig(ctypes.Structure):
-    _fields_ = [("hbm_budget", ctypes.c_uint64), ("slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("slots", ctypes.c_int32), ("overlap_queue", ctypes.c_int32)]
 
 
 class QueryResult(ctypes.Structure):
@@ -93,7 +93,7 @@ class ServerStats(ctypes.Structure):
                 ("slots", ctypes.c_int32), ("peak_inflight", ctypes.c_int32),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("busy_s", ctypes.c_double), ("hbm_budget", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
-                ("pairs", ctypes.c_int64)]
+                ("pairs", ctypes.c_int64), ("releases", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -483,10 +483,10 @@ class Server:
     submit() allocates the two output tensors with torch and keeps them until wait()
     returns them; the server writes them from its own streams."""
 
-    def __init__(self, slots: int = 0, hbm_budget: int = 0):
+    def __init__(self, slots: int = 0, hbm_budget: int = 0, overlap_queue: int = 0):
         lib = load()
         self.handle = ctypes.c_void_p()
-        cfg = ServerConfig(int(hbm_budget), int(slots), 0)
+        cfg = ServerConfig(int(hbm_budget), int(slots), int(overlap_queue))
         _check(lib.ar_server_create(ctypes.byref(cfg), ctypes.byref(self.handle)))
         self._scenes = []
         self._out = {}

@@ -1,6 +1,7 @@
 // Query server with continuous batching over resident scenes (include/ar.h, "Query
 // server").  Host code: one worker thread per slot, each with its own HIP stream and
-// workspace; a FIFO queue with admission by the device-memory budget.
+// workspace; a queue taken in order with admission by the device-memory budget; a query
+// starts beside running ones only when a backlog has built up.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -59,12 +60,14 @@ struct ar_server {
   std::vector<const ar_scene *> scenes;
   std::vector<ar::Density> density;   // per scene, from its last query (rotating and not)
   std::vector<ar::Density> density_rot;
+  std::vector<double> density_pix, density_rot_pix;   // image pixels of those queries
   std::vector<std::unique_ptr<Slot>> slots;
   std::vector<double> latencies;
   int device = 0;
   uint64_t budget = 0, peak_bytes = 0;
-  int64_t next_ticket = 1, submitted = 0, completed = 0, failed = 0, pairs = 0;
+  int64_t next_ticket = 1, submitted = 0, completed = 0, failed = 0, pairs = 0, releases = 0;
   int inflight = 0, peak_inflight = 0;
+  int overlap_queue = 4;       // queries waiting from which one starts beside running ones
   double busy_s = 0.0;
   Clock::time_point busy_since;
   bool stop = false;
@@ -84,10 +87,15 @@ struct ar_server {
       {
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
+          // the next query in order starts when no query runs, or beside running ones
+          // once overlap_queue queries wait (kernels of concurrent queries interleave
+          // without preemption, so a query beside a long one stretches: worth it only
+          // to drain a backlog), and when its workspace fits the budget
           if (!queue.empty()) {
             const auto &h = queue.front();
             const size_t need = std::max(slot.ws.bytes, h->est);
-            if (charged_except(&slot) + need <= budget || inflight == 0) {
+            const bool may_overlap = (int)queue.size() >= overlap_queue;
+            if (inflight == 0 || (may_overlap && charged_except(&slot) + need <= budget)) {
               q = h;
               queue.pop_front();
               slot.charge = need;
@@ -121,6 +129,7 @@ struct ar_server {
           latencies.push_back(ms_between(q->t_submit, now));
           pairs += st.pairs;
           (q->rotates ? density_rot : density)[q->scene] = slot.ws.density;
+          (q->rotates ? density_rot_pix : density_pix)[q->scene] = (double)q->prm.width * q->prm.height;
         } else {
           ++failed;
         }
@@ -132,6 +141,7 @@ struct ar_server {
         if (charged_except(nullptr) > budget) {
           ar::release_workspace(slot.ws);
           slot.charge = 0;
+          ++releases;
         }
       }
       cv_done.notify_all();
@@ -148,15 +158,17 @@ int ar_server_create(const ar_server_config *cfg, ar_server **out) {
   ar_server_config c{};
   if (cfg) c = *cfg;
   if (c.slots < 0 || c.slots > 16) return ar::fail(AR_E_INVALID, "slots %d outside [0, 16]", c.slots);
+  if (c.overlap_queue < 0) return ar::fail(AR_E_INVALID, "overlap_queue %d is negative", c.overlap_queue);
   std::unique_ptr<ar_server> srv(new ar_server());
   HIP_TRY(hipGetDevice(&srv->device));
   if (c.hbm_budget == 0) {
     size_t free_b = 0, total_b = 0;
     HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-    c.hbm_budget = free_b / 4;
+    c.hbm_budget = free_b / 2;
   }
   srv->budget = c.hbm_budget;
   const int nslots = c.slots ? c.slots : 4;
+  srv->overlap_queue = c.overlap_queue ? c.overlap_queue : nslots;
   for (int k = 0; k < nslots; ++k) {
     std::unique_ptr<Slot> s(new Slot());
     HIP_TRY(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
@@ -193,6 +205,8 @@ int ar_server_add_scene(ar_server *srv, const ar_scene *scene, int32_t *scene_id
   srv->scenes.push_back(scene);
   srv->density.push_back(ar::Density{});
   srv->density_rot.push_back(ar::Density{});
+  srv->density_pix.push_back(0.0);
+  srv->density_rot_pix.push_back(0.0);
   return AR_OK;
 }
 
@@ -201,6 +215,7 @@ int ar_server_submit(ar_server *srv, int32_t scene_id, const ar_intrinsics *intr
   if (!srv || !ticket) return ar::fail(AR_E_INVALID, "server or ticket is NULL");
   const ar_scene *scene = nullptr;
   ar::Density dens, dens_rot;
+  double pix = 0.0, pix_rot = 0.0;
   {
     std::lock_guard<std::mutex> lk(srv->mu);
     if (scene_id < 0 || scene_id >= (int32_t)srv->scenes.size())
@@ -208,6 +223,8 @@ int ar_server_submit(ar_server *srv, int32_t scene_id, const ar_intrinsics *intr
     scene = srv->scenes[scene_id];
     dens = srv->density[scene_id];
     dens_rot = srv->density_rot[scene_id];
+    pix = srv->density_pix[scene_id];
+    pix_rot = srv->density_rot_pix[scene_id];
   }
   int rc = ar::validate_box(box);
   if (rc) return rc;
@@ -223,7 +240,12 @@ int ar_server_submit(ar_server *srv, int32_t scene_id, const ar_intrinsics *intr
   q->box = *box;
   q->lo = lo_rgb;
   q->hi = hi_rgb;
-  q->est = ar::query_bytes(scene, q->prm, q->P, q->rotates, 1, q->rotates ? dens_rot : dens);
+  // the scene's last density, its pairs per Gaussian scaled to this image (a Gaussian
+  // covers a number of pixels proportional to the image's at a fixed field of view)
+  ar::Density d = q->rotates ? dens_rot : dens;
+  const double dpix = q->rotates ? pix_rot : pix;
+  if (dpix > 0.0) d.pairs_per_item *= (double)q->prm.width * q->prm.height / dpix;
+  q->est = ar::query_bytes(scene, q->prm, q->P, q->rotates, 1, d);
   q->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> lk(srv->mu);
@@ -294,6 +316,7 @@ int ar_server_report(ar_server *srv, ar_server_stats *out) {
   out->hbm_budget = srv->budget;
   out->peak_bytes = srv->peak_bytes;
   out->pairs = srv->pairs;
+  out->releases = srv->releases;
   return AR_OK;
 }
 

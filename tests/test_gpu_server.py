@@ -45,11 +45,13 @@ def _alone(api, handles, queries):
     return out
 
 
-def test_server_results_same_alone_and_in_mix():
+@pytest.mark.parametrize("overlap_queue", [0, 1])
+def test_server_results_same_alone_and_in_mix(overlap_queue):
+    """24 queries at once (a backlog, so queries overlap under either policy)."""
     api = _api()
     scenes, queries = _workload()
     handles = [api.Scene(sc) for sc in scenes]
-    srv = api.Server(slots=4)
+    srv = api.Server(slots=4, overlap_queue=overlap_queue)
     ids = [srv.add_scene(h) for h in handles]
     tickets = [srv.submit(ids[s], intr, box) for s, intr, box in queries]
     mixed = []
@@ -68,6 +70,29 @@ def test_server_results_same_alone_and_in_mix():
         assert np.array_equal(ml, al) and np.array_equal(mh, ah), k
     for h in handles:
         h.close()
+
+
+def test_server_overlaps_only_under_a_backlog():
+    """Two queries with overlap_queue 4: the second waits for the first (one in flight);
+    with overlap_queue 1 it starts beside it."""
+    api = _api()
+    scenes, queries = _workload(seed=2, nq=2)
+    handles = [api.Scene(sc) for sc in scenes]
+    peaks = {}
+    for ovq in (4, 1):
+        srv = api.Server(slots=4, overlap_queue=ovq)
+        ids = [srv.add_scene(h) for h in handles]
+        tickets = [srv.submit(ids[s], intr, box) for s, intr, box in queries]
+        for t in tickets:
+            assert srv.wait(t)[2]["status"] == 0
+        peaks[ovq] = srv.report()["peak_inflight"]
+        srv.close()
+    for h in handles:
+        h.close()
+    assert peaks[4] == 1
+    assert peaks[1] in (1, 2)
+    with pytest.raises(api.ARError):
+        api.Server(slots=4, overlap_queue=-1)
 
 
 def test_server_budget_admits_one_query_at_a_time():
