@@ -64,8 +64,15 @@ typedef struct ar_scene ar_scene;
  *   cov_factor [9][n]  entry (r, c) of Mw at plane 3 r + c
  *   opacity    [n]
  *   rgb        [3][n]
- * Rejected (AR_E_INVALID): n < 1, a NULL array, a non-finite value, o outside (0, 1],
- * a colour outside [0, 1].
+ * or, in place of cov_factor (NULL), the rotation and scales a trained splat stores:
+ *   quat       [4][n]  quaternion (w, x, y, z), any non-zero length (normalised here)
+ *   scale      [3][n]  scales (standard deviations along the rotated axes), >= 0
+ * from which Mw = R(q) diag(scale) (a factor of Cov = R diag(scale)^2 R^T), formed in
+ * FP64 on the host and rounded to float32.  quat and scale are ignored when cov_factor
+ * is given.
+ * Rejected (AR_E_INVALID): n < 1, a NULL array (quat and scale only when cov_factor is
+ * NULL), a non-finite value, a zero quaternion, a negative scale, o outside (0, 1], a
+ * colour outside [0, 1].
  */
 typedef struct {
   int32_t n;
@@ -74,6 +81,8 @@ typedef struct {
   const float *cov_factor;
   const float *opacity;
   const float *rgb;
+  const float *quat;
+  const float *scale;
 } ar_scene_desc;
 
 /* Pinhole intrinsics and image size (Sec. 2.2, K).  width, height in [1, 16384]. */
@@ -242,10 +251,14 @@ int32_t ar_scene_size(const ar_scene *scene);
 
 /*
  * Lower / upper images over the pose box (AbstractSplat, Sec. 3.3).
- *   lo_rgb, hi_rgb: device pointers to height*width*3 floats, [row][col][channel];
+ *   lo_rgb, hi_rgb: height*width*3 floats, [row][col][channel], both device memory or
+ *   both host memory (pinned or pageable: the images are rendered into the scene
+ *   handle's workspace and copied back before the call returns; with device memory the
+ *   call returns once its work is complete on the stream as well);
  *   for every pose p of the box and every pixel, lo <= GaussianSplat(scene, p) <= hi.
  *   opts, stats may be NULL.  The scene handle's workspace is reused, so calls on the
- *   same scene handle must not overlap in time (serialise them on one stream).
+ *   same scene handle must not overlap in time (serialise them on one stream).  One
+ *   output in device memory and the other not is rejected (AR_E_INVALID).
  */
 int ar_render_bounds(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *box,
                      const ar_options *opts, float *lo_rgb, float *hi_rgb, void *hip_stream,
@@ -258,6 +271,7 @@ int ar_render_bounds(const ar_scene *scene, const ar_intrinsics *intr, const ar_
  * limits:
  *   - translation boxes only (no yaw / pitch / roll, ORBIT width 0); a rotation box is
  *     rejected with AR_E_UNSUPPORTED;
+ *   - the outputs are device memory (host outputs are rejected with AR_E_INVALID);
  *   - every device buffer of the render comes from one static device array of 256 MiB
  *     per GPU, which each GPU the library runs on holds until the process ends; a render
  *     that needs more (e.g. above about 10k Gaussians at 128x128 with a wide box) fails
@@ -275,7 +289,8 @@ int ar_render_bounds_noalloc(const ar_scene *scene, const ar_intrinsics *intr, c
 
 /*
  * Bounds for ncells pose boxes of one scene (the partition of a larger set of poses,
- * Sec. 4.2 "#part"); lo_rgb / hi_rgb hold ncells images back to back.  The result is
+ * Sec. 4.2 "#part"); lo_rgb / hi_rgb hold ncells images back to back, device or host
+ * memory as for ar_render_bounds.  The result is
  * that of ncells calls of ar_render_bounds (bit for bit when opts->chunk is set);
  * consecutive cells with the same pose variables share one launch per stage, up to
  * opts->cells_per_launch cells (default: what fits a quarter of the free device

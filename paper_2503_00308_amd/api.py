@@ -29,7 +29,8 @@ class ARError(RuntimeError):
 class SceneDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("on_device", ctypes.c_int32),
                 ("mean", ctypes.c_void_p), ("cov_factor", ctypes.c_void_p),
-                ("opacity", ctypes.c_void_p), ("rgb", ctypes.c_void_p)]
+                ("opacity", ctypes.c_void_p), ("rgb", ctypes.c_void_p),
+                ("quat", ctypes.c_void_p), ("scale", ctypes.c_void_p)]
 
 
 class SceneSet(ctypes.Structure):
@@ -203,20 +204,26 @@ def options(d=None) -> Options:
 
 class Scene:
     """A device-resident scene (ar_scene handle) built from a dict of arrays:
-    mean (N,3), cov_factor (N,3,3), opacity (N,), rgb (N,3); with any of the keys
-    rgb_hi (N,3), opacity_lo (N,), set_lo / set_hi (nvar,), mean_var (N,), mean_dir (N,3)
-    a set of scenes (ar_scene_create_set)."""
+    mean (N,3), cov_factor (N,3,3) or quat (N,4, w x y z) and scale (N,3), opacity (N,),
+    rgb (N,3); with any of the keys rgb_hi (N,3), opacity_lo (N,), set_lo / set_hi
+    (nvar,), mean_var (N,), mean_dir (N,3) a set of scenes (ar_scene_create_set)."""
 
     def __init__(self, scene, stream=None):
         lib = load()
         n = len(scene["mean"])
         # structure-of-arrays, float32, contiguous (the layout include/ar.h specifies)
         self._mean = np.ascontiguousarray(np.asarray(scene["mean"], np.float32).T)
-        self._cov = np.ascontiguousarray(np.asarray(scene["cov_factor"], np.float32).reshape(n, 9).T)
         self._op = np.ascontiguousarray(np.asarray(scene["opacity"], np.float32))
         self._rgb = np.ascontiguousarray(np.asarray(scene["rgb"], np.float32).T)
-        desc = SceneDesc(n, 0, self._mean.ctypes.data, self._cov.ctypes.data,
-                         self._op.ctypes.data, self._rgb.ctypes.data)
+        self._cov = self._quat = self._scale = None
+        if "cov_factor" in scene:
+            self._cov = np.ascontiguousarray(np.asarray(scene["cov_factor"], np.float32).reshape(n, 9).T)
+        else:
+            self._quat = np.ascontiguousarray(np.asarray(scene["quat"], np.float32).reshape(n, 4).T)
+            self._scale = np.ascontiguousarray(np.asarray(scene["scale"], np.float32).reshape(n, 3).T)
+        ptr = lambda a: a.ctypes.data if a is not None else None
+        desc = SceneDesc(n, 0, self._mean.ctypes.data, ptr(self._cov), self._op.ctypes.data, self._rgb.ctypes.data,
+                         ptr(self._quat), ptr(self._scale))
         h = ctypes.c_void_p()
         if any(k in scene for k in SET_KEYS):
             st = SceneSet()
@@ -266,7 +273,9 @@ def _stream_ptr(stream):
 
 
 def render_bounds(scene: Scene, intr, box, opts=None, stream=None, out=None):
-    """Lower / upper images (torch float32 tensors (H, W, 3) on the GPU) and stats."""
+    """Lower / upper images (torch float32 tensors (H, W, 3) on the GPU) and stats.
+    out = (lo, hi) may give the output tensors (float32, contiguous; GPU or CPU: host
+    outputs are copied back by the library)."""
     import torch
     lib = load()
     ci = intrinsics(intr)
@@ -347,16 +356,21 @@ class Plan:
             pass
 
 
-def render_batch(scene: Scene, intr, cells, opts=None, stream=None):
-    """Bounds for a list of pose boxes: tensors (ncells, H, W, 3) and accumulated stats."""
+def render_batch(scene: Scene, intr, cells, opts=None, stream=None, out=None):
+    """Bounds for a list of pose boxes: tensors (ncells, H, W, 3) and accumulated stats.
+    out = (lo, hi) may give the output tensors (float32, contiguous; GPU or CPU: host
+    outputs are copied back by the library)."""
     import torch
     lib = load()
     ci = intrinsics(intr)
     H, W = ci.height, ci.width
     m = len(cells)
     arr = (PoseBox * m)(*[pose_box(c) for c in cells])
-    lo = torch.empty((m, H, W, 3), dtype=torch.float32, device="cuda")
-    hi = torch.empty((m, H, W, 3), dtype=torch.float32, device="cuda")
+    if out is None:
+        lo = torch.empty((m, H, W, 3), dtype=torch.float32, device="cuda")
+        hi = torch.empty((m, H, W, 3), dtype=torch.float32, device="cuda")
+    else:
+        lo, hi = out
     st = Stats()
     co = options(opts)
     _check(lib.ar_render_batch(scene.handle, ctypes.byref(ci), arr, m, ctypes.byref(co),

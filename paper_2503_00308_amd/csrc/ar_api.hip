@@ -1010,6 +1010,48 @@ int check_outputs(const float *lo, const float *hi) {
   return AR_OK;
 }
 
+// Outputs that are both device memory (*host = false) or both host memory, pinned or
+// pageable (*host = true: the images are rendered into workspace buffers and copied).
+static int check_outputs_any(const float *lo, const float *hi, bool *host) {
+  if (!lo || !hi) return fail(AR_E_INVALID, "output image is NULL");
+  bool dev[2];
+  int k = 0;
+  for (const float *p : {lo, hi}) {
+    hipPointerAttribute_t a{};
+    const hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) (void)hipGetLastError();   // memory HIP does not know: pageable host memory
+    dev[k++] = e == hipSuccess && a.type == hipMemoryTypeDevice;
+  }
+  if (dev[0] != dev[1]) return fail(AR_E_INVALID, "one output image is device memory and the other is not");
+  *host = !dev[0];
+  return AR_OK;
+}
+
+// Host outputs: the device images of `cells` cells (workspace buffers, grown as needed)
+static int ensure_out_stage(Workspace &ws, size_t floats) {
+  if (floats <= ws.cap_out_stage && ws.out_stage) return AR_OK;
+  HIP_TRY(grow(ws, ws.out_stage, 2 * floats));
+  ws.cap_out_stage = floats;
+  return AR_OK;
+}
+
+// Renders m cells of one launch into lo / hi, through the workspace's staging images when
+// the outputs are host memory (copied back before returning).
+static int render_cells_out(const ar_scene *sc, Workspace &ws, const Params &prm, const ar_pose_box *cells, int m,
+                            int P, bool rot, float *lo, float *hi, bool host, hipStream_t s, ar_stats *st) {
+  if (!host) return render_cells(sc, ws, prm, cells, m, P, rot, lo, hi, s, st);
+  const size_t n = (size_t)m * prm.width * prm.height * 3;
+  int rc = ensure_out_stage(ws, n);
+  if (rc) return rc;
+  float *dlo = ws.out_stage, *dhi = ws.out_stage + n;
+  rc = render_cells(sc, ws, prm, cells, m, P, rot, dlo, dhi, s, st);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(lo, dlo, n * sizeof(float), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hi, dhi, n * sizeof(float), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return AR_OK;
+}
+
 // Cells rendered as ar_render_batch in launches of up to 64 cells (or
 // options.cells_per_launch) and united into lo / hi: minimum of the lower images,
 // maximum of the upper ones.  stats (may be NULL) accumulates over the cells.
@@ -1194,6 +1236,38 @@ static int host_view(const T *p, size_t n, bool on_device, hipStream_t s, std::v
   return AR_OK;
 }
 
+// Covariance factors Mw = R(q) diag(s) from quaternions (w, x, y, z; normalised) and
+// scales, in FP64, rounded to float32, in the layout of ar_scene_desc.cov_factor.
+static int cov_from_quat_scale(const ar_scene_desc *d, bool dev, hipStream_t s, std::vector<float> &out,
+                               const float *&cov) {
+  const size_t n = (size_t)d->n;
+  std::vector<float> hq, hs;
+  const float *q = nullptr, *sc = nullptr;
+  int rc = host_view(d->quat, 4 * n, dev, s, hq, q);
+  if (!rc) rc = host_view(d->scale, 3 * n, dev, s, hs, sc);
+  if (rc) return rc;
+  out.resize(9 * n);
+  for (size_t i = 0; i < n; ++i) {
+    double w = q[i], x = q[n + i], y = q[2 * n + i], z = q[3 * n + i];
+    const double len = sqrt(w * w + x * x + y * y + z * z);
+    if (!isfinite(len) || !(len > 0.0)) return fail(AR_E_INVALID, "quaternion %zu is zero or not finite", i);
+    w /= len;
+    x /= len;
+    y /= len;
+    z /= len;
+    const double R[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
+                            {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
+                            {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
+    for (int c = 0; c < 3; ++c) {
+      const double sv = sc[c * n + i];
+      if (!isfinite(sv) || sv < 0.0) return fail(AR_E_INVALID, "scale %g at %zu is negative or not finite", sv, i);
+      for (int r = 0; r < 3; ++r) out[(3 * r + c) * n + i] = (float)(R[r][c] * sv);
+    }
+  }
+  cov = out.data();
+  return AR_OK;
+}
+
 // A scene handle for a scene (set == NULL) or a set of scenes.  Device layout, one
 // allocation: mean 3n, cov 9n, opacity n, rgb 3n, opacity_lo n, rgb_hi 3n, ind_mean 3n,
 // mean_dir 3n floats, then mean_var n int32.
@@ -1202,7 +1276,8 @@ int create_scene(const ar_scene_desc *desc, const ar_scene_set *set, void *hip_s
   *out = nullptr;
   if (!desc) return fail(AR_E_INVALID, "scene description is NULL");
   if (desc->n < 1) return fail(AR_E_INVALID, "scene has n = %d Gaussians", desc->n);
-  if (!desc->mean || !desc->cov_factor || !desc->opacity || !desc->rgb) return fail(AR_E_INVALID, "scene array is NULL");
+  if (!desc->mean || !desc->opacity || !desc->rgb || (!desc->cov_factor && (!desc->quat || !desc->scale)))
+    return fail(AR_E_INVALID, "scene array is NULL");
   hipStream_t s = (hipStream_t)hip_stream;
   const size_t n = (size_t)desc->n;
   std::vector<float> hm, hc, ho, hr, hol, hrh, hmd;
@@ -1211,7 +1286,8 @@ int create_scene(const ar_scene_desc *desc, const ar_scene_set *set, void *hip_s
   const int32_t *mvar = nullptr;
   const bool dev = desc->on_device != 0;
   int rc = host_view(desc->mean, 3 * n, dev, s, hm, mean);
-  if (!rc) rc = host_view(desc->cov_factor, 9 * n, dev, s, hc, cov);
+  if (!rc && desc->cov_factor) rc = host_view(desc->cov_factor, 9 * n, dev, s, hc, cov);
+  if (!rc && !desc->cov_factor) rc = cov_from_quat_scale(desc, dev, s, hc, cov);
   if (!rc) rc = host_view(desc->opacity, n, dev, s, ho, op);
   if (!rc) rc = host_view(desc->rgb, 3 * n, dev, s, hr, rgb);
   if (rc) return rc;
@@ -1313,15 +1389,16 @@ int ar_render_bounds(const ar_scene *scene, const ar_intrinsics *intr, const ar_
   ar::Params prm{};
   rc = ar::make_params(scene, intr, opts, prm);
   if (rc) return rc;
-  rc = ar::check_outputs(lo_rgb, hi_rgb);
+  bool host = false;
+  rc = ar::check_outputs_any(lo_rgb, hi_rgb, &host);
   if (rc) return rc;
   if (stats) memset(stats, 0, sizeof(*stats));
   bool rot = false;
   int P = 0;
   rc = ar::render_vars(scene, box, &rot, &P);
   if (rc) return rc;
-  return ar::render_cells(scene, const_cast<ar_scene *>(scene)->ws, prm, box, 1, P, rot, lo_rgb, hi_rgb,
-                          (hipStream_t)hip_stream, stats);
+  return ar::render_cells_out(scene, const_cast<ar_scene *>(scene)->ws, prm, box, 1, P, rot, lo_rgb, hi_rgb, host,
+                              (hipStream_t)hip_stream, stats);
 }
 
 int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *cells, int32_t ncells,
@@ -1335,7 +1412,8 @@ int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_p
   ar::Params prm{};
   int rc = ar::make_params(scene, intr, opts, prm);
   if (rc) return rc;
-  rc = ar::check_outputs(lo_rgb, hi_rgb);
+  bool host = false;
+  rc = ar::check_outputs_any(lo_rgb, hi_rgb, &host);
   if (rc) return rc;
   if (stats) memset(stats, 0, sizeof(*stats));
   const size_t img = (size_t)intr->width * intr->height * 3;
@@ -1357,8 +1435,8 @@ int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_p
     while (i < j) {
       ar::Workspace &ws = const_cast<ar_scene *>(scene)->ws;
       const int m = std::min(j - i, ar::batch_cells(scene, ws, prm, P, rot, opts));
-      rc = ar::render_cells(scene, ws, prm, cells + i, m, P, rot, lo_rgb + i * img, hi_rgb + i * img,
-                            (hipStream_t)hip_stream, stats);
+      rc = ar::render_cells_out(scene, ws, prm, cells + i, m, P, rot, lo_rgb + i * img, hi_rgb + i * img, host,
+                                (hipStream_t)hip_stream, stats);
       if (rc) return rc;
       i += m;
     }

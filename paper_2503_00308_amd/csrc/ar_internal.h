@@ -225,6 +225,8 @@ struct Workspace {
   size_t cap_listlo = 0;
   unsigned long long *ind_und = nullptr;   // [cells of a launch] undecided Ind pairs
   size_t cap_ind_und = 0;
+  float *out_stage = nullptr;        // host outputs: the device images (lower, then upper)
+  size_t cap_out_stage = 0;
   // Arena mode (the allocation-free entry point): buffers are carved from [arena,
   // arena + arena_cap) by a bump pointer instead of hipMalloc; nothing is freed, pinned
   // host blocks and events are not created (pose_host / host_counters point to host
