@@ -202,6 +202,9 @@ typedef struct {
   int64_t runs;          /* rotation boxes: runs of list positions holding the Ind sets */
   int64_t cycles_a, cycles_b; /* rotation boxes: summed wave clock cycles of the pixel loop's two phases */
   int64_t ind_tests;     /* rotation boxes: pairwise Ind tests (summed window lengths) */
+  int64_t ind_borderline; /* rotation boxes: Ind tests decided by a bound within rounding of its
+                             threshold (1e-12 (1 + |uw_i - uw_j|_1)), which another order of
+                             the same operations might decide otherwise */
 } ar_stats;
 
 /* Copies the scene to the device on `stream` (synchronises it).  *out receives a

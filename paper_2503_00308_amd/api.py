@@ -73,7 +73,8 @@ class Stats(ctypes.Structure):
                 ("n_fallback", ctypes.c_int32), ("n_wild", ctypes.c_int32), ("n_dropped", ctypes.c_int32),
                 ("P", ctypes.c_int32), ("max_window", ctypes.c_int32), ("segment_length", ctypes.c_int32),
                 ("raster_ms", ctypes.c_double), ("total_ms", ctypes.c_double), ("runs", ctypes.c_int64),
-                ("cycles_a", ctypes.c_int64), ("cycles_b", ctypes.c_int64), ("ind_tests", ctypes.c_int64)]
+                ("cycles_a", ctypes.c_int64), ("cycles_b", ctypes.c_int64), ("ind_tests", ctypes.c_int64),
+                ("ind_borderline", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

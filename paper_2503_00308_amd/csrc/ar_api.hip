@@ -428,6 +428,7 @@ void add_stats(ar_stats &a, const ar_stats &b) {
   a.cycles_a += b.cycles_a;
   a.cycles_b += b.cycles_b;
   a.ind_tests += b.ind_tests;
+  a.ind_borderline += b.ind_borderline;
 }
 
 // Cells per launch of a batch: the option if given, else as many as fit a quarter of
@@ -799,7 +800,8 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
     if (rc) return rc;
   }
   if (timed) HIP_TRY(hipEventRecord(ws.ev[3], s));
-  HIP_TRY(hipMemcpyAsync(ws.host_counters, ws.counters, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(ws.host_counters, ws.counters, (kIndBorder + 1) * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   float ms_raster = 0.0f, ms_total = 0.0f;
   if (timed) {
@@ -819,6 +821,7 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
     st->cycles_a += (int64_t)ws.host_counters[6];
     st->cycles_b += (int64_t)ws.host_counters[7];
     st->ind_tests += (int64_t)ws.host_counters[1];
+    st->ind_borderline += (int64_t)ws.host_counters[kIndBorder];
   }
   return AR_OK;
 }

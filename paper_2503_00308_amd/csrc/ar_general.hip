@@ -122,9 +122,13 @@ __global__ __launch_bounds__(256) void k_list_box(const uint32_t *__restrict__ r
 // Ind(d_i - d_j) in {0, 1, 2 = unknown} (see the file comment).  Depth forms: the lower
 // form's coefficients at [0, P) and its constant at [S - 1], the upper form's at
 // [S, S + P) and [2S - 1] (S = kMaxP + 1 by item, S = P + 1 in the compact copy).
-template <int P, int S = kMaxP + 1>
+// BORDER: *border is set when the deciding bound lies within rounding of its threshold
+// (1e-12 (1 + |uw_i - uw_j|_1) of 0 for the identity, of +-kIndMargin for the literal
+// bound, which decides only where the identity does not; an exact tie of the identity,
+// both ends 0, is not borderline): a decision another order of operations might flip.
+template <int P, int S = kMaxP + 1, bool BORDER = false>
 __device__ __forceinline__ int ind_pair(const PoseForms &pose, const double *uwi, const double *uwj,
-                                        const double *dfi, const double *dfj) {
+                                        const double *dfi, const double *dfj, bool *border = nullptr) {
   // identity bound: sum_l A_z,l * (uw_i - uw_j)_l, each term a scaled form; with A_z,l
   // in mid-radius form (m, r), c A_z,l has lower form c m - |c| r and upper c m + |c| r
   double mid[P + 1], rad[P + 1];
@@ -148,6 +152,11 @@ __device__ __forceinline__ int ind_pair(const PoseForms &pose, const double *uwi
     sup += fabs(mid[k] + rad[k]);
   }
   const double lo_r = (mid[P] - rad[P]) - slo, hi_r = (mid[P] + rad[P]) + sup;
+  double sb = 0.0;
+  if (BORDER) {
+    sb = 1e-12 * (1.0 + fabs(uwi[0] - uwj[0]) + fabs(uwi[1] - uwj[1]) + fabs(uwi[2] - uwj[2]));
+    *border = !(lo_r == 0.0 && hi_r == 0.0) && (fabs(lo_r) < sb || fabs(hi_r) < sb);
+  }
   // both bounds are sound, so when the identity decides the literal bound cannot
   // contradict it; its form loads are skipped
   if (lo_r > 0.0) return 1;
@@ -161,6 +170,7 @@ __device__ __forceinline__ int ind_pair(const PoseForms &pose, const double *uwi
   }
   const double lo_l = (dfi[S - 1] - dfj[2 * S - 1]) - sl;
   const double hi_l = (dfi[2 * S - 1] - dfj[S - 1]) + sh;
+  if (BORDER) *border = *border || fabs(lo_l - kIndMargin) < sb || fabs(hi_l + kIndMargin) < sb;
   if (lo_l > kIndMargin) return 1;
   if (hi_l <= -kIndMargin) return 0;
   return 2;
@@ -246,7 +256,8 @@ template <int P, int MODE, bool COMPACT>
 __device__ __forceinline__ void wave_runs(const PoseForms &pose, const IndSrc<P, COMPACT> &src, int i, int ps,
                                           int qe, const double *uwi, const double *dfi,
                                           unsigned long long *masks, uint32_t *out_def, uint32_t *out_may,
-                                          int lane, uint32_t &ndef, uint32_t &nmay, uint32_t &nund) {
+                                          int lane, uint32_t &ndef, uint32_t &nmay, uint32_t &nund,
+                                          uint32_t &nbord) {
   constexpr bool EMIT = MODE == kRunsEmit;
   uint32_t sd = 0, ed = 0, sm = 0, em = 0;      // run starts / ends so far
   bool cd = ps > 0, cm = ps > 0;                // the position before the chunk is in the set
@@ -260,6 +271,7 @@ __device__ __forceinline__ void wave_runs(const PoseForms &pose, const IndSrc<P,
   }
   const unsigned long long below = (1ull << lane) - 1ull;
   nund = 0;
+  nbord = 0;
   for (int t = ps, c = 0; t < qe; t += 64, ++c) {
     const int j = t + lane;
     const bool valid = j < qe;
@@ -270,14 +282,16 @@ __device__ __forceinline__ void wave_runs(const PoseForms &pose, const IndSrc<P,
       M = masks[2 * (size_t)c + 1];
     } else {
       int ind = 0;
+      bool bd = false;
       if (valid && j != i) {
         double uwj[3];
         src.mean_of(j, uwj);
-        ind = ind_pair<P, IndSrc<P, COMPACT>::S>(pose, uwi, uwj, dfi, src.forms_of(j));
+        ind = ind_pair<P, IndSrc<P, COMPACT>::S, MODE == kRunsCount>(pose, uwi, uwj, dfi, src.forms_of(j), &bd);
       }
       D = __ballot(valid && ind == 1);
       M = __ballot(valid && ind != 0);
       nund += (uint32_t)__popcll(M & ~D);
+      if (MODE == kRunsCount) nbord += (uint32_t)__popcll(__ballot(bd));
       if (MODE == kRunsCount && masks && lane == 0) {
         masks[2 * (size_t)c] = D;
         masks[2 * (size_t)c + 1] = M;
@@ -438,7 +452,7 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
       out_def = runs + 2 * (size_t)cnt[2 * (size_t)p];
       out_may = runs + 2 * (size_t)cnt[2 * (size_t)p + 1];
     }
-    uint32_t ndef = 0, nmay = 0, nund = 0;
+    uint32_t ndef = 0, nmay = 0, nund = 0, nbord = 0;
     if (have && !wide) {
       const PoseForms &pose = poses[cell];
       const IndSrc<P, COMPACT> src{lists + beg, sc.ind_mean, COMPACT ? cform : dform, cmean, sc.n,
@@ -448,13 +462,15 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
       int may_start = ps > 0 ? 0 : -1;
       for (int j = ps; j < qe; ++j) {
         int ind = 0;
+        bool bd = false;
         if (j != i) {
           double uwj[3];
           src.mean_of(j, uwj);
-          ind = ind_pair<P, IndSrc<P, COMPACT>::S>(pose, uwi, uwj, dfi, src.forms_of(j));
+          ind = ind_pair<P, IndSrc<P, COMPACT>::S, MODE == kRunsCount>(pose, uwi, uwj, dfi, src.forms_of(j), &bd);
         }
         const bool d1 = ind == 1, m1 = ind != 0;
         nund += ind == 2 ? 1u : 0u;
+        nbord += bd ? 1u : 0u;
         if (d1 && def_start < 0) def_start = j;
         if (!d1 && def_start >= 0) {
           if (EMIT) { out_def[2 * ndef] = (uint32_t)def_start; out_def[2 * ndef + 1] = (uint32_t)j; }
@@ -495,13 +511,14 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
       unsigned long long *km_ = masks ? masks + woff[kp] : nullptr;
       const IndSrc<P, COMPACT> src{lists + kb, sc.ind_mean, COMPACT ? cform : dform, cmean, sc.n, (size_t)kc * sc.n,
                                    (size_t)((uint32_t)kb - pbase)};
-      uint32_t kd, km, ku;
+      uint32_t kd, km, ku, kbd;
       wave_runs<P, MODE, COMPACT>(poses[kc], src, ki, kps, kqe, kuw, src.forms_of(ki), km_, kod, kom, lane, kd, km,
-                                  ku);
+                                  ku, kbd);
       if (lane == k) {
         ndef = kd;
         nmay = km;
         nund = ku;
+        nbord = kbd;
       }
     }
     if (!EMIT && have) {
@@ -509,6 +526,12 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
       cnt[2 * (size_t)p + 1] = nmay;
       // undecided pairs of the cell (counted when asked for)
       if (ind_und && nund) atomicAdd(&ind_und[cell], (unsigned long long)nund);
+    }
+    if (MODE == kRunsCount) {
+      // borderline decisions: one atomic per wave
+      unsigned long long b = nbord;
+      for (int off = 32; off > 0; off >>= 1) b += (unsigned long long)__shfl_xor(b, off);
+      if (lane == 0 && b) atomicAdd(&counters[kIndBorder], b);
     }
   }
   if (MODE == kRunsWindows) {
@@ -543,7 +566,8 @@ __global__ __launch_bounds__(256) void k_runs_count_lanes(const uint32_t *__rest
                                                           unsigned long long *__restrict__ masks,
                                                           uint32_t *__restrict__ cnt,
                                                           const uint32_t *__restrict__ ng_dev,
-                                                          unsigned long long *__restrict__ ind_und) {
+                                                          unsigned long long *__restrict__ ind_und,
+                                                          unsigned long long *__restrict__ counters) {
   using Src = IndSrc<P, true>;
   constexpr int S = Src::S;
   const int lane = threadIdx.x & 63;
@@ -571,7 +595,7 @@ __global__ __launch_bounds__(256) void k_runs_count_lanes(const uint32_t *__rest
 #pragma unroll
       for (int k = 0; k < 2 * S; ++k) dfi[k] = cform[(size_t)p * (2 * S) + k];
     }
-    uint32_t ndef = 0, nmay = 0, nund = 0;
+    uint32_t ndef = 0, nmay = 0, nund = 0, nbord = 0;
     bool pending = have;
     for (;;) {
       const unsigned long long pend = __ballot(pending);
@@ -603,9 +627,11 @@ __global__ __launch_bounds__(256) void k_runs_count_lanes(const uint32_t *__rest
         src.mean_of(j, uwj);
         const double *dfj = src.forms_of(j);
         if (mine && j >= ps && j < qe) {
-          const int ind = j != i ? ind_pair<P, S>(pose, uwi, uwj, dfi, dfj) : 0;
+          bool bd = false;
+          const int ind = j != i ? ind_pair<P, S, true>(pose, uwi, uwj, dfi, dfj, &bd) : 0;
           const bool d1 = ind == 1, m1 = ind != 0;
           nund += ind == 2 ? 1u : 0u;
+          nbord += bd ? 1u : 0u;
           if (d1 && def_start < 0) def_start = j;
           if (!d1 && def_start >= 0) {
             ++nd;
@@ -640,6 +666,9 @@ __global__ __launch_bounds__(256) void k_runs_count_lanes(const uint32_t *__rest
       cnt[2 * (size_t)p + 1] = nmay;
       if (ind_und && nund) atomicAdd(&ind_und[tile / (uint32_t)ntiles], (unsigned long long)nund);
     }
+    unsigned long long b = nbord;
+    for (int off = 32; off > 0; off >>= 1) b += (unsigned long long)__shfl_xor(b, off);
+    if (lane == 0 && b) atomicAdd(&counters[kIndBorder], b);
   }
 }
 
@@ -1090,7 +1119,7 @@ static hipError_t launch_runs_p(const Workspace &ws, const uint32_t *lists, cons
       const dim3 grid((unsigned)std::min<size_t>(((size_t)ng + 255) / 256, 8192)), block(256);
       hipLaunchKernelGGL(k_runs_count_lanes<P>, grid, block, 0, s, ws.pair_key, ws.tile_range, lists,
                          (const float4 *)ws.cmean, ws.cform, poses_dev, ntiles, sc, pbase, ng, ws.win, ws.woff, masks,
-                         ws.run_cnt, dc.entries, dc.ind_und);
+                         ws.run_cnt, dc.entries, dc.ind_und, ws.counters);
       return hipGetLastError();
     }
     return launch_runs_pm<P, kRunsEmit, true>(ws, lists, poses_dev, ntiles, sc, pbase, ng, window_mode, masks, dc, s);

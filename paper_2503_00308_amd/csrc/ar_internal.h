@@ -18,6 +18,7 @@ namespace ar {
 
 constexpr int kMaxP = 6;        // pose variables: 3 translations + 3 angles
 constexpr int kOverflow = 15;   // statistics counter set when a planned launch outgrows a buffer
+constexpr int kIndBorder = 10;  // statistics counter of Ind tests decided within rounding of a threshold
 constexpr int kTile = 8;        // pixel tile side (one 64-lane wave covers a tile)
 constexpr int kTilePix = kTile * kTile;
 constexpr int kListBox = 13;   // per tile list: box of the means, box of their parts across m, max |mean|

@@ -179,6 +179,7 @@ static void fill_stats(const ar_plan *p, ar_stats *st) {
     st->cycles_b += (int64_t)c[7];
     st->tile_pairs += (int64_t)c[8];
     st->runs += (int64_t)c[9];
+    st->ind_borderline += (int64_t)c[ar::kIndBorder];
   }
   st->P = p->P;
   st->segment_length = p->caps.L;

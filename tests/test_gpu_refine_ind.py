@@ -158,6 +158,25 @@ def test_refined_leaves_equal_the_oracle(kind):
         assert np.array_equal(a["hi"], np.asarray(b["hi"], np.float64))
 
 
+def test_borderline_ind_statistic():
+    """ar_stats.ind_borderline: the same with the Ind windows as with every pair tested (a
+    test outside the windows is decided with a margin), and never above the oracle's
+    borderline count (the oracle flags a bound near its threshold even where the other
+    bound decides; the library only where that bound decides)."""
+    from oracle import splat
+    api = _api()
+    for seed, n in ((5, 300), (6, 500)):
+        scene = synth.box_surface_scene(n, n_boxes=4, seed=seed)
+        intr = synth.intrinsics(32)
+        box = synth.camera6_box(dt=0.01, drot=(np.deg2rad(0.7), np.deg2rad(0.4), np.deg2rad(0.2)))
+        sc = api.Scene(scene)
+        got = [api.render_bounds(sc, intr, box, opts)[2]["ind_borderline"] for opts in (None, {"ind_window": 2})]
+        sc.close()
+        count, border = splat.ind_uncertain_count(scene, intr, box)
+        print(f"seed {seed}: gpu borderline {got}, oracle borderline {border}, undecided {count}", flush=True)
+        assert got[0] == got[1] and 0 <= got[0] <= border
+
+
 def test_count_rejections():
     api = _api()
     sc = api.Scene(synth.random_scene(20, seed=1))
