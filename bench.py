@@ -232,7 +232,8 @@ def batched_measure(api, synth, runs=2, per_query_cells=32, autotune=True):
     flops = alg_flops_per_pair(st["P"]) * st["pairs"]
     achieved = flops / (st["raster_ms"] * 1e-3) / 1e12
     return {"workload": desc, "cells": n, "segment_length": st["segment_length"], "autotuned": autotune,
-            "tuned": "segment length only (tile 8x8 and cells per launch are fixed)",
+            "tuned": ("segment length and cells per launch (tile 8x8 fixed)" if autotune else "none"),
+            "cells_per_launch": (int(opts["cells_per_launch"]) if opts else 0),
             "graph": {"ms": t_graph * 1e3, "device_ms": gst["total_ms"], "pairs_per_s": gst["pairs"] / t_graph,
                       "replans": replans, "speedup_vs_per_query": t_single * n / t_graph,
                       "speedup_vs_batch_calls": t_batch / t_graph},

@@ -409,13 +409,17 @@ int ar_render_refined(const ar_scene *scene, const ar_intrinsics *intr, const ar
                       void *hip_stream, ar_pose_box *cells_out, int32_t *ncells_out, ar_stats *stats);
 
 /*
- * Autotuning of the pixel loop's segment length (options.chunk) for a workload: one pose
- * box (ncells = 1) or a batch of cells, rendered as ar_render_batch.  The workload is
- * rendered with the automatic length, then with candidates (translation boxes: the
- * automatic length times 1/2, 3/4, 5/4 and 3/2, multiples of 8 in [8, 4096]; rotation
- * boxes: 32, 48, 64, 96 and 128), reps times each (1..16); *tuned receives a copy of
- * *opts (or of the defaults when opts is NULL) whose chunk is the candidate with the
- * least device time (stats.total_ms).  The workload is rendered once more with *tuned,
+ * Autotuning of the pixel loop's segment length (options.chunk) and, for a batch, of the
+ * cells per launch (options.cells_per_launch) for a workload: one pose box (ncells = 1)
+ * or a batch of cells, rendered as ar_render_batch.  The workload is rendered with the
+ * automatic length, then with candidates (translation boxes: the automatic length times
+ * 1/2, 3/4, 5/4 and 3/2, multiples of 8 in [8, 4096]; rotation boxes: 32, 48, 64, 96
+ * and 128), reps times each (1..16); the chunk is the candidate with the least device
+ * time (stats.total_ms).  With ncells > 1 and no cells_per_launch in *opts, the counts
+ * automatic (what fits the memory budget), half and a quarter of it, 16 and 8 (those
+ * below the automatic count) are then timed by wall clock with that chunk.  *tuned
+ * receives a copy of *opts (or of the defaults when opts is NULL) with the chosen chunk
+ * and cells per launch (0: the automatic count).  The workload is rendered once more with *tuned,
  * so lo_rgb / hi_rgb ([ncells][H][W][3], device memory) hold its bounds, and stats (may
  * be NULL) that render's statistics.  Results with any chunk enclose the same set; with
  * the tuned chunk they are those of ar_render_batch(..., tuned, ...) bit for bit.

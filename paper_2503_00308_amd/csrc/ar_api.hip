@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -1630,6 +1631,40 @@ int ar_autotune(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_
   }
   *tuned = base;
   tuned->chunk = best;
+  // cells per launch, for a batch: the automatic count (what fits the memory budget at the
+  // density just measured) and fractions of it, by wall time (the launches' host
+  // synchronisations count); a count is never above the automatic one
+  if (ncells > 1 && base.cells_per_launch <= 0) {
+    ar::Params prm{};
+    rc = ar::make_params(scene, intr, tuned, prm);
+    if (rc) return rc;
+    int P = 0;
+    rc = ar::render_vars(scene, &cells[0], &rot, &P);
+    if (rc) return rc;
+    const int automatic =
+        std::min(ncells, ar::batch_cells(scene, const_cast<ar_scene *>(scene)->ws, prm, P, rot, nullptr));
+    std::vector<int> cpl = {0};
+    for (int c : {automatic / 2, automatic / 4, 16, 8})
+      if (c >= 1 && c < automatic && std::find(cpl.begin(), cpl.end(), c) == cpl.end()) cpl.push_back(c);
+    int best_c = 0;
+    double best_t = 1e300;
+    for (int c : cpl) {
+      ar_options o = *tuned;
+      o.cells_per_launch = c;
+      double t = 1e300;
+      for (int r = 0; r < reps; ++r) {
+        const auto t0 = std::chrono::steady_clock::now();
+        rc = ar_render_batch(scene, intr, cells, ncells, &o, lo_rgb, hi_rgb, hip_stream, nullptr);
+        if (rc) return rc;
+        t = std::min(t, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+      }
+      if (t < best_t) {
+        best_t = t;
+        best_c = c;
+      }
+    }
+    tuned->cells_per_launch = best_c;
+  }
   return ar_render_batch(scene, intr, cells, ncells, tuned, lo_rgb, hi_rgb, hip_stream, stats);
 }
 

@@ -163,8 +163,13 @@ def test_autotune_segment_length():
     cells = synth.orbit_cells(6, 10.0, seed=3)
     sc = api.Scene(scene)
     tuned, lo, hi, st = api.autotune(sc, intr, cells, reps=1)
-    print("rotation tuned", tuned["chunk"], flush=True)
+    print("rotation tuned", tuned["chunk"], "cells per launch", tuned["cells_per_launch"], flush=True)
     assert tuned["chunk"] in (32, 48, 64, 96, 128)
+    assert 0 <= tuned["cells_per_launch"] <= len(cells)
     l3, h3, _ = _batch(api, sc, intr, cells, tuned)
     assert np.array_equal(lo.cpu().numpy(), l3) and np.array_equal(hi.cpu().numpy(), h3)
+    # every cells-per-launch count gives the same images (rotation cells: bit for bit)
+    for cpl in (1, 2, 4):
+        l4, h4, _ = _batch(api, sc, intr, cells, dict(tuned, cells_per_launch=cpl))
+        assert np.array_equal(l3, l4) and np.array_equal(h3, h4), cpl
     sc.close()
