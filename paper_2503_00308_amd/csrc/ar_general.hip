@@ -493,8 +493,40 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
         ++nmay;
       }
     }
-    // long windows: the whole wave on one entry at a time (all values wave-uniform)
-    unsigned long long todo = __ballot(have && wide);
+    // long windows, emitted from their stored masks: each lane turns its own entry's mask
+    // words into runs with bit operations (the runs wave_runs would write, at the same
+    // places: starts and ends in order, the open run [0, ps) and a run reaching qe), which
+    // takes a few instructions per 64 positions instead of a wave-wide pass per entry
+    if (EMIT && masks && have && wide) {
+      const unsigned long long *mk = masks + woff[p];
+      uint32_t sd = 0, ed = 0, sm = 0, em = 0;
+      bool cd = ps > 0, cm = ps > 0;
+      if (ps > 0) {
+        out_def[0] = 0u;
+        out_may[0] = 0u;
+        sd = sm = 1;
+      }
+      for (int t = ps, c = 0; t < qe; t += 64, ++c) {
+        const int nv = min(64, qe - t);
+        const unsigned long long V = nv == 64 ? ~0ull : ((1ull << nv) - 1ull);
+        const unsigned long long D = mk[2 * (size_t)c], M = mk[2 * (size_t)c + 1];
+        const unsigned long long Dp = (D << 1) | (cd ? 1ull : 0ull), Mp = (M << 1) | (cm ? 1ull : 0ull);
+        unsigned long long sD = D & ~Dp, eD = ~D & Dp & V, sM = M & ~Mp, eM = ~M & Mp & V;
+        for (; sD; sD &= sD - 1ull) out_def[2 * sd++] = (uint32_t)(t + __builtin_ctzll(sD));
+        for (; eD; eD &= eD - 1ull) out_def[2 * ed++ + 1] = (uint32_t)(t + __builtin_ctzll(eD));
+        for (; sM; sM &= sM - 1ull) out_may[2 * sm++] = (uint32_t)(t + __builtin_ctzll(sM));
+        for (; eM; eM &= eM - 1ull) out_may[2 * em++ + 1] = (uint32_t)(t + __builtin_ctzll(eM));
+        cd = (D >> (nv - 1)) & 1ull;
+        cm = (M >> (nv - 1)) & 1ull;
+      }
+      if (cd) out_def[2 * ed++ + 1] = (uint32_t)qe;
+      if (cm) out_may[2 * em++ + 1] = (uint32_t)qe;
+      ndef = ed;
+      nmay = em;
+    }
+    // long windows otherwise: the whole wave on one entry at a time (all values
+    // wave-uniform)
+    unsigned long long todo = __ballot(have && wide && !(EMIT && masks));
     while (todo) {
       const int k = __builtin_ctzll(todo);
       todo &= todo - 1ull;
