@@ -232,7 +232,7 @@ def batched_measure(api, synth, runs=2, per_query_cells=32, autotune=True):
     flops = alg_flops_per_pair(st["P"]) * st["pairs"]
     achieved = flops / (st["raster_ms"] * 1e-3) / 1e12
     return {"workload": desc, "cells": n, "segment_length": st["segment_length"], "autotuned": autotune,
-            "tuned": ("segment length and cells per launch (tile 8x8 fixed)" if autotune else "none"),
+            "tuned": ("segment length and cells per launch (rotation cells: 8x8 tiles)" if autotune else "none"),
             "cells_per_launch": (int(opts["cells_per_launch"]) if opts else 0),
             "graph": {"ms": t_graph * 1e3, "device_ms": gst["total_ms"], "pairs_per_s": gst["pairs"] / t_graph,
                       "replans": replans, "speedup_vs_per_query": t_single * n / t_graph,
@@ -471,7 +471,8 @@ def main():
     ap.add_argument("--no-workload3", action="store_true", help="skip the 100k-Gaussian six-axis query")
     ap.add_argument("--workload3-only", action="store_true",
                     help="only render the 100k-Gaussian six-axis query (warm-up and three timed) and exit")
-    ap.add_argument("--no-autotune", action="store_true", help="batched workload: automatic segment length")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="no autotuning (headline tile report; batched workload: automatic segment length)")
     ap.add_argument("--refined", action="store_true",
                     help="also an orbit box refined where MatrixInv fails (left out of the default run, as "
                          "--partitioned)")
@@ -560,6 +561,14 @@ def main():
                      "flops_per_pair": alg_flops_per_pair(P), "traffic": traffic},
     }
     log(f"headline workload done: {value:.4g} pairs/s")
+    if not args.no_autotune:
+        # the binning tile and segment length the autotuner picks for this workload (the
+        # timed loop above keeps the automatic rule: 8x8 tiles, measured segment length)
+        tuned, _, _, tst = api.autotune(sc, intr, box, reps=3)
+        out["headline_autotune"] = {"tile": tuned["tile"], "segment_length": tuned["chunk"],
+                                    "device_ms": tst["total_ms"], "candidates": "tiles 8 and 16, each with "
+                                    "its automatic segment length times 1/2, 3/4, 1, 5/4, 3/2"}
+        log(f"headline autotune: tile {tuned['tile']}, segment length {tuned['chunk']}")
     if args.partitioned:
         out["partitioned"] = partitioned_measure(api, sc, intr, box)
     sc.close()

@@ -113,7 +113,12 @@ typedef struct {
 
 /*
  * Options; a zero field takes the default.
- *   tile        pixel tile side of the binning and of one workgroup, 8 (only value)
+ *   tile        pixel side of the binning tiles: 8 (default; one 64-lane wave per tile)
+ *               or 16 (translation boxes only: a tile's list serves its four 8x8 blocks,
+ *               one wave each; fewer list entries to sort, every entry walked four
+ *               times).  The bounds enclose the same set with either (rounding aside,
+ *               they agree to a few units of the last place); rotation boxes with 16 are
+ *               rejected (AR_E_UNSUPPORTED), other values too
  *   ind_window  rotation boxes: which pairs of a tile list get the pairwise Ind test;
  *               0 = those inside the smaller of the two depth windows (default),
  *               1 = inside the window from the box of the list's means only,
@@ -409,20 +414,22 @@ int ar_render_refined(const ar_scene *scene, const ar_intrinsics *intr, const ar
                       void *hip_stream, ar_pose_box *cells_out, int32_t *ncells_out, ar_stats *stats);
 
 /*
- * Autotuning of the pixel loop's segment length (options.chunk) and, for a batch, of the
- * cells per launch (options.cells_per_launch) for a workload: one pose box (ncells = 1)
- * or a batch of cells, rendered as ar_render_batch.  The workload is rendered with the
- * automatic length, then with candidates (translation boxes: the automatic length times
- * 1/2, 3/4, 5/4 and 3/2, multiples of 8 in [8, 4096]; rotation boxes: 32, 48, 64, 96
- * and 128), reps times each (1..16); the chunk is the candidate with the least device
- * time (stats.total_ms).  With ncells > 1 and no cells_per_launch in *opts, the counts
+ * Autotuning of the binning tile (options.tile), the pixel loop's segment length
+ * (options.chunk) and, for a batch, the cells per launch (options.cells_per_launch) for
+ * a workload: one pose box (ncells = 1) or a batch of cells, rendered as
+ * ar_render_batch.  Per tile (translation boxes: 8 and 16 unless *opts fixes one;
+ * rotation boxes: 8) the workload is rendered with the automatic length, then with
+ * candidates (translation boxes: the automatic length times 1/2, 3/4, 5/4 and 3/2,
+ * multiples of 8 in [8, 4096]; rotation boxes: 32, 48, 64, 96 and 128), reps times each
+ * (1..16); tile and chunk are the pair with the least device time (stats.total_ms).
+ * With ncells > 1 and no cells_per_launch in *opts, the counts
  * automatic (what fits the memory budget), half and a quarter of it, 16 and 8 (those
  * below the automatic count) are then timed by wall clock with that chunk.  *tuned
- * receives a copy of *opts (or of the defaults when opts is NULL) with the chosen chunk
- * and cells per launch (0: the automatic count).  The workload is rendered once more with *tuned,
+ * receives a copy of *opts (or of the defaults when opts is NULL) with the chosen tile,
+ * chunk and cells per launch (0: the automatic count).  The workload is rendered once more with *tuned,
  * so lo_rgb / hi_rgb ([ncells][H][W][3], device memory) hold its bounds, and stats (may
- * be NULL) that render's statistics.  Results with any chunk enclose the same set; with
- * the tuned chunk they are those of ar_render_batch(..., tuned, ...) bit for bit.
+ * be NULL) that render's statistics.  Results with any tile and chunk enclose the same
+ * set; with the tuned ones they are those of ar_render_batch(..., tuned, ...) bit for bit.
  * Returns AR_OK or an error code as ar_render_batch (ar_last_error).
  */
 int ar_autotune(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_box *cells, int32_t ncells,

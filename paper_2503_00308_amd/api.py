@@ -470,9 +470,10 @@ def options_dict(o: Options) -> dict:
 
 
 def autotune(scene: Scene, intr, cells, opts=None, reps: int = 2, stream=None):
-    """Segment length of the pixel loop tuned on a workload (a pose box or a list of
-    cells, as render_batch); returns the tuned options (a dict for render_bounds /
-    render_batch), the bounds rendered with them and their stats."""
+    """Binning tile, segment length of the pixel loop and cells per launch tuned on a
+    workload (a pose box or a list of cells, as render_batch); returns the tuned options
+    (a dict for render_bounds / render_batch), the bounds rendered with them and their
+    stats."""
     import torch
     lib = load()
     if isinstance(cells, dict):

@@ -110,7 +110,8 @@ int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *o
     return fail(AR_E_INVALID, "intrinsics must be finite with fx, fy > 0");
   ar_options o{};
   if (op) o = *op;
-  if (o.tile != 0 && o.tile != kTile) return fail(AR_E_UNSUPPORTED, "tile %d: only %d is built", o.tile, kTile);
+  if (o.tile != 0 && o.tile != kTile && o.tile != kTileMax)
+    return fail(AR_E_UNSUPPORTED, "tile %d: only %d and %d are built", o.tile, kTile, kTileMax);
   if (o.ind_window < 0 || o.ind_window > 2) return fail(AR_E_INVALID, "ind_window %d outside [0, 2]", o.ind_window);
   if (o.prefix_entries < 0) return fail(AR_E_INVALID, "prefix_entries %d is negative", o.prefix_entries);
   if (o.cells_per_launch < 0 || o.cells_per_launch > 256)
@@ -138,8 +139,9 @@ int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *o
   prm.eps_cull = budget / (double)sc->dev.n;
   prm.E = budget * (1.0 + 0x1p-10);
   prm.t_min = o.t_min == 0.0 ? 1e-7 : o.t_min;  // negative disables the early stop
-  prm.ntx = (in->width + kTile - 1) / kTile;
-  prm.nty = (in->height + kTile - 1) / kTile;
+  prm.tile = o.tile ? o.tile : kTile;
+  prm.ntx = (in->width + prm.tile - 1) / prm.tile;
+  prm.nty = (in->height + prm.tile - 1) / prm.tile;
   prm.ind_window = o.ind_window;
   prm.chunk = o.chunk;  // 0: chosen per call from the number of (tile, Gaussian) pairs
   prm.prefix_entries = o.prefix_entries;
@@ -393,7 +395,7 @@ size_t query_bytes(const ar_scene *sc, const Params &prm, int P, bool rotates, i
     const double segs = pairs / kRotSegment + lists;
     b += 1.25 * segs * 4.0 + 1.25 * std::min(segs, (double)kRotChunkSegs) * (8.0 * part_fields(P) * 64.0 + 16.0 * 64.0);
   } else {
-    const double segs = std::min(8192.0 + lists, pairs / 32.0 + lists);
+    const double segs = tile_subs(prm) * std::min(8192.0 + lists, pairs / 32.0 + lists);
     b += 1.25 * segs * (8.0 * part_fields(P) * 64.0 + 4.0);
   }
   return (size_t)b;
@@ -722,6 +724,7 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
   const size_t n_total = (size_t)ncells * n;
   const size_t nlists = (size_t)ncells * ntiles;
   if (!rotates && P > 3) return fail(AR_E_INVALID, "more than 3 translation variables");
+  if (rotates && prm.tile != kTile) return fail(AR_E_UNSUPPORTED, "tile %d: rotation boxes use %d", prm.tile, kTile);
   if (launch_limit(n_total, 0) || nlists >= kScanMax)
     return fail(AR_E_UNSUPPORTED, "too many cells in one launch (%zu items, %zu tile lists)", n_total, nlists);
   int rc = ensure_ws(ws, n_total, nlists, P, ncells);
@@ -784,15 +787,17 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
   ws.last = LaunchSizes{};
   ws.last.entries = npairs;
   if (!rotates) {
-    const int L = segment_length(prm, npairs, nlists, P);
+    // every 8x8 block of a tile walks the tile's list
+    const size_t nsub = (size_t)tile_subs(prm);
+    const int L = segment_length(prm, npairs * nsub, nlists * nsub, P);
     if (st) st->segment_length = std::max(st->segment_length, L);
-    const size_t nseg_max = (npairs + (size_t)L - 1) / (size_t)L + nlists;
+    const size_t nseg_max = ((npairs + (size_t)L - 1) / (size_t)L + nlists) * nsub;
     ws.last.L = L;
     ws.last.segments = nseg_max;
     ws.last.groups = 1;
     rc = ensure_segments(ws, nlists, nseg_max, P);
     if (rc) return rc;
-    HIP_TRY(launch_segments(ws, (int)nlists, L, s));
+    HIP_TRY(launch_segments(ws, (int)nlists, L, s, tile_subs(prm)));
     HIP_TRY(exclusive_scan_u32(ws.seg_off, (int)nlists + 1, ws, s));
     HIP_TRY(launch_segment_map(ws, (int)nlists, s));
     HIP_TRY(launch_raster_translation(P, ws, ws.pair_val, (int)nlists, prm, L, (int)nseg_max, lo, hi, s));
@@ -906,6 +911,7 @@ int render_cells_planned(const ar_scene *sc, Workspace &ws, const Params &prm_in
   prm.nominal_order = rotates ? 1 : 0;
   prm.pose_vars = P - sc->dev.nvar;
   if (sc->dev.moving) prm.ind_window = 2;
+  if (rotates && prm.tile != kTile) return fail(AR_E_UNSUPPORTED, "tile %d: rotation boxes use %d", prm.tile, kTile);
   const int n = sc->dev.n;
   const int ntiles = prm.ntx * prm.nty;
   const size_t n_total = (size_t)ncells * n;
@@ -951,7 +957,7 @@ int render_cells_planned(const ar_scene *sc, Workspace &ws, const Params &prm_in
   }
   HIP_TRY(launch_tile_ranges(ws.pair_key, (int)cap, ws.tile_range, (int)nlists, s));
   const int L = caps.L;
-  HIP_TRY(launch_segments(ws, (int)nlists, L, s));
+  HIP_TRY(launch_segments(ws, (int)nlists, L, s, tile_subs(prm)));
   HIP_TRY(exclusive_scan_u32(ws.seg_off, (int)nlists + 1, ws, s));
   if (!rotates) {
     HIP_TRY(launch_segment_map(ws, (int)nlists, s, caps.segments));
@@ -1597,39 +1603,50 @@ int ar_autotune(const ar_scene *scene, const ar_intrinsics *intr, const ar_pose_
     if (rc) return rc;
     rot = rot || r;
   }
-  // the automatic length first
-  base.chunk = 0;
-  ar_stats st{};
-  int rc = ar_render_batch(scene, intr, cells, ncells, &base, lo_rgb, hi_rgb, hip_stream, &st);
-  if (rc) return rc;
-  const int L0 = std::max(8, (int)st.segment_length);
-  std::vector<int> cand;
-  if (rot) {
-    cand = {32, 48, 64, 96, 128};
-  } else {
-    for (int num : {2, 3, 4, 5, 6}) {
-      const int L = std::min(4096, std::max(8, (L0 * num / 4 + 7) / 8 * 8));
-      if (std::find(cand.begin(), cand.end(), L) == cand.end()) cand.push_back(L);
-    }
-  }
-  int best = cand[0];
+  // translation boxes: both binning tiles unless the options fix one; per tile the
+  // automatic length first, then candidates around it (rotation boxes: 8x8 tiles and
+  // 32-128 positions)
+  std::vector<int> tiles;
+  if (rot || base.tile != 0) tiles.push_back(base.tile);
+  else tiles = {ar::kTile, ar::kTileMax};
+  int best = 0, best_tile = tiles[0];
   double best_ms = 1e300;
-  for (int L : cand) {
+  for (int tile : tiles) {
     ar_options o = base;
-    o.chunk = L;
-    double t = 1e300;
-    for (int r = 0; r < reps; ++r) {
-      ar_stats s1{};
-      rc = ar_render_batch(scene, intr, cells, ncells, &o, lo_rgb, hi_rgb, hip_stream, &s1);
-      if (rc) return rc;
-      t = std::min(t, s1.total_ms);
+    o.tile = tile;
+    o.chunk = 0;
+    ar_stats st{};
+    int rc = ar_render_batch(scene, intr, cells, ncells, &o, lo_rgb, hi_rgb, hip_stream, &st);
+    if (rc) return rc;
+    const int L0 = std::max(8, (int)st.segment_length);
+    std::vector<int> cand;
+    if (rot) {
+      cand = {32, 48, 64, 96, 128};
+    } else {
+      for (int num : {2, 3, 4, 5, 6}) {
+        const int L = std::min(4096, std::max(8, (L0 * num / 4 + 7) / 8 * 8));
+        if (std::find(cand.begin(), cand.end(), L) == cand.end()) cand.push_back(L);
+      }
     }
-    if (t < best_ms) {
-      best_ms = t;
-      best = L;
+    for (int L : cand) {
+      o.chunk = L;
+      double t = 1e300;
+      for (int r = 0; r < reps; ++r) {
+        ar_stats s1{};
+        rc = ar_render_batch(scene, intr, cells, ncells, &o, lo_rgb, hi_rgb, hip_stream, &s1);
+        if (rc) return rc;
+        t = std::min(t, s1.total_ms);
+      }
+      if (t < best_ms) {
+        best_ms = t;
+        best = L;
+        best_tile = tile;
+      }
     }
   }
+  int rc = AR_OK;
   *tuned = base;
+  tuned->tile = best_tile;
   tuned->chunk = best;
   // cells per launch, for a batch: the automatic count (what fits the memory budget at the
   // density just measured) and fractions of it, by wall time (the launches' host

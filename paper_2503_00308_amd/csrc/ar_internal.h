@@ -19,8 +19,10 @@ namespace ar {
 constexpr int kMaxP = 6;        // pose variables: 3 translations + 3 angles
 constexpr int kOverflow = 15;   // statistics counter set when a planned launch outgrows a buffer
 constexpr int kIndBorder = 10;  // statistics counter of Ind tests decided within rounding of a threshold
-constexpr int kTile = 8;        // pixel tile side (one 64-lane wave covers a tile)
+constexpr int kTile = 8;        // pixel side of the block one 64-lane wave covers (a tile, or a
+                                // quarter of a 16x16 binning tile on the translation path)
 constexpr int kTilePix = kTile * kTile;
+constexpr int kTileMax = 16;    // largest binning tile side
 constexpr int kListBox = 13;   // per tile list: box of the means, box of their parts across m, max |mean|
 
 // Gaussian categories decided in the per-Gaussian stage.
@@ -100,6 +102,7 @@ struct Params {
   double eps_cull;     // cull_budget / n
   double E;            // widening for pruning
   double t_min;
+  int32_t tile;        // binning tile side in pixels: 8, or 16 (translation boxes: four waves per tile)
   int32_t ntx, nty;    // tiles
   int32_t ind_window, chunk;
   int32_t prefix_entries;   // rotation path: list entries per pixel-loop launch
@@ -115,6 +118,12 @@ struct Params {
   unsigned long long *ind_und;
   int32_t ind_only;
 };
+
+// Waves per binning tile: each covers one kTile x kTile block of it (row-major).
+__host__ __device__ inline int tile_subs(const Params &p) {
+  const int k = p.tile / kTile;
+  return k * k;
+}
 
 // A scene, or a set of scenes (Sec. 4.6): colour and opacity intervals per Gaussian,
 // means moved along a direction by scene variables s_v in [s_mid - s_rad, s_mid + s_rad].
@@ -313,7 +322,7 @@ hipError_t launch_tile_ranges(const uint32_t *keys, int npairs, uint32_t *ranges
 int part_fields(int P);
 // waves of the translation pixel kernel the device holds at once
 int seg_resident_waves(int P);
-hipError_t launch_segments(const Workspace &ws, int nlists, int L, hipStream_t s);
+hipError_t launch_segments(const Workspace &ws, int nlists, int L, hipStream_t s, int nsub = 1);
 hipError_t launch_segment_map(const Workspace &ws, int nlists, hipStream_t s, uint32_t cap = 0);
 // records ev[1] / ev[2] around the per-segment pixel kernel; lists cell * ntiles + tile,
 // images [cell][H][W][3]

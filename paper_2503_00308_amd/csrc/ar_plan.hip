@@ -106,10 +106,11 @@ static int plan_size_once(ar_plan *p, hipStream_t s) {
   p->caps.entries = (uint32_t)e;
   p->caps.runs = (uint32_t)r;
   p->caps.L = p->prm.chunk > 0 ? p->prm.chunk : L;
-  // segments: every list of L-position segments fits entries / L + lists, so with the
-  // entries within their room the segments cannot outgrow theirs
+  // segments: every list of L-position segments fits entries / L + lists (times the 8x8
+  // blocks per tile), so with the entries within their room the segments cannot outgrow
+  // theirs
   const uint64_t nlists = (uint64_t)p->per_launch * p->prm.ntx * p->prm.nty;
-  const uint64_t sg_bound = e / (uint64_t)std::max(p->caps.L, 1) + nlists + 1;
+  const uint64_t sg_bound = (e / (uint64_t)std::max(p->caps.L, 1) + nlists + 1) * (uint64_t)tile_subs(p->prm);
   if (std::max(sg, sg_bound) > 0xFFFFFFF0ull)
     return fail(AR_E_UNSUPPORTED, "a planned launch outgrows the 32-bit segment count; use fewer cells per launch");
   p->caps.segments = (uint32_t)std::max(sg, sg_bound);

@@ -605,7 +605,7 @@ __device__ __forceinline__ void project_one(const SceneDev &sc, const PoseForms 
     } else {
       const int ic0 = (int)fmax(c0, 0.0), ic1 = (int)fmin(c1, (double)(prm.width - 1));
       const int ir0 = (int)fmax(r0, 0.0), ir1 = (int)fmin(r1, (double)(prm.height - 1));
-      rc[0] = ic0 / kTile; rc[1] = ir0 / kTile; rc[2] = ic1 / kTile; rc[3] = ir1 / kTile;
+      rc[0] = ic0 / prm.tile; rc[1] = ir0 / prm.tile; rc[2] = ic1 / prm.tile; rc[3] = ir1 / prm.tile;
     }
   }
 }

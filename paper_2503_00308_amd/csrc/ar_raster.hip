@@ -39,8 +39,8 @@ namespace ar {
 // binning
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ float tile_dist2(const float *mu, int tx, int ty, const Params &prm) {
-  const int x0 = tx * kTile, y0 = ty * kTile;
-  const int x1 = min(x0 + kTile, prm.width) - 1, y1 = min(y0 + kTile, prm.height) - 1;
+  const int x0 = tx * prm.tile, y0 = ty * prm.tile;
+  const int x1 = min(x0 + prm.tile, prm.width) - 1, y1 = min(y0 + prm.tile, prm.height) - 1;
   const float ux0 = (float)((double)x0 + 0.5 - prm.cx), ux1 = (float)((double)x1 + 0.5 - prm.cx);
   const float uy0 = (float)((double)y0 + 0.5 - prm.cy), uy1 = (float)((double)y1 + 0.5 - prm.cy);
   return dist2_rect(mu, ux0, ux1, uy0, uy1);
@@ -239,12 +239,14 @@ __device__ __forceinline__ int cut_at(const uint32_t *__restrict__ list, const u
 
 int part_fields(int P) { return 6 * (P + 1) + 8; }
 
-// Segments: tile t's list is cut into ceil(n_t / L) pieces of L positions.
-__global__ void k_seg_count(const uint32_t *__restrict__ ranges, int ntiles, int L, uint32_t *__restrict__ seg_off) {
+// Segments: tile t's list is cut into ceil(n_t / L) pieces of L positions, once for each
+// of the tile's nsub wave blocks (block-major: block b's pieces follow block b - 1's).
+__global__ void k_seg_count(const uint32_t *__restrict__ ranges, int ntiles, int L, int nsub,
+                            uint32_t *__restrict__ seg_off) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < ntiles) {
     const uint32_t n = ranges[2 * t + 1] - ranges[2 * t];
-    seg_off[t] = (n + (uint32_t)L - 1u) / (uint32_t)L;
+    seg_off[t] = (n + (uint32_t)L - 1u) / (uint32_t)L * (uint32_t)nsub;
   } else if (t == ntiles) {
     seg_off[t] = 0u;
   }
@@ -262,9 +264,12 @@ __global__ void k_seg_map(const uint32_t *__restrict__ seg_off, int ntiles, uint
   for (uint32_t s = seg_off[t]; s < e; ++s) seg_tile[s] = (uint32_t)t;
 }
 
-// One wave per segment, one lane per pixel of the segment's 8x8 tile.  The segment's
-// cut points are moved to the next depth change, so a group of equal depths is never
-// split.  Transmittances start at 1; the merge scales by the product in front.
+// One wave per segment, one lane per pixel of the segment's 8x8 block: the whole tile,
+// or with 16x16 tiles the block the segment belongs to (the four blocks of a tile walk
+// the same list, each with its own pixels; the per-pixel pruning test drops the entries
+// that miss a block).  The segment's cut points are moved to the next depth change, so a
+// group of equal depths is never split.  Transmittances start at 1; the merge scales by
+// the product in front.
 template <int P>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_raster_seg(const double *__restrict__ recs, const uint64_t *__restrict__ keys,
                                                     const uint32_t *__restrict__ ranges,
@@ -280,10 +285,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int s = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   if (s >= (int)seg_off[nlists]) return;
   const int list = (int)seg_tile[s];           // cell * ntiles + tile
-  const int i = s - (int)seg_off[list];
+  const int nsub = tile_subs(prm), side = prm.tile / kTile;
+  const int s0 = (int)seg_off[list];
+  const int nch = ((int)seg_off[list + 1] - s0) / nsub;   // pieces per block
+  const int sub = (s - s0) / nch, i = s - s0 - sub * nch;
   const int tile = list % ntiles;
   const int tx = tile % prm.ntx, ty = tile / prm.ntx;
-  const int col = tx * kTile + (lane & 7), row = ty * kTile + (lane >> 3);
+  const int col = tx * prm.tile + (sub % side) * kTile + (lane & 7);
+  const int row = ty * prm.tile + (sub / side) * kTile + (lane >> 3);
   const bool inimg = col < prm.width && row < prm.height;
   const double uxd = (double)col + 0.5 - prm.cx, uyd = (double)row + 0.5 - prm.cy;
   const float ux = (float)uxd, uy = (float)uyd;
@@ -291,7 +300,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int n = (int)ranges[2 * list + 1] - beg;
   const uint32_t *items = lists + beg;
   const int p0 = cut_at(items, keys, n, i * L);
-  const int p1 = cut_at(items, keys, n, (i + 1) * L);
+  // a block wholly outside the image (right or bottom edge of a 16x16 tile) walks nothing
+  const int p1 = __any(inimg) ? cut_at(items, keys, n, (i + 1) * L) : p0;
 
   Acc<P> acc;
   acc_zero<P>(acc);
@@ -401,7 +411,7 @@ struct MergeAcc {
   }
 };
 
-// One workgroup per tile: kMergeWaves waves per colour channel, each composing a
+// One workgroup per 8x8 block of a tile: kMergeWaves waves per colour channel, each composing a
 // contiguous quarter of the tile's segments (loads of four segments issued together),
 // then wave 0 of the channel composes the quarters in order and writes the pixel bounds.
 template <int P>
@@ -418,12 +428,16 @@ __global__ __launch_bounds__(192 * kMergeWaves) void k_merge(const uint32_t *__r
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int c = wid / kMergeWaves, w = wid % kMergeWaves;   // colour channel, quarter
   const int ntiles = prm.ntx * prm.nty;
-  const int list = (int)blockIdx.x;            // cell * ntiles + tile
+  const int nsub = tile_subs(prm), side = prm.tile / kTile;
+  const int list = (int)blockIdx.x / nsub;     // cell * ntiles + tile
+  const int sub = (int)blockIdx.x - list * nsub;
   const int cell = list / ntiles, tile = list % ntiles;
   const int tx = tile % prm.ntx, ty = tile / prm.ntx;
-  const int col = tx * kTile + (lane & 7), row = ty * kTile + (lane >> 3);
+  const int col = tx * prm.tile + (sub % side) * kTile + (lane & 7);
+  const int row = ty * prm.tile + (sub / side) * kTile + (lane >> 3);
   const bool inimg = col < prm.width && row < prm.height;
-  const int s0 = (int)seg_off[list], s1 = (int)seg_off[list + 1];
+  const int nch = ((int)seg_off[list + 1] - (int)seg_off[list]) / nsub;
+  const int s0 = (int)seg_off[list] + sub * nch, s1 = s0 + nch;
   const int per = (s1 - s0 + kMergeWaves - 1) / kMergeWaves;
   const int a0 = min(s1, s0 + w * per), a1 = min(s1, a0 + per);
   M m;
@@ -475,13 +489,13 @@ static hipError_t launch_trans_p(const Workspace &ws, const uint32_t *lists, int
     hipLaunchKernelGGL(k_raster_seg<P>, dim3((nseg_max + 3) / 4), dim3(256), 0, s, ws.rec, ws.key, ws.tile_range,
                        lists, ws.seg_off, ws.seg_tile, L, nlists, prm, ws.part);
   if (ws.ev[2]) HIP_RET(hipEventRecord(ws.ev[2], s));
-  hipLaunchKernelGGL(k_merge<P>, dim3(nlists), dim3(192 * kMergeWaves), 0, s, ws.tile_range, ws.seg_off, ws.part, prm,
-                     lo, hi, ws.counters);
+  hipLaunchKernelGGL(k_merge<P>, dim3(nlists * tile_subs(prm)), dim3(192 * kMergeWaves), 0, s, ws.tile_range,
+                     ws.seg_off, ws.part, prm, lo, hi, ws.counters);
   return hipGetLastError();
 }
 
-hipError_t launch_segments(const Workspace &ws, int nlists, int L, hipStream_t s) {
-  hipLaunchKernelGGL(k_seg_count, dim3((nlists + 1 + 255) / 256), dim3(256), 0, s, ws.tile_range, nlists, L,
+hipError_t launch_segments(const Workspace &ws, int nlists, int L, hipStream_t s, int nsub) {
+  hipLaunchKernelGGL(k_seg_count, dim3((nlists + 1 + 255) / 256), dim3(256), 0, s, ws.tile_range, nlists, L, nsub,
                      ws.seg_off);
   return hipGetLastError();
 }
