@@ -165,6 +165,11 @@ typedef struct {
  *               exceed it is cut into smaller groups of whole lists and done again; only a
  *               single list with more runs is rejected (AR_E_UNSUPPORTED).  The result does
  *               not depend on it (bit for bit).
+ *   ind_quick   rotation boxes: each Ind test first tries the identity bound's constant
+ *               against a per-axis bound of all its other terms (3 + 3 multiply-adds),
+ *               which decides most pairs of a window; where it decides, the full bound
+ *               decides the same way (0 = automatic and 1: on; 2: off, every test takes
+ *               the full bound).  Speed only, never the result (bit for bit)
  *   inverse     the covariance inverse of Step 3 (Conic): 0 = MatrixInv (Sec. 3.1) with
  *               its linear bounds propagated forward (default); 1 = MatrixInv with its
  *               bounds propagated backward (CROWN-style, as the paper's bound engine;
@@ -190,6 +195,7 @@ typedef struct {
   int32_t group_entries;
   int32_t inverse;
   int32_t group_runs;
+  int32_t ind_quick;
 } ar_options;
 
 /* Statistics of one call (filled when the call returns). */

@@ -61,7 +61,8 @@ class Options(ctypes.Structure):
                 ("z_near", ctypes.c_double), ("t_min", ctypes.c_double),
                 ("cells_per_launch", ctypes.c_int32), ("prefix_entries", ctypes.c_int32),
                 ("abs_sums", ctypes.c_int32), ("ind_copy", ctypes.c_int32), ("ind_masks", ctypes.c_int32),
-                ("group_entries", ctypes.c_int32), ("inverse", ctypes.c_int32), ("group_runs", ctypes.c_int32)]
+                ("group_entries", ctypes.c_int32), ("inverse", ctypes.c_int32), ("group_runs", ctypes.c_int32),
+                ("ind_quick", ctypes.c_int32)]
 
 
 # ar_options.inverse: the covariance inverse of Step 3
@@ -200,7 +201,8 @@ def options(d=None) -> Options:
                    int(d.get("cells_per_launch", 0)), int(d.get("prefix_entries", 0)),
                    int(d.get("abs_sums", 0)), int(d.get("ind_copy", 0)), int(d.get("ind_masks", 0)),
                    int(d.get("group_entries", 0)),
-                   INVERSE.get(d.get("inverse", 0), d.get("inverse", 0)), int(d.get("group_runs", 0)))
+                   INVERSE.get(d.get("inverse", 0), d.get("inverse", 0)), int(d.get("group_runs", 0)),
+                   int(d.get("ind_quick", 0)))
 
 
 class Scene:

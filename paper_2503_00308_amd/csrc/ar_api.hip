@@ -127,6 +127,7 @@ int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *o
   if (o.group_entries < 0) return fail(AR_E_INVALID, "group_entries %d is negative", o.group_entries);
   if (o.inverse < 0 || o.inverse > 2) return fail(AR_E_INVALID, "inverse %d outside [0, 2]", o.inverse);
   if (o.group_runs < 0) return fail(AR_E_INVALID, "group_runs %d is negative", o.group_runs);
+  if (o.ind_quick < 0 || o.ind_quick > 2) return fail(AR_E_INVALID, "ind_quick %d outside [0, 2]", o.ind_quick);
   prm.width = in->width;
   prm.height = in->height;
   prm.fx = in->fx;
@@ -150,6 +151,7 @@ int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *o
   prm.ind_masks = o.ind_masks;
   prm.group_entries = o.group_entries;
   prm.inverse = o.inverse;
+  prm.ind_quick = o.ind_quick;
   prm.group_runs = o.group_runs;
   return AR_OK;
 }
@@ -734,8 +736,10 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ws.counters, 16);
   HIP_TRY(hipGetLastError());
   // pose forms on the host; by value for a single translation box, else in device memory
-  for (int c = 0; c < ncells; ++c)
+  for (int c = 0; c < ncells; ++c) {
     if (pose_forms_host(boxes[c], P, ws.pose_host[c])) return fail(AR_E_INVALID, "unsupported pose variables %d", P);
+    if (prm.ind_quick == 2) ind_quick_off(ws.pose_host[c]);
+  }
   const bool by_value = ncells == 1 && !rotates;
   if (!by_value)
     HIP_TRY(hipMemcpyAsync(ws.pose_dev, ws.pose_host, (size_t)ncells * sizeof(PoseForms), hipMemcpyHostToDevice, s));

@@ -129,6 +129,30 @@ __global__ __launch_bounds__(256) void k_list_box(const uint32_t *__restrict__ r
 template <int P, int S = kMaxP + 1, bool BORDER = false>
 __device__ __forceinline__ int ind_pair(const PoseForms &pose, const double *uwi, const double *uwj,
                                         const double *dfi, const double *dfj, bool *border = nullptr) {
+  // Quick test first.  With D = uw_i - uw_j (as rounded) the identity bound below has
+  // lower end >= q - sum_l |D_l| R_l and upper end <= q + sum_l |D_l| R_l, q = sum_l D_l
+  // Zm[l][kMaxP] its constant and R_l = |Zr[l][kMaxP]| + sum_k (|Zm[l][k]| + |Zr[l][k]|)
+  // (triangle inequality on each coefficient).  Zq_l exceeds R_l by 2^-45 (|Zm[l][kMaxP]|
+  // + R_l), more than the rounding of both computations (< 32 u (sum_l |D_l| (|Zm[l][kMaxP]|
+  // + R_l))), so a quick decision beyond the borderline band is the identity's own
+  // decision, with the same borderline flag (false); the result does not change.
+  double qc = 0.0, qr = 0.0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const double d = uwi[l] - uwj[l];
+    qc = fma(d, pose.Zm[l][kMaxP], qc);
+    qr = fma(fabs(d), pose.Zq[l], qr);
+  }
+  const double qt = BORDER ? 1e-12 * (1.0 + fabs(uwi[0] - uwj[0]) + fabs(uwi[1] - uwj[1]) + fabs(uwi[2] - uwj[2]))
+                           : 0.0;
+  if (qc - qr > qt) {
+    if (BORDER) *border = false;
+    return 1;
+  }
+  if (qc + qr < -qt) {
+    if (BORDER) *border = false;
+    return 0;
+  }
   // identity bound: sum_l A_z,l * (uw_i - uw_j)_l, each term a scaled form; with A_z,l
   // in mid-radius form (m, r), c A_z,l has lower form c m - |c| r and upper c m + |c| r
   double mid[P + 1], rad[P + 1];

@@ -92,6 +92,9 @@ struct PoseForms {
   double tau[3][2][kMaxP + 1];
   double beta[3][2][kMaxP + 1];
   double Zm[3][kMaxP + 1], Zr[3][kMaxP + 1];   // depth row of A in mid-radius form (Ind tests)
+  // per l, above |Zr[l][kMaxP]| + sum_k (|Zm[l][k]| + |Zr[l][k]|) by 2^-46 of itself
+  // plus |Zm[l][kMaxP]| (the quick test of an Ind pair)
+  double Zq[3];
 };
 
 struct Params {
@@ -112,12 +115,16 @@ struct Params {
   int32_t inverse;          // conic: 0 MatrixInv (forward), 1 MatrixInv bounded backward, 2 adjugate
   int32_t pose_vars;        // pose variables; scene variables follow them in the forms
   int32_t group_runs;       // rotation path: most Ind runs per list group (0: the uint32 limit)
+  int32_t ind_quick;        // rotation path: quick Ind test (0, 1 on; 2 off)
   // rotation path: per cell of the launch, the number of (list entry, list position) pairs
   // whose Ind is undecided, added here by the counting pass when not null; with ind_only
   // the render stops after that pass (no images)
   unsigned long long *ind_und;
   int32_t ind_only;
 };
+
+// The quick Ind test switched off for a cell: an infinite Zq never decides.
+inline void ind_quick_off(PoseForms &pf) { pf.Zq[0] = pf.Zq[1] = pf.Zq[2] = __builtin_inf(); }
 
 // Waves per binning tile: each covers one kTile x kTile block of it (row-major).
 __host__ __device__ inline int tile_subs(const Params &p) {

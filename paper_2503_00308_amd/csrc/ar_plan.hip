@@ -197,8 +197,10 @@ static int set_cells(ar_plan *p, const ar_pose_box *cells) {
     if (P != p->P || rot != p->rotates)
       return fail(AR_E_INVALID, "cell %d has other pose variables than the plan's cells", i);
   }
-  for (int i = 0; i < p->ncells; ++i)
+  for (int i = 0; i < p->ncells; ++i) {
     if (pose_forms_host(cells[i], p->P, p->pose_host[i])) return fail(AR_E_INVALID, "unsupported pose variables");
+    if (p->prm.ind_quick == 2) ind_quick_off(p->pose_host[i]);
+  }
   p->cells.assign(cells, cells + p->ncells);
   return AR_OK;
 }

@@ -115,11 +115,18 @@ __host__ __device__ void pose_forms(const ar_pose_box &b, PoseForms &pf) {
     store_form<P>(pf.tau[k], tau[k]);
     store_form<P>(pf.beta[k], beta[k]);
   }
-  for (int l = 0; l < 3; ++l)
+  for (int l = 0; l < 3; ++l) {
     for (int k = 0; k <= kMaxP; ++k) {
       pf.Zm[l][k] = 0.5 * (pf.A[6 + l][0][k] + pf.A[6 + l][1][k]);
       pf.Zr[l][k] = 0.5 * (pf.A[6 + l][1][k] - pf.A[6 + l][0][k]);
     }
+    // the lower and upper coefficients of a form need not be ordered, so a "radius"
+    // Zr may be negative: magnitudes throughout; the sum's rounding (< 16 u of it) is far
+    // inside the 2^-45 added
+    double R = fabs(pf.Zr[l][kMaxP]);
+    for (int k = 0; k < kMaxP; ++k) R += fabs(pf.Zm[l][k]) + fabs(pf.Zr[l][k]);
+    pf.Zq[l] = R + 0x1p-45 * (fabs(pf.Zm[l][kMaxP]) + R);
+  }
 }
 
 // ---------------------------------------------------------------------------------
