@@ -200,6 +200,24 @@ __device__ __forceinline__ int ind_pair(const PoseForms &pose, const double *uwi
   return 2;
 }
 
+// sums[key] += v for every lane of the wave (key < 0: nothing): one atomic per distinct
+// key of the wave rather than one per lane (a wave's entries mostly share their cell, and
+// per-lane atomics on one address serialise).  Called by the whole wave.
+__device__ __forceinline__ void wave_add_by_key(unsigned long long *sums, int key, unsigned long long v) {
+  bool pend = key >= 0 && v != 0ull;
+  for (;;) {
+    const unsigned long long m = __ballot(pend);
+    if (!m) break;
+    const int l0 = __builtin_ctzll(m);
+    const int k0 = __builtin_amdgcn_readlane(key, l0);
+    const bool mine = pend && key == k0;
+    unsigned long long t = mine ? v : 0ull;
+    for (int off = 32; off > 0; off >>= 1) t += (unsigned long long)__shfl_xor(t, off);
+    if ((int)(threadIdx.x & 63) == l0) atomicAdd(&sums[k0], t);
+    pend = pend && !mine;
+  }
+}
+
 __device__ __forceinline__ double readlane_d(double x, int k) {
   const unsigned long long b = __double_as_longlong(x);
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, k);
@@ -580,9 +598,9 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
     if (!EMIT && have) {
       cnt[2 * (size_t)p] = ndef;
       cnt[2 * (size_t)p + 1] = nmay;
-      // undecided pairs of the cell (counted when asked for)
-      if (ind_und && nund) atomicAdd(&ind_und[cell], (unsigned long long)nund);
     }
+    // undecided pairs of the cell (counted when asked for)
+    if (!EMIT && ind_und) wave_add_by_key(ind_und, have ? cell : -1, nund);
     if (MODE == kRunsCount) {
       // borderline decisions: one atomic per wave
       unsigned long long b = nbord;
@@ -720,8 +738,8 @@ __global__ __launch_bounds__(256) void k_runs_count_lanes(const uint32_t *__rest
     if (have) {
       cnt[2 * (size_t)p] = ndef;
       cnt[2 * (size_t)p + 1] = nmay;
-      if (ind_und && nund) atomicAdd(&ind_und[tile / (uint32_t)ntiles], (unsigned long long)nund);
     }
+    if (ind_und) wave_add_by_key(ind_und, have ? (int)(tile / (uint32_t)ntiles) : -1, nund);
     unsigned long long b = nbord;
     for (int off = 32; off > 0; off >>= 1) b += (unsigned long long)__shfl_xor(b, off);
     if (lane == 0 && b) atomicAdd(&counters[kIndBorder], b);
