@@ -345,7 +345,7 @@ def synth_intr(side):
     return synth.intrinsics(side)
 
 
-def served_measure(api, synth, nq=48, loads=(0.25, 0.5, 0.75, 0.9), slots=4, seed=0):
+def served_measure(api, synth, nq=96, loads=(0.25, 0.5, 0.75, 0.9), slots=4, seed=0):
     """Poisson arrivals at each load x the one-at-a-time capacity, and a saturation run (all
     queries at once): the server's latencies and throughput against a FIFO one-at-a-time
     queue with each query's measured solo service time (the plain per-query path)."""
@@ -389,10 +389,12 @@ def served_measure(api, synth, nq=48, loads=(0.25, 0.5, 0.75, 0.9), slots=4, see
         log(f"served: load {load}, {lam:.1f} queries per s")
         lat, wall, rep = _served_run(api, slots, handles, queries, arrival)
         out["sweep"].append({"load": load, "arrival_qps": lam, "p50_ms": float(np.percentile(lat, 50)),
+                             "p90_ms": float(np.percentile(lat, 90)),
                              "p99_ms": float(np.percentile(lat, 99)), "throughput_qps": nq / wall,
                              "peak_inflight": rep["peak_inflight"], "peak_workspace_bytes": rep["peak_bytes"],
                              "workspace_releases": rep["releases"],
                              "one_at_a_time": {"p50_ms": float(np.percentile(serial, 50)),
+                                               "p90_ms": float(np.percentile(serial, 90)),
                                                "p99_ms": float(np.percentile(serial, 99)),
                                                "throughput_qps": nq / finish[-1]}})
     log("served: saturation (all queries at once)")
@@ -425,9 +427,51 @@ def served_measure(api, synth, nq=48, loads=(0.25, 0.5, 0.75, 0.9), slots=4, see
                             "pairs": int(st["pairs"]), "tile_pairs": int(st["tile_pairs"]), "runs": int(st["runs"]),
                             "ind_tests": int(st["ind_tests"]), "raster_ms": st["raster_ms"],
                             "device_ms": st["total_ms"]}
+    out["batched_scenes"] = batched_scenes_measure(api, synth, handles)
     for h in handles:
         h.close()
     return out
+
+
+def batched_scenes_measure(api, synth, handles, per_scene=16, side=200, seed=5):
+    """Cells of the four resident scenes (10k to 750k Gaussians) interleaved in one call
+    (ar_render_batch_scenes: cells of different scenes share each launch) against one
+    batch call per scene and one call per cell; the images are the same bit for bit."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(seed)
+    intr = synth.intrinsics(side)
+    cells, owner = [], []
+    for i in range(per_scene):
+        for s in range(len(handles)):
+            dt = 0.5 * rng.uniform(0.005, 0.02, 3)
+            dr = 0.5 * np.deg2rad(rng.uniform(0.0, 0.5, 3))
+            cells.append(synth.camera6_box(dt=dt, drot=dr))
+            owner.append(s)
+    scenes = [handles[s] for s in owner]
+    api.render_batch_scenes(scenes, intr, cells)   # warm-up (workspaces)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lo, hi, st = api.render_batch_scenes(scenes, intr, cells)
+    torch.cuda.synchronize()
+    mixed = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for s in range(len(handles)):
+        api.render_batch(handles[s], intr, [c for c, o in zip(cells, owner) if o == s])
+    torch.cuda.synchronize()
+    per_scene_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for c, o in zip(cells, owner):
+        api.render_bounds(handles[o], intr, c)
+    torch.cuda.synchronize()
+    per_cell = time.perf_counter() - t0
+    log(f"batched scenes: one call {mixed * 1e3:.1f} ms, per scene {per_scene_s * 1e3:.1f} ms, "
+        f"per cell {per_cell * 1e3:.1f} ms")
+    return {"workload": f"{len(cells)} six-axis cells ({per_scene} per scene) over the 10k/100k/300k/750k-Gaussian "
+                        f"scenes interleaved, {side}x{side}",
+            "cells": len(cells), "pairs": int(st["pairs"]), "one_call_ms": mixed * 1e3,
+            "batch_per_scene_ms": per_scene_s * 1e3, "per_cell_ms": per_cell * 1e3,
+            "speedup_vs_per_cell": per_cell / mixed, "speedup_vs_batch_per_scene": per_scene_s / mixed}
 
 
 def workload3_measure(api, synth, runs=3):

@@ -315,6 +315,22 @@ int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_p
                     void *hip_stream, ar_stats *stats);
 
 /*
+ * As ar_render_batch, with a scene per cell: cell c renders scenes[c] (scenes of any
+ * sizes, repeated or not, all on the current device).  Consecutive cells with the same
+ * pose variables share one launch per stage whatever their scenes: cell c's Gaussians
+ * are its own range of the launch's items, and its images are those of
+ * ar_render_batch(scenes[c], ...) for that cell (bit for bit for rotation boxes, and for
+ * translation boxes when opts->chunk is set; the cull threshold is each scene's own).
+ * Launches are sized for the largest scene of their cells.  The call uses the
+ * workspace of scenes[0] (no call on scenes[0] may overlap it).  Sets of scenes (scene
+ * variables) render only in calls of their own: a cell of one among other scenes is
+ * rejected (AR_E_UNSUPPORTED); a NULL scene or one on another device is AR_E_INVALID.
+ */
+int ar_render_batch_scenes(const ar_scene *const *scenes, const ar_intrinsics *intr, const ar_pose_box *cells,
+                           int32_t ncells, const ar_options *opts, float *lo_rgb, float *hi_rgb,
+                           void *hip_stream, ar_stats *stats);
+
+/*
  * Planned batched renders (the batched workload as one HIP graph).  A plan holds the
  * whole launch sequence of a batch of ncells pose boxes (all with the same pose
  * variables, as in ar_render_batch) captured in a HIP graph: every count stays on the

@@ -118,6 +118,10 @@ SYMBOLS = {
     "ar_render_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
                                        ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.POINTER(Stats)]),
+    "ar_render_batch_scenes": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Intrinsics),
+                                              ctypes.POINTER(PoseBox), ctypes.c_int32, ctypes.POINTER(Options),
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.POINTER(Stats)]),
     "ar_plan_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Intrinsics), ctypes.POINTER(PoseBox),
                                       ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
@@ -379,6 +383,32 @@ def render_batch(scene: Scene, intr, cells, opts=None, stream=None, out=None):
     _check(lib.ar_render_batch(scene.handle, ctypes.byref(ci), arr, m, ctypes.byref(co),
                                ctypes.c_void_p(lo.data_ptr()), ctypes.c_void_p(hi.data_ptr()),
                                _stream_ptr(stream), ctypes.byref(st)))
+    return lo, hi, st.as_dict()
+
+
+def render_batch_scenes(scenes, intr, cells, opts=None, stream=None, out=None):
+    """Bounds for a list of pose boxes, cell c rendering scenes[c] (Scene handles, one per
+    cell): tensors (ncells, H, W, 3) and accumulated stats (ar_render_batch_scenes)."""
+    import torch
+    lib = load()
+    ci = intrinsics(intr)
+    H, W = ci.height, ci.width
+    m = len(cells)
+    if len(scenes) != m:
+        raise ValueError(f"{len(scenes)} scenes for {m} cells")
+    arr = (PoseBox * m)(*[pose_box(c) for c in cells])
+    handles = (ctypes.c_void_p * m)(*[sc.handle.value if isinstance(sc.handle, ctypes.c_void_p) else sc.handle
+                                       for sc in scenes])
+    if out is None:
+        lo = torch.empty((m, H, W, 3), dtype=torch.float32, device="cuda")
+        hi = torch.empty((m, H, W, 3), dtype=torch.float32, device="cuda")
+    else:
+        lo, hi = out
+    st = Stats()
+    co = options(opts)
+    _check(lib.ar_render_batch_scenes(handles, ctypes.byref(ci), arr, m, ctypes.byref(co),
+                                      ctypes.c_void_p(lo.data_ptr()), ctypes.c_void_p(hi.data_ptr()),
+                                      _stream_ptr(stream), ctypes.byref(st)))
     return lo, hi, st.as_dict()
 
 

@@ -43,6 +43,8 @@ void release_workspace(Workspace &ws) {
   if (ws.host_ranges) (void)hipHostFree(ws.host_ranges);
   if (ws.host_seg) (void)hipHostFree(ws.host_seg);
   if (ws.pose_host) (void)hipHostFree(ws.pose_host);
+  if (ws.tab_host) (void)hipHostFree(ws.tab_host);
+  if (ws.tab_off_host) (void)hipHostFree(ws.tab_off_host);
   for (int i = 0; i < 4; ++i)
     if (ws.ev[i]) (void)hipEventDestroy(ws.ev[i]);
   ws = Workspace{};
@@ -137,6 +139,7 @@ int make_params(const ar_scene *sc, const ar_intrinsics *in, const ar_options *o
   prm.taylor_k = o.taylor_k ? o.taylor_k : 8;
   prm.z_near = o.z_near > 0 ? o.z_near : 0.01;
   const double budget = o.cull_budget > 0 ? o.cull_budget : 1e-7;
+  prm.cull_budget = budget;
   prm.eps_cull = budget / (double)sc->dev.n;
   prm.E = budget * (1.0 + 0x1p-10);
   prm.t_min = o.t_min == 0.0 ? 1e-7 : o.t_min;  // negative disables the early stop
@@ -715,15 +718,55 @@ static int render_rotation(const ar_scene *sc, Workspace &ws, const Params &prm,
 // launch per stage: item cell * n + g, list cell * ntiles + tile, images [cell][H][W][3].
 // The host waits twice per call (the number of list entries, and on the rotation path
 // the number of Ind runs) and once at the end.
+// The table of a launch whose cells render different scenes: pinned staging and device
+// copy for up to ncells cells.
+static int ensure_tab(Workspace &ws, int ncells) {
+  if ((size_t)ncells <= ws.cap_tab && ws.tab_dev) return AR_OK;
+  if (ws.arena) return fail(AR_E_UNSUPPORTED, "arena workspace renders one scene");
+  if (ws.tab_host) HIP_TRY(hipHostFree(ws.tab_host));
+  if (ws.tab_off_host) HIP_TRY(hipHostFree(ws.tab_off_host));
+  ws.tab_host = nullptr;
+  ws.tab_off_host = nullptr;
+  HIP_TRY(grow(ws, ws.tab_dev, (size_t)ncells));
+  HIP_TRY(grow(ws, ws.tab_off_dev, (size_t)ncells + 1));
+  HIP_TRY(hipHostMalloc((void **)&ws.tab_host, (size_t)ncells * sizeof(CellScene), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void **)&ws.tab_off_host, ((size_t)ncells + 1) * sizeof(uint32_t), hipHostMallocDefault));
+  ws.cap_tab = (size_t)ncells;
+  return AR_OK;
+}
+
+// Clears the workspace's launch table when the launch ends (the table is in use only
+// for the launch that set it).
+struct TabScope {
+  Workspace &ws;
+  ~TabScope() {
+    ws.tab = nullptr;
+    ws.tab_off = nullptr;
+    ws.tab_cells = 0;
+  }
+};
+
 int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const ar_pose_box *boxes, int ncells, int P,
-                 bool rotates, float *lo, float *hi, hipStream_t s, ar_stats *st) {
+                 bool rotates, float *lo, float *hi, hipStream_t s, ar_stats *st, const ar_scene *const *cell_scenes) {
   Params prm = prm_in;
   prm.nominal_order = rotates ? 1 : 0;   // rotation path: lists in order of the nominal depth
   prm.pose_vars = P - sc->dev.nvar;      // scene variables follow the pose variables
   if (sc->dev.moving) prm.ind_window = 2;   // moved means: every pair of a list is tested
+  prm.eps_cull = prm.cull_budget / (double)sc->dev.n;   // this launch's scene (batches of several scenes)
   const int n = sc->dev.n;
   const int ntiles = prm.ntx * prm.nty;
-  const size_t n_total = (size_t)ncells * n;
+  // cells of different scenes: items of cell c at [first_c, first_c + n_c), first_c the
+  // sum of the scenes' sizes before it
+  bool mixed = false;
+  size_t n_total = (size_t)ncells * n;
+  if (cell_scenes) {
+    size_t sum = 0;
+    for (int c = 0; c < ncells; ++c) {
+      mixed = mixed || cell_scenes[c] != sc;
+      sum += (size_t)cell_scenes[c]->dev.n;
+    }
+    if (mixed) n_total = sum;
+  }
   const size_t nlists = (size_t)ncells * ntiles;
   if (!rotates && P > 3) return fail(AR_E_INVALID, "more than 3 translation variables");
   if (rotates && prm.tile != kTile) return fail(AR_E_UNSUPPORTED, "tile %d: rotation boxes use %d", prm.tile, kTile);
@@ -731,6 +774,27 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
     return fail(AR_E_UNSUPPORTED, "too many cells in one launch (%zu items, %zu tile lists)", n_total, nlists);
   int rc = ensure_ws(ws, n_total, nlists, P, ncells);
   if (rc) return rc;
+  TabScope tab_scope{ws};
+  if (mixed) {
+    rc = ensure_tab(ws, ncells);
+    if (rc) return rc;
+    size_t off = 0;
+    for (int c = 0; c < ncells; ++c) {
+      const SceneDev &d = cell_scenes[c]->dev;
+      ws.tab_host[c].sc = d;
+      ws.tab_host[c].off = off;
+      ws.tab_host[c].eps_cull = prm.cull_budget / (double)d.n;   // as a render of that scene alone
+      ws.tab_off_host[c] = (uint32_t)off;
+      off += (size_t)d.n;
+    }
+    ws.tab_off_host[ncells] = (uint32_t)off;
+    HIP_TRY(hipMemcpyAsync(ws.tab_dev, ws.tab_host, (size_t)ncells * sizeof(CellScene), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ws.tab_off_dev, ws.tab_off_host, ((size_t)ncells + 1) * sizeof(uint32_t),
+                           hipMemcpyHostToDevice, s));
+    ws.tab = ws.tab_dev;
+    ws.tab_off = ws.tab_off_dev;
+    ws.tab_cells = ncells;
+  }
   const bool timed = ws.ev[0] != nullptr;   // no events in arena mode
   if (timed) HIP_TRY(hipEventRecord(ws.ev[0], s));
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ws.counters, 16);
@@ -753,7 +817,7 @@ int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm_in, const 
     std::swap(ws.perm, ws.perm_alt);
   }
   if (ncells > 1) {
-    HIP_TRY(launch_cell_keys(ws.perm, (int)n_total, n, ws.cell_key, s));
+    HIP_TRY(launch_cell_keys(ws.perm, (int)n_total, n, ws.cell_key, s, ws.tab_off, ws.tab_cells));
     HIP_TRY(radix_sort_u32(ws.cell_key, ws.cell_key_alt, ws.perm, ws.perm_alt, (int)n_total, 0,
                            ((bits_for((uint32_t)(ncells - 1)) + 7) / 8) * 8, ws, s, &alt));
     if (alt) {
@@ -1052,13 +1116,14 @@ static int ensure_out_stage(Workspace &ws, size_t floats) {
 // Renders m cells of one launch into lo / hi, through the workspace's staging images when
 // the outputs are host memory (copied back before returning).
 static int render_cells_out(const ar_scene *sc, Workspace &ws, const Params &prm, const ar_pose_box *cells, int m,
-                            int P, bool rot, float *lo, float *hi, bool host, hipStream_t s, ar_stats *st) {
-  if (!host) return render_cells(sc, ws, prm, cells, m, P, rot, lo, hi, s, st);
+                            int P, bool rot, float *lo, float *hi, bool host, hipStream_t s, ar_stats *st,
+                            const ar_scene *const *cell_scenes = nullptr) {
+  if (!host) return render_cells(sc, ws, prm, cells, m, P, rot, lo, hi, s, st, cell_scenes);
   const size_t n = (size_t)m * prm.width * prm.height * 3;
   int rc = ensure_out_stage(ws, n);
   if (rc) return rc;
   float *dlo = ws.out_stage, *dhi = ws.out_stage + n;
-  rc = render_cells(sc, ws, prm, cells, m, P, rot, dlo, dhi, s, st);
+  rc = render_cells(sc, ws, prm, cells, m, P, rot, dlo, dhi, s, st, cell_scenes);
   if (rc) return rc;
   HIP_TRY(hipMemcpyAsync(lo, dlo, n * sizeof(float), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(hi, dhi, n * sizeof(float), hipMemcpyDeviceToHost, s));
@@ -1451,6 +1516,65 @@ int ar_render_batch(const ar_scene *scene, const ar_intrinsics *intr, const ar_p
       const int m = std::min(j - i, ar::batch_cells(scene, ws, prm, P, rot, opts));
       rc = ar::render_cells_out(scene, ws, prm, cells + i, m, P, rot, lo_rgb + i * img, hi_rgb + i * img, host,
                                 (hipStream_t)hip_stream, stats);
+      if (rc) return rc;
+      i += m;
+    }
+  }
+  return AR_OK;
+}
+
+int ar_render_batch_scenes(const ar_scene *const *scenes, const ar_intrinsics *intr, const ar_pose_box *cells,
+                           int32_t ncells, const ar_options *opts, float *lo_rgb, float *hi_rgb, void *hip_stream,
+                           ar_stats *stats) {
+  if (!scenes) return fail(AR_E_INVALID, "scenes is NULL");
+  if (!cells || ncells < 1) return fail(AR_E_INVALID, "batch needs at least one cell");
+  bool one = true;
+  for (int i = 0; i < ncells; ++i) {
+    if (!scenes[i]) return fail(AR_E_INVALID, "scene of cell %d is NULL", i);
+    one = one && scenes[i] == scenes[0];
+  }
+  if (one) return ar_render_batch(scenes[0], intr, cells, ncells, opts, lo_rgb, hi_rgb, hip_stream, stats);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  for (int i = 0; i < ncells; ++i) {
+    int rc = ar::validate_box(&cells[i]);
+    if (rc) return rc;
+    if (scenes[i]->dev.nvar > 0)
+      return fail(AR_E_UNSUPPORTED, "cell %d: a set of scenes (scene variables) renders only with cells of its own", i);
+    hipPointerAttribute_t at{};
+    HIP_TRY(hipPointerGetAttributes(&at, scenes[i]->base));
+    if (at.device != dev) return fail(AR_E_INVALID, "scene of cell %d is on device %d, not the current %d", i, at.device, dev);
+  }
+  ar::Params prm{};
+  int rc = ar::make_params(scenes[0], intr, opts, prm);
+  if (rc) return rc;
+  bool host = false;
+  rc = ar::check_outputs_any(lo_rgb, hi_rgb, &host);
+  if (rc) return rc;
+  if (stats) memset(stats, 0, sizeof(*stats));
+  const size_t img = (size_t)intr->width * intr->height * 3;
+  ar::Workspace &ws = const_cast<ar_scene *>(scenes[0])->ws;
+  // runs of consecutive cells with the same pose variables, in launches sized as
+  // ar_render_batch's for the largest scene of the run
+  int i = 0;
+  while (i < ncells) {
+    bool rot = false;
+    int P = 0;
+    rc = ar::render_vars(scenes[i], &cells[i], &rot, &P);
+    if (rc) return rc;
+    int j = i + 1;
+    const ar_scene *big = scenes[i];
+    while (j < ncells) {
+      bool r2 = false;
+      int P2 = 0;
+      if (ar::render_vars(scenes[j], &cells[j], &r2, &P2) || P2 != P || r2 != rot) break;
+      if (scenes[j]->dev.n > big->dev.n) big = scenes[j];
+      ++j;
+    }
+    while (i < j) {
+      const int m = std::min(j - i, ar::batch_cells(big, ws, prm, P, rot, opts));
+      rc = ar::render_cells_out(scenes[i], ws, prm, cells + i, m, P, rot, lo_rgb + i * img, hi_rgb + i * img, host,
+                                (hipStream_t)hip_stream, stats, scenes + i);
       if (rc) return rc;
       i += m;
     }

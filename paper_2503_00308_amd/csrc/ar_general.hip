@@ -61,12 +61,13 @@ constexpr double kZeroFactor = 0x1p-60; // stands for a factor 1 - a_hi = 0 in t
 // [6, 12), and the largest |uw_l| [12] (the scale of the rounding margins).
 __global__ __launch_bounds__(256) void k_list_box(const uint32_t *__restrict__ ranges,
                                                   const uint32_t *__restrict__ lists,
-                                                  const PoseForms *__restrict__ poses, SceneDev sc, int ntiles,
-                                                  double *__restrict__ lbox) {
+                                                  const PoseForms *__restrict__ poses, SceneDev scene, int ntiles,
+                                                  double *__restrict__ lbox, const CellScene *__restrict__ tab) {
   __shared__ double red[kListBox][256];
   const int lst = blockIdx.x;
   const int cell = lst / ntiles;
-  const size_t gbase = (size_t)cell * sc.n;
+  const SceneDev &sc = cell_scene(scene, tab, cell);
+  const size_t gbase = cell_first(scene, tab, cell);
   const PoseForms &pose = poses[cell];
   double m[3], mm = 0.0;
 #pragma unroll
@@ -264,16 +265,19 @@ struct IndSrc {
 template <int P>
 __global__ __launch_bounds__(256) void k_ind_gather(const uint32_t *__restrict__ pkey,
                                                     const uint32_t *__restrict__ lists, const double *__restrict__ dform,
-                                                    SceneDev sc, int ntiles, uint32_t pbase, int ng,
+                                                    SceneDev scene, int ntiles, uint32_t pbase, int ng,
                                                     const uint32_t *__restrict__ ng_dev,
-                                                    float4 *__restrict__ cmean, double *__restrict__ cform) {
+                                                    float4 *__restrict__ cmean, double *__restrict__ cform,
+                                                    const CellScene *__restrict__ tab) {
   constexpr int F = P + 1;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (ng_dev) ng = min(ng, (int)*ng_dev);
   if (q >= ng) return;
   const size_t p = (size_t)pbase + q;
   const uint32_t g = lists[p];
-  const size_t lg = g - (size_t)(pkey[p] / (uint32_t)ntiles) * sc.n;
+  const int cell = (int)(pkey[p] / (uint32_t)ntiles);
+  const SceneDev &sc = cell_scene(scene, tab, cell);
+  const size_t lg = g - cell_first(scene, tab, cell);
   cmean[q] = make_float4(sc.ind_mean[lg], sc.ind_mean[sc.n + lg], sc.ind_mean[2 * (size_t)sc.n + lg], 0.0f);
   const double *d = dform + (size_t)g * 2 * (kMaxP + 1);
   double *o = cform + (size_t)q * 2 * F;
@@ -386,13 +390,14 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
                                               const uint32_t *__restrict__ lists, const double *__restrict__ dint,
                                               const double *__restrict__ dform, const float4 *__restrict__ cmean,
                                               const double *__restrict__ cform, const double *__restrict__ lbox,
-                                              const PoseForms *__restrict__ poses, int ntiles, SceneDev sc,
+                                              const PoseForms *__restrict__ poses, int ntiles, SceneDev scene,
                                               uint32_t pbase, int ng, int window_mode, uint32_t *__restrict__ win,
                                               uint32_t *__restrict__ woff, unsigned long long *__restrict__ masks,
                                               uint32_t *__restrict__ cnt, uint32_t *__restrict__ runs,
                                               unsigned long long *__restrict__ counters,
                                               const uint32_t *__restrict__ ng_dev, uint32_t runs_cap,
-                                              unsigned long long *__restrict__ ind_und) {
+                                              unsigned long long *__restrict__ ind_und,
+                                              const CellScene *__restrict__ tab) {
   constexpr bool EMIT = MODE == kRunsEmit;
   const int lane = threadIdx.x & 63;
   // planned launches: the entries counted on the device, and no runs past the buffer
@@ -417,7 +422,8 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
       i = (int)(pbase + (uint32_t)p) - beg;
       const uint32_t *list = lists + beg;
       gi = list[i];
-      const size_t li = gi - (size_t)cell * sc.n;
+      const SceneDev &sc = cell_scene(scene, tab, cell);
+      const size_t li = gi - cell_first(scene, tab, cell);
       uwi[0] = sc.ind_mean[li];
       uwi[1] = sc.ind_mean[sc.n + li];
       uwi[2] = sc.ind_mean[2 * sc.n + li];
@@ -497,8 +503,9 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
     uint32_t ndef = 0, nmay = 0, nund = 0, nbord = 0;
     if (have && !wide) {
       const PoseForms &pose = poses[cell];
+      const SceneDev &sc = cell_scene(scene, tab, cell);
       const IndSrc<P, COMPACT> src{lists + beg, sc.ind_mean, COMPACT ? cform : dform, cmean, sc.n,
-                                   (size_t)cell * sc.n, (size_t)((uint32_t)beg - pbase)};
+                                   cell_first(scene, tab, cell), (size_t)((uint32_t)beg - pbase)};
       const double *dfi = src.forms_of(i);
       int def_start = ps > 0 ? 0 : -1;   // open run [0, ps) of certain occluders
       int may_start = ps > 0 ? 0 : -1;
@@ -583,8 +590,9 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
         kom = runs + 2 * (size_t)cnt[2 * kp + 1];
       }
       unsigned long long *km_ = masks ? masks + woff[kp] : nullptr;
-      const IndSrc<P, COMPACT> src{lists + kb, sc.ind_mean, COMPACT ? cform : dform, cmean, sc.n, (size_t)kc * sc.n,
-                                   (size_t)((uint32_t)kb - pbase)};
+      const SceneDev &ksc = cell_scene(scene, tab, kc);
+      const IndSrc<P, COMPACT> src{lists + kb, ksc.ind_mean, COMPACT ? cform : dform, cmean, ksc.n,
+                                   cell_first(scene, tab, kc), (size_t)((uint32_t)kb - pbase)};
       uint32_t kd, km, ku, kbd;
       wave_runs<P, MODE, COMPACT>(poses[kc], src, ki, kps, kqe, kuw, src.forms_of(ki), km_, kod, kom, lane, kd, km,
                                   ku, kbd);
@@ -689,6 +697,7 @@ __global__ __launch_bounds__(256) void k_runs_count_lanes(const uint32_t *__rest
       const int gbeg = __builtin_amdgcn_readlane(beg, l0);
       const int gcell = (int)(gtile / (uint32_t)ntiles);
       const PoseForms &pose = poses[gcell];
+      // (the compact copy holds the means and forms by position: the scene's arrays are not read)
       const Src src{lists + gbeg, sc.ind_mean, cform, cmean, sc.n, (size_t)gcell * sc.n, (size_t)((uint32_t)gbeg - pbase)};
       int def_start = (mine && ps > 0) ? 0 : -1;   // open run [0, ps) of certain occluders
       int may_start = def_start;
@@ -1164,7 +1173,8 @@ __global__ __launch_bounds__(192) void k_rot_merge(const uint32_t *__restrict__ 
 // ---------------------------------------------------------------------------------
 hipError_t launch_list_box(const Workspace &ws, const uint32_t *lists, const PoseForms *poses, int nlists, int ntiles,
                            const SceneDev &sc, hipStream_t s) {
-  hipLaunchKernelGGL(k_list_box, dim3(nlists), dim3(256), 0, s, ws.tile_range, lists, poses, sc, ntiles, ws.lbox);
+  hipLaunchKernelGGL(k_list_box, dim3(nlists), dim3(256), 0, s, ws.tile_range, lists, poses, sc, ntiles, ws.lbox,
+                     ws.tab);
   return hipGetLastError();
 }
 
@@ -1177,7 +1187,7 @@ static hipError_t launch_runs_pm(const Workspace &ws, const uint32_t *lists, con
   hipLaunchKernelGGL((k_runs<P, MODE, COMPACT>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint,
                      ws.dform, (const float4 *)ws.cmean, ws.cform, ws.lbox, poses_dev, ntiles, sc, pbase, ng,
                      window_mode, ws.win, ws.woff, masks, ws.run_cnt, ws.runs, ws.counters, dc.entries, dc.runs_cap,
-                     dc.ind_und);
+                     dc.ind_und, ws.tab);
   return hipGetLastError();
 }
 
@@ -1208,7 +1218,7 @@ template <int P>
 static hipError_t launch_ind_gather_p(const Workspace &ws, const uint32_t *lists, const SceneDev &sc, int ntiles,
                                       uint32_t pbase, int ng, const uint32_t *ng_dev, hipStream_t s) {
   hipLaunchKernelGGL(k_ind_gather<P>, dim3((unsigned)(((size_t)ng + 255) / 256)), dim3(256), 0, s, ws.pair_key,
-                     lists, ws.dform, sc, ntiles, pbase, ng, ng_dev, (float4 *)ws.cmean, ws.cform);
+                     lists, ws.dform, sc, ntiles, pbase, ng, ng_dev, (float4 *)ws.cmean, ws.cform, ws.tab);
   return hipGetLastError();
 }
 

@@ -39,9 +39,12 @@ size_t query_bytes(const ar_scene *sc, const Params &prm, int P, bool rotates, i
 int batch_cells(const ar_scene *sc, const Workspace &ws, const Params &prm, int P, bool rotates,
                 const ar_options *opts);
 // ncells pose boxes with the same pose variables into images [cell][H][W][3] on stream s,
-// using workspace ws; waits for the stream before returning
+// using workspace ws; waits for the stream before returning.  cell_scenes (may be null:
+// every cell renders sc) gives each cell's scene; scenes other than sc must be plain
+// (no scene variables), as sc
 int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm, const ar_pose_box *boxes, int ncells, int P,
-                 bool rotates, float *lo, float *hi, hipStream_t s, ar_stats *st);
+                 bool rotates, float *lo, float *hi, hipStream_t s, ar_stats *st,
+                 const ar_scene *const *cell_scenes = nullptr);
 // buffers of a planned launch; the launch itself (no host synchronisation, no
 // allocation: capturable in a HIP graph), pose forms read from poses_dev
 int ensure_planned(Workspace &ws, const ar_scene *sc, const Params &prm, int ncells, int P, bool rotates,

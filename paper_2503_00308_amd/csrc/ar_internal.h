@@ -102,6 +102,7 @@ struct Params {
   double fx, fy, cx, cy;
   int32_t taylor_k;
   double z_near;
+  double cull_budget;  // cull budget per pixel
   double eps_cull;     // cull_budget / n
   double E;            // widening for pruning
   double t_min;
@@ -150,6 +151,35 @@ struct SceneDev {
   double s_mid[kMaxP], s_rad[kMaxP];
 };
 
+// A pose cell's scene in a launch whose cells render different scenes: the cell's
+// Gaussians are the items [off, off + sc.n) of the launch (local Gaussian g at item
+// off + g), and eps_cull is its scene's cull threshold (the budget over its size).  A
+// launch of one scene has no table: cell c's items start at c * n.
+struct CellScene {
+  SceneDev sc;
+  uint64_t off;
+  double eps_cull;
+};
+
+// The scene of cell c, and the first item of cell c (tab: the launch's table, or null).
+__host__ __device__ inline const SceneDev &cell_scene(const SceneDev &sc, const CellScene *tab, int c) {
+  return tab ? tab[c].sc : sc;
+}
+__host__ __device__ inline size_t cell_first(const SceneDev &sc, const CellScene *tab, int c) {
+  return tab ? (size_t)tab[c].off : (size_t)c * (size_t)sc.n;
+}
+// Cell of item i: i / n in a launch of one scene, else the last c with item_off[c] <= i
+// (item_off[0 .. ncells]: the cells' first items, then the total).
+__host__ __device__ inline int item_cell(const uint32_t *item_off, int ncells, int n, uint32_t i) {
+  if (!item_off) return (int)(i / (uint32_t)n);
+  int lo = 0, hi = ncells - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (item_off[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // List density of a launch, used to estimate the workspace of the next one on the same
 // scene: list entries per Gaussian item and, on the rotation path, Ind runs and stored
 // mask words per list entry and whether the compact copy was used (largest over groups).
@@ -186,6 +216,15 @@ struct Workspace {
   Density density;               // of the last launch
   PoseForms *pose_dev = nullptr;   // [cells] pose forms of a launch
   PoseForms *pose_host = nullptr;  // [cells] pinned staging
+  // launches whose cells render different scenes: the cells' table and their first items
+  // ([cells + 1], the total last) in device memory, set for the duration of such a launch
+  // (null otherwise), with their pinned staging and capacity
+  CellScene *tab = nullptr;
+  uint32_t *tab_off = nullptr;
+  int tab_cells = 0;
+  CellScene *tab_dev = nullptr, *tab_host = nullptr;
+  uint32_t *tab_off_dev = nullptr, *tab_off_host = nullptr;
+  size_t cap_tab = 0;
   double *rec = nullptr;       // [n][stride]
   uint64_t *key = nullptr;     // [n] depth key (by gid, kept for tie tests)
   uint64_t *key_sort = nullptr;  // [n] copy of the keys, sorted in place
@@ -275,8 +314,9 @@ hipError_t exclusive_scan_u32(uint32_t *data, int n, Workspace &ws, hipStream_t 
 // *total (zeroed by the caller) += sum of data[0 .. n) in 64 bits (the true total of counts
 // whose 32-bit scan may wrap)
 hipError_t sum_u32_u64(const uint32_t *data, size_t n, unsigned long long *total, hipStream_t s);
-// keys[i] = items[i] / n_cell (cell of a global item)
-hipError_t launch_cell_keys(const uint32_t *items, int n_total, int n_cell, uint32_t *keys, hipStream_t s);
+// keys[i] = cell of the global item items[i] (item_cell; item_off null: items[i] / n_cell)
+hipError_t launch_cell_keys(const uint32_t *items, int n_total, int n_cell, uint32_t *keys, hipStream_t s,
+                            const uint32_t *item_off = nullptr, int ncells = 0);
 hipError_t ensure_hist(Workspace &ws, size_t n_entries);
 
 // (Re)allocate p for `need` elements, keeping the workspace's byte count; old contents

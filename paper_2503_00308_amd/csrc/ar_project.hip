@@ -397,7 +397,8 @@ __device__ __forceinline__ void project_one(const SceneDev &sc, const PoseForms 
                                             size_t oi, double *__restrict__ rec_out, uint64_t *__restrict__ key_out,
                                             uint64_t *__restrict__ key_sort, uint32_t *__restrict__ perm_out,
                                             int32_t *__restrict__ rect_out, double *__restrict__ dform_out,
-                                            double *__restrict__ dint_out, unsigned long long *__restrict__ counters) {
+                                            double *__restrict__ dint_out, unsigned long long *__restrict__ counters,
+                                            double eps_cull) {
   const int n = sc.n;
   double uw[3] = {sc.mean[g], sc.mean[n + g], sc.mean[2 * n + g]};
   // a set of scenes (Sec. 4.6): the mean moved by scene variable v, uw + dir s_v, is the
@@ -496,7 +497,7 @@ __device__ __forceinline__ void project_one(const SceneDev &sc, const PoseForms 
                         sqrt(0.25 * fmax((ahi - clo) * (ahi - clo), (chi - alo) * (chi - alo)) + fmax(blo * blo, bhi * bhi));
     const double dl2 = dlo * dlo;
     lam = lamx / (dl2 * dl2);
-    r2 = ((double)o > prm.eps_cull) ? 2.0 * lam * log((double)o / prm.eps_cull) : -1.0;
+    r2 = ((double)o > eps_cull) ? 2.0 * lam * log((double)o / eps_cull) : -1.0;
     geo_ok = isfinite(m0lo) && isfinite(m0hi) && isfinite(m1lo) && isfinite(m1hi) && isfinite(lam) &&
              isfinite(r2) && lam > 0.0;
   }
@@ -627,22 +628,25 @@ __global__ __launch_bounds__(64) void k_project(SceneDev sc, const PoseForms pos
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= sc.n) return;
   project_one<P>(sc, pose, prm, g, (size_t)g, rec_out, key_out, key_sort, perm_out, rect_out, dform_out, dint_out,
-                 counters);
+                 counters, prm.eps_cull);
 }
 
-// several pose cells (grid.y): pose forms of cell c at poses[c] in device memory
+// several pose cells (grid.y): pose forms of cell c at poses[c] in device memory; with a
+// table (cells of different scenes) cell c renders tab[c]'s scene at its items
 template <int P>
 __global__ __launch_bounds__(64) void k_project_cells(SceneDev sc, const PoseForms *__restrict__ poses, Params prm,
                                                       double *__restrict__ rec_out, uint64_t *__restrict__ key_out,
                                                       uint64_t *__restrict__ key_sort, uint32_t *__restrict__ perm_out,
                                                       int32_t *__restrict__ rect_out, double *__restrict__ dform_out,
                                                       double *__restrict__ dint_out,
-                                                      unsigned long long *__restrict__ counters) {
+                                                      unsigned long long *__restrict__ counters,
+                                                      const CellScene *__restrict__ tab) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= sc.n) return;
   const int c = blockIdx.y;
-  project_one<P>(sc, poses[c], prm, g, (size_t)c * sc.n + g, rec_out, key_out, key_sort, perm_out, rect_out,
-                 dform_out, dint_out, counters);
+  const SceneDev &cs = cell_scene(sc, tab, c);
+  if (g >= cs.n) return;
+  project_one<P>(cs, poses[c], prm, g, cell_first(sc, tab, c) + g, rec_out, key_out, key_sort, perm_out, rect_out,
+                 dform_out, dint_out, counters, tab ? tab[c].eps_cull : prm.eps_cull);
 }
 
 // Types only, for several pose cells (grid.y): counts[2c] = MatrixInv failures of cell c
@@ -655,7 +659,7 @@ __global__ __launch_bounds__(64) void k_classify_cells(SceneDev sc, const PoseFo
   if (g >= sc.n) return;
   const int c = blockIdx.y;
   project_one<P, true>(sc, poses[c], prm, g, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                       counts + 2 * (size_t)c);
+                       counts + 2 * (size_t)c, prm.eps_cull);
 }
 
 // Pose forms on the host: O(1) work, passed to the kernels by value.
@@ -675,9 +679,13 @@ int pose_forms_host(const ar_pose_box &box, int P, PoseForms &out) {
 template <int P>
 static hipError_t launch_project_p(const SceneDev &sc, const PoseForms &pose, const PoseForms *poses_dev, int ncells,
                                    const Params &prm, Workspace &ws, hipStream_t s) {
-  if (poses_dev)
-    hipLaunchKernelGGL(k_project_cells<P>, dim3((sc.n + 63) / 64, ncells), dim3(64), 0, s, sc, poses_dev, prm, ws.rec,
-                       ws.key, ws.key_sort, ws.perm, ws.rect, ws.dform, ws.dint, ws.counters);
+  if (poses_dev) {
+    int nmax = sc.n;   // the largest scene of the cells
+    if (ws.tab)
+      for (int c = 0; c < ncells; ++c) nmax = std::max(nmax, ws.tab_host[c].sc.n);
+    hipLaunchKernelGGL(k_project_cells<P>, dim3((nmax + 63) / 64, ncells), dim3(64), 0, s, sc, poses_dev, prm, ws.rec,
+                       ws.key, ws.key_sort, ws.perm, ws.rect, ws.dform, ws.dint, ws.counters, ws.tab);
+  }
   else
     hipLaunchKernelGGL(k_project<P>, dim3((sc.n + 63) / 64), dim3(64), 0, s, sc, pose, prm, ws.rec, ws.key,
                        ws.key_sort, ws.perm, ws.rect, ws.dform, ws.dint, ws.counters);

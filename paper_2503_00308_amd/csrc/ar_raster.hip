@@ -46,7 +46,8 @@ __device__ __forceinline__ float tile_dist2(const float *mu, int tx, int ty, con
   return dist2_rect(mu, ux0, ux1, uy0, uy1);
 }
 
-// Binning of global item r (depth-rank order; perm[r] = cell * n_cell + gid) to the lists
+// Binning of global item r (depth-rank order; perm[r] = cell * n_cell + gid, or the
+// cell's first item + gid when the cells render different scenes: item_off) to the lists
 // cell * ntiles + tile.  Small inputs: one wave per item, the lanes walk the tile
 // rectangle 64 tiles at a time and a ballot gives each kept tile its slot.  Large
 // inputs (many cells): one thread per item walking its rectangle.  Both emit an item's
@@ -58,7 +59,8 @@ __global__ __launch_bounds__(256) void k_bin(const double *__restrict__ recs, co
                                              const uint32_t *__restrict__ perm, int n_total, int n_cell, Params prm,
                                              uint32_t *__restrict__ counts, uint32_t *__restrict__ pkey,
                                              uint32_t *__restrict__ pval, uint32_t cap,
-                                             unsigned long long *__restrict__ overflow) {
+                                             unsigned long long *__restrict__ overflow,
+                                             const uint32_t *__restrict__ item_off, int ncells) {
   using R = Rec<P>;
   const int lane = threadIdx.x & 63;
   const int r = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(256) void k_bin(const double *__restrict__ recs, co
     return;
   }
   const uint32_t gid = perm[r];
-  const uint32_t lbase = (gid / (uint32_t)n_cell) * (uint32_t)(prm.ntx * prm.nty);
+  const uint32_t lbase = (uint32_t)item_cell(item_off, ncells, n_cell, gid) * (uint32_t)(prm.ntx * prm.nty);
   const double *rec = recs + (size_t)gid * R::STRIDE;
   const int type = rec_type<P>(rec);
   const int32_t *rc = rect + 4 * (size_t)gid;
@@ -101,7 +103,8 @@ __global__ __launch_bounds__(256) void k_bin_thread(const double *__restrict__ r
                                                     const uint32_t *__restrict__ perm, int n_total, int n_cell,
                                                     Params prm, uint32_t *__restrict__ counts,
                                                     uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval,
-                                                    uint32_t cap, unsigned long long *__restrict__ overflow) {
+                                                    uint32_t cap, unsigned long long *__restrict__ overflow,
+                                                    const uint32_t *__restrict__ item_off, int ncells) {
   using R = Rec<P>;
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n_total) return;
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(256) void k_bin_thread(const double *__restrict__ r
     return;
   }
   const uint32_t gid = perm[r];
-  const uint32_t lbase = (gid / (uint32_t)n_cell) * (uint32_t)(prm.ntx * prm.nty);
+  const uint32_t lbase = (uint32_t)item_cell(item_off, ncells, n_cell, gid) * (uint32_t)(prm.ntx * prm.nty);
   const double *rec = recs + (size_t)gid * R::STRIDE;
   const int type = rec_type<P>(rec);
   const int32_t *rc = rect + 4 * (size_t)gid;
@@ -159,18 +162,18 @@ static hipError_t launch_bin_p(const Workspace &ws, int n_total, int n_cell, con
     const dim3 grid((unsigned)((n_total + 3) / 4));   // four waves (items) per block
     if (emit)
       hipLaunchKernelGGL((k_bin<P, true>), grid, dim3(256), 0, s, ws.rec, ws.rect, ws.perm, n_total, n_cell, prm,
-                         ws.count, ws.pair_key, ws.pair_val, cap, ovf);
+                         ws.count, ws.pair_key, ws.pair_val, cap, ovf, ws.tab_off, ws.tab_cells);
     else
       hipLaunchKernelGGL((k_bin<P, false>), grid, dim3(256), 0, s, ws.rec, ws.rect, ws.perm, n_total, n_cell, prm,
-                         ws.count, ws.pair_key, ws.pair_val, 0u, ovf);
+                         ws.count, ws.pair_key, ws.pair_val, 0u, ovf, ws.tab_off, ws.tab_cells);
   } else {
     const dim3 grid((unsigned)((n_total + 255) / 256));
     if (emit)
       hipLaunchKernelGGL((k_bin_thread<P, true>), grid, dim3(256), 0, s, ws.rec, ws.rect, ws.perm, n_total, n_cell,
-                         prm, ws.count, ws.pair_key, ws.pair_val, cap, ovf);
+                         prm, ws.count, ws.pair_key, ws.pair_val, cap, ovf, ws.tab_off, ws.tab_cells);
     else
       hipLaunchKernelGGL((k_bin_thread<P, false>), grid, dim3(256), 0, s, ws.rec, ws.rect, ws.perm, n_total, n_cell,
-                         prm, ws.count, ws.pair_key, ws.pair_val, 0u, ovf);
+                         prm, ws.count, ws.pair_key, ws.pair_val, 0u, ovf, ws.tab_off, ws.tab_cells);
   }
   return hipGetLastError();
 }

@@ -327,14 +327,16 @@ __global__ void k_zero_n(uint32_t *__restrict__ p, int n) {
   if (i < n) p[i] = 0u;
 }
 
-__global__ void k_cell_keys(const uint32_t *__restrict__ items, int n_total, uint32_t n_cell,
-                            uint32_t *__restrict__ keys) {
+__global__ void k_cell_keys(const uint32_t *__restrict__ items, int n_total, int n_cell,
+                            uint32_t *__restrict__ keys, const uint32_t *__restrict__ item_off, int ncells) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_total) keys[i] = items[i] / n_cell;
+  if (i < n_total) keys[i] = (uint32_t)item_cell(item_off, ncells, n_cell, items[i]);
 }
 
-hipError_t launch_cell_keys(const uint32_t *items, int n_total, int n_cell, uint32_t *keys, hipStream_t s) {
-  hipLaunchKernelGGL(k_cell_keys, dim3((n_total + 255) / 256), dim3(256), 0, s, items, n_total, (uint32_t)n_cell, keys);
+hipError_t launch_cell_keys(const uint32_t *items, int n_total, int n_cell, uint32_t *keys, hipStream_t s,
+                            const uint32_t *item_off, int ncells) {
+  hipLaunchKernelGGL(k_cell_keys, dim3((n_total + 255) / 256), dim3(256), 0, s, items, n_total, n_cell, keys, item_off,
+                     ncells);
   return hipGetLastError();
 }
 
