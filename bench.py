@@ -393,6 +393,7 @@ def served_measure(api, synth, nq=96, loads=(0.25, 0.5, 0.75, 0.9), slots=4, see
                              "p99_ms": float(np.percentile(lat, 99)), "throughput_qps": nq / wall,
                              "peak_inflight": rep["peak_inflight"], "peak_workspace_bytes": rep["peak_bytes"],
                              "workspace_releases": rep["releases"],
+                             "shared_launches": rep["shared_launches"], "shared_queries": rep["shared_queries"],
                              "one_at_a_time": {"p50_ms": float(np.percentile(serial, 50)),
                                                "p90_ms": float(np.percentile(serial, 90)),
                                                "p99_ms": float(np.percentile(serial, 99)),
@@ -403,6 +404,7 @@ def served_measure(api, synth, nq=96, loads=(0.25, 0.5, 0.75, 0.9), slots=4, see
     out["saturation"] = {"throughput_qps": nq / wall, "wall_s": wall, "p50_ms": float(np.percentile(lat, 50)),
                          "p99_ms": float(np.percentile(lat, 99)), "peak_inflight": rep["peak_inflight"],
                          "workspace_releases": rep["releases"],
+                         "shared_launches": rep["shared_launches"], "shared_queries": rep["shared_queries"],
                          "one_at_a_time": {"throughput_qps": nq / serial_fin[-1],
                                            "p50_ms": float(np.percentile(serial_fin * 1e3, 50)),
                                            "p99_ms": float(np.percentile(serial_fin * 1e3, 99))},

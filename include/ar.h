@@ -473,8 +473,16 @@ const char *ar_version(void);
  * sizes and boxes run on the device at the same time once a backlog builds up: a query
  * starts beside running ones only while at least overlap_queue queries wait (kernels of
  * concurrent queries interleave without preemption, so a query beside a long one takes
- * longer; overlap pays when it drains a backlog).  A query's result is the same as
- * ar_render_bounds on the same arguments (same kernels, its own workspace).
+ * longer; overlap pays when it drains a backlog).  With batch_max > 1, under the same
+ * backlog a slot also takes, with the query at the head, later queued queries that can
+ * share its launches (same image size and intrinsics, options and pose variables;
+ * rotation boxes, or translation boxes with options.chunk set; plain scenes, or all on
+ * one scene), up to batch_max queries whose estimates fit the budget together: they
+ * render as one batch of cells over their scenes (ar_render_batch_scenes) and complete
+ * together.  Sharing pays for many small queries; queries that fill the device alone
+ * gain nothing from it and wait for each other, so it is off by default.  A query's
+ * result is the same as ar_render_bounds on the same arguments, bit for bit, alone or in
+ * a shared launch.
  *
  * hbm_budget  device bytes all slot workspaces may hold (0: half of the free memory at
  *             creation); scenes are not counted.  A query whose estimate exceeds the
@@ -482,8 +490,10 @@ const char *ar_version(void);
  *             workspace between queries unless the workspaces held exceed the budget,
  *             then it frees it (counted in ar_server_stats.releases).
  * slots       queries in flight at once, 1..16 (0: 4).
- * overlap_queue  queries waiting from which the next starts beside running ones (0: the
- *             number of slots; 1: whenever a slot is free).
+ * overlap_queue  queries waiting from which the next starts beside running ones, and
+ *             from which queries share launches (0: the number of slots; 1: whenever a
+ *             slot is free).
+ * batch_max   most queries in one shared launch, 1..256 (0 and 1: never shared).
  */
 typedef struct ar_server ar_server;
 
@@ -491,6 +501,8 @@ typedef struct {
   uint64_t hbm_budget;
   int32_t slots;
   int32_t overlap_queue;
+  int32_t batch_max;
+  int32_t reserved;     /* must be 0 */
 } ar_server_config;
 
 typedef struct {
@@ -501,6 +513,8 @@ typedef struct {
   ar_stats stats;
   uint64_t est_bytes;    /* workspace bytes estimated for the query at admission */
   uint64_t ws_bytes;     /* workspace bytes the slot held when the query finished */
+  int32_t batched;       /* queries in the launch that rendered it (1: alone); stats are
+                            those of the whole launch */
   char error[256];       /* message of a failed query */
 } ar_query_result;
 
@@ -512,6 +526,8 @@ typedef struct {
   uint64_t hbm_budget, peak_bytes;  /* budget and peak workspace bytes held */
   int64_t pairs;                    /* evaluated (pixel, Gaussian) pairs, all queries */
   int64_t releases;                 /* slot workspaces freed to stay within the budget */
+  int64_t shared_launches;          /* launches that rendered more than one query */
+  int64_t shared_queries;           /* queries rendered in them */
 } ar_server_stats;
 
 /* cfg may be NULL (defaults).  *out receives the handle. */

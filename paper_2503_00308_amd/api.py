@@ -82,13 +82,14 @@ class Stats(ctypes.Structure):
 
 
 class ServerConfig(ctypes.Structure):
-    _fields_ = [("hbm_budget", ctypes.c_uint64), ("slots", ctypes.c_int32), ("overlap_queue", ctypes.c_int32)]
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("slots", ctypes.c_int32), ("overlap_queue", ctypes.c_int32),
+                ("batch_max", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class QueryResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("slot", ctypes.c_int32), ("queue_ms", ctypes.c_double),
                 ("latency_ms", ctypes.c_double), ("stats", Stats), ("est_bytes", ctypes.c_uint64),
-                ("ws_bytes", ctypes.c_uint64), ("error", ctypes.c_char * 256)]
+                ("ws_bytes", ctypes.c_uint64), ("batched", ctypes.c_int32), ("error", ctypes.c_char * 256)]
 
 
 class ServerStats(ctypes.Structure):
@@ -96,7 +97,8 @@ class ServerStats(ctypes.Structure):
                 ("slots", ctypes.c_int32), ("peak_inflight", ctypes.c_int32),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("busy_s", ctypes.c_double), ("hbm_budget", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
-                ("pairs", ctypes.c_int64), ("releases", ctypes.c_int64)]
+                ("pairs", ctypes.c_int64), ("releases", ctypes.c_int64),
+                ("shared_launches", ctypes.c_int64), ("shared_queries", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -531,10 +533,10 @@ class Server:
     submit() allocates the two output tensors with torch and keeps them until wait()
     returns them; the server writes them from its own streams."""
 
-    def __init__(self, slots: int = 0, hbm_budget: int = 0, overlap_queue: int = 0):
+    def __init__(self, slots: int = 0, hbm_budget: int = 0, overlap_queue: int = 0, batch_max: int = 0):
         lib = load()
         self.handle = ctypes.c_void_p()
-        cfg = ServerConfig(int(hbm_budget), int(slots), int(overlap_queue))
+        cfg = ServerConfig(int(hbm_budget), int(slots), int(overlap_queue), int(batch_max), 0)
         _check(lib.ar_server_create(ctypes.byref(cfg), ctypes.byref(self.handle)))
         self._scenes = []
         self._out = {}
@@ -572,7 +574,7 @@ class Server:
         _check(code)
         lo, hi = bufs
         res = {"status": r.status, "slot": r.slot, "queue_ms": r.queue_ms, "latency_ms": r.latency_ms,
-               "stats": r.stats.as_dict(), "est_bytes": r.est_bytes, "ws_bytes": r.ws_bytes}
+               "stats": r.stats.as_dict(), "est_bytes": r.est_bytes, "ws_bytes": r.ws_bytes, "batched": r.batched}
         return lo, hi, res
 
     def report(self) -> dict:

@@ -1106,7 +1106,7 @@ static int check_outputs_any(const float *lo, const float *hi, bool *host) {
 }
 
 // Host outputs: the device images of `cells` cells (workspace buffers, grown as needed)
-static int ensure_out_stage(Workspace &ws, size_t floats) {
+int ensure_out_stage(Workspace &ws, size_t floats) {
   if (floats <= ws.cap_out_stage && ws.out_stage) return AR_OK;
   HIP_TRY(grow(ws, ws.out_stage, 2 * floats));
   ws.cap_out_stage = floats;

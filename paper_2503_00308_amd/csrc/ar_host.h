@@ -45,6 +45,8 @@ int batch_cells(const ar_scene *sc, const Workspace &ws, const Params &prm, int 
 int render_cells(const ar_scene *sc, Workspace &ws, const Params &prm, const ar_pose_box *boxes, int ncells, int P,
                  bool rotates, float *lo, float *hi, hipStream_t s, ar_stats *st,
                  const ar_scene *const *cell_scenes = nullptr);
+// staging images of the workspace: two blocks of `floats` floats at ws.out_stage
+int ensure_out_stage(Workspace &ws, size_t floats);
 // buffers of a planned launch; the launch itself (no host synchronisation, no
 // allocation: capturable in a HIP graph), pose forms read from poses_dev
 int ensure_planned(Workspace &ws, const ar_scene *sc, const Params &prm, int ncells, int P, bool rotates,

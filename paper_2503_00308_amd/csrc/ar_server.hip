@@ -1,7 +1,9 @@
 // Query server with continuous batching over resident scenes (include/ar.h, "Query
 // server").  Host code: one worker thread per slot, each with its own HIP stream and
 // workspace; a queue taken in order with admission by the device-memory budget; a query
-// starts beside running ones only when a backlog has built up.
+// starts beside running ones only when a backlog has built up, and then takes the later
+// queued queries that can share its launches with it (one batch of cells over their
+// scenes).
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -29,6 +31,7 @@ struct Query {
   int64_t ticket = 0;
   int32_t scene = 0;
   ar_pose_box box{};
+  ar_options opts{};
   ar::Params prm{};
   int P = 0;
   bool rotates = false;
@@ -38,6 +41,7 @@ struct Query {
   Clock::time_point t_submit, t_start, t_end;
   int status = AR_PENDING;
   int slot = -1;
+  int batched = 1;             // queries of the launch that rendered it
   ar_stats stats{};
   std::string error;
 };
@@ -66,11 +70,26 @@ struct ar_server {
   int device = 0;
   uint64_t budget = 0, peak_bytes = 0;
   int64_t next_ticket = 1, submitted = 0, completed = 0, failed = 0, pairs = 0, releases = 0;
+  int64_t shared_launches = 0, shared_queries = 0;
   int inflight = 0, peak_inflight = 0;
   int overlap_queue = 4;       // queries waiting from which one starts beside running ones
+  int batch_max = 1;           // most queries in one shared launch (1: none shared)
   double busy_s = 0.0;
   Clock::time_point busy_since;
   bool stop = false;
+
+  // b can share a with launches: the same image, options and pose variables, results
+  // that do not depend on the launch's size (rotation boxes: fixed segment length;
+  // translation boxes: only with options.chunk), and plain scenes or one scene
+  bool shareable(const Query &a, const Query &b) const {
+    if (a.P != b.P || a.rotates != b.rotates) return false;
+    if (!a.rotates && a.opts.chunk <= 0) return false;
+    if (memcmp(&a.opts, &b.opts, sizeof(ar_options)) != 0) return false;
+    if (a.prm.width != b.prm.width || a.prm.height != b.prm.height || a.prm.fx != b.prm.fx ||
+        a.prm.fy != b.prm.fy || a.prm.cx != b.prm.cx || a.prm.cy != b.prm.cy)
+      return false;
+    return a.scene == b.scene || (scenes[a.scene]->dev.nvar == 0 && scenes[b.scene]->dev.nvar == 0);
+  }
 
   size_t charged_except(const Slot *me) const {
     size_t b = 0;
@@ -83,7 +102,7 @@ struct ar_server {
     (void)hipSetDevice(device);
     Slot &slot = *slots[k];
     for (;;) {
-      std::shared_ptr<Query> q;
+      std::vector<std::shared_ptr<Query>> group;   // the head query, then those sharing its launches
       {
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
@@ -92,13 +111,27 @@ struct ar_server {
           // without preemption, so a query beside a long one stretches: worth it only
           // to drain a backlog), and when its workspace fits the budget
           if (!queue.empty()) {
-            const auto &h = queue.front();
+            const auto h = queue.front();
             const size_t need = std::max(slot.ws.bytes, h->est);
-            const bool may_overlap = (int)queue.size() >= overlap_queue;
-            if (inflight == 0 || (may_overlap && charged_except(&slot) + need <= budget)) {
-              q = h;
+            const bool backlog = (int)queue.size() >= overlap_queue;
+            if (inflight == 0 || (backlog && charged_except(&slot) + need <= budget)) {
+              group.push_back(h);
               queue.pop_front();
-              slot.charge = need;
+              size_t total = h->est;
+              // under the backlog, later queries that can share the head's launches, while
+              // their estimates fit the budget together
+              if (backlog && batch_max > 1) {
+                for (auto it = queue.begin(); it != queue.end() && (int)group.size() < batch_max;) {
+                  if (shareable(*h, **it) && charged_except(&slot) + total + (*it)->est <= budget) {
+                    total += (*it)->est;
+                    group.push_back(*it);
+                    it = queue.erase(it);
+                  } else {
+                    ++it;
+                  }
+                }
+              }
+              slot.charge = std::max(slot.ws.bytes, total);
               break;
             }
           } else if (stop) {
@@ -109,32 +142,86 @@ struct ar_server {
         slot.busy = true;
         if (inflight++ == 0) busy_since = Clock::now();
         peak_inflight = std::max(peak_inflight, inflight);
-        q->t_start = Clock::now();
-        q->slot = k;
+        for (auto &g : group) {
+          g->t_start = Clock::now();
+          g->slot = k;
+        }
       }
-      ar_stats st{};
-      const int rc = ar::render_cells(scenes[q->scene], slot.ws, q->prm, &q->box, 1, q->P, q->rotates, q->lo, q->hi,
-                                      slot.stream, &st);
-      const std::string err = rc ? ar::g_error : std::string();
+      const Query &q = *group[0];
+      const int m = (int)group.size();
+      std::vector<ar_stats> st(m);
+      std::vector<int> rcs(m, AR_OK);
+      std::vector<std::string> errs(m);
+      int rc = AR_OK;
+      if (m > 1) {
+        // one batch of cells over the queries' scenes into the slot's staging images, then
+        // copied to each query's outputs
+        std::vector<ar_pose_box> boxes(m);
+        std::vector<const ar_scene *> cs(m);
+        for (int i = 0; i < m; ++i) {
+          boxes[i] = group[i]->box;
+          cs[i] = scenes[group[i]->scene];
+        }
+        const size_t img = (size_t)q.prm.width * q.prm.height * 3;
+        rc = ar::ensure_out_stage(slot.ws, (size_t)m * img);
+        ar_stats bst{};
+        if (rc == AR_OK)
+          rc = ar::render_cells(cs[0], slot.ws, q.prm, boxes.data(), m, q.P, q.rotates, slot.ws.out_stage,
+                                slot.ws.out_stage + (size_t)m * img, slot.stream, &bst, cs.data());
+        for (int i = 0; i < m && rc == AR_OK; ++i) {
+          const float *slo = slot.ws.out_stage + (size_t)i * img, *shi = slot.ws.out_stage + (size_t)(m + i) * img;
+          if (hipMemcpyAsync(group[i]->lo, slo, img * sizeof(float), hipMemcpyDeviceToDevice, slot.stream) !=
+                  hipSuccess ||
+              hipMemcpyAsync(group[i]->hi, shi, img * sizeof(float), hipMemcpyDeviceToDevice, slot.stream) !=
+                  hipSuccess)
+            rc = ar::fail(AR_E_DEVICE, "copy of a shared launch's images failed");
+        }
+        if (rc == AR_OK && hipStreamSynchronize(slot.stream) != hipSuccess)
+          rc = ar::fail(AR_E_DEVICE, "shared launch failed on the device");
+        for (int i = 0; i < m; ++i) st[i] = bst;
+      }
+      if (m == 1 || rc != AR_OK) {
+        // alone (or each query again on its own when the shared launch failed)
+        for (int i = 0; i < m; ++i) {
+          const Query &g = *group[i];
+          st[i] = ar_stats{};
+          rcs[i] = ar::render_cells(scenes[g.scene], slot.ws, g.prm, &g.box, 1, g.P, g.rotates, g.lo, g.hi, slot.stream,
+                                    &st[i]);
+          if (rcs[i]) errs[i] = ar::g_error;
+        }
+      }
+      const bool shared = m > 1 && rc == AR_OK;
       {
         std::lock_guard<std::mutex> lk(mu);
         const Clock::time_point now = Clock::now();
-        q->t_end = now;
-        q->status = rc;
-        q->stats = st;
-        q->error = err;
         if (--inflight == 0) busy_s += std::chrono::duration<double>(now - busy_since).count();
-        if (rc == AR_OK) {
-          ++completed;
-          latencies.push_back(ms_between(q->t_submit, now));
-          pairs += st.pairs;
-          (q->rotates ? density_rot : density)[q->scene] = slot.ws.density;
-          (q->rotates ? density_rot_pix : density_pix)[q->scene] = (double)q->prm.width * q->prm.height;
-        } else {
-          ++failed;
+        if (shared) {
+          ++shared_launches;
+          shared_queries += m;
+          pairs += st[0].pairs;
+        }
+        for (int i = 0; i < m; ++i) {
+          Query &g = *group[i];
+          g.t_end = now;
+          g.status = rcs[i];
+          g.stats = st[i];
+          g.error = errs[i];
+          g.batched = shared ? m : 1;
+          if (rcs[i] == AR_OK) {
+            ++completed;
+            latencies.push_back(ms_between(g.t_submit, now));
+            if (!shared) pairs += st[i].pairs;
+            if (m == 1) {
+              // the scene's density, from a launch of that scene alone
+              (g.rotates ? density_rot : density)[g.scene] = slot.ws.density;
+              (g.rotates ? density_rot_pix : density_pix)[g.scene] = (double)g.prm.width * g.prm.height;
+            }
+          } else {
+            ++failed;
+          }
+          g.ws_bytes = slot.ws.bytes;
         }
         slot.busy = false;
-        q->ws_bytes = slot.ws.bytes;
         slot.charge = slot.ws.bytes;
         peak_bytes = std::max<uint64_t>(peak_bytes, charged_except(nullptr));
         // hand memory back when the held workspaces exceed the budget
@@ -159,6 +246,8 @@ int ar_server_create(const ar_server_config *cfg, ar_server **out) {
   if (cfg) c = *cfg;
   if (c.slots < 0 || c.slots > 16) return ar::fail(AR_E_INVALID, "slots %d outside [0, 16]", c.slots);
   if (c.overlap_queue < 0) return ar::fail(AR_E_INVALID, "overlap_queue %d is negative", c.overlap_queue);
+  if (c.batch_max < 0 || c.batch_max > 256) return ar::fail(AR_E_INVALID, "batch_max %d outside [0, 256]", c.batch_max);
+  if (c.reserved != 0) return ar::fail(AR_E_INVALID, "reserved must be 0");
   std::unique_ptr<ar_server> srv(new ar_server());
   HIP_TRY(hipGetDevice(&srv->device));
   if (c.hbm_budget == 0) {
@@ -169,6 +258,7 @@ int ar_server_create(const ar_server_config *cfg, ar_server **out) {
   srv->budget = c.hbm_budget;
   const int nslots = c.slots ? c.slots : 4;
   srv->overlap_queue = c.overlap_queue ? c.overlap_queue : nslots;
+  srv->batch_max = c.batch_max ? c.batch_max : 1;
   for (int k = 0; k < nslots; ++k) {
     std::unique_ptr<Slot> s(new Slot());
     HIP_TRY(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
@@ -231,6 +321,7 @@ int ar_server_submit(ar_server *srv, int32_t scene_id, const ar_intrinsics *intr
   auto q = std::make_shared<Query>();
   rc = ar::make_params(scene, intr, opts, q->prm);
   if (rc) return rc;
+  if (opts) q->opts = *opts;
   rc = ar::check_outputs(lo_rgb, hi_rgb);
   if (rc) return rc;
   rc = ar::render_vars(scene, box, &q->rotates, &q->P);
@@ -281,6 +372,7 @@ int ar_server_wait(ar_server *srv, int64_t ticket, int32_t block, ar_query_resul
   out->stats = q->stats;
   out->est_bytes = q->est;
   out->ws_bytes = q->ws_bytes;
+  out->batched = q->batched;
   strncpy(out->error, q->error.c_str(), sizeof(out->error) - 1);
   srv->records.erase(ticket);
   if (q->status != AR_OK) return ar::fail(q->status, "%s", q->error.c_str());
@@ -317,6 +409,8 @@ int ar_server_report(ar_server *srv, ar_server_stats *out) {
   out->peak_bytes = srv->peak_bytes;
   out->pairs = srv->pairs;
   out->releases = srv->releases;
+  out->shared_launches = srv->shared_launches;
+  out->shared_queries = srv->shared_queries;
   return AR_OK;
 }
 

@@ -95,6 +95,49 @@ def test_server_overlaps_only_under_a_backlog():
         api.Server(slots=4, overlap_queue=-1)
 
 
+@pytest.mark.parametrize("batch_max", [4, 1])
+def test_server_shares_launches_under_a_backlog(batch_max):
+    """Queued queries of one image size and pose variables over three scenes share
+    launches (up to batch_max) and still equal their own renders bit for bit;
+    translation queries share only with a fixed segment length (options.chunk)."""
+    api = _api()
+    scenes = [synth.box_surface_scene(900, n_boxes=5, seed=31), synth.random_scene(500, seed=32),
+              synth.random_scene(1200, seed=33)]
+    handles = [api.Scene(sc) for sc in scenes]
+    rng = np.random.default_rng(7)
+    intr = synth.intrinsics(48)
+    queries = []
+    for k in range(12):
+        box = synth.camera6_box(dt=0.5 * rng.uniform(0.005, 0.02, 3), drot=0.5 * np.deg2rad(rng.uniform(0.1, 0.6, 3)))
+        queries.append((k % 3, box, None, "rot"))
+    for k in range(4):
+        queries.append((k % 3, synth.camera6_box(dt=0.5 * rng.uniform(0.01, 0.1, 3)), {"chunk": 64}, "trans chunk"))
+    for k in range(3):
+        queries.append((k % 3, synth.camera6_box(dt=0.5 * rng.uniform(0.01, 0.1, 3)), None, "trans"))
+    srv = api.Server(slots=2, overlap_queue=1, batch_max=batch_max)
+    ids = [srv.add_scene(h) for h in handles]
+    tickets = [srv.submit(ids[s], intr, box, opts) for s, box, opts, _ in queries]
+    got = [srv.wait(t) for t in tickets]
+    rep = srv.report()
+    srv.close()
+    print("server report", rep, flush=True)
+    assert rep["completed"] == len(queries) and rep["failed"] == 0
+    for (s, box, opts, kind), (lo, hi, res) in zip(queries, got):
+        al, ah, _ = api.render_bounds(handles[s], intr, box, opts)
+        assert np.array_equal(lo.cpu().numpy(), al.cpu().numpy()) and np.array_equal(hi.cpu().numpy(), ah.cpu().numpy())
+        if kind == "trans" or batch_max == 1:
+            assert res["batched"] == 1
+        assert 1 <= res["batched"] <= batch_max
+    shared = [res["batched"] for (_, _, _, kind), (_, _, res) in zip(queries, got) if kind == "rot"]
+    print(f"batch_max {batch_max}: rotation queries per launch {shared}", flush=True)
+    if batch_max > 1:
+        assert rep["shared_launches"] >= 1 and rep["shared_queries"] >= 2 and max(shared) > 1
+    else:
+        assert rep["shared_launches"] == 0
+    for h in handles:
+        h.close()
+
+
 def test_server_budget_admits_one_query_at_a_time():
     """A budget smaller than any query: each runs only when nothing else is in flight."""
     api = _api()
@@ -203,4 +246,7 @@ def test_server_rejects_bad_requests():
     with pytest.raises(api.ARError):
         srv.wait(12345)
     srv.close()
+    for bm in (-1, 257):
+        with pytest.raises(api.ARError):
+            api.Server(slots=1, batch_max=bm)
     h.close()
