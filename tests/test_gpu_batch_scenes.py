@@ -110,3 +110,29 @@ def test_batch_scenes_rejections():
         api.render_batch_scenes([plain], intr, [box, box])
     plain.close()
     varied.close()
+
+
+def test_orbit_cells_of_several_scenes_and_host_outputs():
+    """Orbit cells (one angle) of two scenes in one call, into device and into host
+    memory: the same images, each equal to its scene's own batch of that cell."""
+    import torch
+    api = _api()
+    raw = _scenes()[:2]
+    scenes = [api.Scene(s) for s in raw]
+    intr = synth.intrinsics(32)
+    cells = synth.orbit_cells(4, 8.0, seed=4)
+    owner = [0, 1, 1, 0]
+    lo, hi, st = api.render_batch_scenes([scenes[k] for k in owner], intr, cells)
+    torch.cuda.synchronize()
+    hlo = torch.empty((4, 32, 32, 3), dtype=torch.float32, pin_memory=True)
+    hhi = torch.empty_like(hlo)
+    api.render_batch_scenes([scenes[k] for k in owner], intr, cells, out=(hlo, hhi))
+    assert np.array_equal(lo.cpu().numpy(), hlo.numpy()) and np.array_equal(hi.cpu().numpy(), hhi.numpy())
+    for c, k in enumerate(owner):
+        l1, h1, _ = api.render_batch(scenes[k], intr, [cells[c]])
+        torch.cuda.synchronize()
+        assert np.array_equal(lo[c].cpu().numpy(), l1[0].cpu().numpy()), c
+        assert np.array_equal(hi[c].cpu().numpy(), h1[0].cpu().numpy()), c
+    assert st["P"] == 1
+    for sc in scenes:
+        sc.close()
