@@ -607,6 +607,22 @@ def main():
                      "flops_per_pair": alg_flops_per_pair(P), "traffic": traffic},
     }
     log(f"headline workload done: {value:.4g} pairs/s")
+    # the same workload replayed from a planned HIP graph (sizes from one render, every
+    # kernel re-run per replay, no host synchronisation inside): for reference, not `value`
+    plan = api.Plan(sc, intr, [box], opts)
+    for _ in range(args.warmup):
+        plan.launch()
+    torch.cuda.synchronize()
+    gp, t0 = 0, time.perf_counter()
+    for _ in range(args.steps):
+        gst, _ = plan.launch()
+        gp += gst["pairs"]
+    torch.cuda.synchronize()
+    gt = time.perf_counter() - t0
+    plan.close()
+    out["graph_replay"] = {"ms_per_step": gt / args.steps * 1e3, "pairs_per_s": gp / gt,
+                           "device_ms_per_step": gst["total_ms"]}
+    log(f"headline workload as a graph replay: {gp / gt:.4g} pairs/s")
     if not args.no_autotune:
         # the binning tile and segment length the autotuner picks for this workload (the
         # timed loop above keeps the automatic rule: 8x8 tiles, measured segment length)
