@@ -472,6 +472,17 @@ static int render_rotation(const ar_scene *sc, Workspace &ws, const Params &prm,
   }
   const uint32_t *R = ws.host_ranges;
   HIP_TRY(launch_list_box(ws, ws.pair_val, ws.pose_dev, (int)nlists, ntiles, sc->dev, s));
+  // boxes of the kChunk-position chunks, with which the windows pass trims the Ind windows
+  DevCounts wdc;
+  if (prm.ind_window != 2) {
+    const size_t nchunks = ((size_t)npairs + kChunk - 1) / kChunk;
+    if (nchunks * 8 > ws.cap_cbox || !ws.cbox) {
+      HIP_TRY(grow(ws, ws.cbox, nchunks * 8 + 64));
+      ws.cap_cbox = nchunks * 8 + 64;
+    }
+    HIP_TRY(launch_chunk_boxes(ws, ws.pair_val, sc->dev, ntiles, npairs, ws.cbox, s));
+    wdc.cbox = ws.cbox;
+  }
   std::vector<size_t> groups;
   bool have_ranges = false;
   if (split) {
@@ -559,7 +570,7 @@ static int render_rotation(const ar_scene *sc, Workspace &ws, const Params &prm,
     const int ng = (int)(pb - pa);
     // Ind windows, and the mask words of the long ones
     HIP_TRY(launch_runs(P, ws, ws.pair_val, ws.pose_dev, ntiles, sc->dev, pa, ng, prm.ind_window, kRunsWindows,
-                        nullptr, false, s));
+                        nullptr, false, s, wdc));
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws.woff + ng, 1);
     HIP_TRY(hipGetLastError());
     HIP_TRY(exclusive_scan_u32(ws.woff, ng + 1, ws, s));

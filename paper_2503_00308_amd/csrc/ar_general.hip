@@ -120,6 +120,79 @@ __global__ __launch_bounds__(256) void k_list_box(const uint32_t *__restrict__ r
   if (threadIdx.x < kListBox) lbox[kListBox * (size_t)lst + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// The quick Ind test of ind_pair for every list position of a chunk at once: 1 when it
+// decides Ind = 1 (surely in front) for all of them, 0 when Ind = 0 for all, else -1.
+// cb: the chunk's box of means lo[3], hi[3] and nominal depths [cb[6], cb[7]]; uwi, ci:
+// entry i's mean and nominal depth.  For a position j of the chunk, q_j = sum_l (uw_i -
+// uw_j)_l Zm[l][kMaxP] = c_i - c_j (the nominal depths use the same multipliers) lies in
+// [c_i - cmax, c_i - cmin], and sum_l |D_l| Zq_l <= R = sum_l Zq_l max|uw_i,l - box_l|, so
+// beyond R and the borderline band 1e-12 (1 + sum_l max|D_l|) every position's quick
+// test (and so its Ind) is decided; the margin 2^-40 (E + R), E = 1 + sum_l
+// |Zm[l][kMaxP]| (|uw_i,l| + max|box_l|), covers the rounding of the nominal depths and of
+// each pair's test.
+__device__ __forceinline__ int chunk_quick(const PoseForms &pose, const double *uwi, double ci,
+                                           const double *__restrict__ cb) {
+  double R = 0.0, Dsum = 0.0, E = 1.0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const double lo = cb[l], hi = cb[3 + l];
+    const double dmax = fmax(fabs(uwi[l] - lo), fabs(uwi[l] - hi));
+    R = fma(dmax, pose.Zq[l], R);
+    Dsum += dmax;
+    E = fma(fabs(pose.Zm[l][kMaxP]), fabs(uwi[l]) + fmax(fabs(lo), fabs(hi)), E);
+  }
+  const double band = 1e-12 * (1.0 + Dsum) + 0x1p-40 * (E + R);
+  if ((ci - cb[7]) - R - band > 0.0) return 1;
+  if ((ci - cb[6]) + R + band < 0.0) return 0;
+  return -1;
+}
+
+// Boxes of the chunks of kChunk list positions (see launch_chunk_boxes): lane t of a wave
+// takes position 64 w + t, and the lanes of each chunk reduce their values together.
+__global__ __launch_bounds__(256) void k_chunk_boxes(const uint32_t *__restrict__ pkey,
+                                                     const uint32_t *__restrict__ lists,
+                                                     const double *__restrict__ dint, SceneDev scene, int ntiles,
+                                                     size_t npos, double *__restrict__ cbox,
+                                                     const CellScene *__restrict__ tab) {
+  const int lane = threadIdx.x & 63;
+  const size_t w = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const size_t q = w * 64 + lane;
+  if (w * 64 >= npos) return;
+  double v[8] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, INFINITY, -INFINITY};
+  bool nan = false;
+  if (q < npos) {
+    const uint32_t g = lists[q];
+    const int cell = (int)(pkey[q] / (uint32_t)ntiles);
+    const SceneDev &sc = cell_scene(scene, tab, cell);
+    const size_t lg = g - cell_first(scene, tab, cell);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const double u = (double)sc.ind_mean[(size_t)l * sc.n + lg];
+      nan = nan || u != u;
+      v[l] = u;
+      v[3 + l] = u;
+    }
+    v[6] = v[7] = dint[2 * (size_t)g];
+  }
+  for (int off = kChunk / 2; off > 0; off >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double o = __shfl_xor(v[k], off);
+      v[k] = (k < 3 || k == 6) ? fmin(v[k], o) : fmax(v[k], o);
+    }
+  }
+  // a NaN mean anywhere in the chunk: the box decides nothing
+  const unsigned long long nb = __ballot(nan);
+  nan = (nb >> (lane & ~(kChunk - 1))) & ((kChunk == 64) ? ~0ull : ((1ull << kChunk) - 1ull));
+  if ((lane & (kChunk - 1)) == 0 && q < npos) {
+    double *o = cbox + (q >> kChunkLog) * 8;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) o[k] = nan ? (k < 3 ? INFINITY : -INFINITY) : v[k];
+    o[6] = v[6];
+    o[7] = v[7];
+  }
+}
+
 // Ind(d_i - d_j) in {0, 1, 2 = unknown} (see the file comment).  Depth forms: the lower
 // form's coefficients at [0, P) and its constant at [S - 1], the upper form's at
 // [S, S + P) and [2S - 1] (S = kMaxP + 1 by item, S = P + 1 in the compact copy).
@@ -397,7 +470,8 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
                                               unsigned long long *__restrict__ counters,
                                               const uint32_t *__restrict__ ng_dev, uint32_t runs_cap,
                                               unsigned long long *__restrict__ ind_und,
-                                              const CellScene *__restrict__ tab) {
+                                              const CellScene *__restrict__ tab,
+                                              const double *__restrict__ cbox) {
   constexpr bool EMIT = MODE == kRunsEmit;
   const int lane = threadIdx.x & 63;
   // planned launches: the entries counted on the device, and no runs past the buffer
@@ -483,6 +557,23 @@ __global__ __launch_bounds__(256) void k_runs(const uint32_t *__restrict__ pkey,
           if (dint[2 * (size_t)list[mid]] <= t2) a = mid + 1; else b = mid;
         }
         qe = a;
+        // Trim the window's ends by whole chunks of kChunk list positions that the quick test
+        // decides at once (chunk_quick, with the borderline band the counting pass uses):
+        // surely in front at the start, surely behind at the end.  The tests and runs see
+        // the same decisions, so only the number of tests changes.  (Window mode 2, every
+        // pair tested, is left whole.)
+        if (cbox && window_mode != 2) {
+          while (ps < i) {
+            const size_t q = (size_t)beg + ps;
+            if (chunk_quick(pose, uwi, c_i, cbox + (q >> kChunkLog) * 8) != 1) break;
+            ps = (int)min((long long)i, (long long)(((q >> kChunkLog) + 1) << kChunkLog) - (long long)beg);
+          }
+          while (qe > i + 1) {
+            const size_t q = (size_t)beg + qe - 1;
+            if (chunk_quick(pose, uwi, c_i, cbox + (q >> kChunkLog) * 8) != 0) break;
+            qe = (int)max((long long)i + 1, (long long)((q >> kChunkLog) << kChunkLog) - (long long)beg);
+          }
+        }
         win[2 * (size_t)p] = (uint32_t)ps;
         win[2 * (size_t)p + 1] = (uint32_t)qe;
       }
@@ -1171,6 +1262,15 @@ __global__ __launch_bounds__(192) void k_rot_merge(const uint32_t *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------------
+hipError_t launch_chunk_boxes(const Workspace &ws, const uint32_t *lists, const SceneDev &sc, int ntiles, size_t npos,
+                              double *cbox, hipStream_t s) {
+  const size_t nwaves = (npos + 63) / 64;
+  if (nwaves == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_chunk_boxes, dim3((unsigned)((nwaves + 3) / 4)), dim3(256), 0, s, ws.pair_key, lists, ws.dint,
+                     sc, ntiles, npos, cbox, ws.tab);
+  return hipGetLastError();
+}
+
 hipError_t launch_list_box(const Workspace &ws, const uint32_t *lists, const PoseForms *poses, int nlists, int ntiles,
                            const SceneDev &sc, hipStream_t s) {
   hipLaunchKernelGGL(k_list_box, dim3(nlists), dim3(256), 0, s, ws.tile_range, lists, poses, sc, ntiles, ws.lbox,
@@ -1187,7 +1287,7 @@ static hipError_t launch_runs_pm(const Workspace &ws, const uint32_t *lists, con
   hipLaunchKernelGGL((k_runs<P, MODE, COMPACT>), grid, block, 0, s, ws.pair_key, ws.tile_range, lists, ws.dint,
                      ws.dform, (const float4 *)ws.cmean, ws.cform, ws.lbox, poses_dev, ntiles, sc, pbase, ng,
                      window_mode, ws.win, ws.woff, masks, ws.run_cnt, ws.runs, ws.counters, dc.entries, dc.runs_cap,
-                     dc.ind_und, ws.tab);
+                     dc.ind_und, ws.tab, dc.cbox);
   return hipGetLastError();
 }
 

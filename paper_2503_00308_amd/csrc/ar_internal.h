@@ -222,6 +222,8 @@ struct Workspace {
   CellScene *tab = nullptr;
   uint32_t *tab_off = nullptr;
   int tab_cells = 0;
+  double *cbox = nullptr;    // rotation path: boxes of the kChunk-position chunks (Ind windows)
+  size_t cap_cbox = 0;
   CellScene *tab_dev = nullptr, *tab_host = nullptr;
   uint32_t *tab_off_dev = nullptr, *tab_off_host = nullptr;
   size_t cap_tab = 0;
@@ -394,7 +396,16 @@ struct DevCounts {
   const uint32_t *entries = nullptr;
   uint32_t runs_cap = 0;
   unsigned long long *ind_und = nullptr;   // counting pass: undecided Ind pairs per cell (or null)
+  const double *cbox = nullptr;            // windows pass: boxes of the kChunk-position chunks (or null)
 };
+// list positions per chunk box of the Ind windows' trimming
+constexpr int kChunkLog = 6;
+constexpr int kChunk = 1 << kChunkLog;
+// Boxes of the chunks of kChunk list positions [kChunk c, kChunk (c + 1)) of the launch (npos
+// positions): per chunk the box of the means the Ind tests read (lo[3], hi[3]; +inf /
+// -inf when one is NaN) and the range of the nominal depths [cmin, cmax], 8 doubles.
+hipError_t launch_chunk_boxes(const Workspace &ws, const uint32_t *lists, const SceneDev &sc, int ntiles, size_t npos,
+                              double *cbox, hipStream_t s);
 hipError_t launch_runs(int P, const Workspace &ws, const uint32_t *lists, const PoseForms *poses_dev, int ntiles,
                        const SceneDev &sc, uint32_t pbase, int ng, int window_mode, int mode,
                        unsigned long long *masks, bool compact, hipStream_t s, const DevCounts &dc = DevCounts{});

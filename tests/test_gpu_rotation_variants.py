@@ -151,10 +151,11 @@ def test_run_limit_regroups_lists_bit_identical():
 
 def test_quick_ind_test_changes_nothing():
     """The quick Ind test (options.ind_quick) fires only where the full identity bound
-    decides the same way, so switching it off changes nothing: the same images, Ind runs,
-    undecided and borderline counts, bit for bit, on the six-axis, one-angle and orbit
-    cases and on the 100k-Gaussian object scene over six axes (400x400), whose windows
-    hold millions of tests the quick test decides."""
+    decides the same way, so switching it off changes nothing but the number of tests
+    (with it, whole chunks of 64 list positions it decides at once leave the windows):
+    the same images, Ind runs, undecided and borderline counts, bit for bit, on the
+    six-axis, one-angle and orbit cases and on the 100k-Gaussian object scene over six
+    axes (400x400), whose windows hold millions of tests the quick test decides."""
     api = _api()
     cases = [(name, c[0], synth.intrinsics(c[1]), [c[2]]) for name, c in _cases().items()]
     cases.append(("orbit", synth.box_surface_scene(1500, n_boxes=8, seed=32), synth.intrinsics(48),
@@ -173,7 +174,7 @@ def test_quick_ind_test_changes_nothing():
         print(f"[{name}] runs {s1['runs']} / {s2['runs']}, Ind tests {s1['ind_tests']}, undecided "
               f"{int(u1.sum())} / {int(u2.sum())}, borderline {s1['ind_borderline']} / {s2['ind_borderline']}, "
               f"{s1['total_ms']:.1f} / {s2['total_ms']:.1f} ms", flush=True)
-        assert s1["runs"] == s2["runs"] and s1["ind_tests"] == s2["ind_tests"]
+        assert s1["runs"] == s2["runs"] and s1["ind_tests"] <= s2["ind_tests"]
         assert s1["ind_borderline"] == s2["ind_borderline"]
         assert np.array_equal(u1, u2)
         assert np.array_equal(l1, l2) and np.array_equal(h1, h2)
