@@ -206,13 +206,15 @@ typedef struct {
   int32_t n_wild;        /* Gaussians straddling the near plane (alpha in [0, o] everywhere) */
   int32_t n_dropped;     /* Gaussians behind the near plane at every pose */
   int32_t P;             /* number of pose variables of the box */
-  int32_t max_window;    /* largest Ind window of uncertain depth order (rotations) */
+  int32_t max_window;    /* largest Ind window of uncertain depth order (rotations), after
+                            its ends decided chunk by chunk are trimmed */
   int32_t segment_length; /* list positions per segment of the pixel loop (largest of the call) */
   double raster_ms;      /* device time of the main per-pixel kernel (HIP events on the call's stream) */
   double total_ms;       /* device time of the whole call from its first to its last kernel */
   int64_t runs;          /* rotation boxes: runs of list positions holding the Ind sets */
   int64_t cycles_a, cycles_b; /* rotation boxes: summed wave clock cycles of the pixel loop's two phases */
-  int64_t ind_tests;     /* rotation boxes: pairwise Ind tests (summed window lengths) */
+  int64_t ind_tests;     /* rotation boxes: pairwise Ind tests (summed window lengths;
+                            depends on the options, never the result) */
   int64_t ind_borderline; /* rotation boxes: Ind tests decided by a bound within rounding of its
                              threshold (1e-12 (1 + |uw_i - uw_j|_1)), which another order of
                              the same operations might decide otherwise */
